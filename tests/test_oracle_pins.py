@@ -1,0 +1,288 @@
+"""Pins of the oracle walker to what the mathematics fixes (no GPU).
+
+Each test names the plausible mistake it is there to catch.  Statistical
+checks use fixed seeds (so they are deterministic) and a 4.5-sigma band.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import stats
+
+from oracle import cn, pure
+from paper_2402_06491_amd import inputs
+
+Z = 4.5
+
+
+def _est(oracle_mod, prob, mc, x, t, n, pid=0):
+    res = oracle_mod.solve(prob, mc, np.atleast_2d(x), [t], [n], point_ids=np.array([pid], np.uint32))[0]
+    return res["a"], np.sqrt(np.maximum(np.diag(res["cov"]), 0.0)), res
+
+
+# --- tree shape: the Yule law ---------------------------------------------
+@pytest.mark.parametrize("t", [0.5, 1.0, 2.0])
+def test_yule_binary(oracle_mod, t):
+    """g = 1, binary splits at rate 1: P(Ne = n) = e^-t (1 - e^-t)^n.
+
+    Catches: wrong clock test (sum of times vs product), wrong theta, children
+    not all visited, preorder counter reuse.
+    """
+    prob = inputs.problem(1, 0.5, [0, -1, 1], inputs.const(1.0))
+    mc = inputs.mc_params(seed=3, max_order=200, prune=0)
+    N = 200_000
+    rec = oracle_mod.walk_point(prob, mc, [0.0], t, 0, N)
+    assert np.all(rec["flags"] == 0)
+    p = math.exp(-t)
+    kmax = int(np.ceil(math.log(5.0 / N) / math.log(1 - p)))
+    obs = np.bincount(np.minimum(rec["ne"], kmax), minlength=kmax + 1)
+    exp = np.array([p * (1 - p) ** n for n in range(kmax)] + [(1 - p) ** kmax]) * N
+    chi = stats.chisquare(obs, exp)
+    assert chi.pvalue > 1e-4
+    # binary trees: nodes = 1 + 2 Ne exactly
+    assert np.array_equal(rec["nodes"], 1 + 2 * rec["ne"])
+    assert abs(rec["nodes"].mean() - (2 * math.exp(t) - 1)) < Z * rec["nodes"].std() / math.sqrt(N)
+
+
+def test_yule_ternary(oracle_mod):
+    """Ternary splits: P(Ne = n) = Gamma(n + 1/2)/(Gamma(1/2) n!) e^-t (1 - e^-2t)^n.
+
+    Catches: arity lookup, the children count of a vertex.
+    """
+    t = 0.6
+    prob = inputs.problem(1, 1.0, [0, -1, 0, 1], inputs.const(1.0))
+    mc = inputs.mc_params(seed=4, max_order=200, prune=0)
+    N = 200_000
+    rec = oracle_mod.walk_point(prob, mc, [0.0], t, 0, N)
+    q = 1 - math.exp(-2 * t)
+    pmf = [math.exp(math.lgamma(n + 0.5) - math.lgamma(0.5) - math.lgamma(n + 1) - t) * q ** n for n in range(60)]
+    kmax = max(n for n in range(60) if pmf[n] * N > 5)
+    obs = np.bincount(np.minimum(rec["ne"], kmax + 1), minlength=kmax + 2)
+    exp = np.array(pmf[: kmax + 1] + [1 - sum(pmf[: kmax + 1])]) * N
+    assert stats.chisquare(obs, exp).pvalue > 1e-4
+    assert np.array_equal(rec["nodes"], 1 + 3 * rec["ne"])
+
+
+# --- Brownian part: heat kernel at f = 0 -----------------------------------
+def test_heat_kernel_1d(oracle_mod):
+    """f = 0, a = 1, g = e^{-x^2/4}/sqrt(4 pi):  u = e^{-x^2/(4(t+1))}/sqrt(4 pi (t+1)).
+
+    This is Example 1's initial profile read at t = 0.  Catches sigma = sqrt(a)
+    instead of sqrt(2a), the Box-Muller normal, the leaf time.
+    """
+    g = inputs.gauss_sum([(1 / math.sqrt(4 * math.pi), 0.0, 0.0, math.sqrt(2.0))])
+    prob = inputs.problem(1, 1.0, [0, 0, 0], g)
+    mc = inputs.mc_params(seed=5)
+    for x, t in [(0.0, 1.0), (1.5, 0.5), (-2.0, 2.0)]:
+        a, se, res = _est(oracle_mod, prob, mc, [x], t, 200_000)
+        exact = math.exp(-x * x / (4 * (t + 1))) / math.sqrt(4 * math.pi * (t + 1))
+        assert res["moments"]["nodes"] == 200_000          # every root is a leaf
+        assert abs(a[0] - exact) < Z * se[0]
+        assert np.all(a[1:] == 0)
+
+
+def test_gauss_sum_2d(oracle_mod):
+    """2-D Gaussian sum at f = 0 convolved with the heat kernel (closed form).
+
+    Catches the second normal (sin branch) and the 2-D position update.
+    """
+    terms = [(0.7, 1.0, -0.5, 0.8), (0.4, -1.5, 1.0, 1.3)]
+    prob = inputs.problem(2, 0.8, [0, 0], inputs.gauss_sum(terms))
+    mc = inputs.mc_params(seed=6)
+    x, t = np.array([0.3, 0.2]), 0.7
+    a, se, _ = _est(oracle_mod, prob, mc, x, t, 200_000)
+    exact = 0.0
+    for A, cx, cy, s in terms:
+        v = s * s + 2 * 0.8 * t
+        exact += A * (s * s / v) * math.exp(-((x[0] - cx) ** 2 + (x[1] - cy) ** 2) / (2 * v))
+    assert abs(a[0] - exact) < Z * se[0]
+
+
+# --- weights and recursion: constant g against the eps-expansion of the ODE --
+def test_kpp_series_closed_form(oracle_mod):
+    """KPP with constant g0: a_n = g0^{n+1} e^-t (1-e^-t)^n.  Catches weight/mu errors."""
+    g0, t = 0.7, 1.0
+    prob = inputs.problem(1, 0.5, [0, -1, 1], inputs.const(g0))
+    mc = inputs.mc_params(seed=7, max_order=12, prune=1)
+    a, se, _ = _est(oracle_mod, prob, mc, [0.0], t, 400_000)
+    for n in range(8):
+        ex = g0 ** (n + 1) * math.exp(-t) * (1 - math.exp(-t)) ** n
+        assert abs(a[n] - ex) < Z * se[n] + 1e-15, n
+
+
+@pytest.mark.parametrize("t", [0.5, 1.0])
+def test_fisher_series_closed_form(oracle_mod, t):
+    """Fisher with constant g0: a_n = g0 e^t (-g0 (e^t - 1))^n.
+
+    Catches the sign of c_2, mu = c_1 + lambda, the e^{mu t} prefactor and the
+    time used in the vertex exponent (remaining time after the split).
+    """
+    g0 = 0.4
+    prob = inputs.problem(1, 1.0, [0, 1, -1], inputs.const(g0))
+    mc = inputs.mc_params(seed=8, max_order=12, prune=1)
+    a, se, _ = _est(oracle_mod, prob, mc, [0.0], t, 400_000)
+    for n in range(8):
+        ex = g0 * math.exp(t) * (-g0 * (math.exp(t) - 1)) ** n
+        assert abs(a[n] - ex) < Z * se[n], n
+
+
+def test_mixed_arity_series_vs_ode(oracle_mod):
+    """Constant, quadratic and cubic terms plus a potential against the ODE hierarchy.
+
+    Catches: arity-0 vertices, uniform choice among K terms (the K factor),
+    c_j of the wrong power, the constant term.
+    """
+    coef = [0.3, -0.4, 0.8, -0.6]
+    g0, t = 0.6, 0.8
+    prob = inputs.problem(1, 1.0, coef, inputs.const(g0))
+    mc = inputs.mc_params(seed=9, max_order=12, prune=1)
+    a, se, _ = _est(oracle_mod, prob, mc, [0.0], t, 400_000)
+    ex = cn.ode_hierarchy(g0, coef, [t], 6)[:, 0]
+    for n in range(7):
+        assert abs(a[n] - ex[n]) < Z * se[n] + 1e-14, n
+
+
+def test_lambda_invariance(oracle_mod):
+    """The coefficients do not depend on the clock rate lambda (only their variance does)."""
+    coef = [0, 0.5, -1.0, 0.0, 0.5]
+    prob = inputs.problem(1, 1.0, coef, inputs.logistic(0.8, 1.0, 0.0, 1))
+    x, t = [0.5], 0.7
+    a1, s1, _ = _est(oracle_mod, prob, inputs.mc_params(seed=10, lam=1.0), x, t, 300_000)
+    a2, s2, _ = _est(oracle_mod, prob, inputs.mc_params(seed=11, lam=2.5), x, t, 300_000)
+    for n in range(6):
+        assert abs(a1[n] - a2[n]) < Z * math.hypot(s1[n], s2[n]), n
+
+
+def test_tree_recursion_symbolic():
+    """Brute force over the shapes with at most one split, integrated symbolically.
+
+    The tree recursion (one exponential time per node, weight
+    K c_j/lam e^{(j-1) mu tau'} with tau' the time left after the split,
+    u = e^{mu t} v) must reproduce the first two eps-coefficients of the ODE
+    u' = c_1 u + eps c_2 u^2 for constant g0.  This pins the reading of the
+    garbled time argument of h^(alpha) in the recursion of Sec. 2.1.
+    """
+    sp = pytest.importorskip("sympy")
+    t, s = sp.symbols("t s", positive=True)
+    # arbitrary exact rationals for the clock rate, the potential, c_2 and g0
+    lam, c1, c2, g0 = sp.Rational(3, 2), sp.Rational(-1, 3), sp.Rational(2, 5), sp.Rational(3, 4)
+    mu = c1 + lam
+    # no split: the root survives to t (probability e^{-lam t}), value g0
+    a0 = sp.exp(mu * t - lam * t) * g0
+    # one split at s < t (density lam e^{-lam s}, weight (c2/lam) e^{mu (t-s)}),
+    # then both children survive the remaining t - s (each e^{-lam (t-s)}) with value g0
+    expo = -lam * s + mu * (t - s) - 2 * lam * (t - s)
+    a1 = sp.exp(mu * t) * sp.integrate(lam * (c2 / lam) * g0 ** 2 * sp.exp(sp.expand(expo)), (s, 0, t))
+    # the eps-expansion of the ODE u' = c1 u + eps c2 u^2: a0' = c1 a0, a1' = c1 a1 + c2 a0^2
+    A0 = g0 * sp.exp(c1 * t)
+    A1 = sp.integrate(c2 * g0 ** 2 * sp.exp(sp.expand(c1 * (t - s) + 2 * c1 * s)), (s, 0, t))
+    for tv in (sp.Rational(1, 3), 1, sp.Rational(5, 2)):
+        assert abs(sp.N((a0 - A0).subs(t, tv), 40)) < 1e-35
+        assert abs(sp.N((a1 - A1).subs(t, tv), 40)) < 1e-35
+    assert abs(sp.N(A1.subs(t, 1), 20)) > 1e-3   # not trivially zero
+
+
+# --- spatial dependence: coefficients against a fine-grid CN hierarchy --------
+def test_kpp_coefficients_vs_cn(oracle_mod):
+    """KPP with logistic g: a_n(x, t) against Crank-Nicolson on the hierarchy.
+
+    Catches: split positions (sqrt(S) increment), children departing from the
+    split point, the leaf increment over the remaining time.
+    """
+    wl = inputs.kpp(n_trees=200_000)
+    prob = wl["problems"][0]
+    mc = dict(wl["mc"])
+    mc["seed"] = 12
+    xq = np.array([-2.0, 0.0, 1.5])
+    t = 1.0
+    g = lambda x: 1.0 / (1.0 + np.exp(x))  # noqa: E731
+    ref = cn.cn_hierarchy(g, 0.5, [0, -1, 1], xq, t, 5, L=16.0, h=1 / 16, dt=1 / 200)
+    for i, x in enumerate(xq):
+        a, se, _ = _est(oracle_mod, prob, mc, [x], t, 200_000, pid=i)
+        for n in range(6):
+            assert abs(a[n] - ref[n, i]) < Z * se[n] + 2e-6, (x, n)
+
+
+# --- whole pipeline: Pade sum against exact travelling waves ----------------
+def test_fisher_wave_pade(oracle_mod):
+    """Fisher travelling wave: the [6/6] Pade sum of the estimated series at z = 1."""
+    wl = inputs.fisher(n_trees=1)
+    prob, mc = wl["problems"][0], dict(wl["mc"])
+    mc["seed"] = 13
+    for x, t in [(-2.0, 0.5), (0.0, 1.0), (3.0, 1.0)]:
+        _, _, res = _est(oracle_mod, prob, mc, [x], t, 400_000)
+        ex = float(inputs.fisher_exact(x, t))
+        assert abs(res["pade"] - ex) < 1e-3 + Z * res["pade_se"], (x, t, res["pade"], ex)
+
+
+def test_nagumo_wave_closed_form():
+    """The travelling wave of Example 3 solves u_t = u_xx - a u + (1+a) u^2 - u^3 (sympy residual 0)."""
+    sp = pytest.importorskip("sympy")
+    x, t, a = sp.symbols("x t a", real=True)
+    u = 1 / (1 + sp.exp(-(x + sp.sqrt(2) * (sp.Rational(1, 2) - a) * t) / sp.sqrt(2)))
+    res = sp.diff(u, t) - (sp.diff(u, x, 2) - a * u + (1 + a) * u ** 2 - u ** 3)
+    assert sp.simplify(res) == 0
+
+
+def test_nagumo_wave_pade(oracle_mod):
+    """Two non-linear terms plus a potential, with the Nagumo travelling wave as exact answer."""
+    aa = 0.25
+    coef = [0.0, -aa, 1 + aa, -1.0]
+    prob = inputs.problem(1, 1.0, coef, inputs.logistic(1.0, -1 / math.sqrt(2), 0.0, 1))
+    mc = inputs.mc_params(seed=14, max_order=12, prune=1)
+    for x, t in [(0.0, 0.5), (1.0, 1.0)]:
+        _, _, res = _est(oracle_mod, prob, mc, [x], t, 400_000)
+        ex = 1 / (1 + math.exp(-(x + math.sqrt(2) * (0.5 - aa) * t) / math.sqrt(2)))
+        assert abs(res["pade"] - ex) < 1e-3 + Z * res["pade_se"], (x, t, res["pade"], ex)
+
+
+# --- implementation cross-checks and special cases ----------------------------
+PROBLEMS = [
+    (inputs.problem(1, 0.5, [0, -1, 1], inputs.logistic(1, 1, 0, 1)), dict(max_order=63, prune=0)),
+    (inputs.problem(1, 1.0, [0, 1, -1], inputs.logistic(1, 1 / math.sqrt(6), 0, 2)), dict(max_order=4, prune=1)),
+    (inputs.problem(2, 1.0, [0, 1, 0, -1], inputs.cubic_2d_u0(0)), dict(max_order=12, prune=1)),
+    (inputs.problem(1, 1.0, [0.3, -0.2, 0.5, 0.0, -0.7, 0.2], inputs.logistic(0.5, 1, 0, 1)),
+     dict(max_order=12, prune=1, node_cap=9)),
+    (inputs.problem(2, 0.3, [0, 0, 1.0], {"u0_kind": "cos2_bump", "u0_params": [-2.0, 2.0, 3.0], "u0_nterms": 0}),
+     dict(max_order=12, prune=0)),
+]
+
+
+@pytest.mark.parametrize("case", range(len(PROBLEMS)))
+def test_recursive_vs_explicit_stack(oracle_mod, case):
+    """walker.c (recursion) against oracle/pure.py (explicit stack), tree by tree."""
+    prob, extra = PROBLEMS[case]
+    mc = inputs.mc_params(seed=100 + case, **extra)
+    nz = oracle_mod.normalize(prob, mc)
+    rng = np.random.default_rng(case)
+    n = 300
+    x = rng.uniform(-2, 2, size=(n, prob["dim"]))
+    t = rng.uniform(0.0, 1.5, size=n)
+    pid = rng.integers(0, 2 ** 32, size=n, dtype=np.uint64).astype(np.uint32)
+    tid = rng.integers(0, 2 ** 32, size=n, dtype=np.uint64).astype(np.uint32)
+    rec = oracle_mod.walk(prob, mc, x, t, pid, tid)
+    for i in range(n):
+        F, ne, nodes, flags = pure.walk_tree(nz, mc, list(x[i]), float(t[i]), int(pid[i]), int(tid[i]))
+        assert (rec["ne"][i], rec["nodes"][i], rec["flags"][i]) == (ne, nodes, flags), i
+        assert abs(rec["F"][i] - F) <= 1e-13 * max(abs(F), 1e-300), i
+
+
+def test_time_zero_is_g(oracle_mod):
+    """t = 0: theta = 1, every root is a leaf with no displacement, F = g(x)."""
+    prob = inputs.problem(1, 1.0, [0, 1, -1], inputs.logistic(1, 1 / math.sqrt(6), 0, 2))
+    x = np.linspace(-3, 3, 7).reshape(-1, 1)
+    rec = oracle_mod.walk(prob, inputs.mc_params(), x, 0.0, 0, np.arange(7))
+    assert np.all(rec["ne"] == 0) and np.all(rec["nodes"] == 1)
+    np.testing.assert_allclose(rec["F"], (1 + np.exp(x[:, 0] / math.sqrt(6))) ** -2, rtol=1e-15)
+
+
+def test_node_cap_and_pruning_flags(oracle_mod):
+    """A cap of 1 node abandons every tree that splits; pruning at order 0 flags them as overflow."""
+    prob = inputs.problem(1, 0.5, [0, -1, 1], inputs.const(1.0))
+    rec = oracle_mod.walk_point(prob, inputs.mc_params(max_order=50, prune=0, node_cap=1), [0.0], 1.0, 0, 2000)
+    split = rec["ne"] > 0
+    assert np.all(rec["flags"][split] == 2) and np.all(rec["flags"][~split] == 0)
+    assert np.all(rec["F"][split] == 0)
+    rec2 = oracle_mod.walk_point(prob, inputs.mc_params(max_order=0, prune=1), [0.0], 1.0, 0, 2000)
+    assert np.array_equal(rec2["flags"] == 1, split)
+    assert abs(split.mean() - (1 - math.exp(-1))) < Z * 0.5 / math.sqrt(2000)
