@@ -1,0 +1,194 @@
+/*
+ * brt.h -- C ABI of the branching-random-tree solver for semilinear parabolic
+ * PDEs on MI355X (gfx950).
+ *
+ * The library estimates u(x,t) for
+ *
+ *     u_t = a Lap(u) + f(u),   f(u) = sum_{j=0}^{7} c_j u^j,   u(x,0) = g(x),
+ *
+ * (problem statement of Sec. 1 of Acebron & Rodriguez-Rozas, "A new parallel
+ * solver suited for arbitrary semilinear parabolic PDEs based on generalized
+ * random trees", with L = a Lap and f a polynomial) at query points (x,t) by
+ * Strategy A of Sec. 2.1: Monte Carlo over random branching trees whose value
+ * is the product of vertex weights and of g at the leaves (eq. rep_strategyB),
+ * binned by number of splits into the coefficients of a possibly divergent
+ * series, which is then summed by a Pade approximant (end of Sec. 2.1 and
+ * Sec. 2.4).  Every step runs in HIP kernels on one GPU.
+ *
+ * Conventions
+ *  - Every call returns int: BRT_OK (0) or a negative BRT_E_* code.
+ *    brt_last_error() returns a message for the calling thread's last error.
+ *  - Structs start with struct_size = sizeof(struct); calls reject other sizes.
+ *  - "host" pointers are read during the call only and never retained.
+ *  - "device" pointers are caller-owned device memory (for example PyTorch
+ *    tensors); the library writes them asynchronously on the given stream and
+ *    never frees them.  Streams are hipStream_t passed as void* (NULL = the
+ *    null stream).
+ *  - The library never calls exit(); device faults surface as BRT_E_DEVICE.
+ *
+ * Randomness (the documented stream; any implementation of the method that
+ * follows it walks the same trees): one Philox4x32-10 block (Salmon et al.,
+ * SC'11) per tree node, key = (seed low 32 bits, seed high 32 bits), counter =
+ * (node preorder index, tree index, point id, 0); word 0 is the clock uniform
+ * U = (w0 + 0.5) 2^-32, word 1 the arity index floor(w1 K / 2^32), words 2-3
+ * a Box-Muller pair u1 = (w2 + 0.5) 2^-32, u2 = w3 2^-32.  A node is a vertex
+ * iff the FP64 product of U along its lineage (itself included) exceeds
+ * theta = exp(-lambda t) computed on the host in FP64.
+ */
+#ifndef BRT_H
+#define BRT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BRT_OK 0
+#define BRT_E_ARG (-1)    /* invalid argument or struct_size */
+#define BRT_E_DEVICE (-2) /* HIP runtime or kernel error */
+#define BRT_E_NOMEM (-3)  /* device or host allocation failed */
+#define BRT_E_BUSY (-4)   /* server admission queue full */
+#define BRT_E_RANGE (-5)  /* a tree exceeded the kernel's stack depth (results of that point flagged) */
+#define BRT_E_STATE (-6)  /* unknown ticket / object in the wrong state */
+
+/* Initial data g (the u(x,0) families of the paper's examples).
+ *  BRT_U0_CONST      params (g0)
+ *  BRT_U0_LOGISTIC   params (A, s, x0, p, n0, n1): A (1 + exp(s (n.x - x0)))^(-p), p in {1,2,3,4}
+ *                    (KPP data of Sec. 1, travelling waves of Example 3 and the Fisher wave)
+ *  BRT_U0_GAUSS_SUM  u0_nterms terms (A, cx, cy, s): sum A exp(-|x - c|^2 / (2 s^2))
+ *                    (heat-kernel data of Examples 1, 2 and 5)
+ *  BRT_U0_COS2_BUMP  params (A, Ax, Ay): A cos^2(pi x / 2Ax) cos^2(pi y / 2Ay) for |x|<=Ax, |y|<=Ay,
+ *                    else 0 (Example 4)
+ * In 1-D the y parts are ignored. */
+#define BRT_U0_CONST 0u
+#define BRT_U0_LOGISTIC 1u
+#define BRT_U0_GAUSS_SUM 2u
+#define BRT_U0_COS2_BUMP 3u
+
+/* The PDE (Sec. 1, eq. nonlinear_new with L = a Lap, constant polynomial coefficients). */
+typedef struct brt_problem {
+  uint32_t struct_size;
+  uint32_t dim;          /* 1 or 2 */
+  double diffusion;      /* a > 0; the paths are x + sqrt(2a) W (Feynman-Kac, eqs. green/SDE) */
+  double coef[8];        /* c_0..c_7; c_1 is absorbed exactly into the exponential prefactor */
+  uint32_t u0_kind;      /* BRT_U0_* */
+  uint32_t u0_nterms;    /* BRT_U0_GAUSS_SUM: 1..8 */
+  double u0_params[40];
+} brt_problem;
+
+/* Monte Carlo parameters shared by all points of one call. */
+typedef struct brt_mc {
+  uint32_t struct_size;
+  uint32_t precision;    /* 32: paths, times and tree products in FP32 (clock product FP64, moments FP64);
+                            64: everything in FP64 */
+  uint64_t seed;         /* Philox key */
+  double lambda;         /* clock rate > 0 (the paper's Strategy A is lambda = 1) */
+  uint32_t max_order;    /* series order N_ord, 0..126: bins 0..N_ord and a tail bin */
+  uint32_t prune;        /* 1: abandon a tree at its (N_ord+1)-th split (counted as overflow) */
+  uint32_t node_cap;     /* abandon a tree when it would visit node number node_cap (1..2^21-1) */
+  uint32_t pade_L;       /* Pade [L/M], L + M <= max_order */
+  uint32_t pade_M;
+} brt_mc;
+
+/* Query points (host arrays, n entries each). */
+typedef struct brt_points {
+  uint32_t struct_size;
+  uint32_t n;
+  const double* x;          /* n*dim, row-major */
+  const double* t;          /* n, t >= 0 */
+  const uint64_t* n_trees;  /* n, 0..2^32-1 trees per point */
+  const uint32_t* problem_id; /* n, index into the problem array; NULL = all 0 */
+  const uint32_t* point_id;   /* n, Philox counter word 2; NULL = 0..n-1 */
+} brt_points;
+
+/* Per-point flags (brt_out.flags). */
+#define BRT_FLAG_POLE 1u       /* the Pade denominator changes sign on [0,1] or vanishes at 1 */
+#define BRT_FLAG_LOWERED 2u    /* singular Pade system: the denominator degree was lowered */
+#define BRT_FLAG_OVERFLOW 4u   /* some trees were pruned */
+#define BRT_FLAG_CAPPED 8u     /* some trees hit the node cap */
+#define BRT_FLAG_DEPTH 16u     /* some trees exceeded the stack depth (their values are missing) */
+
+/* Outputs.  All device pointers, caller-owned, each may be NULL.  B = max_order + 2. */
+typedef struct brt_out {
+  uint32_t struct_size;
+  double* u;          /* n: Pade [L/M] value at z = 1 (u = e^{mu t} v applied) */
+  double* se;         /* n: delta-method standard error of u */
+  double* psum;       /* n: plain sum of all B coefficients */
+  double* coef;       /* n*B: a_0..a_Nord, then the tail (Ne > N_ord, only without pruning) */
+  double* coef_var;   /* n*B: variance of each coefficient estimate */
+  uint64_t* hist;     /* n*(B+3): trees per bin, then overflow, capped, depth-exceeded counts */
+  double* s1;         /* n*B: sum of tree values per bin (before the e^{mu t}/N scaling) */
+  double* s2;         /* n*B: sum of squared tree values per bin */
+  uint64_t* nodes;    /* n: tree nodes walked */
+  uint32_t* flags;    /* n: BRT_FLAG_* */
+  void* tree_f;       /* total trees, double: value of each tree (0 when abandoned); point i's trees
+                         start at sum_{k<i} n_trees[k].  The running product is FP64 on both
+                         precision paths (vertex weights reach e^{32} and overflow FP32). */
+  uint32_t* tree_meta;/* total trees: bits 0-7 min(Ne,255), bit 8 overflow, bit 9 capped,
+                         bit 10 depth exceeded, bits 11-31 nodes visited */
+} brt_out;
+
+typedef struct brt_ctx brt_ctx;
+typedef struct brt_plan brt_plan;
+
+/* Launch settings (defaults chosen by the library; brt_autotune picks them by measurement). */
+typedef struct brt_launch {
+  uint32_t struct_size;
+  uint32_t waves_per_block;  /* 1..16 */
+  uint32_t blocks_per_cu;    /* 0 = as many as fit */
+  uint32_t chunk_trees;      /* trees handed to a wave at a time, multiple of 64 */
+  uint32_t stack_depth;      /* LDS stack levels per lane; 0 = automatic */
+} brt_launch;
+
+/* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
+int brt_version(void);
+
+/* Message of the calling thread's last error ("" if none). The pointer stays valid until the
+ * thread's next brt_* call. */
+const char* brt_last_error(void);
+
+/* Create a context on HIP device `device`.  The context owns device scratch, cached graphs and
+ * launch settings.  Errors: BRT_E_DEVICE, BRT_E_NOMEM. */
+int brt_create(brt_ctx** out, int device);
+void brt_destroy(brt_ctx* ctx);
+
+/* Validate a problem and its Monte Carlo parameters (host only). */
+int brt_problem_check(const brt_problem* problem, const brt_mc* mc);
+
+/* Set / get the launch settings used by plans created afterwards. */
+int brt_set_launch(brt_ctx* ctx, const brt_launch* launch);
+int brt_get_launch(brt_ctx* ctx, brt_launch* launch);
+
+/* Build a plan: normalise the problems (Strategy A change of variables of Sec. 2.1: u = v e^{mu t},
+ * mu = c_1 + lambda, vertex weight K c_j / lambda e^{(j-1) mu tau}), upload the point records, cut
+ * every point's trees into work chunks ordered by estimated cost, and reserve device scratch
+ * (tree records unless the caller supplies brt_out.tree_f/tree_meta).  Host arrays are copied.
+ * At most 16 problems per plan; all of one dim and u0_kind. */
+int brt_plan_create(brt_ctx* ctx, uint32_t n_problems, const brt_problem* problems, const brt_mc* mc,
+                    const brt_points* points, brt_plan** out);
+
+/* Run a plan on `stream`: tree walk (persistent, work-stealing), per-bin moment reduction and the
+ * FP64 finalize (coefficients, covariance, Pade, SE).  Asynchronous; the first run with a given
+ * brt_out is captured into a HIP graph and later runs with the same brt_out replay it. */
+int brt_plan_execute(brt_plan* plan, const brt_out* out, void* stream);
+
+/* Totals of a plan (host): number of points, trees, bins B, work chunks. */
+int brt_plan_info(const brt_plan* plan, uint32_t* n_points, uint64_t* n_trees, uint32_t* n_bins,
+                  uint32_t* n_chunks);
+
+/* Device-side count of trees that exceeded the stack depth in the last run (synchronises). */
+int brt_plan_depth_exceeded(brt_plan* plan, uint64_t* count);
+
+void brt_plan_destroy(brt_plan* plan);
+
+/* One-shot: plan_create + plan_execute + synchronise + plan_destroy.  Returns BRT_E_RANGE if any
+ * tree exceeded the stack depth (other results are still written). */
+int brt_solve(brt_ctx* ctx, uint32_t n_problems, const brt_problem* problems, const brt_mc* mc,
+              const brt_points* points, const brt_out* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BRT_H */

@@ -260,18 +260,24 @@ def pade_coeffs(a, L: int, M: int):
 
     Defined by P(z) - Q(z) F(z) = O(z^{L+M+1}): for k = L+1..L+M,
     sum_{j=0}^{M} q_j a_{k-j} = 0 (a_i = 0 for i < 0); then
-    p_i = sum_{j=0}^{min(i,M)} q_j a_{i-j}.  Raises numpy.linalg.LinAlgError
-    when the M x M system is singular.
+    p_i = sum_{j=0}^{min(i,M)} q_j a_{i-j}.  The M x M system is solved by LU with
+    partial pivoting; it counts as singular (numpy.linalg.LinAlgError) when an
+    entry is not finite or the smallest pivot is below 1e-13 times the largest.
     """
+    from scipy.linalg import lu_factor, lu_solve
+
     a = np.asarray(a, dtype=np.float64)
     coef = lambda i: a[i] if i >= 0 else 0.0  # noqa: E731
     q = np.ones(M + 1)
     if M > 0:
         T = np.array([[coef(L + i - j) for j in range(1, M + 1)] for i in range(1, M + 1)])
         rhs = -np.array([coef(L + i) for i in range(1, M + 1)])
-        if not np.all(np.isfinite(T)) or np.linalg.cond(T) > 1e14:
+        if not (np.all(np.isfinite(T)) and np.all(np.isfinite(rhs))):
+            raise np.linalg.LinAlgError("non-finite Pade system")
+        piv = np.abs(np.diag(lu_factor(T, check_finite=False)[0])) if np.any(T) else np.zeros(M)
+        if piv.max() == 0.0 or piv.min() <= 1e-13 * piv.max():
             raise np.linalg.LinAlgError("singular Pade system")
-        q[1:] = np.linalg.solve(T, rhs)
+        q[1:] = lu_solve(lu_factor(T, check_finite=False), rhs, check_finite=False)
     p = np.array([sum(q[j] * coef(i - j) for j in range(0, min(i, M) + 1)) for i in range(L + 1)])
     return p, q
 
@@ -331,7 +337,7 @@ def solve(problem: dict, mc: dict, x, t, n_trees, point_ids=None, nthreads: int 
         series = a[: no + 1]
         try:
             val, used, q = pade_value(series, L, M)
-            se = pade_se(series, cov[: no + 1, : no + 1], *used)
+            se = pade_se(series, cov[: no + 1, : no + 1], L, M)
         except np.linalg.LinAlgError:
             val, used, q, se = float("nan"), (L, 0), np.ones(1), float("nan")
         out.append({"moments": mom, "a": a, "cov": cov, "pade": val, "pade_order": used, "pade_q": q,

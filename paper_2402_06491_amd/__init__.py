@@ -1,0 +1,288 @@
+"""Random-tree Monte Carlo solver for semilinear parabolic PDEs on MI355X (gfx950).
+
+Thin ctypes binding over ``libbrt.so`` (the C ABI of ``include/brt.h``): argument marshalling only.
+Every step of the method (tree walk, moment reduction, coefficients, Pade) runs in the library's HIP
+kernels.  PyTorch provides device memory and streams.  If the library is missing, every entry point
+raises; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libbrt.so")
+
+BRT_OK = 0
+ERRORS = {-1: "BRT_E_ARG", -2: "BRT_E_DEVICE", -3: "BRT_E_NOMEM", -4: "BRT_E_BUSY", -5: "BRT_E_RANGE",
+          -6: "BRT_E_STATE"}
+U0_KINDS = {"const": 0, "logistic": 1, "gauss_sum": 2, "cos2_bump": 3}
+FLAG_POLE, FLAG_LOWERED, FLAG_OVERFLOW, FLAG_CAPPED, FLAG_DEPTH = 1, 2, 4, 8, 16
+META_OVERFLOW, META_CAPPED, META_DEPTH, META_NODES_SHIFT = 1 << 8, 1 << 9, 1 << 10, 11
+
+
+class BrtError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("dim", ctypes.c_uint32), ("diffusion", ctypes.c_double),
+                ("coef", ctypes.c_double * 8), ("u0_kind", ctypes.c_uint32), ("u0_nterms", ctypes.c_uint32),
+                ("u0_params", ctypes.c_double * 40)]
+
+
+class MC(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("precision", ctypes.c_uint32), ("seed", ctypes.c_uint64),
+                ("lambda_", ctypes.c_double), ("max_order", ctypes.c_uint32), ("prune", ctypes.c_uint32),
+                ("node_cap", ctypes.c_uint32), ("pade_L", ctypes.c_uint32), ("pade_M", ctypes.c_uint32)]
+
+
+class Points(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("n", ctypes.c_uint32), ("x", ctypes.c_void_p),
+                ("t", ctypes.c_void_p), ("n_trees", ctypes.c_void_p), ("problem_id", ctypes.c_void_p),
+                ("point_id", ctypes.c_void_p)]
+
+
+class Out(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32)] + [
+        (name, ctypes.c_void_p) for name in
+        ("u", "se", "psum", "coef", "coef_var", "hist", "s1", "s2", "nodes", "flags", "tree_f", "tree_meta")]
+
+
+class Launch(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("waves_per_block", ctypes.c_uint32),
+                ("blocks_per_cu", ctypes.c_uint32), ("chunk_trees", ctypes.c_uint32),
+                ("stack_depth", ctypes.c_uint32)]
+
+
+_lib = None
+
+# (name, restype, argtypes) for every entry point of include/brt.h
+_SIGS = [
+    ("brt_version", ctypes.c_int, []),
+    ("brt_last_error", ctypes.c_char_p, []),
+    ("brt_create", ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int]),
+    ("brt_destroy", None, [ctypes.c_void_p]),
+    ("brt_problem_check", ctypes.c_int, [ctypes.POINTER(Problem), ctypes.POINTER(MC)]),
+    ("brt_set_launch", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Launch)]),
+    ("brt_get_launch", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Launch)]),
+    ("brt_plan_create", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.POINTER(Problem), ctypes.POINTER(MC),
+                                       ctypes.POINTER(Points), ctypes.POINTER(ctypes.c_void_p)]),
+    ("brt_plan_execute", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Out), ctypes.c_void_p]),
+    ("brt_plan_info", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32),
+                                     ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint32),
+                                     ctypes.POINTER(ctypes.c_uint32)]),
+    ("brt_plan_depth_exceeded", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
+    ("brt_plan_destroy", None, [ctypes.c_void_p]),
+    ("brt_solve", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.POINTER(Problem), ctypes.POINTER(MC),
+                                 ctypes.POINTER(Points), ctypes.POINTER(Out), ctypes.c_void_p]),
+]
+
+
+def lib():
+    """Load libbrt.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2402_06491_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in _SIGS:
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != BRT_OK:
+        raise BrtError(rc, lib().brt_last_error().decode())
+    return rc
+
+
+def make_problem(d: dict) -> Problem:
+    p = Problem()
+    p.struct_size = ctypes.sizeof(Problem)
+    p.dim = int(d["dim"])
+    p.diffusion = float(d["diffusion"])
+    coef = list(d["coef"]) + [0.0] * (8 - len(d["coef"]))
+    for j in range(8):
+        p.coef[j] = float(coef[j])
+    kind = d["u0_kind"]
+    p.u0_kind = U0_KINDS[kind] if isinstance(kind, str) else int(kind)
+    p.u0_nterms = int(d.get("u0_nterms", 0))
+    for i, v in enumerate(d.get("u0_params", [])):
+        p.u0_params[i] = float(v)
+    return p
+
+
+def make_mc(d: dict) -> MC:
+    m = MC()
+    m.struct_size = ctypes.sizeof(MC)
+    m.precision = int(d.get("precision", 32))
+    m.seed = int(d.get("seed", 0))
+    m.lambda_ = float(d.get("lambda", 1.0))
+    m.max_order = int(d.get("max_order", 12))
+    m.prune = int(d.get("prune", 1))
+    m.node_cap = int(d.get("node_cap", 1 << 16))
+    m.pade_L = int(d.get("pade_L", 6))
+    m.pade_M = int(d.get("pade_M", 6))
+    return m
+
+
+class Context:
+    """A brt_ctx on one HIP device."""
+
+    def __init__(self, device: int = 0):
+        self._h = ctypes.c_void_p()
+        _check(lib().brt_create(ctypes.byref(self._h), int(device)))
+        self.device = device
+
+    def set_launch(self, waves_per_block=4, blocks_per_cu=0, chunk_trees=1024, stack_depth=0):
+        l = Launch(ctypes.sizeof(Launch), waves_per_block, blocks_per_cu, chunk_trees, stack_depth)
+        _check(lib().brt_set_launch(self._h, ctypes.byref(l)))
+
+    def get_launch(self) -> dict:
+        l = Launch()
+        _check(lib().brt_get_launch(self._h, ctypes.byref(l)))
+        return {"waves_per_block": l.waves_per_block, "blocks_per_cu": l.blocks_per_cu,
+                "chunk_trees": l.chunk_trees, "stack_depth": l.stack_depth}
+
+    def close(self):
+        if self._h:
+            lib().brt_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _points(x, t, n_trees, problem_id, point_id, dim, keep):
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(-1, dim))
+    n = x.shape[0]
+    t = np.ascontiguousarray(np.broadcast_to(np.asarray(t, dtype=np.float64), (n,)))
+    nt = np.ascontiguousarray(np.broadcast_to(np.asarray(n_trees, dtype=np.uint64), (n,)))
+    pts = Points()
+    pts.struct_size = ctypes.sizeof(Points)
+    pts.n = n
+    pts.x, pts.t, pts.n_trees = x.ctypes.data, t.ctypes.data, nt.ctypes.data
+    keep += [x, t, nt]
+    if problem_id is not None:
+        pid = np.ascontiguousarray(np.asarray(problem_id, dtype=np.uint32).reshape(n))
+        pts.problem_id = pid.ctypes.data
+        keep.append(pid)
+    if point_id is not None:
+        qid = np.ascontiguousarray(np.asarray(point_id, dtype=np.uint32).reshape(n))
+        pts.point_id = qid.ctypes.data
+        keep.append(qid)
+    return pts, n, int(nt.sum())
+
+
+def alloc_outputs(n_points, n_bins, total_trees, precision, records=True, device="cuda"):
+    """Device tensors for every output of brt_out (torch supplies the memory)."""
+    import torch
+
+    o = {
+        "u": torch.empty(n_points, dtype=torch.float64, device=device),
+        "se": torch.empty(n_points, dtype=torch.float64, device=device),
+        "psum": torch.empty(n_points, dtype=torch.float64, device=device),
+        "coef": torch.empty((n_points, n_bins), dtype=torch.float64, device=device),
+        "coef_var": torch.empty((n_points, n_bins), dtype=torch.float64, device=device),
+        "hist": torch.empty((n_points, n_bins + 3), dtype=torch.int64, device=device),
+        "s1": torch.empty((n_points, n_bins), dtype=torch.float64, device=device),
+        "s2": torch.empty((n_points, n_bins), dtype=torch.float64, device=device),
+        "nodes": torch.empty(n_points, dtype=torch.int64, device=device),
+        "flags": torch.empty(n_points, dtype=torch.int32, device=device),
+    }
+    if records:
+        o["tree_f"] = torch.empty(max(total_trees, 1), dtype=torch.float64, device=device)
+        o["tree_meta"] = torch.empty(max(total_trees, 1), dtype=torch.int32, device=device)
+    return o
+
+
+def make_out(tensors: dict) -> Out:
+    o = Out()
+    o.struct_size = ctypes.sizeof(Out)
+    for name, _ in Out._fields_[1:]:
+        v = tensors.get(name)
+        setattr(o, name, v.data_ptr() if v is not None else None)
+    return o
+
+
+def _stream_handle(stream):
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """brt_plan: normalised problems, uploaded points and work chunks, replayable on a stream."""
+
+    def __init__(self, ctx: Context, problems, mc: dict, x, t, n_trees, problem_id=None, point_id=None):
+        if isinstance(problems, dict):
+            problems = [problems]
+        self.ctx = ctx
+        self.mc = dict(mc)
+        self.dim = int(problems[0]["dim"])
+        arr = (Problem * len(problems))(*[make_problem(p) for p in problems])
+        m = make_mc(mc)
+        keep = []
+        pts, self.n_points, self.total_trees = _points(x, t, n_trees, problem_id, point_id, self.dim, keep)
+        self._h = ctypes.c_void_p()
+        _check(lib().brt_plan_create(ctx._h, len(problems), arr, ctypes.byref(m), ctypes.byref(pts),
+                                     ctypes.byref(self._h)))
+        npnt, ntr, nb, nch = ctypes.c_uint32(), ctypes.c_uint64(), ctypes.c_uint32(), ctypes.c_uint32()
+        _check(lib().brt_plan_info(self._h, ctypes.byref(npnt), ctypes.byref(ntr), ctypes.byref(nb), ctypes.byref(nch)))
+        self.n_bins, self.n_chunks = nb.value, nch.value
+        self.precision = int(mc.get("precision", 32))
+        self._out_cache = None
+
+    def outputs(self, records=True):
+        return alloc_outputs(self.n_points, self.n_bins, self.total_trees, self.precision, records)
+
+    def execute(self, tensors: dict, stream=None):
+        """Enqueue the whole path on `stream` (torch's current stream by default)."""
+        o = make_out(tensors)
+        _check(lib().brt_plan_execute(self._h, ctypes.byref(o), _stream_handle(stream)))
+
+    def depth_exceeded(self) -> int:
+        v = ctypes.c_uint64()
+        _check(lib().brt_plan_depth_exceeded(self._h, ctypes.byref(v)))
+        return v.value
+
+    def close(self):
+        if self._h:
+            lib().brt_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve(ctx: Context, problems, mc: dict, x, t, n_trees, problem_id=None, point_id=None, records=True,
+          stream=None):
+    """One-shot brt_solve; returns the output tensors (on the GPU)."""
+    if isinstance(problems, dict):
+        problems = [problems]
+    arr = (Problem * len(problems))(*[make_problem(p) for p in problems])
+    m = make_mc(mc)
+    keep = []
+    pts, n, total = _points(x, t, n_trees, problem_id, point_id, int(problems[0]["dim"]), keep)
+    nb = int(mc.get("max_order", 12)) + 2
+    tensors = alloc_outputs(n, nb, total, int(mc.get("precision", 32)), records)
+    o = make_out(tensors)
+    _check(lib().brt_solve(ctx._h, len(problems), arr, ctypes.byref(m), ctypes.byref(pts), ctypes.byref(o),
+                           _stream_handle(stream)))
+    return tensors

@@ -1,0 +1,135 @@
+// Internal layouts shared by the HIP kernels and the host runtime of libbrt.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "brt.h"
+
+namespace brt {
+
+constexpr int kWave = 64;
+constexpr int kMaxProblems = 16;
+constexpr int kMaxU0Params = 32;
+
+// tree_meta bit layout
+constexpr uint32_t kMetaNeMask = 0xffu;
+constexpr uint32_t kMetaOverflow = 1u << 8;
+constexpr uint32_t kMetaCapped = 1u << 9;
+constexpr uint32_t kMetaDepth = 1u << 10;
+constexpr int kMetaNodesShift = 11;
+constexpr uint32_t kMaxNodeCap = (1u << 21) - 1;  // nodes field is 21 bits
+
+// Per-problem constants after the Strategy A normalisation, in the walker's precision.
+template <typename Real>
+struct PdeT {
+  Real sigma;        // sqrt(2a)
+  Real inv_lambda;   // 1/lambda (unused when K == 0)
+  Real mu;           // c_1 + lambda
+  uint32_t K;        // number of non-linear terms
+  uint32_t jpack;    // their powers, 4 bits each, ascending
+  uint32_t u0_nterms;
+  uint32_t pad0, pad1;
+  Real omega[8];     // K c_j / lambda
+  Real u0[kMaxU0Params];
+};
+
+// Per-point record (device).
+struct PointRec {
+  double x[2];
+  double t;
+  double theta;      // exp(-lambda t) from the host (1 when K == 0)
+  double mu;         // for the finalize
+  uint64_t tree_base;
+  uint32_t n_trees;
+  uint32_t point_id; // Philox counter word 2
+  uint32_t pde;
+  uint32_t seg_begin;  // first reduction segment of this point
+  uint32_t seg_count;
+  uint32_t pad;
+};
+
+// A walker work chunk: trees [begin, end) of one point.
+struct Chunk {
+  uint32_t point;
+  uint32_t begin;
+  uint32_t end;
+  uint32_t pad;
+};
+
+// A reduction segment: trees [begin, end) of one point.
+struct Segment {
+  uint32_t point;
+  uint32_t begin;
+  uint32_t end;
+  uint32_t pad;
+};
+
+// Per (segment, bin) partial moments.
+struct Partial {
+  uint64_t count;
+  double s1;
+  double s2;
+};
+
+struct WalkArgs {
+  const PointRec* points;
+  const Chunk* chunks;
+  uint32_t n_chunks;
+  uint32_t n_problems;
+  const void* pdes;          // PdeT<Real>[n_problems]
+  uint32_t* chunk_counter;   // reset before each launch
+  unsigned long long* depth_counter;
+  double* tree_f;
+  uint32_t* tree_meta;
+  void* spill;               // global stack levels beyond the LDS part: [spill_depth][entry fields][n_threads]
+  uint32_t key0, key1;
+  uint32_t max_order;
+  uint32_t prune;
+  uint32_t node_cap;
+  uint32_t stack_depth;      // LDS levels per lane
+  uint32_t spill_depth;      // global levels per lane
+  uint32_t n_threads;        // grid size in threads (spill stride)
+};
+
+struct ReduceArgs {
+  const PointRec* points;
+  const Segment* segs;
+  uint32_t n_segs;
+  const double* tree_f;
+  const uint32_t* tree_meta;
+  Partial* partials;         // [n_segs][n_bins + 3]
+  unsigned long long* seg_nodes;  // [n_segs]
+  uint32_t n_bins;           // B = max_order + 2
+};
+
+struct FinalizeArgs {
+  const PointRec* points;
+  uint32_t n_points;
+  const Partial* partials;
+  const unsigned long long* seg_nodes;
+  uint32_t n_bins;
+  uint32_t pade_L, pade_M;
+  double* u;
+  double* se;
+  double* psum;
+  double* coef;
+  double* coef_var;
+  unsigned long long* hist;
+  double* s1;
+  double* s2;
+  unsigned long long* nodes;
+  uint32_t* flags;
+};
+
+// Launchers (brt_kernels.hip).
+hipError_t launch_reset(uint32_t* chunk_counter, unsigned long long* depth_counter, hipStream_t s);
+hipError_t launch_walk(int precision, int dim, int u0_kind, const WalkArgs& a, int grid, int waves_per_block,
+                       hipStream_t s);
+hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
+hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s);
+size_t walk_lds_bytes(int precision, int dim, int stack_depth, int waves_per_block);
+size_t stack_entry_size(int precision, int dim);
+int walk_max_blocks_per_cu(int precision, int dim, int u0_kind, int stack_depth, int waves_per_block);
+
+}  // namespace brt

@@ -1,0 +1,778 @@
+// HIP kernels of the random-tree Monte Carlo (Strategy A, Sec. 2.1) for gfx950.
+//
+//  walk_kernel      persistent, work-stealing tree walker: one tree per lane, one node per loop
+//                   iteration, explicit per-lane DFS stack in LDS, lanes refilled from the wave's
+//                   chunk with ballot/popcount; writes one record (value, splits, nodes, flags)
+//                   per tree.
+//  reduce_kernel    per (point, segment of trees): per-bin count / sum F / sum F^2 with per-lane
+//                   LDS accumulators and a fixed-order wave reduction (deterministic).
+//  finalize_kernel  per point, FP64: compensated sum over segments, coefficients
+//                   a_n = e^{mu t} S1_n / N and variances, Pade [L/M] at z = 1 by Gaussian
+//                   elimination, delta-method SE.
+//
+// The walker computes no MFMA work: nothing here is a dense contraction.  It is bound by VALU
+// issue (Philox integer multiplies and transcendentals).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "brt_internal.h"
+
+namespace brt {
+
+// ------------------------------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of two 32x32->64 multiplies and
+// xors, with the Weyl key schedule.  The key is wave-uniform (kernel argument) so its schedule runs
+// on the scalar unit.
+// ------------------------------------------------------------------------------------------------
+struct U4 {
+  uint32_t a, b, c, d;
+};
+
+__device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                            uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return U4{c0, c1, c2, c3};
+}
+
+// ------------------------------------------------------------------------------------------------
+// Precision-dependent elementary functions.
+// FP32: hardware log2/exp2/sqrt/sin/cos (v_log_f32, v_exp_f32, v_sqrt_f32, v_sin_f32, v_cos_f32;
+// the sin/cos units take their argument in revolutions, which is exactly the Box-Muller angle u2).
+// FP64: the device math library.
+// ------------------------------------------------------------------------------------------------
+template <typename Real>
+struct Math;
+
+template <>
+struct Math<float> {
+  static __device__ __forceinline__ float ln(float x) { return __builtin_amdgcn_logf(x) * 0.69314718055994531f; }
+  static __device__ __forceinline__ float ex(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
+  static __device__ __forceinline__ float sq(float x) { return __builtin_amdgcn_sqrtf(x); }
+  static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+  // sin and cos of 2*pi*u for u in [0, 1)
+  static __device__ __forceinline__ void sincos_rev(float u, float* s, float* c) {
+    *s = __builtin_amdgcn_sinf(u);
+    *c = __builtin_amdgcn_cosf(u);
+  }
+  static __device__ __forceinline__ float cos_half_pi(float v) {  // cos(pi v / 2) = cos(2 pi (v/4))
+    return __builtin_amdgcn_cosf(0.25f * v);
+  }
+};
+
+template <>
+struct Math<double> {
+  static __device__ __forceinline__ double ln(double x) { return log(x); }
+  static __device__ __forceinline__ double ex(double x) { return exp(x); }
+  static __device__ __forceinline__ double sq(double x) { return sqrt(x); }
+  static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+  static __device__ __forceinline__ void sincos_rev(double u, double* s, double* c) { sincospi(2.0 * u, s, c); }
+  static __device__ __forceinline__ double cos_half_pi(double v) { return cospi(0.5 * v); }
+};
+
+// ------------------------------------------------------------------------------------------------
+// Initial data g at the end of a leaf path.
+// ------------------------------------------------------------------------------------------------
+template <typename Real, int DIM, int U0>
+__device__ __forceinline__ Real eval_g(const PdeT<Real>& pd, const Real* x) {
+  const Real* p = pd.u0;
+  if constexpr (U0 == 0) {
+    return p[0];
+  } else if constexpr (U0 == 1) {
+    Real nx = x[0] * p[4];
+    if constexpr (DIM == 2) nx += x[1] * p[5];
+    const Real e = Math<Real>::ex(p[1] * (nx - p[2]));
+    const Real base = Math<Real>::rcp((Real)1 + e);
+    Real r = base;
+    const int pw = (int)p[3];
+    for (int i = 1; i < pw; ++i) r *= base;
+    return p[0] * r;
+  } else if constexpr (U0 == 2) {
+    Real acc = 0;
+    for (uint32_t k = 0; k < pd.u0_nterms; ++k) {
+      const Real* q = p + 4 * k;
+      const Real dx = x[0] - q[1];
+      Real r2 = dx * dx;
+      if constexpr (DIM == 2) {
+        const Real dy = x[1] - q[2];
+        r2 += dy * dy;
+      }
+      acc += q[0] * Math<Real>::ex(-r2 * q[3]);  // q[3] holds 1/(2 s^2) on the device
+    }
+    return acc;
+  } else {
+    const Real ax = x[0] < 0 ? -x[0] : x[0];
+    if (ax > p[1]) return 0;
+    const Real cx = Math<Real>::cos_half_pi(x[0] / p[1]);
+    Real v = p[0] * cx * cx;
+    if constexpr (DIM == 2) {
+      const Real ay = x[1] < 0 ? -x[1] : x[1];
+      if (ay > p[2]) return 0;
+      const Real cy = Math<Real>::cos_half_pi(x[1] / p[2]);
+      v *= cy * cy;
+    }
+    return v;
+  }
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const uint32_t lane = __lane_id();
+  return (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+}
+
+template <typename Real, int DIM>
+__host__ __device__ constexpr size_t stack_entry_bytes() {
+  return sizeof(double) + (DIM + 1) * sizeof(Real) + 1;
+}
+
+template <typename Real>
+__host__ __device__ constexpr size_t pde_table_bytes(int n) {
+  return ((size_t)n * sizeof(PdeT<Real>) + 15) & ~(size_t)15;
+}
+
+// ------------------------------------------------------------------------------------------------
+// Per-lane DFS stack.  An entry is pushed for each vertex that still has children to start: the
+// state its children depart from (clock product P, position, time left) and the number of children
+// not yet started.  The top `lds_depth` levels live in LDS (structure of arrays, one slot per lane so
+// lanes never conflict), deeper levels in a per-thread global spill area.
+// ------------------------------------------------------------------------------------------------
+template <typename Real, int DIM>
+struct Stack {
+  double* P;      // LDS [lds_depth][64]
+  Real* X;        // LDS [DIM][lds_depth][64]
+  Real* T;        // LDS [lds_depth][64]
+  uint8_t* R;     // LDS [lds_depth][64]
+  double* gP;     // global [spill_depth][n_threads]
+  Real* gX;       // global [DIM][spill_depth][n_threads]
+  Real* gT;       // global [spill_depth][n_threads]
+  uint8_t* gR;    // global [spill_depth][n_threads]
+  uint32_t lds_depth, spill_depth, n_threads, lane, gtid;
+
+  __device__ __forceinline__ void push(uint32_t sp, double p, const Real* x, Real t, uint32_t rem) {
+    if (sp < lds_depth) {
+      const uint32_t o = sp * kWave + lane;
+      P[o] = p;
+      X[o] = x[0];
+      if constexpr (DIM == 2) X[lds_depth * kWave + o] = x[1];
+      T[o] = t;
+      R[o] = (uint8_t)rem;
+    } else {
+      const size_t o = (size_t)(sp - lds_depth) * n_threads + gtid;
+      gP[o] = p;
+      gX[o] = x[0];
+      if constexpr (DIM == 2) gX[(size_t)spill_depth * n_threads + o] = x[1];
+      gT[o] = t;
+      gR[o] = (uint8_t)rem;
+    }
+  }
+  // Read the top entry (level sp-1) into the departure state; returns the number of children still
+  // to start after the one about to be visited, and stores it back.
+  __device__ __forceinline__ uint32_t top(uint32_t sp, double* p, Real* x, Real* t) {
+    const uint32_t lv = sp - 1;
+    uint32_t rem;
+    if (lv < lds_depth) {
+      const uint32_t o = lv * kWave + lane;
+      *p = P[o];
+      x[0] = X[o];
+      if constexpr (DIM == 2) x[1] = X[lds_depth * kWave + o];
+      *t = T[o];
+      rem = (uint32_t)R[o] - 1u;
+      R[o] = (uint8_t)rem;
+    } else {
+      const size_t o = (size_t)(lv - lds_depth) * n_threads + gtid;
+      *p = gP[o];
+      x[0] = gX[o];
+      if constexpr (DIM == 2) x[1] = gX[(size_t)spill_depth * n_threads + o];
+      *t = gT[o];
+      rem = (uint32_t)gR[o] - 1u;
+      gR[o] = (uint8_t)rem;
+    }
+    return rem;
+  }
+};
+
+// ------------------------------------------------------------------------------------------------
+// The walker.
+// ------------------------------------------------------------------------------------------------
+template <typename Real, int DIM, int U0>
+__global__ __launch_bounds__(1024) void walk_kernel(WalkArgs a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+
+  // problem table -> LDS
+  PdeT<Real>* pdes = reinterpret_cast<PdeT<Real>*>(smem);
+  {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(a.pdes);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(smem);
+    const uint32_t words = (uint32_t)(a.n_problems * sizeof(PdeT<Real>) / 4);
+    for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) dst[i] = src[i];
+  }
+  __syncthreads();
+
+  const uint32_t lane = __lane_id();
+  const uint32_t wave = threadIdx.x / kWave;
+  Stack<Real, DIM> st;
+  {
+    const uint32_t depth = a.stack_depth;
+    unsigned char* wbase = smem + pde_table_bytes<Real>(a.n_problems) +
+                           (size_t)wave * depth * kWave * stack_entry_bytes<Real, DIM>();
+    st.P = reinterpret_cast<double*>(wbase);
+    st.X = reinterpret_cast<Real*>(st.P + depth * kWave);
+    st.T = st.X + DIM * depth * kWave;
+    st.R = reinterpret_cast<uint8_t*>(st.T + depth * kWave);
+    const size_t sd = (size_t)a.spill_depth * a.n_threads;
+    st.gP = reinterpret_cast<double*>(a.spill);
+    st.gX = reinterpret_cast<Real*>(st.gP + sd);
+    st.gT = st.gX + DIM * sd;
+    st.gR = reinterpret_cast<uint8_t*>(st.gT + sd);
+    st.lds_depth = depth;
+    st.spill_depth = a.spill_depth;
+    st.n_threads = a.n_threads;
+    st.lane = lane;
+    st.gtid = blockIdx.x * blockDim.x + threadIdx.x;
+  }
+  const uint32_t max_depth = a.stack_depth + a.spill_depth;
+
+  const uint64_t lt = lanemask_lt();
+  const uint32_t node_cap = a.node_cap;
+  const uint32_t max_order = a.max_order;
+  const bool prune = a.prune != 0;
+
+  // wave-uniform chunk cursor
+  uint32_t c_next = 0, c_end = 0, c_point = 0;
+  bool more = true;
+
+  // per-lane tree state
+  bool active = false;
+  uint32_t tree = 0, node = 0, ne = 0, flags = 0, sp = 0, pid = 0, pde = 0;
+  uint64_t rec = 0;
+  double P = 1.0, theta = 1.0;
+  double F = 1.0;  // running product of the tree's factors (FP64 for range: weights reach e^{32} per vertex)
+  Real tau = 0;
+  Real x[2] = {0, 0};
+  Real sigma = 0, inv_lambda = 0, mu = 0;
+  uint32_t K = 0, jpack = 0;
+
+  while (true) {
+    // ---- refill idle lanes from the wave's chunk, stealing new chunks as needed ----
+    uint64_t need = __ballot(!active);
+    while (need != 0 && more) {
+      if (c_next == c_end) {
+        uint32_t ci = 0;
+        if (lane == 0) ci = atomicAdd(a.chunk_counter, 1u);
+        ci = __shfl(ci, 0);
+        if (ci >= a.n_chunks) {
+          more = false;
+          break;
+        }
+        const Chunk ch = a.chunks[ci];
+        c_next = ch.begin;
+        c_end = ch.end;
+        c_point = ch.point;
+        continue;
+      }
+      const uint32_t avail = c_end - c_next;
+      const uint32_t cnt = (uint32_t)__popcll(need);
+      const uint32_t take = cnt < avail ? cnt : avail;
+      const uint32_t rank = (uint32_t)__popcll(need & lt);
+      const bool mine = ((need >> lane) & 1ull) && rank < take;
+      if (mine) {
+        const PointRec& pr = a.points[c_point];
+        tree = c_next + rank;
+        pid = pr.point_id;
+        pde = pr.pde;
+        rec = pr.tree_base + tree;
+        theta = pr.theta;
+        tau = (Real)pr.t;
+        x[0] = (Real)pr.x[0];
+        x[1] = (Real)pr.x[1];
+        P = 1.0;
+        F = 1.0;
+        node = 0;
+        ne = 0;
+        flags = 0;
+        sp = 0;
+        const PdeT<Real>& pd = pdes[pde];
+        sigma = pd.sigma;
+        inv_lambda = pd.inv_lambda;
+        mu = pd.mu;
+        K = pd.K;
+        jpack = pd.jpack;
+        active = true;
+      }
+      need &= ~__ballot(mine);
+      c_next += take;
+    }
+    if (__ballot(active) == 0) break;
+    if (!active) continue;
+
+    // ---- one node of this lane's tree ----
+    bool done = false;
+    bool branch_end = false;
+    if (node >= node_cap) {
+      flags |= kMetaCapped;
+      done = true;
+    } else {
+      const U4 w = philox4x32_10(node, tree, pid, 0u, a.key0, a.key1);
+      node += 1;
+      const double U = ((double)w.a + 0.5) * 0x1p-32;
+      const double Pn = P * U;
+      const bool vertex = Pn > theta;
+
+      const Real u1 = ((Real)w.c + (Real)0.5) * (Real)0x1p-32;
+      const Real u2 = (Real)w.d * (Real)0x1p-32;
+      const Real r = Math<Real>::sq((Real)-2 * Math<Real>::ln(u1));
+      Real sn, cs;
+      Math<Real>::sincos_rev(u2, &sn, &cs);
+      const Real S = -Math<Real>::ln((Real)U) * inv_lambda;
+      const Real dt = vertex ? S : tau;
+      const Real sd = sigma * Math<Real>::sq(dt);
+      Real xn[2];
+      xn[0] = x[0] + sd * (r * cs);
+      xn[1] = x[1] + sd * (r * sn);
+
+      if (vertex) {
+        ne += 1;
+        if (prune && ne > max_order) {
+          flags |= kMetaOverflow;
+          done = true;
+        } else {
+          Real tau2 = tau - S;
+          tau2 = tau2 < (Real)0 ? (Real)0 : tau2;
+          const uint32_t idx = __umulhi(w.b, K);
+          const uint32_t alpha = (jpack >> (4 * idx)) & 15u;
+          const Real om = pdes[pde].omega[idx];
+          F *= (double)(om * Math<Real>::ex((Real)((int)alpha - 1) * mu * tau2));
+          if (alpha == 0) {
+            branch_end = true;
+          } else {
+            if (alpha >= 2) {
+              if (sp == max_depth) {
+                flags |= kMetaDepth;
+                done = true;
+              } else {
+                st.push(sp, Pn, xn, tau2, alpha - 1);
+                sp += 1;
+              }
+            }
+            x[0] = xn[0];
+            x[1] = xn[1];
+            P = Pn;
+            tau = tau2;
+          }
+        }
+      } else {
+        F *= (double)eval_g<Real, DIM, U0>(pdes[pde], xn);
+        branch_end = true;
+      }
+      if (branch_end) {
+        if (sp == 0) {
+          done = true;
+        } else {
+          const uint32_t rem = st.top(sp, &P, x, &tau);
+          if (rem == 0) sp -= 1;
+        }
+      }
+    }
+    if (done) {
+      a.tree_f[rec] = flags ? 0.0 : F;
+      a.tree_meta[rec] = (ne < 255u ? ne : 255u) | flags | (node << kMetaNodesShift);
+      if (flags & kMetaDepth) atomicAdd(a.depth_counter, 1ull);
+      active = false;
+    }
+  }
+}
+
+__global__ void reset_kernel(uint32_t* chunk_counter, unsigned long long* depth_counter) {
+  if (threadIdx.x == 0) {
+    *chunk_counter = 0u;
+    *depth_counter = 0ull;
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Reduction: one wave per segment of one point's trees.
+// Bins: 0..B-1 (B-1 is the tail: Ne > max_order without pruning), then overflow, capped, depth
+// (counts only).
+// ------------------------------------------------------------------------------------------------
+constexpr int kRedGroup = 16;
+
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+__global__ __launch_bounds__(64) void reduce_kernel(ReduceArgs a) {
+  __shared__ double ls1[kRedGroup][kWave];
+  __shared__ double ls2[kRedGroup][kWave];
+  __shared__ uint32_t lcnt[kRedGroup][kWave];
+
+  const uint32_t seg = blockIdx.x;
+  const uint32_t lane = threadIdx.x;
+  const Segment sg = a.segs[seg];
+  const PointRec& pr = a.points[sg.point];
+  const double* F = a.tree_f + pr.tree_base;
+  const uint32_t* M = a.tree_meta + pr.tree_base;
+  const uint32_t B = a.n_bins;
+  const uint32_t NB = B + 3;
+  Partial* out = a.partials + (size_t)seg * NB;
+
+  unsigned long long nodes = 0;
+  for (uint32_t g0 = 0; g0 < NB; g0 += kRedGroup) {
+    for (int k = 0; k < kRedGroup; ++k) {
+      ls1[k][lane] = 0.0;
+      ls2[k][lane] = 0.0;
+      lcnt[k][lane] = 0u;
+    }
+    bool above = false;
+    for (uint32_t i = sg.begin + lane; i < sg.end; i += kWave) {
+      const uint32_t m = M[i];
+      const double f = F[i];
+      uint32_t bin;
+      if (m & kMetaOverflow)
+        bin = B;
+      else if (m & kMetaCapped)
+        bin = B + 1;
+      else if (m & kMetaDepth)
+        bin = B + 2;
+      else {
+        const uint32_t ne = m & kMetaNeMask;
+        bin = ne < B - 1 ? ne : B - 1;
+      }
+      if (g0 == 0) nodes += (unsigned long long)(m >> kMetaNodesShift);
+      if (bin >= g0 && bin < g0 + kRedGroup) {
+        const uint32_t k = bin - g0;
+        ls1[k][lane] += f;
+        ls2[k][lane] += f * f;
+        lcnt[k][lane] += 1u;
+      }
+      above |= bin >= g0 + kRedGroup;
+    }
+    for (int k = 0; k < kRedGroup; ++k) {
+      const uint32_t b = g0 + k;
+      const double v1 = wave_sum_f64(ls1[k][lane]);
+      const double v2 = wave_sum_f64(ls2[k][lane]);
+      const unsigned long long c = wave_sum_u64((unsigned long long)lcnt[k][lane]);
+      if (lane == 0 && b < NB) {
+        out[b].count = c;
+        out[b].s1 = v1;
+        out[b].s2 = v2;
+      }
+    }
+    if (__ballot(above) == 0) {
+      for (uint32_t b = g0 + kRedGroup + lane; b < NB; b += kWave) {
+        out[b].count = 0;
+        out[b].s1 = 0.0;
+        out[b].s2 = 0.0;
+      }
+      break;
+    }
+  }
+  nodes = wave_sum_u64(nodes);
+  if (lane == 0) a.seg_nodes[seg] = nodes;
+}
+
+// ------------------------------------------------------------------------------------------------
+// Finalize: one wave per point.
+// ------------------------------------------------------------------------------------------------
+constexpr int kMaxBins = 128;  // B = max_order + 2 <= 128
+constexpr int kMaxPadeM = 16;
+
+// [L/M] Pade approximant at z = 1 of sum_n a_n z^n: for k = L+1..L+M,
+// sum_{j=0}^{M} q_j a_{k-j} = 0 with q_0 = 1 (a_i = 0 for i < 0); p_i = sum_{j<=min(i,M)} q_j a_{i-j}.
+// Gaussian elimination with partial pivoting; the system is singular when the smallest pivot is
+// below 1e-13 times the largest.  On singularity the degree pair moves to [L+1/M-1] (same total
+// order), down to M = 0 (the partial sum).  Returns the value, writes q and the degrees used.
+__device__ double pade_eval(const double* a, int L, int M, double* q, int* Lused, int* Mused, double* T) {
+  while (true) {
+    bool ok = true;
+    q[0] = 1.0;
+    if (M > 0) {
+      // T is M x (M+1): columns 0..M-1 the matrix, column M the right-hand side
+      for (int i = 0; i < M; ++i) {
+        for (int j = 0; j < M; ++j) {
+          const int k = L + (i + 1) - (j + 1);
+          T[i * (M + 1) + j] = k >= 0 ? a[k] : 0.0;
+        }
+        T[i * (M + 1) + M] = -a[L + i + 1];
+      }
+      double pmax = 0.0, pmin = 1e308;
+      for (int c = 0; c < M; ++c) {
+        int piv = c;
+        double best = fabs(T[c * (M + 1) + c]);
+        for (int rr = c + 1; rr < M; ++rr) {
+          const double v = fabs(T[rr * (M + 1) + c]);
+          if (v > best) {
+            best = v;
+            piv = rr;
+          }
+        }
+        if (!(best == best) || best > 1e300) {  // NaN or overflow: give up on this order
+          ok = false;
+          break;
+        }
+        if (piv != c)
+          for (int j = 0; j <= M; ++j) {
+            const double tmp = T[c * (M + 1) + j];
+            T[c * (M + 1) + j] = T[piv * (M + 1) + j];
+            T[piv * (M + 1) + j] = tmp;
+          }
+        pmax = best > pmax ? best : pmax;
+        pmin = best < pmin ? best : pmin;
+        if (best == 0.0) {
+          ok = false;
+          break;
+        }
+        for (int rr = c + 1; rr < M; ++rr) {
+          const double fct = T[rr * (M + 1) + c] / T[c * (M + 1) + c];
+          for (int j = c; j <= M; ++j) T[rr * (M + 1) + j] -= fct * T[c * (M + 1) + j];
+        }
+      }
+      if (ok && pmin <= 1e-13 * pmax) ok = false;
+      if (ok) {
+        for (int i = M - 1; i >= 0; --i) {
+          double s = T[i * (M + 1) + M];
+          for (int j = i + 1; j < M; ++j) s -= T[i * (M + 1) + j] * q[j + 1];
+          q[i + 1] = s / T[i * (M + 1) + i];
+        }
+      }
+    }
+    if (ok || M == 0) break;
+    L += 1;
+    M -= 1;
+  }
+  double num = 0.0, den = 0.0;
+  for (int i = 0; i <= L; ++i) {
+    double pi = 0.0;
+    for (int j = 0; j <= (i < M ? i : M); ++j) pi += q[j] * a[i - j];
+    num += pi;
+  }
+  for (int j = 0; j <= M; ++j) den += q[j];
+  *Lused = L;
+  *Mused = M;
+  return num / den;
+}
+
+__global__ __launch_bounds__(64) void finalize_kernel(FinalizeArgs a) {
+  __shared__ double coef[kMaxBins];
+  __shared__ double m1[kMaxBins];
+  __shared__ double m2[kMaxBins];
+  __shared__ double work[kMaxBins];
+  __shared__ double T[kMaxPadeM * (kMaxPadeM + 1)];
+  __shared__ double q[kMaxPadeM + 1];
+
+  const uint32_t p = blockIdx.x;
+  const uint32_t lane = threadIdx.x;
+  const PointRec& pr = a.points[p];
+  const uint32_t B = a.n_bins;
+  const uint32_t NB = B + 3;
+  const double N = (double)pr.n_trees;
+  const double scale = exp(pr.mu * pr.t);
+
+  for (uint32_t b = lane; b < NB; b += kWave) {
+    // Neumaier-compensated sums over the point's segments, in segment order
+    double s1 = 0.0, c1 = 0.0, s2 = 0.0, c2 = 0.0;
+    unsigned long long cnt = 0;
+    for (uint32_t s = 0; s < pr.seg_count; ++s) {
+      const Partial& pt = a.partials[(size_t)(pr.seg_begin + s) * NB + b];
+      cnt += pt.count;
+      double t1 = s1 + pt.s1;
+      c1 += fabs(s1) >= fabs(pt.s1) ? (s1 - t1) + pt.s1 : (pt.s1 - t1) + s1;
+      s1 = t1;
+      double t2 = s2 + pt.s2;
+      c2 += fabs(s2) >= fabs(pt.s2) ? (s2 - t2) + pt.s2 : (pt.s2 - t2) + s2;
+      s2 = t2;
+    }
+    s1 += c1;
+    s2 += c2;
+    if (a.hist) a.hist[(size_t)p * NB + b] = cnt;
+    if (b < B) {
+      if (a.s1) a.s1[(size_t)p * B + b] = s1;
+      if (a.s2) a.s2[(size_t)p * B + b] = s2;
+      const double mm1 = N > 0 ? s1 / N : 0.0;
+      const double mm2 = N > 0 ? s2 / N : 0.0;
+      m1[b] = mm1;
+      m2[b] = mm2;
+      coef[b] = scale * mm1;
+      const double var = N > 1 ? scale * scale * (mm2 - mm1 * mm1) / (N - 1.0) : 0.0;
+      if (a.coef) a.coef[(size_t)p * B + b] = scale * mm1;
+      if (a.coef_var) a.coef_var[(size_t)p * B + b] = var;
+    }
+    if (b == B) work[0] = (double)cnt;      // overflow count
+    if (b == B + 1) work[1] = (double)cnt;  // capped count
+    if (b == B + 2) work[2] = (double)cnt;  // depth count
+  }
+  __syncthreads();
+  unsigned long long nodes = 0;
+  for (uint32_t s = lane; s < pr.seg_count; s += kWave) nodes += a.seg_nodes[pr.seg_begin + s];
+  nodes = wave_sum_u64(nodes);
+
+  if (lane == 0) {
+    uint32_t fl = 0;
+    if (work[0] > 0) fl |= BRT_FLAG_OVERFLOW;
+    if (work[1] > 0) fl |= BRT_FLAG_CAPPED;
+    if (work[2] > 0) fl |= BRT_FLAG_DEPTH;
+    double psum = 0.0;
+    for (uint32_t b = 0; b < B; ++b) psum += coef[b];
+    int Lu, Mu;
+    const int L = (int)a.pade_L, M = (int)a.pade_M;
+    const double u = pade_eval(coef, L, M, q, &Lu, &Mu, T);
+    if (Mu != M) fl |= BRT_FLAG_LOWERED;
+    // pole test: the denominator starts at Q(0) = 1; flag a non-positive value on [0, 1]
+    for (int k = 1; k <= 64; ++k) {
+      const double z = k / 64.0;
+      double qz = 0.0, zp = 1.0;
+      for (int j = 0; j <= Mu; ++j) {
+        qz += q[j] * zp;
+        zp *= z;
+      }
+      if (!(qz > 1e-8)) {
+        fl |= BRT_FLAG_POLE;
+        break;
+      }
+    }
+    // delta-method SE: central differences of the Pade value in each coefficient used
+    const int nuse = L + M + 1;
+    double g1 = 0.0, gv = 0.0;  // sum g_k^2 m2_k and sum g_k m1_k
+    for (int k = 0; k < nuse && k < (int)B; ++k) {
+      for (uint32_t b = 0; b < B; ++b) work[b] = coef[b];
+      const double h = coef[k] != 0.0 ? 1e-6 * fabs(coef[k]) : 1e-12;
+      int l2, m2u;
+      work[k] = coef[k] + h;
+      const double up = pade_eval(work, L, M, q + 0, &l2, &m2u, T);
+      work[k] = coef[k] - h;
+      const double dn = pade_eval(work, L, M, q + 0, &l2, &m2u, T);
+      const double gk = (up - dn) / (2.0 * h) * scale;  // d u / d m1_k
+      g1 += gk * gk * m2[k];
+      gv += gk * m1[k];
+    }
+    const double var = N > 1 ? (g1 - gv * gv) / (N - 1.0) : 0.0;
+    if (a.u) a.u[p] = u;
+    if (a.se) a.se[p] = sqrt(var > 0.0 ? var : 0.0);
+    if (a.psum) a.psum[p] = psum;
+    if (a.flags) a.flags[p] = fl;
+    if (a.nodes) a.nodes[p] = nodes;
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Launchers
+// ------------------------------------------------------------------------------------------------
+size_t stack_entry_size(int precision, int dim) {
+  if (precision == 32) return dim == 1 ? stack_entry_bytes<float, 1>() : stack_entry_bytes<float, 2>();
+  return dim == 1 ? stack_entry_bytes<double, 1>() : stack_entry_bytes<double, 2>();
+}
+
+size_t walk_lds_bytes(int precision, int dim, int stack_depth, int waves_per_block) {
+  const size_t sd = (size_t)stack_depth * kWave * waves_per_block;
+  if (precision == 32)
+    return pde_table_bytes<float>(kMaxProblems) +
+           sd * (dim == 1 ? stack_entry_bytes<float, 1>() : stack_entry_bytes<float, 2>());
+  return pde_table_bytes<double>(kMaxProblems) +
+         sd * (dim == 1 ? stack_entry_bytes<double, 1>() : stack_entry_bytes<double, 2>());
+}
+
+template <typename Real, int DIM, int U0>
+static const void* walk_ptr() {
+  return reinterpret_cast<const void*>(&walk_kernel<Real, DIM, U0>);
+}
+
+template <typename Real, int DIM>
+static const void* walk_ptr_u0(int u0) {
+  switch (u0) {
+    case 0: return walk_ptr<Real, DIM, 0>();
+    case 1: return walk_ptr<Real, DIM, 1>();
+    case 2: return walk_ptr<Real, DIM, 2>();
+    default: return walk_ptr<Real, DIM, 3>();
+  }
+}
+
+static const void* walk_fn(int precision, int dim, int u0) {
+  if (precision == 32) return dim == 1 ? walk_ptr_u0<float, 1>(u0) : walk_ptr_u0<float, 2>(u0);
+  return dim == 1 ? walk_ptr_u0<double, 1>(u0) : walk_ptr_u0<double, 2>(u0);
+}
+
+int walk_max_blocks_per_cu(int precision, int dim, int u0_kind, int stack_depth, int waves_per_block) {
+  int nb = 0;
+  const size_t lds = walk_lds_bytes(precision, dim, stack_depth, waves_per_block);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_fn(precision, dim, u0_kind), waves_per_block * kWave,
+                                                   lds) != hipSuccess)
+    return 0;
+  return nb;
+}
+
+hipError_t launch_reset(uint32_t* chunk_counter, unsigned long long* depth_counter, hipStream_t s) {
+  hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(64), 0, s, chunk_counter, depth_counter);
+  return hipGetLastError();
+}
+
+hipError_t launch_walk(int precision, int dim, int u0_kind, const WalkArgs& a, int grid, int waves_per_block,
+                       hipStream_t s) {
+  const size_t lds = walk_lds_bytes(precision, dim, (int)a.stack_depth, waves_per_block);
+  const dim3 g(grid), b(waves_per_block * kWave);
+  if (precision == 32) {
+    if (dim == 1) {
+      switch (u0_kind) {
+        case 0: hipLaunchKernelGGL((walk_kernel<float, 1, 0>), g, b, lds, s, a); break;
+        case 1: hipLaunchKernelGGL((walk_kernel<float, 1, 1>), g, b, lds, s, a); break;
+        case 2: hipLaunchKernelGGL((walk_kernel<float, 1, 2>), g, b, lds, s, a); break;
+        default: hipLaunchKernelGGL((walk_kernel<float, 1, 3>), g, b, lds, s, a); break;
+      }
+    } else {
+      switch (u0_kind) {
+        case 0: hipLaunchKernelGGL((walk_kernel<float, 2, 0>), g, b, lds, s, a); break;
+        case 1: hipLaunchKernelGGL((walk_kernel<float, 2, 1>), g, b, lds, s, a); break;
+        case 2: hipLaunchKernelGGL((walk_kernel<float, 2, 2>), g, b, lds, s, a); break;
+        default: hipLaunchKernelGGL((walk_kernel<float, 2, 3>), g, b, lds, s, a); break;
+      }
+    }
+  } else {
+    if (dim == 1) {
+      switch (u0_kind) {
+        case 0: hipLaunchKernelGGL((walk_kernel<double, 1, 0>), g, b, lds, s, a); break;
+        case 1: hipLaunchKernelGGL((walk_kernel<double, 1, 1>), g, b, lds, s, a); break;
+        case 2: hipLaunchKernelGGL((walk_kernel<double, 1, 2>), g, b, lds, s, a); break;
+        default: hipLaunchKernelGGL((walk_kernel<double, 1, 3>), g, b, lds, s, a); break;
+      }
+    } else {
+      switch (u0_kind) {
+        case 0: hipLaunchKernelGGL((walk_kernel<double, 2, 0>), g, b, lds, s, a); break;
+        case 1: hipLaunchKernelGGL((walk_kernel<double, 2, 1>), g, b, lds, s, a); break;
+        case 2: hipLaunchKernelGGL((walk_kernel<double, 2, 2>), g, b, lds, s, a); break;
+        default: hipLaunchKernelGGL((walk_kernel<double, 2, 3>), g, b, lds, s, a); break;
+      }
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
+  if (a.n_segs == 0) return hipSuccess;
+  hipLaunchKernelGGL(reduce_kernel, dim3(a.n_segs), dim3(kWave), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s) {
+  if (a.n_points == 0) return hipSuccess;
+  hipLaunchKernelGGL(finalize_kernel, dim3(a.n_points), dim3(kWave), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace brt

@@ -1,0 +1,574 @@
+// Host runtime of libbrt: contexts, plans (problem normalisation, chunking, device buffers),
+// HIP-graph capture/replay and the C ABI declared in include/brt.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "brt.h"
+#include "brt_internal.h"
+
+using namespace brt;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                          \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess) return fail(BRT_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr uint32_t kSegTrees = 1u << 16;  // trees per reduction segment
+constexpr uint32_t kMaxDepthUnpruned = 64; // stack levels per lane when trees are not pruned
+constexpr uint32_t kDefaultLdsLevels = 8;  // stack levels per lane kept in LDS by default
+
+// Strategy A normalisation of one problem (Sec. 2.1): u = v e^{mu t}, mu = c_1 + lambda, clock Exp(lambda),
+// arity uniform over the K non-zero non-linear terms, vertex weight K c_j / lambda e^{(j-1) mu tau}.
+struct Norm {
+  double sigma = 0, lambda = 0, inv_lambda = 0, mu = 0;
+  uint32_t K = 0;
+  uint32_t J[8] = {0};
+  double omega[8] = {0};
+};
+
+Norm normalize(const brt_problem& p, const brt_mc& mc) {
+  Norm n;
+  n.sigma = std::sqrt(2.0 * p.diffusion);
+  for (uint32_t j = 0; j < 8; ++j)
+    if (j != 1 && p.coef[j] != 0.0) n.J[n.K++] = j;
+  if (n.K == 0) {
+    n.lambda = 0.0;
+    n.inv_lambda = 0.0;
+    n.mu = p.coef[1];
+  } else {
+    n.lambda = mc.lambda;
+    n.inv_lambda = 1.0 / mc.lambda;
+    n.mu = p.coef[1] + mc.lambda;
+    for (uint32_t i = 0; i < n.K; ++i) n.omega[i] = (double)n.K * p.coef[n.J[i]] / mc.lambda;
+  }
+  return n;
+}
+
+template <typename Real>
+PdeT<Real> to_device(const brt_problem& p, const Norm& n) {
+  PdeT<Real> d;
+  std::memset(&d, 0, sizeof(d));
+  d.sigma = (Real)n.sigma;
+  d.inv_lambda = (Real)n.inv_lambda;
+  d.mu = (Real)n.mu;
+  d.K = n.K;
+  d.jpack = 0;
+  for (uint32_t i = 0; i < n.K; ++i) {
+    d.jpack |= n.J[i] << (4 * i);
+    d.omega[i] = (Real)n.omega[i];
+  }
+  d.u0_nterms = p.u0_nterms;
+  for (int i = 0; i < kMaxU0Params; ++i) d.u0[i] = (Real)p.u0_params[i];
+  if (p.u0_kind == BRT_U0_GAUSS_SUM)
+    for (uint32_t k = 0; k < p.u0_nterms; ++k) {
+      const double s = p.u0_params[4 * k + 3];
+      d.u0[4 * k + 3] = (Real)(1.0 / (2.0 * s * s));
+    }
+  return d;
+}
+
+// Expected nodes per tree (cost model for ordering work): with arities uniform over J the number of
+// lineages grows like e^{lambda (abar - 1) t}.
+double est_nodes(const Norm& n, const brt_mc& mc, double t) {
+  if (n.K == 0) return 1.0;
+  double abar = 0;
+  for (uint32_t i = 0; i < n.K; ++i) abar += n.J[i];
+  abar /= n.K;
+  double v;
+  if (std::fabs(abar - 1.0) < 1e-9)
+    v = 1.0 + n.lambda * t;
+  else
+    v = 1.0 + abar / (abar - 1.0) * std::expm1(std::min(50.0, n.lambda * (abar - 1.0) * t));
+  if (mc.prune) v = std::min(v, 1.0 + abar * (mc.max_order + 1));
+  return std::max(1.0, std::min(v, (double)mc.node_cap));
+}
+
+bool is_fin(double v) { return std::isfinite(v); }
+
+}  // namespace
+
+struct brt_ctx {
+  int device = 0;
+  int n_cu = 0;
+  brt_launch launch{};
+};
+
+struct brt_plan {
+  brt_ctx* ctx = nullptr;
+  int precision = 32, dim = 1, u0_kind = 0;
+  uint32_t n_problems = 0, n_points = 0, n_bins = 0;
+  uint64_t total_trees = 0;
+  brt_mc mc{};
+  std::vector<PointRec> points;
+  std::vector<Chunk> chunks;
+  std::vector<Segment> segs;
+  // device
+  PointRec* d_points = nullptr;
+  Chunk* d_chunks = nullptr;
+  Segment* d_segs = nullptr;
+  void* d_pdes = nullptr;
+  uint32_t* d_counter = nullptr;
+  unsigned long long* d_depth = nullptr;
+  double* d_tree_f = nullptr;
+  uint32_t* d_tree_meta = nullptr;
+  void* d_spill = nullptr;
+  Partial* d_partials = nullptr;
+  unsigned long long* d_seg_nodes = nullptr;
+  int grid = 0, waves_per_block = 4, stack_depth = 0, spill_depth = 0;
+  // graph cache
+  hipGraphExec_t graph = nullptr;
+  brt_out graph_out{};
+  hipStream_t graph_stream = nullptr;
+  bool use_graph = true;
+};
+
+extern "C" {
+
+int brt_version(void) { return 10000; }
+
+const char* brt_last_error(void) { return g_err.c_str(); }
+
+int brt_create(brt_ctx** out, int device) {
+  if (!out) return fail(BRT_E_ARG, "brt_create: out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(BRT_E_ARG, "brt_create: device %d of %d", device, ndev);
+  HIP_TRY(hipSetDevice(device));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, device));
+  brt_ctx* c = new (std::nothrow) brt_ctx;
+  if (!c) return fail(BRT_E_NOMEM, "brt_create: host allocation");
+  c->device = device;
+  c->n_cu = prop.multiProcessorCount;
+  c->launch.struct_size = sizeof(brt_launch);
+  c->launch.waves_per_block = 4;
+  c->launch.blocks_per_cu = 0;
+  c->launch.chunk_trees = 1024;
+  c->launch.stack_depth = 0;
+  *out = c;
+  g_err.clear();
+  return BRT_OK;
+}
+
+void brt_destroy(brt_ctx* ctx) { delete ctx; }
+
+int brt_set_launch(brt_ctx* ctx, const brt_launch* l) {
+  if (!ctx || !l || l->struct_size != sizeof(brt_launch)) return fail(BRT_E_ARG, "brt_set_launch: bad arguments");
+  if (l->waves_per_block < 1 || l->waves_per_block > 16) return fail(BRT_E_ARG, "waves_per_block must be 1..16");
+  if (l->chunk_trees < 64 || l->chunk_trees % 64 != 0 || l->chunk_trees > (1u << 24))
+    return fail(BRT_E_ARG, "chunk_trees must be a multiple of 64 in [64, 2^24]");
+  if (l->stack_depth > 255) return fail(BRT_E_ARG, "stack_depth must be <= 255");
+  ctx->launch = *l;
+  return BRT_OK;
+}
+
+int brt_get_launch(brt_ctx* ctx, brt_launch* l) {
+  if (!ctx || !l) return fail(BRT_E_ARG, "brt_get_launch: NULL argument");
+  *l = ctx->launch;
+  return BRT_OK;
+}
+
+int brt_problem_check(const brt_problem* p, const brt_mc* mc) {
+  if (!p || !mc) return fail(BRT_E_ARG, "problem/mc is NULL");
+  if (p->struct_size != sizeof(brt_problem)) return fail(BRT_E_ARG, "brt_problem.struct_size mismatch");
+  if (mc->struct_size != sizeof(brt_mc)) return fail(BRT_E_ARG, "brt_mc.struct_size mismatch");
+  if (p->dim != 1 && p->dim != 2) return fail(BRT_E_ARG, "dim must be 1 or 2");
+  if (!(p->diffusion > 0.0) || !is_fin(p->diffusion)) return fail(BRT_E_ARG, "diffusion must be > 0");
+  for (int j = 0; j < 8; ++j)
+    if (!is_fin(p->coef[j])) return fail(BRT_E_ARG, "coef[%d] is not finite", j);
+  for (int j = 0; j < 40; ++j)
+    if (!is_fin(p->u0_params[j])) return fail(BRT_E_ARG, "u0_params[%d] is not finite", j);
+  switch (p->u0_kind) {
+    case BRT_U0_CONST:
+      break;
+    case BRT_U0_LOGISTIC: {
+      const double pw = p->u0_params[3];
+      if (!(pw == 1.0 || pw == 2.0 || pw == 3.0 || pw == 4.0)) return fail(BRT_E_ARG, "logistic power must be 1..4");
+      break;
+    }
+    case BRT_U0_GAUSS_SUM:
+      if (p->u0_nterms < 1 || p->u0_nterms > 8) return fail(BRT_E_ARG, "gauss_sum needs 1..8 terms");
+      for (uint32_t k = 0; k < p->u0_nterms; ++k)
+        if (!(p->u0_params[4 * k + 3] > 0.0)) return fail(BRT_E_ARG, "gauss_sum width must be > 0");
+      break;
+    case BRT_U0_COS2_BUMP:
+      if (!(p->u0_params[1] > 0.0) || (p->dim == 2 && !(p->u0_params[2] > 0.0)))
+        return fail(BRT_E_ARG, "cos2_bump half-widths must be > 0");
+      break;
+    default:
+      return fail(BRT_E_ARG, "unknown u0_kind %u", p->u0_kind);
+  }
+  if (mc->precision != 32 && mc->precision != 64) return fail(BRT_E_ARG, "precision must be 32 or 64");
+  if (!(mc->lambda > 0.0) || !is_fin(mc->lambda)) return fail(BRT_E_ARG, "lambda must be > 0");
+  if (mc->max_order > 126) return fail(BRT_E_ARG, "max_order must be <= 126");
+  if (mc->node_cap < 1 || mc->node_cap > kMaxNodeCap) return fail(BRT_E_ARG, "node_cap must be in [1, 2^21-1]");
+  if (mc->pade_L + mc->pade_M > mc->max_order) return fail(BRT_E_ARG, "pade_L + pade_M must be <= max_order");
+  if (mc->pade_M > 16) return fail(BRT_E_ARG, "pade_M must be <= 16");
+  return BRT_OK;
+}
+
+}  // extern "C"
+
+static void plan_free(brt_plan* p) {
+  if (!p) return;
+  if (p->graph) (void)hipGraphExecDestroy(p->graph);
+  (void)hipFree(p->d_points);
+  (void)hipFree(p->d_chunks);
+  (void)hipFree(p->d_segs);
+  (void)hipFree(p->d_pdes);
+  (void)hipFree(p->d_counter);
+  (void)hipFree(p->d_depth);
+  (void)hipFree(p->d_tree_f);
+  (void)hipFree(p->d_tree_meta);
+  (void)hipFree(p->d_spill);
+  (void)hipFree(p->d_partials);
+  (void)hipFree(p->d_seg_nodes);
+  delete p;
+}
+
+template <typename T>
+static int upload(T** dst, const std::vector<T>& v) {
+  const size_t bytes = std::max<size_t>(1, v.size()) * sizeof(T);
+  if (hipMalloc(reinterpret_cast<void**>(dst), bytes) != hipSuccess)
+    return fail(BRT_E_NOMEM, "hipMalloc(%zu) failed", bytes);
+  if (!v.empty()) HIP_TRY(hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return BRT_OK;
+}
+
+extern "C" int brt_plan_create(brt_ctx* ctx, uint32_t n_problems, const brt_problem* problems, const brt_mc* mc,
+                    const brt_points* pts, brt_plan** out) {
+  if (!ctx || !problems || !mc || !pts || !out) return fail(BRT_E_ARG, "brt_plan_create: NULL argument");
+  *out = nullptr;
+  if (pts->struct_size != sizeof(brt_points)) return fail(BRT_E_ARG, "brt_points.struct_size mismatch");
+  if (n_problems < 1 || n_problems > (uint32_t)kMaxProblems)
+    return fail(BRT_E_ARG, "n_problems must be 1..%d", kMaxProblems);
+  for (uint32_t i = 0; i < n_problems; ++i) {
+    int rc = brt_problem_check(&problems[i], mc);
+    if (rc) return rc;
+    if (problems[i].dim != problems[0].dim || problems[i].u0_kind != problems[0].u0_kind)
+      return fail(BRT_E_ARG, "all problems of a plan must share dim and u0_kind");
+  }
+  if (pts->n > 0 && (!pts->x || !pts->t || !pts->n_trees)) return fail(BRT_E_ARG, "points: NULL array");
+  HIP_TRY(hipSetDevice(ctx->device));
+
+  brt_plan* p = new (std::nothrow) brt_plan;
+  if (!p) return fail(BRT_E_NOMEM, "host allocation");
+  p->ctx = ctx;
+  p->precision = (int)mc->precision;
+  p->dim = (int)problems[0].dim;
+  p->u0_kind = (int)problems[0].u0_kind;
+  p->n_problems = n_problems;
+  p->n_points = pts->n;
+  p->n_bins = mc->max_order + 2;
+  p->mc = *mc;
+
+  std::vector<Norm> norms(n_problems);
+  for (uint32_t i = 0; i < n_problems; ++i) norms[i] = normalize(problems[i], *mc);
+
+  // points
+  const uint32_t dim = (uint32_t)p->dim;
+  p->points.resize(pts->n);
+  std::vector<double> cost(pts->n, 1.0);
+  uint64_t base = 0;
+  for (uint32_t i = 0; i < pts->n; ++i) {
+    const uint32_t pid = pts->problem_id ? pts->problem_id[i] : 0u;
+    if (pid >= n_problems) {
+      plan_free(p);
+      return fail(BRT_E_ARG, "point %u: problem_id %u out of range", i, pid);
+    }
+    const double t = pts->t[i];
+    if (!(t >= 0.0) || !is_fin(t)) {
+      plan_free(p);
+      return fail(BRT_E_ARG, "point %u: t must be finite and >= 0", i);
+    }
+    if (pts->n_trees[i] > 0xffffffffull) {
+      plan_free(p);
+      return fail(BRT_E_ARG, "point %u: at most 2^32-1 trees", i);
+    }
+    PointRec& r = p->points[i];
+    std::memset(&r, 0, sizeof(r));
+    for (uint32_t d = 0; d < dim; ++d) {
+      r.x[d] = pts->x[(size_t)i * dim + d];
+      if (!is_fin(r.x[d])) {
+        plan_free(p);
+        return fail(BRT_E_ARG, "point %u: x is not finite", i);
+      }
+    }
+    r.t = t;
+    const Norm& nz = norms[pid];
+    r.theta = nz.K > 0 ? std::exp(-nz.lambda * t) : 1.0;
+    r.mu = nz.mu;
+    r.tree_base = base;
+    r.n_trees = (uint32_t)pts->n_trees[i];
+    r.point_id = pts->point_id ? pts->point_id[i] : i;
+    r.pde = pid;
+    base += r.n_trees;
+    cost[i] = est_nodes(nz, *mc, t);
+  }
+  p->total_trees = base;
+
+  // walker chunks, most expensive first (longest-processing-time order)
+  const uint32_t ct = ctx->launch.chunk_trees;
+  std::vector<uint32_t> order(pts->n);
+  std::iota(order.begin(), order.end(), 0u);
+  std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return cost[a] > cost[b]; });
+  for (uint32_t i : order) {
+    const uint32_t n = p->points[i].n_trees;
+    for (uint32_t b0 = 0; b0 < n; b0 += ct) p->chunks.push_back(Chunk{i, b0, std::min(n, b0 + ct), 0u});
+  }
+  // reduction segments, in point order
+  for (uint32_t i = 0; i < pts->n; ++i) {
+    PointRec& r = p->points[i];
+    r.seg_begin = (uint32_t)p->segs.size();
+    for (uint32_t b0 = 0; b0 < r.n_trees; b0 += kSegTrees)
+      p->segs.push_back(Segment{i, b0, std::min(r.n_trees, b0 + kSegTrees), 0u});
+    r.seg_count = (uint32_t)p->segs.size() - r.seg_begin;
+  }
+
+  // Stack depth: with pruning a lineage holds at most max_order vertices with children still to
+  // start; without pruning the depth is capped at kMaxDepthUnpruned (deeper trees are flagged).  The
+  // top levels live in LDS, the rest in a per-thread global spill area.
+  const uint32_t needed = mc->prune ? std::max(1u, mc->max_order) : kMaxDepthUnpruned;
+  const uint32_t lds_levels = ctx->launch.stack_depth ? ctx->launch.stack_depth : kDefaultLdsLevels;
+  p->stack_depth = (int)std::min(needed, lds_levels);
+  p->spill_depth = (int)(needed - (uint32_t)p->stack_depth);
+  p->waves_per_block = (int)ctx->launch.waves_per_block;
+
+  int rc = BRT_OK;
+  if (p->precision == 32) {
+    std::vector<PdeT<float>> tab(n_problems);
+    for (uint32_t i = 0; i < n_problems; ++i) tab[i] = to_device<float>(problems[i], norms[i]);
+    rc = upload(reinterpret_cast<PdeT<float>**>(&p->d_pdes), tab);
+  } else {
+    std::vector<PdeT<double>> tab(n_problems);
+    for (uint32_t i = 0; i < n_problems; ++i) tab[i] = to_device<double>(problems[i], norms[i]);
+    rc = upload(reinterpret_cast<PdeT<double>**>(&p->d_pdes), tab);
+  }
+  if (!rc) rc = upload(&p->d_points, p->points);
+  if (!rc) rc = upload(&p->d_chunks, p->chunks);
+  if (!rc) rc = upload(&p->d_segs, p->segs);
+  if (rc) {
+    plan_free(p);
+    return rc;
+  }
+  const size_t nb3 = (size_t)(p->n_bins + 3);
+  if (hipMalloc(reinterpret_cast<void**>(&p->d_counter), 64) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&p->d_depth), 64) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&p->d_partials), std::max<size_t>(1, p->segs.size()) * nb3 * sizeof(Partial)) !=
+          hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&p->d_seg_nodes),
+                std::max<size_t>(1, p->segs.size()) * sizeof(unsigned long long)) != hipSuccess) {
+    plan_free(p);
+    return fail(BRT_E_NOMEM, "plan scratch allocation failed");
+  }
+  HIP_TRY(hipMemset(p->d_depth, 0, 64));
+
+  // persistent grid: as many blocks as are resident at once
+  int bpc = (int)ctx->launch.blocks_per_cu;
+  int maxb = walk_max_blocks_per_cu(p->precision, p->dim, p->u0_kind, p->stack_depth, p->waves_per_block);
+  while (maxb <= 0 && p->waves_per_block > 1) {  // shrink the block until its LDS fits
+    p->waves_per_block -= 1;
+    maxb = walk_max_blocks_per_cu(p->precision, p->dim, p->u0_kind, p->stack_depth, p->waves_per_block);
+  }
+  if (maxb <= 0) {
+    plan_free(p);
+    return fail(BRT_E_ARG, "launch settings do not fit the device (stack_depth %d, %d waves per block)",
+                p->stack_depth, p->waves_per_block);
+  }
+  if (bpc == 0 || bpc > maxb) bpc = maxb;
+  p->grid = std::max(1, std::min<int>(bpc * ctx->n_cu, (int)std::max<size_t>(1, p->chunks.size())));
+  if (p->spill_depth > 0) {
+    const size_t bytes = (size_t)p->grid * p->waves_per_block * kWave * p->spill_depth *
+                         stack_entry_size(p->precision, p->dim);
+    if (hipMalloc(&p->d_spill, bytes) != hipSuccess) {
+      plan_free(p);
+      return fail(BRT_E_NOMEM, "stack spill area: hipMalloc(%zu)", bytes);
+    }
+  }
+  *out = p;
+  g_err.clear();
+  return BRT_OK;
+}
+
+extern "C" {
+int brt_plan_info(const brt_plan* p, uint32_t* n_points, uint64_t* n_trees, uint32_t* n_bins, uint32_t* n_chunks);
+}
+
+static int ensure_records(brt_plan* p) {
+  if (p->d_tree_f) return BRT_OK;
+  const size_t n = std::max<uint64_t>(1, p->total_trees);
+  const size_t fb = n * sizeof(double);
+  if (hipMalloc(reinterpret_cast<void**>(&p->d_tree_f), fb) != hipSuccess) return fail(BRT_E_NOMEM, "tree records: hipMalloc(%zu)", fb);
+  if (hipMalloc(reinterpret_cast<void**>(&p->d_tree_meta), n * 4) != hipSuccess)
+    return fail(BRT_E_NOMEM, "tree records: hipMalloc(%zu)", n * 4);
+  return BRT_OK;
+}
+
+static int enqueue(brt_plan* p, const brt_out* o, hipStream_t s) {
+  double* tf = reinterpret_cast<double*>(o->tree_f);
+  uint32_t* tm = o->tree_meta;
+  if (!tf || !tm) {
+    int rc = ensure_records(p);
+    if (rc) return rc;
+    tf = p->d_tree_f;
+    tm = p->d_tree_meta;
+  }
+  HIP_TRY(launch_reset(p->d_counter, p->d_depth, s));
+  if (!p->chunks.empty()) {
+    WalkArgs w{};
+    w.points = p->d_points;
+    w.chunks = p->d_chunks;
+    w.n_chunks = (uint32_t)p->chunks.size();
+    w.n_problems = p->n_problems;
+    w.pdes = p->d_pdes;
+    w.chunk_counter = p->d_counter;
+    w.depth_counter = p->d_depth;
+    w.tree_f = tf;
+    w.tree_meta = tm;
+    w.key0 = (uint32_t)(p->mc.seed & 0xffffffffull);
+    w.key1 = (uint32_t)(p->mc.seed >> 32);
+    w.max_order = p->mc.max_order;
+    w.prune = p->mc.prune;
+    w.node_cap = p->mc.node_cap;
+    w.stack_depth = (uint32_t)p->stack_depth;
+    w.spill_depth = (uint32_t)p->spill_depth;
+    w.spill = p->d_spill;
+    w.n_threads = (uint32_t)(p->grid * p->waves_per_block * kWave);
+    HIP_TRY(launch_walk(p->precision, p->dim, p->u0_kind, w, p->grid, p->waves_per_block, s));
+  }
+  ReduceArgs r{};
+  r.points = p->d_points;
+  r.segs = p->d_segs;
+  r.n_segs = (uint32_t)p->segs.size();
+  r.tree_f = tf;
+  r.tree_meta = tm;
+  r.partials = p->d_partials;
+  r.seg_nodes = p->d_seg_nodes;
+  r.n_bins = p->n_bins;
+  HIP_TRY(launch_reduce(r, s));
+  FinalizeArgs f{};
+  f.points = p->d_points;
+  f.n_points = p->n_points;
+  f.partials = p->d_partials;
+  f.seg_nodes = p->d_seg_nodes;
+  f.n_bins = p->n_bins;
+  f.pade_L = p->mc.pade_L;
+  f.pade_M = p->mc.pade_M;
+  f.u = o->u;
+  f.se = o->se;
+  f.psum = o->psum;
+  f.coef = o->coef;
+  f.coef_var = o->coef_var;
+  f.hist = reinterpret_cast<unsigned long long*>(o->hist);
+  f.s1 = o->s1;
+  f.s2 = o->s2;
+  f.nodes = reinterpret_cast<unsigned long long*>(o->nodes);
+  f.flags = o->flags;
+  HIP_TRY(launch_finalize(f, s));
+  return BRT_OK;
+}
+
+extern "C" {
+
+int brt_plan_execute(brt_plan* p, const brt_out* o, void* stream) {
+  if (!p || !o) return fail(BRT_E_ARG, "brt_plan_execute: NULL argument");
+  if (o->struct_size != sizeof(brt_out)) return fail(BRT_E_ARG, "brt_out.struct_size mismatch");
+  HIP_TRY(hipSetDevice(p->ctx->device));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (!s || !p->use_graph) return enqueue(p, o, s);
+  if (p->graph && p->graph_stream == s && std::memcmp(&p->graph_out, o, sizeof(brt_out)) == 0) {
+    HIP_TRY(hipGraphLaunch(p->graph, s));
+    return BRT_OK;
+  }
+  if (p->graph) {
+    (void)hipGraphExecDestroy(p->graph);
+    p->graph = nullptr;
+  }
+  if (!o->tree_f || !o->tree_meta) {
+    int rc = ensure_records(p);  // allocate outside the capture
+    if (rc) return rc;
+  }
+  HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  int rc = enqueue(p, o, s);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(s, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(BRT_E_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  e = hipGraphInstantiate(&p->graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    p->graph = nullptr;
+    return fail(BRT_E_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  }
+  p->graph_out = *o;
+  p->graph_stream = s;
+  HIP_TRY(hipGraphLaunch(p->graph, s));
+  return BRT_OK;
+}
+
+int brt_plan_info(const brt_plan* p, uint32_t* n_points, uint64_t* n_trees, uint32_t* n_bins, uint32_t* n_chunks) {
+  if (!p) return fail(BRT_E_ARG, "brt_plan_info: NULL plan");
+  if (n_points) *n_points = p->n_points;
+  if (n_trees) *n_trees = p->total_trees;
+  if (n_bins) *n_bins = p->n_bins;
+  if (n_chunks) *n_chunks = (uint32_t)p->chunks.size();
+  return BRT_OK;
+}
+
+int brt_plan_depth_exceeded(brt_plan* p, uint64_t* count) {
+  if (!p || !count) return fail(BRT_E_ARG, "NULL argument");
+  unsigned long long v = 0;
+  HIP_TRY(hipMemcpy(&v, p->d_depth, sizeof(v), hipMemcpyDeviceToHost));
+  *count = v;
+  return BRT_OK;
+}
+
+void brt_plan_destroy(brt_plan* p) { plan_free(p); }
+
+int brt_solve(brt_ctx* ctx, uint32_t n_problems, const brt_problem* problems, const brt_mc* mc,
+              const brt_points* points, const brt_out* out, void* stream) {
+  brt_plan* p = nullptr;
+  int rc = brt_plan_create(ctx, n_problems, problems, mc, points, &p);
+  if (rc) return rc;
+  p->use_graph = false;
+  rc = enqueue(p, out, reinterpret_cast<hipStream_t>(stream));
+  if (!rc) {
+    hipError_t e = hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) rc = fail(BRT_E_DEVICE, "hipStreamSynchronize: %s", hipGetErrorString(e));
+  }
+  uint64_t deep = 0;
+  if (!rc) rc = brt_plan_depth_exceeded(p, &deep);
+  plan_free(p);
+  if (!rc && deep) rc = fail(BRT_E_RANGE, "%llu trees exceeded the stack depth", (unsigned long long)deep);
+  return rc;
+}
+
+}  // extern "C"

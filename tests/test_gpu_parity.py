@@ -1,0 +1,221 @@
+"""GPU-vs-oracle parity through the C ABI (needs an MI355X).
+
+Every case prints its name, shape and seed before touching the GPU.  Tolerances are stated in
+tests/_parity.py.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2402_06491_amd import inputs
+
+from . import _parity as P
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    assert torch.cuda.is_available(), "no GPU"
+    import paper_2402_06491_amd as brt
+
+    c = brt.Context(0)
+    yield c
+    c.close()
+
+
+def _announce(name, wl):
+    print(f"\n[case] {name}: points={len(wl['t'])} trees={int(np.sum(wl['n_trees']))} "
+          f"precision={wl['mc']['precision']} seed={wl['mc']['seed']}", flush=True)
+
+
+def _full_parity(ctx, name, wl, launch=None, pade_tol=1e-3):
+    _announce(name, wl)
+    tol = P.FP64_TOL if wl["mc"]["precision"] == 64 else P.FP32_TOL
+    gpu = P.gpu_run(ctx, wl, launch=launch)
+    pi, ti, ri = P.tree_items(wl)
+    orc = P.oracle_trees(wl, pi, ti)
+    worst = P.compare_trees(gpu, ri, orc, tol, pi)
+    omom = P.oracle_moments(wl, orc, pi)
+    P.compare_moments(wl, gpu, omom, tol)
+    opade = P.oracle_pade(wl, omom)
+    B = oracle.n_bins(wl["mc"])
+    for p, r in enumerate(opade):
+        a = r["a"]
+        np.testing.assert_allclose(gpu["coef"][p], a, rtol=0, atol=(tol + 1e-12) * np.abs(a).max() + 1e-300)
+        assert abs(gpu["psum"][p] - r["psum"]) <= (tol + 1e-12) * np.abs(a).sum() + 1e-300
+    du, strict, n = P.compare_pade(wl, gpu, opade, pade_tol)
+    print(f"[case] {name}: max rel tree diff {worst:.3e}, max |du| {du:.3e}, {strict}/{n} points within "
+          f"{pade_tol}, bins {B}", flush=True)
+    return gpu, orc
+
+
+def test_kpp_small_fp64(ctx):
+    wl = inputs.kpp(n_trees=3000)
+    _full_parity(ctx, "kpp_small_fp64", wl)
+
+
+def test_kpp_full_fp64(ctx):
+    """The KPP workload at its full size (16 points x 1e5 trees): every tree against the oracle."""
+    wl = inputs.kpp(n_trees=100_000)
+    gpu, _ = _full_parity(ctx, "kpp_full_fp64", wl)
+    assert np.all(gpu["flags"] & 24 == 0)
+
+
+def test_fisher_small_fp32(ctx):
+    wl = inputs.fisher(n_trees=1000)  # ragged: not a multiple of 64
+    _full_parity(ctx, "fisher_small_fp32", wl)
+
+
+def test_fisher_small_fp64(ctx):
+    wl = inputs.fisher(n_trees=1000)
+    wl["mc"] = dict(wl["mc"], precision=64)
+    _full_parity(ctx, "fisher_small_fp64", wl)
+
+
+def test_cubic_2d_small_fp32(ctx):
+    wl = inputs.cubic_2d(n_trees=200, n_per_line=64)
+    _full_parity(ctx, "cubic_2d_small_fp32", wl)
+
+
+def test_poly_batch_small(ctx):
+    for prec in (32, 64):
+        wl = inputs.poly_batch(n_points=512, n_min=64, n_max=2000, precision=prec)
+        _full_parity(ctx, f"poly_batch_small_fp{prec}", wl, pade_tol=1e-3)
+
+
+def test_fisher_full_sampled(ctx):
+    """Fisher at full size (192 points x 1e6 trees): sampled trees against the oracle; the reduction
+    against an independent FP64 sum of the tree records; histogram totals."""
+    import torch
+
+    wl = inputs.fisher(n_trees=1_000_000)
+    _announce("fisher_full_sampled", wl)
+    gpu = P.gpu_run(ctx, wl)
+    rng = np.random.default_rng(2024)
+    pi = rng.integers(0, len(wl["t"]), size=4000)
+    ti = rng.integers(0, 1_000_000, size=4000)
+    _, _, ri = P.tree_items(wl, pi, ti)
+    orc = P.oracle_trees(wl, pi, ti)
+    worst = P.compare_trees(gpu, ri, orc, P.FP32_TOL, pi)
+    B = oracle.n_bins(wl["mc"])
+    assert np.all(gpu["hist"].sum(axis=1) == 1_000_000)
+    # per-bin sums from the records with torch on the GPU (a different summation order)
+    f = torch.from_numpy(gpu["tree_f"]).cuda().view(len(wl["t"]), -1)
+    meta = torch.from_numpy(gpu["tree_meta"]).cuda().long().view(len(wl["t"]), -1)
+    ne = (meta & 255).clamp(max=B - 1)
+    ok = (meta & (7 << 8)) == 0
+    for b in range(B):
+        sel = ok & (ne == b)
+        s1 = torch.where(sel, f, torch.zeros_like(f)).sum(dim=1).cpu().numpy()
+        sa = torch.where(sel, f.abs(), torch.zeros_like(f)).sum(dim=1).cpu().numpy()
+        assert np.all(np.abs(gpu["s1"][:, b] - s1) <= 1e-12 * sa + 1e-300), b
+    print(f"[case] fisher_full_sampled: max rel tree diff {worst:.3e}", flush=True)
+
+
+# ---------------------------------------------------------------- edge cases --------------------
+def test_edge_empty_and_ragged_points(ctx):
+    wl = inputs.fisher(n_trees=1, n_x=6, times=(0.5,))
+    wl["n_trees"] = np.array([0, 1, 63, 64, 65, 1500], np.int64)
+    gpu, _ = _full_parity(ctx, "edge_empty_ragged", wl)
+    assert gpu["hist"][0].sum() == 0 and gpu["u"][0] == 0.0
+
+
+def test_edge_time_zero_and_no_nonlinearity(ctx):
+    wl = inputs.fisher(n_trees=500, n_x=8, times=(0.0,))
+    _full_parity(ctx, "edge_t0", wl)
+    g = inputs.gauss_sum([(1 / math.sqrt(4 * math.pi), 0.0, 0.0, math.sqrt(2.0))])
+    wl = {"problems": [inputs.problem(1, 1.0, [0, 0, 0], g)], "mc": inputs.mc_params(seed=3, precision=64),
+          "x": np.linspace(-2, 2, 5).reshape(-1, 1), "t": np.full(5, 1.0), "n_trees": np.full(5, 700)}
+    gpu, _ = _full_parity(ctx, "edge_heat_kernel", wl)
+    assert np.all(gpu["nodes"] == 700)
+
+
+def test_edge_node_cap_and_order_zero(ctx):
+    wl = inputs.kpp(n_trees=800)
+    wl["mc"] = dict(wl["mc"], node_cap=5)
+    gpu, _ = _full_parity(ctx, "edge_node_cap", wl)
+    assert np.all(gpu["flags"] & 8)
+    wl = inputs.fisher(n_trees=800, n_x=4, times=(1.0,))
+    wl["mc"] = dict(wl["mc"], max_order=0, pade_L=0, pade_M=0)
+    _full_parity(ctx, "edge_order_zero", wl)
+
+
+def test_edge_max_order_and_mixed_problems(ctx):
+    wl = inputs.kpp(n_trees=600)
+    wl["mc"] = dict(wl["mc"], max_order=62, prune=1, pade_L=8, pade_M=8)
+    _full_parity(ctx, "edge_max_order_62", wl)
+    probs = []
+    for k in range(16):
+        rng = np.random.default_rng(100 + k)
+        probs.append(inputs.problem(1, rng.uniform(0.3, 1.5), list(rng.uniform(-1, 1, size=4)),
+                                    inputs.logistic(0.6, 1.0, rng.uniform(-1, 1), 1)))
+    rng = np.random.default_rng(9)
+    n = 64
+    wl = {"problems": probs, "mc": inputs.mc_params(seed=77, precision=32),
+          "x": rng.uniform(-3, 3, size=(n, 1)), "t": rng.uniform(0.1, 1.5, size=n),
+          "n_trees": rng.integers(0, 900, size=n), "problem_id": rng.integers(0, 16, size=n).astype(np.uint32),
+          "point_id": rng.integers(0, 2 ** 32, size=n, dtype=np.uint64).astype(np.uint32)}
+    _full_parity(ctx, "edge_16_problems", wl, pade_tol=1e-3)
+
+
+def test_edge_cos2_bump_2d(ctx):
+    prob = inputs.problem(2, 1.0, [0, 0, -1.25, -1.0], {"u0_kind": "cos2_bump", "u0_params": [-2.0, 10.0, 40.0],
+                                                         "u0_nterms": 0})
+    rng = np.random.default_rng(4)
+    wl = {"problems": [prob], "mc": inputs.mc_params(seed=5, precision=32),
+          "x": rng.uniform(-12, 12, size=(40, 2)), "t": np.full(40, 0.5), "n_trees": np.full(40, 300)}
+    _full_parity(ctx, "edge_cos2_bump_2d", wl, pade_tol=1e-3)
+
+
+def test_edge_small_chunks_and_stack_depth(ctx):
+    """Tiny chunks (one wave's worth) and the smallest stack that the workload needs."""
+    wl = inputs.fisher(n_trees=700, n_x=8)
+    _full_parity(ctx, "edge_chunk64", wl, launch={"chunk_trees": 64, "waves_per_block": 1})
+    ctx.set_launch()
+
+
+def test_determinism_and_graph_replay(ctx):
+    """Two executes of one plan (graph replay) and a fresh plan give identical bits."""
+    import torch
+
+    from paper_2402_06491_amd import Plan
+
+    wl = inputs.fisher(n_trees=5000, n_x=16)
+    _announce("determinism", wl)
+    plan = Plan(ctx, wl["problems"], wl["mc"], wl["x"], wl["t"], wl["n_trees"])
+    out = plan.outputs()
+    results = []
+    for _ in range(3):
+        plan.execute(out)
+        torch.cuda.synchronize()
+        results.append({k: v.cpu().numpy().copy() for k, v in out.items()})
+        for v in out.values():
+            v.zero_()
+    plan2 = Plan(ctx, wl["problems"], wl["mc"], wl["x"], wl["t"], wl["n_trees"])
+    out2 = plan2.outputs()
+    plan2.execute(out2)
+    torch.cuda.synchronize()
+    results.append({k: v.cpu().numpy() for k, v in out2.items()})
+    for r in results[1:]:
+        for k in r:
+            np.testing.assert_array_equal(r[k], results[0][k], err_msg=k)
+
+
+def test_alone_equals_in_batch(ctx):
+    """A point's results alone equal its results inside a larger mixed batch (bit-identical)."""
+    wl = inputs.poly_batch(n_points=256, n_min=64, n_max=3000, precision=32)
+    wl["point_id"] = np.arange(256, dtype=np.uint32)
+    _announce("alone_vs_batch", wl)
+    batch = P.gpu_run(ctx, wl, records=False)
+    for p in (0, 17, 255):
+        one = {"problems": wl["problems"], "mc": wl["mc"], "x": wl["x"][p:p + 1], "t": wl["t"][p:p + 1],
+               "n_trees": wl["n_trees"][p:p + 1], "problem_id": wl["problem_id"][p:p + 1],
+               "point_id": wl["point_id"][p:p + 1]}
+        alone = P.gpu_run(ctx, one, records=False)
+        for k in ("u", "se", "coef", "hist", "s1", "s2", "nodes"):
+            np.testing.assert_array_equal(alone[k][0], batch[k][p], err_msg=f"{k} point {p}")
