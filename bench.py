@@ -1,0 +1,243 @@
+#!/usr/bin/env python3
+"""Throughput of the random-tree Monte Carlo hot path on one MI355X.
+
+Workload (default): the 1-D Fisher equation u_t = u_xx + u - u^2 with the travelling-wave initial data
+(1 + e^{x/sqrt6})^-2, 64 points in [-10, 10] times t in {0.5, 1, 2} (192 queries), 1e6 trees per point,
+series order 12 with pruning, Pade [6/6], FP32 paths with FP64 clock, products and moments.
+
+One step = one run of the whole path (tree walk, per-bin moment reduction, FP64 finalize with Pade)
+over all 192 points, replayed as a HIP graph with the inputs already resident in HBM.
+
+Prints one JSON line on stdout (progress goes to stderr):
+  value          trees per second over the timed steps (whole job)
+  latency_ms     p50/p99 of per-step latency (one step answers the 192 point queries)
+  roofline       the walker kernel: algorithmic VALU operations per launch / its average duration
+                 (HIP events on the launch stream), against the FP32 vector peak expressed in ops
+  cpu_baseline   the CPU oracle timed on a bounded sample of the same trees, on the host's cores
+  parity         the sampled trees compared with the oracle (shape bit-exact, value within tolerance)
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "random trees/sec at fixed error vs oracle; p50/p99 point-query latency"
+
+# Algorithmic work per tree node, in 32-bit VALU lane operations (a 32x32->64 product counts 2, an FP64
+# operation 1, a transcendental 1).  Per node: Philox4x32-10 80 (10 rounds x (2 wide products = 4,
+# 2 three-input xors = 4)); uniform conversions 8; clock product and test 2; Box-Muller 7 (log, scale,
+# sqrt, sin, cos, two products); exponential time 2; Brownian step 3 + 2 d; then either a vertex
+# (count, prune test, time left and clamp, arity product and lookup, weight exponent, exp, two
+# products: 12) or a leaf (initial data: about 9 for the logistic families), counted as 10 on average.
+OPS_PER_NODE = {1: 114, 2: 116}
+# FP32 vector peak of MI355X expressed in operations: 157.3 TFLOP/s counts an FMA as 2 flops, i.e.
+# 78.6 T lane-operations/s with packed FP32 (256 CUs x 4 SIMDs x 16 lanes x 2 x 2.4 GHz); plain
+# (non-packed) VALU issue is half of that, 39.3 T/s.
+PEAK_TOPS = 78.6
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def workload(name):
+    from paper_2402_06491_amd import inputs
+
+    if name == "fisher":
+        return inputs.fisher()
+    if name == "kpp":
+        return inputs.kpp()
+    if name == "cubic_2d":
+        return inputs.cubic_2d()
+    if name == "poly_batch":
+        return inputs.poly_batch()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def describe(wl):
+    if wl["name"] == "fisher_1d":
+        return ("fisher_1d: u_t=u_xx+u-u^2, u0=(1+e^{x/sqrt6})^-2, 64 x in [-10,10] x t in {0.5,1,2}, "
+                "1e6 trees/point, order 12 pruned, Pade [6/6], FP32 paths, FP64 clock/products/moments")
+    return wl["name"]
+
+
+def cpu_threads():
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def cpu_baseline(wl, gpu_meta, gpu_f, target_s):
+    """Time the oracle on the first S trees of every point; compare those trees with the GPU records."""
+    import oracle
+
+    oracle.build(force=False)
+    threads = cpu_threads()
+    npts = len(wl["t"])
+    n_trees = np.asarray(wl["n_trees"], dtype=np.int64)
+    base = np.concatenate([[0], np.cumsum(n_trees)])
+    prob = wl["problems"][0]
+
+    def run(S):
+        t0 = time.perf_counter()
+        recs = []
+        for p in range(npts):
+            r = oracle.walk_point(prob, wl["mc"], wl["x"][p], float(wl["t"][p]), p, S, nthreads=threads)
+            recs.append(r)
+        return time.perf_counter() - t0, recs
+
+    dt, _ = run(2000)  # calibration
+    rate = npts * 2000 / max(dt, 1e-6)
+    S = int(min(n_trees.min(), max(1000, rate * target_s / npts)))
+    log(f"cpu baseline: {threads} threads, calibrated {rate:.3g} trees/s, sample {S} trees x {npts} points")
+    dt, recs = run(S)
+    # parity of the sampled trees: shapes bit-exact; values within tol |F| + 1e-6 max_point |F|
+    tol = 2e-4 if wl["mc"]["precision"] == 32 else 1e-12
+    max_rel, mism, checked, worst_ratio, worst = 0.0, 0, 0, 0.0, []
+    for p, r in enumerate(recs):
+        sl = slice(int(base[p]), int(base[p]) + S)
+        m = gpu_meta[sl].astype(np.uint32)
+        mism += int(np.sum((m & 0xFF) != np.minimum(r["ne"], 255)))
+        mism += int(np.sum((m >> 11) != r["nodes"]))
+        fl = ((m >> 8) & 1) + 2 * ((m >> 9) & 1)
+        mism += int(np.sum(fl != r["flags"]))
+        absF = np.abs(r["F"])
+        diff = np.abs(gpu_f[sl] - r["F"])
+        floor = (1e-6 * absF.max()) if wl["mc"]["precision"] == 32 else 1e-300
+        ratio = diff / (tol * absF + floor + 1e-300)
+        k = int(np.argmax(ratio))
+        if ratio[k] > worst_ratio:
+            worst_ratio = float(ratio[k])
+            worst = [p, k, int(r["ne"][k]), int(r["nodes"][k]), float(gpu_f[sl][k]), float(r["F"][k])]
+        big = absF > 1e-3 * max(absF.max(), 1e-300)
+        if big.any():
+            max_rel = max(max_rel, float((diff[big] / absF[big]).max()))
+        checked += S
+    return ({"value": npts * S / dt, "unit": "trees/s", "cores": threads, "kind": "oracle",
+             "sample": f"first {S} trees of each of the {npts} points ({npts * S} trees, {dt:.1f} s)"},
+            {"trees_checked": checked, "shape_mismatches": mism, "max_rel_tree_diff_big": max_rel,
+             "tree_tol": tol, "worst_err_over_bound": worst_ratio,
+             "worst_tree": dict(zip(["point", "tree", "ne", "nodes", "F_gpu", "F_oracle"], worst))})
+
+
+def pmc_traffic(kernel_src_sha, launches_trees):
+    """HBM bytes per walker launch from the committed rocprofv3 counter summary, if it was taken on
+    the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "walk_fisher_pmc.json")
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_sha256") != kernel_src_sha:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="fisher")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2402_06491_amd as brt
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    wl = workload(args.workload)
+    log(f"workload {wl['name']}: {len(wl['t'])} points, {int(np.sum(wl['n_trees']))} trees")
+    ctx = brt.Context(0)
+    plan = brt.Plan(ctx, wl["problems"], wl["mc"], wl["x"], wl["t"], wl["n_trees"],
+                    problem_id=wl.get("problem_id"), point_id=wl.get("point_id"))
+    out = plan.outputs(records=True)
+    stream = torch.cuda.current_stream()
+    for i in range(args.warmup):
+        plan.execute(out)
+    torch.cuda.synchronize()
+    log(f"warmup done ({args.warmup} steps)")
+
+    # ---- timed region: K graph replays ----
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        starts[i].record(stream)
+        plan.execute(out)
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
+    total_trees = int(np.sum(wl["n_trees"]))
+    value = total_trees * args.steps / wall
+    log(f"timed {args.steps} steps: {wall * 1e3 / args.steps:.3f} ms/step, {value:.4g} trees/s")
+
+    # ---- walker kernel duration with HIP events on the launch stream ----
+    plan.set_timing(True)
+    for i in range(args.steps):
+        plan.execute(out)
+    (walk_ms, red_ms, fin_ms), runs = plan.get_timing()
+    plan.set_timing(False)
+    walk_s = walk_ms / runs / 1e3
+    nodes = int(out["nodes"].sum().item())
+    dim = int(wl["problems"][0]["dim"])
+    ops = nodes * OPS_PER_NODE[dim]
+    achieved = ops / walk_s / 1e12
+    src = open(os.path.join(ROOT, "paper_2402_06491_amd", "csrc", "brt_kernels.hip"), "rb").read()
+    sha = hashlib.sha256(src).hexdigest()
+    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_TOPS, "unit": "Top/s",
+                "frac": achieved / PEAK_TOPS, "traffic": pmc_traffic(sha, total_trees),
+                "kernel": "walk_kernel", "kernel_ms": walk_s * 1e3, "nodes_per_launch": nodes,
+                "ops_per_node": OPS_PER_NODE[dim], "reduce_ms": red_ms / runs, "finalize_ms": fin_ms / runs}
+    log(f"walk kernel {walk_s * 1e3:.3f} ms, {nodes} nodes, {achieved:.2f} Top/s "
+        f"({100 * achieved / PEAK_TOPS:.1f}% of {PEAK_TOPS}); reduce {red_ms / runs:.3f} ms, "
+        f"finalize {fin_ms / runs:.3f} ms")
+
+    u = out["u"].cpu().numpy()
+    flags = out["flags"].cpu().numpy()
+    result = {
+        "metric": METRIC, "value": value, "unit": "trees/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if wl["mc"]["precision"] == 32 else "f64",
+        "data": "synthetic",
+        "config": {"workload": describe(wl), "points": len(wl["t"]), "total_trees": total_trees,
+                   "nodes_per_step": nodes, "parallelism": "single GPU, persistent work-stealing launch"},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "what": "one step = all point queries of the workload"},
+        "roofline": roofline,
+        "pade": {"finite": int(np.isfinite(u).sum()), "pole_flagged": int(((flags & 1) != 0).sum())},
+    }
+    if not args.no_cpu_baseline:
+        meta = out["tree_meta"].cpu().numpy()
+        f = out["tree_f"].cpu().numpy()
+        cb, parity = cpu_baseline(wl, meta, f, args.cpu_seconds)
+        result["cpu_baseline"] = cb
+        result["parity"] = parity
+        log(f"cpu baseline {cb['value']:.4g} trees/s on {cb['cores']} threads; parity {parity}")
+    plan.close()
+    ctx.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -136,7 +136,7 @@ typedef struct brt_plan brt_plan;
 /* Launch settings (defaults chosen by the library; brt_autotune picks them by measurement). */
 typedef struct brt_launch {
   uint32_t struct_size;
-  uint32_t waves_per_block;  /* 1..16 */
+  uint32_t waves_per_block;  /* 1..4 */
   uint32_t blocks_per_cu;    /* 0 = as many as fit */
   uint32_t chunk_trees;      /* trees handed to a wave at a time, multiple of 64 */
   uint32_t stack_depth;      /* LDS stack levels per lane; 0 = automatic */
@@ -180,6 +180,14 @@ int brt_plan_info(const brt_plan* plan, uint32_t* n_points, uint64_t* n_trees, u
 
 /* Device-side count of trees that exceeded the stack depth in the last run (synchronises). */
 int brt_plan_depth_exceeded(brt_plan* plan, uint64_t* count);
+
+/* Per-kernel timing mode (for measurement).  While enabled, brt_plan_execute enqueues the kernels
+ * directly (no graph) and records HIP events on the launch stream around the walk, reduce and
+ * finalize kernels of every run.  brt_plan_get_timing waits for the recorded runs, writes the summed
+ * durations in milliseconds to ms[0] (walk), ms[1] (reduce), ms[2] (finalize), the number of runs to
+ * *runs (nullable), and starts a new accumulation. */
+int brt_plan_set_timing(brt_plan* plan, int enable);
+int brt_plan_get_timing(brt_plan* plan, double* ms, uint64_t* runs);
 
 void brt_plan_destroy(brt_plan* plan);
 

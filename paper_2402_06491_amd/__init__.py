@@ -77,6 +77,9 @@ _SIGS = [
                                      ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint32),
                                      ctypes.POINTER(ctypes.c_uint32)]),
     ("brt_plan_depth_exceeded", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
+    ("brt_plan_set_timing", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    ("brt_plan_get_timing", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_uint64)]),
     ("brt_plan_destroy", None, [ctypes.c_void_p]),
     ("brt_solve", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.POINTER(Problem), ctypes.POINTER(MC),
                                  ctypes.POINTER(Points), ctypes.POINTER(Out), ctypes.c_void_p]),
@@ -258,6 +261,16 @@ class Plan:
         v = ctypes.c_uint64()
         _check(lib().brt_plan_depth_exceeded(self._h, ctypes.byref(v)))
         return v.value
+
+    def set_timing(self, enable: bool):
+        _check(lib().brt_plan_set_timing(self._h, int(bool(enable))))
+
+    def get_timing(self):
+        """Summed (walk, reduce, finalize) kernel milliseconds and run count since the last call."""
+        ms = (ctypes.c_double * 3)()
+        runs = ctypes.c_uint64()
+        _check(lib().brt_plan_get_timing(self._h, ms, ctypes.byref(runs)))
+        return (ms[0], ms[1], ms[2]), runs.value
 
     def close(self):
         if self._h:

@@ -11,6 +11,7 @@ namespace brt {
 constexpr int kWave = 64;
 constexpr int kMaxProblems = 16;
 constexpr int kMaxU0Params = 32;
+constexpr int kMaxWalkThreads = 256;  // walker block size limit (4 waves): lets FP64 walkers keep state in VGPRs
 
 // tree_meta bit layout
 constexpr uint32_t kMetaNeMask = 0xffu;

@@ -4,12 +4,8 @@
 //                   iteration, explicit per-lane DFS stack in LDS, lanes refilled from the wave's
 //                   chunk with ballot/popcount; writes one record (value, splits, nodes, flags)
 //                   per tree.
-//  reduce_kernel    per (point, segment of trees): per-bin count / sum F / sum F^2 with per-lane
-//                   LDS accumulators and a fixed-order wave reduction (deterministic).
-//  finalize_kernel  per point, FP64: compensated sum over segments, coefficients
-//                   a_n = e^{mu t} S1_n / N and variances, Pade [L/M] at z = 1 by Gaussian
-//                   elimination, delta-method SE.
 //
+// The moment reduction and the FP64 finalize are in brt_moments.hip.
 // The walker computes no MFMA work: nothing here is a dense contraction.  It is bound by VALU
 // issue (Philox integer multiplies and transcendentals).
 #include <hip/hip_runtime.h>
@@ -126,6 +122,23 @@ __device__ __forceinline__ Real eval_g(const PdeT<Real>& pd, const Real* x) {
   }
 }
 
+// Logistic initial data A (1 + e^{s (n.x - x0)})^{-p}, split around its exponential.
+template <typename Real, int DIM>
+__device__ __forceinline__ Real logistic_arg(const PdeT<Real>& pd, const Real* x) {
+  Real nx = x[0] * pd.u0[4];
+  if constexpr (DIM == 2) nx += x[1] * pd.u0[5];
+  return pd.u0[1] * (nx - pd.u0[2]);
+}
+
+template <typename Real>
+__device__ __forceinline__ Real logistic_finish(const PdeT<Real>& pd, Real e) {
+  const Real base = Math<Real>::rcp((Real)1 + e);
+  Real r = base;
+  const int pw = (int)pd.u0[3];
+  for (int i = 1; i < pw; ++i) r *= base;
+  return pd.u0[0] * r;
+}
+
 __device__ __forceinline__ uint64_t lanemask_lt() {
   const uint32_t lane = __lane_id();
   return (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -147,12 +160,16 @@ __host__ __device__ constexpr size_t pde_table_bytes(int n) {
 // not yet started.  The top `lds_depth` levels live in LDS (structure of arrays, one slot per lane so
 // lanes never conflict), deeper levels in a per-thread global spill area.
 // ------------------------------------------------------------------------------------------------
+#define BRT_LDS __attribute__((address_space(3)))
+
 template <typename Real, int DIM>
 struct Stack {
-  double* P;      // LDS [lds_depth][64]
-  Real* X;        // LDS [DIM][lds_depth][64]
-  Real* T;        // LDS [lds_depth][64]
-  uint8_t* R;     // LDS [lds_depth][64]
+  // LDS pointers carry their address space so that the compiler keeps ds_* instructions for them
+  // instead of merging both tiers into generic (flat) accesses through a selected pointer.
+  BRT_LDS double* P;   // LDS [lds_depth][64]
+  BRT_LDS Real* X;     // LDS [DIM][lds_depth][64]
+  BRT_LDS Real* T;     // LDS [lds_depth][64]
+  BRT_LDS uint8_t* R;  // LDS [lds_depth][64]
   double* gP;     // global [spill_depth][n_threads]
   Real* gX;       // global [DIM][spill_depth][n_threads]
   Real* gT;       // global [spill_depth][n_threads]
@@ -206,7 +223,7 @@ struct Stack {
 // The walker.
 // ------------------------------------------------------------------------------------------------
 template <typename Real, int DIM, int U0>
-__global__ __launch_bounds__(1024) void walk_kernel(WalkArgs a) {
+__global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
 
   // problem table -> LDS
@@ -226,10 +243,10 @@ __global__ __launch_bounds__(1024) void walk_kernel(WalkArgs a) {
     const uint32_t depth = a.stack_depth;
     unsigned char* wbase = smem + pde_table_bytes<Real>(a.n_problems) +
                            (size_t)wave * depth * kWave * stack_entry_bytes<Real, DIM>();
-    st.P = reinterpret_cast<double*>(wbase);
-    st.X = reinterpret_cast<Real*>(st.P + depth * kWave);
+    st.P = (BRT_LDS double*)(wbase);
+    st.X = (BRT_LDS Real*)(st.P + depth * kWave);
     st.T = st.X + DIM * depth * kWave;
-    st.R = reinterpret_cast<uint8_t*>(st.T + depth * kWave);
+    st.R = (BRT_LDS uint8_t*)(st.T + depth * kWave);
     const size_t sd = (size_t)a.spill_depth * a.n_threads;
     st.gP = reinterpret_cast<double*>(a.spill);
     st.gX = reinterpret_cast<Real*>(st.gP + sd);
@@ -341,18 +358,29 @@ __global__ __launch_bounds__(1024) void walk_kernel(WalkArgs a) {
       xn[0] = x[0] + sd * (r * cs);
       xn[1] = x[1] + sd * (r * sn);
 
+      // One exponential per node, taken outside the vertex/leaf branches: the vertex weight
+      // e^{(alpha-1) mu tau'} or, for logistic initial data, e^{s (n.x - x0)} at the leaf.
+      Real earg = 0, om = 0, tau2 = 0;
+      uint32_t alpha = 0;
+      if (vertex) {
+        tau2 = tau - S;
+        tau2 = tau2 < (Real)0 ? (Real)0 : tau2;
+        const uint32_t idx = __umulhi(w.b, K);
+        alpha = (jpack >> (4 * idx)) & 15u;
+        om = pdes[pde].omega[idx];
+        earg = (Real)((int)alpha - 1) * mu * tau2;
+      } else if constexpr (U0 == 1) {
+        earg = logistic_arg<Real, DIM>(pdes[pde], xn);
+      }
+      const Real E = Math<Real>::ex(earg);
+
       if (vertex) {
         ne += 1;
         if (prune && ne > max_order) {
           flags |= kMetaOverflow;
           done = true;
         } else {
-          Real tau2 = tau - S;
-          tau2 = tau2 < (Real)0 ? (Real)0 : tau2;
-          const uint32_t idx = __umulhi(w.b, K);
-          const uint32_t alpha = (jpack >> (4 * idx)) & 15u;
-          const Real om = pdes[pde].omega[idx];
-          F *= (double)(om * Math<Real>::ex((Real)((int)alpha - 1) * mu * tau2));
+          F *= (double)(om * E);
           if (alpha == 0) {
             branch_end = true;
           } else {
@@ -372,7 +400,10 @@ __global__ __launch_bounds__(1024) void walk_kernel(WalkArgs a) {
           }
         }
       } else {
-        F *= (double)eval_g<Real, DIM, U0>(pdes[pde], xn);
+        if constexpr (U0 == 1)
+          F *= (double)logistic_finish<Real>(pdes[pde], E);
+        else
+          F *= (double)eval_g<Real, DIM, U0>(pdes[pde], xn);
         branch_end = true;
       }
       if (branch_end) {
@@ -397,278 +428,6 @@ __global__ void reset_kernel(uint32_t* chunk_counter, unsigned long long* depth_
   if (threadIdx.x == 0) {
     *chunk_counter = 0u;
     *depth_counter = 0ull;
-  }
-}
-
-// ------------------------------------------------------------------------------------------------
-// Reduction: one wave per segment of one point's trees.
-// Bins: 0..B-1 (B-1 is the tail: Ne > max_order without pruning), then overflow, capped, depth
-// (counts only).
-// ------------------------------------------------------------------------------------------------
-constexpr int kRedGroup = 16;
-
-__device__ __forceinline__ double wave_sum_f64(double v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-  return v;
-}
-
-__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-  return v;
-}
-
-__global__ __launch_bounds__(64) void reduce_kernel(ReduceArgs a) {
-  __shared__ double ls1[kRedGroup][kWave];
-  __shared__ double ls2[kRedGroup][kWave];
-  __shared__ uint32_t lcnt[kRedGroup][kWave];
-
-  const uint32_t seg = blockIdx.x;
-  const uint32_t lane = threadIdx.x;
-  const Segment sg = a.segs[seg];
-  const PointRec& pr = a.points[sg.point];
-  const double* F = a.tree_f + pr.tree_base;
-  const uint32_t* M = a.tree_meta + pr.tree_base;
-  const uint32_t B = a.n_bins;
-  const uint32_t NB = B + 3;
-  Partial* out = a.partials + (size_t)seg * NB;
-
-  unsigned long long nodes = 0;
-  for (uint32_t g0 = 0; g0 < NB; g0 += kRedGroup) {
-    for (int k = 0; k < kRedGroup; ++k) {
-      ls1[k][lane] = 0.0;
-      ls2[k][lane] = 0.0;
-      lcnt[k][lane] = 0u;
-    }
-    bool above = false;
-    for (uint32_t i = sg.begin + lane; i < sg.end; i += kWave) {
-      const uint32_t m = M[i];
-      const double f = F[i];
-      uint32_t bin;
-      if (m & kMetaOverflow)
-        bin = B;
-      else if (m & kMetaCapped)
-        bin = B + 1;
-      else if (m & kMetaDepth)
-        bin = B + 2;
-      else {
-        const uint32_t ne = m & kMetaNeMask;
-        bin = ne < B - 1 ? ne : B - 1;
-      }
-      if (g0 == 0) nodes += (unsigned long long)(m >> kMetaNodesShift);
-      if (bin >= g0 && bin < g0 + kRedGroup) {
-        const uint32_t k = bin - g0;
-        ls1[k][lane] += f;
-        ls2[k][lane] += f * f;
-        lcnt[k][lane] += 1u;
-      }
-      above |= bin >= g0 + kRedGroup;
-    }
-    for (int k = 0; k < kRedGroup; ++k) {
-      const uint32_t b = g0 + k;
-      const double v1 = wave_sum_f64(ls1[k][lane]);
-      const double v2 = wave_sum_f64(ls2[k][lane]);
-      const unsigned long long c = wave_sum_u64((unsigned long long)lcnt[k][lane]);
-      if (lane == 0 && b < NB) {
-        out[b].count = c;
-        out[b].s1 = v1;
-        out[b].s2 = v2;
-      }
-    }
-    if (__ballot(above) == 0) {
-      for (uint32_t b = g0 + kRedGroup + lane; b < NB; b += kWave) {
-        out[b].count = 0;
-        out[b].s1 = 0.0;
-        out[b].s2 = 0.0;
-      }
-      break;
-    }
-  }
-  nodes = wave_sum_u64(nodes);
-  if (lane == 0) a.seg_nodes[seg] = nodes;
-}
-
-// ------------------------------------------------------------------------------------------------
-// Finalize: one wave per point.
-// ------------------------------------------------------------------------------------------------
-constexpr int kMaxBins = 128;  // B = max_order + 2 <= 128
-constexpr int kMaxPadeM = 16;
-
-// [L/M] Pade approximant at z = 1 of sum_n a_n z^n: for k = L+1..L+M,
-// sum_{j=0}^{M} q_j a_{k-j} = 0 with q_0 = 1 (a_i = 0 for i < 0); p_i = sum_{j<=min(i,M)} q_j a_{i-j}.
-// Gaussian elimination with partial pivoting; the system is singular when the smallest pivot is
-// below 1e-13 times the largest.  On singularity the degree pair moves to [L+1/M-1] (same total
-// order), down to M = 0 (the partial sum).  Returns the value, writes q and the degrees used.
-__device__ double pade_eval(const double* a, int L, int M, double* q, int* Lused, int* Mused, double* T) {
-  while (true) {
-    bool ok = true;
-    q[0] = 1.0;
-    if (M > 0) {
-      // T is M x (M+1): columns 0..M-1 the matrix, column M the right-hand side
-      for (int i = 0; i < M; ++i) {
-        for (int j = 0; j < M; ++j) {
-          const int k = L + (i + 1) - (j + 1);
-          T[i * (M + 1) + j] = k >= 0 ? a[k] : 0.0;
-        }
-        T[i * (M + 1) + M] = -a[L + i + 1];
-      }
-      double pmax = 0.0, pmin = 1e308;
-      for (int c = 0; c < M; ++c) {
-        int piv = c;
-        double best = fabs(T[c * (M + 1) + c]);
-        for (int rr = c + 1; rr < M; ++rr) {
-          const double v = fabs(T[rr * (M + 1) + c]);
-          if (v > best) {
-            best = v;
-            piv = rr;
-          }
-        }
-        if (!(best == best) || best > 1e300) {  // NaN or overflow: give up on this order
-          ok = false;
-          break;
-        }
-        if (piv != c)
-          for (int j = 0; j <= M; ++j) {
-            const double tmp = T[c * (M + 1) + j];
-            T[c * (M + 1) + j] = T[piv * (M + 1) + j];
-            T[piv * (M + 1) + j] = tmp;
-          }
-        pmax = best > pmax ? best : pmax;
-        pmin = best < pmin ? best : pmin;
-        if (best == 0.0) {
-          ok = false;
-          break;
-        }
-        for (int rr = c + 1; rr < M; ++rr) {
-          const double fct = T[rr * (M + 1) + c] / T[c * (M + 1) + c];
-          for (int j = c; j <= M; ++j) T[rr * (M + 1) + j] -= fct * T[c * (M + 1) + j];
-        }
-      }
-      if (ok && pmin <= 1e-13 * pmax) ok = false;
-      if (ok) {
-        for (int i = M - 1; i >= 0; --i) {
-          double s = T[i * (M + 1) + M];
-          for (int j = i + 1; j < M; ++j) s -= T[i * (M + 1) + j] * q[j + 1];
-          q[i + 1] = s / T[i * (M + 1) + i];
-        }
-      }
-    }
-    if (ok || M == 0) break;
-    L += 1;
-    M -= 1;
-  }
-  double num = 0.0, den = 0.0;
-  for (int i = 0; i <= L; ++i) {
-    double pi = 0.0;
-    for (int j = 0; j <= (i < M ? i : M); ++j) pi += q[j] * a[i - j];
-    num += pi;
-  }
-  for (int j = 0; j <= M; ++j) den += q[j];
-  *Lused = L;
-  *Mused = M;
-  return num / den;
-}
-
-__global__ __launch_bounds__(64) void finalize_kernel(FinalizeArgs a) {
-  __shared__ double coef[kMaxBins];
-  __shared__ double m1[kMaxBins];
-  __shared__ double m2[kMaxBins];
-  __shared__ double work[kMaxBins];
-  __shared__ double T[kMaxPadeM * (kMaxPadeM + 1)];
-  __shared__ double q[kMaxPadeM + 1];
-
-  const uint32_t p = blockIdx.x;
-  const uint32_t lane = threadIdx.x;
-  const PointRec& pr = a.points[p];
-  const uint32_t B = a.n_bins;
-  const uint32_t NB = B + 3;
-  const double N = (double)pr.n_trees;
-  const double scale = exp(pr.mu * pr.t);
-
-  for (uint32_t b = lane; b < NB; b += kWave) {
-    // Neumaier-compensated sums over the point's segments, in segment order
-    double s1 = 0.0, c1 = 0.0, s2 = 0.0, c2 = 0.0;
-    unsigned long long cnt = 0;
-    for (uint32_t s = 0; s < pr.seg_count; ++s) {
-      const Partial& pt = a.partials[(size_t)(pr.seg_begin + s) * NB + b];
-      cnt += pt.count;
-      double t1 = s1 + pt.s1;
-      c1 += fabs(s1) >= fabs(pt.s1) ? (s1 - t1) + pt.s1 : (pt.s1 - t1) + s1;
-      s1 = t1;
-      double t2 = s2 + pt.s2;
-      c2 += fabs(s2) >= fabs(pt.s2) ? (s2 - t2) + pt.s2 : (pt.s2 - t2) + s2;
-      s2 = t2;
-    }
-    s1 += c1;
-    s2 += c2;
-    if (a.hist) a.hist[(size_t)p * NB + b] = cnt;
-    if (b < B) {
-      if (a.s1) a.s1[(size_t)p * B + b] = s1;
-      if (a.s2) a.s2[(size_t)p * B + b] = s2;
-      const double mm1 = N > 0 ? s1 / N : 0.0;
-      const double mm2 = N > 0 ? s2 / N : 0.0;
-      m1[b] = mm1;
-      m2[b] = mm2;
-      coef[b] = scale * mm1;
-      const double var = N > 1 ? scale * scale * (mm2 - mm1 * mm1) / (N - 1.0) : 0.0;
-      if (a.coef) a.coef[(size_t)p * B + b] = scale * mm1;
-      if (a.coef_var) a.coef_var[(size_t)p * B + b] = var;
-    }
-    if (b == B) work[0] = (double)cnt;      // overflow count
-    if (b == B + 1) work[1] = (double)cnt;  // capped count
-    if (b == B + 2) work[2] = (double)cnt;  // depth count
-  }
-  __syncthreads();
-  unsigned long long nodes = 0;
-  for (uint32_t s = lane; s < pr.seg_count; s += kWave) nodes += a.seg_nodes[pr.seg_begin + s];
-  nodes = wave_sum_u64(nodes);
-
-  if (lane == 0) {
-    uint32_t fl = 0;
-    if (work[0] > 0) fl |= BRT_FLAG_OVERFLOW;
-    if (work[1] > 0) fl |= BRT_FLAG_CAPPED;
-    if (work[2] > 0) fl |= BRT_FLAG_DEPTH;
-    double psum = 0.0;
-    for (uint32_t b = 0; b < B; ++b) psum += coef[b];
-    int Lu, Mu;
-    const int L = (int)a.pade_L, M = (int)a.pade_M;
-    const double u = pade_eval(coef, L, M, q, &Lu, &Mu, T);
-    if (Mu != M) fl |= BRT_FLAG_LOWERED;
-    // pole test: the denominator starts at Q(0) = 1; flag a non-positive value on [0, 1]
-    for (int k = 1; k <= 64; ++k) {
-      const double z = k / 64.0;
-      double qz = 0.0, zp = 1.0;
-      for (int j = 0; j <= Mu; ++j) {
-        qz += q[j] * zp;
-        zp *= z;
-      }
-      if (!(qz > 1e-8)) {
-        fl |= BRT_FLAG_POLE;
-        break;
-      }
-    }
-    // delta-method SE: central differences of the Pade value in each coefficient used
-    const int nuse = L + M + 1;
-    double g1 = 0.0, gv = 0.0;  // sum g_k^2 m2_k and sum g_k m1_k
-    for (int k = 0; k < nuse && k < (int)B; ++k) {
-      for (uint32_t b = 0; b < B; ++b) work[b] = coef[b];
-      const double h = coef[k] != 0.0 ? 1e-6 * fabs(coef[k]) : 1e-12;
-      int l2, m2u;
-      work[k] = coef[k] + h;
-      const double up = pade_eval(work, L, M, q + 0, &l2, &m2u, T);
-      work[k] = coef[k] - h;
-      const double dn = pade_eval(work, L, M, q + 0, &l2, &m2u, T);
-      const double gk = (up - dn) / (2.0 * h) * scale;  // d u / d m1_k
-      g1 += gk * gk * m2[k];
-      gv += gk * m1[k];
-    }
-    const double var = N > 1 ? (g1 - gv * gv) / (N - 1.0) : 0.0;
-    if (a.u) a.u[p] = u;
-    if (a.se) a.se[p] = sqrt(var > 0.0 ? var : 0.0);
-    if (a.psum) a.psum[p] = psum;
-    if (a.flags) a.flags[p] = fl;
-    if (a.nodes) a.nodes[p] = nodes;
   }
 }
 
@@ -760,18 +519,6 @@ hipError_t launch_walk(int precision, int dim, int u0_kind, const WalkArgs& a, i
       }
     }
   }
-  return hipGetLastError();
-}
-
-hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
-  if (a.n_segs == 0) return hipSuccess;
-  hipLaunchKernelGGL(reduce_kernel, dim3(a.n_segs), dim3(kWave), 0, s, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s) {
-  if (a.n_points == 0) return hipSuccess;
-  hipLaunchKernelGGL(finalize_kernel, dim3(a.n_points), dim3(kWave), 0, s, a);
   return hipGetLastError();
 }
 

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -37,7 +38,7 @@ int fail(int code, const char* fmt, ...) {
     if (e_ != hipSuccess) return fail(BRT_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
-constexpr uint32_t kSegTrees = 1u << 16;  // trees per reduction segment
+constexpr uint32_t kSegTrees = 1u << 13;  // trees per reduction segment
 constexpr uint32_t kMaxDepthUnpruned = 64; // stack levels per lane when trees are not pruned
 constexpr uint32_t kDefaultLdsLevels = 8;  // stack levels per lane kept in LDS by default
 
@@ -144,6 +145,10 @@ struct brt_plan {
   brt_out graph_out{};
   hipStream_t graph_stream = nullptr;
   bool use_graph = true;
+  // per-kernel timing mode: events before the walk and after walk, reduce and finalize
+  bool timing = false;
+  std::vector<std::array<hipEvent_t, 4>> ev_pool;
+  size_t ev_used = 0;
 };
 
 extern "C" {
@@ -179,7 +184,7 @@ void brt_destroy(brt_ctx* ctx) { delete ctx; }
 
 int brt_set_launch(brt_ctx* ctx, const brt_launch* l) {
   if (!ctx || !l || l->struct_size != sizeof(brt_launch)) return fail(BRT_E_ARG, "brt_set_launch: bad arguments");
-  if (l->waves_per_block < 1 || l->waves_per_block > 16) return fail(BRT_E_ARG, "waves_per_block must be 1..16");
+  if (l->waves_per_block < 1 || l->waves_per_block > 4) return fail(BRT_E_ARG, "waves_per_block must be 1..4");
   if (l->chunk_trees < 64 || l->chunk_trees % 64 != 0 || l->chunk_trees > (1u << 24))
     return fail(BRT_E_ARG, "chunk_trees must be a multiple of 64 in [64, 2^24]");
   if (l->stack_depth > 255) return fail(BRT_E_ARG, "stack_depth must be <= 255");
@@ -237,6 +242,8 @@ int brt_problem_check(const brt_problem* p, const brt_mc* mc) {
 static void plan_free(brt_plan* p) {
   if (!p) return;
   if (p->graph) (void)hipGraphExecDestroy(p->graph);
+  for (auto& e : p->ev_pool)
+    for (hipEvent_t ev : e) (void)hipEventDestroy(ev);
   (void)hipFree(p->d_points);
   (void)hipFree(p->d_chunks);
   (void)hipFree(p->d_segs);
@@ -438,7 +445,17 @@ static int enqueue(brt_plan* p, const brt_out* o, hipStream_t s) {
     tf = p->d_tree_f;
     tm = p->d_tree_meta;
   }
+  std::array<hipEvent_t, 4>* ev = nullptr;
+  if (p->timing) {
+    if (p->ev_used == p->ev_pool.size()) {
+      std::array<hipEvent_t, 4> e{};
+      for (auto& x : e) HIP_TRY(hipEventCreate(&x));
+      p->ev_pool.push_back(e);
+    }
+    ev = &p->ev_pool[p->ev_used++];
+  }
   HIP_TRY(launch_reset(p->d_counter, p->d_depth, s));
+  if (ev) HIP_TRY(hipEventRecord((*ev)[0], s));
   if (!p->chunks.empty()) {
     WalkArgs w{};
     w.points = p->d_points;
@@ -461,6 +478,7 @@ static int enqueue(brt_plan* p, const brt_out* o, hipStream_t s) {
     w.n_threads = (uint32_t)(p->grid * p->waves_per_block * kWave);
     HIP_TRY(launch_walk(p->precision, p->dim, p->u0_kind, w, p->grid, p->waves_per_block, s));
   }
+  if (ev) HIP_TRY(hipEventRecord((*ev)[1], s));
   ReduceArgs r{};
   r.points = p->d_points;
   r.segs = p->d_segs;
@@ -471,6 +489,7 @@ static int enqueue(brt_plan* p, const brt_out* o, hipStream_t s) {
   r.seg_nodes = p->d_seg_nodes;
   r.n_bins = p->n_bins;
   HIP_TRY(launch_reduce(r, s));
+  if (ev) HIP_TRY(hipEventRecord((*ev)[2], s));
   FinalizeArgs f{};
   f.points = p->d_points;
   f.n_points = p->n_points;
@@ -490,6 +509,7 @@ static int enqueue(brt_plan* p, const brt_out* o, hipStream_t s) {
   f.nodes = reinterpret_cast<unsigned long long*>(o->nodes);
   f.flags = o->flags;
   HIP_TRY(launch_finalize(f, s));
+  if (ev) HIP_TRY(hipEventRecord((*ev)[3], s));
   return BRT_OK;
 }
 
@@ -500,7 +520,7 @@ int brt_plan_execute(brt_plan* p, const brt_out* o, void* stream) {
   if (o->struct_size != sizeof(brt_out)) return fail(BRT_E_ARG, "brt_out.struct_size mismatch");
   HIP_TRY(hipSetDevice(p->ctx->device));
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  if (!s || !p->use_graph) return enqueue(p, o, s);
+  if (!s || !p->use_graph || p->timing) return enqueue(p, o, s);
   if (p->graph && p->graph_stream == s && std::memcmp(&p->graph_out, o, sizeof(brt_out)) == 0) {
     HIP_TRY(hipGraphLaunch(p->graph, s));
     return BRT_OK;
@@ -548,6 +568,31 @@ int brt_plan_depth_exceeded(brt_plan* p, uint64_t* count) {
   unsigned long long v = 0;
   HIP_TRY(hipMemcpy(&v, p->d_depth, sizeof(v), hipMemcpyDeviceToHost));
   *count = v;
+  return BRT_OK;
+}
+
+int brt_plan_set_timing(brt_plan* p, int enable) {
+  if (!p) return fail(BRT_E_ARG, "brt_plan_set_timing: NULL plan");
+  p->timing = enable != 0;
+  p->ev_used = 0;
+  return BRT_OK;
+}
+
+int brt_plan_get_timing(brt_plan* p, double* ms, uint64_t* runs) {
+  if (!p || !ms) return fail(BRT_E_ARG, "brt_plan_get_timing: NULL argument");
+  double acc[3] = {0, 0, 0};
+  for (size_t i = 0; i < p->ev_used; ++i) {
+    auto& e = p->ev_pool[i];
+    HIP_TRY(hipEventSynchronize(e[3]));
+    for (int k = 0; k < 3; ++k) {
+      float v = 0.f;
+      HIP_TRY(hipEventElapsedTime(&v, e[k], e[k + 1]));
+      acc[k] += v;
+    }
+  }
+  for (int k = 0; k < 3; ++k) ms[k] = acc[k];
+  if (runs) *runs = p->ev_used;
+  p->ev_used = 0;
   return BRT_OK;
 }
 

@@ -152,9 +152,10 @@ def oracle_pade(wl, omom):
         a, cov = oracle.coefficients(m, nz.mu, float(wl["t"][p]))
         try:
             val, used, _ = oracle.pade_value(a[: no + 1], L, M)
+            se = oracle.pade_se(a[: no + 1], cov[: no + 1, : no + 1], L, M)
         except np.linalg.LinAlgError:
-            val, used = float("nan"), None
-        res.append({"a": a, "cov": cov, "pade": val, "used": used, "psum": math.fsum(a.tolist())})
+            val, used, se = float("nan"), None, float("nan")
+        res.append({"a": a, "cov": cov, "pade": val, "used": used, "se": se, "psum": math.fsum(a.tolist())})
     return res
 
 
@@ -192,6 +193,12 @@ def compare_pade(wl, gpu, opade, pade_tol=1e-3):
         v, used, _ = oracle.pade_value(ag, L, M)
         if used == r["used"]:
             assert abs(gpu["u"][p] - v) <= 1e-9 * max(1.0, abs(v)), (p, gpu["u"][p], v)
+            # delta-method SE: the device's exact gradient against the oracle's central differences
+            se_tol = 1e-4 if mc["precision"] == 64 else 1e-2
+            if np.isfinite(r["se"]) and abs(r["pade"]) < 1e3:
+                # absolute floor: sqrt of the rounding of m2 - m1^2 (exact cancellation at t = 0)
+                floor = 1e-7 * float(np.abs(r["a"]).max())
+                assert abs(gpu["se"][p] - r["se"]) <= se_tol * r["se"] + floor, (p, gpu["se"][p], r["se"])
         du = abs(gpu["u"][p] - r["pade"])
         prop = float(np.abs(pade_grad(r["a"][: no + 1], L, M)) @ np.abs(ag - r["a"][: no + 1]))
         assert du <= pade_tol + 4 * prop, (p, gpu["u"][p], r["pade"], prop)
