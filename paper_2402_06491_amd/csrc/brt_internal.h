@@ -131,6 +131,6 @@ hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s);
 size_t walk_lds_bytes(int precision, int dim, int stack_depth, int waves_per_block);
 size_t stack_entry_size(int precision, int dim);
-int walk_max_blocks_per_cu(int precision, int dim, int u0_kind, int stack_depth, int waves_per_block);
+int walk_max_blocks_per_cu(int precision, int dim, int u0_kind, bool multi, int stack_depth, int waves_per_block);
 
 }  // namespace brt

@@ -1,13 +1,13 @@
-// HIP kernels of the random-tree Monte Carlo (Strategy A, Sec. 2.1) for gfx950.
+// HIP tree walker of the random-tree Monte Carlo (Strategy A, Sec. 2.1) for gfx950.
 //
-//  walk_kernel      persistent, work-stealing tree walker: one tree per lane, one node per loop
-//                   iteration, explicit per-lane DFS stack in LDS, lanes refilled from the wave's
-//                   chunk with ballot/popcount; writes one record (value, splits, nodes, flags)
-//                   per tree.
+//  walk_kernel  persistent, work-stealing: one tree per lane, one node per loop iteration, an
+//               explicit per-lane DFS stack (LDS, then a per-thread global spill area), idle lanes
+//               refilled from the wave's chunk with ballot/popcount; one record (value, splits,
+//               nodes, flags) per tree.
 //
-// The moment reduction and the FP64 finalize are in brt_moments.hip.
-// The walker computes no MFMA work: nothing here is a dense contraction.  It is bound by VALU
-// issue (Philox integer multiplies and transcendentals).
+// The moment reduction and the FP64 finalize are in brt_moments.hip.  Nothing here is a dense
+// contraction, so there is no MFMA work: the kernel is bound by VALU issue (Philox's 32x32->64
+// integer multiplies and the transcendentals of Box-Muller, the clock and the weights).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -17,12 +17,18 @@ namespace brt {
 
 // ------------------------------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of two 32x32->64 multiplies and
-// xors, with the Weyl key schedule.  The key is wave-uniform (kernel argument) so its schedule runs
+// xors, with the Weyl key schedule.  The key is wave-uniform (kernel argument), so its schedule runs
 // on the scalar unit.
 // ------------------------------------------------------------------------------------------------
 struct U4 {
   uint32_t a, b, c, d;
 };
+
+// Three-input xor in one VALU instruction: gfx950's v_bitop3_b32 with truth table 0x96
+// (a ^ b ^ c); the compiler otherwise emits two v_xor_b32.
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t k) {
+  return __builtin_amdgcn_bitop3_b32(a, b, k, 0x96);
+}
 
 __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
                                             uint32_t k1) {
@@ -30,8 +36,8 @@ __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c
   for (int r = 0; r < 10; ++r) {
     const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
     const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
-    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+    const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
     c1 = (uint32_t)p1;
     c3 = (uint32_t)p0;
     c0 = n0;
@@ -44,9 +50,9 @@ __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c
 
 // ------------------------------------------------------------------------------------------------
 // Precision-dependent elementary functions.
-// FP32: hardware log2/exp2/sqrt/sin/cos (v_log_f32, v_exp_f32, v_sqrt_f32, v_sin_f32, v_cos_f32;
-// the sin/cos units take their argument in revolutions, which is exactly the Box-Muller angle u2).
-// FP64: the device math library.
+// FP32: hardware log2/exp2/sqrt/sin/cos/rcp (v_log_f32, v_exp_f32, v_sqrt_f32, v_sin_f32, v_cos_f32,
+// v_rcp_f32; the sin/cos units take their argument in revolutions, which is exactly the Box-Muller
+// angle u2).  FP64: the device math library.
 // ------------------------------------------------------------------------------------------------
 template <typename Real>
 struct Math;
@@ -80,20 +86,30 @@ struct Math<double> {
 // ------------------------------------------------------------------------------------------------
 // Initial data g at the end of a leaf path.
 // ------------------------------------------------------------------------------------------------
+// Logistic initial data A (1 + e^{s (n.x - x0)})^{-p}, split around its exponential.
+template <typename Real, int DIM>
+__device__ __forceinline__ Real logistic_arg(const PdeT<Real>& pd, const Real* x) {
+  Real nx = x[0] * pd.u0[4];
+  if constexpr (DIM == 2) nx += x[1] * pd.u0[5];
+  return pd.u0[1] * (nx - pd.u0[2]);
+}
+
+template <typename Real>
+__device__ __forceinline__ Real logistic_finish(const PdeT<Real>& pd, Real e) {
+  const Real base = Math<Real>::rcp((Real)1 + e);
+  Real r = base;
+  const int pw = (int)pd.u0[3];
+  for (int i = 1; i < pw; ++i) r *= base;
+  return pd.u0[0] * r;
+}
+
 template <typename Real, int DIM, int U0>
 __device__ __forceinline__ Real eval_g(const PdeT<Real>& pd, const Real* x) {
   const Real* p = pd.u0;
   if constexpr (U0 == 0) {
     return p[0];
   } else if constexpr (U0 == 1) {
-    Real nx = x[0] * p[4];
-    if constexpr (DIM == 2) nx += x[1] * p[5];
-    const Real e = Math<Real>::ex(p[1] * (nx - p[2]));
-    const Real base = Math<Real>::rcp((Real)1 + e);
-    Real r = base;
-    const int pw = (int)p[3];
-    for (int i = 1; i < pw; ++i) r *= base;
-    return p[0] * r;
+    return logistic_finish<Real>(pd, Math<Real>::ex(logistic_arg<Real, DIM>(pd, x)));
   } else if constexpr (U0 == 2) {
     Real acc = 0;
     for (uint32_t k = 0; k < pd.u0_nterms; ++k) {
@@ -122,23 +138,6 @@ __device__ __forceinline__ Real eval_g(const PdeT<Real>& pd, const Real* x) {
   }
 }
 
-// Logistic initial data A (1 + e^{s (n.x - x0)})^{-p}, split around its exponential.
-template <typename Real, int DIM>
-__device__ __forceinline__ Real logistic_arg(const PdeT<Real>& pd, const Real* x) {
-  Real nx = x[0] * pd.u0[4];
-  if constexpr (DIM == 2) nx += x[1] * pd.u0[5];
-  return pd.u0[1] * (nx - pd.u0[2]);
-}
-
-template <typename Real>
-__device__ __forceinline__ Real logistic_finish(const PdeT<Real>& pd, Real e) {
-  const Real base = Math<Real>::rcp((Real)1 + e);
-  Real r = base;
-  const int pw = (int)pd.u0[3];
-  for (int i = 1; i < pw; ++i) r *= base;
-  return pd.u0[0] * r;
-}
-
 __device__ __forceinline__ uint64_t lanemask_lt() {
   const uint32_t lane = __lane_id();
   return (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -158,7 +157,7 @@ __host__ __device__ constexpr size_t pde_table_bytes(int n) {
 // Per-lane DFS stack.  An entry is pushed for each vertex that still has children to start: the
 // state its children depart from (clock product P, position, time left) and the number of children
 // not yet started.  The top `lds_depth` levels live in LDS (structure of arrays, one slot per lane so
-// lanes never conflict), deeper levels in a per-thread global spill area.
+// lanes never conflict); deeper levels go to the thread's own slice of a global spill area.
 // ------------------------------------------------------------------------------------------------
 #define BRT_LDS __attribute__((address_space(3)))
 
@@ -166,15 +165,15 @@ template <typename Real, int DIM>
 struct Stack {
   // LDS pointers carry their address space so that the compiler keeps ds_* instructions for them
   // instead of merging both tiers into generic (flat) accesses through a selected pointer.
-  BRT_LDS double* P;   // LDS [lds_depth][64]
-  BRT_LDS Real* X;     // LDS [DIM][lds_depth][64]
-  BRT_LDS Real* T;     // LDS [lds_depth][64]
-  BRT_LDS uint8_t* R;  // LDS [lds_depth][64]
-  double* gP;     // global [spill_depth][n_threads]
-  Real* gX;       // global [DIM][spill_depth][n_threads]
-  Real* gT;       // global [spill_depth][n_threads]
-  uint8_t* gR;    // global [spill_depth][n_threads]
-  uint32_t lds_depth, spill_depth, n_threads, lane, gtid;
+  BRT_LDS double* P;   // [lds_depth][64]
+  BRT_LDS Real* X;     // [DIM][lds_depth][64]
+  BRT_LDS Real* T;     // [lds_depth][64]
+  BRT_LDS uint8_t* R;  // [lds_depth][64]
+  double* gP;          // this thread's spill levels: [spill_depth]
+  Real* gX;            // [DIM][spill_depth]
+  Real* gT;            // [spill_depth]
+  uint8_t* gR;         // [spill_depth]
+  uint32_t lds_depth, spill_depth, lane;
 
   __device__ __forceinline__ void push(uint32_t sp, double p, const Real* x, Real t, uint32_t rem) {
     if (sp < lds_depth) {
@@ -185,10 +184,10 @@ struct Stack {
       T[o] = t;
       R[o] = (uint8_t)rem;
     } else {
-      const size_t o = (size_t)(sp - lds_depth) * n_threads + gtid;
+      const uint32_t o = sp - lds_depth;
       gP[o] = p;
       gX[o] = x[0];
-      if constexpr (DIM == 2) gX[(size_t)spill_depth * n_threads + o] = x[1];
+      if constexpr (DIM == 2) gX[spill_depth + o] = x[1];
       gT[o] = t;
       gR[o] = (uint8_t)rem;
     }
@@ -207,10 +206,10 @@ struct Stack {
       rem = (uint32_t)R[o] - 1u;
       R[o] = (uint8_t)rem;
     } else {
-      const size_t o = (size_t)(lv - lds_depth) * n_threads + gtid;
+      const uint32_t o = lv - lds_depth;
       *p = gP[o];
       x[0] = gX[o];
-      if constexpr (DIM == 2) x[1] = gX[(size_t)spill_depth * n_threads + o];
+      if constexpr (DIM == 2) x[1] = gX[spill_depth + o];
       *t = gT[o];
       rem = (uint32_t)gR[o] - 1u;
       gR[o] = (uint8_t)rem;
@@ -220,9 +219,10 @@ struct Stack {
 };
 
 // ------------------------------------------------------------------------------------------------
-// The walker.
+// The walker.  MULTI: the plan has several problems (per-lane problem index); otherwise the
+// problem constants are loop invariants.
 // ------------------------------------------------------------------------------------------------
-template <typename Real, int DIM, int U0>
+template <typename Real, int DIM, int U0, bool MULTI>
 __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
 
@@ -247,16 +247,17 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
     st.X = (BRT_LDS Real*)(st.P + depth * kWave);
     st.T = st.X + DIM * depth * kWave;
     st.R = (BRT_LDS uint8_t*)(st.T + depth * kWave);
+    // spill area: per thread, stride-1 levels (deep levels are rare, so coalescing does not matter)
+    const size_t gtid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t sd = (size_t)a.spill_depth * a.n_threads;
-    st.gP = reinterpret_cast<double*>(a.spill);
-    st.gX = reinterpret_cast<Real*>(st.gP + sd);
-    st.gT = st.gX + DIM * sd;
-    st.gR = reinterpret_cast<uint8_t*>(st.gT + sd);
+    const size_t me = gtid * a.spill_depth;
+    st.gP = reinterpret_cast<double*>(a.spill) + me;
+    st.gX = reinterpret_cast<Real*>(reinterpret_cast<double*>(a.spill) + sd) + DIM * me;
+    st.gT = reinterpret_cast<Real*>(reinterpret_cast<double*>(a.spill) + sd) + DIM * sd + me;
+    st.gR = reinterpret_cast<uint8_t*>(reinterpret_cast<Real*>(reinterpret_cast<double*>(a.spill) + sd) + (DIM + 1) * sd) + me;
     st.lds_depth = depth;
     st.spill_depth = a.spill_depth;
-    st.n_threads = a.n_threads;
     st.lane = lane;
-    st.gtid = blockIdx.x * blockDim.x + threadIdx.x;
   }
   const uint32_t max_depth = a.stack_depth + a.spill_depth;
 
@@ -265,154 +266,152 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
   const uint32_t max_order = a.max_order;
   const bool prune = a.prune != 0;
 
-  // wave-uniform chunk cursor
-  uint32_t c_next = 0, c_end = 0, c_point = 0;
+  // Wave-uniform chunk cursor and the constants of the chunk's point, held in scalar registers: a
+  // refill copies them into the new lanes without touching memory.  The index of the chunk after
+  // the current one is requested as soon as the current one starts.
+  uint32_t c_next = 0, c_end = 0;
   bool more = true;
+  uint32_t c_pid = 0, c_pde = 0;
+  uint64_t c_base = 0;
+  double c_theta = 1.0;
+  Real c_t = 0, c_x0 = 0, c_x1 = 0;
+  uint32_t next_raw = 0;
+  if (lane == 0) next_raw = atomicAdd(a.chunk_counter, 1u);
 
   // per-lane tree state
   bool active = false;
-  uint32_t tree = 0, node = 0, ne = 0, flags = 0, sp = 0, pid = 0, pde = 0;
+  uint32_t tree = 0, node = 0, ne = 0, flags = 0, sp = 0, pid = 0, pde_lane = 0;
   uint64_t rec = 0;
   double P = 1.0, theta = 1.0;
   double F = 1.0;  // running product of the tree's factors (FP64 for range: weights reach e^{32} per vertex)
   Real tau = 0;
   Real x[2] = {0, 0};
-  Real sigma = 0, inv_lambda = 0, mu = 0;
-  uint32_t K = 0, jpack = 0;
 
   while (true) {
-    // ---- refill idle lanes from the wave's chunk, stealing new chunks as needed ----
-    uint64_t need = __ballot(!active);
-    while (need != 0 && more) {
+    // ---- refill: idle lanes take trees from the wave's chunk; at most one chunk switch per
+    // iteration (lanes left without a tree at a chunk boundary wait one node step) ----
+    const uint64_t need = __ballot(!active);
+    if (need != 0 && more) {
       if (c_next == c_end) {
-        uint32_t ci = 0;
-        if (lane == 0) ci = atomicAdd(a.chunk_counter, 1u);
-        ci = __shfl(ci, 0);
+        const uint32_t ci = __builtin_amdgcn_readfirstlane(next_raw);
         if (ci >= a.n_chunks) {
           more = false;
-          break;
+        } else {
+          if (lane == 0) next_raw = atomicAdd(a.chunk_counter, 1u);
+          const Chunk ch = a.chunks[ci];
+          c_next = __builtin_amdgcn_readfirstlane(ch.begin);
+          c_end = __builtin_amdgcn_readfirstlane(ch.end);
+          const uint32_t point = __builtin_amdgcn_readfirstlane(ch.point);
+          const PointRec& pr = a.points[point];
+          c_pid = pr.point_id;
+          c_pde = pr.pde;
+          c_base = pr.tree_base;
+          c_theta = pr.theta;
+          c_t = (Real)pr.t;
+          c_x0 = (Real)pr.x[0];
+          c_x1 = (Real)pr.x[1];
         }
-        const Chunk ch = a.chunks[ci];
-        c_next = ch.begin;
-        c_end = ch.end;
-        c_point = ch.point;
-        continue;
       }
-      const uint32_t avail = c_end - c_next;
-      const uint32_t cnt = (uint32_t)__popcll(need);
-      const uint32_t take = cnt < avail ? cnt : avail;
-      const uint32_t rank = (uint32_t)__popcll(need & lt);
-      const bool mine = ((need >> lane) & 1ull) && rank < take;
-      if (mine) {
-        const PointRec& pr = a.points[c_point];
-        tree = c_next + rank;
-        pid = pr.point_id;
-        pde = pr.pde;
-        rec = pr.tree_base + tree;
-        theta = pr.theta;
-        tau = (Real)pr.t;
-        x[0] = (Real)pr.x[0];
-        x[1] = (Real)pr.x[1];
-        P = 1.0;
-        F = 1.0;
-        node = 0;
-        ne = 0;
-        flags = 0;
-        sp = 0;
-        const PdeT<Real>& pd = pdes[pde];
-        sigma = pd.sigma;
-        inv_lambda = pd.inv_lambda;
-        mu = pd.mu;
-        K = pd.K;
-        jpack = pd.jpack;
-        active = true;
+      if (more) {
+        const uint32_t avail = c_end - c_next;
+        const uint32_t cnt = (uint32_t)__popcll(need);
+        const uint32_t take = cnt < avail ? cnt : avail;
+        const uint32_t rank = (uint32_t)__popcll(need & lt);
+        if (!active && rank < take) {
+          tree = c_next + rank;
+          pid = c_pid;
+          pde_lane = c_pde;
+          rec = c_base + tree;
+          theta = c_theta;
+          tau = c_t;
+          x[0] = c_x0;
+          x[1] = c_x1;
+          P = 1.0;
+          F = 1.0;
+          node = 0;
+          ne = 0;
+          flags = 0;
+          sp = 0;
+          active = true;
+        }
+        c_next += take;
       }
-      need &= ~__ballot(mine);
-      c_next += take;
     }
-    if (__ballot(active) == 0) break;
+    if (__ballot(active) == 0) {
+      if (!more) break;
+      continue;
+    }
     if (!active) continue;
 
+    const PdeT<Real>& pd = pdes[MULTI ? pde_lane : 0u];
+
     // ---- one node of this lane's tree ----
-    bool done = false;
-    bool branch_end = false;
-    if (node >= node_cap) {
-      flags |= kMetaCapped;
-      done = true;
+    // Vertex and leaf quantities are computed for every lane and chosen with selects; only the stack
+    // push, the stack pop and the record write are divergent.
+    const bool capped = node >= node_cap;
+    const U4 w = philox4x32_10(node, tree, pid, 0u, a.key0, a.key1);
+    const double U = fma((double)w.a, 0x1p-32, 0x1p-33);  // (w0 + 1/2) 2^-32, exact
+    const double Pn = P * U;
+    const bool vertex = !capped && Pn > theta;
+
+    const Real u1 = ((Real)w.c + (Real)0.5) * (Real)0x1p-32;
+    const Real u2 = (Real)w.d * (Real)0x1p-32;
+    const Real r = Math<Real>::sq((Real)-2 * Math<Real>::ln(u1));
+    Real sn, cs;
+    Math<Real>::sincos_rev(u2, &sn, &cs);
+    const Real S = -Math<Real>::ln((Real)U) * pd.inv_lambda;
+    const Real sd = pd.sigma * Math<Real>::sq(vertex ? S : tau);
+    Real xn[2];
+    xn[0] = x[0] + sd * (r * cs);
+    xn[1] = x[1] + sd * (r * sn);
+
+    // one exponential per node: the vertex weight e^{(alpha-1) mu tau'} or, for logistic initial
+    // data, e^{s (n.x - x0)} at the leaf
+    Real tau2 = tau - S;
+    tau2 = tau2 < (Real)0 ? (Real)0 : tau2;
+    const uint32_t idx = __umulhi(w.b, pd.K);
+    const uint32_t alpha = (pd.jpack >> (4 * idx)) & 15u;
+    Real earg = (Real)((int)alpha - 1) * pd.mu * tau2;
+    if constexpr (U0 == 1) earg = vertex ? earg : logistic_arg<Real, DIM>(pd, xn);
+    const Real E = Math<Real>::ex(earg);
+    Real factor;
+    if constexpr (U0 == 1) {
+      factor = vertex ? pd.omega[idx] * E : logistic_finish<Real>(pd, E);
     } else {
-      const U4 w = philox4x32_10(node, tree, pid, 0u, a.key0, a.key1);
-      node += 1;
-      const double U = ((double)w.a + 0.5) * 0x1p-32;
-      const double Pn = P * U;
-      const bool vertex = Pn > theta;
+      if (vertex)
+        factor = pd.omega[idx] * E;
+      else
+        factor = eval_g<Real, DIM, U0>(pd, xn);
+    }
 
-      const Real u1 = ((Real)w.c + (Real)0.5) * (Real)0x1p-32;
-      const Real u2 = (Real)w.d * (Real)0x1p-32;
-      const Real r = Math<Real>::sq((Real)-2 * Math<Real>::ln(u1));
-      Real sn, cs;
-      Math<Real>::sincos_rev(u2, &sn, &cs);
-      const Real S = -Math<Real>::ln((Real)U) * inv_lambda;
-      const Real dt = vertex ? S : tau;
-      const Real sd = sigma * Math<Real>::sq(dt);
-      Real xn[2];
-      xn[0] = x[0] + sd * (r * cs);
-      xn[1] = x[1] + sd * (r * sn);
-
-      // One exponential per node, taken outside the vertex/leaf branches: the vertex weight
-      // e^{(alpha-1) mu tau'} or, for logistic initial data, e^{s (n.x - x0)} at the leaf.
-      Real earg = 0, om = 0, tau2 = 0;
-      uint32_t alpha = 0;
-      if (vertex) {
-        tau2 = tau - S;
-        tau2 = tau2 < (Real)0 ? (Real)0 : tau2;
-        const uint32_t idx = __umulhi(w.b, K);
-        alpha = (jpack >> (4 * idx)) & 15u;
-        om = pdes[pde].omega[idx];
-        earg = (Real)((int)alpha - 1) * mu * tau2;
-      } else if constexpr (U0 == 1) {
-        earg = logistic_arg<Real, DIM>(pdes[pde], xn);
-      }
-      const Real E = Math<Real>::ex(earg);
-
-      if (vertex) {
-        ne += 1;
-        if (prune && ne > max_order) {
-          flags |= kMetaOverflow;
-          done = true;
-        } else {
-          F *= (double)(om * E);
-          if (alpha == 0) {
-            branch_end = true;
-          } else {
-            if (alpha >= 2) {
-              if (sp == max_depth) {
-                flags |= kMetaDepth;
-                done = true;
-              } else {
-                st.push(sp, Pn, xn, tau2, alpha - 1);
-                sp += 1;
-              }
-            }
-            x[0] = xn[0];
-            x[1] = xn[1];
-            P = Pn;
-            tau = tau2;
-          }
-        }
+    ne += vertex ? 1u : 0u;
+    const bool ovf = vertex && prune && ne > max_order;
+    const bool vok = vertex && !ovf;
+    flags |= (capped ? kMetaCapped : 0u) | (ovf ? kMetaOverflow : 0u);
+    node += capped ? 0u : 1u;
+    F *= (double)factor;
+    bool done = capped || ovf;
+    if (vok && alpha >= 2) {
+      if (sp == max_depth) {
+        flags |= kMetaDepth;
+        done = true;
       } else {
-        if constexpr (U0 == 1)
-          F *= (double)logistic_finish<Real>(pdes[pde], E);
-        else
-          F *= (double)eval_g<Real, DIM, U0>(pdes[pde], xn);
-        branch_end = true;
+        st.push(sp, Pn, xn, tau2, alpha - 1);
+        sp += 1;
       }
-      if (branch_end) {
-        if (sp == 0) {
-          done = true;
-        } else {
-          const uint32_t rem = st.top(sp, &P, x, &tau);
-          if (rem == 0) sp -= 1;
-        }
+    }
+    const bool cont = vok && alpha > 0;  // the vertex's first child departs from the split point
+    x[0] = cont ? xn[0] : x[0];
+    x[1] = cont ? xn[1] : x[1];
+    P = cont ? Pn : P;
+    tau = cont ? tau2 : tau;
+    const bool branch_end = !done && !cont;  // a leaf, or a vertex without children
+    if (branch_end) {
+      if (sp == 0) {
+        done = true;
+      } else {
+        const uint32_t rem = st.top(sp, &P, x, &tau);
+        if (rem == 0) sp -= 1;
       }
     }
     if (done) {
@@ -441,38 +440,40 @@ size_t stack_entry_size(int precision, int dim) {
 
 size_t walk_lds_bytes(int precision, int dim, int stack_depth, int waves_per_block) {
   const size_t sd = (size_t)stack_depth * kWave * waves_per_block;
-  if (precision == 32)
-    return pde_table_bytes<float>(kMaxProblems) +
-           sd * (dim == 1 ? stack_entry_bytes<float, 1>() : stack_entry_bytes<float, 2>());
-  return pde_table_bytes<double>(kMaxProblems) +
-         sd * (dim == 1 ? stack_entry_bytes<double, 1>() : stack_entry_bytes<double, 2>());
+  if (precision == 32) return pde_table_bytes<float>(kMaxProblems) + sd * stack_entry_size(32, dim);
+  return pde_table_bytes<double>(kMaxProblems) + sd * stack_entry_size(64, dim);
 }
 
-template <typename Real, int DIM, int U0>
+template <typename Real, int DIM, int U0, bool MULTI>
 static const void* walk_ptr() {
-  return reinterpret_cast<const void*>(&walk_kernel<Real, DIM, U0>);
+  return reinterpret_cast<const void*>(&walk_kernel<Real, DIM, U0, MULTI>);
 }
 
-template <typename Real, int DIM>
+template <typename Real, int DIM, bool MULTI>
 static const void* walk_ptr_u0(int u0) {
   switch (u0) {
-    case 0: return walk_ptr<Real, DIM, 0>();
-    case 1: return walk_ptr<Real, DIM, 1>();
-    case 2: return walk_ptr<Real, DIM, 2>();
-    default: return walk_ptr<Real, DIM, 3>();
+    case 0: return walk_ptr<Real, DIM, 0, MULTI>();
+    case 1: return walk_ptr<Real, DIM, 1, MULTI>();
+    case 2: return walk_ptr<Real, DIM, 2, MULTI>();
+    default: return walk_ptr<Real, DIM, 3, MULTI>();
   }
 }
 
-static const void* walk_fn(int precision, int dim, int u0) {
-  if (precision == 32) return dim == 1 ? walk_ptr_u0<float, 1>(u0) : walk_ptr_u0<float, 2>(u0);
-  return dim == 1 ? walk_ptr_u0<double, 1>(u0) : walk_ptr_u0<double, 2>(u0);
+template <typename Real, int DIM>
+static const void* walk_ptr_m(int u0, bool multi) {
+  return multi ? walk_ptr_u0<Real, DIM, true>(u0) : walk_ptr_u0<Real, DIM, false>(u0);
 }
 
-int walk_max_blocks_per_cu(int precision, int dim, int u0_kind, int stack_depth, int waves_per_block) {
+static const void* walk_fn(int precision, int dim, int u0, bool multi) {
+  if (precision == 32) return dim == 1 ? walk_ptr_m<float, 1>(u0, multi) : walk_ptr_m<float, 2>(u0, multi);
+  return dim == 1 ? walk_ptr_m<double, 1>(u0, multi) : walk_ptr_m<double, 2>(u0, multi);
+}
+
+int walk_max_blocks_per_cu(int precision, int dim, int u0_kind, bool multi, int stack_depth, int waves_per_block) {
   int nb = 0;
   const size_t lds = walk_lds_bytes(precision, dim, stack_depth, waves_per_block);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_fn(precision, dim, u0_kind), waves_per_block * kWave,
-                                                   lds) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_fn(precision, dim, u0_kind, multi),
+                                                   waves_per_block * kWave, lds) != hipSuccess)
     return 0;
   return nb;
 }
@@ -485,41 +486,9 @@ hipError_t launch_reset(uint32_t* chunk_counter, unsigned long long* depth_count
 hipError_t launch_walk(int precision, int dim, int u0_kind, const WalkArgs& a, int grid, int waves_per_block,
                        hipStream_t s) {
   const size_t lds = walk_lds_bytes(precision, dim, (int)a.stack_depth, waves_per_block);
-  const dim3 g(grid), b(waves_per_block * kWave);
-  if (precision == 32) {
-    if (dim == 1) {
-      switch (u0_kind) {
-        case 0: hipLaunchKernelGGL((walk_kernel<float, 1, 0>), g, b, lds, s, a); break;
-        case 1: hipLaunchKernelGGL((walk_kernel<float, 1, 1>), g, b, lds, s, a); break;
-        case 2: hipLaunchKernelGGL((walk_kernel<float, 1, 2>), g, b, lds, s, a); break;
-        default: hipLaunchKernelGGL((walk_kernel<float, 1, 3>), g, b, lds, s, a); break;
-      }
-    } else {
-      switch (u0_kind) {
-        case 0: hipLaunchKernelGGL((walk_kernel<float, 2, 0>), g, b, lds, s, a); break;
-        case 1: hipLaunchKernelGGL((walk_kernel<float, 2, 1>), g, b, lds, s, a); break;
-        case 2: hipLaunchKernelGGL((walk_kernel<float, 2, 2>), g, b, lds, s, a); break;
-        default: hipLaunchKernelGGL((walk_kernel<float, 2, 3>), g, b, lds, s, a); break;
-      }
-    }
-  } else {
-    if (dim == 1) {
-      switch (u0_kind) {
-        case 0: hipLaunchKernelGGL((walk_kernel<double, 1, 0>), g, b, lds, s, a); break;
-        case 1: hipLaunchKernelGGL((walk_kernel<double, 1, 1>), g, b, lds, s, a); break;
-        case 2: hipLaunchKernelGGL((walk_kernel<double, 1, 2>), g, b, lds, s, a); break;
-        default: hipLaunchKernelGGL((walk_kernel<double, 1, 3>), g, b, lds, s, a); break;
-      }
-    } else {
-      switch (u0_kind) {
-        case 0: hipLaunchKernelGGL((walk_kernel<double, 2, 0>), g, b, lds, s, a); break;
-        case 1: hipLaunchKernelGGL((walk_kernel<double, 2, 1>), g, b, lds, s, a); break;
-        case 2: hipLaunchKernelGGL((walk_kernel<double, 2, 2>), g, b, lds, s, a); break;
-        default: hipLaunchKernelGGL((walk_kernel<double, 2, 3>), g, b, lds, s, a); break;
-      }
-    }
-  }
-  return hipGetLastError();
+  const void* fn = walk_fn(precision, dim, u0_kind, a.n_problems > 1);
+  void* args[] = {const_cast<WalkArgs*>(&a)};
+  return hipLaunchKernel(fn, dim3(grid), dim3(waves_per_block * kWave), args, lds, s);
 }
 
 }  // namespace brt

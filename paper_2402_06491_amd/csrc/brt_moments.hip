@@ -16,6 +16,9 @@
 namespace brt {
 
 constexpr int kRedGroup = 16;  // moment bins accumulated per pass over a segment
+constexpr int kRedBatch = 8;   // records loaded per lane before they are accumulated
+constexpr uint32_t kAbsent = 0xffffffffu;  // marks a batch slot past the end of the segment (no real
+                                           // record has every flag bit set)
 
 __device__ __forceinline__ double wave_sum_f64(double v) {
 #pragma unroll
@@ -54,9 +57,22 @@ __global__ __launch_bounds__(64) void reduce_kernel(ReduceArgs a) {
       lcnt[k][lane] = 0u;
     }
     bool above = false;
-    for (uint32_t i = sg.begin + lane; i < sg.end; i += kWave) {
-      const uint32_t m = M[i];
-      const double f = F[i];
+    // records are loaded kRedBatch at a time so that many loads are in flight per lane; each lane
+    // still adds its records in increasing index order
+    for (uint32_t i0 = sg.begin + lane; i0 < sg.end; i0 += kWave * kRedBatch) {
+      uint32_t mb[kRedBatch];
+      double fb[kRedBatch];
+#pragma unroll
+      for (int j = 0; j < kRedBatch; ++j) {
+        const uint32_t i = i0 + j * kWave;
+        mb[j] = i < sg.end ? M[i] : kAbsent;
+        fb[j] = i < sg.end ? F[i] : 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < kRedBatch; ++j) {
+      const uint32_t m = mb[j];
+      const double f = fb[j];
+      if (m == kAbsent) continue;
       if (g0 == 0) {
         nodes += (unsigned long long)(m >> kMetaNodesShift);
         n_ovf += (m >> 8) & 1u;
@@ -73,6 +89,7 @@ __global__ __launch_bounds__(64) void reduce_kernel(ReduceArgs a) {
         lcnt[k][lane] += 1u;
       }
       above |= bin >= g0 + kRedGroup;
+      }
     }
     for (int k = 0; k < kRedGroup; ++k) {
       const uint32_t b = g0 + k;
