@@ -286,3 +286,24 @@ def test_node_cap_and_pruning_flags(oracle_mod):
     rec2 = oracle_mod.walk_point(prob, inputs.mc_params(max_order=0, prune=1), [0.0], 1.0, 0, 2000)
     assert np.array_equal(rec2["flags"] == 1, split)
     assert abs(split.mean() - (1 - math.exp(-1))) < Z * 0.5 / math.sqrt(2000)
+
+
+# --- the Crank-Nicolson reference itself ---------------------------------------------------------
+def test_cn_hierarchy_constant_data_is_ode_series():
+    """With spatially constant g the CN hierarchy must give the KPP closed form at every x."""
+    g0, t = 0.7, 1.0
+    xq = np.array([-1.0, 0.0, 2.0])
+    ref = cn.cn_hierarchy(lambda x: np.full_like(x, g0), 0.5, [0, -1, 1], xq, t, 4, L=8.0, h=1 / 8, dt=1 / 100)
+    for n in range(5):
+        ex = g0 ** (n + 1) * math.exp(-t) * (1 - math.exp(-t)) ** n
+        np.testing.assert_allclose(ref[n], ex, rtol=0, atol=1e-8)
+
+
+def test_cn_full_heat_kernel():
+    """f = 0: CN on the heat equation against the exact spreading of a Gaussian."""
+    t = 0.8
+    xq = np.array([-2.0, 0.0, 1.5])
+    g = lambda x: np.exp(-x * x / 4) / math.sqrt(4 * math.pi)  # noqa: E731
+    u = cn.cn_full(g, 1.0, [0.0, 0.0], xq, t, L=20.0, h=1 / 16, dt=1 / 200)
+    ex = np.exp(-xq * xq / (4 * (t + 1))) / np.sqrt(4 * math.pi * (t + 1))
+    np.testing.assert_allclose(u, ex, rtol=0, atol=1e-7)
