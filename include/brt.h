@@ -101,6 +101,8 @@ typedef struct brt_points {
   const uint64_t* n_trees;  /* n, 0..2^32-1 trees per point */
   const uint32_t* problem_id; /* n, index into the problem array; NULL = all 0 */
   const uint32_t* point_id;   /* n, Philox counter word 2; NULL = 0..n-1 */
+  const uint32_t* tree_first; /* n, tree counter of each point's first tree (a later call continues a
+                                 point's sample with fresh trees); NULL = 0 */
 } brt_points;
 
 /* Per-point flags (brt_out.flags). */
@@ -165,7 +167,7 @@ int brt_get_launch(brt_ctx* ctx, brt_launch* launch);
  * mu = c_1 + lambda, vertex weight K c_j / lambda e^{(j-1) mu tau}), upload the point records, cut
  * every point's trees into work chunks ordered by estimated cost, and reserve device scratch
  * (tree records unless the caller supplies brt_out.tree_f/tree_meta).  Host arrays are copied.
- * At most 16 problems per plan; all of one dim and u0_kind. */
+ * At most 64 problems per plan; all of one dim and u0_kind. */
 int brt_plan_create(brt_ctx* ctx, uint32_t n_problems, const brt_problem* problems, const brt_mc* mc,
                     const brt_points* points, brt_plan** out);
 
@@ -195,6 +197,77 @@ void brt_plan_destroy(brt_plan* plan);
  * tree exceeded the stack depth (other results are still written). */
 int brt_solve(brt_ctx* ctx, uint32_t n_problems, const brt_problem* problems, const brt_mc* mc,
               const brt_points* points, const brt_out* out, void* stream);
+
+/* ------------------------------------------------------------------------------------------------
+ * Serving: continuous batching of point-query requests (the data-parallel structure of the
+ * probabilistic part of Sec. 3: independent points, each summed from independent trees).
+ *
+ * An engine thread runs ticks; each tick adds one round of `round_trees` trees to every unfinished
+ * point of every admitted request, packing all requests (64 per launch) into shared launches.  The
+ * reduction partials of every round stay on the device in the point's slot; the finalize recomputes
+ * coefficients, Pade value and SE from them after every round.  A point finishes when its SE
+ * <= target_se or its trees reach max_trees; a request completes when all its points finish.
+ * Requests are admitted at tick boundaries while enough free slots (max_points, the memory bound)
+ * remain; at most queue_cap requests wait, beyond that submit returns BRT_E_BUSY.  A point's trees
+ * are addressed by (mc.seed, stream_id*1024 + point index, tree counter), so its results are
+ * bit-identical whether it is served alone or in a mix.
+ * ------------------------------------------------------------------------------------------------ */
+typedef struct brt_server brt_server;
+
+typedef struct brt_server_opts {
+  uint32_t struct_size;
+  uint32_t dim;                 /* problem family served: 1 or 2 */
+  uint32_t u0_kind;             /* BRT_U0_* of every request */
+  brt_mc mc;                    /* shared Monte Carlo parameters; mc.seed is the Philox key */
+  uint32_t max_points;          /* device slots: points resident at once (1..2^20) */
+  uint32_t round_trees;         /* trees per point per tick, a multiple of 8192 (<= 2^22) */
+  uint32_t max_trees;           /* per-point cap, a multiple of round_trees (<= 2^26) */
+  double target_se;             /* finish a point when its Pade SE <= target_se (0: always run to the cap) */
+  uint32_t queue_cap;           /* requests waiting for admission (>= 1) */
+  uint32_t max_active_requests; /* 0: no limit; 1: one request at a time (unbatched) */
+} brt_server_opts;
+
+typedef struct brt_request {
+  uint32_t struct_size;
+  uint32_t n;                   /* points, 1..min(1024, max_points) */
+  const brt_problem* problem;   /* host; copied */
+  const double* x;              /* host n*dim; copied */
+  const double* t;              /* host n; copied */
+  uint32_t stream_id;           /* < 2^22; the points' Philox ids are stream_id*1024 + i */
+} brt_request;
+
+typedef struct brt_result {     /* host buffers supplied by the caller, each nullable */
+  uint32_t struct_size;
+  double* u;                    /* n Pade values */
+  double* se;                   /* n standard errors */
+  double* coef;                 /* n*B coefficients (B = mc.max_order + 2) */
+  uint64_t* trees;              /* n trees used per point */
+  uint32_t* flags;              /* n BRT_FLAG_* */
+  double latency_s;             /* written: submit to completion */
+} brt_result;
+
+typedef struct brt_server_stats {
+  uint32_t struct_size;
+  uint64_t submitted, completed, rejected, ticks, trees, nodes;
+  double p50_latency_s, p99_latency_s, mean_latency_s;
+  double busy_s;                /* wall time spent in ticks */
+  double span_s;                /* first submit to last completion */
+  double trees_per_s;           /* trees / span_s */
+} brt_server_stats;
+
+/* Create a server on the context's device (allocates all device slots up front).  Errors:
+ * BRT_E_ARG, BRT_E_NOMEM, BRT_E_DEVICE. */
+int brt_server_create(brt_ctx* ctx, const brt_server_opts* opts, brt_server** out);
+/* Queue a request (copies it).  BRT_E_BUSY if the admission queue is full. */
+int brt_server_submit(brt_server* srv, const brt_request* req, uint64_t* ticket);
+/* *done = 1 when the request is complete; then the results are written to `out` (nullable) and the
+ * ticket is released.  BRT_E_STATE for an unknown ticket. */
+int brt_server_poll(brt_server* srv, uint64_t ticket, brt_result* out, int* done);
+/* Wait until every submitted request has completed (BRT_E_BUSY on timeout). */
+int brt_server_drain(brt_server* srv, double timeout_s);
+int brt_server_stats_get(brt_server* srv, brt_server_stats* out);
+/* Stop the engine (requests in flight are abandoned) and free everything. */
+void brt_server_destroy(brt_server* srv);
 
 #ifdef __cplusplus
 }

@@ -44,7 +44,7 @@ class MC(ctypes.Structure):
 class Points(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("n", ctypes.c_uint32), ("x", ctypes.c_void_p),
                 ("t", ctypes.c_void_p), ("n_trees", ctypes.c_void_p), ("problem_id", ctypes.c_void_p),
-                ("point_id", ctypes.c_void_p)]
+                ("point_id", ctypes.c_void_p), ("tree_first", ctypes.c_void_p)]
 
 
 class Out(ctypes.Structure):
@@ -57,6 +57,31 @@ class Launch(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("waves_per_block", ctypes.c_uint32),
                 ("blocks_per_cu", ctypes.c_uint32), ("chunk_trees", ctypes.c_uint32),
                 ("stack_depth", ctypes.c_uint32)]
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("dim", ctypes.c_uint32), ("u0_kind", ctypes.c_uint32),
+                ("mc", MC), ("max_points", ctypes.c_uint32), ("round_trees", ctypes.c_uint32),
+                ("max_trees", ctypes.c_uint32), ("target_se", ctypes.c_double), ("queue_cap", ctypes.c_uint32),
+                ("max_active_requests", ctypes.c_uint32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("n", ctypes.c_uint32), ("problem", ctypes.POINTER(Problem)),
+                ("x", ctypes.c_void_p), ("t", ctypes.c_void_p), ("stream_id", ctypes.c_uint32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("u", ctypes.c_void_p), ("se", ctypes.c_void_p),
+                ("coef", ctypes.c_void_p), ("trees", ctypes.c_void_p), ("flags", ctypes.c_void_p),
+                ("latency_s", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32)] + [
+        (n, ctypes.c_uint64) for n in ("submitted", "completed", "rejected", "ticks", "trees", "nodes")] + [
+        (n, ctypes.c_double) for n in ("p50_latency_s", "p99_latency_s", "mean_latency_s", "busy_s", "span_s",
+                                       "trees_per_s")]
 
 
 _lib = None
@@ -83,6 +108,13 @@ _SIGS = [
     ("brt_plan_destroy", None, [ctypes.c_void_p]),
     ("brt_solve", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.POINTER(Problem), ctypes.POINTER(MC),
                                  ctypes.POINTER(Points), ctypes.POINTER(Out), ctypes.c_void_p]),
+    ("brt_server_create", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ServerOpts), ctypes.POINTER(ctypes.c_void_p)]),
+    ("brt_server_submit", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
+    ("brt_server_poll", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(Result),
+                                       ctypes.POINTER(ctypes.c_int)]),
+    ("brt_server_drain", ctypes.c_int, [ctypes.c_void_p, ctypes.c_double]),
+    ("brt_server_stats_get", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ServerStats)]),
+    ("brt_server_destroy", None, [ctypes.c_void_p]),
 ]
 
 
@@ -167,7 +199,7 @@ class Context:
             pass
 
 
-def _points(x, t, n_trees, problem_id, point_id, dim, keep):
+def _points(x, t, n_trees, problem_id, point_id, dim, keep, tree_first=None):
     x = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(-1, dim))
     n = x.shape[0]
     t = np.ascontiguousarray(np.broadcast_to(np.asarray(t, dtype=np.float64), (n,)))
@@ -185,6 +217,10 @@ def _points(x, t, n_trees, problem_id, point_id, dim, keep):
         qid = np.ascontiguousarray(np.asarray(point_id, dtype=np.uint32).reshape(n))
         pts.point_id = qid.ctypes.data
         keep.append(qid)
+    if tree_first is not None:
+        tf = np.ascontiguousarray(np.broadcast_to(np.asarray(tree_first, dtype=np.uint32), (n,)))
+        pts.tree_first = tf.ctypes.data
+        keep.append(tf)
     return pts, n, int(nt.sum())
 
 
@@ -230,7 +266,8 @@ def _stream_handle(stream):
 class Plan:
     """brt_plan: normalised problems, uploaded points and work chunks, replayable on a stream."""
 
-    def __init__(self, ctx: Context, problems, mc: dict, x, t, n_trees, problem_id=None, point_id=None):
+    def __init__(self, ctx: Context, problems, mc: dict, x, t, n_trees, problem_id=None, point_id=None,
+                 tree_first=None):
         if isinstance(problems, dict):
             problems = [problems]
         self.ctx = ctx
@@ -239,7 +276,8 @@ class Plan:
         arr = (Problem * len(problems))(*[make_problem(p) for p in problems])
         m = make_mc(mc)
         keep = []
-        pts, self.n_points, self.total_trees = _points(x, t, n_trees, problem_id, point_id, self.dim, keep)
+        pts, self.n_points, self.total_trees = _points(x, t, n_trees, problem_id, point_id, self.dim, keep,
+                                                       tree_first)
         self._h = ctypes.c_void_p()
         _check(lib().brt_plan_create(ctx._h, len(problems), arr, ctypes.byref(m), ctypes.byref(pts),
                                      ctypes.byref(self._h)))
@@ -299,3 +337,66 @@ def solve(ctx: Context, problems, mc: dict, x, t, n_trees, problem_id=None, poin
     _check(lib().brt_solve(ctx._h, len(problems), arr, ctypes.byref(m), ctypes.byref(pts), ctypes.byref(o),
                            _stream_handle(stream)))
     return tensors
+
+
+class Server:
+    """brt_server: continuous batching of point-query requests (see include/brt.h)."""
+
+    def __init__(self, ctx: Context, dim: int, u0_kind, mc: dict, max_points=4096, round_trees=16384,
+                 max_trees=1 << 20, target_se=1e-3, queue_cap=100_000, max_active_requests=0):
+        o = ServerOpts()
+        o.struct_size = ctypes.sizeof(ServerOpts)
+        o.dim = int(dim)
+        o.u0_kind = U0_KINDS[u0_kind] if isinstance(u0_kind, str) else int(u0_kind)
+        o.mc = make_mc(mc)
+        o.max_points, o.round_trees, o.max_trees = int(max_points), int(round_trees), int(max_trees)
+        o.target_se, o.queue_cap, o.max_active_requests = float(target_se), int(queue_cap), int(max_active_requests)
+        self.B = int(mc.get("max_order", 12)) + 2
+        self.dim = int(dim)
+        self._h = ctypes.c_void_p()
+        _check(lib().brt_server_create(ctx._h, ctypes.byref(o), ctypes.byref(self._h)))
+
+    def submit(self, problem: dict, x, t, stream_id: int) -> int:
+        """Queue one request; returns its ticket (raises BrtError with code -4 when the queue is full)."""
+        x = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(-1, self.dim))
+        t = np.ascontiguousarray(np.broadcast_to(np.asarray(t, dtype=np.float64), (x.shape[0],)))
+        p = make_problem(problem)
+        q = Request(ctypes.sizeof(Request), x.shape[0], ctypes.pointer(p), x.ctypes.data, t.ctypes.data,
+                    int(stream_id))
+        ticket = ctypes.c_uint64()
+        _check(lib().brt_server_submit(self._h, ctypes.byref(q), ctypes.byref(ticket)))
+        return ticket.value
+
+    def poll(self, ticket: int, n: int):
+        """None while running; when complete, a dict of host arrays (and the ticket is released)."""
+        u, se = np.zeros(n), np.zeros(n)
+        coef = np.zeros((n, self.B))
+        trees = np.zeros(n, np.uint64)
+        flags = np.zeros(n, np.uint32)
+        r = Result(ctypes.sizeof(Result), u.ctypes.data, se.ctypes.data, coef.ctypes.data, trees.ctypes.data,
+                   flags.ctypes.data, 0.0)
+        done = ctypes.c_int()
+        _check(lib().brt_server_poll(self._h, int(ticket), ctypes.byref(r), ctypes.byref(done)))
+        if not done.value:
+            return None
+        return {"u": u, "se": se, "coef": coef, "trees": trees, "flags": flags, "latency_s": r.latency_s}
+
+    def drain(self, timeout_s=600.0):
+        _check(lib().brt_server_drain(self._h, float(timeout_s)))
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        s.struct_size = ctypes.sizeof(ServerStats)
+        _check(lib().brt_server_stats_get(self._h, ctypes.byref(s)))
+        return {name: getattr(s, name) for name, _ in ServerStats._fields_[1:]}
+
+    def close(self):
+        if self._h:
+            lib().brt_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -9,7 +9,7 @@
 namespace brt {
 
 constexpr int kWave = 64;
-constexpr int kMaxProblems = 16;
+constexpr int kMaxProblems = 64;
 constexpr int kMaxU0Params = 32;
 constexpr int kMaxWalkThreads = 256;  // walker block size limit (4 waves): lets FP64 walkers keep state in VGPRs
 
@@ -45,8 +45,11 @@ struct PointRec {
   uint32_t n_trees;
   uint32_t point_id; // Philox counter word 2
   uint32_t pde;
-  uint32_t seg_begin;  // first reduction segment of this point
-  uint32_t seg_count;
+  uint32_t seg_begin;  // first reduction partial of this point (finalize)
+  uint32_t seg_count;  // number of partials of this point (finalize)
+  uint32_t tree_first; // Philox tree counter of the point's first tree in this launch
+  uint64_t n_total;    // trees behind the point's partials (the N of the sample mean)
+  uint32_t out_row;    // row of the per-point outputs written by the finalize
   uint32_t pad;
 };
 
@@ -63,7 +66,7 @@ struct Segment {
   uint32_t point;
   uint32_t begin;
   uint32_t end;
-  uint32_t pad;
+  uint32_t out;  // index of the partial this segment writes
 };
 
 // Per (segment, bin) partial moments.
@@ -123,14 +126,30 @@ struct FinalizeArgs {
   uint32_t* flags;
 };
 
+// Strategy A normalisation of one problem (brt_runtime.hip).
+struct Norm {
+  double sigma = 0, lambda = 0, inv_lambda = 0, mu = 0;
+  uint32_t K = 0;
+  uint32_t J[8] = {0};
+  double omega[8] = {0};
+};
+Norm normalize(const brt_problem& p, const brt_mc& mc);
+size_t pde_bytes(int precision);
+void pde_to_device(const brt_problem& p, const Norm& n, int precision, void* dst);
+double est_nodes(const Norm& n, const brt_mc& mc, double t);
+int set_error(int code, const char* fmt, ...);  // records the thread's error message, returns code
+constexpr uint32_t kSegTrees = 1u << 13;          // trees per reduction segment
+constexpr uint32_t kMaxDepthUnpruned = 64;        // stack levels per lane when trees are not pruned
+constexpr uint32_t kDefaultLdsLevels = 8;         // stack levels per lane kept in LDS by default
+
 // Launchers (brt_kernels.hip).
 hipError_t launch_reset(uint32_t* chunk_counter, unsigned long long* depth_counter, hipStream_t s);
 hipError_t launch_walk(int precision, int dim, int u0_kind, const WalkArgs& a, int grid, int waves_per_block,
                        hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s);
-size_t walk_lds_bytes(int precision, int dim, int stack_depth, int waves_per_block);
+size_t walk_lds_bytes(int precision, int dim, int stack_depth, int waves_per_block, int n_problems);
 size_t stack_entry_size(int precision, int dim);
-int walk_max_blocks_per_cu(int precision, int dim, int u0_kind, bool multi, int stack_depth, int waves_per_block);
+int walk_max_blocks_per_cu(int precision, int dim, int u0_kind, int n_problems, int stack_depth, int waves_per_block);
 
 }  // namespace brt

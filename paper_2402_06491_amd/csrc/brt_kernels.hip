@@ -271,7 +271,7 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
   // the current one is requested as soon as the current one starts.
   uint32_t c_next = 0, c_end = 0;
   bool more = true;
-  uint32_t c_pid = 0, c_pde = 0;
+  uint32_t c_pid = 0, c_pde = 0, c_tfirst = 0;
   uint64_t c_base = 0;
   double c_theta = 1.0;
   Real c_t = 0, c_x0 = 0, c_x1 = 0;
@@ -305,6 +305,7 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
           const PointRec& pr = a.points[point];
           c_pid = pr.point_id;
           c_pde = pr.pde;
+          c_tfirst = pr.tree_first;
           c_base = pr.tree_base;
           c_theta = pr.theta;
           c_t = (Real)pr.t;
@@ -318,10 +319,10 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
         const uint32_t take = cnt < avail ? cnt : avail;
         const uint32_t rank = (uint32_t)__popcll(need & lt);
         if (!active && rank < take) {
-          tree = c_next + rank;
+          tree = c_tfirst + c_next + rank;
           pid = c_pid;
           pde_lane = c_pde;
-          rec = c_base + tree;
+          rec = c_base + c_next + rank;
           theta = c_theta;
           tau = c_t;
           x[0] = c_x0;
@@ -438,10 +439,10 @@ size_t stack_entry_size(int precision, int dim) {
   return dim == 1 ? stack_entry_bytes<double, 1>() : stack_entry_bytes<double, 2>();
 }
 
-size_t walk_lds_bytes(int precision, int dim, int stack_depth, int waves_per_block) {
+size_t walk_lds_bytes(int precision, int dim, int stack_depth, int waves_per_block, int n_problems) {
   const size_t sd = (size_t)stack_depth * kWave * waves_per_block;
-  if (precision == 32) return pde_table_bytes<float>(kMaxProblems) + sd * stack_entry_size(32, dim);
-  return pde_table_bytes<double>(kMaxProblems) + sd * stack_entry_size(64, dim);
+  if (precision == 32) return pde_table_bytes<float>(n_problems) + sd * stack_entry_size(32, dim);
+  return pde_table_bytes<double>(n_problems) + sd * stack_entry_size(64, dim);
 }
 
 template <typename Real, int DIM, int U0, bool MULTI>
@@ -469,10 +470,10 @@ static const void* walk_fn(int precision, int dim, int u0, bool multi) {
   return dim == 1 ? walk_ptr_m<double, 1>(u0, multi) : walk_ptr_m<double, 2>(u0, multi);
 }
 
-int walk_max_blocks_per_cu(int precision, int dim, int u0_kind, bool multi, int stack_depth, int waves_per_block) {
+int walk_max_blocks_per_cu(int precision, int dim, int u0_kind, int n_problems, int stack_depth, int waves_per_block) {
   int nb = 0;
-  const size_t lds = walk_lds_bytes(precision, dim, stack_depth, waves_per_block);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_fn(precision, dim, u0_kind, multi),
+  const size_t lds = walk_lds_bytes(precision, dim, stack_depth, waves_per_block, n_problems);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_fn(precision, dim, u0_kind, n_problems > 1),
                                                    waves_per_block * kWave, lds) != hipSuccess)
     return 0;
   return nb;
@@ -485,7 +486,7 @@ hipError_t launch_reset(uint32_t* chunk_counter, unsigned long long* depth_count
 
 hipError_t launch_walk(int precision, int dim, int u0_kind, const WalkArgs& a, int grid, int waves_per_block,
                        hipStream_t s) {
-  const size_t lds = walk_lds_bytes(precision, dim, (int)a.stack_depth, waves_per_block);
+  const size_t lds = walk_lds_bytes(precision, dim, (int)a.stack_depth, waves_per_block, (int)a.n_problems);
   const void* fn = walk_fn(precision, dim, u0_kind, a.n_problems > 1);
   void* args[] = {const_cast<WalkArgs*>(&a)};
   return hipLaunchKernel(fn, dim3(grid), dim3(waves_per_block * kWave), args, lds, s);

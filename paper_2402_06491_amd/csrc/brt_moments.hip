@@ -46,7 +46,7 @@ __global__ __launch_bounds__(64) void reduce_kernel(ReduceArgs a) {
   const double* F = a.tree_f + pr.tree_base;
   const uint32_t* M = a.tree_meta + pr.tree_base;
   const uint32_t B = a.n_bins;
-  Partial* out = a.partials + (size_t)seg * (B + 3);
+  Partial* out = a.partials + (size_t)sg.out * (B + 3);
 
   unsigned long long nodes = 0;
   uint32_t n_ovf = 0, n_cap = 0, n_dep = 0;
@@ -114,7 +114,7 @@ __global__ __launch_bounds__(64) void reduce_kernel(ReduceArgs a) {
   nodes = wave_sum_u64(nodes);
   const unsigned long long o = wave_sum_u64(n_ovf), c = wave_sum_u64(n_cap), d = wave_sum_u64(n_dep);
   if (lane == 0) {
-    a.seg_nodes[seg] = nodes;
+    a.seg_nodes[sg.out] = nodes;
     out[B] = Partial{o, 0.0, 0.0};
     out[B + 1] = Partial{c, 0.0, 0.0};
     out[B + 2] = Partial{d, 0.0, 0.0};
@@ -272,9 +272,10 @@ __global__ __launch_bounds__(64) void finalize_kernel(FinalizeArgs a) {
   const uint32_t p = blockIdx.x;
   const uint32_t lane = threadIdx.x;
   const PointRec& pr = a.points[p];
+  const uint32_t row = pr.out_row;  // output row of this point
   const uint32_t B = a.n_bins;
   const uint32_t NB = B + 3;
-  const double N = (double)pr.n_trees;
+  const double N = (double)pr.n_total;
   const double scale = exp(pr.mu * pr.t);
 
   for (uint32_t b = lane; b < NB; b += kWave) {
@@ -293,18 +294,18 @@ __global__ __launch_bounds__(64) void finalize_kernel(FinalizeArgs a) {
     }
     s1 += c1;
     s2 += c2;
-    if (a.hist) a.hist[(size_t)p * NB + b] = cnt;
+    if (a.hist) a.hist[(size_t)row * NB + b] = cnt;
     if (b < B) {
-      if (a.s1) a.s1[(size_t)p * B + b] = s1;
-      if (a.s2) a.s2[(size_t)p * B + b] = s2;
+      if (a.s1) a.s1[(size_t)row * B + b] = s1;
+      if (a.s2) a.s2[(size_t)row * B + b] = s2;
       const double mm1 = N > 0 ? s1 / N : 0.0;
       const double mm2 = N > 0 ? s2 / N : 0.0;
       m1[b] = mm1;
       m2[b] = mm2;
       coef[b] = scale * mm1;
       const double var = N > 1 ? scale * scale * (mm2 - mm1 * mm1) / (N - 1.0) : 0.0;
-      if (a.coef) a.coef[(size_t)p * B + b] = scale * mm1;
-      if (a.coef_var) a.coef_var[(size_t)p * B + b] = var;
+      if (a.coef) a.coef[(size_t)row * B + b] = scale * mm1;
+      if (a.coef_var) a.coef_var[(size_t)row * B + b] = var;
     } else {
       extra[b - B] = cnt;
     }
@@ -345,11 +346,11 @@ __global__ __launch_bounds__(64) void finalize_kernel(FinalizeArgs a) {
       gm += grad[k] * m1[k];
     }
     const double var = N > 1 ? scale * scale * (gg - gm * gm) / (N - 1.0) : 0.0;
-    if (a.u) a.u[p] = r.value;
-    if (a.se) a.se[p] = sqrt(var > 0.0 ? var : 0.0);
-    if (a.psum) a.psum[p] = psum;
-    if (a.flags) a.flags[p] = fl;
-    if (a.nodes) a.nodes[p] = nodes;
+    if (a.u) a.u[row] = r.value;
+    if (a.se) a.se[row] = sqrt(var > 0.0 ? var : 0.0);
+    if (a.psum) a.psum[row] = psum;
+    if (a.flags) a.flags[row] = fl;
+    if (a.nodes) a.nodes[row] = nodes;
   }
 }
 

@@ -22,13 +22,18 @@ namespace {
 
 thread_local std::string g_err;
 
-int fail(int code, const char* fmt, ...) {
+int vfail(int code, const char* fmt, va_list ap) {
   char buf[512];
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  g_err = buf;
+  return code;
+}
+
+int fail(int code, const char* fmt, ...) {
   va_list ap;
   va_start(ap, fmt);
-  vsnprintf(buf, sizeof(buf), fmt, ap);
+  vfail(code, fmt, ap);
   va_end(ap);
-  g_err = buf;
   return code;
 }
 
@@ -38,36 +43,7 @@ int fail(int code, const char* fmt, ...) {
     if (e_ != hipSuccess) return fail(BRT_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
-constexpr uint32_t kSegTrees = 1u << 13;  // trees per reduction segment
-constexpr uint32_t kMaxDepthUnpruned = 64; // stack levels per lane when trees are not pruned
-constexpr uint32_t kDefaultLdsLevels = 8;  // stack levels per lane kept in LDS by default
-
-// Strategy A normalisation of one problem (Sec. 2.1): u = v e^{mu t}, mu = c_1 + lambda, clock Exp(lambda),
-// arity uniform over the K non-zero non-linear terms, vertex weight K c_j / lambda e^{(j-1) mu tau}.
-struct Norm {
-  double sigma = 0, lambda = 0, inv_lambda = 0, mu = 0;
-  uint32_t K = 0;
-  uint32_t J[8] = {0};
-  double omega[8] = {0};
-};
-
-Norm normalize(const brt_problem& p, const brt_mc& mc) {
-  Norm n;
-  n.sigma = std::sqrt(2.0 * p.diffusion);
-  for (uint32_t j = 0; j < 8; ++j)
-    if (j != 1 && p.coef[j] != 0.0) n.J[n.K++] = j;
-  if (n.K == 0) {
-    n.lambda = 0.0;
-    n.inv_lambda = 0.0;
-    n.mu = p.coef[1];
-  } else {
-    n.lambda = mc.lambda;
-    n.inv_lambda = 1.0 / mc.lambda;
-    n.mu = p.coef[1] + mc.lambda;
-    for (uint32_t i = 0; i < n.K; ++i) n.omega[i] = (double)n.K * p.coef[n.J[i]] / mc.lambda;
-  }
-  return n;
-}
+bool is_fin(double v) { return std::isfinite(v); }
 
 template <typename Real>
 PdeT<Real> to_device(const brt_problem& p, const Norm& n) {
@@ -92,6 +68,50 @@ PdeT<Real> to_device(const brt_problem& p, const Norm& n) {
   return d;
 }
 
+}  // namespace
+
+namespace brt {
+
+int set_error(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vfail(code, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+// Strategy A normalisation of one problem (Sec. 2.1): u = v e^{mu t}, mu = c_1 + lambda, clock Exp(lambda),
+// arity uniform over the K non-zero non-linear terms, vertex weight K c_j / lambda e^{(j-1) mu tau}.
+Norm normalize(const brt_problem& p, const brt_mc& mc) {
+  Norm n;
+  n.sigma = std::sqrt(2.0 * p.diffusion);
+  for (uint32_t j = 0; j < 8; ++j)
+    if (j != 1 && p.coef[j] != 0.0) n.J[n.K++] = j;
+  if (n.K == 0) {
+    n.lambda = 0.0;
+    n.inv_lambda = 0.0;
+    n.mu = p.coef[1];
+  } else {
+    n.lambda = mc.lambda;
+    n.inv_lambda = 1.0 / mc.lambda;
+    n.mu = p.coef[1] + mc.lambda;
+    for (uint32_t i = 0; i < n.K; ++i) n.omega[i] = (double)n.K * p.coef[n.J[i]] / mc.lambda;
+  }
+  return n;
+}
+
+size_t pde_bytes(int precision) { return precision == 32 ? sizeof(PdeT<float>) : sizeof(PdeT<double>); }
+
+void pde_to_device(const brt_problem& p, const Norm& n, int precision, void* dst) {
+  if (precision == 32) {
+    const PdeT<float> d = to_device<float>(p, n);
+    std::memcpy(dst, &d, sizeof(d));
+  } else {
+    const PdeT<double> d = to_device<double>(p, n);
+    std::memcpy(dst, &d, sizeof(d));
+  }
+}
+
 // Expected nodes per tree (cost model for ordering work): with arities uniform over J the number of
 // lineages grows like e^{lambda (abar - 1) t}.
 double est_nodes(const Norm& n, const brt_mc& mc, double t) {
@@ -108,9 +128,7 @@ double est_nodes(const Norm& n, const brt_mc& mc, double t) {
   return std::max(1.0, std::min(v, (double)mc.node_cap));
 }
 
-bool is_fin(double v) { return std::isfinite(v); }
-
-}  // namespace
+}  // namespace brt
 
 struct brt_ctx {
   int device = 0;
@@ -333,6 +351,13 @@ extern "C" int brt_plan_create(brt_ctx* ctx, uint32_t n_problems, const brt_prob
     r.tree_base = base;
     r.n_trees = (uint32_t)pts->n_trees[i];
     r.point_id = pts->point_id ? pts->point_id[i] : i;
+    r.tree_first = pts->tree_first ? pts->tree_first[i] : 0u;
+    r.n_total = r.n_trees;
+    r.out_row = i;
+    if ((uint64_t)r.tree_first + r.n_trees > 0xffffffffull) {
+      plan_free(p);
+      return fail(BRT_E_ARG, "point %u: tree_first + n_trees exceeds 2^32-1", i);
+    }
     r.pde = pid;
     base += r.n_trees;
     cost[i] = est_nodes(nz, *mc, t);
@@ -353,7 +378,7 @@ extern "C" int brt_plan_create(brt_ctx* ctx, uint32_t n_problems, const brt_prob
     PointRec& r = p->points[i];
     r.seg_begin = (uint32_t)p->segs.size();
     for (uint32_t b0 = 0; b0 < r.n_trees; b0 += kSegTrees)
-      p->segs.push_back(Segment{i, b0, std::min(r.n_trees, b0 + kSegTrees), 0u});
+      p->segs.push_back(Segment{i, b0, std::min(r.n_trees, b0 + kSegTrees), (uint32_t)p->segs.size()});
     r.seg_count = (uint32_t)p->segs.size() - r.seg_begin;
   }
 
@@ -397,10 +422,10 @@ extern "C" int brt_plan_create(brt_ctx* ctx, uint32_t n_problems, const brt_prob
 
   // persistent grid: as many blocks as are resident at once
   int bpc = (int)ctx->launch.blocks_per_cu;
-  int maxb = walk_max_blocks_per_cu(p->precision, p->dim, p->u0_kind, p->n_problems > 1, p->stack_depth, p->waves_per_block);
+  int maxb = walk_max_blocks_per_cu(p->precision, p->dim, p->u0_kind, (int)p->n_problems, p->stack_depth, p->waves_per_block);
   while (maxb <= 0 && p->waves_per_block > 1) {  // shrink the block until its LDS fits
     p->waves_per_block -= 1;
-    maxb = walk_max_blocks_per_cu(p->precision, p->dim, p->u0_kind, p->n_problems > 1, p->stack_depth, p->waves_per_block);
+    maxb = walk_max_blocks_per_cu(p->precision, p->dim, p->u0_kind, (int)p->n_problems, p->stack_depth, p->waves_per_block);
   }
   if (maxb <= 0) {
     plan_free(p);

@@ -1,0 +1,597 @@
+// Continuous-batching server for point queries (brt_server_* in include/brt.h).
+//
+// An engine thread runs ticks.  A tick gives every unfinished point of every admitted request one
+// more round of `round_trees` trees: the rounds of all requests are packed into as few launches as
+// the problem table allows (64 problems, i.e. requests, per launch), so requests of different sizes
+// and horizons share the GPU.  Each point owns a device slot holding the reduction partials of all
+// its rounds; the finalize recomputes the point's coefficients, Pade value and SE from the slot after
+// every round.  A point finishes when its SE reaches the target or its trees reach the cap; a request
+// completes when all its points have finished, and its slots are freed.  New requests are admitted
+// at tick boundaries while free slots remain (memory admission); the submission queue is bounded.
+//
+// A point's trees are addressed by (seed, point id, tree counter), its partials are combined in
+// round order, and the number of rounds depends only on its own SE: its results are bit-identical
+// whether it is served alone or among other requests.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "brt.h"
+#include "brt_internal.h"
+
+using namespace brt;
+using Clock = std::chrono::steady_clock;
+
+namespace {
+
+constexpr uint32_t kMaxRequestPoints = 1024;
+constexpr uint32_t kChunkTrees = 1024;
+
+struct Request {
+  uint64_t ticket = 0;
+  brt_problem prob{};
+  Norm norm;
+  uint32_t stream_id = 0;
+  uint32_t n = 0;
+  std::vector<double> x, t;
+  Clock::time_point arrival, finished_at;
+  std::vector<uint32_t> slot, rounds;
+  std::vector<uint8_t> done;
+  uint32_t n_done = 0;
+  bool complete = false;
+  std::vector<double> u, se, coef;
+  std::vector<uint32_t> flags;
+};
+
+}  // namespace
+
+struct brt_server {
+  int device = 0;
+  int n_cu = 0;
+  brt_server_opts opts{};
+  hipStream_t stream = nullptr;
+  uint32_t B = 0, NB = 0, segs_per_round = 0, max_segs = 0, chunks_per_round = 0;
+  int grid = 0, wpb = 4, lds_depth = 0, spill_depth = 0;
+  // device buffers
+  void* d_pdes = nullptr;
+  PointRec* d_points = nullptr;
+  Chunk* d_chunks = nullptr;
+  Segment* d_segs = nullptr;
+  uint32_t* d_counter = nullptr;
+  unsigned long long* d_depth = nullptr;
+  double* d_tree_f = nullptr;
+  uint32_t* d_tree_meta = nullptr;
+  void* d_spill = nullptr;
+  Partial* d_partials = nullptr;
+  unsigned long long* d_seg_nodes = nullptr;
+  double *d_u = nullptr, *d_se = nullptr, *d_coef = nullptr;
+  unsigned long long* d_nodes = nullptr;
+  uint32_t* d_flags = nullptr;
+  // pinned staging
+  PointRec* h_points = nullptr;
+  Chunk* h_chunks = nullptr;
+  Segment* h_segs = nullptr;
+  unsigned char* h_pdes = nullptr;
+  double *h_u = nullptr, *h_se = nullptr;
+  unsigned long long* h_nodes = nullptr;
+  uint32_t* h_flags = nullptr;
+  // state
+  std::mutex mu;
+  std::condition_variable cv, done_cv;
+  std::deque<Request*> queue;
+  std::vector<Request*> active;
+  std::unordered_map<uint64_t, Request*> requests;
+  std::vector<uint32_t> free_slots;
+  uint64_t next_ticket = 1;
+  bool stop = false;     // finish the admitted requests, then exit
+  bool abandon = false;  // exit at the next tick boundary
+  int engine_rc = BRT_OK;
+  std::string engine_msg;
+  std::thread engine;
+  // statistics
+  std::vector<double> latencies;
+  uint64_t submitted = 0, completed = 0, rejected = 0, ticks = 0, trees = 0, nodes = 0;
+  double busy_s = 0.0;
+  bool any_submit = false;
+  Clock::time_point first_submit, last_complete;
+};
+
+namespace {
+
+#define SRV_TRY(expr)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) return set_error(BRT_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+void server_free(brt_server* s) {
+  if (!s) return;
+  if (s->stream) (void)hipStreamDestroy(s->stream);
+  void* dev[] = {s->d_pdes, s->d_points, s->d_chunks, s->d_segs, s->d_counter, s->d_depth, s->d_tree_f,
+                 s->d_tree_meta, s->d_spill, s->d_partials, s->d_seg_nodes, s->d_u, s->d_se, s->d_coef,
+                 s->d_nodes, s->d_flags};
+  for (void* p : dev) (void)hipFree(p);
+  void* host[] = {s->h_points, s->h_chunks, s->h_segs, s->h_pdes, s->h_u, s->h_se, s->h_nodes, s->h_flags};
+  for (void* p : host) (void)hipHostFree(p);
+  for (auto& kv : s->requests) delete kv.second;
+  for (Request* r : s->queue)
+    if (!s->requests.count(r->ticket)) delete r;
+  delete s;
+}
+
+template <typename T>
+int dev_alloc(T** p, size_t n) {
+  if (hipMalloc(reinterpret_cast<void**>(p), std::max<size_t>(1, n) * sizeof(T)) != hipSuccess)
+    return set_error(BRT_E_NOMEM, "server: device allocation of %zu bytes failed", n * sizeof(T));
+  return BRT_OK;
+}
+
+template <typename T>
+int host_alloc(T** p, size_t n) {
+  if (hipHostMalloc(reinterpret_cast<void**>(p), std::max<size_t>(1, n) * sizeof(T)) != hipSuccess)
+    return set_error(BRT_E_NOMEM, "server: pinned allocation of %zu bytes failed", n * sizeof(T));
+  return BRT_OK;
+}
+
+// One launch group: up to kMaxProblems requests' unfinished points, one round each.
+int run_group(brt_server* s, const std::vector<Request*>& group) {
+  const brt_mc& mc = s->opts.mc;
+  const uint32_t R = s->opts.round_trees;
+  const size_t pb = pde_bytes((int)mc.precision);
+  // points, most expensive first (longest-processing-time order of the chunks)
+  struct Item {
+    Request* r;
+    uint32_t i, k;
+    double cost;
+  };
+  std::vector<Item> items;
+  for (uint32_t k = 0; k < group.size(); ++k) {
+    Request* r = group[k];
+    pde_to_device(r->prob, r->norm, (int)mc.precision, s->h_pdes + (size_t)k * pb);
+    for (uint32_t i = 0; i < r->n; ++i)
+      if (!r->done[i]) items.push_back(Item{r, i, k, est_nodes(r->norm, mc, r->t[i])});
+  }
+  std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.cost > b.cost; });
+  const uint32_t np = (uint32_t)items.size();
+  uint32_t nc = 0, ns = 0;
+  for (uint32_t p = 0; p < np; ++p) {
+    const Item& it = items[p];
+    Request* r = it.r;
+    const uint32_t slot = r->slot[it.i];
+    const uint32_t round = r->rounds[it.i];
+    PointRec& pr = s->h_points[p];
+    std::memset(&pr, 0, sizeof(pr));
+    pr.x[0] = r->x[(size_t)it.i * s->opts.dim];
+    pr.x[1] = s->opts.dim == 2 ? r->x[(size_t)it.i * 2 + 1] : 0.0;
+    pr.t = r->t[it.i];
+    pr.theta = r->norm.K > 0 ? std::exp(-r->norm.lambda * pr.t) : 1.0;
+    pr.mu = r->norm.mu;
+    pr.tree_base = (uint64_t)p * R;
+    pr.n_trees = R;
+    pr.point_id = r->stream_id * kMaxRequestPoints + it.i;
+    pr.pde = it.k;
+    pr.tree_first = round * R;
+    pr.n_total = (uint64_t)(round + 1) * R;
+    pr.seg_begin = slot * s->max_segs;
+    pr.seg_count = (round + 1) * s->segs_per_round;
+    pr.out_row = slot;
+    for (uint32_t c = 0; c < s->chunks_per_round; ++c)
+      s->h_chunks[nc++] = Chunk{p, c * kChunkTrees, (c + 1) * kChunkTrees, 0u};
+    for (uint32_t g = 0; g < s->segs_per_round; ++g)
+      s->h_segs[ns++] = Segment{p, g * kSegTrees, (g + 1) * kSegTrees, slot * s->max_segs + round * s->segs_per_round + g};
+  }
+  // chunks interleaved in cost order: all points' first chunks, then their second chunks, ...
+  std::vector<Chunk> order(nc);
+  for (uint32_t c = 0, o = 0; c < s->chunks_per_round; ++c)
+    for (uint32_t p = 0; p < np; ++p) order[o++] = s->h_chunks[(size_t)p * s->chunks_per_round + c];
+  std::memcpy(s->h_chunks, order.data(), nc * sizeof(Chunk));
+
+  SRV_TRY(hipMemcpyAsync(s->d_pdes, s->h_pdes, group.size() * pb, hipMemcpyHostToDevice, s->stream));
+  SRV_TRY(hipMemcpyAsync(s->d_points, s->h_points, np * sizeof(PointRec), hipMemcpyHostToDevice, s->stream));
+  SRV_TRY(hipMemcpyAsync(s->d_chunks, s->h_chunks, nc * sizeof(Chunk), hipMemcpyHostToDevice, s->stream));
+  SRV_TRY(hipMemcpyAsync(s->d_segs, s->h_segs, ns * sizeof(Segment), hipMemcpyHostToDevice, s->stream));
+  SRV_TRY(launch_reset(s->d_counter, s->d_depth, s->stream));
+  WalkArgs w{};
+  w.points = s->d_points;
+  w.chunks = s->d_chunks;
+  w.n_chunks = nc;
+  w.n_problems = (uint32_t)group.size();
+  w.pdes = s->d_pdes;
+  w.chunk_counter = s->d_counter;
+  w.depth_counter = s->d_depth;
+  w.tree_f = s->d_tree_f;
+  w.tree_meta = s->d_tree_meta;
+  w.spill = s->d_spill;
+  w.key0 = (uint32_t)(mc.seed & 0xffffffffull);
+  w.key1 = (uint32_t)(mc.seed >> 32);
+  w.max_order = mc.max_order;
+  w.prune = mc.prune;
+  w.node_cap = mc.node_cap;
+  w.stack_depth = (uint32_t)s->lds_depth;
+  w.spill_depth = (uint32_t)s->spill_depth;
+  w.n_threads = (uint32_t)(s->grid * s->wpb * kWave);
+  const int grid = std::max(1, std::min<int>(s->grid, (int)nc));
+  SRV_TRY(launch_walk((int)mc.precision, (int)s->opts.dim, (int)s->opts.u0_kind, w, grid, s->wpb, s->stream));
+  ReduceArgs ra{};
+  ra.points = s->d_points;
+  ra.segs = s->d_segs;
+  ra.n_segs = ns;
+  ra.tree_f = s->d_tree_f;
+  ra.tree_meta = s->d_tree_meta;
+  ra.partials = s->d_partials;
+  ra.seg_nodes = s->d_seg_nodes;
+  ra.n_bins = s->B;
+  SRV_TRY(launch_reduce(ra, s->stream));
+  FinalizeArgs f{};
+  f.points = s->d_points;
+  f.n_points = np;
+  f.partials = s->d_partials;
+  f.seg_nodes = s->d_seg_nodes;
+  f.n_bins = s->B;
+  f.pade_L = mc.pade_L;
+  f.pade_M = mc.pade_M;
+  f.u = s->d_u;
+  f.se = s->d_se;
+  f.coef = s->d_coef;
+  f.nodes = s->d_nodes;
+  f.flags = s->d_flags;
+  SRV_TRY(launch_finalize(f, s->stream));
+  // the staging buffers are reused by the next group: wait for this group's copies and kernels
+  SRV_TRY(hipStreamSynchronize(s->stream));
+  return BRT_OK;
+}
+
+int run_tick(brt_server* s, const std::vector<Request*>& act) {
+  const auto t0 = Clock::now();
+  std::vector<Request*> group;
+  for (Request* r : act) {
+    group.push_back(r);
+    if (group.size() == (size_t)kMaxProblems) {
+      int rc = run_group(s, group);
+      if (rc) return rc;
+      group.clear();
+    }
+  }
+  if (!group.empty()) {
+    int rc = run_group(s, group);
+    if (rc) return rc;
+  }
+  const uint32_t slots = s->opts.max_points;
+  SRV_TRY(hipMemcpyAsync(s->h_u, s->d_u, slots * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  SRV_TRY(hipMemcpyAsync(s->h_se, s->d_se, slots * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  SRV_TRY(hipMemcpyAsync(s->h_flags, s->d_flags, slots * sizeof(uint32_t), hipMemcpyDeviceToHost, s->stream));
+  SRV_TRY(hipMemcpyAsync(s->h_nodes, s->d_nodes, slots * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                         s->stream));
+  SRV_TRY(hipStreamSynchronize(s->stream));
+  s->busy_s += std::chrono::duration<double>(Clock::now() - t0).count();
+  s->ticks += 1;
+  return BRT_OK;
+}
+
+void engine_main(brt_server* s) {
+  if (hipSetDevice(s->device) != hipSuccess) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->engine_rc = BRT_E_DEVICE;
+    s->engine_msg = "server engine: hipSetDevice failed";
+    s->done_cv.notify_all();
+    return;
+  }
+  const uint32_t R = s->opts.round_trees;
+  while (true) {
+    std::vector<Request*> act;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      if (s->abandon) return;
+      // admission: by free slots (device memory) and the optional cap on requests in flight
+      while (!s->queue.empty()) {
+        Request* r = s->queue.front();
+        if (r->n > s->free_slots.size()) break;
+        if (s->opts.max_active_requests && s->active.size() >= s->opts.max_active_requests) break;
+        s->queue.pop_front();
+        for (uint32_t i = 0; i < r->n; ++i) {
+          r->slot[i] = s->free_slots.back();
+          s->free_slots.pop_back();
+        }
+        s->active.push_back(r);
+      }
+      if (s->active.empty()) {
+        if (s->stop) return;
+        s->cv.wait_for(lk, std::chrono::milliseconds(2));
+        continue;
+      }
+      act = s->active;
+    }
+    const int rc = run_tick(s, act);
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (rc) {
+      s->engine_rc = rc;
+      s->engine_msg = brt_last_error();
+      s->stop = true;
+      s->done_cv.notify_all();
+      return;
+    }
+    const auto now = Clock::now();
+    std::vector<Request*> still;
+    for (Request* r : act) {
+      for (uint32_t i = 0; i < r->n; ++i) {
+        if (r->done[i]) continue;
+        const uint32_t slot = r->slot[i];
+        r->rounds[i] += 1;
+        s->trees += R;
+        const uint64_t n_trees = (uint64_t)r->rounds[i] * R;
+        const double se = s->h_se[slot];
+        const bool reached = s->opts.target_se > 0.0 && se <= s->opts.target_se;
+        if (reached || n_trees >= s->opts.max_trees) {
+          r->done[i] = 1;
+          r->n_done += 1;
+          r->u[i] = s->h_u[slot];
+          r->se[i] = se;
+          r->flags[i] = s->h_flags[slot];
+          s->nodes += s->h_nodes[slot];
+          // coefficients of the finished point
+          (void)hipMemcpy(r->coef.data() + (size_t)i * s->B, s->d_coef + (size_t)slot * s->B, s->B * sizeof(double),
+                          hipMemcpyDeviceToHost);
+        }
+      }
+      if (r->n_done == r->n) {
+        r->complete = true;
+        r->finished_at = now;
+        for (uint32_t i = 0; i < r->n; ++i) s->free_slots.push_back(r->slot[i]);
+        s->latencies.push_back(std::chrono::duration<double>(now - r->arrival).count());
+        s->completed += 1;
+        s->last_complete = now;
+      } else {
+        still.push_back(r);
+      }
+    }
+    s->active.swap(still);
+    s->done_cv.notify_all();
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int brt_server_create(brt_ctx* ctx, const brt_server_opts* o, brt_server** out) {
+  if (!ctx || !o || !out) return set_error(BRT_E_ARG, "brt_server_create: NULL argument");
+  *out = nullptr;
+  if (o->struct_size != sizeof(brt_server_opts)) return set_error(BRT_E_ARG, "brt_server_opts.struct_size mismatch");
+  if (o->dim != 1 && o->dim != 2) return set_error(BRT_E_ARG, "server: dim must be 1 or 2");
+  if (o->u0_kind > BRT_U0_COS2_BUMP) return set_error(BRT_E_ARG, "server: unknown u0_kind");
+  const brt_mc& mc = o->mc;
+  if (mc.struct_size != sizeof(brt_mc) || (mc.precision != 32 && mc.precision != 64) || !(mc.lambda > 0.0) ||
+      mc.max_order > 126 || mc.node_cap < 1 || mc.node_cap > kMaxNodeCap || mc.pade_L + mc.pade_M > mc.max_order ||
+      mc.pade_M > 16)
+    return set_error(BRT_E_ARG, "server: invalid Monte Carlo parameters");
+  if (o->max_points < 1 || o->max_points > (1u << 20)) return set_error(BRT_E_ARG, "server: max_points must be 1..2^20");
+  if (o->round_trees < kSegTrees || o->round_trees % kSegTrees || o->round_trees > (1u << 22))
+    return set_error(BRT_E_ARG, "server: round_trees must be a multiple of %u, at most 2^22", kSegTrees);
+  if (o->max_trees < o->round_trees || o->max_trees % o->round_trees || o->max_trees > (1u << 26))
+    return set_error(BRT_E_ARG, "server: max_trees must be a multiple of round_trees, at most 2^26");
+  if (!(o->target_se >= 0.0)) return set_error(BRT_E_ARG, "server: target_se must be >= 0");
+  if (o->queue_cap < 1) return set_error(BRT_E_ARG, "server: queue_cap must be >= 1");
+
+  brt_server* s = new (std::nothrow) brt_server;
+  if (!s) return set_error(BRT_E_NOMEM, "server: host allocation");
+  s->opts = *o;
+  brt_launch lc{};
+  lc.struct_size = sizeof(lc);
+  brt_get_launch(ctx, &lc);
+  s->wpb = (int)lc.waves_per_block;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&s->device) != hipSuccess || hipGetDeviceProperties(&prop, s->device) != hipSuccess) {
+    server_free(s);
+    return set_error(BRT_E_DEVICE, "server: device query failed");
+  }
+  s->n_cu = prop.multiProcessorCount;
+  s->B = mc.max_order + 2;
+  s->NB = s->B + 3;
+  s->segs_per_round = o->round_trees / kSegTrees;
+  s->max_segs = o->max_trees / kSegTrees;
+  s->chunks_per_round = o->round_trees / kChunkTrees;
+  const uint32_t needed = mc.prune ? std::max(1u, mc.max_order) : kMaxDepthUnpruned;
+  s->lds_depth = (int)std::min(needed, lc.stack_depth ? lc.stack_depth : kDefaultLdsLevels);
+  s->spill_depth = (int)(needed - (uint32_t)s->lds_depth);
+  int maxb = walk_max_blocks_per_cu((int)mc.precision, (int)o->dim, (int)o->u0_kind, kMaxProblems, s->lds_depth, s->wpb);
+  while (maxb <= 0 && s->wpb > 1) {
+    s->wpb -= 1;
+    maxb = walk_max_blocks_per_cu((int)mc.precision, (int)o->dim, (int)o->u0_kind, kMaxProblems, s->lds_depth, s->wpb);
+  }
+  if (maxb <= 0) {
+    server_free(s);
+    return set_error(BRT_E_ARG, "server: walker launch does not fit the device");
+  }
+  s->grid = maxb * s->n_cu;
+  const size_t P = o->max_points;
+  const size_t R = o->round_trees;
+  int rc = BRT_OK;
+  rc = rc ? rc : (hipStreamCreate(&s->stream) == hipSuccess ? BRT_OK : set_error(BRT_E_DEVICE, "server: stream"));
+  rc = rc ? rc : dev_alloc(reinterpret_cast<unsigned char**>(&s->d_pdes), kMaxProblems * pde_bytes((int)mc.precision));
+  rc = rc ? rc : dev_alloc(&s->d_points, P);
+  rc = rc ? rc : dev_alloc(&s->d_chunks, P * s->chunks_per_round);
+  rc = rc ? rc : dev_alloc(&s->d_segs, P * s->segs_per_round);
+  rc = rc ? rc : dev_alloc(&s->d_counter, 16);
+  rc = rc ? rc : dev_alloc(&s->d_depth, 8);
+  rc = rc ? rc : dev_alloc(&s->d_tree_f, P * R);
+  rc = rc ? rc : dev_alloc(&s->d_tree_meta, P * R);
+  rc = rc ? rc : dev_alloc(&s->d_partials, P * s->max_segs * s->NB);
+  rc = rc ? rc : dev_alloc(&s->d_seg_nodes, P * s->max_segs);
+  rc = rc ? rc : dev_alloc(&s->d_u, P);
+  rc = rc ? rc : dev_alloc(&s->d_se, P);
+  rc = rc ? rc : dev_alloc(&s->d_coef, P * s->B);
+  rc = rc ? rc : dev_alloc(&s->d_nodes, P);
+  rc = rc ? rc : dev_alloc(&s->d_flags, P);
+  if (!rc && s->spill_depth > 0)
+    rc = dev_alloc(reinterpret_cast<unsigned char**>(&s->d_spill), (size_t)s->grid * s->wpb * kWave *
+                                                                       s->spill_depth * stack_entry_size((int)mc.precision, (int)o->dim));
+  rc = rc ? rc : host_alloc(&s->h_points, P);
+  rc = rc ? rc : host_alloc(&s->h_chunks, P * s->chunks_per_round);
+  rc = rc ? rc : host_alloc(&s->h_segs, P * s->segs_per_round);
+  rc = rc ? rc : host_alloc(&s->h_pdes, kMaxProblems * pde_bytes((int)mc.precision));
+  rc = rc ? rc : host_alloc(&s->h_u, P);
+  rc = rc ? rc : host_alloc(&s->h_se, P);
+  rc = rc ? rc : host_alloc(&s->h_nodes, P);
+  rc = rc ? rc : host_alloc(&s->h_flags, P);
+  if (rc) {
+    server_free(s);
+    return rc;
+  }
+  s->free_slots.resize(P);
+  for (size_t i = 0; i < P; ++i) s->free_slots[i] = (uint32_t)(P - 1 - i);
+  s->engine = std::thread(engine_main, s);
+  *out = s;
+  return BRT_OK;
+}
+
+int brt_server_submit(brt_server* s, const brt_request* q, uint64_t* ticket) {
+  if (!s || !q || !ticket) return set_error(BRT_E_ARG, "brt_server_submit: NULL argument");
+  if (q->struct_size != sizeof(brt_request)) return set_error(BRT_E_ARG, "brt_request.struct_size mismatch");
+  if (!q->problem || !q->x || !q->t) return set_error(BRT_E_ARG, "brt_server_submit: NULL array");
+  if (q->n < 1 || q->n > kMaxRequestPoints || q->n > s->opts.max_points)
+    return set_error(BRT_E_ARG, "brt_server_submit: 1..%u points per request", std::min(kMaxRequestPoints, s->opts.max_points));
+  if (q->stream_id >= (1u << 22)) return set_error(BRT_E_ARG, "brt_server_submit: stream_id must be < 2^22");
+  int rc = brt_problem_check(q->problem, &s->opts.mc);
+  if (rc) return rc;
+  if (q->problem->dim != s->opts.dim || q->problem->u0_kind != s->opts.u0_kind)
+    return set_error(BRT_E_ARG, "brt_server_submit: problem dim/u0_kind differ from the server's");
+  for (uint32_t i = 0; i < q->n; ++i)
+    if (!(q->t[i] >= 0.0) || !std::isfinite(q->t[i])) return set_error(BRT_E_ARG, "brt_server_submit: bad t");
+  Request* r = new (std::nothrow) Request;
+  if (!r) return set_error(BRT_E_NOMEM, "brt_server_submit: host allocation");
+  r->prob = *q->problem;
+  r->norm = normalize(r->prob, s->opts.mc);
+  r->stream_id = q->stream_id;
+  r->n = q->n;
+  r->x.assign(q->x, q->x + (size_t)q->n * s->opts.dim);
+  r->t.assign(q->t, q->t + q->n);
+  r->slot.assign(q->n, 0u);
+  r->rounds.assign(q->n, 0u);
+  r->done.assign(q->n, 0u);
+  r->u.assign(q->n, 0.0);
+  r->se.assign(q->n, 0.0);
+  r->flags.assign(q->n, 0u);
+  r->coef.assign((size_t)q->n * s->B, 0.0);
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->engine_rc) {
+    delete r;
+    return set_error(s->engine_rc, "server stopped: %s", s->engine_msg.c_str());
+  }
+  if (s->queue.size() >= s->opts.queue_cap) {
+    delete r;
+    s->rejected += 1;
+    return set_error(BRT_E_BUSY, "server: admission queue full (%u requests)", s->opts.queue_cap);
+  }
+  r->ticket = s->next_ticket++;
+  r->arrival = Clock::now();
+  if (!s->any_submit) {
+    s->any_submit = true;
+    s->first_submit = r->arrival;
+  }
+  s->submitted += 1;
+  s->queue.push_back(r);
+  s->requests[r->ticket] = r;
+  *ticket = r->ticket;
+  s->cv.notify_all();
+  return BRT_OK;
+}
+
+int brt_server_poll(brt_server* s, uint64_t ticket, brt_result* out, int* done) {
+  if (!s || !done) return set_error(BRT_E_ARG, "brt_server_poll: NULL argument");
+  if (out && out->struct_size != sizeof(brt_result)) return set_error(BRT_E_ARG, "brt_result.struct_size mismatch");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->requests.find(ticket);
+  if (it == s->requests.end()) return set_error(BRT_E_STATE, "brt_server_poll: unknown ticket %llu", (unsigned long long)ticket);
+  Request* r = it->second;
+  *done = r->complete ? 1 : 0;
+  if (!r->complete) {
+    if (s->engine_rc) return set_error(s->engine_rc, "server stopped: %s", s->engine_msg.c_str());
+    return BRT_OK;
+  }
+  if (out) {
+    const uint32_t R = s->opts.round_trees;
+    for (uint32_t i = 0; i < r->n; ++i) {
+      if (out->u) out->u[i] = r->u[i];
+      if (out->se) out->se[i] = r->se[i];
+      if (out->flags) out->flags[i] = r->flags[i];
+      if (out->trees) out->trees[i] = (uint64_t)r->rounds[i] * R;
+    }
+    if (out->coef) std::memcpy(out->coef, r->coef.data(), r->coef.size() * sizeof(double));
+    out->latency_s = std::chrono::duration<double>(r->finished_at - r->arrival).count();
+  }
+  s->requests.erase(it);
+  delete r;
+  return BRT_OK;
+}
+
+int brt_server_drain(brt_server* s, double timeout_s) {
+  if (!s) return set_error(BRT_E_ARG, "brt_server_drain: NULL server");
+  std::unique_lock<std::mutex> lk(s->mu);
+  const auto deadline = Clock::now() + std::chrono::duration<double>(timeout_s);
+  while (!s->queue.empty() || !s->active.empty()) {
+    if (s->engine_rc) return set_error(s->engine_rc, "server stopped: %s", s->engine_msg.c_str());
+    if (s->done_cv.wait_until(lk, deadline) == std::cv_status::timeout &&
+        (!s->queue.empty() || !s->active.empty()))
+      return set_error(BRT_E_BUSY, "brt_server_drain: timed out");
+  }
+  return s->engine_rc;
+}
+
+int brt_server_stats_get(brt_server* s, brt_server_stats* o) {
+  if (!s || !o || o->struct_size != sizeof(brt_server_stats)) return set_error(BRT_E_ARG, "brt_server_stats_get: bad arguments");
+  std::lock_guard<std::mutex> lk(s->mu);
+  std::vector<double> l = s->latencies;
+  std::sort(l.begin(), l.end());
+  auto pct = [&](double q) {
+    if (l.empty()) return 0.0;
+    const double pos = q * (double)(l.size() - 1);
+    const size_t i = (size_t)pos;
+    const double f = pos - (double)i;
+    return i + 1 < l.size() ? l[i] * (1 - f) + l[i + 1] * f : l[i];
+  };
+  o->submitted = s->submitted;
+  o->completed = s->completed;
+  o->rejected = s->rejected;
+  o->ticks = s->ticks;
+  o->trees = s->trees;
+  o->nodes = s->nodes;
+  o->p50_latency_s = pct(0.50);
+  o->p99_latency_s = pct(0.99);
+  o->mean_latency_s = l.empty() ? 0.0 : std::accumulate(l.begin(), l.end(), 0.0) / (double)l.size();
+  o->busy_s = s->busy_s;
+  o->span_s = (s->any_submit && s->completed) ? std::chrono::duration<double>(s->last_complete - s->first_submit).count() : 0.0;
+  o->trees_per_s = o->span_s > 0 ? (double)s->trees / o->span_s : 0.0;
+  return BRT_OK;
+}
+
+void brt_server_destroy(brt_server* s) {
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+    s->abandon = true;  // requests in flight are abandoned at the next tick boundary
+    // requests never admitted are dropped
+    for (Request* r : s->queue) {
+      s->requests.erase(r->ticket);
+      delete r;
+    }
+    s->queue.clear();
+    s->cv.notify_all();
+  }
+  if (s->engine.joinable()) s->engine.join();
+  s->queue.clear();
+  server_free(s);
+}
+
+}  // extern "C"
