@@ -145,6 +145,55 @@ def pmc_traffic(kernel_src_sha, launches_trees):
     return d.get("hbm_bytes_per_launch")
 
 
+def serve_stream(ctx, reqs, mc, max_active, opts):
+    """Replay a request stream in real time through a brt_server; returns its statistics."""
+    import paper_2402_06491_amd as brt
+
+    srv = brt.Server(ctx, 2, "gauss_sum", mc, max_active_requests=max_active, **opts)
+    pending, rejected = {}, 0
+    t0 = time.perf_counter()
+    for r in reqs:
+        while time.perf_counter() - t0 < r["arrival"]:
+            for tk in [tk for tk, n in pending.items() if srv.poll(tk, n) is not None]:
+                del pending[tk]
+            time.sleep(0.0005)
+        try:
+            pending[srv.submit(r["problem"], r["x"], r["t"], stream_id=r["id"])] = len(r["t"])
+        except brt.BrtError as e:
+            if e.code != -4:
+                raise
+            rejected += 1
+    srv.drain(timeout_s=900.0)
+    for tk, n in pending.items():
+        srv.poll(tk, n)
+    st = srv.stats()
+    srv.close()
+    st["rejected_at_submit"] = rejected
+    return st
+
+
+def serve_bench(ctx, duration, rate, opts):
+    """The served mixed-size query stream: continuous batching against one request at a time."""
+    from paper_2402_06491_amd import inputs
+
+    reqs = inputs.served_stream(rate=rate, duration=duration)
+    mc = inputs.mc_params(seed=0, max_order=12, prune=1, precision=32)
+    log(f"serving: {len(reqs)} requests over {duration} s ({sum(len(r['t']) for r in reqs)} points)")
+    out = {"requests": len(reqs), "arrival_rate_per_s": rate, "duration_s": duration,
+           "points": int(sum(len(r["t"]) for r in reqs)), **{k: v for k, v in opts.items()}}
+    for name, max_active in (("batched", 0), ("one_request_at_a_time", 1)):
+        st = serve_stream(ctx, reqs, mc, max_active, opts)
+        out[name] = {"trees_per_s": st["trees_per_s"], "p50_latency_s": st["p50_latency_s"],
+                     "p99_latency_s": st["p99_latency_s"], "mean_latency_s": st["mean_latency_s"],
+                     "completed": st["completed"], "trees": st["trees"], "ticks": st["ticks"],
+                     "span_s": st["span_s"], "busy_s": st["busy_s"]}
+        log(f"serving {name}: {st['trees_per_s']:.4g} trees/s, p50 {st['p50_latency_s']:.3f} s, "
+            f"p99 {st['p99_latency_s']:.3f} s, {st['completed']} completed in {st['span_s']:.2f} s")
+    b, o = out["batched"], out["one_request_at_a_time"]
+    out["speedup_trees_per_s"] = b["trees_per_s"] / o["trees_per_s"] if o["trees_per_s"] else None
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,6 +202,10 @@ def main():
     ap.add_argument("--workload", default="fisher")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=2.0,
+                    help="length of the served request stream replayed after the throughput steps (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-max-trees", type=int, default=1 << 18)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
@@ -235,6 +288,12 @@ def main():
         result["parity"] = parity
         log(f"cpu baseline {cb['value']:.4g} trees/s on {cb['cores']} threads; parity {parity}")
     plan.close()
+    del out
+    if args.serve_seconds > 0:
+        result["serving"] = serve_bench(ctx, args.serve_seconds, args.serve_rate,
+                                        {"max_points": 8192, "round_trees": 16384,
+                                         "max_trees": args.serve_max_trees, "target_se": 1e-3,
+                                         "queue_cap": 100_000})
     ctx.close()
     print(json.dumps(result), flush=True)
 
