@@ -220,6 +220,12 @@ def main():
     wl = workload(args.workload)
     log(f"workload {wl['name']}: {len(wl['t'])} points, {int(np.sum(wl['n_trees']))} trees")
     ctx = brt.Context(0)
+    import tempfile
+
+    t_tune = time.perf_counter()
+    tuned = ctx.autotune(wl["problems"], wl["mc"], wl["x"], wl["t"], wl["n_trees"], problem_id=wl.get("problem_id"),
+                         cache_path=os.path.join(tempfile.gettempdir(), "brt_autotune.jsonl"))
+    log(f"autotuned launch {tuned} in {time.perf_counter() - t_tune:.1f} s")
     plan = brt.Plan(ctx, wl["problems"], wl["mc"], wl["x"], wl["t"], wl["n_trees"],
                     problem_id=wl.get("problem_id"), point_id=wl.get("point_id"))
     out = plan.outputs(records=True)
@@ -274,7 +280,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32" if wl["mc"]["precision"] == 32 else "f64",
         "data": "synthetic",
         "config": {"workload": describe(wl), "points": len(wl["t"]), "total_trees": total_trees,
-                   "nodes_per_step": nodes, "parallelism": "single GPU, persistent work-stealing launch"},
+                   "nodes_per_step": nodes, "parallelism": "single GPU, persistent work-stealing launch",
+                   "launch": tuned},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "what": "one step = all point queries of the workload"},
         "roofline": roofline,

@@ -108,6 +108,8 @@ _SIGS = [
     ("brt_plan_destroy", None, [ctypes.c_void_p]),
     ("brt_solve", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.POINTER(Problem), ctypes.POINTER(MC),
                                  ctypes.POINTER(Points), ctypes.POINTER(Out), ctypes.c_void_p]),
+    ("brt_autotune", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.POINTER(Problem), ctypes.POINTER(MC),
+                                    ctypes.POINTER(Points), ctypes.c_char_p, ctypes.POINTER(Launch)]),
     ("brt_server_create", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ServerOpts), ctypes.POINTER(ctypes.c_void_p)]),
     ("brt_server_submit", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
     ("brt_server_poll", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(Result),
@@ -180,6 +182,22 @@ class Context:
     def set_launch(self, waves_per_block=4, blocks_per_cu=0, chunk_trees=1024, stack_depth=0):
         l = Launch(ctypes.sizeof(Launch), waves_per_block, blocks_per_cu, chunk_trees, stack_depth)
         _check(lib().brt_set_launch(self._h, ctypes.byref(l)))
+
+    def autotune(self, problems, mc: dict, x, t, n_trees, problem_id=None, cache_path=None) -> dict:
+        """brt_autotune on these points; returns the chosen launch settings (now set on the context)."""
+        if isinstance(problems, dict):
+            problems = [problems]
+        arr = (Problem * len(problems))(*[make_problem(p) for p in problems])
+        m = make_mc(mc)
+        keep = []
+        pts, _, _ = _points(x, t, n_trees, problem_id, None, int(problems[0]["dim"]), keep)
+        best = Launch()
+        best.struct_size = ctypes.sizeof(Launch)
+        path = cache_path.encode() if cache_path else None
+        _check(lib().brt_autotune(self._h, len(problems), arr, ctypes.byref(m), ctypes.byref(pts), path,
+                                  ctypes.byref(best)))
+        return {"waves_per_block": best.waves_per_block, "blocks_per_cu": best.blocks_per_cu,
+                "chunk_trees": best.chunk_trees, "stack_depth": best.stack_depth}
 
     def get_launch(self) -> dict:
         l = Launch()

@@ -206,6 +206,41 @@ def test_determinism_and_graph_replay(ctx):
             np.testing.assert_array_equal(r[k], results[0][k], err_msg=k)
 
 
+def test_launch_settings_do_not_change_results(ctx):
+    """Every tree is computed by one lane from its own counters and segments are fixed, so launch
+    settings (block size, LDS stack levels, chunk size) change nothing in the outputs."""
+    wl = inputs.fisher(n_trees=3000, n_x=8)
+    _announce("launch_settings", wl)
+    ref = None
+    for launch in ({"waves_per_block": 4, "chunk_trees": 1024, "stack_depth": 8},
+                   {"waves_per_block": 1, "chunk_trees": 256, "stack_depth": 2},
+                   {"waves_per_block": 2, "chunk_trees": 4096, "stack_depth": 12}):
+        res = P.gpu_run(ctx, wl, launch=launch)
+        res.pop("plan")
+        if ref is None:
+            ref = res
+        else:
+            for k in ref:
+                np.testing.assert_array_equal(res[k], ref[k], err_msg=f"{k} {launch}")
+    ctx.set_launch()
+
+
+def test_autotune_and_cache(ctx, tmp_path):
+    wl = inputs.fisher(n_trees=20000, n_x=16)
+    _announce("autotune", wl)
+    path = str(tmp_path / "tune.jsonl")
+    best = ctx.autotune(wl["problems"], wl["mc"], wl["x"], wl["t"], wl["n_trees"], cache_path=path)
+    assert best["waves_per_block"] in (1, 2, 4) and best["chunk_trees"] in (256, 1024, 4096)
+    assert ctx.get_launch()["stack_depth"] == best["stack_depth"]
+    lines = open(path).read().strip().split("\n")
+    assert len(lines) == 1 and '"key": "' in lines[0]
+    ctx.set_launch()
+    again = ctx.autotune(wl["problems"], wl["mc"], wl["x"], wl["t"], wl["n_trees"], cache_path=path)
+    assert again == best and len(open(path).read().strip().split("\n")) == 1
+    _full_parity(ctx, "after_autotune", inputs.fisher(n_trees=500, n_x=8))
+    ctx.set_launch()
+
+
 def test_alone_equals_in_batch(ctx):
     """A point's results alone equal its results inside a larger mixed batch (bit-identical)."""
     wl = inputs.poly_batch(n_points=256, n_min=64, n_max=3000, precision=32)
