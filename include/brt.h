@@ -33,7 +33,10 @@
  * U = (w0 + 0.5) 2^-32, word 1 the arity index floor(w1 K / 2^32), words 2-3
  * a Box-Muller pair u1 = (w2 + 0.5) 2^-32, u2 = w3 2^-32.  A node is a vertex
  * iff the FP64 product of U along its lineage (itself included) exceeds
- * theta = exp(-lambda t) computed on the host in FP64.
+ * theta = exp(-lambda t) computed on the host in FP64.  Strategy B (Sec. 2.2)
+ * uses word 0 as the coin instead: with Q = floor(q 2^32) the node is a leaf
+ * iff w0 < Q, and a vertex splits after the fraction S = (w0 - Q + 0.5) /
+ * (2^32 - Q) of its time left.
  */
 #ifndef BRT_H
 #define BRT_H
@@ -90,7 +93,15 @@ typedef struct brt_mc {
   uint32_t node_cap;     /* abandon a tree when it would visit node number node_cap (1..2^21-1) */
   uint32_t pade_L;       /* Pade [L/M], L + M <= max_order */
   uint32_t pade_M;
+  uint32_t strategy;     /* BRT_STRATEGY_A: exponential clock of rate lambda (Sec. 2.1);
+                            BRT_STRATEGY_B: coin with P(leaf) = q and split after a uniform fraction of
+                            the time left (Sec. 2.2) */
+  double q;              /* Strategy B: leaf probability, 0 < q <= 1; without pruning the trees must be
+                            subcritical, (1 - q) * mean arity < 1 */
 } brt_mc;
+
+#define BRT_STRATEGY_A 0u
+#define BRT_STRATEGY_B 1u
 
 /* Query points (host arrays, n entries each). */
 typedef struct brt_points {

@@ -70,7 +70,9 @@ class _Problem(ctypes.Structure):
         ("max_order", ctypes.c_int32),
         ("prune", ctypes.c_int32),
         ("node_cap", ctypes.c_uint32),
-        ("pad", ctypes.c_int32),
+        ("strategy", ctypes.c_int32),
+        ("Q", ctypes.c_uint64),
+        ("q", ctypes.c_double),
     ]
 
 
@@ -109,6 +111,8 @@ class Normalized:
     u0_kind: int
     u0_params: list
     u0_nterms: int
+    strategy: int = 0     # 0: Strategy A (Sec. 2.1), 1: Strategy B (Sec. 2.2)
+    q: float = 1.0        # Strategy B: probability that a node is a leaf
 
 
 def normalize(problem: dict, mc: dict) -> Normalized:
@@ -123,10 +127,18 @@ def normalize(problem: dict, mc: dict) -> Normalized:
     """
     coef = [float(c) for c in problem["coef"]] + [0.0] * (8 - len(problem["coef"]))
     lam = float(mc.get("lambda", 1.0))
+    strategy = strategy_of(mc)
     J = [j for j in range(8) if j != 1 and coef[j] != 0.0]
     K = len(J)
+    q = 1.0
     if K == 0:
         lam_eff, mu, omega = 0.0, coef[1], []
+    elif strategy == 1:
+        # Strategy B: u = v e^{c_1 t}; a vertex carries t K c_j / (1 - q) e^{(j-1) c_1 tau'}
+        q = float(mc.get("q", 0.5))
+        lam_eff = 0.0
+        mu = coef[1]
+        omega = [K * coef[j] / (1.0 - q) for j in J]
     else:
         lam_eff = lam
         mu = coef[1] + lam
@@ -139,7 +151,12 @@ def normalize(problem: dict, mc: dict) -> Normalized:
         raise ValueError("logistic u0 takes (A, s, x0, pow, n0, n1)")
     return Normalized(dim=int(problem["dim"]), sigma=math.sqrt(2.0 * float(problem["diffusion"])),
                       lam=lam_eff, mu=mu, J=J, omega=omega, u0_kind=kind,
-                      u0_params=params, u0_nterms=nterms)
+                      u0_params=params, u0_nterms=nterms, strategy=strategy, q=q)
+
+
+def strategy_of(mc: dict) -> int:
+    s = mc.get("strategy", 0)
+    return {"A": 0, "B": 1}[s] if isinstance(s, str) else int(s)
 
 
 def _make_struct(nz: Normalized, mc: dict) -> _Problem:
@@ -162,6 +179,9 @@ def _make_struct(nz: Normalized, mc: dict) -> _Problem:
     pb.max_order = int(mc.get("max_order", 12))
     pb.prune = int(mc.get("prune", 1))
     pb.node_cap = int(mc.get("node_cap", 1 << 16))
+    pb.strategy = nz.strategy
+    pb.q = nz.q
+    pb.Q = int(math.floor(nz.q * 4294967296.0))
     return pb
 
 

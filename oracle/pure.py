@@ -61,6 +61,8 @@ def walk_tree(nz, mc, x0, t, point_id, tree):
     number of children not yet started.  Every node multiplies its factor
     (vertex weight or g at the leaf) into a running product.
     """
+    if getattr(nz, "strategy", 0) == 1:
+        return _walk_tree_b(nz, mc, x0, t, point_id, tree)
     seed = int(mc.get("seed", 0))
     key = (seed & _MASK, (seed >> 32) & _MASK)
     K = len(nz.J)
@@ -114,3 +116,55 @@ def walk_tree(nz, mc, x0, t, point_id, tree):
             top[1] -= 1
             if top[1] == 0:
                 stack.pop()
+
+
+def _walk_tree_b(nz, mc, x0, t, point_id, tree):
+    """Strategy B (coin with P(leaf) = q, split after a uniform fraction of the time left), explicit stack."""
+    seed = int(mc.get("seed", 0))
+    key = (seed & _MASK, (seed >> 32) & _MASK)
+    K = len(nz.J)
+    Q = int(math.floor(nz.q * 2.0 ** 32))
+    cap = int(mc.get("node_cap", 1 << 16))
+    max_order = int(mc.get("max_order", 12))
+    prune = int(mc.get("prune", 1))
+    dim = nz.dim
+    state = (list(x0[:dim]), t)     # departure state of the next node: position, time left
+    stack = []
+    node = ne = 0
+    prod = 1.0
+    while True:
+        if node >= cap:
+            return 0.0, ne, node, 2
+        w = philox4x32_10((node, tree, point_id, 0), key)
+        node += 1
+        x, tau = state
+        u1 = (w[2] + 0.5) / 2.0 ** 32
+        u2 = w[3] / 2.0 ** 32
+        r = math.sqrt(-2.0 * math.log(u1))
+        z = (r * math.cos(2.0 * math.pi * u2), r * math.sin(2.0 * math.pi * u2))
+        if w[0] >= Q:
+            span = 2.0 ** 32 - Q
+            s = tau * ((w[0] - Q + 0.5) / span)
+            tau2 = tau * ((2 ** 32 - 1 - w[0] + 0.5) / span)  # tau (1 - V) without cancellation
+            xs = [x[d] + nz.sigma * math.sqrt(s) * z[d] for d in range(dim)]
+            ne += 1
+            if prune and ne > max_order:
+                return 0.0, ne, node, 1
+            idx = (w[1] * K) >> 32
+            alpha = nz.J[idx]
+            prod *= tau * nz.omega[idx] * math.exp((alpha - 1) * nz.mu * tau2)
+            if alpha > 0:
+                if alpha > 1:
+                    stack.append([(xs, tau2), alpha - 1])
+                state = (xs, tau2)
+                continue
+        else:
+            xl = [x[d] + nz.sigma * math.sqrt(tau) * z[d] for d in range(dim)]
+            prod *= _g(nz.u0_kind, nz.u0_params, nz.u0_nterms, dim, xl) / nz.q
+        if not stack:
+            return prod, ne, node, 0
+        top = stack[-1]
+        state = top[0]
+        top[1] -= 1
+        if top[1] == 0:
+            stack.pop()

@@ -73,7 +73,9 @@ typedef struct {
   int32_t max_order;
   int32_t prune;
   uint32_t node_cap;
-  int32_t pad;
+  int32_t strategy;   /* 0: Strategy A (exponential clock), 1: Strategy B (coin + uniform time) */
+  uint64_t Q;         /* Strategy B: a node is a leaf iff w0 < Q = floor(q 2^32) */
+  double q;           /* Strategy B: probability of a leaf */
 } or_problem;
 
 /* ---- Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) ------------------ */
@@ -197,6 +199,59 @@ static double or_visit(const or_problem* pb, or_tree* st, const double* x, doubl
   return or_g(pb, xl);
 }
 
+/* Strategy B (Sec. 2.2): the integral equation is sampled with a coin xi, P(leaf) = q.  A leaf
+ * evaluates g where its path ends, divided by q.  A vertex splits after the uniform fraction S of the
+ * time left tau (the path moves for tau S, its children have tau' = tau (1 - S) left) and carries
+ * tau * K c_alpha / (1 - q) * e^{(alpha-1) mu tau'} (eta(t) = t, c~ = c/(1-q), c' = (m-1)c~, with the
+ * linear coefficient absorbed as u = v e^{mu t}, mu = c_1).  Randomness: the coin is w0 < Q; for a
+ * vertex S = (w0 - Q + 1/2) / (2^32 - Q) (w0 is uniform on [Q, 2^32) given the coin); w1 picks the
+ * arity; w2, w3 the normals. */
+static double or_visit_b(const or_problem* pb, or_tree* st, const double* x, double tau) {
+  if (st->node >= pb->node_cap) {
+    st->flags |= OR_FLAG_CAPPED;
+    return 0.0;
+  }
+  uint32_t ctr[4] = {st->node, st->tree, st->pid, 0u};
+  uint32_t w[4];
+  or_philox4x32_10(ctr, pb->key, w);
+  st->node += 1;
+
+  const double two32 = 4294967296.0;
+  double u1 = ((double)w[2] + 0.5) / two32;
+  double u2 = (double)w[3] / two32;
+  double r = sqrt(-2.0 * log(u1));
+  double z[2] = {r * cos(2.0 * M_PI * u2), r * sin(2.0 * M_PI * u2)};
+
+  if ((uint64_t)w[0] >= pb->Q) {
+    /* vertex */
+    /* split after the fraction V = (w0 - Q + 1/2)/(2^32 - Q) of tau; the time left after it,
+       tau (1 - V), is formed from the complementary count 2^32 - w0 - 1/2 so that it carries no
+       cancellation when V is close to 1 (the vertex weight is proportional to it) */
+    const double span = two32 - (double)pb->Q;
+    double s = tau * (((double)((uint64_t)w[0] - pb->Q) + 0.5) / span);
+    double tau2 = tau * (((double)(0xFFFFFFFFu - w[0]) + 0.5) / span);
+    double xs[2];
+    for (int d = 0; d < pb->dim; d++) xs[d] = x[d] + pb->sigma * sqrt(s) * z[d];
+    st->ne += 1;
+    if (pb->prune && st->ne > (uint32_t)pb->max_order) {
+      st->flags |= OR_FLAG_OVERFLOW;
+      return 0.0;
+    }
+    uint32_t idx = (uint32_t)(((uint64_t)w[1] * (uint64_t)pb->K) >> 32);
+    int alpha = pb->J[idx];
+    double val = tau * pb->omega[idx] * exp((double)(alpha - 1) * pb->mu * tau2);
+    for (int c = 0; c < alpha; c++) {
+      double child = or_visit_b(pb, st, xs, tau2);
+      if (st->flags) return 0.0;
+      val *= child;
+    }
+    return val;
+  }
+  double xl[2];
+  for (int d = 0; d < pb->dim; d++) xl[d] = x[d] + pb->sigma * sqrt(tau) * z[d];
+  return or_g(pb, xl) / pb->q;
+}
+
 /*
  * Walk n independent trees.  Item i is tree tree_idx[i] of the point with
  * position x[i*dim..], time t[i] and id point_id[i].  Outputs per item: the
@@ -223,7 +278,7 @@ int or_walk(const or_problem* pb, int64_t n, const double* x, const double* t,
     /* K = 0 (no non-linear term): no clock, the root is always a leaf */
     st.theta = (pb->K > 0) ? exp(-pb->lambda * t[i]) : 1.0;
     double x0[2] = {x[i * pb->dim], pb->dim == 2 ? x[i * pb->dim + 1] : 0.0};
-    double v = or_visit(pb, &st, x0, 1.0, t[i]);
+    double v = pb->strategy == 1 ? or_visit_b(pb, &st, x0, t[i]) : or_visit(pb, &st, x0, 1.0, t[i]);
     F[i] = st.flags ? 0.0 : v;
     ne[i] = st.ne;
     nodes[i] = st.node;

@@ -38,7 +38,8 @@ class Problem(ctypes.Structure):
 class MC(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("precision", ctypes.c_uint32), ("seed", ctypes.c_uint64),
                 ("lambda_", ctypes.c_double), ("max_order", ctypes.c_uint32), ("prune", ctypes.c_uint32),
-                ("node_cap", ctypes.c_uint32), ("pade_L", ctypes.c_uint32), ("pade_M", ctypes.c_uint32)]
+                ("node_cap", ctypes.c_uint32), ("pade_L", ctypes.c_uint32), ("pade_M", ctypes.c_uint32),
+                ("strategy", ctypes.c_uint32), ("q", ctypes.c_double)]
 
 
 class Points(ctypes.Structure):
@@ -168,6 +169,9 @@ def make_mc(d: dict) -> MC:
     m.node_cap = int(d.get("node_cap", 1 << 16))
     m.pade_L = int(d.get("pade_L", 6))
     m.pade_M = int(d.get("pade_M", 6))
+    s = d.get("strategy", 0)
+    m.strategy = {"A": 0, "B": 1}[s] if isinstance(s, str) else int(s)
+    m.q = float(d.get("q", 0.5))
     return m
 
 

@@ -25,13 +25,16 @@ constexpr uint32_t kMaxNodeCap = (1u << 21) - 1;  // nodes field is 21 bits
 template <typename Real>
 struct PdeT {
   Real sigma;        // sqrt(2a)
-  Real inv_lambda;   // 1/lambda (unused when K == 0)
-  Real mu;           // c_1 + lambda
+  Real inv_lambda;   // Strategy A: 1/lambda (unused when K == 0)
+  Real mu;           // Strategy A: c_1 + lambda; Strategy B: c_1
+  Real inv_q;        // Strategy B: 1/q (leaf values are g/q)
+  Real s_scale;      // Strategy B: 1/(2^32 - Q), maps a vertex's w0 to its split fraction
   uint32_t K;        // number of non-linear terms
   uint32_t jpack;    // their powers, 4 bits each, ascending
   uint32_t u0_nterms;
-  uint32_t pad0, pad1;
-  Real omega[8];     // K c_j / lambda
+  uint32_t q_lo;     // Strategy B: Q - 1 with Q = floor(q 2^32); a node is a leaf iff w0 <= q_lo
+  uint32_t pad;
+  Real omega[8];     // Strategy A: K c_j / lambda; Strategy B: K c_j / (1 - q)
   Real u0[kMaxU0Params];
 };
 
@@ -91,6 +94,7 @@ struct WalkArgs {
   uint32_t max_order;
   uint32_t prune;
   uint32_t node_cap;
+  uint32_t strategy;         // 0: Strategy A, 1: Strategy B
   uint32_t stack_depth;      // LDS levels per lane
   uint32_t spill_depth;      // global levels per lane
   uint32_t n_threads;        // grid size in threads (spill stride)
@@ -129,6 +133,8 @@ struct FinalizeArgs {
 // Strategy A normalisation of one problem (brt_runtime.hip).
 struct Norm {
   double sigma = 0, lambda = 0, inv_lambda = 0, mu = 0;
+  double q = 1.0;       // Strategy B: probability of a leaf (1 when K == 0)
+  uint64_t Q = 0;       // Strategy B: floor(q 2^32)
   uint32_t K = 0;
   uint32_t J[8] = {0};
   double omega[8] = {0};

@@ -220,9 +220,10 @@ struct Stack {
 
 // ------------------------------------------------------------------------------------------------
 // The walker.  MULTI: the plan has several problems (per-lane problem index); otherwise the
-// problem constants are loop invariants.
+// problem constants are loop invariants.  STRAT: 0 = Strategy A (Sec. 2.1), 1 = Strategy B
+// (Sec. 2.2).
 // ------------------------------------------------------------------------------------------------
-template <typename Real, int DIM, int U0, bool MULTI>
+template <typename Real, int DIM, int U0, bool MULTI, int STRAT>
 __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
 
@@ -351,16 +352,33 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
     // push, the stack pop and the record write are divergent.
     const bool capped = node >= node_cap;
     const U4 w = philox4x32_10(node, tree, pid, 0u, a.key0, a.key1);
-    const double U = fma((double)w.a, 0x1p-32, 0x1p-33);  // (w0 + 1/2) 2^-32, exact
-    const double Pn = P * U;
-    const bool vertex = !capped && Pn > theta;
+    double Pn = P;
+    bool vertex;
+    Real S;     // time from the node's start to its split
+    Real tau2;  // time left after the split
+    if constexpr (STRAT == 0) {
+      // Strategy A: Exp(lambda) clock; vertex iff the lineage's product of uniforms exceeds theta
+      const double U = fma((double)w.a, 0x1p-32, 0x1p-33);  // (w0 + 1/2) 2^-32, exact
+      Pn = P * U;
+      vertex = !capped && Pn > theta;
+      S = -Math<Real>::ln((Real)U) * pd.inv_lambda;
+      tau2 = tau - S;
+      tau2 = tau2 < (Real)0 ? (Real)0 : tau2;
+    } else {
+      // Strategy B: coin w0 >= Q; the split comes after the fraction V = (w0 - Q + 1/2)/(2^32 - Q)
+      // of tau.  tau (1 - V) comes from the complementary count 2^32 - w0 - 1/2, free of the
+      // cancellation of tau - S near V = 1 (it multiplies the weights of the vertex's children).
+      vertex = !capped && w.a > pd.q_lo;
+      const Real ts = tau * pd.s_scale;
+      S = ((Real)(w.a - pd.q_lo - 1u) + (Real)0.5) * ts;
+      tau2 = ((Real)(~w.a) + (Real)0.5) * ts;
+    }
 
     const Real u1 = ((Real)w.c + (Real)0.5) * (Real)0x1p-32;
     const Real u2 = (Real)w.d * (Real)0x1p-32;
     const Real r = Math<Real>::sq((Real)-2 * Math<Real>::ln(u1));
     Real sn, cs;
     Math<Real>::sincos_rev(u2, &sn, &cs);
-    const Real S = -Math<Real>::ln((Real)U) * pd.inv_lambda;
     const Real sd = pd.sigma * Math<Real>::sq(vertex ? S : tau);
     Real xn[2];
     xn[0] = x[0] + sd * (r * cs);
@@ -368,21 +386,22 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
 
     // one exponential per node: the vertex weight e^{(alpha-1) mu tau'} or, for logistic initial
     // data, e^{s (n.x - x0)} at the leaf
-    Real tau2 = tau - S;
-    tau2 = tau2 < (Real)0 ? (Real)0 : tau2;
     const uint32_t idx = __umulhi(w.b, pd.K);
     const uint32_t alpha = (pd.jpack >> (4 * idx)) & 15u;
     Real earg = (Real)((int)alpha - 1) * pd.mu * tau2;
     if constexpr (U0 == 1) earg = vertex ? earg : logistic_arg<Real, DIM>(pd, xn);
     const Real E = Math<Real>::ex(earg);
+    // Strategy B's vertex weight carries the time left tau (eta(t) = t) and its leaves divide by q
+    const Real wscale = STRAT == 1 ? tau : (Real)1;
+    const Real lscale = STRAT == 1 ? pd.inv_q : (Real)1;
     Real factor;
     if constexpr (U0 == 1) {
-      factor = vertex ? pd.omega[idx] * E : logistic_finish<Real>(pd, E);
+      factor = vertex ? wscale * pd.omega[idx] * E : lscale * logistic_finish<Real>(pd, E);
     } else {
       if (vertex)
-        factor = pd.omega[idx] * E;
+        factor = wscale * pd.omega[idx] * E;
       else
-        factor = eval_g<Real, DIM, U0>(pd, xn);
+        factor = lscale * eval_g<Real, DIM, U0>(pd, xn);
     }
 
     ne += vertex ? 1u : 0u;
@@ -445,35 +464,38 @@ size_t walk_lds_bytes(int precision, int dim, int stack_depth, int waves_per_blo
   return pde_table_bytes<double>(n_problems) + sd * stack_entry_size(64, dim);
 }
 
-template <typename Real, int DIM, int U0, bool MULTI>
+template <typename Real, int DIM, int U0, bool MULTI, int STRAT>
 static const void* walk_ptr() {
-  return reinterpret_cast<const void*>(&walk_kernel<Real, DIM, U0, MULTI>);
+  return reinterpret_cast<const void*>(&walk_kernel<Real, DIM, U0, MULTI, STRAT>);
 }
 
-template <typename Real, int DIM, bool MULTI>
+template <typename Real, int DIM, bool MULTI, int STRAT>
 static const void* walk_ptr_u0(int u0) {
   switch (u0) {
-    case 0: return walk_ptr<Real, DIM, 0, MULTI>();
-    case 1: return walk_ptr<Real, DIM, 1, MULTI>();
-    case 2: return walk_ptr<Real, DIM, 2, MULTI>();
-    default: return walk_ptr<Real, DIM, 3, MULTI>();
+    case 0: return walk_ptr<Real, DIM, 0, MULTI, STRAT>();
+    case 1: return walk_ptr<Real, DIM, 1, MULTI, STRAT>();
+    case 2: return walk_ptr<Real, DIM, 2, MULTI, STRAT>();
+    default: return walk_ptr<Real, DIM, 3, MULTI, STRAT>();
   }
 }
 
 template <typename Real, int DIM>
-static const void* walk_ptr_m(int u0, bool multi) {
-  return multi ? walk_ptr_u0<Real, DIM, true>(u0) : walk_ptr_u0<Real, DIM, false>(u0);
+static const void* walk_ptr_m(int u0, bool multi, int strat) {
+  if (strat == 1) return multi ? walk_ptr_u0<Real, DIM, true, 1>(u0) : walk_ptr_u0<Real, DIM, false, 1>(u0);
+  return multi ? walk_ptr_u0<Real, DIM, true, 0>(u0) : walk_ptr_u0<Real, DIM, false, 0>(u0);
 }
 
-static const void* walk_fn(int precision, int dim, int u0, bool multi) {
-  if (precision == 32) return dim == 1 ? walk_ptr_m<float, 1>(u0, multi) : walk_ptr_m<float, 2>(u0, multi);
-  return dim == 1 ? walk_ptr_m<double, 1>(u0, multi) : walk_ptr_m<double, 2>(u0, multi);
+static const void* walk_fn(int precision, int dim, int u0, bool multi, int strat) {
+  if (precision == 32)
+    return dim == 1 ? walk_ptr_m<float, 1>(u0, multi, strat) : walk_ptr_m<float, 2>(u0, multi, strat);
+  return dim == 1 ? walk_ptr_m<double, 1>(u0, multi, strat) : walk_ptr_m<double, 2>(u0, multi, strat);
 }
 
 int walk_max_blocks_per_cu(int precision, int dim, int u0_kind, int n_problems, int stack_depth, int waves_per_block) {
   int nb = 0;
   const size_t lds = walk_lds_bytes(precision, dim, stack_depth, waves_per_block, n_problems);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_fn(precision, dim, u0_kind, n_problems > 1),
+  // occupancy of the Strategy A variant (the B variant needs no more registers)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_fn(precision, dim, u0_kind, n_problems > 1, 0),
                                                    waves_per_block * kWave, lds) != hipSuccess)
     return 0;
   return nb;
@@ -487,7 +509,7 @@ hipError_t launch_reset(uint32_t* chunk_counter, unsigned long long* depth_count
 hipError_t launch_walk(int precision, int dim, int u0_kind, const WalkArgs& a, int grid, int waves_per_block,
                        hipStream_t s) {
   const size_t lds = walk_lds_bytes(precision, dim, (int)a.stack_depth, waves_per_block, (int)a.n_problems);
-  const void* fn = walk_fn(precision, dim, u0_kind, a.n_problems > 1);
+  const void* fn = walk_fn(precision, dim, u0_kind, a.n_problems > 1, (int)a.strategy);
   void* args[] = {const_cast<WalkArgs*>(&a)};
   return hipLaunchKernel(fn, dim3(grid), dim3(waves_per_block * kWave), args, lds, s);
 }

@@ -52,6 +52,9 @@ PdeT<Real> to_device(const brt_problem& p, const Norm& n) {
   d.sigma = (Real)n.sigma;
   d.inv_lambda = (Real)n.inv_lambda;
   d.mu = (Real)n.mu;
+  d.inv_q = (Real)(1.0 / n.q);
+  d.q_lo = (uint32_t)(n.Q - 1);  // Q >= 1
+  d.s_scale = n.Q < (1ull << 32) ? (Real)(1.0 / (4294967296.0 - (double)n.Q)) : (Real)0;
   d.K = n.K;
   d.jpack = 0;
   for (uint32_t i = 0; i < n.K; ++i) {
@@ -91,12 +94,18 @@ Norm normalize(const brt_problem& p, const brt_mc& mc) {
     n.lambda = 0.0;
     n.inv_lambda = 0.0;
     n.mu = p.coef[1];
+  } else if (mc.strategy == BRT_STRATEGY_B) {
+    // Strategy B: u = v e^{c_1 t}; a vertex carries tau K c_j / (1 - q) e^{(j-1) c_1 tau'}
+    n.q = mc.q;
+    n.mu = p.coef[1];
+    for (uint32_t i = 0; i < n.K; ++i) n.omega[i] = (double)n.K * p.coef[n.J[i]] / (1.0 - mc.q);
   } else {
     n.lambda = mc.lambda;
     n.inv_lambda = 1.0 / mc.lambda;
     n.mu = p.coef[1] + mc.lambda;
     for (uint32_t i = 0; i < n.K; ++i) n.omega[i] = (double)n.K * p.coef[n.J[i]] / mc.lambda;
   }
+  n.Q = (uint64_t)std::floor(n.q * 4294967296.0);  // exact: q 2^32 is a scaling by a power of two
   return n;
 }
 
@@ -252,6 +261,20 @@ int brt_problem_check(const brt_problem* p, const brt_mc* mc) {
   if (mc->node_cap < 1 || mc->node_cap > kMaxNodeCap) return fail(BRT_E_ARG, "node_cap must be in [1, 2^21-1]");
   if (mc->pade_L + mc->pade_M > mc->max_order) return fail(BRT_E_ARG, "pade_L + pade_M must be <= max_order");
   if (mc->pade_M > 16) return fail(BRT_E_ARG, "pade_M must be <= 16");
+  if (mc->strategy != BRT_STRATEGY_A && mc->strategy != BRT_STRATEGY_B) return fail(BRT_E_ARG, "unknown strategy");
+  if (mc->strategy == BRT_STRATEGY_B) {
+    if (!(mc->q >= 1e-9 && mc->q <= 1.0)) return fail(BRT_E_ARG, "Strategy B needs 1e-9 <= q <= 1");
+    double abar = 0.0;
+    uint32_t K = 0;
+    for (uint32_t j = 0; j < 8; ++j)
+      if (j != 1 && p->coef[j] != 0.0) {
+        abar += j;
+        K += 1;
+      }
+    if (K > 0 && mc->q >= 1.0) return fail(BRT_E_ARG, "Strategy B with a non-linear term needs q < 1");
+    if (K > 0 && !mc->prune && (1.0 - mc->q) * abar / K >= 1.0)
+      return fail(BRT_E_ARG, "Strategy B without pruning needs subcritical trees: (1 - q) * mean arity < 1");
+  }
   return BRT_OK;
 }
 
@@ -497,6 +520,7 @@ static int enqueue(brt_plan* p, const brt_out* o, hipStream_t s) {
     w.max_order = p->mc.max_order;
     w.prune = p->mc.prune;
     w.node_cap = p->mc.node_cap;
+    w.strategy = p->mc.strategy;
     w.stack_depth = (uint32_t)p->stack_depth;
     w.spill_depth = (uint32_t)p->spill_depth;
     w.spill = p->d_spill;

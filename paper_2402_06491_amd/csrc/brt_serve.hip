@@ -218,6 +218,7 @@ int run_group(brt_server* s, const std::vector<Request*>& group) {
   w.max_order = mc.max_order;
   w.prune = mc.prune;
   w.node_cap = mc.node_cap;
+  w.strategy = mc.strategy;
   w.stack_depth = (uint32_t)s->lds_depth;
   w.spill_depth = (uint32_t)s->spill_depth;
   w.n_threads = (uint32_t)(s->grid * s->wpb * kWave);
@@ -373,7 +374,7 @@ int brt_server_create(brt_ctx* ctx, const brt_server_opts* o, brt_server** out) 
   const brt_mc& mc = o->mc;
   if (mc.struct_size != sizeof(brt_mc) || (mc.precision != 32 && mc.precision != 64) || !(mc.lambda > 0.0) ||
       mc.max_order > 126 || mc.node_cap < 1 || mc.node_cap > kMaxNodeCap || mc.pade_L + mc.pade_M > mc.max_order ||
-      mc.pade_M > 16)
+      mc.pade_M > 16 || mc.strategy > BRT_STRATEGY_B)
     return set_error(BRT_E_ARG, "server: invalid Monte Carlo parameters");
   if (o->max_points < 1 || o->max_points > (1u << 20)) return set_error(BRT_E_ARG, "server: max_points must be 1..2^20");
   if (o->round_trees < kSegTrees || o->round_trees % kSegTrees || o->round_trees > (1u << 22))

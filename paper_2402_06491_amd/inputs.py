@@ -50,10 +50,11 @@ def problem(dim, diffusion, coef, u0):
     return d
 
 
-def mc_params(seed=0, lam=1.0, max_order=12, prune=1, node_cap=1 << 16, pade=(6, 6), precision=32):
+def mc_params(seed=0, lam=1.0, max_order=12, prune=1, node_cap=1 << 16, pade=(6, 6), precision=32, strategy=0,
+              q=0.5):
     return {"seed": int(seed), "lambda": float(lam), "max_order": int(max_order), "prune": int(prune),
             "node_cap": int(node_cap), "pade_L": int(pade[0]), "pade_M": int(pade[1]),
-            "precision": int(precision)}
+            "precision": int(precision), "strategy": int(strategy), "q": float(q)}
 
 
 # ---------------------------------------------------------------------------

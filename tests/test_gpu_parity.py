@@ -206,6 +206,35 @@ def test_determinism_and_graph_replay(ctx):
             np.testing.assert_array_equal(r[k], results[0][k], err_msg=k)
 
 
+@pytest.mark.parametrize("prec", [32, 64])
+def test_strategy_b_fisher(ctx, prec):
+    wl = inputs.fisher(n_trees=1000)
+    wl["mc"] = dict(wl["mc"], precision=prec, strategy=1, q=0.55)
+    _full_parity(ctx, f"strategy_b_fisher_fp{prec}", wl)
+
+
+def test_strategy_b_cubic_2d_and_batch(ctx):
+    wl = inputs.cubic_2d(n_trees=200, n_per_line=64)
+    wl["mc"] = dict(wl["mc"], strategy=1, q=0.7)
+    _full_parity(ctx, "strategy_b_cubic_2d", wl)
+    wl = inputs.poly_batch(n_points=256, n_min=64, n_max=1500, precision=32)
+    wl["mc"] = dict(wl["mc"], strategy=1, q=0.8)
+    _full_parity(ctx, "strategy_b_poly_batch", wl)
+
+
+def test_strategy_b_unpruned_and_heat(ctx):
+    """Subcritical Galton-Watson trees without pruning (tail bin), and q forced to 1 at f = 0."""
+    wl = inputs.kpp(n_trees=2000)
+    wl["mc"] = dict(wl["mc"], strategy=1, q=0.6)
+    _full_parity(ctx, "strategy_b_kpp_unpruned", wl)
+    g = inputs.gauss_sum([(1 / math.sqrt(4 * math.pi), 0.0, 0.0, math.sqrt(2.0))])
+    wl = {"problems": [inputs.problem(1, 1.0, [0, 0, 0], g)],
+          "mc": inputs.mc_params(seed=3, precision=64, strategy=1, q=0.5),
+          "x": np.linspace(-2, 2, 5).reshape(-1, 1), "t": np.full(5, 1.0), "n_trees": np.full(5, 700)}
+    gpu, _ = _full_parity(ctx, "strategy_b_heat_kernel", wl)
+    assert np.all(gpu["nodes"] == 700)
+
+
 def test_launch_settings_do_not_change_results(ctx):
     """Every tree is computed by one lane from its own counters and segments are fixed, so launch
     settings (block size, LDS stack levels, chunk size) change nothing in the outputs."""
