@@ -135,7 +135,9 @@ def normalize(problem: dict, mc: dict) -> Normalized:
         lam_eff, mu, omega = 0.0, coef[1], []
     elif strategy == 1:
         # Strategy B: u = v e^{c_1 t}; a vertex carries t K c_j / (1 - q) e^{(j-1) c_1 tau'}
-        q = float(mc.get("q", 0.5))
+        # the coin is w0 < floor(q 2^32) for a uniform 32-bit w0: its leaf probability is exactly
+        # floor(q 2^32) / 2^32, and that is the q of the weights g/q and c/(1-q)
+        q = math.floor(float(mc.get("q", 0.5)) * 4294967296.0) / 4294967296.0
         lam_eff = 0.0
         mu = coef[1]
         omega = [K * coef[j] / (1.0 - q) for j in J]

@@ -95,10 +95,11 @@ Norm normalize(const brt_problem& p, const brt_mc& mc) {
     n.inv_lambda = 0.0;
     n.mu = p.coef[1];
   } else if (mc.strategy == BRT_STRATEGY_B) {
-    // Strategy B: u = v e^{c_1 t}; a vertex carries tau K c_j / (1 - q) e^{(j-1) c_1 tau'}
-    n.q = mc.q;
+    // Strategy B: u = v e^{c_1 t}; a vertex carries tau K c_j / (1 - q) e^{(j-1) c_1 tau'}.  q is the
+    // coin's realised leaf probability floor(q 2^32) / 2^32, so the weights match the coin exactly.
+    n.q = std::floor(mc.q * 4294967296.0) * 0x1p-32;
     n.mu = p.coef[1];
-    for (uint32_t i = 0; i < n.K; ++i) n.omega[i] = (double)n.K * p.coef[n.J[i]] / (1.0 - mc.q);
+    for (uint32_t i = 0; i < n.K; ++i) n.omega[i] = (double)n.K * p.coef[n.J[i]] / (1.0 - n.q);
   } else {
     n.lambda = mc.lambda;
     n.inv_lambda = 1.0 / mc.lambda;
