@@ -130,6 +130,21 @@ def cubic_2d(n_trees=100_000, n_per_line=256, u0_seed=0):
             "n_trees": np.full(n, n_trees, np.int64), "problem_id": np.zeros(n, np.uint32)}
 
 
+def pdd_cubic_2d(n_trees=100_000, cells=512, n_steps=1000, ns=33, nt=8, outer="mc", u0_seed=0, precision=32):
+    """Domain decomposition of the 2-D cubic problem on [-8, 8]^2 into 4 x 4 subdomains.
+
+    Lines: the interfaces x, y in {-4, 0, 4} and (outer="mc") the edges x, y = +-8, each with ns nodes
+    uniform over [-8, 8] at the times k/nt, k = 1..nt (t = 1); 33 x 8 = 264 Monte Carlo points per
+    line.  Subdomains: cells x cells fine cells (h = 4/cells), n_steps Crank-Nicolson ADI steps, FP64.
+    """
+    grid = {"x_lo": -8.0, "x_hi": 8.0, "y_lo": -8.0, "y_hi": 8.0, "px": 4, "py": 4, "cx": int(cells),
+            "cy": int(cells), "T": 1.0, "n_steps": int(n_steps), "ns_x": int(ns), "ns_y": int(ns),
+            "nt": int(nt), "outer": outer}
+    mc = mc_params(seed=0, max_order=12, prune=1, node_cap=1 << 16, precision=precision)
+    return {"name": "pdd_cubic_2d", "problem": problem(2, 1.0, [0.0, 1.0, 0.0, -1.0], cubic_2d_u0(u0_seed)),
+            "mc": mc, "grid": grid, "n_trees": int(n_trees)}
+
+
 def poly_batch(n_points=4096, n_min=10_000, n_max=1_000_000, seed=1234, precision=32):
     """8 PDEs with polynomial f of degree 2,2,3,3,4,4,5,5 (coefficients U[-1,1]).
 
