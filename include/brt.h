@@ -289,6 +289,83 @@ int brt_server_stats_get(brt_server* srv, brt_server_stats* out);
 /* Stop the engine (requests in flight are abandoned) and free everything. */
 void brt_server_destroy(brt_server* srv);
 
+/* ------------------------------------------------------------------------------------------------
+ * Domain decomposition tail (Sec. 3, the PDD algorithm): the Monte Carlo values at nodes on lines
+ * of the space-time domain are interpolated into boundary data, which decouple the subdomains; each
+ * subdomain is then solved by finite differences.
+ *
+ * Geometry.  The rectangle [x_lo, x_hi] x [y_lo, y_hi] is cut into px x py equal subdomains of
+ * cx x cy fine cells (NX = px cx, NY = py cy; spacings hx = (x_hi - x_lo)/NX, hy likewise).  The cuts
+ * and, with outer = BRT_PDD_OUTER_LINES, the four outer edges are lines.  Lines are numbered vertical
+ * first (x = x_lo + k (x_hi - x_lo)/px, ascending k), then horizontal.  A vertical line carries ns_y
+ * nodes uniform over [y_lo, y_hi], a horizontal line ns_x nodes uniform over [x_lo, x_hi], at the
+ * times k T/nt (k = 1..nt); node values at t = 0 are u0.  With BRT_PDD_OUTER_ZERO the outer edges are
+ * held at 0.
+ *
+ * Interpolation (Sec. 3, "Interpolation"): on each line the tensor product of not-a-knot cubic
+ * splines over the uniform nodes, first along the line for every node time, then in time, evaluated
+ * at every fine node of the line at every time level n T/n_steps.  A node on both a vertical and a
+ * horizontal line takes the vertical line's value.
+ *
+ * Local solver (Sec. 3, "Local solver", Crank-Nicolson): the Peaceman-Rachford ADI form of
+ * Crank-Nicolson for u_t = a (u_xx + u_yy) + sum_j c_j u^j on every subdomain, the reaction taken at
+ * the extrapolated mid-step value (3 u^n - u^{n-1})/2 (u^{-1} = u^0):
+ *     (I - rx/2 dxx) u*      = (I + ry/2 dyy) u^n + dt/2 F,
+ *     (I - ry/2 dyy) u^{n+1} = (I + rx/2 dxx) u*  + dt/2 F,   rx = a dt/hx^2, ry = a dt/hy^2,
+ * with u* on the vertical lines set to ((I + ry/2 dyy) g^n + (I - ry/2 dyy) g^{n+1})/2, which makes the
+ * two half-steps exactly the factored Crank-Nicolson step.  All FP64.  The fields are row-major
+ * (NY+1) x (NX+1) arrays of doubles, x fastest, node (i, j) at (x_lo + i hx, y_lo + j hy).
+ * ------------------------------------------------------------------------------------------------ */
+#define BRT_PDD_OUTER_LINES 0u
+#define BRT_PDD_OUTER_ZERO 1u
+
+typedef struct brt_pdd_grid {
+  uint32_t struct_size;
+  double x_lo, x_hi, y_lo, y_hi;
+  uint32_t px, py;        /* subdomains per direction, 1..64 */
+  uint32_t cx, cy;        /* fine cells per subdomain per direction, 2..4096 */
+  double T;               /* final time > 0 */
+  uint32_t n_steps;       /* time steps to T, 1..2^20 */
+  uint32_t ns_x, ns_y;    /* nodes per horizontal / vertical line, 4..257 */
+  uint32_t nt;            /* node time levels, 3..63 (with t = 0: at least 4 rows in time) */
+  uint32_t outer;         /* BRT_PDD_OUTER_* */
+} brt_pdd_grid;
+
+typedef struct brt_pdd brt_pdd;
+
+/* Create the tail for one 2-D problem on a grid: validates the grid, precomputes the tridiagonal
+ * factors and allocates the device fields (three of (NY+1)(NX+1) doubles) and the boundary data
+ * ((n_steps+1) x fine nodes per line, doubles).  Errors: BRT_E_ARG, BRT_E_NOMEM, BRT_E_DEVICE. */
+int brt_pdd_create(brt_ctx* ctx, const brt_problem* problem, const brt_pdd_grid* grid, brt_pdd** out);
+/* Node query points in line order, then time level k = 1..nt, then position along the line (host).
+ * *n receives their number; xy (2n, x then y) and t (n) are written when not NULL. */
+int brt_pdd_nodes(const brt_pdd* pdd, double* xy, double* t, uint64_t* n);
+/* Number of lines and, per line (arrays of n_lines, each nullable): orientation (0 vertical,
+ * 1 horizontal), its coordinate, and its number of fine nodes (NY+1 or NX+1). */
+int brt_pdd_lines(const brt_pdd* pdd, uint32_t* n_lines, uint32_t* orient, double* coord, uint32_t* n_fine);
+/* Interpolate node values (device, FP64, in the order of brt_pdd_nodes) into the boundary data of
+ * every line at every time level (device, owned by pdd).  Asynchronous on `stream`. */
+int brt_pdd_interpolate(brt_pdd* pdd, const double* node_values, void* stream);
+/* Copy the boundary data of one line ((n_steps+1) x n_fine doubles, time level major) to dst
+ * (device).  Asynchronous. */
+int brt_pdd_boundary(const brt_pdd* pdd, uint32_t line, double* dst, void* stream);
+/* Solve every subdomain from u0 at the grid nodes through `steps` time steps (1..n_steps) with the
+ * current boundary data and write the field at step `steps` to `field` (device).  One persistent
+ * cooperative launch; work items of 64 lines are taken from per-phase counters, phases are separated
+ * by a grid barrier.  Asynchronous; BRT_E_DEVICE if the barrier timed out (reported by the next
+ * brt_pdd_* call that synchronises: brt_pdd_get_timing). */
+int brt_pdd_solve(brt_pdd* pdd, uint32_t steps, double* field, void* stream);
+/* The whole tail: Monte Carlo at the nodes (a plan with `mc` and trees_per_node trees per node,
+ * Pade values), interpolation, and the solve through n_steps.  node_u (device, nullable) receives the
+ * node values.  Asynchronous. */
+int brt_pdd_run(brt_pdd* pdd, const brt_mc* mc, uint64_t trees_per_node, double* node_u, double* field,
+                void* stream);
+/* Wait for the last run / solve and report its stage times in ms (events on its stream):
+ * ms[0] Monte Carlo (0 after brt_pdd_solve), ms[1] interpolation, ms[2] subdomain solves; BRT_E_DEVICE
+ * if the solver's grid barrier timed out. */
+int brt_pdd_get_timing(brt_pdd* pdd, double* ms);
+void brt_pdd_destroy(brt_pdd* pdd);
+
 #ifdef __cplusplus
 }
 #endif

@@ -160,9 +160,10 @@ class Grid:
         return out
 
     def line_nodes(self, orient):
+        """Nodes s_lo + i h_s, h_s = (line length) / (ns - 1): the uniform nodes at spacing h_s."""
         if orient == "v":
-            return self.y_lo + np.arange(self.ns_y) * (self.y_hi - self.y_lo) / (self.ns_y - 1)
-        return self.x_lo + np.arange(self.ns_x) * (self.x_hi - self.x_lo) / (self.ns_x - 1)
+            return self.y_lo + np.arange(self.ns_y) * ((self.y_hi - self.y_lo) / (self.ns_y - 1))
+        return self.x_lo + np.arange(self.ns_x) * ((self.x_hi - self.x_lo) / (self.ns_x - 1))
 
 
 def node_points(grid: Grid):

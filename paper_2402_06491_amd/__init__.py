@@ -85,6 +85,14 @@ class ServerStats(ctypes.Structure):
                                        "trees_per_s")]
 
 
+class PddGrid(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("x_lo", ctypes.c_double), ("x_hi", ctypes.c_double),
+                ("y_lo", ctypes.c_double), ("y_hi", ctypes.c_double), ("px", ctypes.c_uint32),
+                ("py", ctypes.c_uint32), ("cx", ctypes.c_uint32), ("cy", ctypes.c_uint32), ("T", ctypes.c_double),
+                ("n_steps", ctypes.c_uint32), ("ns_x", ctypes.c_uint32), ("ns_y", ctypes.c_uint32),
+                ("nt", ctypes.c_uint32), ("outer", ctypes.c_uint32)]
+
+
 _lib = None
 
 # (name, restype, argtypes) for every entry point of include/brt.h
@@ -118,6 +126,19 @@ _SIGS = [
     ("brt_server_drain", ctypes.c_int, [ctypes.c_void_p, ctypes.c_double]),
     ("brt_server_stats_get", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ServerStats)]),
     ("brt_server_destroy", None, [ctypes.c_void_p]),
+    ("brt_pdd_create", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Problem), ctypes.POINTER(PddGrid),
+                                      ctypes.POINTER(ctypes.c_void_p)]),
+    ("brt_pdd_nodes", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.POINTER(ctypes.c_uint64)]),
+    ("brt_pdd_lines", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32), ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p]),
+    ("brt_pdd_interpolate", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    ("brt_pdd_boundary", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p]),
+    ("brt_pdd_solve", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p]),
+    ("brt_pdd_run", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(MC), ctypes.c_uint64, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_void_p]),
+    ("brt_pdd_get_timing", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
+    ("brt_pdd_destroy", None, [ctypes.c_void_p]),
 ]
 
 
@@ -415,6 +436,105 @@ class Server:
     def close(self):
         if self._h:
             lib().brt_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+PDD_OUTER = {"mc": 0, "lines": 0, "zero": 1}
+
+
+def make_pdd_grid(d: dict) -> PddGrid:
+    g = PddGrid()
+    g.struct_size = ctypes.sizeof(PddGrid)
+    for k in ("x_lo", "x_hi", "y_lo", "y_hi", "T"):
+        setattr(g, k, float(d[k]))
+    for k in ("px", "py", "cx", "cy", "n_steps", "ns_x", "ns_y", "nt"):
+        setattr(g, k, int(d[k]))
+    o = d.get("outer", "mc")
+    g.outer = PDD_OUTER[o] if isinstance(o, str) else int(o)
+    return g
+
+
+class Pdd:
+    """The domain-decomposition tail (brt_pdd_*) for one 2-D problem on one grid."""
+
+    def __init__(self, ctx: Context, problem: dict, grid: dict):
+        import torch
+
+        self._torch = torch
+        self.ctx = ctx
+        self.grid = dict(grid)
+        self._prob = make_problem(problem)
+        self._grid = make_pdd_grid(grid)
+        self._h = ctypes.c_void_p()
+        _check(lib().brt_pdd_create(ctx._h, ctypes.byref(self._prob), ctypes.byref(self._grid),
+                                    ctypes.byref(self._h)))
+        self.NX = self._grid.px * self._grid.cx
+        self.NY = self._grid.py * self._grid.cy
+
+    def nodes(self):
+        """(xy[n, 2], t[n]) host arrays of the Monte Carlo query points."""
+        n = ctypes.c_uint64()
+        _check(lib().brt_pdd_nodes(self._h, None, None, ctypes.byref(n)))
+        xy = np.empty((n.value, 2), np.float64)
+        t = np.empty(n.value, np.float64)
+        _check(lib().brt_pdd_nodes(self._h, xy.ctypes.data, t.ctypes.data, ctypes.byref(n)))
+        return xy, t
+
+    def lines(self):
+        n = ctypes.c_uint32()
+        _check(lib().brt_pdd_lines(self._h, ctypes.byref(n), None, None, None))
+        o = np.empty(n.value, np.uint32)
+        c = np.empty(n.value, np.float64)
+        f = np.empty(n.value, np.uint32)
+        _check(lib().brt_pdd_lines(self._h, ctypes.byref(n), o.ctypes.data, c.ctypes.data, f.ctypes.data))
+        return o, c, f
+
+    def _stream(self):
+        return ctypes.c_void_p(self._torch.cuda.current_stream().cuda_stream)
+
+    def interpolate(self, node_values):
+        """node_values: a float64 CUDA tensor in node order."""
+        v = node_values.contiguous()
+        _check(lib().brt_pdd_interpolate(self._h, ctypes.c_void_p(v.data_ptr()), self._stream()))
+        self._keep = v
+
+    def boundary(self, line):
+        _, _, f = self.lines()
+        out = self._torch.empty((self._grid.n_steps + 1, int(f[line])), dtype=self._torch.float64, device="cuda")
+        _check(lib().brt_pdd_boundary(self._h, int(line), ctypes.c_void_p(out.data_ptr()), self._stream()))
+        return out
+
+    def solve(self, steps=None, field=None):
+        steps = self._grid.n_steps if steps is None else int(steps)
+        if field is None:
+            field = self._torch.empty((self.NY + 1, self.NX + 1), dtype=self._torch.float64, device="cuda")
+        _check(lib().brt_pdd_solve(self._h, steps, ctypes.c_void_p(field.data_ptr()), self._stream()))
+        return field
+
+    def run(self, mc: dict, trees_per_node: int, node_u=None, field=None):
+        m = make_mc(mc)
+        if field is None:
+            field = self._torch.empty((self.NY + 1, self.NX + 1), dtype=self._torch.float64, device="cuda")
+        nu = ctypes.c_void_p(node_u.data_ptr()) if node_u is not None else None
+        _check(lib().brt_pdd_run(self._h, ctypes.byref(m), int(trees_per_node), nu,
+                                 ctypes.c_void_p(field.data_ptr()), self._stream()))
+        return field
+
+    def timing(self):
+        """(Monte Carlo, interpolation, solve) in ms of the last run; waits for it."""
+        ms = (ctypes.c_double * 3)()
+        _check(lib().brt_pdd_get_timing(self._h, ms))
+        return tuple(ms)
+
+    def close(self):
+        if self._h:
+            lib().brt_pdd_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

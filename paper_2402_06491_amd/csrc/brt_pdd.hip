@@ -1,0 +1,839 @@
+// Domain decomposition tail (Sec. 3): interpolation of the Monte Carlo node values into boundary data
+// (tensor-product not-a-knot cubic splines) and the decoupled subdomain solves (Crank-Nicolson in
+// Peaceman-Rachford ADI form), FP64 throughout.
+//
+// Kernels
+//   spline_rows_kernel  one thread per (line, node time): spline moments along the line
+//   spline_s_kernel     one thread per (line, node time, fine node): values along the line
+//   spline_t_kernel     one thread per (line, fine node): spline in time, written at every time level
+//   init_field_kernel   u0 at every grid node, line data at level 0
+//   adi_kernel          persistent cooperative launch through all time steps: per step an x phase and
+//                       a y phase; a work item is 64 lines of one subdomain (one lane per line, the
+//                       tridiagonal system solved by the Thomas recurrence with precomputed factors),
+//                       taken from a per-phase counter; a grid barrier separates the phases.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "brt.h"
+#include "brt_internal.h"
+
+using brt::set_error;
+
+namespace {
+
+constexpr int kLanes = 64;
+constexpr uint32_t kMaxSub = 64;
+constexpr uint32_t kMaxCells = 4096;
+constexpr uint32_t kMaxNodesPerLine = 257;
+constexpr uint32_t kMaxNt = 63;
+constexpr double kBarrierSeconds = 5.0;
+
+#define PDD_TRY(expr)                                                                               \
+  do {                                                                                              \
+    hipError_t e_ = (expr);                                                                         \
+    if (e_ != hipSuccess) return set_error(BRT_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+struct LineDev {
+  uint32_t orient;    // 0 vertical, 1 horizontal
+  uint32_t k;         // index of the cut along x (vertical) or y (horizontal)
+  uint32_t n_fine;    // fine nodes along the line
+  uint32_t ns;        // interpolation nodes along the line
+  uint64_t bd_off;    // offset (doubles) of time level 0 in the boundary data
+  uint64_t node_off;  // index of the line's first node value
+  double c;           // x of a vertical line, y of a horizontal one
+  double s_lo;        // first position along the line
+  double hs;          // node spacing
+  double hf;          // fine spacing
+};
+
+struct U0Dev {
+  uint32_t kind;
+  uint32_t nterms;
+  double p[40];
+};
+
+__device__ double u0_value(const U0Dev& u, double x, double y) {
+  const double* p = u.p;
+  switch (u.kind) {
+    case BRT_U0_CONST:
+      return p[0];
+    case BRT_U0_LOGISTIC: {
+      const double nx = x * p[4] + y * p[5];
+      const double base = 1.0 / (1.0 + exp(p[1] * (nx - p[2])));
+      double v = 1.0;
+      for (int k = 0; k < (int)p[3]; ++k) v *= base;
+      return p[0] * v;
+    }
+    case BRT_U0_GAUSS_SUM: {
+      double tot = 0.0;
+      for (uint32_t k = 0; k < u.nterms; ++k) {
+        const double A = p[4 * k], cx = p[4 * k + 1], cy = p[4 * k + 2], s = p[4 * k + 3];
+        tot += A * exp(-((x - cx) * (x - cx) + (y - cy) * (y - cy)) / (2.0 * s * s));
+      }
+      return tot;
+    }
+    default: {
+      if (fabs(x) > p[1] || fabs(y) > p[2]) return 0.0;
+      const double cxv = cos(M_PI * x / (2.0 * p[1]));
+      const double cyv = cos(M_PI * y / (2.0 * p[2]));
+      return p[0] * (cxv * cxv) * (cyv * cyv);
+    }
+  }
+}
+
+// Moments (second derivatives) of the not-a-knot spline through y[0..m-1] at spacing h, m >= 4.  With
+// uniform nodes the not-a-knot conditions M0 = 2 M1 - M2 and M(m-1) = 2 M(m-2) - M(m-3) turn the first
+// and last interior equations into 6 M1 = r1 and 6 M(m-2) = r(m-2); the rest is the (1, 4, 1) system.
+__device__ void notaknot_moments(const double* y, size_t ys, double* M, size_t ms, double* cp, size_t cs,
+                                 int m, double h) {
+  const double k6 = 6.0 / (h * h);
+  auto r = [&](int i) { return k6 * ((y[(i - 1) * ys] - 2.0 * y[i * ys]) + y[(i + 1) * ys]); };
+  const double M1 = r(1) / 6.0;
+  const double Mm2 = r(m - 2) / 6.0;
+  M[1 * ms] = M1;
+  M[(m - 2) * ms] = Mm2;
+  if (m >= 5) {
+    // unknowns i = 2..m-3
+    double dprev = 0.0, cprev = 0.0;
+    for (int i = 2; i <= m - 3; ++i) {
+      double rhs = r(i);
+      if (i == 2) rhs -= M1;
+      if (i == m - 3) rhs -= Mm2;
+      const double inv = 1.0 / (4.0 - (i == 2 ? 0.0 : cprev));
+      const double c = inv;
+      const double d = (rhs - (i == 2 ? 0.0 : dprev)) * inv;
+      cp[i * cs] = c;
+      M[i * ms] = d;
+      cprev = c;
+      dprev = d;
+    }
+    double xn = M[(m - 3) * ms];
+    for (int i = m - 4; i >= 2; --i) {
+      xn = M[i * ms] - cp[i * cs] * xn;
+      M[i * ms] = xn;
+    }
+  }
+  M[0] = 2.0 * M1 - M[2 * ms];
+  M[(m - 1) * ms] = 2.0 * Mm2 - M[(m - 3) * ms];
+}
+
+// Value at s (relative to node 0) of the spline with values y and moments M; s beyond the ends uses
+// the end intervals' cubics.
+__device__ double spline_value(const double* y, size_t ys, const double* M, size_t ms, int m, double h, double s) {
+  int i = (int)floor(s / h);
+  i = i < 0 ? 0 : (i > m - 2 ? m - 2 : i);
+  const double ds = s - i * h;
+  const double y0 = y[i * ys], y1 = y[(i + 1) * ys];
+  const double M0 = M[i * ms], M1 = M[(i + 1) * ms];
+  const double b = (y1 - y0) / h - h * (2.0 * M0 + M1) / 6.0;
+  return y0 + ds * (b + ds * (0.5 * M0 + ds * ((M1 - M0) / (6.0 * h))));
+}
+
+struct SplineArgs {
+  const LineDev* lines;
+  uint32_t n_lines;
+  uint32_t rows;      // nt + 1
+  uint32_t max_ns;
+  uint32_t max_fine;
+  const double* node_values;
+  double* vals;       // [line][row][max_ns]
+  double* mom;        // [line][row][max_ns]
+  double* cp;         // [line][row][max_ns] scratch
+  double* rowsv;      // [row][line][max_fine]: values along the line at the fine nodes
+  double* tmom;       // [row][line][max_fine]
+  double* tcp;        // [row][line][max_fine]
+  double* bd;
+  double ht;          // node time spacing T / nt
+  double dt;          // fine time step
+  uint32_t n_steps;
+  U0Dev u0;
+};
+
+__global__ void spline_rows_kernel(SplineArgs a) {
+  const uint32_t id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= a.n_lines * a.rows) return;
+  const uint32_t l = id / a.rows, row = id % a.rows;
+  const LineDev L = a.lines[l];
+  const size_t base = (size_t)id * a.max_ns;
+  double* y = a.vals + base;
+  for (uint32_t i = 0; i < L.ns; ++i) {
+    double v;
+    if (row == 0) {
+      const double s = L.s_lo + i * L.hs;
+      v = L.orient == 0 ? u0_value(a.u0, L.c, s) : u0_value(a.u0, s, L.c);
+    } else {
+      v = a.node_values[L.node_off + (size_t)(row - 1) * L.ns + i];
+    }
+    y[i] = v;
+  }
+  notaknot_moments(y, 1, a.mom + base, 1, a.cp + base, 1, (int)L.ns, L.hs);
+}
+
+__global__ void spline_s_kernel(SplineArgs a) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t lr = blockIdx.y;  // line * rows + row
+  const uint32_t l = lr / a.rows, row = lr % a.rows;
+  const LineDev L = a.lines[l];
+  if (j >= L.n_fine) return;
+  const size_t base = (size_t)lr * a.max_ns;
+  const double v = spline_value(a.vals + base, 1, a.mom + base, 1, (int)L.ns, L.hs, j * L.hf);
+  a.rowsv[((size_t)row * a.n_lines + l) * a.max_fine + j] = v;
+}
+
+__global__ void spline_t_kernel(SplineArgs a) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t l = blockIdx.y;
+  const LineDev L = a.lines[l];
+  if (j >= L.n_fine) return;
+  const size_t stride = (size_t)a.n_lines * a.max_fine;  // between node times
+  const size_t off = (size_t)l * a.max_fine + j;
+  const double* y = a.rowsv + off;
+  double* M = a.tmom + off;
+  notaknot_moments(y, stride, M, stride, a.tcp + off, stride, (int)a.rows, a.ht);
+  double* out = a.bd + L.bd_off + j;
+  for (uint32_t n = 0; n <= a.n_steps; ++n)
+    out[(size_t)n * L.n_fine] = spline_value(y, stride, M, stride, (int)a.rows, a.ht, n * a.dt);
+}
+
+struct FieldArgs {
+  double* f0;
+  double* f1;
+  const double* bd;
+  const LineDev* lines;
+  uint32_t NX, NY, cx, cy, zero_outer;
+  double x_lo, y_lo, hx, hy;
+  int16_t vline[kMaxSub + 1];
+  int16_t hline[kMaxSub + 1];
+  U0Dev u0;
+};
+
+__global__ void init_field_kernel(FieldArgs a) {
+  const uint64_t id = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (uint64_t)(a.NX + 1) * (a.NY + 1)) return;
+  const uint32_t i = (uint32_t)(id % (a.NX + 1)), j = (uint32_t)(id / (a.NX + 1));
+  double v = u0_value(a.u0, a.x_lo + i * a.hx, a.y_lo + j * a.hy);
+  const bool on_v = i % a.cx == 0 && a.vline[i / a.cx] >= 0;
+  const bool on_h = j % a.cy == 0 && a.hline[j / a.cy] >= 0;
+  if (on_v) {
+    const LineDev& L = a.lines[a.vline[i / a.cx]];
+    v = a.bd[L.bd_off + j];
+  } else if (on_h) {
+    const LineDev& L = a.lines[a.hline[j / a.cy]];
+    v = a.bd[L.bd_off + i];
+  } else if (a.zero_outer && (i == 0 || i == a.NX || j == 0 || j == a.NY)) {
+    v = 0.0;
+  }
+  const size_t idx = (size_t)j * (a.NX + 1) + i;
+  a.f0[idx] = v;
+  a.f1[idx] = v;
+}
+
+struct AdiArgs {
+  double* f0;
+  double* f1;
+  double* star;
+  const double* bd;
+  const LineDev* lines;
+  const double* inv_x;
+  const double* cp_x;
+  const double* inv_y;
+  const double* cp_y;
+  uint32_t* sync;       // [0] arrivals, [1] generation, [2] abort, [3 + 2n], [4 + 2n] work counters of step n
+  uint64_t spin_limit;  // wall-clock ticks a barrier may wait
+  double coef[8];
+  double rx2, ry2, dt2;
+  uint32_t W;           // row stride NX + 1
+  uint32_t px, py, cx, cy;
+  uint32_t steps;
+  uint32_t nblocks;
+  uint32_t x_blk, y_blk;       // 64-line blocks per subdomain in the x and the y phase
+  uint32_t n_vlines, bv, bh;   // data lines: vertical count; 64-node blocks per vertical / horizontal line
+  uint32_t n_lines;
+  int16_t vline[kMaxSub + 1];
+  int16_t hline[kMaxSub + 1];
+};
+
+__device__ inline double reaction(const double* c, double u) {
+  double f = 0.0;
+  for (int j = 7; j >= 0; --j) f = f * u + c[j];
+  return f;
+}
+
+__device__ inline uint32_t grab(uint32_t* ctr) {
+  uint32_t v = 0;
+  if (threadIdx.x == 0) v = atomicAdd(ctr, 1u);
+  return __shfl(v, 0);
+}
+
+// Grid barrier (sense by generation count).  Every block waits at most spin_limit wall-clock ticks; on
+// a time-out, or when another block has timed out, it raises the abort word and returns false so that
+// every block leaves the kernel.
+__device__ bool grid_barrier(uint32_t* sync, uint32_t nblocks, uint32_t& gen, uint64_t spin_limit) {
+  __syncthreads();
+  int ok = 1;
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const uint32_t target = gen + 1;
+    if (atomicAdd(&sync[0], 1u) == nblocks - 1) {
+      __hip_atomic_store(&sync[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&sync[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      const uint64_t t0 = wall_clock64();
+      while (__hip_atomic_load(&sync[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != target) {
+        if (__hip_atomic_load(&sync[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+            wall_clock64() - t0 > spin_limit) {
+          atomicExch(&sync[2], 1u);
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+    __threadfence();
+    gen = target;
+  }
+  ok = __shfl(ok, 0);
+  gen = __shfl(gen, 0);
+  return ok != 0;
+}
+
+// Intermediate-level value on the vertical line kx at row y between levels n and n+1.
+__device__ inline double ustar_line(const AdiArgs& a, uint32_t kx, uint32_t y, uint32_t n) {
+  const int vl = a.vline[kx];
+  if (vl < 0) return 0.0;
+  const LineDev& L = a.lines[vl];
+  const double* g0 = a.bd + L.bd_off + (size_t)n * L.n_fine;
+  const double* g1 = g0 + L.n_fine;
+  const double d0 = (g0[y - 1] - 2.0 * g0[y]) + g0[y + 1];
+  const double d1 = (g1[y - 1] - 2.0 * g1[y]) + g1[y + 1];
+  return 0.5 * (g0[y] + a.ry2 * d0) + 0.5 * (g1[y] - a.ry2 * d1);
+}
+
+// Value at level n on the horizontal line ky at column x (0 for an outer edge held at zero).
+__device__ inline double hline_value(const AdiArgs& a, uint32_t ky, uint32_t x, uint32_t n) {
+  const int hl = a.hline[ky];
+  if (hl < 0) return 0.0;
+  const LineDev& L = a.lines[hl];
+  return a.bd[L.bd_off + (size_t)n * L.n_fine + x];
+}
+
+__device__ void x_sweep(const AdiArgs& a, uint32_t item, uint32_t n, const double* cur, const double* prev) {
+  const uint32_t sub = item / a.x_blk, blk = item % a.x_blk;
+  const uint32_t sx = sub % a.px, sy = sub / a.px;
+  const uint32_t y = sy * a.cy + 1 + blk * kLanes + threadIdx.x;
+  if (y >= (sy + 1) * a.cy) return;
+  const uint32_t c0 = sx * a.cx, m = a.cx - 1, W = a.W;
+  const size_t base = (size_t)y * W;
+  const double usl = ustar_line(a, sx, y, n);
+  const double usr = ustar_line(a, sx + 1, y, n);
+  a.star[base + c0] = usl;
+  if (sx == a.px - 1) a.star[base + c0 + a.cx] = usr;
+  double dp = 0.0;
+  for (uint32_t i = 0; i < m; ++i) {
+    const size_t idx = base + c0 + 1 + i;
+    const double u = cur[idx];
+    const double F = reaction(a.coef, 1.5 * u - 0.5 * prev[idx]);
+    double d = u + a.ry2 * ((cur[idx - W] - 2.0 * u) + cur[idx + W]) + a.dt2 * F;
+    if (i == 0) d += a.rx2 * usl;
+    if (i == m - 1) d += a.rx2 * usr;
+    dp = (i == 0 ? d : d + a.rx2 * dp) * a.inv_x[i];
+    a.star[idx] = dp;
+  }
+  double xv = dp;
+  for (int i = (int)m - 2; i >= 0; --i) {
+    const size_t idx = base + c0 + 1 + i;
+    xv = a.star[idx] - a.cp_x[i] * xv;
+    a.star[idx] = xv;
+  }
+}
+
+__device__ void y_sweep(const AdiArgs& a, uint32_t item, uint32_t n, const double* cur, double* next) {
+  const uint32_t sub = item / a.y_blk, blk = item % a.y_blk;
+  const uint32_t sx = sub % a.px, sy = sub / a.px;
+  const uint32_t x = sx * a.cx + 1 + blk * kLanes + threadIdx.x;
+  if (x >= (sx + 1) * a.cx) return;
+  const uint32_t r0 = sy * a.cy, m = a.cy - 1, W = a.W;
+  const double gb0 = hline_value(a, sy, x, n + 1);
+  const double gb1 = hline_value(a, sy + 1, x, n + 1);
+  double dp = 0.0;
+  for (uint32_t i = 0; i < m; ++i) {
+    const size_t idx = (size_t)(r0 + 1 + i) * W + x;
+    const double us = a.star[idx];
+    const double F = reaction(a.coef, 1.5 * cur[idx] - 0.5 * next[idx]);  // next still holds u^{n-1}
+    double d = us + a.rx2 * ((a.star[idx - 1] - 2.0 * us) + a.star[idx + 1]) + a.dt2 * F;
+    if (i == 0) d += a.ry2 * gb0;
+    if (i == m - 1) d += a.ry2 * gb1;
+    dp = (i == 0 ? d : d + a.ry2 * dp) * a.inv_y[i];
+    next[idx] = dp;
+  }
+  double xv = dp;
+  for (int i = (int)m - 2; i >= 0; --i) {
+    const size_t idx = (size_t)(r0 + 1 + i) * W + x;
+    xv = next[idx] - a.cp_y[i] * xv;
+    next[idx] = xv;
+  }
+}
+
+// Line nodes of level n+1 into the new field; a horizontal line leaves the nodes it shares with a
+// vertical data line to that line.
+__device__ void write_lines(const AdiArgs& a, uint32_t item, uint32_t n, double* next) {
+  uint32_t l, blk;
+  if (item < a.n_vlines * a.bv) {
+    l = item / a.bv;
+    blk = item % a.bv;
+  } else {
+    item -= a.n_vlines * a.bv;
+    l = a.n_vlines + item / a.bh;
+    blk = item % a.bh;
+  }
+  const LineDev& L = a.lines[l];
+  const uint32_t j = blk * kLanes + threadIdx.x;
+  if (j >= L.n_fine) return;
+  const double v = a.bd[L.bd_off + (size_t)(n + 1) * L.n_fine + j];
+  if (L.orient == 0) {
+    next[(size_t)j * a.W + L.k * a.cx] = v;
+  } else {
+    if (j % a.cx == 0 && a.vline[j / a.cx] >= 0) return;
+    next[(size_t)(L.k * a.cy) * a.W + j] = v;
+  }
+}
+
+__global__ __launch_bounds__(64) void adi_kernel(AdiArgs a) {
+  uint32_t gen = 0;
+  const uint32_t nsub = a.px * a.py;
+  const uint32_t x_items = nsub * a.x_blk;
+  const uint32_t y_items = nsub * a.y_blk;
+  const uint32_t l_items = a.n_vlines * a.bv + (a.n_lines - a.n_vlines) * a.bh;
+  for (uint32_t n = 0; n < a.steps; ++n) {
+    const double* cur = (n & 1) ? a.f1 : a.f0;
+    double* prev = (n & 1) ? a.f0 : a.f1;  // holds u^{n-1}; receives u^{n+1}
+    for (;;) {
+      const uint32_t it = grab(&a.sync[3 + 2 * n]);
+      if (it >= x_items) break;
+      x_sweep(a, it, n, cur, prev);
+    }
+    if (!grid_barrier(a.sync, a.nblocks, gen, a.spin_limit)) return;
+    for (;;) {
+      const uint32_t it = grab(&a.sync[4 + 2 * n]);
+      if (it >= y_items + l_items) break;
+      if (it < y_items)
+        y_sweep(a, it, n, cur, prev);
+      else
+        write_lines(a, it - y_items, n, prev);
+    }
+    if (!grid_barrier(a.sync, a.nblocks, gen, a.spin_limit)) return;
+  }
+}
+
+}  // namespace
+
+struct brt_pdd {
+  brt_ctx* ctx = nullptr;
+  brt_problem prob{};
+  brt_pdd_grid g{};
+  int device = 0, n_cu = 0;
+  uint32_t NX = 0, NY = 0, max_ns = 0, max_fine = 0, n_vlines = 0;
+  double hx = 0, hy = 0, dt = 0, rx = 0, ry = 0;
+  std::vector<LineDev> lines;
+  int16_t vline[kMaxSub + 1];
+  int16_t hline[kMaxSub + 1];
+  uint64_t n_nodes = 0, bd_doubles = 0;
+  U0Dev u0{};
+  // device
+  LineDev* d_lines = nullptr;
+  double* d_bd = nullptr;
+  double* d_f[3] = {nullptr, nullptr, nullptr};
+  double* d_fac = nullptr;
+  double* d_spl = nullptr;  // vals, mom, cp, rowsv, tmom, tcp
+  uint32_t* d_sync = nullptr;
+  double* d_node_u = nullptr;
+  size_t spl_rows = 0, spl_fine = 0;
+  // Monte Carlo plan of the nodes (built on first run, rebuilt when mc or the tree count change)
+  brt_plan* plan = nullptr;
+  brt_mc plan_mc{};
+  uint64_t plan_trees = 0;
+  hipEvent_t ev[6] = {};
+  bool recorded[3] = {false, false, false};
+  int grid = 0;
+};
+
+namespace {
+
+void pdd_free(brt_pdd* p) {
+  if (!p) return;
+  if (p->plan) brt_plan_destroy(p->plan);
+  (void)hipFree(p->d_lines);
+  (void)hipFree(p->d_bd);
+  for (double* f : p->d_f) (void)hipFree(f);
+  (void)hipFree(p->d_fac);
+  (void)hipFree(p->d_spl);
+  (void)hipFree(p->d_sync);
+  (void)hipFree(p->d_node_u);
+  for (hipEvent_t e : p->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete p;
+}
+
+void thomas_factors(double r, uint32_t m, double* inv, double* cp) {
+  // (1 + r) on the diagonal, -r/2 beside it: the scaled Thomas factors
+  const double b = 1.0 + r, off = -0.5 * r;
+  inv[0] = 1.0 / b;
+  cp[0] = off * inv[0];
+  for (uint32_t i = 1; i < m; ++i) {
+    inv[i] = 1.0 / (b - off * cp[i - 1]);
+    cp[i] = off * inv[i];
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int brt_pdd_create(brt_ctx* ctx, const brt_problem* prob, const brt_pdd_grid* grid, brt_pdd** out) {
+  if (!ctx || !prob || !grid || !out) return set_error(BRT_E_ARG, "brt_pdd_create: NULL argument");
+  *out = nullptr;
+  if (prob->struct_size != sizeof(brt_problem)) return set_error(BRT_E_ARG, "brt_problem.struct_size mismatch");
+  if (grid->struct_size != sizeof(brt_pdd_grid)) return set_error(BRT_E_ARG, "brt_pdd_grid.struct_size mismatch");
+  const brt_pdd_grid& g = *grid;
+  if (prob->dim != 2) return set_error(BRT_E_ARG, "pdd: the problem must be 2-D");
+  if (!(prob->diffusion > 0.0) || !std::isfinite(prob->diffusion)) return set_error(BRT_E_ARG, "pdd: diffusion must be > 0");
+  for (double c : prob->coef)
+    if (!std::isfinite(c)) return set_error(BRT_E_ARG, "pdd: non-finite coefficient");
+  if (prob->u0_kind > BRT_U0_COS2_BUMP) return set_error(BRT_E_ARG, "pdd: unknown u0_kind");
+  if (prob->u0_kind == BRT_U0_GAUSS_SUM && (prob->u0_nterms < 1 || prob->u0_nterms > 8))
+    return set_error(BRT_E_ARG, "pdd: gauss_sum needs 1..8 terms");
+  if (!(g.x_hi > g.x_lo) || !(g.y_hi > g.y_lo) || !std::isfinite(g.x_lo + g.x_hi + g.y_lo + g.y_hi))
+    return set_error(BRT_E_ARG, "pdd: empty or non-finite domain");
+  if (g.px < 1 || g.py < 1 || g.px > kMaxSub || g.py > kMaxSub) return set_error(BRT_E_ARG, "pdd: px, py must be 1..64");
+  if (g.cx < 2 || g.cy < 2 || g.cx > kMaxCells || g.cy > kMaxCells) return set_error(BRT_E_ARG, "pdd: cx, cy must be 2..4096");
+  if (!(g.T > 0.0) || !std::isfinite(g.T)) return set_error(BRT_E_ARG, "pdd: T must be > 0");
+  if (g.n_steps < 1 || g.n_steps > (1u << 20)) return set_error(BRT_E_ARG, "pdd: n_steps must be 1..2^20");
+  if (g.ns_x < 4 || g.ns_y < 4 || g.ns_x > kMaxNodesPerLine || g.ns_y > kMaxNodesPerLine)
+    return set_error(BRT_E_ARG, "pdd: ns_x, ns_y must be 4..257");
+  if (g.nt < 3 || g.nt > kMaxNt) return set_error(BRT_E_ARG, "pdd: nt must be 3..63");
+  if (g.outer != BRT_PDD_OUTER_LINES && g.outer != BRT_PDD_OUTER_ZERO) return set_error(BRT_E_ARG, "pdd: unknown outer");
+  if (g.outer == BRT_PDD_OUTER_ZERO && g.px == 1 && g.py == 1)
+    return set_error(BRT_E_ARG, "pdd: no lines (one subdomain with zero outer edges)");
+
+  brt_pdd* p = new (std::nothrow) brt_pdd;
+  if (!p) return set_error(BRT_E_NOMEM, "pdd: host allocation");
+  p->ctx = ctx;
+  p->prob = *prob;
+  p->g = g;
+  p->NX = g.px * g.cx;
+  p->NY = g.py * g.cy;
+  p->hx = (g.x_hi - g.x_lo) / p->NX;
+  p->hy = (g.y_hi - g.y_lo) / p->NY;
+  p->dt = g.T / g.n_steps;
+  p->rx = prob->diffusion * p->dt / (p->hx * p->hx);
+  p->ry = prob->diffusion * p->dt / (p->hy * p->hy);
+  p->u0.kind = prob->u0_kind;
+  p->u0.nterms = prob->u0_nterms;
+  std::memcpy(p->u0.p, prob->u0_params, sizeof(p->u0.p));
+  for (auto& v : p->vline) v = -1;
+  for (auto& v : p->hline) v = -1;
+  const bool edges = g.outer == BRT_PDD_OUTER_LINES;
+  uint64_t node_off = 0, bd_off = 0;
+  for (int orient = 0; orient < 2; ++orient) {
+    const uint32_t parts = orient == 0 ? g.px : g.py;
+    for (uint32_t k = 0; k <= parts; ++k) {
+      if (!edges && (k == 0 || k == parts)) continue;
+      LineDev L{};
+      L.orient = (uint32_t)orient;
+      L.k = k;
+      if (orient == 0) {
+        L.c = g.x_lo + k * (g.x_hi - g.x_lo) / g.px;
+        L.n_fine = p->NY + 1;
+        L.ns = g.ns_y;
+        L.s_lo = g.y_lo;
+        L.hs = (g.y_hi - g.y_lo) / (g.ns_y - 1);
+        L.hf = p->hy;
+        p->vline[k] = (int16_t)p->lines.size();
+        p->n_vlines += 1;
+      } else {
+        L.c = g.y_lo + k * (g.y_hi - g.y_lo) / g.py;
+        L.n_fine = p->NX + 1;
+        L.ns = g.ns_x;
+        L.s_lo = g.x_lo;
+        L.hs = (g.x_hi - g.x_lo) / (g.ns_x - 1);
+        L.hf = p->hx;
+        p->hline[k] = (int16_t)p->lines.size();
+      }
+      L.node_off = node_off;
+      L.bd_off = bd_off;
+      node_off += (uint64_t)g.nt * L.ns;
+      bd_off += (uint64_t)(g.n_steps + 1) * L.n_fine;
+      p->lines.push_back(L);
+    }
+  }
+  p->n_nodes = node_off;
+  p->bd_doubles = bd_off;
+  p->max_ns = std::max(g.ns_x, g.ns_y);
+  p->max_fine = std::max(p->NX, p->NY) + 1;
+  const size_t field = (size_t)(p->NX + 1) * (p->NY + 1);
+  const double bytes = 8.0 * ((double)p->bd_doubles + 3.0 * (double)field);
+  if (bytes > 128e9) {
+    pdd_free(p);
+    return set_error(BRT_E_ARG, "pdd: grid needs %.1f GB of device memory (limit 128 GB)", bytes / 1e9);
+  }
+  int rc = BRT_OK;
+  auto dev_alloc = [&](void** ptr, size_t n) {
+    if (rc != BRT_OK) return;
+    if (hipMalloc(ptr, n) != hipSuccess) rc = set_error(BRT_E_NOMEM, "pdd: device allocation of %zu bytes", n);
+  };
+  if (hipGetDevice(&p->device) != hipSuccess) rc = set_error(BRT_E_DEVICE, "pdd: no device");
+  hipDeviceProp_t prop;
+  if (rc == BRT_OK && hipGetDeviceProperties(&prop, p->device) != hipSuccess) rc = set_error(BRT_E_DEVICE, "pdd: device query");
+  if (rc == BRT_OK) p->n_cu = prop.multiProcessorCount;
+  const uint32_t rows = g.nt + 1;
+  p->spl_rows = (size_t)p->lines.size() * rows * p->max_ns;
+  p->spl_fine = (size_t)rows * p->lines.size() * p->max_fine;
+  dev_alloc((void**)&p->d_lines, sizeof(LineDev) * p->lines.size());
+  dev_alloc((void**)&p->d_bd, 8 * p->bd_doubles);
+  for (double*& f : p->d_f) dev_alloc((void**)&f, 8 * field);
+  dev_alloc((void**)&p->d_fac, 8 * 2 * (size_t)(g.cx + g.cy));
+  dev_alloc((void**)&p->d_spl, 8 * (3 * p->spl_rows + 3 * p->spl_fine));
+  dev_alloc((void**)&p->d_sync, 4 * (3 + 2 * (size_t)g.n_steps));
+  dev_alloc((void**)&p->d_node_u, 8 * std::max<uint64_t>(p->n_nodes, 1));
+  for (hipEvent_t& e : p->ev)
+    if (rc == BRT_OK && hipEventCreate(&e) != hipSuccess) rc = set_error(BRT_E_DEVICE, "pdd: event creation");
+  if (rc == BRT_OK) {
+    std::vector<double> fac(2 * (size_t)(g.cx + g.cy));
+    thomas_factors(p->rx, g.cx - 1, fac.data(), fac.data() + g.cx);
+    thomas_factors(p->ry, g.cy - 1, fac.data() + 2 * g.cx, fac.data() + 2 * g.cx + g.cy);
+    if (hipMemcpy(p->d_fac, fac.data(), 8 * fac.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->d_lines, p->lines.data(), sizeof(LineDev) * p->lines.size(), hipMemcpyHostToDevice) != hipSuccess)
+      rc = set_error(BRT_E_DEVICE, "pdd: upload");
+  }
+  if (rc == BRT_OK) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&adi_kernel), kLanes, 0) !=
+            hipSuccess ||
+        per_cu < 1)
+      rc = set_error(BRT_E_DEVICE, "pdd: solver occupancy query");
+    const uint32_t nsub = g.px * g.py;
+    const uint32_t x_items = nsub * ((g.cy - 1 + kLanes - 1) / kLanes);
+    const uint32_t y_items = nsub * ((g.cx - 1 + kLanes - 1) / kLanes);
+    const uint64_t cap = (uint64_t)per_cu * p->n_cu;
+    p->grid = (int)std::min<uint64_t>({(uint64_t)std::max(x_items, y_items), 2ull * p->n_cu, cap});
+  }
+  if (rc != BRT_OK) {
+    pdd_free(p);
+    return rc;
+  }
+  *out = p;
+  return BRT_OK;
+}
+
+int brt_pdd_nodes(const brt_pdd* p, double* xy, double* t, uint64_t* n) {
+  if (!p || !n) return set_error(BRT_E_ARG, "brt_pdd_nodes: NULL argument");
+  *n = p->n_nodes;
+  uint64_t i = 0;
+  for (const LineDev& L : p->lines) {
+    for (uint32_t k = 1; k <= p->g.nt; ++k) {
+      const double tk = k * p->g.T / p->g.nt;
+      for (uint32_t s = 0; s < L.ns; ++s, ++i) {
+        const double pos = L.s_lo + s * L.hs;
+        if (xy) {
+          xy[2 * i] = L.orient == 0 ? L.c : pos;
+          xy[2 * i + 1] = L.orient == 0 ? pos : L.c;
+        }
+        if (t) t[i] = tk;
+      }
+    }
+  }
+  return BRT_OK;
+}
+
+int brt_pdd_lines(const brt_pdd* p, uint32_t* n_lines, uint32_t* orient, double* coord, uint32_t* n_fine) {
+  if (!p || !n_lines) return set_error(BRT_E_ARG, "brt_pdd_lines: NULL argument");
+  *n_lines = (uint32_t)p->lines.size();
+  for (size_t l = 0; l < p->lines.size(); ++l) {
+    if (orient) orient[l] = p->lines[l].orient;
+    if (coord) coord[l] = p->lines[l].c;
+    if (n_fine) n_fine[l] = p->lines[l].n_fine;
+  }
+  return BRT_OK;
+}
+
+int brt_pdd_interpolate(brt_pdd* p, const double* node_values, void* stream) {
+  if (!p || !node_values) return set_error(BRT_E_ARG, "brt_pdd_interpolate: NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  SplineArgs a{};
+  a.lines = p->d_lines;
+  a.n_lines = (uint32_t)p->lines.size();
+  a.rows = p->g.nt + 1;
+  a.max_ns = p->max_ns;
+  a.max_fine = p->max_fine;
+  a.node_values = node_values;
+  a.vals = p->d_spl;
+  a.mom = a.vals + p->spl_rows;
+  a.cp = a.mom + p->spl_rows;
+  a.rowsv = a.cp + p->spl_rows;
+  a.tmom = a.rowsv + p->spl_fine;
+  a.tcp = a.tmom + p->spl_fine;
+  a.bd = p->d_bd;
+  a.ht = p->g.T / p->g.nt;
+  a.dt = p->dt;
+  a.n_steps = p->g.n_steps;
+  a.u0 = p->u0;
+  PDD_TRY(hipEventRecord(p->ev[2], s));
+  const uint32_t nr = a.n_lines * a.rows;
+  spline_rows_kernel<<<(nr + 63) / 64, 64, 0, s>>>(a);
+  PDD_TRY(hipGetLastError());
+  spline_s_kernel<<<dim3((p->max_fine + 255) / 256, nr), 256, 0, s>>>(a);
+  PDD_TRY(hipGetLastError());
+  spline_t_kernel<<<dim3((p->max_fine + 255) / 256, a.n_lines), 256, 0, s>>>(a);
+  PDD_TRY(hipGetLastError());
+  PDD_TRY(hipEventRecord(p->ev[3], s));
+  p->recorded[1] = true;
+  return BRT_OK;
+}
+
+int brt_pdd_boundary(const brt_pdd* p, uint32_t line, double* dst, void* stream) {
+  if (!p || !dst) return set_error(BRT_E_ARG, "brt_pdd_boundary: NULL argument");
+  if (line >= p->lines.size()) return set_error(BRT_E_ARG, "brt_pdd_boundary: no line %u", line);
+  const LineDev& L = p->lines[line];
+  PDD_TRY(hipMemcpyAsync(dst, p->d_bd + L.bd_off, 8 * (size_t)(p->g.n_steps + 1) * L.n_fine, hipMemcpyDeviceToDevice,
+                         (hipStream_t)stream));
+  return BRT_OK;
+}
+
+int brt_pdd_solve(brt_pdd* p, uint32_t steps, double* field, void* stream) {
+  if (!p || !field) return set_error(BRT_E_ARG, "brt_pdd_solve: NULL argument");
+  if (steps < 1 || steps > p->g.n_steps) return set_error(BRT_E_ARG, "brt_pdd_solve: steps must be 1..%u", p->g.n_steps);
+  hipStream_t s = (hipStream_t)stream;
+  const brt_pdd_grid& g = p->g;
+  PDD_TRY(hipEventRecord(p->ev[4], s));
+  FieldArgs fa{};
+  fa.f0 = p->d_f[0];
+  fa.f1 = p->d_f[1];
+  fa.bd = p->d_bd;
+  fa.lines = p->d_lines;
+  fa.NX = p->NX;
+  fa.NY = p->NY;
+  fa.cx = g.cx;
+  fa.cy = g.cy;
+  fa.zero_outer = g.outer == BRT_PDD_OUTER_ZERO;
+  fa.x_lo = g.x_lo;
+  fa.y_lo = g.y_lo;
+  fa.hx = p->hx;
+  fa.hy = p->hy;
+  std::memcpy(fa.vline, p->vline, sizeof(fa.vline));
+  std::memcpy(fa.hline, p->hline, sizeof(fa.hline));
+  fa.u0 = p->u0;
+  const uint64_t n_field = (uint64_t)(p->NX + 1) * (p->NY + 1);
+  init_field_kernel<<<(unsigned)((n_field + 255) / 256), 256, 0, s>>>(fa);
+  PDD_TRY(hipGetLastError());
+  PDD_TRY(hipMemsetAsync(p->d_sync, 0, 4 * (3 + 2 * (size_t)steps), s));
+
+  AdiArgs a{};
+  a.f0 = p->d_f[0];
+  a.f1 = p->d_f[1];
+  a.star = p->d_f[2];
+  a.bd = p->d_bd;
+  a.lines = p->d_lines;
+  a.inv_x = p->d_fac;
+  a.cp_x = p->d_fac + g.cx;
+  a.inv_y = p->d_fac + 2 * g.cx;
+  a.cp_y = p->d_fac + 2 * g.cx + g.cy;
+  a.sync = p->d_sync;
+  int rate_khz = 0;
+  PDD_TRY(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, p->device));
+  a.spin_limit = (uint64_t)(kBarrierSeconds * 1e3 * (rate_khz > 0 ? rate_khz : 100000));
+  for (int j = 0; j < 8; ++j) a.coef[j] = p->prob.coef[j];
+  a.rx2 = 0.5 * p->rx;
+  a.ry2 = 0.5 * p->ry;
+  a.dt2 = 0.5 * p->dt;
+  a.W = p->NX + 1;
+  a.px = g.px;
+  a.py = g.py;
+  a.cx = g.cx;
+  a.cy = g.cy;
+  a.steps = steps;
+  a.nblocks = (uint32_t)p->grid;
+  a.x_blk = (g.cy - 1 + kLanes - 1) / kLanes;
+  a.y_blk = (g.cx - 1 + kLanes - 1) / kLanes;
+  a.n_vlines = p->n_vlines;
+  a.bv = (p->NY + 1 + kLanes - 1) / kLanes;
+  a.bh = (p->NX + 1 + kLanes - 1) / kLanes;
+  a.n_lines = (uint32_t)p->lines.size();
+  std::memcpy(a.vline, p->vline, sizeof(a.vline));
+  std::memcpy(a.hline, p->hline, sizeof(a.hline));
+  void* kargs[] = {&a};
+  PDD_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&adi_kernel), dim3(p->grid), dim3(kLanes), kargs, 0, s));
+  const double* result = (steps & 1) ? p->d_f[1] : p->d_f[0];
+  PDD_TRY(hipMemcpyAsync(field, result, 8 * (size_t)(p->NX + 1) * (p->NY + 1), hipMemcpyDeviceToDevice, s));
+  PDD_TRY(hipEventRecord(p->ev[5], s));
+  p->recorded[2] = true;
+  return BRT_OK;
+}
+
+int brt_pdd_run(brt_pdd* p, const brt_mc* mc, uint64_t trees_per_node, double* node_u, double* field, void* stream) {
+  if (!p || !mc || !field) return set_error(BRT_E_ARG, "brt_pdd_run: NULL argument");
+  if (mc->struct_size != sizeof(brt_mc)) return set_error(BRT_E_ARG, "brt_mc.struct_size mismatch");
+  if (trees_per_node < 1 || trees_per_node > 0xffffffffull) return set_error(BRT_E_ARG, "brt_pdd_run: trees_per_node must be 1..2^32-1");
+  hipStream_t s = (hipStream_t)stream;
+  if (p->plan && (std::memcmp(&p->plan_mc, mc, sizeof(brt_mc)) != 0 || p->plan_trees != trees_per_node)) {
+    brt_plan_destroy(p->plan);
+    p->plan = nullptr;
+  }
+  if (!p->plan) {
+    std::vector<double> xy(2 * p->n_nodes), t(p->n_nodes);
+    std::vector<uint64_t> nt(p->n_nodes, trees_per_node);
+    uint64_t n = 0;
+    brt_pdd_nodes(p, xy.data(), t.data(), &n);
+    brt_points pts{};
+    pts.struct_size = sizeof(pts);
+    pts.n = (uint32_t)n;
+    pts.x = xy.data();
+    pts.t = t.data();
+    pts.n_trees = nt.data();
+    const int rc = brt_plan_create(p->ctx, 1, &p->prob, mc, &pts, &p->plan);
+    if (rc != BRT_OK) {
+      p->plan = nullptr;
+      return rc;
+    }
+    p->plan_mc = *mc;
+    p->plan_trees = trees_per_node;
+  }
+  double* u = node_u ? node_u : p->d_node_u;
+  brt_out o{};
+  o.struct_size = sizeof(o);
+  o.u = u;
+  PDD_TRY(hipEventRecord(p->ev[0], s));
+  int rc = brt_plan_execute(p->plan, &o, stream);
+  if (rc != BRT_OK) return rc;
+  PDD_TRY(hipEventRecord(p->ev[1], s));
+  p->recorded[0] = true;
+  rc = brt_pdd_interpolate(p, u, stream);
+  if (rc != BRT_OK) return rc;
+  return brt_pdd_solve(p, p->g.n_steps, field, stream);
+}
+
+int brt_pdd_get_timing(brt_pdd* p, double* ms) {
+  if (!p || !ms) return set_error(BRT_E_ARG, "brt_pdd_get_timing: NULL argument");
+  for (int k = 0; k < 3; ++k) {
+    ms[k] = 0.0;
+    if (!p->recorded[k]) continue;
+    PDD_TRY(hipEventSynchronize(p->ev[2 * k + 1]));
+    float v = 0.f;
+    PDD_TRY(hipEventElapsedTime(&v, p->ev[2 * k], p->ev[2 * k + 1]));
+    ms[k] = v;
+  }
+  p->recorded[0] = false;
+  uint32_t abort_word = 0;
+  PDD_TRY(hipMemcpy(&abort_word, p->d_sync + 2, 4, hipMemcpyDeviceToHost));
+  if (abort_word) return set_error(BRT_E_DEVICE, "pdd: the solver's grid barrier timed out");
+  return BRT_OK;
+}
+
+void brt_pdd_destroy(brt_pdd* p) { pdd_free(p); }
+
+}  // extern "C"

@@ -1,0 +1,168 @@
+"""Domain-decomposition tail on the GPU against the oracle (needs an MI355X).
+
+Node values given to both sides are synthetic (seeded) or computed by each side's own Monte Carlo;
+nothing the GPU computes is fed to the oracle.  Tolerances: the spline and the solver are FP64 with the
+same operations in a different order (Thomas recurrence vs banded LU, fused multiply-adds), so
+boundary data agree to 1e-12 and fields to 1e-11 of their largest magnitude.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import pdd as opdd
+from paper_2402_06491_amd import inputs
+
+from . import _parity as P
+
+pytestmark = pytest.mark.gpu
+
+BD_TOL = 1e-12
+FIELD_TOL = 1e-11
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    assert torch.cuda.is_available(), "no GPU"
+    import paper_2402_06491_amd as brt
+
+    c = brt.Context(0)
+    yield c
+    c.close()
+
+
+def _announce(name, grid):
+    print(f"\n[case] {name}: px={grid['px']} py={grid['py']} cx={grid['cx']} cy={grid['cy']} "
+          f"steps={grid['n_steps']} ns={grid['ns_x']}x{grid['ns_y']} nt={grid['nt']} outer={grid['outer']}",
+          flush=True)
+
+
+def _grid(**kw):
+    g = {"x_lo": -4.0, "x_hi": 4.0, "y_lo": -4.0, "y_hi": 4.0, "px": 2, "py": 2, "cx": 16, "cy": 16, "T": 0.5,
+         "n_steps": 40, "ns_x": 9, "ns_y": 9, "nt": 4, "outer": "mc"}
+    g.update(kw)
+    return g
+
+
+def _cubic(seed=0):
+    return inputs.problem(2, 1.0, [0.0, 1.0, 0.0, -1.0], inputs.cubic_2d_u0(seed))
+
+
+def _tail_parity(ctx, name, problem, grid, node_values, steps=None):
+    import torch
+
+    import paper_2402_06491_amd as brt
+
+    _announce(name, grid)
+    og = opdd.Grid(**grid)
+    pd = brt.Pdd(ctx, problem, grid)
+    try:
+        xy, t = pd.nodes()
+        oxy, ot = opdd.node_points(og)
+        np.testing.assert_array_equal(xy, oxy)
+        np.testing.assert_array_equal(t, ot)
+        o, c, f = pd.lines()
+        assert [(int(a), float(b)) for a, b in zip(o, c)] == [(0 if s == "v" else 1, cc) for s, _, cc in og.lines()]
+        pd.interpolate(torch.tensor(node_values, dtype=torch.float64, device="cuda"))
+        obd = opdd.boundary_data(og, problem, node_values)
+        scale = max(float(np.abs(v).max()) for v in obd.values())
+        for li in range(len(o)):
+            gb = pd.boundary(li).cpu().numpy()
+            np.testing.assert_allclose(gb, obd[li], rtol=0, atol=BD_TOL * scale, err_msg=f"line {li}")
+        steps = grid["n_steps"] if steps is None else steps
+        field = pd.solve(steps).cpu().numpy()
+        ms = pd.timing()
+        ofield = opdd.adi_solve(og, problem, obd, n_steps=steps)
+        err = float(np.abs(field - ofield).max())
+        print(f"[case] {name}: max |dU| {err:.3e} of max |U| {np.abs(ofield).max():.3e}; "
+              f"interp {ms[1]:.3f} ms, solve {ms[2]:.3f} ms", flush=True)
+        np.testing.assert_allclose(field, ofield, rtol=0, atol=FIELD_TOL * max(1.0, float(np.abs(ofield).max())))
+        return field, ofield
+    finally:
+        pd.close()
+
+
+def test_tail_small_synthetic_nodes(ctx):
+    grid = _grid()
+    og = opdd.Grid(**grid)
+    rng = np.random.default_rng(11)
+    xy, t = opdd.node_points(og)
+    vals = 0.5 * np.exp(-(xy[:, 0] ** 2 + xy[:, 1] ** 2) / 8.0) * (1 + t) + 0.01 * rng.normal(size=len(t))
+    _tail_parity(ctx, "tail_small_synthetic", _cubic(), grid, vals)
+
+
+def test_tail_ragged_zero_outer_fisher(ctx):
+    """3 x 2 subdomains of 20 x 70 cells (x blocks ragged against 64 lanes, y items span two blocks),
+    outer edges held at zero, Fisher reaction, logistic initial data."""
+    grid = _grid(x_lo=-6.0, x_hi=6.0, px=3, py=2, cx=20, cy=70, n_steps=30, ns_x=13, ns_y=5, nt=3, outer="zero",
+                 T=0.3)
+    prob = inputs.problem(2, 1.0, [0.0, 1.0, -1.0], inputs.logistic(1.0, 1.0 / math.sqrt(6.0), 0.0, 2,
+                                                                  (math.cos(0.4), math.sin(0.4))))
+    og = opdd.Grid(**grid)
+    xy, t = opdd.node_points(og)
+    vals = opdd.fisher_plane_wave(0.4)(xy[:, 0], xy[:, 1], t)
+    _tail_parity(ctx, "tail_ragged_zero_outer", prob, grid, vals)
+
+
+def test_tail_single_subdomain_and_cos2(ctx):
+    grid = _grid(px=1, py=1, cx=37, cy=29, n_steps=25, ns_x=4, ns_y=6, nt=5)
+    prob = inputs.problem(2, 0.5, [0.1, -0.3, 0.0, -0.2], {"u0_kind": "cos2_bump", "u0_params": [-2.0, 3.0, 3.5],
+                                                               "u0_nterms": 0})
+    og = opdd.Grid(**grid)
+    rng = np.random.default_rng(3)
+    vals = rng.uniform(-0.1, 0.1, size=len(opdd.node_points(og)[1]))
+    _tail_parity(ctx, "tail_single_cos2", prob, grid, vals)
+
+
+def test_tail_full_size_first_steps(ctx):
+    """The decomposition of the 2-D cubic workload at its full size (4 x 4 subdomains of 512^2 cells,
+    264 nodes per line on 10 lines, 1000 steps of boundary data), solved through its first 100 steps."""
+    wl = inputs.pdd_cubic_2d()
+    grid = wl["grid"]
+    og = opdd.Grid(**grid)
+    xy, t = opdd.node_points(og)
+    # stand-in node values: u0 carried along by the heat kernel's widening (smooth, the workload's scale)
+    vals = opdd.g_grid(wl["problem"], xy[:, 0], xy[:, 1]) * np.exp(-0.3 * t)
+    _tail_parity(ctx, "tail_full_size_100_steps", wl["problem"], grid, vals, steps=100)
+
+
+def test_pdd_end_to_end_against_oracle_monte_carlo(ctx):
+    """Monte Carlo at the nodes (FP64 paths) then the tail, against the oracle's own Monte Carlo values
+    fed to the oracle's tail.  The node values agree to the Pade parity bound; the fields then agree to
+    a small multiple of the largest node difference (interpolation and the solve do not amplify it)."""
+    import torch
+
+    import paper_2402_06491_amd as brt
+
+    grid = _grid(cx=32, cy=32, n_steps=50)
+    prob = _cubic(seed=2)
+    mc = inputs.mc_params(seed=5, max_order=12, prune=1, node_cap=1 << 16, precision=64)
+    n_trees = 2000
+    _announce("pdd_end_to_end", grid)
+    og = opdd.Grid(**grid)
+    xy, t = opdd.node_points(og)
+    n = len(t)
+    wl = {"problems": [prob], "mc": mc, "x": xy, "t": t, "n_trees": np.full(n, n_trees, np.int64)}
+    pi, ti, _ = P.tree_items(wl)
+    orc = P.oracle_trees(wl, pi, ti)
+    omom = P.oracle_moments(wl, orc, pi)
+    opade = P.oracle_pade(wl, omom)
+    onode = np.array([r["pade"] for r in opade])
+    pd = brt.Pdd(ctx, prob, grid)
+    try:
+        node_u = torch.empty(n, dtype=torch.float64, device="cuda")
+        field = pd.run(mc, n_trees, node_u=node_u).cpu().numpy()
+        ms = pd.timing()
+        gnode = node_u.cpu().numpy()
+    finally:
+        pd.close()
+    dnode = float(np.abs(gnode - onode).max())
+    assert dnode <= 1e-9 * max(1.0, float(np.abs(onode).max())), dnode
+    ofield = opdd.pdd_solve(og, prob, onode)
+    dfield = float(np.abs(field - ofield).max())
+    print(f"[case] pdd_end_to_end: max |d node| {dnode:.3e}, max |dU| {dfield:.3e}; MC {ms[0]:.2f} ms, "
+          f"interp {ms[1]:.3f} ms, solve {ms[2]:.3f} ms", flush=True)
+    assert dfield <= 4.0 * dnode + FIELD_TOL * max(1.0, float(np.abs(ofield).max()))
