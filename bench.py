@@ -41,8 +41,8 @@ METRIC = "random trees/sec at fixed error vs oracle; p50/p99 point-query latency
 # products: 12) or a leaf (initial data: about 9 for the logistic families), counted as 10 on average.
 OPS_PER_NODE = {1: 114, 2: 116}
 # FP32 vector peak of MI355X expressed in operations: 157.3 TFLOP/s counts an FMA as 2 flops, i.e.
-# 78.6 T lane-operations/s with packed FP32 (256 CUs x 4 SIMDs x 16 lanes x 2 x 2.4 GHz); plain
-# (non-packed) VALU issue is half of that, 39.3 T/s.
+# 78.6 T lane-operations/s (256 CUs x 4 SIMDs x 32 lanes per cycle x 2.4 GHz).  Plain, non-packed VALU
+# code reaches it: a microbenchmark of independent FMA chains measured 62.6 T FMA/s on the box.
 PEAK_TOPS = 78.6
 
 
@@ -194,6 +194,55 @@ def serve_bench(ctx, duration, rate, opts):
     return out
 
 
+def pdd_bench(ctx, trees_per_node, cpu_steps):
+    """The domain-decomposition tail of the 2-D cubic workload: Monte Carlo at the 2640 line nodes,
+    spline interpolation, 1000 ADI steps on 4 x 4 subdomains of 512^2 cells.  Reports stage times and
+    the ADI kernel's rate against HBM (40 algorithmic bytes per interior point and step: u^n and
+    u^{n-1} read, u^{n+1} written, the intermediate level written and read back)."""
+    import torch
+
+    import paper_2402_06491_amd as brt
+    from paper_2402_06491_amd import inputs
+
+    wl = inputs.pdd_cubic_2d(n_trees=trees_per_node)
+    g = wl["grid"]
+    pd = brt.Pdd(ctx, wl["problem"], g)
+    xy, t = pd.nodes()
+    node_u = torch.empty(len(t), dtype=torch.float64, device="cuda")
+    field = torch.empty((pd.NY + 1, pd.NX + 1), dtype=torch.float64, device="cuda")
+    times = []
+    for rep in range(3):  # the first run builds the nodes' plan and captures its graph
+        pd.run(wl["mc"], trees_per_node, node_u=node_u, field=field)
+        times.append(pd.timing())
+    mc_ms, int_ms, solve_ms = (min(x[k] for x in times[1:]) for k in range(3))
+    interior = g["px"] * g["py"] * (g["cx"] - 1) * (g["cy"] - 1)
+    alg_bytes = 40.0 * interior * g["n_steps"]
+    achieved = alg_bytes / (solve_ms * 1e-3) / 1e9
+    u = field.cpu().numpy()
+    res = {"workload": wl["name"], "nodes": int(len(t)), "trees_per_node": int(trees_per_node),
+           "grid": {k: g[k] for k in ("px", "py", "cx", "cy", "n_steps", "ns_x", "nt")},
+           "mc_ms": mc_ms, "interp_ms": int_ms, "solve_ms": solve_ms,
+           "adi_us_per_step": solve_ms * 1e3 / g["n_steps"],
+           "adi_roofline": {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
+                            "frac": achieved / 8000.0, "algorithmic_bytes": alg_bytes, "traffic": None},
+           "field_finite": bool(np.isfinite(u).all()), "field_max": float(np.abs(u).max())}
+    pd.close()
+    if cpu_steps > 0:
+        from oracle import pdd as opdd
+
+        og = opdd.Grid(**g)
+        vals = opdd.g_grid(wl["problem"], xy[:, 0], xy[:, 1])  # stand-in node values: timing only
+        bd = opdd.boundary_data(og, wl["problem"], vals)
+        t0 = time.perf_counter()
+        opdd.adi_solve(og, wl["problem"], bd, n_steps=cpu_steps)
+        dt = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": dt * 1e3 / cpu_steps, "unit": "ms/step", "kind": "oracle",
+                               "cores": 1, "sample": f"first {cpu_steps} ADI steps of the same grid (numpy/LAPACK)"}
+    log(f"pdd tail: MC {mc_ms:.2f} ms, interpolation {int_ms:.3f} ms, {g['n_steps']} ADI steps {solve_ms:.2f} ms "
+        f"({achieved:.0f} GB/s algorithmic)")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -206,6 +255,9 @@ def main():
                     help="length of the served request stream replayed after the throughput steps (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-max-trees", type=int, default=1 << 18)
+    ap.add_argument("--pdd-trees", type=int, default=100_000,
+                    help="trees per node of the domain-decomposition tail run after the steps (0: skip)")
+    ap.add_argument("--pdd-cpu-steps", type=int, default=5)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
@@ -301,6 +353,8 @@ def main():
                                         {"max_points": 8192, "round_trees": 16384,
                                          "max_trees": args.serve_max_trees, "target_se": 1e-3,
                                          "queue_cap": 100_000})
+    if args.pdd_trees > 0:
+        result["pdd"] = pdd_bench(ctx, args.pdd_trees, args.pdd_cpu_steps)
     ctx.close()
     print(json.dumps(result), flush=True)
 

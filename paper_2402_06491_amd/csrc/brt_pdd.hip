@@ -323,60 +323,245 @@ __device__ inline double hline_value(const AdiArgs& a, uint32_t ky, uint32_t x, 
   return a.bd[L.bd_off + (size_t)n * L.n_fine + x];
 }
 
-__device__ void x_sweep(const AdiArgs& a, uint32_t item, uint32_t n, const double* cur, const double* prev) {
+// A work item is kLines lines of one subdomain.  The sweeps go through the lines in tiles of 64
+// positions.  A tile's right-hand sides are formed first from global loads issued together (all 64
+// lanes: along the positions in the x phase; 16 lines x 4 position groups in the y phase) into an LDS
+// tile; the Thomas recurrence then runs from LDS, one lane per line; the tile goes back to global
+// memory with all lanes.  The forward pass leaves d' in the output field; the backward pass reads it
+// back tile by tile in reverse order.  Many short items keep enough waves in flight to cover the
+// memory latency the recurrences cannot hide themselves.
+constexpr int kLines = 16;
+constexpr int kTile = 64;
+constexpr int kGroups = kLanes / kLines;  // position groups of the y phase
+constexpr int kXPitch = kTile + 1;        // x phase LDS tile [line][position]
+constexpr int kYPitch = kLines + 1;       // y phase LDS tile [position][line]
+constexpr int kLdsDoubles = kLines * kXPitch > kTile * kYPitch ? kLines * kXPitch : kTile * kYPitch;
+
+// Work items run in single-wave blocks: LDS accesses of one wavefront are performed in order, so a
+// wavefront-scope fence (which also keeps the compiler from moving LDS accesses across it) replaces
+// a workgroup barrier, and no wait on outstanding global stores is forced between tiles.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+constexpr int kChain = 16;  // recurrence steps whose operands are loaded together
+
+// Forward Thomas recurrence over positions [p0, p0 + np) of one line whose right-hand sides sit in LDS
+// at D[off + c * stride]; d' replaces them.  Operands are fetched kChain at a time before use.
+__device__ inline double chain_forward(double* __restrict__ D, uint32_t off, uint32_t stride, uint32_t p0, uint32_t np,
+                                       const double* __restrict__ F, double r2, double dp) {
+  for (uint32_t cb = 0; cb < np; cb += kChain) {
+    double dv[kChain], fv[kChain];
+#pragma unroll
+    for (int k = 0; k < kChain; ++k) {
+      const uint32_t c = min(cb + k, np - 1);
+      dv[k] = D[off + c * stride];
+      fv[k] = F[c];
+    }
+#pragma unroll
+    for (int k = 0; k < kChain; ++k) {  // fully unrolled: steps past the tile's end keep dp
+      const double nd = (p0 + cb + k == 0 ? dv[k] : dv[k] + r2 * dp) * fv[k];
+      dp = cb + k < np ? nd : dp;
+      dv[k] = nd;
+    }
+#pragma unroll
+    for (int k = 0; k < kChain; ++k)
+      if (cb + k < np) D[off + (cb + k) * stride] = dv[k];
+  }
+  return dp;
+}
+
+// Backward substitution over positions [p0, p0 + np) in reverse; x of the last unknown (position m-1)
+// is its d'.
+__device__ inline double chain_backward(double* __restrict__ D, uint32_t off, uint32_t stride, uint32_t p0, uint32_t np,
+                                        uint32_t m, const double* __restrict__ F, double xv) {
+  for (int cb = (int)np - 1; cb >= 0; cb -= kChain) {
+    double dv[kChain], fv[kChain];
+#pragma unroll
+    for (int k = 0; k < kChain; ++k) {
+      const int c = max(cb - k, 0);
+      dv[k] = D[off + c * stride];
+      fv[k] = F[c];
+    }
+#pragma unroll
+    for (int k = 0; k < kChain; ++k) {  // fully unrolled: steps before the tile's start keep xv
+      const int ii = (int)p0 + cb - k;
+      const double nx = ii == (int)m - 1 ? dv[k] : dv[k] - fv[k] * xv;
+      xv = cb - k >= 0 ? nx : xv;
+      dv[k] = nx;
+    }
+#pragma unroll
+    for (int k = 0; k < kChain; ++k)
+      if (cb - k >= 0) D[off + (cb - k) * stride] = dv[k];
+  }
+  return xv;
+}
+
+__device__ void x_sweep(const AdiArgs& a, uint32_t item, uint32_t n, const double* __restrict__ cur,
+                        const double* __restrict__ prev, double* __restrict__ D, double* __restrict__ SB,
+                        double* __restrict__ FB) {
+  const uint32_t lane = threadIdx.x;
   const uint32_t sub = item / a.x_blk, blk = item % a.x_blk;
   const uint32_t sx = sub % a.px, sy = sub / a.px;
-  const uint32_t y = sy * a.cy + 1 + blk * kLanes + threadIdx.x;
-  if (y >= (sy + 1) * a.cy) return;
+  const uint32_t ybase = sy * a.cy + 1 + blk * kLines;
+  const uint32_t nrows = min((uint32_t)kLines, (sy + 1) * a.cy - ybase);  // lines of this item
   const uint32_t c0 = sx * a.cx, m = a.cx - 1, W = a.W;
-  const size_t base = (size_t)y * W;
-  const double usl = ustar_line(a, sx, y, n);
-  const double usr = ustar_line(a, sx + 1, y, n);
-  a.star[base + c0] = usl;
-  if (sx == a.px - 1) a.star[base + c0 + a.cx] = usr;
-  double dp = 0.0;
-  for (uint32_t i = 0; i < m; ++i) {
-    const size_t idx = base + c0 + 1 + i;
-    const double u = cur[idx];
-    const double F = reaction(a.coef, 1.5 * u - 0.5 * prev[idx]);
-    double d = u + a.ry2 * ((cur[idx - W] - 2.0 * u) + cur[idx + W]) + a.dt2 * F;
-    if (i == 0) d += a.rx2 * usl;
-    if (i == m - 1) d += a.rx2 * usr;
-    dp = (i == 0 ? d : d + a.rx2 * dp) * a.inv_x[i];
-    a.star[idx] = dp;
+  double* __restrict__ star = a.star;
+  // intermediate-level values on the two vertical lines, lane = line
+  if (lane < nrows) {
+    const uint32_t y = ybase + lane;
+    const double usl = ustar_line(a, sx, y, n);
+    const double usr = ustar_line(a, sx + 1, y, n);
+    SB[lane] = usl;
+    SB[kLines + lane] = usr;
+    star[(size_t)y * W + c0] = usl;
+    if (sx == a.px - 1) star[(size_t)y * W + c0 + a.cx] = usr;
   }
-  double xv = dp;
-  for (int i = (int)m - 2; i >= 0; --i) {
-    const size_t idx = base + c0 + 1 + i;
-    xv = a.star[idx] - a.cp_x[i] * xv;
-    a.star[idx] = xv;
+  wave_sync();
+  const uint32_t ntiles = (m + kTile - 1) / kTile;
+  double dp = 0.0;  // lane = line: running d' of the forward recurrence
+  for (uint32_t t = 0; t < ntiles; ++t) {
+    const uint32_t p0 = t * kTile, np = min((uint32_t)kTile, m - p0);
+    // right-hand sides: lane = position (clamped to a valid column), all rows of the item at once
+    const bool ok = lane < np;
+    const uint32_t i = p0 + min(lane, np - 1);
+    const size_t xcol = c0 + 1 + i;
+    FB[lane] = a.inv_x[i];
+    {
+      double cv[kLines + 2], pv[kLines];
+#pragma unroll
+      for (int k = 0; k < kLines + 2; ++k) cv[k] = cur[(size_t)min(ybase - 1 + k, ybase + nrows) * W + xcol];
+#pragma unroll
+      for (int k = 0; k < kLines; ++k) pv[k] = prev[(size_t)min(ybase + k, ybase + nrows - 1) * W + xcol];
+#pragma unroll
+      for (int k = 0; k < kLines; ++k) {
+        const double u = cv[k + 1];
+        const double F = reaction(a.coef, 1.5 * u - 0.5 * pv[k]);
+        double d = u + a.ry2 * ((cv[k] - 2.0 * u) + cv[k + 2]) + a.dt2 * F;
+        if (i == 0) d += a.rx2 * SB[k];
+        if (i == m - 1) d += a.rx2 * SB[kLines + k];
+        if (ok && k < (int)nrows) D[k * kXPitch + lane] = d;
+      }
+    }
+    wave_sync();
+    if (lane < nrows) dp = chain_forward(D, lane * kXPitch, 1, p0, np, FB, a.rx2, dp);
+    wave_sync();
+    if (ok)
+#pragma unroll
+      for (int k = 0; k < kLines; ++k)
+        if (k < (int)nrows) star[(size_t)(ybase + k) * W + xcol] = D[k * kXPitch + lane];
+    wave_sync();
+  }
+  double xv = 0.0;
+  for (int t = (int)ntiles - 1; t >= 0; --t) {
+    const uint32_t p0 = t * kTile, np = min((uint32_t)kTile, m - p0);
+    const bool ok = lane < np;
+    const size_t xcol = c0 + 1 + p0 + min(lane, np - 1);
+    FB[lane] = a.cp_x[p0 + min(lane, np - 1)];
+    if (t != (int)ntiles - 1) {  // the last tile's d' is still in LDS
+      double v[kLines];
+#pragma unroll
+      for (int k = 0; k < kLines; ++k) v[k] = star[(size_t)min(ybase + k, ybase + nrows - 1) * W + xcol];
+#pragma unroll
+      for (int k = 0; k < kLines; ++k)
+        if (ok && k < (int)nrows) D[k * kXPitch + lane] = v[k];
+      wave_sync();
+    }
+    wave_sync();
+    if (lane < nrows) xv = chain_backward(D, lane * kXPitch, 1, p0, np, m, FB, xv);
+    wave_sync();
+    if (ok)
+#pragma unroll
+      for (int k = 0; k < kLines; ++k)
+        if (k < (int)nrows) star[(size_t)(ybase + k) * W + xcol] = D[k * kXPitch + lane];
+    wave_sync();
   }
 }
 
-__device__ void y_sweep(const AdiArgs& a, uint32_t item, uint32_t n, const double* cur, double* next) {
+__device__ void y_sweep(const AdiArgs& a, uint32_t item, uint32_t n, const double* __restrict__ cur,
+                        double* __restrict__ next, double* __restrict__ D, double* __restrict__ FB) {
+  const uint32_t lane = threadIdx.x;
+  const uint32_t l = lane % kLines, q = lane / kLines;  // line, position group
   const uint32_t sub = item / a.y_blk, blk = item % a.y_blk;
   const uint32_t sx = sub % a.px, sy = sub / a.px;
-  const uint32_t x = sx * a.cx + 1 + blk * kLanes + threadIdx.x;
-  if (x >= (sx + 1) * a.cx) return;
+  const uint32_t xfirst = sx * a.cx + 1 + blk * kLines;
+  const uint32_t nl = min((uint32_t)kLines, (sx + 1) * a.cx - xfirst);
+  const bool ok = l < nl;
+  const uint32_t x = xfirst + min(l, nl - 1);
   const uint32_t r0 = sy * a.cy, m = a.cy - 1, W = a.W;
+  const double* __restrict__ star = a.star;
   const double gb0 = hline_value(a, sy, x, n + 1);
   const double gb1 = hline_value(a, sy + 1, x, n + 1);
+  const uint32_t ntiles = (m + kTile - 1) / kTile;
+  constexpr int kPer = kTile / kGroups;  // positions per lane in a tile
   double dp = 0.0;
-  for (uint32_t i = 0; i < m; ++i) {
-    const size_t idx = (size_t)(r0 + 1 + i) * W + x;
-    const double us = a.star[idx];
-    const double F = reaction(a.coef, 1.5 * cur[idx] - 0.5 * next[idx]);  // next still holds u^{n-1}
-    double d = us + a.rx2 * ((a.star[idx - 1] - 2.0 * us) + a.star[idx + 1]) + a.dt2 * F;
-    if (i == 0) d += a.ry2 * gb0;
-    if (i == m - 1) d += a.ry2 * gb1;
-    dp = (i == 0 ? d : d + a.ry2 * dp) * a.inv_y[i];
-    next[idx] = dp;
+  for (uint32_t t = 0; t < ntiles; ++t) {
+    const uint32_t p0 = t * kTile, np = min((uint32_t)kTile, m - p0);
+    FB[lane] = a.inv_y[p0 + min(lane, np - 1)];
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      double sl[kPer / 2], sc[kPer / 2], sr[kPer / 2], cu[kPer / 2], pr[kPer / 2];
+#pragma unroll
+      for (int k = 0; k < kPer / 2; ++k) {
+        const uint32_t p = q + kGroups * (half * (kPer / 2) + k);
+        const size_t idx = (size_t)(r0 + 1 + p0 + min(p, np - 1)) * W + x;
+        sl[k] = star[idx - 1];
+        sc[k] = star[idx];
+        sr[k] = star[idx + 1];
+        cu[k] = cur[idx];
+        pr[k] = next[idx];  // next still holds u^{n-1}
+      }
+#pragma unroll
+      for (int k = 0; k < kPer / 2; ++k) {
+        const uint32_t p = q + kGroups * (half * (kPer / 2) + k);
+        const uint32_t i = p0 + p;
+        const double F = reaction(a.coef, 1.5 * cu[k] - 0.5 * pr[k]);
+        double d = sc[k] + a.rx2 * ((sl[k] - 2.0 * sc[k]) + sr[k]) + a.dt2 * F;
+        if (i == 0) d += a.ry2 * gb0;
+        if (i == m - 1) d += a.ry2 * gb1;
+        if (p < np) D[p * kYPitch + l] = d;
+      }
+    }
+    wave_sync();
+    if (q == 0) dp = chain_forward(D, l, kYPitch, p0, np, FB, a.ry2, dp);
+    wave_sync();
+    if (ok)
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) {
+        const uint32_t p = q + kGroups * k;
+        if (p < np) next[(size_t)(r0 + 1 + p0 + p) * W + x] = D[p * kYPitch + l];
+      }
+    wave_sync();
   }
-  double xv = dp;
-  for (int i = (int)m - 2; i >= 0; --i) {
-    const size_t idx = (size_t)(r0 + 1 + i) * W + x;
-    xv = next[idx] - a.cp_y[i] * xv;
-    next[idx] = xv;
+  double xv = dp;  // broadcast below: only the q == 0 lanes hold the recurrence
+  for (int t = (int)ntiles - 1; t >= 0; --t) {
+    const uint32_t p0 = t * kTile, np = min((uint32_t)kTile, m - p0);
+    FB[lane] = a.cp_y[p0 + min(lane, (uint32_t)np - 1)];
+    if (t != (int)ntiles - 1) {  // the last tile's d' is still in LDS
+      double v[kPer];
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) {
+        const uint32_t p = q + kGroups * k;
+        v[k] = next[(size_t)(r0 + 1 + p0 + min(p, np - 1)) * W + x];
+      }
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) {
+        const uint32_t p = q + kGroups * k;
+        if (p < np) D[p * kYPitch + l] = v[k];
+      }
+      wave_sync();
+    }
+    wave_sync();
+    if (q == 0) xv = chain_backward(D, l, kYPitch, p0, np, m, FB, xv);
+    wave_sync();
+    if (ok)
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) {
+        const uint32_t p = q + kGroups * k;
+        if (p < np) next[(size_t)(r0 + 1 + p0 + p) * W + x] = D[p * kYPitch + l];
+      }
+    wave_sync();
   }
 }
 
@@ -405,6 +590,9 @@ __device__ void write_lines(const AdiArgs& a, uint32_t item, uint32_t n, double*
 }
 
 __global__ __launch_bounds__(64) void adi_kernel(AdiArgs a) {
+  __shared__ double D[kLdsDoubles];
+  __shared__ double SB[2 * kLines];
+  __shared__ double FB[kTile];  // Thomas factors of the current tile
   uint32_t gen = 0;
   const uint32_t nsub = a.px * a.py;
   const uint32_t x_items = nsub * a.x_blk;
@@ -416,14 +604,14 @@ __global__ __launch_bounds__(64) void adi_kernel(AdiArgs a) {
     for (;;) {
       const uint32_t it = grab(&a.sync[3 + 2 * n]);
       if (it >= x_items) break;
-      x_sweep(a, it, n, cur, prev);
+      x_sweep(a, it, n, cur, prev, D, SB, FB);
     }
     if (!grid_barrier(a.sync, a.nblocks, gen, a.spin_limit)) return;
     for (;;) {
       const uint32_t it = grab(&a.sync[4 + 2 * n]);
       if (it >= y_items + l_items) break;
       if (it < y_items)
-        y_sweep(a, it, n, cur, prev);
+        y_sweep(a, it, n, cur, prev, D, FB);
       else
         write_lines(a, it - y_items, n, prev);
     }
@@ -618,10 +806,10 @@ int brt_pdd_create(brt_ctx* ctx, const brt_problem* prob, const brt_pdd_grid* gr
         per_cu < 1)
       rc = set_error(BRT_E_DEVICE, "pdd: solver occupancy query");
     const uint32_t nsub = g.px * g.py;
-    const uint32_t x_items = nsub * ((g.cy - 1 + kLanes - 1) / kLanes);
-    const uint32_t y_items = nsub * ((g.cx - 1 + kLanes - 1) / kLanes);
+    const uint32_t x_items = nsub * ((g.cy - 1 + kLines - 1) / kLines);
+    const uint32_t y_items = nsub * ((g.cx - 1 + kLines - 1) / kLines);
     const uint64_t cap = (uint64_t)per_cu * p->n_cu;
-    p->grid = (int)std::min<uint64_t>({(uint64_t)std::max(x_items, y_items), 2ull * p->n_cu, cap});
+    p->grid = (int)std::min<uint64_t>({(uint64_t)std::max(x_items, y_items), 4ull * p->n_cu, cap});
   }
   if (rc != BRT_OK) {
     pdd_free(p);
@@ -758,8 +946,8 @@ int brt_pdd_solve(brt_pdd* p, uint32_t steps, double* field, void* stream) {
   a.cy = g.cy;
   a.steps = steps;
   a.nblocks = (uint32_t)p->grid;
-  a.x_blk = (g.cy - 1 + kLanes - 1) / kLanes;
-  a.y_blk = (g.cx - 1 + kLanes - 1) / kLanes;
+  a.x_blk = (g.cy - 1 + kLines - 1) / kLines;
+  a.y_blk = (g.cx - 1 + kLines - 1) / kLines;
   a.n_vlines = p->n_vlines;
   a.bv = (p->NY + 1 + kLanes - 1) / kLanes;
   a.bh = (p->NX + 1 + kLanes - 1) / kLanes;
