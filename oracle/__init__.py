@@ -73,6 +73,11 @@ class _Problem(ctypes.Structure):
         ("strategy", ctypes.c_int32),
         ("Q", ctypes.c_uint64),
         ("q", ctypes.c_double),
+        ("cmod", ctypes.c_int32),
+        ("cmod_pow", ctypes.c_int32),
+        ("cmod_bx", ctypes.c_double),
+        ("cmod_by", ctypes.c_double),
+        ("cmod_t0", ctypes.c_double),
     ]
 
 
@@ -113,6 +118,7 @@ class Normalized:
     u0_nterms: int
     strategy: int = 0     # 0: Strategy A (Sec. 2.1), 1: Strategy B (Sec. 2.2)
     q: float = 1.0        # Strategy B: probability that a node is a leaf
+    cmod: tuple = None    # variable coefficients (bx, by, t0, pow): c_j exp(-bx x^2 - by y^2) (t + t0)^-pow
 
 
 def normalize(problem: dict, mc: dict) -> Normalized:
@@ -153,7 +159,17 @@ def normalize(problem: dict, mc: dict) -> Normalized:
         raise ValueError("logistic u0 takes (A, s, x0, pow, n0, n1)")
     return Normalized(dim=int(problem["dim"]), sigma=math.sqrt(2.0 * float(problem["diffusion"])),
                       lam=lam_eff, mu=mu, J=J, omega=omega, u0_kind=kind,
-                      u0_params=params, u0_nterms=nterms, strategy=strategy, q=q)
+                      u0_params=params, u0_nterms=nterms, strategy=strategy, q=q, cmod=cmod_of(problem))
+
+
+def cmod_of(problem: dict):
+    """(bx, by, t0, pow) of a problem with variable coefficients, else None."""
+    cm = problem.get("coef_mod")
+    if not cm:
+        return None
+    beta = list(cm.get("beta", (0.0, 0.0))) + [0.0]
+    by = float(beta[1]) if int(problem["dim"]) == 2 else 0.0
+    return (float(beta[0]), by, float(cm.get("t0", 0.0)), int(cm.get("pow", 0)))
 
 
 def strategy_of(mc: dict) -> int:
@@ -182,6 +198,9 @@ def _make_struct(nz: Normalized, mc: dict) -> _Problem:
     pb.prune = int(mc.get("prune", 1))
     pb.node_cap = int(mc.get("node_cap", 1 << 16))
     pb.strategy = nz.strategy
+    if nz.cmod:
+        pb.cmod = 1
+        pb.cmod_bx, pb.cmod_by, pb.cmod_t0, pb.cmod_pow = nz.cmod
     pb.q = nz.q
     pb.Q = int(math.floor(nz.q * 4294967296.0))
     return pb

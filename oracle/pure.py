@@ -53,6 +53,17 @@ def _g(kind, p, nterms, dim, x):
     raise ValueError(kind)
 
 
+def _cmod(nz, x, tau):
+    """Scale of the constant coefficients at a split at x with PDE time tau left (variable c_j(x, t))."""
+    cm = getattr(nz, "cmod", None)
+    if not cm:
+        return 1.0
+    bx, by, t0, pw = cm
+    e = bx * x[0] * x[0] + (by * x[1] * x[1] if len(x) > 1 else 0.0)
+    v = math.exp(-e)
+    return v / (tau + t0) if pw == 1 else v
+
+
 def walk_tree(nz, mc, x0, t, point_id, tree):
     """One tree with an explicit stack.  Returns (F, ne, nodes, flags).
 
@@ -97,7 +108,7 @@ def walk_tree(nz, mc, x0, t, point_id, tree):
                 return 0.0, ne, node, 1
             idx = (w[1] * K) >> 32
             alpha = nz.J[idx]
-            prod *= nz.omega[idx] * math.exp((alpha - 1) * nz.mu * tau2)
+            prod *= nz.omega[idx] * math.exp((alpha - 1) * nz.mu * tau2) * _cmod(nz, xs, tau2)
             if alpha == 0:
                 branch_done = True
             else:
@@ -152,7 +163,7 @@ def _walk_tree_b(nz, mc, x0, t, point_id, tree):
                 return 0.0, ne, node, 1
             idx = (w[1] * K) >> 32
             alpha = nz.J[idx]
-            prod *= tau * nz.omega[idx] * math.exp((alpha - 1) * nz.mu * tau2)
+            prod *= tau * nz.omega[idx] * math.exp((alpha - 1) * nz.mu * tau2) * _cmod(nz, xs, tau2)
             if alpha > 0:
                 if alpha > 1:
                     stack.append([(xs, tau2), alpha - 1])

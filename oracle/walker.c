@@ -76,6 +76,9 @@ typedef struct {
   int32_t strategy;   /* 0: Strategy A (exponential clock), 1: Strategy B (coin + uniform time) */
   uint64_t Q;         /* Strategy B: a node is a leaf iff w0 < Q = floor(q 2^32) */
   double q;           /* Strategy B: probability of a leaf */
+  int32_t cmod;       /* 1: c_j(x, t) = c_j exp(-bx x^2 - by y^2) (t + t0)^(-pow) */
+  int32_t cmod_pow;
+  double cmod_bx, cmod_by, cmod_t0;
 } or_problem;
 
 /* ---- Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) ------------------ */
@@ -151,6 +154,17 @@ typedef struct {
   double theta;
 } or_tree;
 
+/* Factor by which a split at position x with PDE time tau left scales its constant coefficient
+ * (variable coefficients c_j(x, t), evaluated where and when the tree splits). */
+static double or_cmod(const or_problem* pb, const double* x, double tau) {
+  if (!pb->cmod) return 1.0;
+  double e = pb->cmod_bx * x[0] * x[0];
+  if (pb->dim == 2) e += pb->cmod_by * x[1] * x[1];
+  double v = exp(-e);
+  if (pb->cmod_pow == 1) v /= tau + pb->cmod_t0;
+  return v;
+}
+
 /* Value of the subtree whose root starts at position x with lineage clock
  * product P and remaining PDE time tau. */
 static double or_visit(const or_problem* pb, or_tree* st, const double* x, double P, double tau) {
@@ -185,7 +199,7 @@ static double or_visit(const or_problem* pb, or_tree* st, const double* x, doubl
     }
     uint32_t idx = (uint32_t)(((uint64_t)w[1] * (uint64_t)pb->K) >> 32);
     int alpha = pb->J[idx];
-    double val = pb->omega[idx] * exp((double)(alpha - 1) * pb->mu * tau2);
+    double val = pb->omega[idx] * exp((double)(alpha - 1) * pb->mu * tau2) * or_cmod(pb, xs, tau2);
     for (int c = 0; c < alpha; c++) {
       double child = or_visit(pb, st, xs, Pn, tau2);
       if (st->flags) return 0.0;
@@ -239,7 +253,7 @@ static double or_visit_b(const or_problem* pb, or_tree* st, const double* x, dou
     }
     uint32_t idx = (uint32_t)(((uint64_t)w[1] * (uint64_t)pb->K) >> 32);
     int alpha = pb->J[idx];
-    double val = tau * pb->omega[idx] * exp((double)(alpha - 1) * pb->mu * tau2);
+    double val = tau * pb->omega[idx] * exp((double)(alpha - 1) * pb->mu * tau2) * or_cmod(pb, xs, tau2);
     for (int c = 0; c < alpha; c++) {
       double child = or_visit_b(pb, st, xs, tau2);
       if (st->flags) return 0.0;

@@ -43,10 +43,15 @@ def gauss_sum(terms):
     return {"u0_kind": "gauss_sum", "u0_params": params, "u0_nterms": len(terms)}
 
 
-def problem(dim, diffusion, coef, u0):
+def problem(dim, diffusion, coef, u0, coef_mod=None):
+    """coef_mod (optional): {"beta": (bx, by), "t0": t0, "pow": 0|1} makes every non-linear coefficient
+    c_j exp(-bx x^2 - by y^2) (t + t0)^(-pow)."""
     coef = [float(c) for c in coef] + [0.0] * (8 - len(coef))
     d = {"dim": int(dim), "diffusion": float(diffusion), "coef": coef}
     d.update(u0)
+    if coef_mod:
+        d["coef_mod"] = {"beta": [float(b) for b in coef_mod.get("beta", (0.0, 0.0))],
+                         "t0": float(coef_mod.get("t0", 0.0)), "pow": int(coef_mod.get("pow", 0))}
     return d
 
 
@@ -143,6 +148,19 @@ def pdd_cubic_2d(n_trees=100_000, cells=512, n_steps=1000, ns=33, nt=8, outer="m
     mc = mc_params(seed=0, max_order=12, prune=1, node_cap=1 << 16, precision=precision)
     return {"name": "pdd_cubic_2d", "problem": problem(2, 1.0, [0.0, 1.0, 0.0, -1.0], cubic_2d_u0(u0_seed)),
             "mc": mc, "grid": grid, "n_trees": int(n_trees)}
+
+
+def example5(n_trees=100_000, n_x=64, t=0.5, precision=32, strategy=0, q=0.5):
+    """A single non-linear term with a coefficient varying in space and time (the paper's Example 5):
+    u_t = Lap u - e^{-x^2} / (t + 0.1) u^2, u0 = e^{-x^2/4} / sqrt(4 pi).  Neither the data nor the
+    coefficient depend on y, so the solution does not either and the 2-D problem is the 1-D problem
+    u_t = u_xx - e^{-x^2} / (t + 0.1) u^2 exactly; it is posed in 1-D here.  64 points in [-6, 6] at t."""
+    prob = problem(1, 1.0, [0.0, 0.0, -1.0], gauss_sum([(1.0 / math.sqrt(4 * math.pi), 0.0, 0.0, math.sqrt(2.0))]),
+                   coef_mod={"beta": (1.0, 0.0), "t0": 0.1, "pow": 1})
+    x = np.linspace(-6.0, 6.0, n_x).reshape(-1, 1)
+    mc = mc_params(seed=0, max_order=12, prune=1, node_cap=1 << 16, precision=precision, strategy=strategy, q=q)
+    return {"name": "example5", "problems": [prob], "mc": mc, "x": x, "t": np.full(n_x, float(t)),
+            "n_trees": np.full(n_x, n_trees, np.int64), "problem_id": np.zeros(n_x, np.uint32)}
 
 
 def poly_batch(n_points=4096, n_min=10_000, n_max=1_000_000, seed=1234, precision=32):
