@@ -23,6 +23,9 @@ values into boundary data and solves the decoupled subdomain problems (Sec. 3, "
   with dxx, dyy the second differences.  Boundary nodes hold the interpolated data at every time
   level; the intermediate level's boundary values on the lines that bound the x-sweeps follow from
   adding the two half-steps:  u*_b = (I + ry/2 dyy) g^n / 2 + (I - ry/2 dyy) g^{n+1} / 2.
+  With variable coefficients c_j(x, t) = c_j exp(-bx x^2 - by y^2) (t + t0)^-pow the non-linear part of f
+  is taken at the node and at the mid-step time (n + 1/2) dt: F = c_1 u~ + (e^{-bx x^2} e^{-by y^2})
+  (t_mid + t0)^-pow sum_{j != 1} c_j u~^j.
 """
 from __future__ import annotations
 
@@ -305,8 +308,21 @@ def adi_solve(grid: Grid, problem, bd, U0=None, n_steps=None):
 
     abx = band(rx, grid.cx - 1)
     aby = band(ry, grid.cy - 1)
+    from oracle import cmod_of
+
+    cm = cmod_of(problem)
+    if cm:
+        bx, by, t0, pw = cm
+        exy = np.exp(-by * ys * ys)[:, None] * np.exp(-bx * xs * xs)[None, :]
+        pcoef = list(coef)
+        pcoef[1] = 0.0
     for n in range(n_steps):
-        F = f_poly(coef, 1.5 * U - 0.5 * Uold)
+        ut = 1.5 * U - 0.5 * Uold
+        if cm:
+            T = 1.0 / ((n + 0.5) * dt + t0) if pw == 1 else 1.0
+            F = coef[1] * ut + (exy * T) * f_poly(pcoef, ut)
+        else:
+            F = f_poly(coef, ut)
         Unew = np.zeros_like(U)
         _set_boundary(grid, Unew, bd, n + 1)
         # intermediate level: interior rows from the x-sweeps; on the vertical lines from the data

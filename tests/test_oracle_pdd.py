@@ -237,3 +237,41 @@ def test_adi_equals_factored_crank_nicolson(px, py):
                 Unew[ys, xs_] = sol.reshape(cy + 1, cx + 1)
         Uold, U = U, Unew
     np.testing.assert_allclose(got, U, rtol=0, atol=1e-12 * np.abs(U).max())
+
+
+def test_time_varying_coefficient_second_order():
+    """u_t = Lap u + c u^2/(t + t0) with constant data stays constant in space; the ADI then integrates the
+    ODE, whose solution is 1/(1/g0 - c ln(1 + t/t0)), at second order (the coefficient is taken at the
+    mid-step time)."""
+    g0, c, t0 = 0.7, -1.5, 0.1
+    prob = inputs.problem(2, 1.0, [0.0, 0.0, c], inputs.const(g0), coef_mod={"beta": (0.0, 0.0), "t0": t0, "pow": 1})
+
+    def fn(X, Y, t):
+        return np.full(np.broadcast(X, Y).shape, 1.0 / (1.0 / g0 - c * math.log(1.0 + t / t0)))
+    # 1/(t + t0) varies on the scale t0 = 0.1, so the asymptotic ratio 4 is reached from above
+    e = [_max_err(_grid(8, s, T=0.5), prob, fn) for s in (80, 160, 320)]
+    for a, b in zip(e, e[1:]):
+        assert 3.5 < a / b < 5.0, e
+
+
+def test_space_varying_coefficient_is_applied_at_the_node():
+    """beta_x > 0, beta_y = 0: against the constant coefficient, the damping u^2 term is weaker away from
+    x = 0, so the field grows there, more off-centre along x than along y (a coordinate mix-up would
+    reverse that), symmetrically in both axes."""
+    base = {"beta": (0.0, 0.0), "t0": 0.0, "pow": 0}
+    var = {"beta": (0.6, 0.0), "t0": 0.0, "pow": 0}
+    g = _grid(32, 20, px=1, py=1, T=0.4)  # one subdomain: the middle row is not a line
+    og = g
+    u0 = inputs.gauss_sum([(0.8, 0.0, 0.0, 1.5)])
+    p0 = inputs.problem(2, 1.0, [0.0, 0.0, -2.0], u0, coef_mod=base)
+    p1 = inputs.problem(2, 1.0, [0.0, 0.0, -2.0], u0, coef_mod=var)
+    xs, ys = pdd.grid_coords(og)
+    fn = lambda X, Y, t: np.zeros(np.broadcast(X, Y).shape)
+    bd = pdd.boundary_from_function(og, fn)
+    U0 = pdd.g_grid(p0, xs[None, :], ys[:, None])
+    d = pdd.adi_solve(og, p1, bd, U0=U0) - pdd.adi_solve(og, p0, bd, U0=U0)
+    i0, j0 = len(xs) // 2, len(ys) // 2
+    assert d.min() >= -1e-14
+    assert d[j0, i0 + 6] > 2.0 * d[j0 + 6, i0] > 1e-3
+    np.testing.assert_allclose(d, d[::-1, :], atol=1e-12)
+    np.testing.assert_allclose(d, d[:, ::-1], atol=1e-12)
