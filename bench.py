@@ -243,6 +243,44 @@ def pdd_bench(ctx, trees_per_node, cpu_steps):
     return res
 
 
+def strategy_compare(ctx, wl, ms_a, se_a, qs=(0.4, 0.5, 0.6, 0.7), reps=5):
+    """Strategy B (Sec. 2.2) on the same workload and trees, against Strategy A's step time and standard
+    errors: the efficiency ratio (time x SE^2 of A) / (time x SE^2 of B) compares the two at equal error
+    (the paper reports B 1.2-1.6x faster at equal maximum error)."""
+    import torch
+
+    import paper_2402_06491_amd as brt
+
+    stream = torch.cuda.current_stream()
+    rows = []
+    for q in qs:
+        mc = dict(wl["mc"], strategy=1, q=q)
+        plan = brt.Plan(ctx, wl["problems"], mc, wl["x"], wl["t"], wl["n_trees"],
+                        problem_id=wl.get("problem_id"), point_id=wl.get("point_id"))
+        out = plan.outputs(records=True)
+        plan.execute(out)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for _ in range(reps):
+            plan.execute(out)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        ms_b = ev[0].elapsed_time(ev[1]) / reps
+        se_b = out["se"].cpu().numpy()
+        ok = np.isfinite(se_a) & np.isfinite(se_b) & (se_b > 0) & (se_a > 0)
+        ratio = (ms_a * se_a[ok] ** 2) / (ms_b * se_b[ok] ** 2)
+        rows.append({"q": q, "ms_per_step": ms_b, "trees_per_s": float(np.sum(wl["n_trees"])) / (ms_b * 1e-3),
+                     "efficiency_vs_A_median": float(np.median(ratio)),
+                     "efficiency_vs_A_total": float(ms_a * np.sum(se_a[ok] ** 2) / (ms_b * np.sum(se_b[ok] ** 2)))})
+        log(f"strategy B q={q}: {ms_b:.3f} ms/step, efficiency vs A {rows[-1]['efficiency_vs_A_median']:.3f} (median), "
+            f"{rows[-1]['efficiency_vs_A_total']:.3f} (total)")
+        plan.close()
+        del out
+    return {"strategy_A_ms_per_step": ms_a, "strategy_B": rows,
+            "what": "efficiency = (time x SE^2 of A) / (time x SE^2 of B) per point, same trees per point"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -258,6 +296,7 @@ def main():
     ap.add_argument("--pdd-trees", type=int, default=100_000,
                     help="trees per node of the domain-decomposition tail run after the steps (0: skip)")
     ap.add_argument("--pdd-cpu-steps", type=int, default=5)
+    ap.add_argument("--no-strategy-b", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
@@ -346,8 +385,11 @@ def main():
         result["cpu_baseline"] = cb
         result["parity"] = parity
         log(f"cpu baseline {cb['value']:.4g} trees/s on {cb['cores']} threads; parity {parity}")
+    se_a = out["se"].cpu().numpy()
     plan.close()
     del out
+    if not args.no_strategy_b:
+        result["strategy_b"] = strategy_compare(ctx, wl, wall * 1e3 / args.steps, se_a)
     if args.serve_seconds > 0:
         result["serving"] = serve_bench(ctx, args.serve_seconds, args.serve_rate,
                                         {"max_points": 8192, "round_trees": 16384,

@@ -79,7 +79,19 @@ typedef struct brt_problem {
   uint32_t u0_kind;      /* BRT_U0_* */
   uint32_t u0_nterms;    /* BRT_U0_GAUSS_SUM: 1..8 */
   double u0_params[40];
+  /* Variable coefficients (Sec. 2's c_j(x, t); Example 5): with coef_mod = BRT_COEF_MOD_GAUSS_TIME every
+   * non-linear coefficient becomes c_j(x, t) = c_j exp(-beta_x x^2 - beta_y y^2) (t + t0)^(-coef_mod_pow),
+   * evaluated where and when a tree splits (the split position and the PDE time left after the split).
+   * The linear coefficient c_1 stays constant.  beta >= 0; coef_mod_pow is 0 or 1, and t0 > 0 when it is
+   * 1.  BRT_COEF_MOD_NONE (0) keeps every c_j constant. */
+  uint32_t coef_mod;
+  uint32_t coef_mod_pow;
+  double coef_mod_beta[2];
+  double coef_mod_t0;
 } brt_problem;
+
+#define BRT_COEF_MOD_NONE 0u
+#define BRT_COEF_MOD_GAUSS_TIME 1u
 
 /* Monte Carlo parameters shared by all points of one call. */
 typedef struct brt_mc {
@@ -210,7 +222,7 @@ int brt_solve(brt_ctx* ctx, uint32_t n_problems, const brt_problem* problems, co
               const brt_points* points, const brt_out* out, void* stream);
 
 /* Autotuner: time the tree walker for candidate launch settings (waves per block 1/2/4, LDS stack
- * levels 4..16, chunk sizes 256/1024/4096 trees) on a subsample (about 2^25 trees) of the given
+ * levels 4..16, chunk sizes 256/1024/4096 trees) on a subsample (about 2^26 trees, fastest of three runs) of the given
  * points, set the fastest on the context (used by plans and servers created afterwards) and write it
  * to *best (nullable).  cache_path (nullable) is a JSON-lines file keyed by the GPU architecture and
  * the workload shape (precision, dim, initial-data family, arities, order, pruning): a cached entry

@@ -32,7 +32,8 @@ class BrtError(RuntimeError):
 class Problem(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("dim", ctypes.c_uint32), ("diffusion", ctypes.c_double),
                 ("coef", ctypes.c_double * 8), ("u0_kind", ctypes.c_uint32), ("u0_nterms", ctypes.c_uint32),
-                ("u0_params", ctypes.c_double * 40)]
+                ("u0_params", ctypes.c_double * 40), ("coef_mod", ctypes.c_uint32), ("coef_mod_pow", ctypes.c_uint32),
+                ("coef_mod_beta", ctypes.c_double * 2), ("coef_mod_t0", ctypes.c_double)]
 
 
 class MC(ctypes.Structure):
@@ -176,6 +177,14 @@ def make_problem(d: dict) -> Problem:
     p.u0_nterms = int(d.get("u0_nterms", 0))
     for i, v in enumerate(d.get("u0_params", [])):
         p.u0_params[i] = float(v)
+    cm = d.get("coef_mod")
+    if cm:
+        p.coef_mod = 1
+        beta = list(cm.get("beta", (0.0, 0.0))) + [0.0]
+        p.coef_mod_beta[0] = float(beta[0])
+        p.coef_mod_beta[1] = float(beta[1])
+        p.coef_mod_pow = int(cm.get("pow", 0))
+        p.coef_mod_t0 = float(cm.get("t0", 0.0))
     return p
 
 

@@ -33,7 +33,10 @@ struct PdeT {
   uint32_t jpack;    // their powers, 4 bits each, ascending
   uint32_t u0_nterms;
   uint32_t q_lo;     // Strategy B: Q - 1 with Q = floor(q 2^32); a node is a leaf iff w0 <= q_lo
-  uint32_t pad;
+  uint32_t cmod;     // 0: constant coefficients; 1: c_j exp(-bx x^2 - by y^2) (tau + t0)^(-cm_pow)
+  uint32_t cm_pow;   // 0 or 1
+  uint32_t pad2;
+  Real cm_bx, cm_by, cm_t0;
   Real omega[8];     // Strategy A: K c_j / lambda; Strategy B: K c_j / (1 - q)
   Real u0[kMaxU0Params];
 };
@@ -95,6 +98,7 @@ struct WalkArgs {
   uint32_t prune;
   uint32_t node_cap;
   uint32_t strategy;         // 0: Strategy A, 1: Strategy B
+  uint32_t cmod;             // 1: some problem of the launch has variable coefficients
   uint32_t stack_depth;      // LDS levels per lane
   uint32_t spill_depth;      // global levels per lane
   uint32_t n_threads;        // grid size in threads (spill stride)

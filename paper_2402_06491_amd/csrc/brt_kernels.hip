@@ -220,11 +220,14 @@ struct Stack {
 
 // ------------------------------------------------------------------------------------------------
 // The walker.  MULTI: the plan has several problems (per-lane problem index); otherwise the
-// problem constants are loop invariants.  STRAT: 0 = Strategy A (Sec. 2.1), 1 = Strategy B
-// (Sec. 2.2).
+// problem constants are loop invariants.  MODE bit 0 (STRAT): Strategy A (0, Sec. 2.1) or B (1, Sec. 2.2);
+// bit 1 (CMOD): some problem of the launch has variable coefficients, so the variants for constant
+// coefficients carry no trace of them.
 // ------------------------------------------------------------------------------------------------
-template <typename Real, int DIM, int U0, bool MULTI, int STRAT>
+template <typename Real, int DIM, int U0, bool MULTI, int MODE>
 __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
+  constexpr int STRAT = MODE & 1;
+  constexpr bool CMOD = (MODE & 2) != 0;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
 
   // problem table -> LDS
@@ -389,10 +392,19 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
     const uint32_t idx = __umulhi(w.b, pd.K);
     const uint32_t alpha = (pd.jpack >> (4 * idx)) & 15u;
     Real earg = (Real)((int)alpha - 1) * pd.mu * tau2;
+    // variable coefficients: c_j exp(-bx x^2 - by y^2) (tau' + t0)^(-pow) at the split, folded into the
+    // vertex's exponential
+    Real cscale = (Real)1;
+    if constexpr (CMOD) {
+      if (pd.cmod) {
+        earg -= pd.cm_bx * (xn[0] * xn[0]) + (DIM == 2 ? pd.cm_by * (xn[1] * xn[1]) : (Real)0);
+        if (pd.cm_pow) cscale = (Real)1 / (tau2 + pd.cm_t0);
+      }
+    }
     if constexpr (U0 == 1) earg = vertex ? earg : logistic_arg<Real, DIM>(pd, xn);
     const Real E = Math<Real>::ex(earg);
     // Strategy B's vertex weight carries the time left tau (eta(t) = t) and its leaves divide by q
-    const Real wscale = STRAT == 1 ? tau : (Real)1;
+    const Real wscale = (STRAT == 1 ? tau : (Real)1) * cscale;
     const Real lscale = STRAT == 1 ? pd.inv_q : (Real)1;
     Real factor;
     if constexpr (U0 == 1) {
@@ -464,41 +476,54 @@ size_t walk_lds_bytes(int precision, int dim, int stack_depth, int waves_per_blo
   return pde_table_bytes<double>(n_problems) + sd * stack_entry_size(64, dim);
 }
 
-template <typename Real, int DIM, int U0, bool MULTI, int STRAT>
+template <typename Real, int DIM, int U0, bool MULTI, int MODE>
 static const void* walk_ptr() {
-  return reinterpret_cast<const void*>(&walk_kernel<Real, DIM, U0, MULTI, STRAT>);
+  return reinterpret_cast<const void*>(&walk_kernel<Real, DIM, U0, MULTI, MODE>);
 }
 
-template <typename Real, int DIM, bool MULTI, int STRAT>
+template <typename Real, int DIM, bool MULTI, int MODE>
 static const void* walk_ptr_u0(int u0) {
   switch (u0) {
-    case 0: return walk_ptr<Real, DIM, 0, MULTI, STRAT>();
-    case 1: return walk_ptr<Real, DIM, 1, MULTI, STRAT>();
-    case 2: return walk_ptr<Real, DIM, 2, MULTI, STRAT>();
-    default: return walk_ptr<Real, DIM, 3, MULTI, STRAT>();
+    case 0: return walk_ptr<Real, DIM, 0, MULTI, MODE>();
+    case 1: return walk_ptr<Real, DIM, 1, MULTI, MODE>();
+    case 2: return walk_ptr<Real, DIM, 2, MULTI, MODE>();
+    default: return walk_ptr<Real, DIM, 3, MULTI, MODE>();
   }
 }
 
-template <typename Real, int DIM>
-static const void* walk_ptr_m(int u0, bool multi, int strat) {
-  if (strat == 1) return multi ? walk_ptr_u0<Real, DIM, true, 1>(u0) : walk_ptr_u0<Real, DIM, false, 1>(u0);
-  return multi ? walk_ptr_u0<Real, DIM, true, 0>(u0) : walk_ptr_u0<Real, DIM, false, 0>(u0);
+template <typename Real, int DIM, int MODE>
+static const void* walk_ptr_multi(int u0, bool multi) {
+  return multi ? walk_ptr_u0<Real, DIM, true, MODE>(u0) : walk_ptr_u0<Real, DIM, false, MODE>(u0);
 }
 
-static const void* walk_fn(int precision, int dim, int u0, bool multi, int strat) {
+template <typename Real, int DIM>
+static const void* walk_ptr_m(int u0, bool multi, int mode) {
+  switch (mode) {
+    case 0: return walk_ptr_multi<Real, DIM, 0>(u0, multi);
+    case 1: return walk_ptr_multi<Real, DIM, 1>(u0, multi);
+    case 2: return walk_ptr_multi<Real, DIM, 2>(u0, multi);
+    default: return walk_ptr_multi<Real, DIM, 3>(u0, multi);
+  }
+}
+
+static const void* walk_fn(int precision, int dim, int u0, bool multi, int mode) {
   if (precision == 32)
-    return dim == 1 ? walk_ptr_m<float, 1>(u0, multi, strat) : walk_ptr_m<float, 2>(u0, multi, strat);
-  return dim == 1 ? walk_ptr_m<double, 1>(u0, multi, strat) : walk_ptr_m<double, 2>(u0, multi, strat);
+    return dim == 1 ? walk_ptr_m<float, 1>(u0, multi, mode) : walk_ptr_m<float, 2>(u0, multi, mode);
+  return dim == 1 ? walk_ptr_m<double, 1>(u0, multi, mode) : walk_ptr_m<double, 2>(u0, multi, mode);
 }
 
 int walk_max_blocks_per_cu(int precision, int dim, int u0_kind, int n_problems, int stack_depth, int waves_per_block) {
   int nb = 0;
   const size_t lds = walk_lds_bytes(precision, dim, stack_depth, waves_per_block, n_problems);
-  // occupancy of the Strategy A variant (the B variant needs no more registers)
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_fn(precision, dim, u0_kind, n_problems > 1, 0),
-                                                   waves_per_block * kWave, lds) != hipSuccess)
-    return 0;
-  return nb;
+  // the smallest occupancy over the strategy / coefficient variants, so a grid sized by it stays resident
+  int best = 1 << 30;
+  for (int mode = 0; mode < 4; ++mode) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_fn(precision, dim, u0_kind, n_problems > 1, mode),
+                                                     waves_per_block * kWave, lds) != hipSuccess)
+      return 0;
+    best = nb < best ? nb : best;
+  }
+  return best;
 }
 
 hipError_t launch_reset(uint32_t* chunk_counter, unsigned long long* depth_counter, hipStream_t s) {
@@ -509,7 +534,7 @@ hipError_t launch_reset(uint32_t* chunk_counter, unsigned long long* depth_count
 hipError_t launch_walk(int precision, int dim, int u0_kind, const WalkArgs& a, int grid, int waves_per_block,
                        hipStream_t s) {
   const size_t lds = walk_lds_bytes(precision, dim, (int)a.stack_depth, waves_per_block, (int)a.n_problems);
-  const void* fn = walk_fn(precision, dim, u0_kind, a.n_problems > 1, (int)a.strategy);
+  const void* fn = walk_fn(precision, dim, u0_kind, a.n_problems > 1, (int)(a.strategy | (a.cmod ? 2u : 0u)));
   void* args[] = {const_cast<WalkArgs*>(&a)};
   return hipLaunchKernel(fn, dim3(grid), dim3(waves_per_block * kWave), args, lds, s);
 }

@@ -247,6 +247,11 @@ struct AdiArgs {
   uint32_t* sync;       // [0] arrivals, [1] generation, [2] abort, [3 + 2n], [4 + 2n] work counters of step n
   uint64_t spin_limit;  // wall-clock ticks a barrier may wait
   double coef[8];
+  double pcoef[8];      // variable coefficients: the non-linear part (c_1 zeroed) ...
+  const double* ex;     // ... scaled by ex[i] ey[j] (t_mid + t0)^-pow, plus c_1 u
+  const double* ey;
+  uint32_t cmod, cm_pow;
+  double cm_t0, c1, dt;
   double rx2, ry2, dt2;
   uint32_t W;           // row stride NX + 1
   uint32_t px, py, cx, cy;
@@ -263,6 +268,17 @@ __device__ inline double reaction(const double* c, double u) {
   double f = 0.0;
   for (int j = 7; j >= 0; --j) f = f * u + c[j];
   return f;
+}
+
+// f at the extrapolated value ut for the node with modulation factor exy (variable coefficients) and the
+// step's time factor tf; with constant coefficients the plain polynomial.
+__device__ inline double reaction_at(const AdiArgs& a, double ut, double exy, double tf) {
+  if (!a.cmod) return reaction(a.coef, ut);
+  return a.c1 * ut + (exy * tf) * reaction(a.pcoef, ut);
+}
+
+__device__ inline double time_factor(const AdiArgs& a, uint32_t n) {
+  return a.cmod && a.cm_pow ? 1.0 / ((n + 0.5) * a.dt + a.cm_t0) : 1.0;
 }
 
 __device__ inline uint32_t grab(uint32_t* ctr) {
@@ -408,6 +424,7 @@ __device__ void x_sweep(const AdiArgs& a, uint32_t item, uint32_t n, const doubl
   const uint32_t nrows = min((uint32_t)kLines, (sy + 1) * a.cy - ybase);  // lines of this item
   const uint32_t c0 = sx * a.cx, m = a.cx - 1, W = a.W;
   double* __restrict__ star = a.star;
+  const double tf = time_factor(a, n);
   // intermediate-level values on the two vertical lines, lane = line
   if (lane < nrows) {
     const uint32_t y = ybase + lane;
@@ -434,10 +451,12 @@ __device__ void x_sweep(const AdiArgs& a, uint32_t item, uint32_t n, const doubl
       for (int k = 0; k < kLines + 2; ++k) cv[k] = cur[(size_t)min(ybase - 1 + k, ybase + nrows) * W + xcol];
 #pragma unroll
       for (int k = 0; k < kLines; ++k) pv[k] = prev[(size_t)min(ybase + k, ybase + nrows - 1) * W + xcol];
+      const double exv = a.cmod ? a.ex[xcol] : 1.0;
 #pragma unroll
       for (int k = 0; k < kLines; ++k) {
         const double u = cv[k + 1];
-        const double F = reaction(a.coef, 1.5 * u - 0.5 * pv[k]);
+        const double exy = a.cmod ? exv * a.ey[min(ybase + k, ybase + nrows - 1)] : 1.0;
+        const double F = reaction_at(a, 1.5 * u - 0.5 * pv[k], exy, tf);
         double d = u + a.ry2 * ((cv[k] - 2.0 * u) + cv[k + 2]) + a.dt2 * F;
         if (i == 0) d += a.rx2 * SB[k];
         if (i == m - 1) d += a.rx2 * SB[kLines + k];
@@ -493,6 +512,8 @@ __device__ void y_sweep(const AdiArgs& a, uint32_t item, uint32_t n, const doubl
   const double* __restrict__ star = a.star;
   const double gb0 = hline_value(a, sy, x, n + 1);
   const double gb1 = hline_value(a, sy + 1, x, n + 1);
+  const double tf = time_factor(a, n);
+  const double exv = a.cmod ? a.ex[x] : 1.0;
   const uint32_t ntiles = (m + kTile - 1) / kTile;
   constexpr int kPer = kTile / kGroups;  // positions per lane in a tile
   double dp = 0.0;
@@ -516,7 +537,8 @@ __device__ void y_sweep(const AdiArgs& a, uint32_t item, uint32_t n, const doubl
       for (int k = 0; k < kPer / 2; ++k) {
         const uint32_t p = q + kGroups * (half * (kPer / 2) + k);
         const uint32_t i = p0 + p;
-        const double F = reaction(a.coef, 1.5 * cu[k] - 0.5 * pr[k]);
+        const double exy = a.cmod ? exv * a.ey[r0 + 1 + p0 + min(p, np - 1)] : 1.0;
+        const double F = reaction_at(a, 1.5 * cu[k] - 0.5 * pr[k], exy, tf);
         double d = sc[k] + a.rx2 * ((sl[k] - 2.0 * sc[k]) + sr[k]) + a.dt2 * F;
         if (i == 0) d += a.ry2 * gb0;
         if (i == m - 1) d += a.ry2 * gb1;
@@ -641,6 +663,7 @@ struct brt_pdd {
   double* d_spl = nullptr;  // vals, mom, cp, rowsv, tmom, tcp
   uint32_t* d_sync = nullptr;
   double* d_node_u = nullptr;
+  double* d_exy = nullptr;  // variable coefficients: e^{-bx x_i^2} (NX+1), then e^{-by y_j^2} (NY+1)
   size_t spl_rows = 0, spl_fine = 0;
   // Monte Carlo plan of the nodes (built on first run, rebuilt when mc or the tree count change)
   brt_plan* plan = nullptr;
@@ -663,6 +686,7 @@ void pdd_free(brt_pdd* p) {
   (void)hipFree(p->d_spl);
   (void)hipFree(p->d_sync);
   (void)hipFree(p->d_node_u);
+  (void)hipFree(p->d_exy);
   for (hipEvent_t e : p->ev)
     if (e) (void)hipEventDestroy(e);
   delete p;
@@ -694,6 +718,11 @@ int brt_pdd_create(brt_ctx* ctx, const brt_problem* prob, const brt_pdd_grid* gr
   for (double c : prob->coef)
     if (!std::isfinite(c)) return set_error(BRT_E_ARG, "pdd: non-finite coefficient");
   if (prob->u0_kind > BRT_U0_COS2_BUMP) return set_error(BRT_E_ARG, "pdd: unknown u0_kind");
+  if (prob->coef_mod > BRT_COEF_MOD_GAUSS_TIME) return set_error(BRT_E_ARG, "pdd: unknown coef_mod");
+  if (prob->coef_mod == BRT_COEF_MOD_GAUSS_TIME &&
+      (!(prob->coef_mod_beta[0] >= 0.0) || !(prob->coef_mod_beta[1] >= 0.0) || prob->coef_mod_pow > 1 ||
+       (prob->coef_mod_pow == 1 && !(prob->coef_mod_t0 > 0.0))))
+    return set_error(BRT_E_ARG, "pdd: invalid variable-coefficient parameters");
   if (prob->u0_kind == BRT_U0_GAUSS_SUM && (prob->u0_nterms < 1 || prob->u0_nterms > 8))
     return set_error(BRT_E_ARG, "pdd: gauss_sum needs 1..8 terms");
   if (!(g.x_hi > g.x_lo) || !(g.y_hi > g.y_lo) || !std::isfinite(g.x_lo + g.x_hi + g.y_lo + g.y_hi))
@@ -789,13 +818,26 @@ int brt_pdd_create(brt_ctx* ctx, const brt_problem* prob, const brt_pdd_grid* gr
   dev_alloc((void**)&p->d_spl, 8 * (3 * p->spl_rows + 3 * p->spl_fine));
   dev_alloc((void**)&p->d_sync, 4 * (3 + 2 * (size_t)g.n_steps));
   dev_alloc((void**)&p->d_node_u, 8 * std::max<uint64_t>(p->n_nodes, 1));
+  dev_alloc((void**)&p->d_exy, 8 * (size_t)(p->NX + 1 + p->NY + 1));
   for (hipEvent_t& e : p->ev)
     if (rc == BRT_OK && hipEventCreate(&e) != hipSuccess) rc = set_error(BRT_E_DEVICE, "pdd: event creation");
   if (rc == BRT_OK) {
     std::vector<double> fac(2 * (size_t)(g.cx + g.cy));
     thomas_factors(p->rx, g.cx - 1, fac.data(), fac.data() + g.cx);
     thomas_factors(p->ry, g.cy - 1, fac.data() + 2 * g.cx, fac.data() + 2 * g.cx + g.cy);
-    if (hipMemcpy(p->d_fac, fac.data(), 8 * fac.size(), hipMemcpyHostToDevice) != hipSuccess ||
+    std::vector<double> exy(p->NX + 1 + p->NY + 1, 1.0);
+    if (prob->coef_mod == BRT_COEF_MOD_GAUSS_TIME) {
+      for (uint32_t i = 0; i <= p->NX; ++i) {
+        const double x = g.x_lo + i * p->hx;
+        exy[i] = std::exp(-prob->coef_mod_beta[0] * x * x);
+      }
+      for (uint32_t j = 0; j <= p->NY; ++j) {
+        const double y = g.y_lo + j * p->hy;
+        exy[p->NX + 1 + j] = std::exp(-prob->coef_mod_beta[1] * y * y);
+      }
+    }
+    if (hipMemcpy(p->d_exy, exy.data(), 8 * exy.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->d_fac, fac.data(), 8 * fac.size(), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(p->d_lines, p->lines.data(), sizeof(LineDev) * p->lines.size(), hipMemcpyHostToDevice) != hipSuccess)
       rc = set_error(BRT_E_DEVICE, "pdd: upload");
   }
@@ -935,7 +977,15 @@ int brt_pdd_solve(brt_pdd* p, uint32_t steps, double* field, void* stream) {
   int rate_khz = 0;
   PDD_TRY(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, p->device));
   a.spin_limit = (uint64_t)(kBarrierSeconds * 1e3 * (rate_khz > 0 ? rate_khz : 100000));
-  for (int j = 0; j < 8; ++j) a.coef[j] = p->prob.coef[j];
+  for (int j = 0; j < 8; ++j) a.coef[j] = a.pcoef[j] = p->prob.coef[j];
+  a.pcoef[1] = 0.0;
+  a.cmod = p->prob.coef_mod == BRT_COEF_MOD_GAUSS_TIME ? 1u : 0u;
+  a.cm_pow = p->prob.coef_mod_pow;
+  a.cm_t0 = p->prob.coef_mod_t0;
+  a.c1 = p->prob.coef[1];
+  a.dt = p->dt;
+  a.ex = p->d_exy;
+  a.ey = p->d_exy + p->NX + 1;
   a.rx2 = 0.5 * p->rx;
   a.ry2 = 0.5 * p->ry;
   a.dt2 = 0.5 * p->dt;

@@ -62,6 +62,11 @@ PdeT<Real> to_device(const brt_problem& p, const Norm& n) {
     d.omega[i] = (Real)n.omega[i];
   }
   d.u0_nterms = p.u0_nterms;
+  d.cmod = p.coef_mod;
+  d.cm_pow = p.coef_mod_pow;
+  d.cm_bx = (Real)p.coef_mod_beta[0];
+  d.cm_by = (Real)(p.dim == 2 ? p.coef_mod_beta[1] : 0.0);
+  d.cm_t0 = (Real)p.coef_mod_t0;
   for (int i = 0; i < kMaxU0Params; ++i) d.u0[i] = (Real)p.u0_params[i];
   if (p.u0_kind == BRT_U0_GAUSS_SUM)
     for (uint32_t k = 0; k < p.u0_nterms; ++k) {
@@ -150,6 +155,7 @@ struct brt_plan {
   brt_ctx* ctx = nullptr;
   int precision = 32, dim = 1, u0_kind = 0;
   uint32_t n_problems = 0, n_points = 0, n_bins = 0;
+  uint32_t cmod = 0;  // some problem has variable coefficients
   uint64_t total_trees = 0;
   brt_mc mc{};
   std::vector<PointRec> points;
@@ -256,6 +262,20 @@ int brt_problem_check(const brt_problem* p, const brt_mc* mc) {
     default:
       return fail(BRT_E_ARG, "unknown u0_kind %u", p->u0_kind);
   }
+  switch (p->coef_mod) {
+    case BRT_COEF_MOD_NONE:
+      break;
+    case BRT_COEF_MOD_GAUSS_TIME:
+      if (!(p->coef_mod_beta[0] >= 0.0) || !(p->coef_mod_beta[1] >= 0.0) || !is_fin(p->coef_mod_beta[0]) ||
+          !is_fin(p->coef_mod_beta[1]))
+        return fail(BRT_E_ARG, "coef_mod_beta must be finite and >= 0");
+      if (p->coef_mod_pow > 1) return fail(BRT_E_ARG, "coef_mod_pow must be 0 or 1");
+      if (p->coef_mod_pow == 1 && !(p->coef_mod_t0 > 0.0 && is_fin(p->coef_mod_t0)))
+        return fail(BRT_E_ARG, "coef_mod_t0 must be > 0 with coef_mod_pow 1");
+      break;
+    default:
+      return fail(BRT_E_ARG, "unknown coef_mod %u", p->coef_mod);
+  }
   if (mc->precision != 32 && mc->precision != 64) return fail(BRT_E_ARG, "precision must be 32 or 64");
   if (!(mc->lambda > 0.0) || !is_fin(mc->lambda)) return fail(BRT_E_ARG, "lambda must be > 0");
   if (mc->max_order > 126) return fail(BRT_E_ARG, "max_order must be <= 126");
@@ -332,6 +352,7 @@ extern "C" int brt_plan_create(brt_ctx* ctx, uint32_t n_problems, const brt_prob
   p->dim = (int)problems[0].dim;
   p->u0_kind = (int)problems[0].u0_kind;
   p->n_problems = n_problems;
+  for (uint32_t i = 0; i < n_problems; ++i) p->cmod |= problems[i].coef_mod != BRT_COEF_MOD_NONE ? 1u : 0u;
   p->n_points = pts->n;
   p->n_bins = mc->max_order + 2;
   p->mc = *mc;
@@ -522,6 +543,7 @@ static int enqueue(brt_plan* p, const brt_out* o, hipStream_t s) {
     w.prune = p->mc.prune;
     w.node_cap = p->mc.node_cap;
     w.strategy = p->mc.strategy;
+    w.cmod = p->cmod;
     w.stack_depth = (uint32_t)p->stack_depth;
     w.spill_depth = (uint32_t)p->spill_depth;
     w.spill = p->d_spill;

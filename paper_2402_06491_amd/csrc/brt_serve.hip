@@ -156,9 +156,11 @@ int run_group(brt_server* s, const std::vector<Request*>& group) {
     double cost;
   };
   std::vector<Item> items;
+  uint32_t cmod = 0;
   for (uint32_t k = 0; k < group.size(); ++k) {
     Request* r = group[k];
     pde_to_device(r->prob, r->norm, (int)mc.precision, s->h_pdes + (size_t)k * pb);
+    cmod |= r->prob.coef_mod != BRT_COEF_MOD_NONE ? 1u : 0u;
     for (uint32_t i = 0; i < r->n; ++i)
       if (!r->done[i]) items.push_back(Item{r, i, k, est_nodes(r->norm, mc, r->t[i])});
   }
@@ -219,6 +221,7 @@ int run_group(brt_server* s, const std::vector<Request*>& group) {
   w.prune = mc.prune;
   w.node_cap = mc.node_cap;
   w.strategy = mc.strategy;
+  w.cmod = cmod;
   w.stack_depth = (uint32_t)s->lds_depth;
   w.spill_depth = (uint32_t)s->spill_depth;
   w.n_threads = (uint32_t)(s->grid * s->wpb * kWave);

@@ -87,11 +87,12 @@ extern "C" int brt_autotune(brt_ctx* ctx, uint32_t n_problems, const brt_problem
     return BRT_OK;
   }
 
-  // subsample: every point keeps its share, about 2^25 trees in total, at least 1024 each
+  // subsample: every point keeps its share, about 2^26 trees in total, at least 1024 each (long enough that
+  // the drain of the persistent grid at the end of a launch does not decide the ranking)
   uint64_t total = 0;
   for (uint32_t i = 0; i < pts->n; ++i) total += pts->n_trees[i];
   if (total == 0) return set_error(BRT_E_ARG, "brt_autotune: no trees to time");
-  const double frac = std::min(1.0, (double)(1u << 25) / (double)total);
+  const double frac = std::min(1.0, (double)(1u << 26) / (double)total);
   std::vector<uint64_t> sub(pts->n);
   for (uint32_t i = 0; i < pts->n; ++i)
     sub[i] = pts->n_trees[i] ? std::max<uint64_t>(std::min<uint64_t>(1024, pts->n_trees[i]),
@@ -127,14 +128,17 @@ extern "C" int brt_autotune(brt_ctx* ctx, uint32_t n_problems, const brt_problem
         double ms[3] = {0, 0, 0};
         uint64_t runs = 0;
         erc = erc ? erc : brt_plan_get_timing(plan, ms, &runs);
-        for (int k = 0; !erc && k < 3; ++k) erc = brt_plan_execute(plan, &o, nullptr);
-        erc = erc ? erc : brt_plan_get_timing(plan, ms, &runs);
+        double walk = 1e30;  // fastest of three runs
+        for (int k = 0; !erc && k < 3; ++k) {
+          erc = brt_plan_execute(plan, &o, nullptr);
+          erc = erc ? erc : brt_plan_get_timing(plan, ms, &runs);
+          if (!erc && runs) walk = std::min(walk, ms[0] / (double)runs);
+        }
         brt_plan_destroy(plan);
         if (erc) {
           brt_set_launch(ctx, &cur);
           return erc;
         }
-        const double walk = ms[0] / (double)std::max<uint64_t>(1, runs);
         if (walk < best_ms) {
           best_ms = walk;
           best_l = l;

@@ -83,3 +83,22 @@ def test_strategy_b_validation_host_only():
     assert L.brt_problem_check(ctypes.byref(p), ctypes.byref(bad)) == -1
     bad = brt.make_mc(dict(wl["mc"], strategy=1, q=1.0))
     assert L.brt_problem_check(ctypes.byref(p), ctypes.byref(bad)) == -1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libbrt.so not built")
+def test_coef_mod_validation_host_only():
+    import paper_2402_06491_amd as brt
+    from paper_2402_06491_amd import inputs
+
+    L = brt.lib()
+    mc = brt.make_mc(inputs.mc_params())
+    good = brt.make_problem(inputs.example5()["problems"][0])
+    assert L.brt_problem_check(ctypes.byref(good), ctypes.byref(mc)) == 0
+    for bad_mod in ({"beta": (-1.0, 0.0), "t0": 0.1, "pow": 1}, {"beta": (1.0, 0.0), "t0": 0.0, "pow": 1},
+                    {"beta": (1.0, 0.0), "t0": 0.1, "pow": 2}):
+        d = inputs.problem(1, 1.0, [0.0, 0.0, -1.0], inputs.const(1.0), coef_mod=bad_mod)
+        p = brt.make_problem(d)
+        assert L.brt_problem_check(ctypes.byref(p), ctypes.byref(mc)) == -1, bad_mod
+    p = brt.make_problem(inputs.problem(1, 1.0, [0.0, 0.0, -1.0], inputs.const(1.0)))
+    p.coef_mod = 7
+    assert L.brt_problem_check(ctypes.byref(p), ctypes.byref(mc)) == -1

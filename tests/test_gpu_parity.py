@@ -235,6 +235,30 @@ def test_strategy_b_unpruned_and_heat(ctx):
     assert np.all(gpu["nodes"] == 700)
 
 
+@pytest.mark.parametrize("prec", [32, 64])
+def test_variable_coefficients_example5(ctx, prec):
+    """The paper's Example 5 coefficient -e^{-x^2}/(t + 0.1), evaluated at every split."""
+    wl = inputs.example5(n_trees=1500, n_x=24, precision=prec)
+    _full_parity(ctx, f"example5_fp{prec}", wl)
+
+
+def test_variable_coefficients_2d_strategy_b_and_mixed(ctx):
+    prob = inputs.problem(2, 0.8, [0.1, -0.4, 0.6, -0.5], inputs.cubic_2d_u0(3),
+                          coef_mod={"beta": (0.3, 0.7), "t0": 0.2, "pow": 1})
+    x = inputs.interface_points(16)[::3]
+    n = len(x)
+    wl = {"problems": [prob], "mc": inputs.mc_params(seed=12, precision=32, strategy=1, q=0.55), "x": x,
+          "t": np.full(n, 0.9), "n_trees": np.full(n, 700)}
+    _full_parity(ctx, "varcoef_2d_strategy_b", wl)
+    # constant and variable coefficients in one launch (per-lane problem tables)
+    plain = inputs.problem(2, 0.8, [0.1, -0.4, 0.6, -0.5], inputs.cubic_2d_u0(3))
+    space = inputs.problem(2, 0.8, [0.1, -0.4, 0.6, -0.5], inputs.cubic_2d_u0(3),
+                           coef_mod={"beta": (0.5, 0.0), "t0": 0.0, "pow": 0})
+    wl = {"problems": [plain, prob, space], "mc": inputs.mc_params(seed=13, precision=64), "x": x,
+          "t": np.full(n, 0.7), "n_trees": np.full(n, 500), "problem_id": (np.arange(n) % 3).astype(np.uint32)}
+    _full_parity(ctx, "varcoef_mixed_problems", wl)
+
+
 def test_launch_settings_do_not_change_results(ctx):
     """Every tree is computed by one lane from its own counters and segments are fixed, so launch
     settings (block size, LDS stack levels, chunk size) change nothing in the outputs."""

@@ -166,3 +166,16 @@ def test_pdd_end_to_end_against_oracle_monte_carlo(ctx):
     print(f"[case] pdd_end_to_end: max |d node| {dnode:.3e}, max |dU| {dfield:.3e}; MC {ms[0]:.2f} ms, "
           f"interp {ms[1]:.3f} ms, solve {ms[2]:.3f} ms", flush=True)
     assert dfield <= 4.0 * dnode + FIELD_TOL * max(1.0, float(np.abs(ofield).max()))
+
+
+@pytest.mark.parametrize("pw", [0, 1])
+def test_tail_variable_coefficients(ctx, pw):
+    """Reaction with c_j(x, t) = c_j e^{-bx x^2 - by y^2} (t + t0)^-pow at the node and the mid-step time."""
+    grid = _grid(px=2, py=3, cx=24, cy=20, n_steps=30, ns_x=9, ns_y=13, nt=4, T=0.4)
+    prob = inputs.problem(2, 0.9, [0.05, 0.6, -1.0, -0.3], inputs.cubic_2d_u0(4),
+                          coef_mod={"beta": (0.3, 0.5), "t0": 0.1, "pow": pw})
+    og = opdd.Grid(**grid)
+    rng = np.random.default_rng(21 + pw)
+    xy, t = opdd.node_points(og)
+    vals = opdd.g_grid(prob, xy[:, 0], xy[:, 1]) * np.exp(-0.5 * t) + 0.01 * rng.normal(size=len(t))
+    _tail_parity(ctx, f"tail_varcoef_pow{pw}", prob, grid, vals)
