@@ -145,6 +145,55 @@ def pmc_traffic(kernel_src_sha, launches_trees):
     return d.get("hbm_bytes_per_launch")
 
 
+def walker_source_sha():
+    h = hashlib.sha256()
+    for f in ("brt_kernels.hip", "brt_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2402_06491_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
+COPY_BYTES = 512 << 20  # the plain device copy of --pmc-calibration
+
+
+def pmc_summary(fetch_dir, write_dir, command):
+    """Write profiles/walk_fisher_pmc.json from two rocprofv3 --pmc runs of this script (FETCH_SIZE, then
+    WRITE_SIZE, with --pmc-calibration): the last walker dispatch (the timed plan's last direct launch)
+    and the calibration copy, whose known size gives each counter's scale."""
+    import csv
+
+    def read(d, counter):
+        rows = []
+        for root, _, files in os.walk(d):
+            for f in files:
+                if f.endswith("counter_collection.csv"):
+                    rows += list(csv.DictReader(open(os.path.join(root, f))))
+        per = {}
+        for r in rows:
+            if r["Counter_Name"] != counter:
+                continue
+            key = (int(r["Dispatch_Id"]), r["Kernel_Name"])
+            per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+        walk = [v for (i, k), v in sorted(per.items()) if "walk_kernel" in k]
+        copy = [v for (i, k), v in sorted(per.items()) if "copyBuffer" in k]
+        return walk[-1], copy[-1]
+
+    fw, fc = read(fetch_dir, "FETCH_SIZE")
+    ww, wc = read(write_dir, "WRITE_SIZE")
+    fs = COPY_BYTES / (fc * 1024.0)
+    ws = COPY_BYTES / (wc * 1024.0)
+    wl = workload("fisher")
+    trees = int(np.sum(wl["n_trees"]))
+    out = {"kernel": "walk_kernel", "workload": wl["name"], "kernel_source_sha256": walker_source_sha(),
+           "fetch_kib_per_dispatch": fw, "write_kib_per_dispatch": ww,
+           "copy_fetch_kib": fc, "copy_write_kib": wc, "copy_bytes": COPY_BYTES,
+           "fetch_scale": fs, "write_scale": ws,
+           "hbm_bytes_per_launch": fw * 1024.0 * fs + ww * 1024.0 * ws,
+           "algorithmic_bytes_per_launch": 12 * trees, "command": command}
+    path = os.path.join(ROOT, "profiles", "walk_fisher_pmc.json")
+    json.dump(out, open(path, "w"), indent=1)
+    print(json.dumps(out))
+
+
 def serve_stream(ctx, reqs, mc, max_active, opts):
     """Replay a request stream in real time through a brt_server; returns its statistics."""
     import paper_2402_06491_amd as brt
@@ -297,7 +346,15 @@ def main():
                     help="trees per node of the domain-decomposition tail run after the steps (0: skip)")
     ap.add_argument("--pdd-cpu-steps", type=int, default=5)
     ap.add_argument("--no-strategy-b", action="store_true")
+    ap.add_argument("--pmc-calibration", action="store_true",
+                    help="end with a plain 512 MiB device copy (scale of the rocprofv3 byte counters)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/walk_fisher_pmc.json from two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--pmc-command", default="", help="the command of the counter runs, recorded in the summary")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.pmc_command)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
@@ -353,8 +410,7 @@ def main():
     dim = int(wl["problems"][0]["dim"])
     ops = nodes * OPS_PER_NODE[dim]
     achieved = ops / walk_s / 1e12
-    src = open(os.path.join(ROOT, "paper_2402_06491_amd", "csrc", "brt_kernels.hip"), "rb").read()
-    sha = hashlib.sha256(src).hexdigest()
+    sha = walker_source_sha()
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_TOPS, "unit": "Top/s",
                 "frac": achieved / PEAK_TOPS, "traffic": pmc_traffic(sha, total_trees),
                 "kernel": "walk_kernel", "kernel_ms": walk_s * 1e3, "nodes_per_launch": nodes,
@@ -397,6 +453,12 @@ def main():
                                          "queue_cap": 100_000})
     if args.pdd_trees > 0:
         result["pdd"] = pdd_bench(ctx, args.pdd_trees, args.pdd_cpu_steps)
+    if args.pmc_calibration:
+        a = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     ctx.close()
     print(json.dumps(result), flush=True)
 

@@ -335,7 +335,7 @@ typedef struct brt_pdd_grid {
   uint32_t struct_size;
   double x_lo, x_hi, y_lo, y_hi;
   uint32_t px, py;        /* subdomains per direction, 1..64 */
-  uint32_t cx, cy;        /* fine cells per subdomain per direction, 2..4096 */
+  uint32_t cx, cy;        /* fine cells per subdomain per direction, 2..1024 (16 lines of a subdomain stay in LDS) */
   double T;               /* final time > 0 */
   uint32_t n_steps;       /* time steps to T, 1..2^20 */
   uint32_t ns_x, ns_y;    /* nodes per horizontal / vertical line, 4..257 */

@@ -28,7 +28,7 @@ namespace {
 
 constexpr int kLanes = 64;
 constexpr uint32_t kMaxSub = 64;
-constexpr uint32_t kMaxCells = 4096;
+constexpr uint32_t kMaxCells = 1024;
 constexpr uint32_t kMaxNodesPerLine = 257;
 constexpr uint32_t kMaxNt = 63;
 constexpr double kBarrierSeconds = 5.0;
@@ -246,11 +246,10 @@ struct AdiArgs {
   const double* cp_y;
   uint32_t* sync;       // [0] arrivals, [1] generation, [2] abort, [3 + 2n], [4 + 2n] work counters of step n
   uint64_t spin_limit;  // wall-clock ticks a barrier may wait
-  double coef[8];
-  double pcoef[8];      // variable coefficients: the non-linear part (c_1 zeroed) ...
-  const double* ex;     // ... scaled by ex[i] ey[j] (t_mid + t0)^-pow, plus c_1 u
+  double pcoef[8];      // f(u) = c_1 u + m(x, y, t) sum_{j != 1} c_j u^j: the non-linear part (c_1 zeroed) ...
+  const double* ex;     // ... scaled by ex[i] ey[j] (t_mid + t0)^-pow (all 1 with constant coefficients)
   const double* ey;
-  uint32_t cmod, cm_pow;
+  uint32_t cm_pow;
   double cm_t0, c1, dt;
   double rx2, ry2, dt2;
   uint32_t W;           // row stride NX + 1
@@ -270,21 +269,14 @@ __device__ inline double reaction(const double* c, double u) {
   return f;
 }
 
-// f at the extrapolated value ut for the node with modulation factor exy (variable coefficients) and the
-// step's time factor tf; with constant coefficients the plain polynomial.
+// f at the extrapolated value ut for the node with modulation factor exy and the step's time factor tf
+// (both 1 with constant coefficients): c_1 ut + (exy tf) P(ut), P the non-linear part.
 __device__ inline double reaction_at(const AdiArgs& a, double ut, double exy, double tf) {
-  if (!a.cmod) return reaction(a.coef, ut);
   return a.c1 * ut + (exy * tf) * reaction(a.pcoef, ut);
 }
 
 __device__ inline double time_factor(const AdiArgs& a, uint32_t n) {
-  return a.cmod && a.cm_pow ? 1.0 / ((n + 0.5) * a.dt + a.cm_t0) : 1.0;
-}
-
-__device__ inline uint32_t grab(uint32_t* ctr) {
-  uint32_t v = 0;
-  if (threadIdx.x == 0) v = atomicAdd(ctr, 1u);
-  return __shfl(v, 0);
+  return a.cm_pow ? 1.0 / ((n + 0.5) * a.dt + a.cm_t0) : 1.0;
 }
 
 // Grid barrier (sense by generation count).  Every block waits at most spin_limit wall-clock ticks; on
@@ -301,7 +293,9 @@ __device__ bool grid_barrier(uint32_t* sync, uint32_t nblocks, uint32_t& gen, ui
       __hip_atomic_fetch_add(&sync[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       const uint64_t t0 = wall_clock64();
-      while (__hip_atomic_load(&sync[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != target) {
+      // relaxed polling: an acquiring load would invalidate this XCD's L2 on every poll while other
+      // blocks still work; the fence below acquires once the generation has moved
+      while (__hip_atomic_load(&sync[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != target) {
         if (__hip_atomic_load(&sync[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
             wall_clock64() - t0 > spin_limit) {
           atomicExch(&sync[2], 1u);
@@ -339,19 +333,23 @@ __device__ inline double hline_value(const AdiArgs& a, uint32_t ky, uint32_t x, 
   return a.bd[L.bd_off + (size_t)n * L.n_fine + x];
 }
 
-// A work item is kLines lines of one subdomain.  The sweeps go through the lines in tiles of 64
-// positions.  A tile's right-hand sides are formed first from global loads issued together (all 64
-// lanes: along the positions in the x phase; 16 lines x 4 position groups in the y phase) into an LDS
-// tile; the Thomas recurrence then runs from LDS, one lane per line; the tile goes back to global
-// memory with all lanes.  The forward pass leaves d' in the output field; the backward pass reads it
-// back tile by tile in reverse order.  Many short items keep enough waves in flight to cover the
-// memory latency the recurrences cannot hide themselves.
+// A work item is kLines lines of one subdomain, resident in LDS for the whole sweep: the right-hand
+// sides of all its positions are formed first from global loads issued in large batches (lanes along
+// the positions in the x phase; 16 lines x 4 position groups in the y phase), the forward and the
+// backward Thomas recurrences then run from LDS with one lane per line and the factors of the
+// direction in LDS, and the solution goes back to global memory once.  Subdomains have at most 1024
+// cells per side so that 16 lines fit beside the factors.
 constexpr int kLines = 16;
-constexpr int kTile = 64;
-constexpr int kGroups = kLanes / kLines;  // position groups of the y phase
-constexpr int kXPitch = kTile + 1;        // x phase LDS tile [line][position]
-constexpr int kYPitch = kLines + 1;       // y phase LDS tile [position][line]
-constexpr int kLdsDoubles = kLines * kXPitch > kTile * kYPitch ? kLines * kXPitch : kTile * kYPitch;
+constexpr int kTile = 64;                  // positions per x-phase load batch (one per lane)
+constexpr int kGroups = kLanes / kLines;   // position groups of the y phase
+constexpr int kYPitch = kLines + 1;        // y phase LDS [position][line]
+constexpr int kYBatch = 16;                // positions per lane loaded together in the y phase
+
+// LDS (doubles) of a sweep over lines of m unknowns: x phase [line][pitch] + factors + boundary values;
+// y phase [position][line] + factors.
+__host__ __device__ inline uint32_t x_pitch(uint32_t m) { return m | 1u; }
+__host__ __device__ inline size_t x_lds(uint32_t m) { return (size_t)kLines * x_pitch(m) + 2 * m + 3 * kLines; }
+__host__ __device__ inline size_t y_lds(uint32_t m) { return (size_t)m * kYPitch + 3 * m; }
 
 // Work items run in single-wave blocks: LDS accesses of one wavefront are performed in order, so a
 // wavefront-scope fence (which also keeps the compiler from moving LDS accesses across it) replaces
@@ -367,23 +365,30 @@ constexpr int kChain = 16;  // recurrence steps whose operands are loaded togeth
 // at D[off + c * stride]; d' replaces them.  Operands are fetched kChain at a time before use.
 __device__ inline double chain_forward(double* __restrict__ D, uint32_t off, uint32_t stride, uint32_t p0, uint32_t np,
                                        const double* __restrict__ F, double r2, double dp) {
-  for (uint32_t cb = 0; cb < np; cb += kChain) {
+  uint32_t cb = 0;
+  if (p0 == 0 && np > 0) {  // the first unknown has no predecessor
+    dp = D[off] * F[0];
+    D[off] = dp;
+    cb = 1;
+  }
+  for (; cb + kChain <= np; cb += kChain) {  // full batches: operands fetched together, no conditions
     double dv[kChain], fv[kChain];
 #pragma unroll
     for (int k = 0; k < kChain; ++k) {
-      const uint32_t c = min(cb + k, np - 1);
-      dv[k] = D[off + c * stride];
-      fv[k] = F[c];
+      dv[k] = D[off + (cb + k) * stride];
+      fv[k] = F[cb + k];
     }
 #pragma unroll
-    for (int k = 0; k < kChain; ++k) {  // fully unrolled: steps past the tile's end keep dp
-      const double nd = (p0 + cb + k == 0 ? dv[k] : dv[k] + r2 * dp) * fv[k];
-      dp = cb + k < np ? nd : dp;
-      dv[k] = nd;
+    for (int k = 0; k < kChain; ++k) {
+      dp = (dv[k] + r2 * dp) * fv[k];
+      dv[k] = dp;
     }
 #pragma unroll
-    for (int k = 0; k < kChain; ++k)
-      if (cb + k < np) D[off + (cb + k) * stride] = dv[k];
+    for (int k = 0; k < kChain; ++k) D[off + (cb + k) * stride] = dv[k];
+  }
+  for (; cb < np; ++cb) {
+    dp = (D[off + cb * stride] + r2 * dp) * F[cb];
+    D[off + cb * stride] = dp;
   }
   return dp;
 }
@@ -392,40 +397,54 @@ __device__ inline double chain_forward(double* __restrict__ D, uint32_t off, uin
 // is its d'.
 __device__ inline double chain_backward(double* __restrict__ D, uint32_t off, uint32_t stride, uint32_t p0, uint32_t np,
                                         uint32_t m, const double* __restrict__ F, double xv) {
-  for (int cb = (int)np - 1; cb >= 0; cb -= kChain) {
+  int cb = (int)np - 1;
+  if (p0 + np == m && np > 0) {  // the last unknown is its own d'
+    xv = D[off + cb * stride];
+    --cb;
+  }
+  for (; cb - kChain + 1 >= 0; cb -= kChain) {
     double dv[kChain], fv[kChain];
 #pragma unroll
     for (int k = 0; k < kChain; ++k) {
-      const int c = max(cb - k, 0);
-      dv[k] = D[off + c * stride];
-      fv[k] = F[c];
+      dv[k] = D[off + (cb - k) * stride];
+      fv[k] = F[cb - k];
     }
 #pragma unroll
-    for (int k = 0; k < kChain; ++k) {  // fully unrolled: steps before the tile's start keep xv
-      const int ii = (int)p0 + cb - k;
-      const double nx = ii == (int)m - 1 ? dv[k] : dv[k] - fv[k] * xv;
-      xv = cb - k >= 0 ? nx : xv;
-      dv[k] = nx;
+    for (int k = 0; k < kChain; ++k) {
+      xv = dv[k] - fv[k] * xv;
+      dv[k] = xv;
     }
 #pragma unroll
-    for (int k = 0; k < kChain; ++k)
-      if (cb - k >= 0) D[off + (cb - k) * stride] = dv[k];
+    for (int k = 0; k < kChain; ++k) D[off + (cb - k) * stride] = dv[k];
+  }
+  for (; cb >= 0; --cb) {
+    xv = D[off + cb * stride] - F[cb] * xv;
+    D[off + cb * stride] = xv;
   }
   return xv;
 }
 
 __device__ void x_sweep(const AdiArgs& a, uint32_t item, uint32_t n, const double* __restrict__ cur,
-                        const double* __restrict__ prev, double* __restrict__ D, double* __restrict__ SB,
-                        double* __restrict__ FB) {
+                        const double* __restrict__ prev, double* __restrict__ smem) {
   const uint32_t lane = threadIdx.x;
   const uint32_t sub = item / a.x_blk, blk = item % a.x_blk;
   const uint32_t sx = sub % a.px, sy = sub / a.px;
   const uint32_t ybase = sy * a.cy + 1 + blk * kLines;
   const uint32_t nrows = min((uint32_t)kLines, (sy + 1) * a.cy - ybase);  // lines of this item
   const uint32_t c0 = sx * a.cx, m = a.cx - 1, W = a.W;
+  const uint32_t pitch = x_pitch(m);
+  double* __restrict__ D = smem;              // [line][pitch]
+  double* __restrict__ FI = D + kLines * pitch;
+  double* __restrict__ FC = FI + m;
+  double* __restrict__ SB = FC + m;           // intermediate values on the two vertical lines
+  double* __restrict__ EY = SB + 2 * kLines;  // coefficient modulation of the item's rows
   double* __restrict__ star = a.star;
   const double tf = time_factor(a, n);
-  // intermediate-level values on the two vertical lines, lane = line
+  for (uint32_t i = lane; i < m; i += kLanes) {
+    FI[i] = a.inv_x[i];
+    FC[i] = a.cp_x[i];
+  }
+  if (lane < kLines) EY[lane] = a.ey[min(ybase + lane, ybase + nrows - 1)];
   if (lane < nrows) {
     const uint32_t y = ybase + lane;
     const double usl = ustar_line(a, sx, y, n);
@@ -436,70 +455,63 @@ __device__ void x_sweep(const AdiArgs& a, uint32_t item, uint32_t n, const doubl
     if (sx == a.px - 1) star[(size_t)y * W + c0 + a.cx] = usr;
   }
   wave_sync();
-  const uint32_t ntiles = (m + kTile - 1) / kTile;
-  double dp = 0.0;  // lane = line: running d' of the forward recurrence
-  for (uint32_t t = 0; t < ntiles; ++t) {
-    const uint32_t p0 = t * kTile, np = min((uint32_t)kTile, m - p0);
-    // right-hand sides: lane = position (clamped to a valid column), all rows of the item at once
-    const bool ok = lane < np;
-    const uint32_t i = p0 + min(lane, np - 1);
-    const size_t xcol = c0 + 1 + i;
-    FB[lane] = a.inv_x[i];
-    {
-      double cv[kLines + 2], pv[kLines];
+  double eyv[kLines], slv[kLines], srv[kLines];  // per row, in registers for the right-hand sides
 #pragma unroll
-      for (int k = 0; k < kLines + 2; ++k) cv[k] = cur[(size_t)min(ybase - 1 + k, ybase + nrows) * W + xcol];
-#pragma unroll
-      for (int k = 0; k < kLines; ++k) pv[k] = prev[(size_t)min(ybase + k, ybase + nrows - 1) * W + xcol];
-      const double exv = a.cmod ? a.ex[xcol] : 1.0;
-#pragma unroll
-      for (int k = 0; k < kLines; ++k) {
-        const double u = cv[k + 1];
-        const double exy = a.cmod ? exv * a.ey[min(ybase + k, ybase + nrows - 1)] : 1.0;
-        const double F = reaction_at(a, 1.5 * u - 0.5 * pv[k], exy, tf);
-        double d = u + a.ry2 * ((cv[k] - 2.0 * u) + cv[k + 2]) + a.dt2 * F;
-        if (i == 0) d += a.rx2 * SB[k];
-        if (i == m - 1) d += a.rx2 * SB[kLines + k];
-        if (ok && k < (int)nrows) D[k * kXPitch + lane] = d;
-      }
-    }
-    wave_sync();
-    if (lane < nrows) dp = chain_forward(D, lane * kXPitch, 1, p0, np, FB, a.rx2, dp);
-    wave_sync();
-    if (ok)
-#pragma unroll
-      for (int k = 0; k < kLines; ++k)
-        if (k < (int)nrows) star[(size_t)(ybase + k) * W + xcol] = D[k * kXPitch + lane];
-    wave_sync();
+  for (int k = 0; k < kLines; ++k) {
+    eyv[k] = EY[k];
+    slv[k] = a.rx2 * SB[k];
+    srv[k] = a.rx2 * SB[kLines + k];
   }
-  double xv = 0.0;
-  for (int t = (int)ntiles - 1; t >= 0; --t) {
-    const uint32_t p0 = t * kTile, np = min((uint32_t)kTile, m - p0);
-    const bool ok = lane < np;
-    const size_t xcol = c0 + 1 + p0 + min(lane, np - 1);
-    FB[lane] = a.cp_x[p0 + min(lane, np - 1)];
-    if (t != (int)ntiles - 1) {  // the last tile's d' is still in LDS
-      double v[kLines];
+  // right-hand sides of every position: lane = position within a batch of 64, two batches in flight
+  const uint32_t nb = (m + kTile - 1) / kTile;
+  auto load = [&](uint32_t t, double* cv, double* pv, double& exv) {
+    const uint32_t tt = min(t, nb - 1);
+    const size_t xcol = c0 + 1 + min(tt * kTile + lane, m - 1);
 #pragma unroll
-      for (int k = 0; k < kLines; ++k) v[k] = star[(size_t)min(ybase + k, ybase + nrows - 1) * W + xcol];
+    for (int k = 0; k < kLines + 2; ++k) cv[k] = cur[(size_t)min(ybase - 1 + k, ybase + nrows) * W + xcol];
 #pragma unroll
-      for (int k = 0; k < kLines; ++k)
-        if (ok && k < (int)nrows) D[k * kXPitch + lane] = v[k];
-      wave_sync();
+    for (int k = 0; k < kLines; ++k) pv[k] = prev[(size_t)min(ybase + k, ybase + nrows - 1) * W + xcol];
+    exv = a.ex[xcol];
+  };
+  auto rhs = [&](uint32_t t, const double* cv, const double* pv, double exv) {
+    const uint32_t i = t * kTile + lane;
+    if (t >= nb || i >= m) return;
+    const double first = i == 0 ? 1.0 : 0.0, last = i == m - 1 ? 1.0 : 0.0;
+#pragma unroll
+    for (int k = 0; k < kLines; ++k) {
+      const double u = cv[k + 1];
+      const double F = reaction_at(a, 1.5 * u - 0.5 * pv[k], exv * eyv[k], tf);
+      double d = u + a.ry2 * ((cv[k] - 2.0 * u) + cv[k + 2]) + a.dt2 * F;
+      d += first * slv[k];
+      d += last * srv[k];
+      if (k < (int)nrows) D[k * pitch + i] = d;
     }
-    wave_sync();
-    if (lane < nrows) xv = chain_backward(D, lane * kXPitch, 1, p0, np, m, FB, xv);
-    wave_sync();
-    if (ok)
+  };
+  for (uint32_t t = 0; t < nb; t += 2) {
+    double cvA[kLines + 2], pvA[kLines], cvB[kLines + 2], pvB[kLines], exA, exB;
+    load(t, cvA, pvA, exA);
+    load(t + 1, cvB, pvB, exB);
+    rhs(t, cvA, pvA, exA);
+    rhs(t + 1, cvB, pvB, exB);
+  }
+  wave_sync();
+  if (lane < nrows) {
+    chain_forward(D, lane * pitch, 1, 0, m, FI, a.rx2, 0.0);
+    chain_backward(D, lane * pitch, 1, 0, m, m, FC, 0.0);
+  }
+  wave_sync();
+  for (uint32_t t = 0; t < nb; ++t) {
+    const uint32_t i = t * kTile + lane;
+    if (i < m)
 #pragma unroll
       for (int k = 0; k < kLines; ++k)
-        if (k < (int)nrows) star[(size_t)(ybase + k) * W + xcol] = D[k * kXPitch + lane];
-    wave_sync();
+        if (k < (int)nrows) star[(size_t)(ybase + k) * W + c0 + 1 + i] = D[k * pitch + i];
   }
+  wave_sync();
 }
 
 __device__ void y_sweep(const AdiArgs& a, uint32_t item, uint32_t n, const double* __restrict__ cur,
-                        double* __restrict__ next, double* __restrict__ D, double* __restrict__ FB) {
+                        double* __restrict__ next, double* __restrict__ smem) {
   const uint32_t lane = threadIdx.x;
   const uint32_t l = lane % kLines, q = lane / kLines;  // line, position group
   const uint32_t sub = item / a.y_blk, blk = item % a.y_blk;
@@ -509,82 +521,57 @@ __device__ void y_sweep(const AdiArgs& a, uint32_t item, uint32_t n, const doubl
   const bool ok = l < nl;
   const uint32_t x = xfirst + min(l, nl - 1);
   const uint32_t r0 = sy * a.cy, m = a.cy - 1, W = a.W;
+  double* __restrict__ D = smem;  // [position][line]
+  double* __restrict__ FI = D + (size_t)m * kYPitch;
+  double* __restrict__ FC = FI + m;
+  double* __restrict__ EY = FC + m;  // coefficient modulation of the subdomain's rows
   const double* __restrict__ star = a.star;
+  for (uint32_t i = lane; i < m; i += kLanes) {
+    FI[i] = a.inv_y[i];
+    FC[i] = a.cp_y[i];
+    EY[i] = a.ey[r0 + 1 + i];
+  }
   const double gb0 = hline_value(a, sy, x, n + 1);
   const double gb1 = hline_value(a, sy + 1, x, n + 1);
   const double tf = time_factor(a, n);
-  const double exv = a.cmod ? a.ex[x] : 1.0;
-  const uint32_t ntiles = (m + kTile - 1) / kTile;
-  constexpr int kPer = kTile / kGroups;  // positions per lane in a tile
-  double dp = 0.0;
-  for (uint32_t t = 0; t < ntiles; ++t) {
-    const uint32_t p0 = t * kTile, np = min((uint32_t)kTile, m - p0);
-    FB[lane] = a.inv_y[p0 + min(lane, np - 1)];
+  const double exv = a.ex[x];
+  const uint32_t npl = (m + kGroups - 1) / kGroups;  // positions per lane: p = q + kGroups k
+  wave_sync();
+  for (uint32_t kb = 0; kb < npl; kb += kYBatch) {
+    double sl[kYBatch], sc[kYBatch], sr[kYBatch], cu[kYBatch], pr[kYBatch], ey[kYBatch];
 #pragma unroll
-    for (int half = 0; half < 2; ++half) {
-      double sl[kPer / 2], sc[kPer / 2], sr[kPer / 2], cu[kPer / 2], pr[kPer / 2];
-#pragma unroll
-      for (int k = 0; k < kPer / 2; ++k) {
-        const uint32_t p = q + kGroups * (half * (kPer / 2) + k);
-        const size_t idx = (size_t)(r0 + 1 + p0 + min(p, np - 1)) * W + x;
-        sl[k] = star[idx - 1];
-        sc[k] = star[idx];
-        sr[k] = star[idx + 1];
-        cu[k] = cur[idx];
-        pr[k] = next[idx];  // next still holds u^{n-1}
-      }
-#pragma unroll
-      for (int k = 0; k < kPer / 2; ++k) {
-        const uint32_t p = q + kGroups * (half * (kPer / 2) + k);
-        const uint32_t i = p0 + p;
-        const double exy = a.cmod ? exv * a.ey[r0 + 1 + p0 + min(p, np - 1)] : 1.0;
-        const double F = reaction_at(a, 1.5 * cu[k] - 0.5 * pr[k], exy, tf);
-        double d = sc[k] + a.rx2 * ((sl[k] - 2.0 * sc[k]) + sr[k]) + a.dt2 * F;
-        if (i == 0) d += a.ry2 * gb0;
-        if (i == m - 1) d += a.ry2 * gb1;
-        if (p < np) D[p * kYPitch + l] = d;
-      }
+    for (int k = 0; k < kYBatch; ++k) {
+      const uint32_t p = min(q + kGroups * (kb + k), m - 1);
+      const size_t idx = (size_t)(r0 + 1 + p) * W + x;
+      sl[k] = star[idx - 1];
+      sc[k] = star[idx];
+      sr[k] = star[idx + 1];
+      cu[k] = cur[idx];
+      pr[k] = next[idx];  // next still holds u^{n-1}
+      ey[k] = EY[p];
     }
-    wave_sync();
-    if (q == 0) dp = chain_forward(D, l, kYPitch, p0, np, FB, a.ry2, dp);
-    wave_sync();
-    if (ok)
 #pragma unroll
-      for (int k = 0; k < kPer; ++k) {
-        const uint32_t p = q + kGroups * k;
-        if (p < np) next[(size_t)(r0 + 1 + p0 + p) * W + x] = D[p * kYPitch + l];
-      }
-    wave_sync();
-  }
-  double xv = dp;  // broadcast below: only the q == 0 lanes hold the recurrence
-  for (int t = (int)ntiles - 1; t >= 0; --t) {
-    const uint32_t p0 = t * kTile, np = min((uint32_t)kTile, m - p0);
-    FB[lane] = a.cp_y[p0 + min(lane, (uint32_t)np - 1)];
-    if (t != (int)ntiles - 1) {  // the last tile's d' is still in LDS
-      double v[kPer];
-#pragma unroll
-      for (int k = 0; k < kPer; ++k) {
-        const uint32_t p = q + kGroups * k;
-        v[k] = next[(size_t)(r0 + 1 + p0 + min(p, np - 1)) * W + x];
-      }
-#pragma unroll
-      for (int k = 0; k < kPer; ++k) {
-        const uint32_t p = q + kGroups * k;
-        if (p < np) D[p * kYPitch + l] = v[k];
-      }
-      wave_sync();
+    for (int k = 0; k < kYBatch; ++k) {
+      const uint32_t p = q + kGroups * (kb + k);
+      const double F = reaction_at(a, 1.5 * cu[k] - 0.5 * pr[k], exv * ey[k], tf);
+      double d = sc[k] + a.rx2 * ((sl[k] - 2.0 * sc[k]) + sr[k]) + a.dt2 * F;
+      d += p == 0 ? a.ry2 * gb0 : 0.0;
+      d += p == m - 1 ? a.ry2 * gb1 : 0.0;
+      if (p < m) D[p * kYPitch + l] = d;
     }
-    wave_sync();
-    if (q == 0) xv = chain_backward(D, l, kYPitch, p0, np, m, FB, xv);
-    wave_sync();
-    if (ok)
-#pragma unroll
-      for (int k = 0; k < kPer; ++k) {
-        const uint32_t p = q + kGroups * k;
-        if (p < np) next[(size_t)(r0 + 1 + p0 + p) * W + x] = D[p * kYPitch + l];
-      }
-    wave_sync();
   }
+  wave_sync();
+  if (q == 0) {
+    chain_forward(D, l, kYPitch, 0, m, FI, a.ry2, 0.0);
+    chain_backward(D, l, kYPitch, 0, m, m, FC, 0.0);
+  }
+  wave_sync();
+  if (ok)
+    for (uint32_t k = 0; k < npl; ++k) {
+      const uint32_t p = q + kGroups * k;
+      if (p < m) next[(size_t)(r0 + 1 + p) * W + x] = D[p * kYPitch + l];
+    }
+  wave_sync();
 }
 
 // Line nodes of level n+1 into the new field; a horizontal line leaves the nodes it shares with a
@@ -612,28 +599,22 @@ __device__ void write_lines(const AdiArgs& a, uint32_t item, uint32_t n, double*
 }
 
 __global__ __launch_bounds__(64) void adi_kernel(AdiArgs a) {
-  __shared__ double D[kLdsDoubles];
-  __shared__ double SB[2 * kLines];
-  __shared__ double FB[kTile];  // Thomas factors of the current tile
+  extern __shared__ double smem[];
   uint32_t gen = 0;
   const uint32_t nsub = a.px * a.py;
   const uint32_t x_items = nsub * a.x_blk;
   const uint32_t y_items = nsub * a.y_blk;
   const uint32_t l_items = a.n_vlines * a.bv + (a.n_lines - a.n_vlines) * a.bh;
+  // Items of a phase cost the same (equal subdomains), so they are dealt round-robin: no counter
+  // traffic between the barriers.
   for (uint32_t n = 0; n < a.steps; ++n) {
     const double* cur = (n & 1) ? a.f1 : a.f0;
     double* prev = (n & 1) ? a.f0 : a.f1;  // holds u^{n-1}; receives u^{n+1}
-    for (;;) {
-      const uint32_t it = grab(&a.sync[3 + 2 * n]);
-      if (it >= x_items) break;
-      x_sweep(a, it, n, cur, prev, D, SB, FB);
-    }
+    for (uint32_t it = blockIdx.x; it < x_items; it += gridDim.x) x_sweep(a, it, n, cur, prev, smem);
     if (!grid_barrier(a.sync, a.nblocks, gen, a.spin_limit)) return;
-    for (;;) {
-      const uint32_t it = grab(&a.sync[4 + 2 * n]);
-      if (it >= y_items + l_items) break;
+    for (uint32_t it = blockIdx.x; it < y_items + l_items; it += gridDim.x) {
       if (it < y_items)
-        y_sweep(a, it, n, cur, prev, D, FB);
+        y_sweep(a, it, n, cur, prev, smem);
       else
         write_lines(a, it - y_items, n, prev);
     }
@@ -672,6 +653,7 @@ struct brt_pdd {
   hipEvent_t ev[6] = {};
   bool recorded[3] = {false, false, false};
   int grid = 0;
+  size_t lds = 0;  // dynamic LDS of the solver launch (bytes)
 };
 
 namespace {
@@ -728,7 +710,7 @@ int brt_pdd_create(brt_ctx* ctx, const brt_problem* prob, const brt_pdd_grid* gr
   if (!(g.x_hi > g.x_lo) || !(g.y_hi > g.y_lo) || !std::isfinite(g.x_lo + g.x_hi + g.y_lo + g.y_hi))
     return set_error(BRT_E_ARG, "pdd: empty or non-finite domain");
   if (g.px < 1 || g.py < 1 || g.px > kMaxSub || g.py > kMaxSub) return set_error(BRT_E_ARG, "pdd: px, py must be 1..64");
-  if (g.cx < 2 || g.cy < 2 || g.cx > kMaxCells || g.cy > kMaxCells) return set_error(BRT_E_ARG, "pdd: cx, cy must be 2..4096");
+  if (g.cx < 2 || g.cy < 2 || g.cx > kMaxCells || g.cy > kMaxCells) return set_error(BRT_E_ARG, "pdd: cx, cy must be 2..1024");
   if (!(g.T > 0.0) || !std::isfinite(g.T)) return set_error(BRT_E_ARG, "pdd: T must be > 0");
   if (g.n_steps < 1 || g.n_steps > (1u << 20)) return set_error(BRT_E_ARG, "pdd: n_steps must be 1..2^20");
   if (g.ns_x < 4 || g.ns_y < 4 || g.ns_x > kMaxNodesPerLine || g.ns_y > kMaxNodesPerLine)
@@ -843,10 +825,15 @@ int brt_pdd_create(brt_ctx* ctx, const brt_problem* prob, const brt_pdd_grid* gr
   }
   if (rc == BRT_OK) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&adi_kernel), kLanes, 0) !=
-            hipSuccess ||
-        per_cu < 1)
-      rc = set_error(BRT_E_DEVICE, "pdd: solver occupancy query");
+    p->lds = 8 * std::max(x_lds(g.cx - 1), y_lds(g.cy - 1));
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&adi_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)p->lds) != hipSuccess)
+      rc = set_error(BRT_E_DEVICE, "pdd: solver LDS of %zu bytes", p->lds);
+    if (rc == BRT_OK &&
+        (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&adi_kernel), kLanes,
+                                                      p->lds) != hipSuccess ||
+         per_cu < 1))
+      rc = set_error(BRT_E_DEVICE, "pdd: solver occupancy query (LDS %zu bytes)", p->lds);
     const uint32_t nsub = g.px * g.py;
     const uint32_t x_items = nsub * ((g.cy - 1 + kLines - 1) / kLines);
     const uint32_t y_items = nsub * ((g.cx - 1 + kLines - 1) / kLines);
@@ -977,10 +964,10 @@ int brt_pdd_solve(brt_pdd* p, uint32_t steps, double* field, void* stream) {
   int rate_khz = 0;
   PDD_TRY(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, p->device));
   a.spin_limit = (uint64_t)(kBarrierSeconds * 1e3 * (rate_khz > 0 ? rate_khz : 100000));
-  for (int j = 0; j < 8; ++j) a.coef[j] = a.pcoef[j] = p->prob.coef[j];
+  for (int j = 0; j < 8; ++j) a.pcoef[j] = p->prob.coef[j];
   a.pcoef[1] = 0.0;
-  a.cmod = p->prob.coef_mod == BRT_COEF_MOD_GAUSS_TIME ? 1u : 0u;
-  a.cm_pow = p->prob.coef_mod_pow;
+  const bool cmod = p->prob.coef_mod == BRT_COEF_MOD_GAUSS_TIME;
+  a.cm_pow = cmod ? p->prob.coef_mod_pow : 0u;
   a.cm_t0 = p->prob.coef_mod_t0;
   a.c1 = p->prob.coef[1];
   a.dt = p->dt;
@@ -1005,7 +992,8 @@ int brt_pdd_solve(brt_pdd* p, uint32_t steps, double* field, void* stream) {
   std::memcpy(a.vline, p->vline, sizeof(a.vline));
   std::memcpy(a.hline, p->hline, sizeof(a.hline));
   void* kargs[] = {&a};
-  PDD_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&adi_kernel), dim3(p->grid), dim3(kLanes), kargs, 0, s));
+  PDD_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&adi_kernel), dim3(p->grid), dim3(kLanes), kargs,
+                                     (unsigned)p->lds, s));
   const double* result = (steps & 1) ? p->d_f[1] : p->d_f[0];
   PDD_TRY(hipMemcpyAsync(field, result, 8 * (size_t)(p->NX + 1) * (p->NY + 1), hipMemcpyDeviceToDevice, s));
   PDD_TRY(hipEventRecord(p->ev[5], s));
