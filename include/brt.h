@@ -222,9 +222,9 @@ int brt_solve(brt_ctx* ctx, uint32_t n_problems, const brt_problem* problems, co
               const brt_points* points, const brt_out* out, void* stream);
 
 /* Autotuner: time the tree walker for candidate launch settings (waves per block 1/2/4, LDS stack
- * levels 4..16, chunk sizes 256/1024/4096 trees) on a subsample (about 2^26 trees, fastest of three runs) of the given
- * points, set the fastest on the context (used by plans and servers created afterwards) and write it
- * to *best (nullable).  cache_path (nullable) is a JSON-lines file keyed by the GPU architecture and
+ * levels 4..16, chunk sizes 256/1024/4096 trees) on the given points (subsampled to about 2^28 trees
+ * when larger; fastest of three runs), set the fastest on the context (used by plans and servers
+ * created afterwards) and write it to *best (nullable).  cache_path (nullable) is a JSON-lines file keyed by the GPU architecture and
  * the workload shape (precision, dim, initial-data family, arities, order, pruning): a cached entry
  * is applied without timing, a new result is appended.  Synchronises the device. */
 int brt_autotune(brt_ctx* ctx, uint32_t n_problems, const brt_problem* problems, const brt_mc* mc,

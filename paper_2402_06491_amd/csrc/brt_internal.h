@@ -158,8 +158,9 @@ hipError_t launch_walk(int precision, int dim, int u0_kind, const WalkArgs& a, i
                        hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s);
-size_t walk_lds_bytes(int precision, int dim, int stack_depth, int waves_per_block, int n_problems);
-size_t stack_entry_size(int precision, int dim);
-int walk_max_blocks_per_cu(int precision, int dim, int u0_kind, int n_problems, int stack_depth, int waves_per_block);
+size_t walk_lds_bytes(int precision, int dim, int stack_depth, int waves_per_block, int n_problems, int strategy);
+size_t stack_entry_size(int precision, int dim);  // bytes of one spill level (full layout)
+int walk_max_blocks_per_cu(int precision, int dim, int u0_kind, int n_problems, int stack_depth, int waves_per_block,
+                           int strategy);
 
 }  // namespace brt

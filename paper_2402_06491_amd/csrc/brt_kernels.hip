@@ -148,6 +148,13 @@ __host__ __device__ constexpr size_t stack_entry_bytes() {
   return sizeof(double) + (DIM + 1) * sizeof(Real) + 1;
 }
 
+// LDS bytes of one stack level of one lane.  Strategy A keeps the lineage's clock product (the time left
+// follows from it, t + ln(P)/lambda); Strategy B, which has no clock, keeps the time left instead.
+template <typename Real, int DIM, int STRAT>
+__host__ __device__ constexpr size_t stack_lds_entry_bytes() {
+  return (STRAT == 0 ? sizeof(double) : sizeof(Real)) + DIM * sizeof(Real) + 1;
+}
+
 template <typename Real>
 __host__ __device__ constexpr size_t pde_table_bytes(int n) {
   return ((size_t)n * sizeof(PdeT<Real>) + 15) & ~(size_t)15;
@@ -161,13 +168,14 @@ __host__ __device__ constexpr size_t pde_table_bytes(int n) {
 // ------------------------------------------------------------------------------------------------
 #define BRT_LDS __attribute__((address_space(3)))
 
-template <typename Real, int DIM>
+template <typename Real, int DIM, int STRAT>
 struct Stack {
   // LDS pointers carry their address space so that the compiler keeps ds_* instructions for them
-  // instead of merging both tiers into generic (flat) accesses through a selected pointer.
-  BRT_LDS double* P;   // [lds_depth][64]
+  // instead of merging both tiers into generic (flat) accesses through a selected pointer.  LDS levels
+  // hold P (Strategy A) or T (Strategy B), never both; the spill levels keep the full layout.
+  BRT_LDS double* P;   // [lds_depth][64], Strategy A
   BRT_LDS Real* X;     // [DIM][lds_depth][64]
-  BRT_LDS Real* T;     // [lds_depth][64]
+  BRT_LDS Real* T;     // [lds_depth][64], Strategy B
   BRT_LDS uint8_t* R;  // [lds_depth][64]
   double* gP;          // this thread's spill levels: [spill_depth]
   Real* gX;            // [DIM][spill_depth]
@@ -178,39 +186,40 @@ struct Stack {
   __device__ __forceinline__ void push(uint32_t sp, double p, const Real* x, Real t, uint32_t rem) {
     if (sp < lds_depth) {
       const uint32_t o = sp * kWave + lane;
-      P[o] = p;
+      if constexpr (STRAT == 0) P[o] = p;
+      else T[o] = t;
       X[o] = x[0];
       if constexpr (DIM == 2) X[lds_depth * kWave + o] = x[1];
-      T[o] = t;
       R[o] = (uint8_t)rem;
     } else {
       const uint32_t o = sp - lds_depth;
-      gP[o] = p;
+      if constexpr (STRAT == 0) gP[o] = p;
+      else gT[o] = t;
       gX[o] = x[0];
       if constexpr (DIM == 2) gX[spill_depth + o] = x[1];
-      gT[o] = t;
       gR[o] = (uint8_t)rem;
     }
   }
-  // Read the top entry (level sp-1) into the departure state; returns the number of children still
-  // to start after the one about to be visited, and stores it back.
+  // Read the top entry (level sp-1) into the departure state (P for Strategy A, whose time left the
+  // caller derives from it; the time left for Strategy B); returns the number of children still to
+  // start after the one about to be visited, and stores it back.
   __device__ __forceinline__ uint32_t top(uint32_t sp, double* p, Real* x, Real* t) {
     const uint32_t lv = sp - 1;
     uint32_t rem;
     if (lv < lds_depth) {
       const uint32_t o = lv * kWave + lane;
-      *p = P[o];
+      if constexpr (STRAT == 0) *p = P[o];
+      else *t = T[o];
       x[0] = X[o];
       if constexpr (DIM == 2) x[1] = X[lds_depth * kWave + o];
-      *t = T[o];
       rem = (uint32_t)R[o] - 1u;
       R[o] = (uint8_t)rem;
     } else {
       const uint32_t o = lv - lds_depth;
-      *p = gP[o];
+      if constexpr (STRAT == 0) *p = gP[o];
+      else *t = gT[o];
       x[0] = gX[o];
       if constexpr (DIM == 2) x[1] = gX[spill_depth + o];
-      *t = gT[o];
       rem = (uint32_t)gR[o] - 1u;
       gR[o] = (uint8_t)rem;
     }
@@ -242,15 +251,16 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
 
   const uint32_t lane = __lane_id();
   const uint32_t wave = threadIdx.x / kWave;
-  Stack<Real, DIM> st;
+  Stack<Real, DIM, STRAT> st;
   {
     const uint32_t depth = a.stack_depth;
     unsigned char* wbase = smem + pde_table_bytes<Real>(a.n_problems) +
-                           (size_t)wave * depth * kWave * stack_entry_bytes<Real, DIM>();
+                           (size_t)wave * depth * kWave * stack_lds_entry_bytes<Real, DIM, STRAT>();
+    // Strategy A: [P double][X DIM reals][R bytes]; Strategy B: [X DIM reals][T reals][R bytes]
     st.P = (BRT_LDS double*)(wbase);
-    st.X = (BRT_LDS Real*)(st.P + depth * kWave);
+    st.X = STRAT == 0 ? (BRT_LDS Real*)(st.P + depth * kWave) : (BRT_LDS Real*)(wbase);
     st.T = st.X + DIM * depth * kWave;
-    st.R = (BRT_LDS uint8_t*)(st.T + depth * kWave);
+    st.R = STRAT == 0 ? (BRT_LDS uint8_t*)(st.X + DIM * depth * kWave) : (BRT_LDS uint8_t*)(st.T + depth * kWave);
     // spill area: per thread, stride-1 levels (deep levels are rare, so coalescing does not matter)
     const size_t gtid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t sd = (size_t)a.spill_depth * a.n_threads;
@@ -289,6 +299,7 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
   double P = 1.0, theta = 1.0;
   double F = 1.0;  // running product of the tree's factors (FP64 for range: weights reach e^{32} per vertex)
   Real tau = 0;
+  Real troot = 0;  // the point's time: Strategy A derives a sibling's time left from it and the clock product
   Real x[2] = {0, 0};
 
   while (true) {
@@ -329,6 +340,7 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
           rec = c_base + c_next + rank;
           theta = c_theta;
           tau = c_t;
+          troot = c_t;
           x[0] = c_x0;
           x[1] = c_x1;
           P = 1.0;
@@ -444,6 +456,13 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
       } else {
         const uint32_t rem = st.top(sp, &P, x, &tau);
         if (rem == 0) sp -= 1;
+        if constexpr (STRAT == 0) {
+          // the time left at the split: the point's time less the lineage's exponential times, which
+          // sum to -ln(P)/lambda
+          const PdeT<Real>& pdp = pdes[MULTI ? pde_lane : 0u];
+          const Real tl = troot + Math<Real>::ln((Real)P) * pdp.inv_lambda;
+          tau = tl < (Real)0 ? (Real)0 : tl;
+        }
       }
     }
     if (done) {
@@ -470,10 +489,16 @@ size_t stack_entry_size(int precision, int dim) {
   return dim == 1 ? stack_entry_bytes<double, 1>() : stack_entry_bytes<double, 2>();
 }
 
-size_t walk_lds_bytes(int precision, int dim, int stack_depth, int waves_per_block, int n_problems) {
+template <typename Real>
+static size_t lds_entry(int dim, int strategy) {
+  if (dim == 1) return strategy ? stack_lds_entry_bytes<Real, 1, 1>() : stack_lds_entry_bytes<Real, 1, 0>();
+  return strategy ? stack_lds_entry_bytes<Real, 2, 1>() : stack_lds_entry_bytes<Real, 2, 0>();
+}
+
+size_t walk_lds_bytes(int precision, int dim, int stack_depth, int waves_per_block, int n_problems, int strategy) {
   const size_t sd = (size_t)stack_depth * kWave * waves_per_block;
-  if (precision == 32) return pde_table_bytes<float>(n_problems) + sd * stack_entry_size(32, dim);
-  return pde_table_bytes<double>(n_problems) + sd * stack_entry_size(64, dim);
+  if (precision == 32) return pde_table_bytes<float>(n_problems) + sd * lds_entry<float>(dim, strategy);
+  return pde_table_bytes<double>(n_problems) + sd * lds_entry<double>(dim, strategy);
 }
 
 template <typename Real, int DIM, int U0, bool MULTI, int MODE>
@@ -512,12 +537,14 @@ static const void* walk_fn(int precision, int dim, int u0, bool multi, int mode)
   return dim == 1 ? walk_ptr_m<double, 1>(u0, multi, mode) : walk_ptr_m<double, 2>(u0, multi, mode);
 }
 
-int walk_max_blocks_per_cu(int precision, int dim, int u0_kind, int n_problems, int stack_depth, int waves_per_block) {
+int walk_max_blocks_per_cu(int precision, int dim, int u0_kind, int n_problems, int stack_depth, int waves_per_block,
+                           int strategy) {
   int nb = 0;
-  const size_t lds = walk_lds_bytes(precision, dim, stack_depth, waves_per_block, n_problems);
-  // the smallest occupancy over the strategy / coefficient variants, so a grid sized by it stays resident
+  const size_t lds = walk_lds_bytes(precision, dim, stack_depth, waves_per_block, n_problems, strategy);
+  // the smaller occupancy of the strategy's variants with and without variable coefficients, so a grid
+  // sized by it stays resident
   int best = 1 << 30;
-  for (int mode = 0; mode < 4; ++mode) {
+  for (int mode = strategy; mode < 4; mode += 2) {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_fn(precision, dim, u0_kind, n_problems > 1, mode),
                                                      waves_per_block * kWave, lds) != hipSuccess)
       return 0;
@@ -533,7 +560,8 @@ hipError_t launch_reset(uint32_t* chunk_counter, unsigned long long* depth_count
 
 hipError_t launch_walk(int precision, int dim, int u0_kind, const WalkArgs& a, int grid, int waves_per_block,
                        hipStream_t s) {
-  const size_t lds = walk_lds_bytes(precision, dim, (int)a.stack_depth, waves_per_block, (int)a.n_problems);
+  const size_t lds = walk_lds_bytes(precision, dim, (int)a.stack_depth, waves_per_block, (int)a.n_problems,
+                                    (int)a.strategy);
   const void* fn = walk_fn(precision, dim, u0_kind, a.n_problems > 1, (int)(a.strategy | (a.cmod ? 2u : 0u)));
   void* args[] = {const_cast<WalkArgs*>(&a)};
   return hipLaunchKernel(fn, dim3(grid), dim3(waves_per_block * kWave), args, lds, s);

@@ -467,10 +467,12 @@ extern "C" int brt_plan_create(brt_ctx* ctx, uint32_t n_problems, const brt_prob
 
   // persistent grid: as many blocks as are resident at once
   int bpc = (int)ctx->launch.blocks_per_cu;
-  int maxb = walk_max_blocks_per_cu(p->precision, p->dim, p->u0_kind, (int)p->n_problems, p->stack_depth, p->waves_per_block);
+  int maxb = walk_max_blocks_per_cu(p->precision, p->dim, p->u0_kind, (int)p->n_problems, p->stack_depth, p->waves_per_block,
+                                 (int)p->mc.strategy);
   while (maxb <= 0 && p->waves_per_block > 1) {  // shrink the block until its LDS fits
     p->waves_per_block -= 1;
-    maxb = walk_max_blocks_per_cu(p->precision, p->dim, p->u0_kind, (int)p->n_problems, p->stack_depth, p->waves_per_block);
+    maxb = walk_max_blocks_per_cu(p->precision, p->dim, p->u0_kind, (int)p->n_problems, p->stack_depth, p->waves_per_block,
+                                 (int)p->mc.strategy);
   }
   if (maxb <= 0) {
     plan_free(p);

@@ -408,10 +408,12 @@ int brt_server_create(brt_ctx* ctx, const brt_server_opts* o, brt_server** out) 
   const uint32_t needed = mc.prune ? std::max(1u, mc.max_order) : kMaxDepthUnpruned;
   s->lds_depth = (int)std::min(needed, lc.stack_depth ? lc.stack_depth : kDefaultLdsLevels);
   s->spill_depth = (int)(needed - (uint32_t)s->lds_depth);
-  int maxb = walk_max_blocks_per_cu((int)mc.precision, (int)o->dim, (int)o->u0_kind, kMaxProblems, s->lds_depth, s->wpb);
+  int maxb = walk_max_blocks_per_cu((int)mc.precision, (int)o->dim, (int)o->u0_kind, kMaxProblems, s->lds_depth, s->wpb,
+                                 (int)mc.strategy);
   while (maxb <= 0 && s->wpb > 1) {
     s->wpb -= 1;
-    maxb = walk_max_blocks_per_cu((int)mc.precision, (int)o->dim, (int)o->u0_kind, kMaxProblems, s->lds_depth, s->wpb);
+    maxb = walk_max_blocks_per_cu((int)mc.precision, (int)o->dim, (int)o->u0_kind, kMaxProblems, s->lds_depth, s->wpb,
+                                 (int)mc.strategy);
   }
   if (maxb <= 0) {
     server_free(s);

@@ -87,12 +87,13 @@ extern "C" int brt_autotune(brt_ctx* ctx, uint32_t n_problems, const brt_problem
     return BRT_OK;
   }
 
-  // subsample: every point keeps its share, about 2^26 trees in total, at least 1024 each (long enough that
-  // the drain of the persistent grid at the end of a launch does not decide the ranking)
+  // subsample: every point keeps its share, at most about 2^28 trees in total (workloads below that are
+  // timed whole), at least 1024 each; shorter samples let the drain of the persistent grid at the end of
+  // a launch decide the ranking
   uint64_t total = 0;
   for (uint32_t i = 0; i < pts->n; ++i) total += pts->n_trees[i];
   if (total == 0) return set_error(BRT_E_ARG, "brt_autotune: no trees to time");
-  const double frac = std::min(1.0, (double)(1u << 26) / (double)total);
+  const double frac = std::min(1.0, (double)(1u << 28) / (double)total);
   std::vector<uint64_t> sub(pts->n);
   for (uint32_t i = 0; i < pts->n; ++i)
     sub[i] = pts->n_trees[i] ? std::max<uint64_t>(std::min<uint64_t>(1024, pts->n_trees[i]),
