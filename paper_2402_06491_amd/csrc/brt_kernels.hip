@@ -86,21 +86,51 @@ struct Math<double> {
 // ------------------------------------------------------------------------------------------------
 // Initial data g at the end of a leaf path.
 // ------------------------------------------------------------------------------------------------
-// Logistic initial data A (1 + e^{s (n.x - x0)})^{-p}, split around its exponential.
+// The problem constants the node step reads every time.  With one problem per launch they are loaded
+// once, before the loop, and stay in scalar registers; with several they come from the LDS table.
+template <typename Real>
+struct HotC {
+  Real sigma, inv_lambda, mu, inv_q, s_scale;
+  uint32_t K, jpack, q_lo, cmod, cm_pow;
+  Real cm_bx, cm_by, cm_t0;
+  Real g[6];  // first initial-data parameters (the logistic family's A, s, x0, p, n0, n1)
+};
+
+template <typename Real>
+__device__ __forceinline__ HotC<Real> hot_of(const PdeT<Real>& pd) {
+  HotC<Real> h;
+  h.sigma = pd.sigma;
+  h.inv_lambda = pd.inv_lambda;
+  h.mu = pd.mu;
+  h.inv_q = pd.inv_q;
+  h.s_scale = pd.s_scale;
+  h.K = pd.K;
+  h.jpack = pd.jpack;
+  h.q_lo = pd.q_lo;
+  h.cmod = pd.cmod;
+  h.cm_pow = pd.cm_pow;
+  h.cm_bx = pd.cm_bx;
+  h.cm_by = pd.cm_by;
+  h.cm_t0 = pd.cm_t0;
+  for (int i = 0; i < 6; ++i) h.g[i] = pd.u0[i];
+  return h;
+}
+
+// Logistic initial data A (1 + e^{s (n.x - x0)})^{-p}, split around its exponential; g = (A, s, x0, p, n0, n1).
 template <typename Real, int DIM>
-__device__ __forceinline__ Real logistic_arg(const PdeT<Real>& pd, const Real* x) {
-  Real nx = x[0] * pd.u0[4];
-  if constexpr (DIM == 2) nx += x[1] * pd.u0[5];
-  return pd.u0[1] * (nx - pd.u0[2]);
+__device__ __forceinline__ Real logistic_arg(const Real* g, const Real* x) {
+  Real nx = x[0] * g[4];
+  if constexpr (DIM == 2) nx += x[1] * g[5];
+  return g[1] * (nx - g[2]);
 }
 
 template <typename Real>
-__device__ __forceinline__ Real logistic_finish(const PdeT<Real>& pd, Real e) {
+__device__ __forceinline__ Real logistic_finish(const Real* g, Real e) {
   const Real base = Math<Real>::rcp((Real)1 + e);
   Real r = base;
-  const int pw = (int)pd.u0[3];
+  const int pw = (int)g[3];
   for (int i = 1; i < pw; ++i) r *= base;
-  return pd.u0[0] * r;
+  return g[0] * r;
 }
 
 template <typename Real, int DIM, int U0>
@@ -109,7 +139,7 @@ __device__ __forceinline__ Real eval_g(const PdeT<Real>& pd, const Real* x) {
   if constexpr (U0 == 0) {
     return p[0];
   } else if constexpr (U0 == 1) {
-    return logistic_finish<Real>(pd, Math<Real>::ex(logistic_arg<Real, DIM>(pd, x)));
+    return logistic_finish<Real>(pd.u0, Math<Real>::ex(logistic_arg<Real, DIM>(pd.u0, x)));
   } else if constexpr (U0 == 2) {
     Real acc = 0;
     for (uint32_t k = 0; k < pd.u0_nterms; ++k) {
@@ -276,6 +306,8 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
   const uint32_t max_depth = a.stack_depth + a.spill_depth;
 
   const uint64_t lt = lanemask_lt();
+  // one problem: its constants loaded once (uniform, scalar registers)
+  const HotC<Real> h0 = hot_of(*reinterpret_cast<const PdeT<Real>*>(a.pdes));
   const uint32_t node_cap = a.node_cap;
   const uint32_t max_order = a.max_order;
   const bool prune = a.prune != 0;
@@ -360,7 +392,8 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
     }
     if (!active) continue;
 
-    const PdeT<Real>& pd = pdes[MULTI ? pde_lane : 0u];
+    const PdeT<Real>& pd = pdes[MULTI ? pde_lane : 0u];  // per-arity weights and the other data families
+    const HotC<Real> hc = MULTI ? hot_of(pd) : h0;
 
     // ---- one node of this lane's tree ----
     // Vertex and leaf quantities are computed for every lane and chosen with selects; only the stack
@@ -376,16 +409,16 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
       const double U = fma((double)w.a, 0x1p-32, 0x1p-33);  // (w0 + 1/2) 2^-32, exact
       Pn = P * U;
       vertex = !capped && Pn > theta;
-      S = -Math<Real>::ln((Real)U) * pd.inv_lambda;
+      S = -Math<Real>::ln((Real)U) * hc.inv_lambda;
       tau2 = tau - S;
       tau2 = tau2 < (Real)0 ? (Real)0 : tau2;
     } else {
       // Strategy B: coin w0 >= Q; the split comes after the fraction V = (w0 - Q + 1/2)/(2^32 - Q)
       // of tau.  tau (1 - V) comes from the complementary count 2^32 - w0 - 1/2, free of the
       // cancellation of tau - S near V = 1 (it multiplies the weights of the vertex's children).
-      vertex = !capped && w.a > pd.q_lo;
-      const Real ts = tau * pd.s_scale;
-      S = ((Real)(w.a - pd.q_lo - 1u) + (Real)0.5) * ts;
+      vertex = !capped && w.a > hc.q_lo;
+      const Real ts = tau * hc.s_scale;
+      S = ((Real)(w.a - hc.q_lo - 1u) + (Real)0.5) * ts;
       tau2 = ((Real)(~w.a) + (Real)0.5) * ts;
     }
 
@@ -394,33 +427,33 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
     const Real r = Math<Real>::sq((Real)-2 * Math<Real>::ln(u1));
     Real sn, cs;
     Math<Real>::sincos_rev(u2, &sn, &cs);
-    const Real sd = pd.sigma * Math<Real>::sq(vertex ? S : tau);
+    const Real sd = hc.sigma * Math<Real>::sq(vertex ? S : tau);
     Real xn[2];
     xn[0] = x[0] + sd * (r * cs);
     xn[1] = x[1] + sd * (r * sn);
 
     // one exponential per node: the vertex weight e^{(alpha-1) mu tau'} or, for logistic initial
     // data, e^{s (n.x - x0)} at the leaf
-    const uint32_t idx = __umulhi(w.b, pd.K);
-    const uint32_t alpha = (pd.jpack >> (4 * idx)) & 15u;
-    Real earg = (Real)((int)alpha - 1) * pd.mu * tau2;
+    const uint32_t idx = __umulhi(w.b, hc.K);
+    const uint32_t alpha = (hc.jpack >> (4 * idx)) & 15u;
+    Real earg = (Real)((int)alpha - 1) * hc.mu * tau2;
     // variable coefficients: c_j exp(-bx x^2 - by y^2) (tau' + t0)^(-pow) at the split, folded into the
     // vertex's exponential
     Real cscale = (Real)1;
     if constexpr (CMOD) {
-      if (pd.cmod) {
-        earg -= pd.cm_bx * (xn[0] * xn[0]) + (DIM == 2 ? pd.cm_by * (xn[1] * xn[1]) : (Real)0);
-        if (pd.cm_pow) cscale = (Real)1 / (tau2 + pd.cm_t0);
+      if (hc.cmod) {
+        earg -= hc.cm_bx * (xn[0] * xn[0]) + (DIM == 2 ? hc.cm_by * (xn[1] * xn[1]) : (Real)0);
+        if (hc.cm_pow) cscale = (Real)1 / (tau2 + hc.cm_t0);
       }
     }
-    if constexpr (U0 == 1) earg = vertex ? earg : logistic_arg<Real, DIM>(pd, xn);
+    if constexpr (U0 == 1) earg = vertex ? earg : logistic_arg<Real, DIM>(hc.g, xn);
     const Real E = Math<Real>::ex(earg);
     // Strategy B's vertex weight carries the time left tau (eta(t) = t) and its leaves divide by q
     const Real wscale = (STRAT == 1 ? tau : (Real)1) * cscale;
-    const Real lscale = STRAT == 1 ? pd.inv_q : (Real)1;
+    const Real lscale = STRAT == 1 ? hc.inv_q : (Real)1;
     Real factor;
     if constexpr (U0 == 1) {
-      factor = vertex ? wscale * pd.omega[idx] * E : lscale * logistic_finish<Real>(pd, E);
+      factor = vertex ? wscale * pd.omega[idx] * E : lscale * logistic_finish<Real>(hc.g, E);
     } else {
       if (vertex)
         factor = wscale * pd.omega[idx] * E;
@@ -459,8 +492,7 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
         if constexpr (STRAT == 0) {
           // the time left at the split: the point's time less the lineage's exponential times, which
           // sum to -ln(P)/lambda
-          const PdeT<Real>& pdp = pdes[MULTI ? pde_lane : 0u];
-          const Real tl = troot + Math<Real>::ln((Real)P) * pdp.inv_lambda;
+          const Real tl = troot + Math<Real>::ln((Real)P) * hc.inv_lambda;
           tau = tl < (Real)0 ? (Real)0 : tl;
         }
       }
