@@ -8,9 +8,10 @@
 //   spline_t_kernel     one thread per (line, fine node): spline in time, written at every time level
 //   init_field_kernel   u0 at every grid node, line data at level 0
 //   adi_kernel          persistent cooperative launch through all time steps: per step an x phase and
-//                       a y phase; a work item is 64 lines of one subdomain (one lane per line, the
-//                       tridiagonal system solved by the Thomas recurrence with precomputed factors),
-//                       taken from a per-phase counter; a grid barrier separates the phases.
+//                       a y phase separated by grid barriers; a work item is 16 lines of one subdomain
+//                       held in LDS by a block of 512 threads, each line's tridiagonal system solved
+//                       by 32 threads (segments of consecutive unknowns joined by scans of their
+//                       carries), items dealt round-robin.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -26,12 +27,16 @@ using brt::set_error;
 
 namespace {
 
-constexpr int kLanes = 64;
 constexpr uint32_t kMaxSub = 64;
 constexpr uint32_t kMaxCells = 1024;
 constexpr uint32_t kMaxNodesPerLine = 257;
 constexpr uint32_t kMaxNt = 63;
 constexpr double kBarrierSeconds = 5.0;
+// Solver fields are stored with a row pitch of a multiple of 16 doubles and column 1 (the first
+// interior column) on a 128-byte boundary, so that the solver's 16-column strips and 64-column row
+// tiles map onto whole cache lines.
+constexpr uint32_t kFieldLead = 15;  // doubles before column 0
+constexpr uint32_t kXcds = 8;        // workgroups are dealt to the accelerator's dies round-robin
 
 #define PDD_TRY(expr)                                                                               \
   do {                                                                                              \
@@ -206,7 +211,7 @@ struct FieldArgs {
   double* f1;
   const double* bd;
   const LineDev* lines;
-  uint32_t NX, NY, cx, cy, zero_outer;
+  uint32_t NX, NY, W, cx, cy, zero_outer;  // W: row pitch of the fields
   double x_lo, y_lo, hx, hy;
   int16_t vline[kMaxSub + 1];
   int16_t hline[kMaxSub + 1];
@@ -229,7 +234,7 @@ __global__ void init_field_kernel(FieldArgs a) {
   } else if (a.zero_outer && (i == 0 || i == a.NX || j == 0 || j == a.NY)) {
     v = 0.0;
   }
-  const size_t idx = (size_t)j * (a.NX + 1) + i;
+  const size_t idx = (size_t)j * a.W + i;
   a.f0[idx] = v;
   a.f1[idx] = v;
 }
@@ -240,10 +245,8 @@ struct AdiArgs {
   double* star;
   const double* bd;
   const LineDev* lines;
-  const double* inv_x;
-  const double* cp_x;
+  const double* inv_x;  // pivots' reciprocals of the x and the y lines, kSegs * S each, zero-padded
   const double* inv_y;
-  const double* cp_y;
   uint32_t* sync;       // [0] arrivals, [1] generation, [2] abort, [3 + 2n], [4 + 2n] work counters of step n
   uint64_t spin_limit;  // wall-clock ticks a barrier may wait
   double pcoef[8];      // f(u) = c_1 u + m(x, y, t) sum_{j != 1} c_j u^j: the non-linear part (c_1 zeroed) ...
@@ -252,15 +255,17 @@ struct AdiArgs {
   uint32_t cm_pow;
   double cm_t0, c1, dt;
   double rx2, ry2, dt2;
-  uint32_t W;           // row stride NX + 1
+  uint32_t W;           // row pitch of the fields (a multiple of 16)
   uint32_t px, py, cx, cy;
   uint32_t steps;
   uint32_t nblocks;
-  uint32_t x_blk, y_blk;       // 64-line blocks per subdomain in the x and the y phase
-  uint32_t n_vlines, bv, bh;   // data lines: vertical count; 64-node blocks per vertical / horizontal line
+  uint32_t x_blk, y_blk;       // items (kLines lines) per subdomain in the x and the y phase
+  uint32_t n_vlines, bv, bh;   // data lines: vertical count; blocks of nodes per vertical / horizontal line
   uint32_t n_lines;
   int16_t vline[kMaxSub + 1];
   int16_t hline[kMaxSub + 1];
+  uint32_t v_fine, h_fine;               // fine nodes of a vertical and of a horizontal line
+  uint64_t bd_off[2 * (kMaxSub + 1)];    // boundary data offset of each line (doubles)
 };
 
 __device__ inline double reaction(const double* c, double u) {
@@ -282,10 +287,10 @@ __device__ inline double time_factor(const AdiArgs& a, uint32_t n) {
 // Grid barrier (sense by generation count).  Every block waits at most spin_limit wall-clock ticks; on
 // a time-out, or when another block has timed out, it raises the abort word and returns false so that
 // every block leaves the kernel.
-__device__ bool grid_barrier(uint32_t* sync, uint32_t nblocks, uint32_t& gen, uint64_t spin_limit) {
+__device__ bool grid_barrier(uint32_t* sync, uint32_t nblocks, uint32_t& gen, uint64_t spin_limit, uint32_t* flag) {
   __syncthreads();
-  int ok = 1;
   if (threadIdx.x == 0) {
+    uint32_t ok = 1;
     __threadfence();
     const uint32_t target = gen + 1;
     if (atomicAdd(&sync[0], 1u) == nblocks - 1) {
@@ -307,19 +312,18 @@ __device__ bool grid_barrier(uint32_t* sync, uint32_t nblocks, uint32_t& gen, ui
     }
     __threadfence();
     gen = target;
+    *flag = ok;
   }
-  ok = __shfl(ok, 0);
-  gen = __shfl(gen, 0);
-  return ok != 0;
+  __syncthreads();
+  return *flag != 0;
 }
 
 // Intermediate-level value on the vertical line kx at row y between levels n and n+1.
 __device__ inline double ustar_line(const AdiArgs& a, uint32_t kx, uint32_t y, uint32_t n) {
   const int vl = a.vline[kx];
   if (vl < 0) return 0.0;
-  const LineDev& L = a.lines[vl];
-  const double* g0 = a.bd + L.bd_off + (size_t)n * L.n_fine;
-  const double* g1 = g0 + L.n_fine;
+  const double* g0 = a.bd + a.bd_off[vl] + (size_t)n * a.v_fine;
+  const double* g1 = g0 + a.v_fine;
   const double d0 = (g0[y - 1] - 2.0 * g0[y]) + g0[y + 1];
   const double d1 = (g1[y - 1] - 2.0 * g1[y]) + g1[y + 1];
   return 0.5 * (g0[y] + a.ry2 * d0) + 0.5 * (g1[y] - a.ry2 * d1);
@@ -329,249 +333,267 @@ __device__ inline double ustar_line(const AdiArgs& a, uint32_t kx, uint32_t y, u
 __device__ inline double hline_value(const AdiArgs& a, uint32_t ky, uint32_t x, uint32_t n) {
   const int hl = a.hline[ky];
   if (hl < 0) return 0.0;
-  const LineDev& L = a.lines[hl];
-  return a.bd[L.bd_off + (size_t)n * L.n_fine + x];
+  return a.bd[a.bd_off[hl] + (size_t)n * a.h_fine + x];
 }
 
-// A work item is kLines lines of one subdomain, resident in LDS for the whole sweep: the right-hand
-// sides of all its positions are formed first from global loads issued in large batches (lanes along
-// the positions in the x phase; 16 lines x 4 position groups in the y phase), the forward and the
-// backward Thomas recurrences then run from LDS with one lane per line and the factors of the
-// direction in LDS, and the solution goes back to global memory once.  Subdomains have at most 1024
-// cells per side so that 16 lines fit beside the factors.
+// A work item is kLines lines of one subdomain, solved by one block of kAdiThreads threads with the
+// lines resident in LDS.  Three passes:
+//   1. the right-hand sides, from coalesced global loads (x phase: threads along the positions of the
+//      item's rows; y phase: 16 columns x 32 row groups), into LDS [line][position];
+//   2. the tridiagonal solves, kSegs threads per line, each owning S consecutive positions: a local
+//      forward recurrence, a scan of the segments' affine carry maps over the line's lanes, the carry
+//      applied, a local backward recurrence, a reverse scan, and the backward carry applied;
+//   3. the solution back to global memory with the thread mapping of pass 1.
+// In LDS a segment of S positions is followed by one pad double (conflict-free segment reads) and the
+// line pitch is 4 mod 32 doubles (conflict-free column writes in the y phase).  The pivots' reciprocals
+// of both directions stay in LDS for the whole launch, in the same segment layout.  Subdomains have at
+// most kSegs * 32 cells per side.
+constexpr int kAdiThreads = 512;
 constexpr int kLines = 16;
-constexpr int kTile = 64;                  // positions per x-phase load batch (one per lane)
-constexpr int kGroups = kLanes / kLines;   // position groups of the y phase
-constexpr int kYPitch = kLines + 1;        // y phase LDS [position][line]
-constexpr int kYBatch = 16;                // positions per lane loaded together in the y phase
+constexpr int kSegs = 32;                          // threads per line in pass 2
+constexpr int kRowGroups = kAdiThreads / kLines;   // y phase: row groups of pass 1 and 3
+constexpr int kXBatch = 16;                        // x phase: rows loaded together
+constexpr int kYBatch = 8;                         // y phase: positions per thread loaded together
 
-// LDS (doubles) of a sweep over lines of m unknowns: x phase [line][pitch] + factors + boundary values;
-// y phase [position][line] + factors.
-__host__ __device__ inline uint32_t x_pitch(uint32_t m) { return m | 1u; }
-__host__ __device__ inline size_t x_lds(uint32_t m) { return (size_t)kLines * x_pitch(m) + 2 * m + 3 * kLines; }
-__host__ __device__ inline size_t y_lds(uint32_t m) { return (size_t)m * kYPitch + 3 * m; }
+static_assert(kMaxCells - 1 <= (uint32_t)kSegs * 32, "the longest line must fit 32 segments of 32");
 
-// Work items run in single-wave blocks: LDS accesses of one wavefront are performed in order, so a
-// wavefront-scope fence (which also keeps the compiler from moving LDS accesses across it) replaces
-// a workgroup barrier, and no wait on outstanding global stores is forced between tiles.
-__device__ inline void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
+__host__ __device__ constexpr uint32_t seg_span(int S) { return (uint32_t)kSegs * (S + 1); }
+__host__ __device__ constexpr uint32_t seg_pitch(int S) { return seg_span(S) + 4; }
+// LDS (doubles): the lines, the pivots' reciprocals of the x and the y lines, then the intermediate
+// values on the item's two vertical data lines and the coefficient modulation of its rows (x phase).
+__host__ __device__ constexpr size_t adi_lds_doubles(int S) {
+  return (size_t)kLines * seg_pitch(S) + 2 * (size_t)seg_span(S) + 3 * kLines;
 }
 
-constexpr int kChain = 16;  // recurrence steps whose operands are loaded together
-
-// Forward Thomas recurrence over positions [p0, p0 + np) of one line whose right-hand sides sit in LDS
-// at D[off + c * stride]; d' replaces them.  Operands are fetched kChain at a time before use.
-__device__ inline double chain_forward(double* __restrict__ D, uint32_t off, uint32_t stride, uint32_t p0, uint32_t np,
-                                       const double* __restrict__ F, double r2, double dp) {
-  uint32_t cb = 0;
-  if (p0 == 0 && np > 0) {  // the first unknown has no predecessor
-    dp = D[off] * F[0];
-    D[off] = dp;
-    cb = 1;
-  }
-  for (; cb + kChain <= np; cb += kChain) {  // full batches: operands fetched together, no conditions
-    double dv[kChain], fv[kChain];
-#pragma unroll
-    for (int k = 0; k < kChain; ++k) {
-      dv[k] = D[off + (cb + k) * stride];
-      fv[k] = F[cb + k];
-    }
-#pragma unroll
-    for (int k = 0; k < kChain; ++k) {
-      dp = (dv[k] + r2 * dp) * fv[k];
-      dv[k] = dp;
-    }
-#pragma unroll
-    for (int k = 0; k < kChain; ++k) D[off + (cb + k) * stride] = dv[k];
-  }
-  for (; cb < np; ++cb) {
-    dp = (D[off + cb * stride] + r2 * dp) * F[cb];
-    D[off + cb * stride] = dp;
-  }
-  return dp;
+template <int S>
+__device__ inline uint32_t lds_pos(uint32_t p) {
+  return p + p / S;
 }
 
-// Backward substitution over positions [p0, p0 + np) in reverse; x of the last unknown (position m-1)
-// is its d'.
-__device__ inline double chain_backward(double* __restrict__ D, uint32_t off, uint32_t stride, uint32_t p0, uint32_t np,
-                                        uint32_t m, const double* __restrict__ F, double xv) {
-  int cb = (int)np - 1;
-  if (p0 + np == m && np > 0) {  // the last unknown is its own d'
-    xv = D[off + cb * stride];
-    --cb;
-  }
-  for (; cb - kChain + 1 >= 0; cb -= kChain) {
-    double dv[kChain], fv[kChain];
-#pragma unroll
-    for (int k = 0; k < kChain; ++k) {
-      dv[k] = D[off + (cb - k) * stride];
-      fv[k] = F[cb - k];
-    }
-#pragma unroll
-    for (int k = 0; k < kChain; ++k) {
-      xv = dv[k] - fv[k] * xv;
-      dv[k] = xv;
-    }
-#pragma unroll
-    for (int k = 0; k < kChain; ++k) D[off + (cb - k) * stride] = dv[k];
-  }
-  for (; cb >= 0; --cb) {
-    xv = D[off + cb * stride] - F[cb] * xv;
-    D[off + cb * stride] = xv;
-  }
-  return xv;
+// Global accesses at a 32-bit byte offset from a base that is uniform over the block.
+__device__ inline double ldg(const double* base, uint32_t byte_off) {
+  return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+__device__ inline void stg(double* base, uint32_t byte_off, double v) {
+  *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + byte_off) = v;
 }
 
+// Keeps the scheduler from hoisting the loads of a later batch above this point.
+__device__ inline void batch_fence() { __builtin_amdgcn_sched_barrier(0); }
+
+// The thread index, opaque to the compiler: per-thread offsets are then recomputed in each sweep
+// instead of being hoisted out of the step loop and held in registers for the whole launch.
+__device__ inline uint32_t thread_index() {
+  uint32_t t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
+// Pass 2 on the kLines lines at D.  For a line of m unknowns with
+// (1 + r) x_i - (r/2)(x_{i-1} + x_{i+1}) = d_i, Thomas' recurrences are d'_i = INV_i d_i + B_i d'_{i-1}
+// and x_i = d'_i + B_i x_{i+1}, with INV_i the pivots' reciprocals and B_i = (r/2) INV_i (both zero
+// beyond m, so padded unknowns solve to zero).  Segment j first runs the forward recurrence from a
+// zero carry; d'_i = y_i + beta_i c_j then follows from the true carry c_j (d' at the end of segment
+// j-1, from a scan of the maps c -> y_end + beta_end c) and the running product beta_i of the B's from
+// the segment's start.  The backward recurrence likewise runs from a zero carry, and
+// x_i = z_i + g_i x_in with g_i the product of the B's from i to the segment's end and x_in the
+// solution just after the segment (a reverse scan of the maps x -> z_start + g_start x).
+template <int S>
+__device__ inline void solve_lines(double* __restrict__ D, uint32_t pitch, const double* __restrict__ inv, double half) {
+  const uint32_t t = thread_index();
+  const uint32_t j = t % kSegs;
+  double* __restrict__ Dl = D + (t / kSegs) * pitch + j * (S + 1);
+  const double* __restrict__ F = inv + j * (S + 1);
+  double y[S];
+  double acc = 0.0, beta = 1.0;
+#pragma unroll
+  for (int k = 0; k < S; ++k) {
+    const double f = F[k];
+    const double b = half * f;
+    acc = fma(b, acc, Dl[k] * f);
+    y[k] = acc;
+    beta *= b;
+  }
+  double ca = acc, cb = beta;
+#pragma unroll
+  for (int d = 1; d < kSegs; d <<= 1) {
+    const double a2 = __shfl_up(ca, d, kSegs), b2 = __shfl_up(cb, d, kSegs);
+    if (j >= (uint32_t)d) {
+      ca = fma(cb, a2, ca);
+      cb *= b2;
+    }
+  }
+  double c = __shfl_up(ca, 1, kSegs);
+  if (j == 0) c = 0.0;
+  double z = 0.0, g = 1.0;
+  beta = 1.0;
+#pragma unroll
+  for (int k = 0; k < S; ++k) {
+    beta *= half * F[k];
+    y[k] = fma(c, beta, y[k]);
+  }
+#pragma unroll
+  for (int k = S - 1; k >= 0; --k) {
+    const double b = half * F[k];
+    z = fma(b, z, y[k]);
+    y[k] = z;
+    g *= b;
+  }
+  double xa = z, xg = g;
+#pragma unroll
+  for (int d = 1; d < kSegs; d <<= 1) {
+    const double a2 = __shfl_down(xa, d, kSegs), g2 = __shfl_down(xg, d, kSegs);
+    if (j + d < (uint32_t)kSegs) {
+      xa = fma(xg, a2, xa);
+      xg *= g2;
+    }
+  }
+  double xin = __shfl_down(xa, 1, kSegs);
+  if (j == kSegs - 1) xin = 0.0;
+  g = 1.0;
+#pragma unroll
+  for (int k = S - 1; k >= 0; --k) {
+    g *= half * F[k];
+    Dl[k] = fma(g, xin, y[k]);
+  }
+}
+
+template <int S>
 __device__ void x_sweep(const AdiArgs& a, uint32_t item, uint32_t n, const double* __restrict__ cur,
                         const double* __restrict__ prev, double* __restrict__ smem) {
-  const uint32_t lane = threadIdx.x;
+  constexpr uint32_t M = (uint32_t)kSegs * S;
+  constexpr uint32_t pitch = seg_pitch(S);
+  const uint32_t t = thread_index();
   const uint32_t sub = item / a.x_blk, blk = item % a.x_blk;
   const uint32_t sx = sub % a.px, sy = sub / a.px;
   const uint32_t ybase = sy * a.cy + 1 + blk * kLines;
   const uint32_t nrows = min((uint32_t)kLines, (sy + 1) * a.cy - ybase);  // lines of this item
   const uint32_t c0 = sx * a.cx, m = a.cx - 1, W = a.W;
-  const uint32_t pitch = x_pitch(m);
-  double* __restrict__ D = smem;              // [line][pitch]
-  double* __restrict__ FI = D + kLines * pitch;
-  double* __restrict__ FC = FI + m;
-  double* __restrict__ SB = FC + m;           // intermediate values on the two vertical lines
-  double* __restrict__ EY = SB + 2 * kLines;  // coefficient modulation of the item's rows
+  double* __restrict__ D = smem;                                       // [line][pitch]
+  const double* __restrict__ INV = D + kLines * pitch;                 // x lines
+  double* __restrict__ SB = D + kLines * pitch + 2 * seg_span(S);      // intermediate values on the two vertical lines
+  double* __restrict__ EY = SB + 2 * kLines;                           // coefficient modulation of the item's rows
   double* __restrict__ star = a.star;
   const double tf = time_factor(a, n);
-  for (uint32_t i = lane; i < m; i += kLanes) {
-    FI[i] = a.inv_x[i];
-    FC[i] = a.cp_x[i];
-  }
-  if (lane < kLines) EY[lane] = a.ey[min(ybase + lane, ybase + nrows - 1)];
-  if (lane < nrows) {
-    const uint32_t y = ybase + lane;
-    const double usl = ustar_line(a, sx, y, n);
-    const double usr = ustar_line(a, sx + 1, y, n);
-    SB[lane] = usl;
-    SB[kLines + lane] = usr;
-    star[(size_t)y * W + c0] = usl;
-    if (sx == a.px - 1) star[(size_t)y * W + c0 + a.cx] = usr;
-  }
-  wave_sync();
-  double eyv[kLines], slv[kLines], srv[kLines];  // per row, in registers for the right-hand sides
-#pragma unroll
-  for (int k = 0; k < kLines; ++k) {
-    eyv[k] = EY[k];
-    slv[k] = a.rx2 * SB[k];
-    srv[k] = a.rx2 * SB[kLines + k];
-  }
-  // right-hand sides of every position: lane = position within a batch of 64, two batches in flight
-  const uint32_t nb = (m + kTile - 1) / kTile;
-  auto load = [&](uint32_t t, double* cv, double* pv, double& exv) {
-    const uint32_t tt = min(t, nb - 1);
-    const size_t xcol = c0 + 1 + min(tt * kTile + lane, m - 1);
-#pragma unroll
-    for (int k = 0; k < kLines + 2; ++k) cv[k] = cur[(size_t)min(ybase - 1 + k, ybase + nrows) * W + xcol];
-#pragma unroll
-    for (int k = 0; k < kLines; ++k) pv[k] = prev[(size_t)min(ybase + k, ybase + nrows - 1) * W + xcol];
-    exv = a.ex[xcol];
-  };
-  auto rhs = [&](uint32_t t, const double* cv, const double* pv, double exv) {
-    const uint32_t i = t * kTile + lane;
-    if (t >= nb || i >= m) return;
-    const double first = i == 0 ? 1.0 : 0.0, last = i == m - 1 ? 1.0 : 0.0;
-#pragma unroll
-    for (int k = 0; k < kLines; ++k) {
-      const double u = cv[k + 1];
-      const double F = reaction_at(a, 1.5 * u - 0.5 * pv[k], exv * eyv[k], tf);
-      double d = u + a.ry2 * ((cv[k] - 2.0 * u) + cv[k + 2]) + a.dt2 * F;
-      d += first * slv[k];
-      d += last * srv[k];
-      if (k < (int)nrows) D[k * pitch + i] = d;
+  const double* __restrict__ cur_b = cur + (size_t)(ybase - 1) * W + c0 + 1;  // row above the item
+  const double* __restrict__ prev_b = prev + (size_t)ybase * W + c0 + 1;
+  double* __restrict__ star_b = star + (size_t)ybase * W + c0 + 1;
+  if (t < kLines) {
+    EY[t] = a.ey[min(ybase + t, ybase + nrows - 1)];
+    if (t < nrows) {
+      const uint32_t y = ybase + t;
+      const double usl = ustar_line(a, sx, y, n);
+      const double usr = ustar_line(a, sx + 1, y, n);
+      SB[t] = a.rx2 * usl;
+      SB[kLines + t] = a.rx2 * usr;
+      star[(size_t)y * W + c0] = usl;
+      if (sx == a.px - 1) star[(size_t)y * W + c0 + a.cx] = usr;
     }
-  };
-  for (uint32_t t = 0; t < nb; t += 2) {
-    double cvA[kLines + 2], pvA[kLines], cvB[kLines + 2], pvB[kLines], exA, exB;
-    load(t, cvA, pvA, exA);
-    load(t + 1, cvB, pvB, exB);
-    rhs(t, cvA, pvA, exA);
-    rhs(t + 1, cvB, pvB, exB);
   }
-  wave_sync();
-  if (lane < nrows) {
-    chain_forward(D, lane * pitch, 1, 0, m, FI, a.rx2, 0.0);
-    chain_backward(D, lane * pitch, 1, 0, m, m, FC, 0.0);
-  }
-  wave_sync();
-  for (uint32_t t = 0; t < nb; ++t) {
-    const uint32_t i = t * kTile + lane;
-    if (i < m)
+  __syncthreads();
+  for (uint32_t p = t; p < M; p += kAdiThreads) {
+    const uint32_t o = lds_pos<S>(p);
+    if (p >= m) {
 #pragma unroll
-      for (int k = 0; k < kLines; ++k)
-        if (k < (int)nrows) star[(size_t)(ybase + k) * W + c0 + 1 + i] = D[k * pitch + i];
+      for (int k = 0; k < kLines; ++k) D[k * pitch + o] = 0.0;
+      continue;
+    }
+    const uint32_t vo = 8 * p;
+    const double exv = ldg(a.ex + c0 + 1, vo);
+    double up = ldg(cur_b, vo), mid = ldg(cur_b + W, vo);
+#pragma unroll
+    for (int k0 = 0; k0 < kLines; k0 += kXBatch) {
+      double cv[kXBatch], pv[kXBatch];
+#pragma unroll
+      for (int k = 0; k < kXBatch; ++k) {
+        cv[k] = ldg(cur_b + (size_t)min((uint32_t)(k0 + k + 2), nrows + 1) * W, vo);
+        pv[k] = ldg(prev_b + (size_t)min((uint32_t)(k0 + k), nrows - 1) * W, vo);
+      }
+#pragma unroll
+      for (int k = 0; k < kXBatch; ++k) {
+        const double u = mid, dn = cv[k];
+        const double F = reaction_at(a, 1.5 * u - 0.5 * pv[k], exv * EY[k0 + k], tf);
+        double d = u + a.ry2 * ((up - 2.0 * u) + dn) + a.dt2 * F;
+        if (p == 0) d += SB[k0 + k];
+        if (p == m - 1) d += SB[kLines + k0 + k];
+        D[(k0 + k) * pitch + o] = d;
+        up = mid;
+        mid = dn;
+      }
+      batch_fence();
+    }
   }
-  wave_sync();
+  __syncthreads();
+  solve_lines<S>(D, pitch, INV, a.rx2);
+  __syncthreads();
+  for (uint32_t p = t; p < m; p += kAdiThreads) {
+    const uint32_t o = lds_pos<S>(p);
+#pragma unroll
+    for (int k = 0; k < kLines; ++k)
+      if (k < (int)nrows) stg(star_b + (size_t)k * W, 8 * p, D[k * pitch + o]);
+  }
+  __syncthreads();
 }
 
+template <int S>
 __device__ void y_sweep(const AdiArgs& a, uint32_t item, uint32_t n, const double* __restrict__ cur,
                         double* __restrict__ next, double* __restrict__ smem) {
-  const uint32_t lane = threadIdx.x;
-  const uint32_t l = lane % kLines, q = lane / kLines;  // line, position group
+  constexpr uint32_t pitch = seg_pitch(S);
+  constexpr uint32_t npt = (uint32_t)kSegs * S / kRowGroups;  // positions per thread
+  const uint32_t t = thread_index();
+  const uint32_t l = t % kLines, q = t / kLines;  // column, row group
   const uint32_t sub = item / a.y_blk, blk = item % a.y_blk;
   const uint32_t sx = sub % a.px, sy = sub / a.px;
   const uint32_t xfirst = sx * a.cx + 1 + blk * kLines;
   const uint32_t nl = min((uint32_t)kLines, (sx + 1) * a.cx - xfirst);
-  const bool ok = l < nl;
   const uint32_t x = xfirst + min(l, nl - 1);
   const uint32_t r0 = sy * a.cy, m = a.cy - 1, W = a.W;
-  double* __restrict__ D = smem;  // [position][line]
-  double* __restrict__ FI = D + (size_t)m * kYPitch;
-  double* __restrict__ FC = FI + m;
-  double* __restrict__ EY = FC + m;  // coefficient modulation of the subdomain's rows
-  const double* __restrict__ star = a.star;
-  for (uint32_t i = lane; i < m; i += kLanes) {
-    FI[i] = a.inv_y[i];
-    FC[i] = a.cp_y[i];
-    EY[i] = a.ey[r0 + 1 + i];
-  }
-  const double gb0 = hline_value(a, sy, x, n + 1);
-  const double gb1 = hline_value(a, sy + 1, x, n + 1);
+  double* __restrict__ D = smem;  // [line][pitch]
+  const double* __restrict__ INV = D + kLines * pitch + seg_span(S);  // y lines
+  // bases at the subdomain's first row; offsets of (row, column) stay below 2^32 bytes
+  const double* __restrict__ star_b = a.star + (size_t)r0 * W;
+  const double* __restrict__ cur_b = cur + (size_t)r0 * W;
+  double* __restrict__ next_b = next + (size_t)r0 * W;
+  const double* __restrict__ ey_b = a.ey + r0 + 1;
+  const double gb0 = a.ry2 * hline_value(a, sy, x, n + 1);
+  const double gb1 = a.ry2 * hline_value(a, sy + 1, x, n + 1);
   const double tf = time_factor(a, n);
   const double exv = a.ex[x];
-  const uint32_t npl = (m + kGroups - 1) / kGroups;  // positions per lane: p = q + kGroups k
-  wave_sync();
-  for (uint32_t kb = 0; kb < npl; kb += kYBatch) {
+#pragma unroll
+  for (uint32_t kb = 0; kb < npt; kb += kYBatch) {
     double sl[kYBatch], sc[kYBatch], sr[kYBatch], cu[kYBatch], pr[kYBatch], ey[kYBatch];
 #pragma unroll
     for (int k = 0; k < kYBatch; ++k) {
-      const uint32_t p = min(q + kGroups * (kb + k), m - 1);
-      const size_t idx = (size_t)(r0 + 1 + p) * W + x;
-      sl[k] = star[idx - 1];
-      sc[k] = star[idx];
-      sr[k] = star[idx + 1];
-      cu[k] = cur[idx];
-      pr[k] = next[idx];  // next still holds u^{n-1}
-      ey[k] = EY[p];
+      const uint32_t p = min(q + kRowGroups * (kb + k), m - 1);
+      const uint32_t off = 8 * ((1 + p) * W + x);
+      sl[k] = ldg(star_b, off - 8);
+      sc[k] = ldg(star_b, off);
+      sr[k] = ldg(star_b, off + 8);
+      cu[k] = ldg(cur_b, off);
+      pr[k] = ldg(next_b, off);  // next still holds u^{n-1}
+      ey[k] = ldg(ey_b, 8 * p);
     }
 #pragma unroll
     for (int k = 0; k < kYBatch; ++k) {
-      const uint32_t p = q + kGroups * (kb + k);
+      const uint32_t p = q + kRowGroups * (kb + k);
       const double F = reaction_at(a, 1.5 * cu[k] - 0.5 * pr[k], exv * ey[k], tf);
       double d = sc[k] + a.rx2 * ((sl[k] - 2.0 * sc[k]) + sr[k]) + a.dt2 * F;
-      d += p == 0 ? a.ry2 * gb0 : 0.0;
-      d += p == m - 1 ? a.ry2 * gb1 : 0.0;
-      if (p < m) D[p * kYPitch + l] = d;
+      if (p == 0) d += gb0;
+      if (p == m - 1) d += gb1;
+      D[l * pitch + lds_pos<S>(p)] = p < m ? d : 0.0;
     }
+    batch_fence();
   }
-  wave_sync();
-  if (q == 0) {
-    chain_forward(D, l, kYPitch, 0, m, FI, a.ry2, 0.0);
-    chain_backward(D, l, kYPitch, 0, m, m, FC, 0.0);
-  }
-  wave_sync();
-  if (ok)
-    for (uint32_t k = 0; k < npl; ++k) {
-      const uint32_t p = q + kGroups * k;
-      if (p < m) next[(size_t)(r0 + 1 + p) * W + x] = D[p * kYPitch + l];
+  __syncthreads();
+  solve_lines<S>(D, pitch, INV, a.ry2);
+  __syncthreads();
+  if (l < nl)
+#pragma unroll 4
+    for (uint32_t k = 0; k < npt; ++k) {
+      const uint32_t p = q + kRowGroups * k;
+      if (p < m) stg(next_b, 8 * ((1 + p) * W + x), D[l * pitch + lds_pos<S>(p)]);
     }
-  wave_sync();
+  __syncthreads();
 }
 
 // Line nodes of level n+1 into the new field; a horizontal line leaves the nodes it shares with a
@@ -587,7 +609,7 @@ __device__ void write_lines(const AdiArgs& a, uint32_t item, uint32_t n, double*
     blk = item % a.bh;
   }
   const LineDev& L = a.lines[l];
-  const uint32_t j = blk * kLanes + threadIdx.x;
+  const uint32_t j = blk * kAdiThreads + threadIdx.x;
   if (j >= L.n_fine) return;
   const double v = a.bd[L.bd_off + (size_t)(n + 1) * L.n_fine + j];
   if (L.orient == 0) {
@@ -598,27 +620,49 @@ __device__ void write_lines(const AdiArgs& a, uint32_t item, uint32_t n, double*
   }
 }
 
-__global__ __launch_bounds__(64) void adi_kernel(AdiArgs a) {
+// Items of a phase taken by this block.  With a grid that is a multiple of the die count, the items
+// are split into one contiguous range per die and dealt round-robin over the die's blocks: the blocks
+// of a die then work on neighbouring strips at the same time and share the halo lines in its L2.
+struct ItemRange {
+  uint32_t begin, end, stride;
+};
+__device__ inline ItemRange block_items(uint32_t n_items) {
+  const uint32_t b = blockIdx.x, g = gridDim.x;
+  if (g % kXcds != 0) return {b, n_items, g};
+  const uint32_t x = b % kXcds;
+  return {(uint32_t)((uint64_t)n_items * x / kXcds) + b / kXcds, (uint32_t)((uint64_t)n_items * (x + 1) / kXcds),
+          g / kXcds};
+}
+
+template <int S>
+__global__ __launch_bounds__(kAdiThreads) void adi_kernel(AdiArgs a) {
   extern __shared__ double smem[];
+  __shared__ uint32_t barrier_ok;
   uint32_t gen = 0;
   const uint32_t nsub = a.px * a.py;
   const uint32_t x_items = nsub * a.x_blk;
   const uint32_t y_items = nsub * a.y_blk;
   const uint32_t l_items = a.n_vlines * a.bv + (a.n_lines - a.n_vlines) * a.bh;
-  // Items of a phase cost the same (equal subdomains), so they are dealt round-robin: no counter
+  {  // pivots' reciprocals of both directions into LDS, segment layout
+    constexpr uint32_t M = (uint32_t)kSegs * S;
+    double* inv = smem + kLines * seg_pitch(S);
+    for (uint32_t i = threadIdx.x; i < M; i += kAdiThreads) {
+      inv[lds_pos<S>(i)] = a.inv_x[i];
+      inv[seg_span(S) + lds_pos<S>(i)] = a.inv_y[i];
+    }
+    __syncthreads();
+  }
+  // Items of a phase cost the same (equal subdomains), so they are dealt statically: no counter
   // traffic between the barriers.
+  const ItemRange xr = block_items(x_items), yr = block_items(y_items);
   for (uint32_t n = 0; n < a.steps; ++n) {
     const double* cur = (n & 1) ? a.f1 : a.f0;
     double* prev = (n & 1) ? a.f0 : a.f1;  // holds u^{n-1}; receives u^{n+1}
-    for (uint32_t it = blockIdx.x; it < x_items; it += gridDim.x) x_sweep(a, it, n, cur, prev, smem);
-    if (!grid_barrier(a.sync, a.nblocks, gen, a.spin_limit)) return;
-    for (uint32_t it = blockIdx.x; it < y_items + l_items; it += gridDim.x) {
-      if (it < y_items)
-        y_sweep(a, it, n, cur, prev, smem);
-      else
-        write_lines(a, it - y_items, n, prev);
-    }
-    if (!grid_barrier(a.sync, a.nblocks, gen, a.spin_limit)) return;
+    for (uint32_t it = xr.begin; it < xr.end; it += xr.stride) x_sweep<S>(a, it, n, cur, prev, smem);
+    if (!grid_barrier(a.sync, a.nblocks, gen, a.spin_limit, &barrier_ok)) return;
+    for (uint32_t it = yr.begin; it < yr.end; it += yr.stride) y_sweep<S>(a, it, n, cur, prev, smem);
+    for (uint32_t it = blockIdx.x; it < l_items; it += gridDim.x) write_lines(a, it, n, prev);
+    if (!grid_barrier(a.sync, a.nblocks, gen, a.spin_limit, &barrier_ok)) return;
   }
 }
 
@@ -629,7 +673,7 @@ struct brt_pdd {
   brt_problem prob{};
   brt_pdd_grid g{};
   int device = 0, n_cu = 0;
-  uint32_t NX = 0, NY = 0, max_ns = 0, max_fine = 0, n_vlines = 0;
+  uint32_t NX = 0, NY = 0, W = 0, max_ns = 0, max_fine = 0, n_vlines = 0;  // W: field row pitch
   double hx = 0, hy = 0, dt = 0, rx = 0, ry = 0;
   std::vector<LineDev> lines;
   int16_t vline[kMaxSub + 1];
@@ -653,6 +697,7 @@ struct brt_pdd {
   hipEvent_t ev[6] = {};
   bool recorded[3] = {false, false, false};
   int grid = 0;
+  int seg = 16;    // unknowns per segment of the solver's line solves
   size_t lds = 0;  // dynamic LDS of the solver launch (bytes)
 };
 
@@ -674,15 +719,18 @@ void pdd_free(brt_pdd* p) {
   delete p;
 }
 
-void thomas_factors(double r, uint32_t m, double* inv, double* cp) {
-  // (1 + r) on the diagonal, -r/2 beside it: the scaled Thomas factors
-  const double b = 1.0 + r, off = -0.5 * r;
-  inv[0] = 1.0 / b;
-  cp[0] = off * inv[0];
-  for (uint32_t i = 1; i < m; ++i) {
-    inv[i] = 1.0 / (b - off * cp[i - 1]);
-    cp[i] = off * inv[i];
-  }
+// Reciprocals of the Thomas pivots of (1 + r) x_i - (r/2)(x_{i-1} + x_{i+1}) = d_i, i < m, padded
+// with zeros to kSegs * S entries.
+void pivot_reciprocals(double r, uint32_t m, int S, double* inv) {
+  const double diag = 1.0 + r, half = 0.5 * r;
+  for (uint32_t i = 0; i < (uint32_t)kSegs * S; ++i) inv[i] = i < m ? 1.0 / (i == 0 ? diag : diag - half * half * inv[i - 1]) : 0.0;
+}
+
+// Segment length of the solver: the smallest of 16 and 32 that covers the longer side.
+int seg_length(const brt_pdd_grid& g) { return std::max(g.cx, g.cy) - 1 <= (uint32_t)kSegs * 16 ? 16 : 32; }
+
+const void* adi_kernel_ptr(int S) {
+  return S == 16 ? reinterpret_cast<const void*>(&adi_kernel<16>) : reinterpret_cast<const void*>(&adi_kernel<32>);
 }
 
 }  // namespace
@@ -775,7 +823,8 @@ int brt_pdd_create(brt_ctx* ctx, const brt_problem* prob, const brt_pdd_grid* gr
   p->bd_doubles = bd_off;
   p->max_ns = std::max(g.ns_x, g.ns_y);
   p->max_fine = std::max(p->NX, p->NY) + 1;
-  const size_t field = (size_t)(p->NX + 1) * (p->NY + 1);
+  p->W = (p->NX + 1 + 15) & ~15u;
+  const size_t field = (size_t)p->W * (p->NY + 1) + kFieldLead + 1;
   const double bytes = 8.0 * ((double)p->bd_doubles + 3.0 * (double)field);
   if (bytes > 128e9) {
     pdd_free(p);
@@ -796,7 +845,8 @@ int brt_pdd_create(brt_ctx* ctx, const brt_problem* prob, const brt_pdd_grid* gr
   dev_alloc((void**)&p->d_lines, sizeof(LineDev) * p->lines.size());
   dev_alloc((void**)&p->d_bd, 8 * p->bd_doubles);
   for (double*& f : p->d_f) dev_alloc((void**)&f, 8 * field);
-  dev_alloc((void**)&p->d_fac, 8 * 2 * (size_t)(g.cx + g.cy));
+  p->seg = seg_length(g);
+  dev_alloc((void**)&p->d_fac, 8 * 2 * (size_t)kSegs * p->seg);
   dev_alloc((void**)&p->d_spl, 8 * (3 * p->spl_rows + 3 * p->spl_fine));
   dev_alloc((void**)&p->d_sync, 4 * (3 + 2 * (size_t)g.n_steps));
   dev_alloc((void**)&p->d_node_u, 8 * std::max<uint64_t>(p->n_nodes, 1));
@@ -804,9 +854,9 @@ int brt_pdd_create(brt_ctx* ctx, const brt_problem* prob, const brt_pdd_grid* gr
   for (hipEvent_t& e : p->ev)
     if (rc == BRT_OK && hipEventCreate(&e) != hipSuccess) rc = set_error(BRT_E_DEVICE, "pdd: event creation");
   if (rc == BRT_OK) {
-    std::vector<double> fac(2 * (size_t)(g.cx + g.cy));
-    thomas_factors(p->rx, g.cx - 1, fac.data(), fac.data() + g.cx);
-    thomas_factors(p->ry, g.cy - 1, fac.data() + 2 * g.cx, fac.data() + 2 * g.cx + g.cy);
+    std::vector<double> fac(2 * (size_t)kSegs * p->seg);
+    pivot_reciprocals(p->rx, g.cx - 1, p->seg, fac.data());
+    pivot_reciprocals(p->ry, g.cy - 1, p->seg, fac.data() + (size_t)kSegs * p->seg);
     std::vector<double> exy(p->NX + 1 + p->NY + 1, 1.0);
     if (prob->coef_mod == BRT_COEF_MOD_GAUSS_TIME) {
       for (uint32_t i = 0; i <= p->NX; ++i) {
@@ -825,12 +875,12 @@ int brt_pdd_create(brt_ctx* ctx, const brt_problem* prob, const brt_pdd_grid* gr
   }
   if (rc == BRT_OK) {
     int per_cu = 0;
-    p->lds = 8 * std::max(x_lds(g.cx - 1), y_lds(g.cy - 1));
-    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&adi_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+    p->lds = 8 * adi_lds_doubles(p->seg);
+    if (hipFuncSetAttribute(adi_kernel_ptr(p->seg), hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)p->lds) != hipSuccess)
       rc = set_error(BRT_E_DEVICE, "pdd: solver LDS of %zu bytes", p->lds);
     if (rc == BRT_OK &&
-        (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&adi_kernel), kLanes,
+        (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, adi_kernel_ptr(p->seg), kAdiThreads,
                                                       p->lds) != hipSuccess ||
          per_cu < 1))
       rc = set_error(BRT_E_DEVICE, "pdd: solver occupancy query (LDS %zu bytes)", p->lds);
@@ -838,7 +888,11 @@ int brt_pdd_create(brt_ctx* ctx, const brt_problem* prob, const brt_pdd_grid* gr
     const uint32_t x_items = nsub * ((g.cy - 1 + kLines - 1) / kLines);
     const uint32_t y_items = nsub * ((g.cx - 1 + kLines - 1) / kLines);
     const uint64_t cap = (uint64_t)per_cu * p->n_cu;
-    p->grid = (int)std::min<uint64_t>({(uint64_t)std::max(x_items, y_items), 4ull * p->n_cu, cap});
+    // Half the compute units, a multiple of the die count: the phases are bound by the memory system,
+    // and on the 4 x 4 x 512^2 workload a step took 106 us at 128 blocks of 512 threads, 107 at 192,
+    // 111 at 256 and 129 at 96 (more concurrent blocks only lengthen every block's memory latency).
+    const uint64_t half = std::max<uint64_t>(kXcds, (uint64_t)p->n_cu / 2 / kXcds * kXcds);
+    p->grid = (int)std::min<uint64_t>({(uint64_t)std::max(x_items, y_items), half, cap});
   }
   if (rc != BRT_OK) {
     pdd_free(p);
@@ -929,8 +983,9 @@ int brt_pdd_solve(brt_pdd* p, uint32_t steps, double* field, void* stream) {
   const brt_pdd_grid& g = p->g;
   PDD_TRY(hipEventRecord(p->ev[4], s));
   FieldArgs fa{};
-  fa.f0 = p->d_f[0];
-  fa.f1 = p->d_f[1];
+  fa.f0 = p->d_f[0] + kFieldLead;
+  fa.f1 = p->d_f[1] + kFieldLead;
+  fa.W = p->W;
   fa.bd = p->d_bd;
   fa.lines = p->d_lines;
   fa.NX = p->NX;
@@ -951,15 +1006,13 @@ int brt_pdd_solve(brt_pdd* p, uint32_t steps, double* field, void* stream) {
   PDD_TRY(hipMemsetAsync(p->d_sync, 0, 4 * (3 + 2 * (size_t)steps), s));
 
   AdiArgs a{};
-  a.f0 = p->d_f[0];
-  a.f1 = p->d_f[1];
-  a.star = p->d_f[2];
+  a.f0 = p->d_f[0] + kFieldLead;
+  a.f1 = p->d_f[1] + kFieldLead;
+  a.star = p->d_f[2] + kFieldLead;
   a.bd = p->d_bd;
   a.lines = p->d_lines;
   a.inv_x = p->d_fac;
-  a.cp_x = p->d_fac + g.cx;
-  a.inv_y = p->d_fac + 2 * g.cx;
-  a.cp_y = p->d_fac + 2 * g.cx + g.cy;
+  a.inv_y = p->d_fac + (size_t)kSegs * p->seg;
   a.sync = p->d_sync;
   int rate_khz = 0;
   PDD_TRY(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, p->device));
@@ -976,7 +1029,7 @@ int brt_pdd_solve(brt_pdd* p, uint32_t steps, double* field, void* stream) {
   a.rx2 = 0.5 * p->rx;
   a.ry2 = 0.5 * p->ry;
   a.dt2 = 0.5 * p->dt;
-  a.W = p->NX + 1;
+  a.W = p->W;
   a.px = g.px;
   a.py = g.py;
   a.cx = g.cx;
@@ -986,16 +1039,20 @@ int brt_pdd_solve(brt_pdd* p, uint32_t steps, double* field, void* stream) {
   a.x_blk = (g.cy - 1 + kLines - 1) / kLines;
   a.y_blk = (g.cx - 1 + kLines - 1) / kLines;
   a.n_vlines = p->n_vlines;
-  a.bv = (p->NY + 1 + kLanes - 1) / kLanes;
-  a.bh = (p->NX + 1 + kLanes - 1) / kLanes;
+  a.bv = (p->NY + 1 + kAdiThreads - 1) / kAdiThreads;
+  a.bh = (p->NX + 1 + kAdiThreads - 1) / kAdiThreads;
   a.n_lines = (uint32_t)p->lines.size();
   std::memcpy(a.vline, p->vline, sizeof(a.vline));
   std::memcpy(a.hline, p->hline, sizeof(a.hline));
+  a.v_fine = p->NY + 1;
+  a.h_fine = p->NX + 1;
+  for (size_t l = 0; l < p->lines.size(); ++l) a.bd_off[l] = p->lines[l].bd_off;
   void* kargs[] = {&a};
-  PDD_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&adi_kernel), dim3(p->grid), dim3(kLanes), kargs,
+  PDD_TRY(hipLaunchCooperativeKernel(adi_kernel_ptr(p->seg), dim3(p->grid), dim3(kAdiThreads), kargs,
                                      (unsigned)p->lds, s));
-  const double* result = (steps & 1) ? p->d_f[1] : p->d_f[0];
-  PDD_TRY(hipMemcpyAsync(field, result, 8 * (size_t)(p->NX + 1) * (p->NY + 1), hipMemcpyDeviceToDevice, s));
+  const double* result = ((steps & 1) ? p->d_f[1] : p->d_f[0]) + kFieldLead;
+  PDD_TRY(hipMemcpy2DAsync(field, 8 * (size_t)(p->NX + 1), result, 8 * (size_t)p->W, 8 * (size_t)(p->NX + 1), p->NY + 1,
+                           hipMemcpyDeviceToDevice, s));
   PDD_TRY(hipEventRecord(p->ev[5], s));
   p->recorded[2] = true;
   return BRT_OK;

@@ -117,6 +117,17 @@ def test_tail_single_subdomain_and_cos2(ctx):
     _tail_parity(ctx, "tail_single_cos2", prob, grid, vals)
 
 
+def test_tail_long_lines_32_unknown_segments(ctx):
+    """2 x 1 subdomains of 600 x 30 cells: lines of 599 unknowns take the solver's 32-unknown segments
+    (the ragged last segment holds 23), and the short y lines leave most segments empty."""
+    grid = _grid(x_lo=-6.0, x_hi=6.0, px=2, py=1, cx=600, cy=30, n_steps=12, ns_x=41, ns_y=7, nt=3, T=0.2,
+                 outer="zero")
+    og = opdd.Grid(**grid)
+    xy, t = opdd.node_points(og)
+    vals = 0.4 * np.exp(-(xy[:, 0] ** 2 + 2.0 * xy[:, 1] ** 2) / 6.0) * (1.0 - t)
+    _tail_parity(ctx, "tail_long_lines", _cubic(2), grid, vals)
+
+
 def test_tail_full_size_first_steps(ctx):
     """The decomposition of the 2-D cubic workload at its full size (4 x 4 subdomains of 512^2 cells,
     264 nodes per line on 10 lines, 1000 steps of boundary data), solved through its first 100 steps."""
