@@ -259,7 +259,7 @@ struct AdiArgs {
   uint32_t px, py, cx, cy;
   uint32_t steps;
   uint32_t nblocks;
-  uint32_t x_blk, y_blk;       // items (kLines lines) per subdomain in the x and the y phase
+  uint32_t x_blk, y_blk;       // items per subdomain in the x and the y phase
   uint32_t n_vlines, bv, bh;   // data lines: vertical count; blocks of nodes per vertical / horizontal line
   uint32_t n_lines;
   int16_t vline[kMaxSub + 1];
@@ -336,10 +336,10 @@ __device__ inline double hline_value(const AdiArgs& a, uint32_t ky, uint32_t x, 
   return a.bd[a.bd_off[hl] + (size_t)n * a.h_fine + x];
 }
 
-// A work item is kLines lines of one subdomain, solved by one block of kAdiThreads threads with the
-// lines resident in LDS.  Three passes:
+// A work item is L lines of one subdomain, solved by one block of 32 L threads with the lines resident
+// in LDS (L = 32 for segments of 16 unknowns, 16 for segments of 32).  Three passes:
 //   1. the right-hand sides, from coalesced global loads (x phase: threads along the positions of the
-//      item's rows; y phase: 16 columns x 32 row groups), into LDS [line][position];
+//      item's rows; y phase: L columns x 32 row groups), into LDS [line][position];
 //   2. the tridiagonal solves, kSegs threads per line, each owning S consecutive positions: a local
 //      forward recurrence, a scan of the segments' affine carry maps over the line's lanes, the carry
 //      applied, a local backward recurrence, a reverse scan, and the backward carry applied;
@@ -348,21 +348,27 @@ __device__ inline double hline_value(const AdiArgs& a, uint32_t ky, uint32_t x, 
 // line pitch is 4 mod 32 doubles (conflict-free column writes in the y phase).  The pivots' reciprocals
 // of both directions stay in LDS for the whole launch, in the same segment layout.  Subdomains have at
 // most kSegs * 32 cells per side.
-constexpr int kAdiThreads = 512;
-constexpr int kLines = 16;
-constexpr int kSegs = 32;                          // threads per line in pass 2
-constexpr int kRowGroups = kAdiThreads / kLines;   // y phase: row groups of pass 1 and 3
-constexpr int kXBatch = 16;                        // x phase: rows loaded together
-constexpr int kYBatch = 8;                         // y phase: positions per thread loaded together
+constexpr int kSegs = 32;    // threads per line in pass 2; row groups of the y phase's passes 1 and 3
+constexpr int kXBatch = 8;   // x phase: rows loaded together
+constexpr int kYBatch = 4;   // y phase: positions per thread loaded together
+
+template <int S>
+struct AdiShape {
+  static constexpr int lines = S == 16 ? 32 : 16;  // lines per item
+  static constexpr int threads = lines * kSegs;    // threads per block
+};
+constexpr int kMaxAdiThreads = 1024;
 
 static_assert(kMaxCells - 1 <= (uint32_t)kSegs * 32, "the longest line must fit 32 segments of 32");
 
 __host__ __device__ constexpr uint32_t seg_span(int S) { return (uint32_t)kSegs * (S + 1); }
 __host__ __device__ constexpr uint32_t seg_pitch(int S) { return seg_span(S) + 4; }
+__host__ __device__ constexpr int adi_lines(int S) { return S == 16 ? AdiShape<16>::lines : AdiShape<32>::lines; }
+__host__ __device__ constexpr int adi_threads(int S) { return adi_lines(S) * kSegs; }
 // LDS (doubles): the lines, the pivots' reciprocals of the x and the y lines, then the intermediate
 // values on the item's two vertical data lines and the coefficient modulation of its rows (x phase).
 __host__ __device__ constexpr size_t adi_lds_doubles(int S) {
-  return (size_t)kLines * seg_pitch(S) + 2 * (size_t)seg_span(S) + 3 * kLines;
+  return (size_t)adi_lines(S) * seg_pitch(S) + 2 * (size_t)seg_span(S) + 3 * (size_t)adi_lines(S);
 }
 
 template <int S>
@@ -389,7 +395,7 @@ __device__ inline uint32_t thread_index() {
   return t;
 }
 
-// Pass 2 on the kLines lines at D.  For a line of m unknowns with
+// Pass 2 on the lines at D (kSegs threads per line).  For a line of m unknowns with
 // (1 + r) x_i - (r/2)(x_{i-1} + x_{i+1}) = d_i, Thomas' recurrences are d'_i = INV_i d_i + B_i d'_{i-1}
 // and x_i = d'_i + B_i x_{i+1}, with INV_i the pivots' reciprocals and B_i = (r/2) INV_i (both zero
 // beyond m, so padded unknowns solve to zero).  Segment j first runs the forward recurrence from a
@@ -461,62 +467,67 @@ __device__ inline void solve_lines(double* __restrict__ D, uint32_t pitch, const
 template <int S>
 __device__ void x_sweep(const AdiArgs& a, uint32_t item, uint32_t n, const double* __restrict__ cur,
                         const double* __restrict__ prev, double* __restrict__ smem) {
+  constexpr int L = AdiShape<S>::lines, T = AdiShape<S>::threads;
   constexpr uint32_t M = (uint32_t)kSegs * S;
   constexpr uint32_t pitch = seg_pitch(S);
+  // pass 1 and 3: threads along the positions; with more threads than positions, row sets of R rows
+  constexpr uint32_t sets = T >= (int)M ? T / M : 1, R = L / sets, pstep = sets > 1 ? M : T;
   const uint32_t t = thread_index();
+  const uint32_t h = sets > 1 ? t / M : 0, p0 = sets > 1 ? t % M : t, r0 = h * R;
   const uint32_t sub = item / a.x_blk, blk = item % a.x_blk;
   const uint32_t sx = sub % a.px, sy = sub / a.px;
-  const uint32_t ybase = sy * a.cy + 1 + blk * kLines;
-  const uint32_t nrows = min((uint32_t)kLines, (sy + 1) * a.cy - ybase);  // lines of this item
+  const uint32_t ybase = sy * a.cy + 1 + blk * L;
+  const uint32_t nrows = min((uint32_t)L, (sy + 1) * a.cy - ybase);  // lines of this item
   const uint32_t c0 = sx * a.cx, m = a.cx - 1, W = a.W;
-  double* __restrict__ D = smem;                                       // [line][pitch]
-  const double* __restrict__ INV = D + kLines * pitch;                 // x lines
-  double* __restrict__ SB = D + kLines * pitch + 2 * seg_span(S);      // intermediate values on the two vertical lines
-  double* __restrict__ EY = SB + 2 * kLines;                           // coefficient modulation of the item's rows
+  double* __restrict__ D = smem;                                  // [line][pitch]
+  const double* __restrict__ INV = D + L * pitch;                 // x lines
+  double* __restrict__ SB = D + L * pitch + 2 * seg_span(S);      // intermediate values on the two vertical lines
+  double* __restrict__ EY = SB + 2 * L;                           // coefficient modulation of the item's rows
   double* __restrict__ star = a.star;
   const double tf = time_factor(a, n);
   const double* __restrict__ cur_b = cur + (size_t)(ybase - 1) * W + c0 + 1;  // row above the item
   const double* __restrict__ prev_b = prev + (size_t)ybase * W + c0 + 1;
   double* __restrict__ star_b = star + (size_t)ybase * W + c0 + 1;
-  if (t < kLines) {
+  if (t < (uint32_t)L) {
     EY[t] = a.ey[min(ybase + t, ybase + nrows - 1)];
     if (t < nrows) {
       const uint32_t y = ybase + t;
       const double usl = ustar_line(a, sx, y, n);
       const double usr = ustar_line(a, sx + 1, y, n);
       SB[t] = a.rx2 * usl;
-      SB[kLines + t] = a.rx2 * usr;
+      SB[L + t] = a.rx2 * usr;
       star[(size_t)y * W + c0] = usl;
       if (sx == a.px - 1) star[(size_t)y * W + c0 + a.cx] = usr;
     }
   }
   __syncthreads();
-  for (uint32_t p = t; p < M; p += kAdiThreads) {
+  for (uint32_t p = p0; p < M; p += pstep) {
     const uint32_t o = lds_pos<S>(p);
     if (p >= m) {
 #pragma unroll
-      for (int k = 0; k < kLines; ++k) D[k * pitch + o] = 0.0;
+      for (uint32_t k = 0; k < R; ++k) D[(r0 + k) * pitch + o] = 0.0;
       continue;
     }
     const uint32_t vo = 8 * p;
     const double exv = ldg(a.ex + c0 + 1, vo);
-    double up = ldg(cur_b, vo), mid = ldg(cur_b + W, vo);
+    double up = ldg(cur_b + (size_t)min(r0, nrows + 1) * W, vo), mid = ldg(cur_b + (size_t)min(r0 + 1, nrows + 1) * W, vo);
 #pragma unroll
-    for (int k0 = 0; k0 < kLines; k0 += kXBatch) {
+    for (uint32_t k0 = 0; k0 < R; k0 += kXBatch) {
       double cv[kXBatch], pv[kXBatch];
 #pragma unroll
       for (int k = 0; k < kXBatch; ++k) {
-        cv[k] = ldg(cur_b + (size_t)min((uint32_t)(k0 + k + 2), nrows + 1) * W, vo);
-        pv[k] = ldg(prev_b + (size_t)min((uint32_t)(k0 + k), nrows - 1) * W, vo);
+        cv[k] = ldg(cur_b + (size_t)min(r0 + k0 + k + 2, nrows + 1) * W, vo);
+        pv[k] = ldg(prev_b + (size_t)min(r0 + k0 + k, nrows - 1) * W, vo);
       }
 #pragma unroll
       for (int k = 0; k < kXBatch; ++k) {
+        const uint32_t row = r0 + k0 + k;
         const double u = mid, dn = cv[k];
-        const double F = reaction_at(a, 1.5 * u - 0.5 * pv[k], exv * EY[k0 + k], tf);
+        const double F = reaction_at(a, 1.5 * u - 0.5 * pv[k], exv * EY[row], tf);
         double d = u + a.ry2 * ((up - 2.0 * u) + dn) + a.dt2 * F;
-        if (p == 0) d += SB[k0 + k];
-        if (p == m - 1) d += SB[kLines + k0 + k];
-        D[(k0 + k) * pitch + o] = d;
+        if (p == 0) d += SB[row];
+        if (p == m - 1) d += SB[L + row];
+        D[row * pitch + o] = d;
         up = mid;
         mid = dn;
       }
@@ -526,11 +537,11 @@ __device__ void x_sweep(const AdiArgs& a, uint32_t item, uint32_t n, const doubl
   __syncthreads();
   solve_lines<S>(D, pitch, INV, a.rx2);
   __syncthreads();
-  for (uint32_t p = t; p < m; p += kAdiThreads) {
+  for (uint32_t p = p0; p < m; p += pstep) {
     const uint32_t o = lds_pos<S>(p);
 #pragma unroll
-    for (int k = 0; k < kLines; ++k)
-      if (k < (int)nrows) stg(star_b + (size_t)k * W, 8 * p, D[k * pitch + o]);
+    for (uint32_t k = 0; k < R; ++k)
+      if (r0 + k < nrows) stg(star_b + (size_t)(r0 + k) * W, 8 * p, D[(r0 + k) * pitch + o]);
   }
   __syncthreads();
 }
@@ -538,18 +549,19 @@ __device__ void x_sweep(const AdiArgs& a, uint32_t item, uint32_t n, const doubl
 template <int S>
 __device__ void y_sweep(const AdiArgs& a, uint32_t item, uint32_t n, const double* __restrict__ cur,
                         double* __restrict__ next, double* __restrict__ smem) {
+  constexpr int L = AdiShape<S>::lines;
   constexpr uint32_t pitch = seg_pitch(S);
-  constexpr uint32_t npt = (uint32_t)kSegs * S / kRowGroups;  // positions per thread
+  constexpr uint32_t npt = S;  // positions per thread: kSegs row groups cover kSegs * S positions
   const uint32_t t = thread_index();
-  const uint32_t l = t % kLines, q = t / kLines;  // column, row group
+  const uint32_t l = t % L, q = t / L;  // column, row group
   const uint32_t sub = item / a.y_blk, blk = item % a.y_blk;
   const uint32_t sx = sub % a.px, sy = sub / a.px;
-  const uint32_t xfirst = sx * a.cx + 1 + blk * kLines;
-  const uint32_t nl = min((uint32_t)kLines, (sx + 1) * a.cx - xfirst);
+  const uint32_t xfirst = sx * a.cx + 1 + blk * L;
+  const uint32_t nl = min((uint32_t)L, (sx + 1) * a.cx - xfirst);
   const uint32_t x = xfirst + min(l, nl - 1);
   const uint32_t r0 = sy * a.cy, m = a.cy - 1, W = a.W;
   double* __restrict__ D = smem;  // [line][pitch]
-  const double* __restrict__ INV = D + kLines * pitch + seg_span(S);  // y lines
+  const double* __restrict__ INV = D + L * pitch + seg_span(S);  // y lines
   // bases at the subdomain's first row; offsets of (row, column) stay below 2^32 bytes
   const double* __restrict__ star_b = a.star + (size_t)r0 * W;
   const double* __restrict__ cur_b = cur + (size_t)r0 * W;
@@ -564,7 +576,7 @@ __device__ void y_sweep(const AdiArgs& a, uint32_t item, uint32_t n, const doubl
     double sl[kYBatch], sc[kYBatch], sr[kYBatch], cu[kYBatch], pr[kYBatch], ey[kYBatch];
 #pragma unroll
     for (int k = 0; k < kYBatch; ++k) {
-      const uint32_t p = min(q + kRowGroups * (kb + k), m - 1);
+      const uint32_t p = min(q + kSegs * (kb + k), m - 1);
       const uint32_t off = 8 * ((1 + p) * W + x);
       sl[k] = ldg(star_b, off - 8);
       sc[k] = ldg(star_b, off);
@@ -575,7 +587,7 @@ __device__ void y_sweep(const AdiArgs& a, uint32_t item, uint32_t n, const doubl
     }
 #pragma unroll
     for (int k = 0; k < kYBatch; ++k) {
-      const uint32_t p = q + kRowGroups * (kb + k);
+      const uint32_t p = q + kSegs * (kb + k);
       const double F = reaction_at(a, 1.5 * cu[k] - 0.5 * pr[k], exv * ey[k], tf);
       double d = sc[k] + a.rx2 * ((sl[k] - 2.0 * sc[k]) + sr[k]) + a.dt2 * F;
       if (p == 0) d += gb0;
@@ -590,7 +602,7 @@ __device__ void y_sweep(const AdiArgs& a, uint32_t item, uint32_t n, const doubl
   if (l < nl)
 #pragma unroll 4
     for (uint32_t k = 0; k < npt; ++k) {
-      const uint32_t p = q + kRowGroups * k;
+      const uint32_t p = q + kSegs * k;
       if (p < m) stg(next_b, 8 * ((1 + p) * W + x), D[l * pitch + lds_pos<S>(p)]);
     }
   __syncthreads();
@@ -609,7 +621,7 @@ __device__ void write_lines(const AdiArgs& a, uint32_t item, uint32_t n, double*
     blk = item % a.bh;
   }
   const LineDev& L = a.lines[l];
-  const uint32_t j = blk * kAdiThreads + threadIdx.x;
+  const uint32_t j = blk * blockDim.x + threadIdx.x;
   if (j >= L.n_fine) return;
   const double v = a.bd[L.bd_off + (size_t)(n + 1) * L.n_fine + j];
   if (L.orient == 0) {
@@ -635,7 +647,7 @@ __device__ inline ItemRange block_items(uint32_t n_items) {
 }
 
 template <int S>
-__global__ __launch_bounds__(kAdiThreads) void adi_kernel(AdiArgs a) {
+__global__ __launch_bounds__(AdiShape<S>::threads) void adi_kernel(AdiArgs a) {
   extern __shared__ double smem[];
   __shared__ uint32_t barrier_ok;
   uint32_t gen = 0;
@@ -645,8 +657,8 @@ __global__ __launch_bounds__(kAdiThreads) void adi_kernel(AdiArgs a) {
   const uint32_t l_items = a.n_vlines * a.bv + (a.n_lines - a.n_vlines) * a.bh;
   {  // pivots' reciprocals of both directions into LDS, segment layout
     constexpr uint32_t M = (uint32_t)kSegs * S;
-    double* inv = smem + kLines * seg_pitch(S);
-    for (uint32_t i = threadIdx.x; i < M; i += kAdiThreads) {
+    double* inv = smem + AdiShape<S>::lines * seg_pitch(S);
+    for (uint32_t i = threadIdx.x; i < M; i += AdiShape<S>::threads) {
       inv[lds_pos<S>(i)] = a.inv_x[i];
       inv[seg_span(S) + lds_pos<S>(i)] = a.inv_y[i];
     }
@@ -880,13 +892,14 @@ int brt_pdd_create(brt_ctx* ctx, const brt_problem* prob, const brt_pdd_grid* gr
                             (int)p->lds) != hipSuccess)
       rc = set_error(BRT_E_DEVICE, "pdd: solver LDS of %zu bytes", p->lds);
     if (rc == BRT_OK &&
-        (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, adi_kernel_ptr(p->seg), kAdiThreads,
+        (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, adi_kernel_ptr(p->seg), adi_threads(p->seg),
                                                       p->lds) != hipSuccess ||
          per_cu < 1))
       rc = set_error(BRT_E_DEVICE, "pdd: solver occupancy query (LDS %zu bytes)", p->lds);
     const uint32_t nsub = g.px * g.py;
-    const uint32_t x_items = nsub * ((g.cy - 1 + kLines - 1) / kLines);
-    const uint32_t y_items = nsub * ((g.cx - 1 + kLines - 1) / kLines);
+    const uint32_t lines = adi_lines(p->seg);
+    const uint32_t x_items = nsub * ((g.cy - 1 + lines - 1) / lines);
+    const uint32_t y_items = nsub * ((g.cx - 1 + lines - 1) / lines);
     const uint64_t cap = (uint64_t)per_cu * p->n_cu;
     // Half the compute units, a multiple of the die count: the phases are bound by the memory system,
     // and on the 4 x 4 x 512^2 workload a step took 106 us at 128 blocks of 512 threads, 107 at 192,
@@ -1036,11 +1049,12 @@ int brt_pdd_solve(brt_pdd* p, uint32_t steps, double* field, void* stream) {
   a.cy = g.cy;
   a.steps = steps;
   a.nblocks = (uint32_t)p->grid;
-  a.x_blk = (g.cy - 1 + kLines - 1) / kLines;
-  a.y_blk = (g.cx - 1 + kLines - 1) / kLines;
+  const uint32_t lines = adi_lines(p->seg), threads = adi_threads(p->seg);
+  a.x_blk = (g.cy - 1 + lines - 1) / lines;
+  a.y_blk = (g.cx - 1 + lines - 1) / lines;
   a.n_vlines = p->n_vlines;
-  a.bv = (p->NY + 1 + kAdiThreads - 1) / kAdiThreads;
-  a.bh = (p->NX + 1 + kAdiThreads - 1) / kAdiThreads;
+  a.bv = (p->NY + 1 + threads - 1) / threads;
+  a.bh = (p->NX + 1 + threads - 1) / threads;
   a.n_lines = (uint32_t)p->lines.size();
   std::memcpy(a.vline, p->vline, sizeof(a.vline));
   std::memcpy(a.hline, p->hline, sizeof(a.hline));
@@ -1048,7 +1062,7 @@ int brt_pdd_solve(brt_pdd* p, uint32_t steps, double* field, void* stream) {
   a.h_fine = p->NX + 1;
   for (size_t l = 0; l < p->lines.size(); ++l) a.bd_off[l] = p->lines[l].bd_off;
   void* kargs[] = {&a};
-  PDD_TRY(hipLaunchCooperativeKernel(adi_kernel_ptr(p->seg), dim3(p->grid), dim3(kAdiThreads), kargs,
+  PDD_TRY(hipLaunchCooperativeKernel(adi_kernel_ptr(p->seg), dim3(p->grid), dim3(threads), kargs,
                                      (unsigned)p->lds, s));
   const double* result = ((steps & 1) ? p->d_f[1] : p->d_f[0]) + kFieldLead;
   PDD_TRY(hipMemcpy2DAsync(field, 8 * (size_t)(p->NX + 1), result, 8 * (size_t)p->W, 8 * (size_t)(p->NX + 1), p->NY + 1,
