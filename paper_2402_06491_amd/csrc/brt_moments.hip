@@ -16,7 +16,7 @@
 namespace brt {
 
 constexpr int kRedGroup = 16;  // moment bins accumulated per pass over a segment
-constexpr int kRedBatch = 8;   // records loaded per lane before they are accumulated
+constexpr int kRedBatch = 32;  // records loaded per lane before they are accumulated
 constexpr uint32_t kAbsent = 0xffffffffu;  // marks a batch slot past the end of the segment (no real
                                            // record has every flag bit set)
 
