@@ -422,15 +422,16 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
       tau2 = ((Real)(~w.a) + (Real)0.5) * ts;
     }
 
+    // Box-Muller radius and the Brownian scale under one square root: sigma sqrt(-2 ln(u1) dt) with
+    // dt = S on the way to a split, tau to a leaf
     const Real u1 = ((Real)w.c + (Real)0.5) * (Real)0x1p-32;
     const Real u2 = (Real)w.d * (Real)0x1p-32;
-    const Real r = Math<Real>::sq((Real)-2 * Math<Real>::ln(u1));
     Real sn, cs;
     Math<Real>::sincos_rev(u2, &sn, &cs);
-    const Real sd = hc.sigma * Math<Real>::sq(vertex ? S : tau);
+    const Real sdr = hc.sigma * Math<Real>::sq((Real)-2 * Math<Real>::ln(u1) * (vertex ? S : tau));
     Real xn[2];
-    xn[0] = x[0] + sd * (r * cs);
-    xn[1] = x[1] + sd * (r * sn);
+    xn[0] = x[0] + sdr * cs;
+    xn[1] = x[1] + sdr * sn;
 
     // one exponential per node: the vertex weight e^{(alpha-1) mu tau'} or, for logistic initial
     // data, e^{s (n.x - x0)} at the leaf
