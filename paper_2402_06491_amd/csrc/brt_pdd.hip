@@ -339,7 +339,7 @@ __device__ inline double hline_value(const AdiArgs& a, uint32_t ky, uint32_t x, 
 // A work item is L lines of one subdomain, solved by one block of 32 L threads with the lines resident
 // in LDS (L = 32 for segments of 16 unknowns, 16 for segments of 32).  Three passes:
 //   1. the right-hand sides, from coalesced global loads (x phase: threads along the positions of the
-//      item's rows; y phase: L columns x 32 row groups), into LDS [line][position];
+//      item's rows; y phase: L/2 column pairs x 64 row groups), into LDS [line][position];
 //   2. the tridiagonal solves, kSegs threads per line, each owning S consecutive positions: a local
 //      forward recurrence, a scan of the segments' affine carry maps over the line's lanes, the carry
 //      applied, a local backward recurrence, a reverse scan, and the backward carry applied;
@@ -382,6 +382,15 @@ __device__ inline double ldg(const double* base, uint32_t byte_off) {
 }
 __device__ inline void stg(double* base, uint32_t byte_off, double v) {
   *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + byte_off) = v;
+}
+// Two neighbouring columns in one access; only 8-byte alignment is assumed (multi-dword global
+// accesses need dword alignment), so a pair may start at any column.
+typedef double dpair __attribute__((ext_vector_type(2), aligned(8)));
+__device__ inline dpair ldg2(const double* base, uint32_t byte_off) {
+  return *reinterpret_cast<const dpair*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+__device__ inline void stg2(double* base, uint32_t byte_off, dpair v) {
+  *reinterpret_cast<dpair*>(reinterpret_cast<char*>(base) + byte_off) = v;
 }
 
 // Keeps the scheduler from hoisting the loads of a later batch above this point.
@@ -549,61 +558,73 @@ __device__ void x_sweep(const AdiArgs& a, uint32_t item, uint32_t n, const doubl
 template <int S>
 __device__ void y_sweep(const AdiArgs& a, uint32_t item, uint32_t n, const double* __restrict__ cur,
                         double* __restrict__ next, double* __restrict__ smem) {
-  constexpr int L = AdiShape<S>::lines;
+  constexpr int L = AdiShape<S>::lines, T = AdiShape<S>::threads;
   constexpr uint32_t pitch = seg_pitch(S);
-  constexpr uint32_t npt = S;  // positions per thread: kSegs row groups cover kSegs * S positions
+  constexpr uint32_t P2 = L / 2, G = T / P2, npt = (uint32_t)kSegs * S / G;  // pairs per row, row groups, positions per thread
   const uint32_t t = thread_index();
-  const uint32_t l = t % L, q = t / L;  // column, row group
+  const uint32_t c = t % P2, q = t / P2;  // column pair, row group
   const uint32_t sub = item / a.y_blk, blk = item % a.y_blk;
   const uint32_t sx = sub % a.px, sy = sub / a.px;
   const uint32_t xfirst = sx * a.cx + 1 + blk * L;
   const uint32_t nl = min((uint32_t)L, (sx + 1) * a.cx - xfirst);
-  const uint32_t x = xfirst + min(l, nl - 1);
+  const uint32_t cc = min(c, (nl - 1) / 2);
+  const uint32_t x = xfirst + 2 * cc;   // first column of the pair (x + 1 exists: interior or the line column)
   const uint32_t r0 = sy * a.cy, m = a.cy - 1, W = a.W;
   double* __restrict__ D = smem;  // [line][pitch]
   const double* __restrict__ INV = D + L * pitch + seg_span(S);  // y lines
-  // bases at the subdomain's first row; offsets of (row, column) stay below 2^32 bytes
   const double* __restrict__ star_b = a.star + (size_t)r0 * W;
   const double* __restrict__ cur_b = cur + (size_t)r0 * W;
   double* __restrict__ next_b = next + (size_t)r0 * W;
   const double* __restrict__ ey_b = a.ey + r0 + 1;
-  const double gb0 = a.ry2 * hline_value(a, sy, x, n + 1);
-  const double gb1 = a.ry2 * hline_value(a, sy + 1, x, n + 1);
+  const double gb00 = a.ry2 * hline_value(a, sy, x, n + 1), gb01 = a.ry2 * hline_value(a, sy, x + 1, n + 1);
+  const double gb10 = a.ry2 * hline_value(a, sy + 1, x, n + 1), gb11 = a.ry2 * hline_value(a, sy + 1, x + 1, n + 1);
   const double tf = time_factor(a, n);
-  const double exv = a.ex[x];
+  const double ex0 = a.ex[x], ex1 = a.ex[x + 1];
+  const uint32_t l0 = 2 * c, l1 = 2 * c + 1;
 #pragma unroll
   for (uint32_t kb = 0; kb < npt; kb += kYBatch) {
-    double sl[kYBatch], sc[kYBatch], sr[kYBatch], cu[kYBatch], pr[kYBatch], ey[kYBatch];
+    dpair sc[kYBatch], cu[kYBatch], pr[kYBatch];
+    double sl[kYBatch], sr[kYBatch], ey[kYBatch];
 #pragma unroll
     for (int k = 0; k < kYBatch; ++k) {
-      const uint32_t p = min(q + kSegs * (kb + k), m - 1);
+      const uint32_t p = min(q + G * (kb + k), m - 1);
       const uint32_t off = 8 * ((1 + p) * W + x);
       sl[k] = ldg(star_b, off - 8);
-      sc[k] = ldg(star_b, off);
-      sr[k] = ldg(star_b, off + 8);
-      cu[k] = ldg(cur_b, off);
-      pr[k] = ldg(next_b, off);  // next still holds u^{n-1}
+      sc[k] = ldg2(star_b, off);
+      sr[k] = ldg(star_b, off + 16);
+      cu[k] = ldg2(cur_b, off);
+      pr[k] = ldg2(next_b, off);  // next still holds u^{n-1}
       ey[k] = ldg(ey_b, 8 * p);
     }
 #pragma unroll
     for (int k = 0; k < kYBatch; ++k) {
-      const uint32_t p = q + kSegs * (kb + k);
-      const double F = reaction_at(a, 1.5 * cu[k] - 0.5 * pr[k], exv * ey[k], tf);
-      double d = sc[k] + a.rx2 * ((sl[k] - 2.0 * sc[k]) + sr[k]) + a.dt2 * F;
-      if (p == 0) d += gb0;
-      if (p == m - 1) d += gb1;
-      D[l * pitch + lds_pos<S>(p)] = p < m ? d : 0.0;
+      const uint32_t p = q + G * (kb + k);
+      const double F0 = reaction_at(a, 1.5 * cu[k].x - 0.5 * pr[k].x, ex0 * ey[k], tf);
+      const double F1 = reaction_at(a, 1.5 * cu[k].y - 0.5 * pr[k].y, ex1 * ey[k], tf);
+      double d0 = sc[k].x + a.rx2 * ((sl[k] - 2.0 * sc[k].x) + sc[k].y) + a.dt2 * F0;
+      double d1 = sc[k].y + a.rx2 * ((sc[k].x - 2.0 * sc[k].y) + sr[k]) + a.dt2 * F1;
+      if (p == 0) { d0 += gb00; d1 += gb01; }
+      if (p == m - 1) { d0 += gb10; d1 += gb11; }
+      const uint32_t o = lds_pos<S>(p);
+      D[l0 * pitch + o] = p < m ? d0 : 0.0;
+      D[l1 * pitch + o] = p < m ? d1 : 0.0;
     }
     batch_fence();
   }
   __syncthreads();
   solve_lines<S>(D, pitch, INV, a.ry2);
   __syncthreads();
-  if (l < nl)
+  if (l0 < nl)
 #pragma unroll 4
     for (uint32_t k = 0; k < npt; ++k) {
-      const uint32_t p = q + kSegs * k;
-      if (p < m) stg(next_b, 8 * ((1 + p) * W + x), D[l * pitch + lds_pos<S>(p)]);
+      const uint32_t p = q + G * k;
+      if (p < m) {
+        const uint32_t o = lds_pos<S>(p), off = 8 * ((1 + p) * W + x);
+        if (l1 < nl)
+          stg2(next_b, off, dpair{D[l0 * pitch + o], D[l1 * pitch + o]});
+        else
+          stg(next_b, off, D[l0 * pitch + o]);
+      }
     }
   __syncthreads();
 }

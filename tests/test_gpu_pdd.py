@@ -117,6 +117,17 @@ def test_tail_single_subdomain_and_cos2(ctx):
     _tail_parity(ctx, "tail_single_cos2", prob, grid, vals)
 
 
+def test_tail_odd_subdomain_width(ctx):
+    """3 x 2 subdomains of 21 x 19 cells: with an odd width the y sweep's column pairs of the middle
+    subdomain start on 8-byte (not 16-byte) boundaries, and the last pair of each strip is ragged."""
+    grid = _grid(px=3, py=2, cx=21, cy=19, n_steps=20, ns_x=11, ns_y=7, nt=4)
+    og = opdd.Grid(**grid)
+    rng = np.random.default_rng(23)
+    xy, t = opdd.node_points(og)
+    vals = 0.3 * np.cos(0.4 * xy[:, 0]) * np.exp(-xy[:, 1] ** 2 / 10.0) * (1 + 0.5 * t) + 0.01 * rng.normal(size=len(t))
+    _tail_parity(ctx, "tail_odd_width", _cubic(1), grid, vals)
+
+
 def test_tail_long_lines_32_unknown_segments(ctx):
     """2 x 1 subdomains of 600 x 30 cells: lines of 599 unknowns take the solver's 32-unknown segments
     (the ragged last segment holds 23), and the short y lines leave most segments empty."""
