@@ -357,7 +357,6 @@ struct AdiShape {
   static constexpr int lines = S == 16 ? 32 : 16;  // lines per item
   static constexpr int threads = lines * kSegs;    // threads per block
 };
-constexpr int kMaxAdiThreads = 1024;
 
 static_assert(kMaxCells - 1 <= (uint32_t)kSegs * 32, "the longest line must fit 32 segments of 32");
 
@@ -479,10 +478,10 @@ __device__ void x_sweep(const AdiArgs& a, uint32_t item, uint32_t n, const doubl
   constexpr int L = AdiShape<S>::lines, T = AdiShape<S>::threads;
   constexpr uint32_t M = (uint32_t)kSegs * S;
   constexpr uint32_t pitch = seg_pitch(S);
-  // pass 1 and 3: threads along the positions; with more threads than positions, row sets of R rows
-  constexpr uint32_t sets = T >= (int)M ? T / M : 1, R = L / sets, pstep = sets > 1 ? M : T;
+  // pass 1 and 3: threads along the position pairs; with more threads than pairs, row sets of R rows
+  constexpr uint32_t NP = M / 2, sets = T >= (int)NP ? T / NP : 1, R = L / sets, pstep = sets > 1 ? NP : T;
   const uint32_t t = thread_index();
-  const uint32_t h = sets > 1 ? t / M : 0, p0 = sets > 1 ? t % M : t, r0 = h * R;
+  const uint32_t h = sets > 1 ? t / NP : 0, pp0 = sets > 1 ? t % NP : t, r0 = h * R;
   const uint32_t sub = item / a.x_blk, blk = item % a.x_blk;
   const uint32_t sx = sub % a.px, sy = sub / a.px;
   const uint32_t ybase = sy * a.cy + 1 + blk * L;
@@ -510,33 +509,42 @@ __device__ void x_sweep(const AdiArgs& a, uint32_t item, uint32_t n, const doubl
     }
   }
   __syncthreads();
-  for (uint32_t p = p0; p < M; p += pstep) {
-    const uint32_t o = lds_pos<S>(p);
-    if (p >= m) {
+  for (uint32_t pp = pp0; pp < NP; pp += pstep) {
+    const uint32_t pa = 2 * pp, pb = pa + 1;  // the pair's positions (pb may be the line column)
+    const uint32_t oa = lds_pos<S>(pa), ob = lds_pos<S>(pb);
+    if (pa >= m) {
 #pragma unroll
-      for (uint32_t k = 0; k < R; ++k) D[(r0 + k) * pitch + o] = 0.0;
+      for (uint32_t k = 0; k < R; ++k) {
+        D[(r0 + k) * pitch + oa] = 0.0;
+        D[(r0 + k) * pitch + ob] = 0.0;
+      }
       continue;
     }
-    const uint32_t vo = 8 * p;
-    const double exv = ldg(a.ex + c0 + 1, vo);
-    double up = ldg(cur_b + (size_t)min(r0, nrows + 1) * W, vo), mid = ldg(cur_b + (size_t)min(r0 + 1, nrows + 1) * W, vo);
+    const uint32_t vo = 8 * pa;
+    const dpair exv = ldg2(a.ex + c0 + 1, vo);
+    dpair up = ldg2(cur_b + (size_t)min(r0, nrows + 1) * W, vo), mid = ldg2(cur_b + (size_t)min(r0 + 1, nrows + 1) * W, vo);
 #pragma unroll
     for (uint32_t k0 = 0; k0 < R; k0 += kXBatch) {
-      double cv[kXBatch], pv[kXBatch];
+      dpair cv[kXBatch], pv[kXBatch];
 #pragma unroll
       for (int k = 0; k < kXBatch; ++k) {
-        cv[k] = ldg(cur_b + (size_t)min(r0 + k0 + k + 2, nrows + 1) * W, vo);
-        pv[k] = ldg(prev_b + (size_t)min(r0 + k0 + k, nrows - 1) * W, vo);
+        cv[k] = ldg2(cur_b + (size_t)min(r0 + k0 + k + 2, nrows + 1) * W, vo);
+        pv[k] = ldg2(prev_b + (size_t)min(r0 + k0 + k, nrows - 1) * W, vo);
       }
 #pragma unroll
       for (int k = 0; k < kXBatch; ++k) {
         const uint32_t row = r0 + k0 + k;
-        const double u = mid, dn = cv[k];
-        const double F = reaction_at(a, 1.5 * u - 0.5 * pv[k], exv * EY[row], tf);
-        double d = u + a.ry2 * ((up - 2.0 * u) + dn) + a.dt2 * F;
-        if (p == 0) d += SB[row];
-        if (p == m - 1) d += SB[L + row];
-        D[row * pitch + o] = d;
+        const dpair u = mid, dn = cv[k];
+        const double ey = EY[row];
+        const double Fa = reaction_at(a, 1.5 * u.x - 0.5 * pv[k].x, exv.x * ey, tf);
+        const double Fb = reaction_at(a, 1.5 * u.y - 0.5 * pv[k].y, exv.y * ey, tf);
+        double da = u.x + a.ry2 * ((up.x - 2.0 * u.x) + dn.x) + a.dt2 * Fa;
+        double db = u.y + a.ry2 * ((up.y - 2.0 * u.y) + dn.y) + a.dt2 * Fb;
+        if (pa == 0) da += SB[row];
+        if (pa == m - 1) da += SB[L + row];
+        if (pb == m - 1) db += SB[L + row];
+        D[row * pitch + oa] = da;
+        D[row * pitch + ob] = pb < m ? db : 0.0;
         up = mid;
         mid = dn;
       }
@@ -546,11 +554,18 @@ __device__ void x_sweep(const AdiArgs& a, uint32_t item, uint32_t n, const doubl
   __syncthreads();
   solve_lines<S>(D, pitch, INV, a.rx2);
   __syncthreads();
-  for (uint32_t p = p0; p < m; p += pstep) {
-    const uint32_t o = lds_pos<S>(p);
+  for (uint32_t pp = pp0; 2 * pp < m; pp += pstep) {
+    const uint32_t pa = 2 * pp, pb = pa + 1;
+    const uint32_t oa = lds_pos<S>(pa), ob = lds_pos<S>(pb);
 #pragma unroll
-    for (uint32_t k = 0; k < R; ++k)
-      if (r0 + k < nrows) stg(star_b + (size_t)(r0 + k) * W, 8 * p, D[(r0 + k) * pitch + o]);
+    for (uint32_t k = 0; k < R; ++k) {
+      if (r0 + k >= nrows) continue;
+      double* row = star_b + (size_t)(r0 + k) * W;
+      if (pb < m)
+        stg2(row, 8 * pa, dpair{D[(r0 + k) * pitch + oa], D[(r0 + k) * pitch + ob]});
+      else
+        stg(row, 8 * pa, D[(r0 + k) * pitch + oa]);
+    }
   }
   __syncthreads();
 }
