@@ -37,6 +37,7 @@ constexpr double kBarrierSeconds = 5.0;
 // tiles map onto whole cache lines.
 constexpr uint32_t kFieldLead = 15;  // doubles before column 0
 constexpr uint32_t kXcds = 8;        // workgroups are dealt to the accelerator's dies round-robin
+constexpr uint32_t kSyncWords = 4 + 2 * kXcds;  // abort word, then arrivals and generation per group
 
 #define PDD_TRY(expr)                                                                               \
   do {                                                                                              \
@@ -247,7 +248,8 @@ struct AdiArgs {
   const LineDev* lines;
   const double* inv_x;  // pivots' reciprocals of the x and the y lines, kSegs * S each, zero-padded
   const double* inv_y;
-  uint32_t* sync;       // [0] arrivals, [1] generation, [2] abort, [3 + 2n], [4 + 2n] work counters of step n
+  uint32_t* sync;       // [2] abort; [4 + 2g], [5 + 2g] arrivals and generation of barrier group g
+  double* edge;         // per subdomain: intermediate values on its left and right vertical line (cy each)
   uint64_t spin_limit;  // wall-clock ticks a barrier may wait
   double pcoef[8];      // f(u) = c_1 u + m(x, y, t) sum_{j != 1} c_j u^j: the non-linear part (c_1 zeroed) ...
   const double* ex;     // ... scaled by ex[i] ey[j] (t_mid + t0)^-pow (all 1 with constant coefficients)
@@ -259,6 +261,7 @@ struct AdiArgs {
   uint32_t px, py, cx, cy;
   uint32_t steps;
   uint32_t nblocks;
+  uint32_t groups;      // barrier groups: 1 (the whole grid) or one per die, each owning whole subdomains
   uint32_t x_blk, y_blk;       // items per subdomain in the x and the y phase
   uint32_t n_vlines, bv, bh;   // data lines: vertical count; blocks of nodes per vertical / horizontal line
   uint32_t n_lines;
@@ -284,26 +287,27 @@ __device__ inline double time_factor(const AdiArgs& a, uint32_t n) {
   return a.cm_pow ? 1.0 / ((n + 0.5) * a.dt + a.cm_t0) : 1.0;
 }
 
-// Grid barrier (sense by generation count).  Every block waits at most spin_limit wall-clock ticks; on
-// a time-out, or when another block has timed out, it raises the abort word and returns false so that
-// every block leaves the kernel.
-__device__ bool grid_barrier(uint32_t* sync, uint32_t nblocks, uint32_t& gen, uint64_t spin_limit, uint32_t* flag) {
+// Barrier of a group of blocks (sense by generation count; cnt[0] counts arrivals, cnt[1] is the
+// generation).  Every block waits at most spin_limit wall-clock ticks; on a time-out, or when any block
+// has timed out, it raises the abort word and returns false so that every block leaves the kernel.
+__device__ bool group_barrier(uint32_t* cnt, uint32_t* abort_word, uint32_t members, uint32_t& gen, uint64_t spin_limit,
+                              uint32_t* flag) {
   __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t ok = 1;
     __threadfence();
     const uint32_t target = gen + 1;
-    if (atomicAdd(&sync[0], 1u) == nblocks - 1) {
-      __hip_atomic_store(&sync[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(&sync[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (atomicAdd(&cnt[0], 1u) == members - 1) {
+      __hip_atomic_store(&cnt[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&cnt[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       const uint64_t t0 = wall_clock64();
       // relaxed polling: an acquiring load would invalidate this XCD's L2 on every poll while other
       // blocks still work; the fence below acquires once the generation has moved
-      while (__hip_atomic_load(&sync[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != target) {
-        if (__hip_atomic_load(&sync[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+      while (__hip_atomic_load(&cnt[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != target) {
+        if (__hip_atomic_load(abort_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
             wall_clock64() - t0 > spin_limit) {
-          atomicExch(&sync[2], 1u);
+          atomicExch(abort_word, 1u);
           ok = 0;
           break;
         }
@@ -496,16 +500,28 @@ __device__ void x_sweep(const AdiArgs& a, uint32_t item, uint32_t n, const doubl
   const double* __restrict__ cur_b = cur + (size_t)(ybase - 1) * W + c0 + 1;  // row above the item
   const double* __restrict__ prev_b = prev + (size_t)ybase * W + c0 + 1;
   double* __restrict__ star_b = star + (size_t)ybase * W + c0 + 1;
+  // Halo rows on the subdomain's horizontal data lines are read from the boundary data (level n), so a
+  // subdomain never reads field values that another subdomain's solve writes.
+  const int hl_top = blk == 0 ? a.hline[sy] : -1;
+  const int hl_bot = ybase + nrows == (sy + 1) * a.cy ? a.hline[sy + 1] : -1;
+  const double* __restrict__ top_b = hl_top >= 0 ? a.bd + a.bd_off[hl_top] + (size_t)n * a.h_fine + c0 + 1 : cur_b;
+  const double* __restrict__ bot_b =
+      hl_bot >= 0 ? a.bd + a.bd_off[hl_bot] + (size_t)n * a.h_fine + c0 + 1 : cur_b + (size_t)(nrows + 1) * W;
+  auto cur_row = [&](uint32_t rel) {  // rel: row above the item = 0; clamped to nrows + 1
+    return rel == 0 ? top_b : rel >= nrows + 1 ? bot_b : cur_b + (size_t)rel * W;
+  };
   if (t < (uint32_t)L) {
     EY[t] = a.ey[min(ybase + t, ybase + nrows - 1)];
     if (t < nrows) {
+      // the intermediate level on the subdomain's vertical lines, kept for the y phase in the
+      // subdomain's own edge buffer (neighbouring subdomains never share a location)
       const uint32_t y = ybase + t;
-      const double usl = ustar_line(a, sx, y, n);
-      const double usr = ustar_line(a, sx + 1, y, n);
+      const double usl = ustar_line(a, sx, y, n), usr = ustar_line(a, sx + 1, y, n);
       SB[t] = a.rx2 * usl;
       SB[L + t] = a.rx2 * usr;
-      star[(size_t)y * W + c0] = usl;
-      if (sx == a.px - 1) star[(size_t)y * W + c0 + a.cx] = usr;
+      double* e = a.edge + (size_t)sub * 2 * a.cy + (y - sy * a.cy);
+      e[0] = usl;
+      e[a.cy] = usr;
     }
   }
   __syncthreads();
@@ -522,13 +538,13 @@ __device__ void x_sweep(const AdiArgs& a, uint32_t item, uint32_t n, const doubl
     }
     const uint32_t vo = 8 * pa;
     const dpair exv = ldg2(a.ex + c0 + 1, vo);
-    dpair up = ldg2(cur_b + (size_t)min(r0, nrows + 1) * W, vo), mid = ldg2(cur_b + (size_t)min(r0 + 1, nrows + 1) * W, vo);
+    dpair up = ldg2(cur_row(min(r0, nrows + 1)), vo), mid = ldg2(cur_row(min(r0 + 1, nrows + 1)), vo);
 #pragma unroll
     for (uint32_t k0 = 0; k0 < R; k0 += kXBatch) {
       dpair cv[kXBatch], pv[kXBatch];
 #pragma unroll
       for (int k = 0; k < kXBatch; ++k) {
-        cv[k] = ldg2(cur_b + (size_t)min(r0 + k0 + k + 2, nrows + 1) * W, vo);
+        cv[k] = ldg2(cur_row(min(r0 + k0 + k + 2, nrows + 1)), vo);
         pv[k] = ldg2(prev_b + (size_t)min(r0 + k0 + k, nrows - 1) * W, vo);
       }
 #pragma unroll
@@ -596,6 +612,10 @@ __device__ void y_sweep(const AdiArgs& a, uint32_t item, uint32_t n, const doubl
   const double tf = time_factor(a, n);
   const double ex0 = a.ex[x], ex1 = a.ex[x + 1];
   const uint32_t l0 = 2 * c, l1 = 2 * c + 1;
+  // intermediate values on the subdomain's vertical data lines come from its edge buffer
+  const bool lft = x - 1 == sx * a.cx, rgt1 = x + 1 == (sx + 1) * a.cx, rgt2 = x + 2 == (sx + 1) * a.cx;
+  const double* __restrict__ el = a.edge + (size_t)sub * 2 * a.cy + 1;  // by position p
+  const double* __restrict__ er = el + a.cy;
 #pragma unroll
   for (uint32_t kb = 0; kb < npt; kb += kYBatch) {
     dpair sc[kYBatch], cu[kYBatch], pr[kYBatch];
@@ -604,9 +624,10 @@ __device__ void y_sweep(const AdiArgs& a, uint32_t item, uint32_t n, const doubl
     for (int k = 0; k < kYBatch; ++k) {
       const uint32_t p = min(q + G * (kb + k), m - 1);
       const uint32_t off = 8 * ((1 + p) * W + x);
-      sl[k] = ldg(star_b, off - 8);
+      sl[k] = lft ? el[p] : ldg(star_b, off - 8);
       sc[k] = ldg2(star_b, off);
-      sr[k] = ldg(star_b, off + 16);
+      if (rgt1) sc[k].y = er[p];
+      sr[k] = rgt2 ? er[p] : ldg(star_b, off + 16);
       cu[k] = ldg2(cur_b, off);
       pr[k] = ldg2(next_b, off);  // next still holds u^{n-1}
       ey[k] = ldg(ey_b, 8 * p);
@@ -688,6 +709,8 @@ __global__ __launch_bounds__(AdiShape<S>::threads) void adi_kernel(AdiArgs a) {
   __shared__ uint32_t barrier_ok;
   uint32_t gen = 0;
   const uint32_t nsub = a.px * a.py;
+  uint32_t* const bar = a.sync + 4 + 2 * (blockIdx.x % a.groups);
+  const uint32_t members = gridDim.x / a.groups;
   const uint32_t x_items = nsub * a.x_blk;
   const uint32_t y_items = nsub * a.y_blk;
   const uint32_t l_items = a.n_vlines * a.bv + (a.n_lines - a.n_vlines) * a.bh;
@@ -707,10 +730,10 @@ __global__ __launch_bounds__(AdiShape<S>::threads) void adi_kernel(AdiArgs a) {
     const double* cur = (n & 1) ? a.f1 : a.f0;
     double* prev = (n & 1) ? a.f0 : a.f1;  // holds u^{n-1}; receives u^{n+1}
     for (uint32_t it = xr.begin; it < xr.end; it += xr.stride) x_sweep<S>(a, it, n, cur, prev, smem);
-    if (!grid_barrier(a.sync, a.nblocks, gen, a.spin_limit, &barrier_ok)) return;
+    if (!group_barrier(bar, a.sync + 2, members, gen, a.spin_limit, &barrier_ok)) return;
     for (uint32_t it = yr.begin; it < yr.end; it += yr.stride) y_sweep<S>(a, it, n, cur, prev, smem);
     for (uint32_t it = blockIdx.x; it < l_items; it += gridDim.x) write_lines(a, it, n, prev);
-    if (!grid_barrier(a.sync, a.nblocks, gen, a.spin_limit, &barrier_ok)) return;
+    if (!group_barrier(bar, a.sync + 2, members, gen, a.spin_limit, &barrier_ok)) return;
   }
 }
 
@@ -735,6 +758,7 @@ struct brt_pdd {
   double* d_fac = nullptr;
   double* d_spl = nullptr;  // vals, mom, cp, rowsv, tmom, tcp
   uint32_t* d_sync = nullptr;
+  double* d_edge = nullptr;  // solver: per-subdomain intermediate values on its vertical lines
   double* d_node_u = nullptr;
   double* d_exy = nullptr;  // variable coefficients: e^{-bx x_i^2} (NX+1), then e^{-by y_j^2} (NY+1)
   size_t spl_rows = 0, spl_fine = 0;
@@ -760,6 +784,7 @@ void pdd_free(brt_pdd* p) {
   (void)hipFree(p->d_fac);
   (void)hipFree(p->d_spl);
   (void)hipFree(p->d_sync);
+  (void)hipFree(p->d_edge);
   (void)hipFree(p->d_node_u);
   (void)hipFree(p->d_exy);
   for (hipEvent_t e : p->ev)
@@ -896,7 +921,8 @@ int brt_pdd_create(brt_ctx* ctx, const brt_problem* prob, const brt_pdd_grid* gr
   p->seg = seg_length(g);
   dev_alloc((void**)&p->d_fac, 8 * 2 * (size_t)kSegs * p->seg);
   dev_alloc((void**)&p->d_spl, 8 * (3 * p->spl_rows + 3 * p->spl_fine));
-  dev_alloc((void**)&p->d_sync, 4 * (3 + 2 * (size_t)g.n_steps));
+  dev_alloc((void**)&p->d_sync, 4 * (size_t)kSyncWords);
+  dev_alloc((void**)&p->d_edge, 8 * 2 * (size_t)g.px * g.py * g.cy);
   dev_alloc((void**)&p->d_node_u, 8 * std::max<uint64_t>(p->n_nodes, 1));
   dev_alloc((void**)&p->d_exy, 8 * (size_t)(p->NX + 1 + p->NY + 1));
   for (hipEvent_t& e : p->ev)
@@ -1052,7 +1078,7 @@ int brt_pdd_solve(brt_pdd* p, uint32_t steps, double* field, void* stream) {
   const uint64_t n_field = (uint64_t)(p->NX + 1) * (p->NY + 1);
   init_field_kernel<<<(unsigned)((n_field + 255) / 256), 256, 0, s>>>(fa);
   PDD_TRY(hipGetLastError());
-  PDD_TRY(hipMemsetAsync(p->d_sync, 0, 4 * (3 + 2 * (size_t)steps), s));
+  PDD_TRY(hipMemsetAsync(p->d_sync, 0, 4 * (size_t)kSyncWords, s));
 
   AdiArgs a{};
   a.f0 = p->d_f[0] + kFieldLead;
@@ -1063,6 +1089,7 @@ int brt_pdd_solve(brt_pdd* p, uint32_t steps, double* field, void* stream) {
   a.inv_x = p->d_fac;
   a.inv_y = p->d_fac + (size_t)kSegs * p->seg;
   a.sync = p->d_sync;
+  a.edge = p->d_edge;
   int rate_khz = 0;
   PDD_TRY(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, p->device));
   a.spin_limit = (uint64_t)(kBarrierSeconds * 1e3 * (rate_khz > 0 ? rate_khz : 100000));
@@ -1085,6 +1112,9 @@ int brt_pdd_solve(brt_pdd* p, uint32_t steps, double* field, void* stream) {
   a.cy = g.cy;
   a.steps = steps;
   a.nblocks = (uint32_t)p->grid;
+  // Subdomains are decoupled: when every die's blocks own whole subdomains in both phases, each die's
+  // blocks synchronise among themselves only.
+  a.groups = (p->grid % kXcds == 0 && (g.px * g.py) % kXcds == 0) ? kXcds : 1u;
   const uint32_t lines = adi_lines(p->seg), threads = adi_threads(p->seg);
   a.x_blk = (g.cy - 1 + lines - 1) / lines;
   a.y_blk = (g.cx - 1 + lines - 1) / lines;
