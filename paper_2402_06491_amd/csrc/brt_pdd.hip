@@ -964,8 +964,8 @@ int brt_pdd_create(brt_ctx* ctx, const brt_problem* prob, const brt_pdd_grid* gr
     const uint32_t y_items = nsub * ((g.cx - 1 + lines - 1) / lines);
     const uint64_t cap = (uint64_t)per_cu * p->n_cu;
     // Half the compute units, a multiple of the die count: the phases are bound by the memory system,
-    // and on the 4 x 4 x 512^2 workload a step took 99 us at 128 blocks of 1024 threads, 110 at 192 and
-    // at 256, 116 at 96 (more concurrent blocks only lengthen every block's memory latency).
+    // and on the 4 x 4 x 512^2 workload a step took 76 us at 128 blocks of 1024 threads and 88 at 256
+    // (more concurrent blocks only lengthen every block's memory latency).
     const uint64_t half = std::max<uint64_t>(kXcds, (uint64_t)p->n_cu / 2 / kXcds * kXcds);
     p->grid = (int)std::min<uint64_t>({(uint64_t)std::max(x_items, y_items), half, cap});
   }
