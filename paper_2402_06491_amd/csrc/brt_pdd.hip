@@ -243,13 +243,12 @@ __global__ void init_field_kernel(FieldArgs a) {
 struct AdiArgs {
   double* f0;
   double* f1;
-  double* star;
+  double* yrhs;         // the y phase's right-hand sides without boundary terms, written by the x phase
   const double* bd;
   const LineDev* lines;
   const double* inv_x;  // pivots' reciprocals of the x and the y lines, kSegs * S each, zero-padded
   const double* inv_y;
   uint32_t* sync;       // [2] abort; [4 + 2g], [5 + 2g] arrivals and generation of barrier group g
-  double* edge;         // per subdomain: intermediate values on its left and right vertical line (cy each)
   uint64_t spin_limit;  // wall-clock ticks a barrier may wait
   double pcoef[8];      // f(u) = c_1 u + m(x, y, t) sum_{j != 1} c_j u^j: the non-linear part (c_1 zeroed) ...
   const double* ex;     // ... scaled by ex[i] ey[j] (t_mid + t0)^-pow (all 1 with constant coefficients)
@@ -369,9 +368,10 @@ __host__ __device__ constexpr uint32_t seg_pitch(int S) { return seg_span(S) + 4
 __host__ __device__ constexpr int adi_lines(int S) { return S == 16 ? AdiShape<16>::lines : AdiShape<32>::lines; }
 __host__ __device__ constexpr int adi_threads(int S) { return adi_lines(S) * kSegs; }
 // LDS (doubles): the lines, the pivots' reciprocals of the x and the y lines, then the intermediate
-// values on the item's two vertical data lines and the coefficient modulation of its rows (x phase).
+// values on the item's two vertical data lines (scaled by r/2, then plain) and the coefficient
+// modulation of its rows (x phase).
 __host__ __device__ constexpr size_t adi_lds_doubles(int S) {
-  return (size_t)adi_lines(S) * seg_pitch(S) + 2 * (size_t)seg_span(S) + 3 * (size_t)adi_lines(S);
+  return (size_t)adi_lines(S) * seg_pitch(S) + 2 * (size_t)seg_span(S) + 5 * (size_t)adi_lines(S);
 }
 
 template <int S>
@@ -476,6 +476,11 @@ __device__ inline void solve_lines(double* __restrict__ D, uint32_t pitch, const
   }
 }
 
+// The x phase solves the x lines for the intermediate level u* and then forms, while u* is in LDS, the
+// right-hand side of the y phase at every interior node except its boundary terms:
+// u* + (r/2) d_xx u* + (dt/2) f, with f the reaction it used itself.  The y phase then reads one value
+// per node instead of u*, its x neighbours, u^n and u^{n-1}.  (dt/2) f waits in the output array
+// between the two passes (the same thread overwrites it; the lines stay in L2), not in registers.
 template <int S>
 __device__ void x_sweep(const AdiArgs& a, uint32_t item, uint32_t n, const double* __restrict__ cur,
                         const double* __restrict__ prev, double* __restrict__ smem) {
@@ -484,8 +489,9 @@ __device__ void x_sweep(const AdiArgs& a, uint32_t item, uint32_t n, const doubl
   constexpr uint32_t pitch = seg_pitch(S);
   // pass 1 and 3: threads along the position pairs; with more threads than pairs, row sets of R rows
   constexpr uint32_t NP = M / 2, sets = T >= (int)NP ? T / NP : 1, R = L / sets, pstep = sets > 1 ? NP : T;
+  static_assert(pstep >= NP, "one position pair per thread");
   const uint32_t t = thread_index();
-  const uint32_t h = sets > 1 ? t / NP : 0, pp0 = sets > 1 ? t % NP : t, r0 = h * R;
+  const uint32_t h = sets > 1 ? t / NP : 0, pp = sets > 1 ? t % NP : t, r0 = h * R;
   const uint32_t sub = item / a.x_blk, blk = item % a.x_blk;
   const uint32_t sx = sub % a.px, sy = sub / a.px;
   const uint32_t ybase = sy * a.cy + 1 + blk * L;
@@ -493,13 +499,12 @@ __device__ void x_sweep(const AdiArgs& a, uint32_t item, uint32_t n, const doubl
   const uint32_t c0 = sx * a.cx, m = a.cx - 1, W = a.W;
   double* __restrict__ D = smem;                                  // [line][pitch]
   const double* __restrict__ INV = D + L * pitch;                 // x lines
-  double* __restrict__ SB = D + L * pitch + 2 * seg_span(S);      // intermediate values on the two vertical lines
-  double* __restrict__ EY = SB + 2 * L;                           // coefficient modulation of the item's rows
-  double* __restrict__ star = a.star;
+  double* __restrict__ SB = D + L * pitch + 2 * seg_span(S);      // u* on the two vertical lines: scaled, plain
+  double* __restrict__ EY = SB + 4 * L;                           // coefficient modulation of the item's rows
   const double tf = time_factor(a, n);
   const double* __restrict__ cur_b = cur + (size_t)(ybase - 1) * W + c0 + 1;  // row above the item
   const double* __restrict__ prev_b = prev + (size_t)ybase * W + c0 + 1;
-  double* __restrict__ star_b = star + (size_t)ybase * W + c0 + 1;
+  double* __restrict__ yr_b = a.yrhs + (size_t)ybase * W + c0 + 1;
   // Halo rows on the subdomain's horizontal data lines are read from the boundary data (level n), so a
   // subdomain never reads field values that another subdomain's solve writes.
   const int hl_top = blk == 0 ? a.hline[sy] : -1;
@@ -513,29 +518,24 @@ __device__ void x_sweep(const AdiArgs& a, uint32_t item, uint32_t n, const doubl
   if (t < (uint32_t)L) {
     EY[t] = a.ey[min(ybase + t, ybase + nrows - 1)];
     if (t < nrows) {
-      // the intermediate level on the subdomain's vertical lines, kept for the y phase in the
-      // subdomain's own edge buffer (neighbouring subdomains never share a location)
       const uint32_t y = ybase + t;
       const double usl = ustar_line(a, sx, y, n), usr = ustar_line(a, sx + 1, y, n);
       SB[t] = a.rx2 * usl;
       SB[L + t] = a.rx2 * usr;
-      double* e = a.edge + (size_t)sub * 2 * a.cy + (y - sy * a.cy);
-      e[0] = usl;
-      e[a.cy] = usr;
+      SB[2 * L + t] = usl;
+      SB[3 * L + t] = usr;
     }
   }
   __syncthreads();
-  for (uint32_t pp = pp0; pp < NP; pp += pstep) {
-    const uint32_t pa = 2 * pp, pb = pa + 1;  // the pair's positions (pb may be the line column)
-    const uint32_t oa = lds_pos<S>(pa), ob = lds_pos<S>(pb);
-    if (pa >= m) {
+  const uint32_t pa = 2 * pp, pb = pa + 1;  // the pair's positions (pb may be the line column)
+  const uint32_t oa = lds_pos<S>(pa), ob = lds_pos<S>(pb);
+  if (pa >= m) {
 #pragma unroll
-      for (uint32_t k = 0; k < R; ++k) {
-        D[(r0 + k) * pitch + oa] = 0.0;
-        D[(r0 + k) * pitch + ob] = 0.0;
-      }
-      continue;
+    for (uint32_t k = 0; k < R; ++k) {
+      D[(r0 + k) * pitch + oa] = 0.0;
+      D[(r0 + k) * pitch + ob] = 0.0;
     }
+  } else {
     const uint32_t vo = 8 * pa;
     const dpair exv = ldg2(a.ex + c0 + 1, vo);
     dpair up = ldg2(cur_row(min(r0, nrows + 1)), vo), mid = ldg2(cur_row(min(r0 + 1, nrows + 1)), vo);
@@ -552,10 +552,16 @@ __device__ void x_sweep(const AdiArgs& a, uint32_t item, uint32_t n, const doubl
         const uint32_t row = r0 + k0 + k;
         const dpair u = mid, dn = cv[k];
         const double ey = EY[row];
-        const double Fa = reaction_at(a, 1.5 * u.x - 0.5 * pv[k].x, exv.x * ey, tf);
-        const double Fb = reaction_at(a, 1.5 * u.y - 0.5 * pv[k].y, exv.y * ey, tf);
-        double da = u.x + a.ry2 * ((up.x - 2.0 * u.x) + dn.x) + a.dt2 * Fa;
-        double db = u.y + a.ry2 * ((up.y - 2.0 * u.y) + dn.y) + a.dt2 * Fb;
+        const double fa = a.dt2 * reaction_at(a, 1.5 * u.x - 0.5 * pv[k].x, exv.x * ey, tf);
+        const double fb = a.dt2 * reaction_at(a, 1.5 * u.y - 0.5 * pv[k].y, exv.y * ey, tf);
+        double da = u.x + a.ry2 * ((up.x - 2.0 * u.x) + dn.x) + fa;
+        double db = u.y + a.ry2 * ((up.y - 2.0 * u.y) + dn.y) + fb;
+        if (row < nrows) {
+          if (pb < m)
+            stg2(yr_b + (size_t)row * W, 8 * pa, dpair{fa, fb});
+          else
+            stg(yr_b + (size_t)row * W, 8 * pa, fa);
+        }
         if (pa == 0) da += SB[row];
         if (pa == m - 1) da += SB[L + row];
         if (pb == m - 1) db += SB[L + row];
@@ -570,25 +576,41 @@ __device__ void x_sweep(const AdiArgs& a, uint32_t item, uint32_t n, const doubl
   __syncthreads();
   solve_lines<S>(D, pitch, INV, a.rx2);
   __syncthreads();
-  for (uint32_t pp = pp0; 2 * pp < m; pp += pstep) {
-    const uint32_t pa = 2 * pp, pb = pa + 1;
-    const uint32_t oa = lds_pos<S>(pa), ob = lds_pos<S>(pb);
+  if (pa < m) {
+    const uint32_t ol = pa > 0 ? lds_pos<S>(pa - 1) : oa, orr = pb + 1 < m ? lds_pos<S>(pb + 1) : oa;
+    dpair fv[R];
+#pragma unroll
+    for (uint32_t k = 0; k < R; ++k)
+      fv[k] = r0 + k < nrows ? (pb < m ? ldg2(yr_b + (size_t)(r0 + k) * W, 8 * pa)
+                                       : dpair{ldg(yr_b + (size_t)(r0 + k) * W, 8 * pa), 0.0})
+                             : dpair{0.0, 0.0};
 #pragma unroll
     for (uint32_t k = 0; k < R; ++k) {
-      if (r0 + k >= nrows) continue;
-      double* row = star_b + (size_t)(r0 + k) * W;
-      if (pb < m)
-        stg2(row, 8 * pa, dpair{D[(r0 + k) * pitch + oa], D[(r0 + k) * pitch + ob]});
-      else
-        stg(row, 8 * pa, D[(r0 + k) * pitch + oa]);
+      const uint32_t row = r0 + k;
+      if (row >= nrows) continue;
+      const double* Dr = D + row * pitch;
+      const double usr = SB[3 * L + row];
+      const double sa = Dr[oa];
+      const double sl = pa > 0 ? Dr[ol] : SB[2 * L + row];
+      const double sb = pb < m ? Dr[ob] : usr;
+      const double ra = sa + a.rx2 * ((sl - 2.0 * sa) + sb) + fv[k].x;
+      double* out = yr_b + (size_t)row * W;
+      if (pb < m) {
+        const double sr = pb + 1 < m ? Dr[orr] : usr;
+        stg2(out, 8 * pa, dpair{ra, sb + a.rx2 * ((sa - 2.0 * sb) + sr) + fv[k].y});
+      } else {
+        stg(out, 8 * pa, ra);
+      }
     }
   }
   __syncthreads();
 }
 
+// The y phase adds the boundary terms of the horizontal data lines (level n+1) to the right-hand sides
+// the x phase left, solves the y lines and writes u^{n+1}.
 template <int S>
-__device__ void y_sweep(const AdiArgs& a, uint32_t item, uint32_t n, const double* __restrict__ cur,
-                        double* __restrict__ next, double* __restrict__ smem) {
+__device__ void y_sweep(const AdiArgs& a, uint32_t item, uint32_t n, double* __restrict__ next,
+                        double* __restrict__ smem) {
   constexpr int L = AdiShape<S>::lines, T = AdiShape<S>::threads;
   constexpr uint32_t pitch = seg_pitch(S);
   constexpr uint32_t P2 = L / 2, G = T / P2, npt = (uint32_t)kSegs * S / G;  // pairs per row, row groups, positions per thread
@@ -603,49 +625,35 @@ __device__ void y_sweep(const AdiArgs& a, uint32_t item, uint32_t n, const doubl
   const uint32_t r0 = sy * a.cy, m = a.cy - 1, W = a.W;
   double* __restrict__ D = smem;  // [line][pitch]
   const double* __restrict__ INV = D + L * pitch + seg_span(S);  // y lines
-  const double* __restrict__ star_b = a.star + (size_t)r0 * W;
-  const double* __restrict__ cur_b = cur + (size_t)r0 * W;
+  const double* __restrict__ yr_b = a.yrhs + (size_t)r0 * W;
   double* __restrict__ next_b = next + (size_t)r0 * W;
-  const double* __restrict__ ey_b = a.ey + r0 + 1;
   const double gb00 = a.ry2 * hline_value(a, sy, x, n + 1), gb01 = a.ry2 * hline_value(a, sy, x + 1, n + 1);
   const double gb10 = a.ry2 * hline_value(a, sy + 1, x, n + 1), gb11 = a.ry2 * hline_value(a, sy + 1, x + 1, n + 1);
-  const double tf = time_factor(a, n);
-  const double ex0 = a.ex[x], ex1 = a.ex[x + 1];
   const uint32_t l0 = 2 * c, l1 = 2 * c + 1;
-  // intermediate values on the subdomain's vertical data lines come from its edge buffer
-  const bool lft = x - 1 == sx * a.cx, rgt1 = x + 1 == (sx + 1) * a.cx, rgt2 = x + 2 == (sx + 1) * a.cx;
-  const double* __restrict__ el = a.edge + (size_t)sub * 2 * a.cy + 1;  // by position p
-  const double* __restrict__ er = el + a.cy;
 #pragma unroll
   for (uint32_t kb = 0; kb < npt; kb += kYBatch) {
-    dpair sc[kYBatch], cu[kYBatch], pr[kYBatch];
-    double sl[kYBatch], sr[kYBatch], ey[kYBatch];
+    dpair rv[kYBatch];
 #pragma unroll
     for (int k = 0; k < kYBatch; ++k) {
       const uint32_t p = min(q + G * (kb + k), m - 1);
-      const uint32_t off = 8 * ((1 + p) * W + x);
-      sl[k] = lft ? el[p] : ldg(star_b, off - 8);
-      sc[k] = ldg2(star_b, off);
-      if (rgt1) sc[k].y = er[p];
-      sr[k] = rgt2 ? er[p] : ldg(star_b, off + 16);
-      cu[k] = ldg2(cur_b, off);
-      pr[k] = ldg2(next_b, off);  // next still holds u^{n-1}
-      ey[k] = ldg(ey_b, 8 * p);
+      rv[k] = ldg2(yr_b, 8 * ((1 + p) * W + x));
     }
 #pragma unroll
     for (int k = 0; k < kYBatch; ++k) {
       const uint32_t p = q + G * (kb + k);
-      const double F0 = reaction_at(a, 1.5 * cu[k].x - 0.5 * pr[k].x, ex0 * ey[k], tf);
-      const double F1 = reaction_at(a, 1.5 * cu[k].y - 0.5 * pr[k].y, ex1 * ey[k], tf);
-      double d0 = sc[k].x + a.rx2 * ((sl[k] - 2.0 * sc[k].x) + sc[k].y) + a.dt2 * F0;
-      double d1 = sc[k].y + a.rx2 * ((sc[k].x - 2.0 * sc[k].y) + sr[k]) + a.dt2 * F1;
-      if (p == 0) { d0 += gb00; d1 += gb01; }
-      if (p == m - 1) { d0 += gb10; d1 += gb11; }
+      double d0 = rv[k].x, d1 = rv[k].y;
+      if (p == 0) {
+        d0 += gb00;
+        d1 += gb01;
+      }
+      if (p == m - 1) {
+        d0 += gb10;
+        d1 += gb11;
+      }
       const uint32_t o = lds_pos<S>(p);
       D[l0 * pitch + o] = p < m ? d0 : 0.0;
       D[l1 * pitch + o] = p < m ? d1 : 0.0;
     }
-    batch_fence();
   }
   __syncthreads();
   solve_lines<S>(D, pitch, INV, a.ry2);
@@ -731,7 +739,7 @@ __global__ __launch_bounds__(AdiShape<S>::threads) void adi_kernel(AdiArgs a) {
     double* prev = (n & 1) ? a.f0 : a.f1;  // holds u^{n-1}; receives u^{n+1}
     for (uint32_t it = xr.begin; it < xr.end; it += xr.stride) x_sweep<S>(a, it, n, cur, prev, smem);
     if (!group_barrier(bar, a.sync + 2, members, gen, a.spin_limit, &barrier_ok)) return;
-    for (uint32_t it = yr.begin; it < yr.end; it += yr.stride) y_sweep<S>(a, it, n, cur, prev, smem);
+    for (uint32_t it = yr.begin; it < yr.end; it += yr.stride) y_sweep<S>(a, it, n, prev, smem);
     for (uint32_t it = blockIdx.x; it < l_items; it += gridDim.x) write_lines(a, it, n, prev);
     if (!group_barrier(bar, a.sync + 2, members, gen, a.spin_limit, &barrier_ok)) return;
   }
@@ -758,7 +766,6 @@ struct brt_pdd {
   double* d_fac = nullptr;
   double* d_spl = nullptr;  // vals, mom, cp, rowsv, tmom, tcp
   uint32_t* d_sync = nullptr;
-  double* d_edge = nullptr;  // solver: per-subdomain intermediate values on its vertical lines
   double* d_node_u = nullptr;
   double* d_exy = nullptr;  // variable coefficients: e^{-bx x_i^2} (NX+1), then e^{-by y_j^2} (NY+1)
   size_t spl_rows = 0, spl_fine = 0;
@@ -784,7 +791,6 @@ void pdd_free(brt_pdd* p) {
   (void)hipFree(p->d_fac);
   (void)hipFree(p->d_spl);
   (void)hipFree(p->d_sync);
-  (void)hipFree(p->d_edge);
   (void)hipFree(p->d_node_u);
   (void)hipFree(p->d_exy);
   for (hipEvent_t e : p->ev)
@@ -922,7 +928,6 @@ int brt_pdd_create(brt_ctx* ctx, const brt_problem* prob, const brt_pdd_grid* gr
   dev_alloc((void**)&p->d_fac, 8 * 2 * (size_t)kSegs * p->seg);
   dev_alloc((void**)&p->d_spl, 8 * (3 * p->spl_rows + 3 * p->spl_fine));
   dev_alloc((void**)&p->d_sync, 4 * (size_t)kSyncWords);
-  dev_alloc((void**)&p->d_edge, 8 * 2 * (size_t)g.px * g.py * g.cy);
   dev_alloc((void**)&p->d_node_u, 8 * std::max<uint64_t>(p->n_nodes, 1));
   dev_alloc((void**)&p->d_exy, 8 * (size_t)(p->NX + 1 + p->NY + 1));
   for (hipEvent_t& e : p->ev)
@@ -1083,13 +1088,12 @@ int brt_pdd_solve(brt_pdd* p, uint32_t steps, double* field, void* stream) {
   AdiArgs a{};
   a.f0 = p->d_f[0] + kFieldLead;
   a.f1 = p->d_f[1] + kFieldLead;
-  a.star = p->d_f[2] + kFieldLead;
+  a.yrhs = p->d_f[2] + kFieldLead;
   a.bd = p->d_bd;
   a.lines = p->d_lines;
   a.inv_x = p->d_fac;
   a.inv_y = p->d_fac + (size_t)kSegs * p->seg;
   a.sync = p->d_sync;
-  a.edge = p->d_edge;
   int rate_khz = 0;
   PDD_TRY(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, p->device));
   a.spin_limit = (uint64_t)(kBarrierSeconds * 1e3 * (rate_khz > 0 ? rate_khz : 100000));
