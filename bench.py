@@ -132,10 +132,10 @@ def cpu_baseline(wl, gpu_meta, gpu_f, target_s):
              "worst_tree": dict(zip(["point", "tree", "ne", "nodes", "F_gpu", "F_oracle"], worst))})
 
 
-def pmc_traffic(kernel_src_sha, launches_trees):
-    """HBM bytes per walker launch from the committed rocprofv3 counter summary, if it was taken on
-    the current kernel source (else None)."""
-    path = os.path.join(ROOT, "profiles", "walk_fisher_pmc.json")
+def pmc_traffic(kernel_src_sha, launches_trees=None, name="walk_fisher_pmc.json"):
+    """HBM bytes per launch of a kernel from its committed rocprofv3 counter summary, if that was taken
+    on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", name)
     try:
         d = json.load(open(path))
     except (OSError, ValueError):
@@ -145,23 +145,34 @@ def pmc_traffic(kernel_src_sha, launches_trees):
     return d.get("hbm_bytes_per_launch")
 
 
-def walker_source_sha():
+def source_sha(files):
     h = hashlib.sha256()
-    for f in ("brt_kernels.hip", "brt_internal.h"):
+    for f in files:
         h.update(open(os.path.join(ROOT, "paper_2402_06491_amd", "csrc", f), "rb").read())
     return h.hexdigest()
 
 
+def walker_source_sha():
+    return source_sha(("brt_kernels.hip", "brt_internal.h"))
+
+
+def adi_source_sha():
+    return source_sha(("brt_pdd.hip", "brt_internal.h"))
+
+
 COPY_BYTES = 512 << 20  # the plain device copy of --pmc-calibration
+FISHER_WALKER = "walk_kernel<float, 1, 1, false, 0>"  # the headline's walker (1-D, logistic data, Strategy A)
 
 
 def pmc_summary(fetch_dir, write_dir, command):
-    """Write profiles/walk_fisher_pmc.json from two rocprofv3 --pmc runs of this script (FETCH_SIZE, then
-    WRITE_SIZE, with --pmc-calibration): the last walker dispatch (the timed plan's last direct launch)
-    and the calibration copy, whose known size gives each counter's scale."""
+    """Write profiles/walk_fisher_pmc.json (and profiles/adi_pdd_cubic_2d_pmc.json when the runs include
+    the domain-decomposition tail) from two rocprofv3 --pmc runs of this script (FETCH_SIZE, then
+    WRITE_SIZE, with --pmc-calibration): the last dispatch of each kernel (the timed plan's last direct
+    walker launch, the last 1000-step solve) and the calibration copy, whose known size gives each
+    counter's scale."""
     import csv
 
-    def read(d, counter):
+    def read(d, counter, kernel="walk_kernel"):
         rows = []
         for root, _, files in os.walk(d):
             for f in files:
@@ -173,12 +184,14 @@ def pmc_summary(fetch_dir, write_dir, command):
                 continue
             key = (int(r["Dispatch_Id"]), r["Kernel_Name"])
             per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
-        walk = [v for (i, k), v in sorted(per.items()) if "walk_kernel" in k]
-        copy = [v for (i, k), v in sorted(per.items()) if "copyBuffer" in k]
-        return walk[-1], copy[-1]
+        walk = [v for (i, k), v in sorted(per.items()) if kernel in k]
+        copy = [v for (i, k), v in sorted(per.items()) if "copyBuffer(" in k or k.endswith("copyBuffer")]
+        if not copy:
+            copy = [v for (i, k), v in sorted(per.items()) if "copyBuffer" in k and "Rect" not in k]
+        return (walk[-1] if walk else None), copy[-1]
 
-    fw, fc = read(fetch_dir, "FETCH_SIZE")
-    ww, wc = read(write_dir, "WRITE_SIZE")
+    fw, fc = read(fetch_dir, "FETCH_SIZE", FISHER_WALKER)
+    ww, wc = read(write_dir, "WRITE_SIZE", FISHER_WALKER)
     fs = COPY_BYTES / (fc * 1024.0)
     ws = COPY_BYTES / (wc * 1024.0)
     wl = workload("fisher")
@@ -192,6 +205,21 @@ def pmc_summary(fetch_dir, write_dir, command):
     path = os.path.join(ROOT, "profiles", "walk_fisher_pmc.json")
     json.dump(out, open(path, "w"), indent=1)
     print(json.dumps(out))
+    fa, _ = read(fetch_dir, "FETCH_SIZE", "adi_kernel")
+    wa, _ = read(write_dir, "WRITE_SIZE", "adi_kernel")
+    if fa is not None and wa is not None:
+        from paper_2402_06491_amd import inputs
+
+        g = inputs.pdd_cubic_2d()["grid"]
+        interior = g["px"] * g["py"] * (g["cx"] - 1) * (g["cy"] - 1)
+        adi = {"kernel": "adi_kernel", "workload": "pdd_cubic_2d", "kernel_source_sha256": adi_source_sha(),
+               "steps_per_launch": g["n_steps"], "fetch_kib_per_dispatch": fa, "write_kib_per_dispatch": wa,
+               "copy_fetch_kib": fc, "copy_write_kib": wc, "copy_bytes": COPY_BYTES,
+               "fetch_scale": fs, "write_scale": ws,
+               "hbm_bytes_per_launch": fa * 1024.0 * fs + wa * 1024.0 * ws,
+               "algorithmic_bytes_per_launch": 40.0 * interior * g["n_steps"], "command": command}
+        json.dump(adi, open(os.path.join(ROOT, "profiles", "adi_pdd_cubic_2d_pmc.json"), "w"), indent=1)
+        print(json.dumps(adi))
 
 
 def serve_stream(ctx, reqs, mc, max_active, opts):
@@ -273,7 +301,8 @@ def pdd_bench(ctx, trees_per_node, cpu_steps):
            "mc_ms": mc_ms, "interp_ms": int_ms, "solve_ms": solve_ms,
            "adi_us_per_step": solve_ms * 1e3 / g["n_steps"],
            "adi_roofline": {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
-                            "frac": achieved / 8000.0, "algorithmic_bytes": alg_bytes, "traffic": None},
+                            "frac": achieved / 8000.0, "algorithmic_bytes": alg_bytes,
+                            "traffic": pmc_traffic(adi_source_sha(), name="adi_pdd_cubic_2d_pmc.json")},
            "field_finite": bool(np.isfinite(u).all()), "field_max": float(np.abs(u).max())}
     pd.close()
     if cpu_steps > 0:
@@ -349,7 +378,7 @@ def main():
     ap.add_argument("--pmc-calibration", action="store_true",
                     help="end with a plain 512 MiB device copy (scale of the rocprofv3 byte counters)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
-                    help="write profiles/walk_fisher_pmc.json from two rocprofv3 --pmc runs and exit")
+                    help="write the counter summaries under profiles/ from two rocprofv3 --pmc runs and exit")
     ap.add_argument("--pmc-command", default="", help="the command of the counter runs, recorded in the summary")
     args = ap.parse_args()
     if args.pmc_summary:
