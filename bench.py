@@ -274,8 +274,9 @@ def serve_bench(ctx, duration, rate, opts):
 def pdd_bench(ctx, trees_per_node, cpu_steps):
     """The domain-decomposition tail of the 2-D cubic workload: Monte Carlo at the 2640 line nodes,
     spline interpolation, 1000 ADI steps on 4 x 4 subdomains of 512^2 cells.  Reports stage times and
-    the ADI kernel's rate against HBM (40 algorithmic bytes per interior point and step: u^n and
-    u^{n-1} read, u^{n+1} written, the intermediate level written and read back)."""
+    the ADI kernel's rate against HBM (40 algorithmic bytes per interior node and step: the x phase
+    reads u^n and u^{n-1} and writes the y phase's right-hand side, the y phase reads it and writes
+    u^{n+1})."""
     import torch
 
     import paper_2402_06491_amd as brt
