@@ -8,10 +8,12 @@
 //   spline_t_kernel     one thread per (line, fine node): spline in time, written at every time level
 //   init_field_kernel   u0 at every grid node, line data at level 0
 //   adi_kernel          persistent cooperative launch through all time steps: per step an x phase and
-//                       a y phase separated by grid barriers; a work item is 16 lines of one subdomain
-//                       held in LDS by a block of 512 threads, each line's tridiagonal system solved
-//                       by 32 threads (segments of consecutive unknowns joined by scans of their
-//                       carries), items dealt round-robin.
+//                       a y phase, each followed by a barrier (among the blocks of a die when the dies
+//                       own whole subdomains, else over the grid); a work item is 32 lines of one
+//                       subdomain (16 for lines of more than 512 unknowns) held in LDS by one block,
+//                       each line's tridiagonal system solved by 32 threads (segments of consecutive
+//                       unknowns joined by scans of their carries); the x phase also forms the y
+//                       phase's right-hand sides.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
