@@ -128,6 +128,19 @@ def test_tail_odd_subdomain_width(ctx):
     _tail_parity(ctx, "tail_odd_width", _cubic(1), grid, vals)
 
 
+@pytest.mark.parametrize("px,py", [(4, 2), (4, 4)])
+def test_tail_die_barrier_groups(ctx, px, py):
+    """8 and 16 small subdomains: the solver launches one block per subdomain and, with the subdomains
+    split evenly over the dies, synchronises each die's blocks among themselves (one and two blocks
+    per group); the subdomains then never read each other's field values."""
+    grid = _grid(x_lo=-6.0, x_hi=6.0, px=px, py=py, cx=16, cy=12, n_steps=30, ns_x=13, ns_y=9, nt=3, T=0.3)
+    og = opdd.Grid(**grid)
+    rng = np.random.default_rng(px * 10 + py)
+    xy, t = opdd.node_points(og)
+    vals = 0.5 * np.exp(-(xy[:, 0] ** 2 + xy[:, 1] ** 2) / 12.0) * (1 + t) + 0.02 * rng.normal(size=len(t))
+    _tail_parity(ctx, f"tail_groups_{px}x{py}", _cubic(3), grid, vals)
+
+
 def test_tail_long_lines_32_unknown_segments(ctx):
     """2 x 1 subdomains of 600 x 30 cells: lines of 599 unknowns take the solver's 32-unknown segments
     (the ragged last segment holds 23), and the short y lines leave most segments empty."""
