@@ -88,6 +88,11 @@ typedef struct brt_problem {
   uint32_t coef_mod_pow;
   double coef_mod_beta[2];
   double coef_mod_t0;
+  /* Constant drift b of the operator L = a Lap + b . grad (Sec. 2.1's SDE with a constant drift term):
+   * an edge of duration s moves its path by b s + sqrt(2a) W_s, exactly, with no time stepping.  Finite;
+   * drift[1] must be 0 in 1-D.  {0, 0} is the paper's L = a Lap.  The domain-decomposition tail
+   * (brt_pdd_*) takes drift-free problems only. */
+  double drift[2];
 } brt_problem;
 
 #define BRT_COEF_MOD_NONE 0u

@@ -78,6 +78,7 @@ class _Problem(ctypes.Structure):
         ("cmod_bx", ctypes.c_double),
         ("cmod_by", ctypes.c_double),
         ("cmod_t0", ctypes.c_double),
+        ("drift", ctypes.c_double * 2),
     ]
 
 
@@ -119,6 +120,7 @@ class Normalized:
     strategy: int = 0     # 0: Strategy A (Sec. 2.1), 1: Strategy B (Sec. 2.2)
     q: float = 1.0        # Strategy B: probability that a node is a leaf
     cmod: tuple = None    # variable coefficients (bx, by, t0, pow): c_j exp(-bx x^2 - by y^2) (t + t0)^-pow
+    drift: tuple = (0.0, 0.0)  # constant drift b of L = a Lap + b.grad (the paths are x + b s + sigma W_s)
 
 
 def normalize(problem: dict, mc: dict) -> Normalized:
@@ -159,7 +161,14 @@ def normalize(problem: dict, mc: dict) -> Normalized:
         raise ValueError("logistic u0 takes (A, s, x0, pow, n0, n1)")
     return Normalized(dim=int(problem["dim"]), sigma=math.sqrt(2.0 * float(problem["diffusion"])),
                       lam=lam_eff, mu=mu, J=J, omega=omega, u0_kind=kind,
-                      u0_params=params, u0_nterms=nterms, strategy=strategy, q=q, cmod=cmod_of(problem))
+                      u0_params=params, u0_nterms=nterms, strategy=strategy, q=q, cmod=cmod_of(problem),
+                      drift=drift_of(problem))
+
+
+def drift_of(problem: dict):
+    """The constant drift b (x and y components; y is 0 in 1-D)."""
+    b = [float(v) for v in problem.get("drift", (0.0, 0.0))] + [0.0, 0.0]
+    return (b[0], b[1] if int(problem["dim"]) == 2 else 0.0)
 
 
 def cmod_of(problem: dict):
@@ -198,6 +207,7 @@ def _make_struct(nz: Normalized, mc: dict) -> _Problem:
     pb.prune = int(mc.get("prune", 1))
     pb.node_cap = int(mc.get("node_cap", 1 << 16))
     pb.strategy = nz.strategy
+    pb.drift[0], pb.drift[1] = nz.drift
     if nz.cmod:
         pb.cmod = 1
         pb.cmod_bx, pb.cmod_by, pb.cmod_t0, pb.cmod_pow = nz.cmod

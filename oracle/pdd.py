@@ -285,6 +285,8 @@ def adi_solve(grid: Grid, problem, bd, U0=None, n_steps=None):
     (default u0 at the grid nodes).  Returns the field at step n_steps (default grid.n_steps).
     """
     n_steps = grid.n_steps if n_steps is None else n_steps
+    if any(float(b) != 0.0 for b in problem.get("drift", (0.0, 0.0))):
+        raise ValueError("the subdomain solver is for L = a Lap (no drift)")
     a = float(problem["diffusion"])
     coef = [float(c) for c in problem["coef"]]
     dt = grid.dt

@@ -102,7 +102,7 @@ def walk_tree(nz, mc, x0, t, point_id, tree):
         if Pn > theta:
             S = -math.log(U) / nz.lam
             tau2 = max(tau - S, 0.0)
-            xs = [x[d] + nz.sigma * math.sqrt(S) * z[d] for d in range(dim)]
+            xs = [x[d] + nz.drift[d] * S + nz.sigma * math.sqrt(S) * z[d] for d in range(dim)]
             ne += 1
             if prune and ne > max_order:
                 return 0.0, ne, node, 1
@@ -116,7 +116,7 @@ def walk_tree(nz, mc, x0, t, point_id, tree):
                     stack.append([(xs, Pn, tau2), alpha - 1])
                 state = (xs, Pn, tau2)
         else:
-            xl = [x[d] + nz.sigma * math.sqrt(tau) * z[d] for d in range(dim)]
+            xl = [x[d] + nz.drift[d] * tau + nz.sigma * math.sqrt(tau) * z[d] for d in range(dim)]
             prod *= _g(nz.u0_kind, nz.u0_params, nz.u0_nterms, dim, xl)
             branch_done = True
         if branch_done:
@@ -157,7 +157,7 @@ def _walk_tree_b(nz, mc, x0, t, point_id, tree):
             span = 2.0 ** 32 - Q
             s = tau * ((w[0] - Q + 0.5) / span)
             tau2 = tau * ((2 ** 32 - 1 - w[0] + 0.5) / span)  # tau (1 - V) without cancellation
-            xs = [x[d] + nz.sigma * math.sqrt(s) * z[d] for d in range(dim)]
+            xs = [x[d] + nz.drift[d] * s + nz.sigma * math.sqrt(s) * z[d] for d in range(dim)]
             ne += 1
             if prune and ne > max_order:
                 return 0.0, ne, node, 1
@@ -170,7 +170,7 @@ def _walk_tree_b(nz, mc, x0, t, point_id, tree):
                 state = (xs, tau2)
                 continue
         else:
-            xl = [x[d] + nz.sigma * math.sqrt(tau) * z[d] for d in range(dim)]
+            xl = [x[d] + nz.drift[d] * tau + nz.sigma * math.sqrt(tau) * z[d] for d in range(dim)]
             prod *= _g(nz.u0_kind, nz.u0_params, nz.u0_nterms, dim, xl) / nz.q
         if not stack:
             return prod, ne, node, 0

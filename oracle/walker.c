@@ -79,6 +79,7 @@ typedef struct {
   int32_t cmod;       /* 1: c_j(x, t) = c_j exp(-bx x^2 - by y^2) (t + t0)^(-pow) */
   int32_t cmod_pow;
   double cmod_bx, cmod_by, cmod_t0;
+  double drift[2];    /* constant drift b of L = a Lap + b.grad: an edge of duration s moves by b s + sigma W_s */
 } or_problem;
 
 /* ---- Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) ------------------ */
@@ -191,7 +192,7 @@ static double or_visit(const or_problem* pb, or_tree* st, const double* x, doubl
     double tau2 = tau - S;
     if (tau2 < 0.0) tau2 = 0.0;
     double xs[2];
-    for (int d = 0; d < pb->dim; d++) xs[d] = x[d] + pb->sigma * sqrt(S) * z[d];
+    for (int d = 0; d < pb->dim; d++) xs[d] = x[d] + pb->drift[d] * S + pb->sigma * sqrt(S) * z[d];
     st->ne += 1;
     if (pb->prune && st->ne > (uint32_t)pb->max_order) {
       st->flags |= OR_FLAG_OVERFLOW;
@@ -209,7 +210,7 @@ static double or_visit(const or_problem* pb, or_tree* st, const double* x, doubl
   }
   /* leaf: the path runs to the final time; evaluate g where it ends */
   double xl[2];
-  for (int d = 0; d < pb->dim; d++) xl[d] = x[d] + pb->sigma * sqrt(tau) * z[d];
+  for (int d = 0; d < pb->dim; d++) xl[d] = x[d] + pb->drift[d] * tau + pb->sigma * sqrt(tau) * z[d];
   return or_g(pb, xl);
 }
 
@@ -245,7 +246,7 @@ static double or_visit_b(const or_problem* pb, or_tree* st, const double* x, dou
     double s = tau * (((double)((uint64_t)w[0] - pb->Q) + 0.5) / span);
     double tau2 = tau * (((double)(0xFFFFFFFFu - w[0]) + 0.5) / span);
     double xs[2];
-    for (int d = 0; d < pb->dim; d++) xs[d] = x[d] + pb->sigma * sqrt(s) * z[d];
+    for (int d = 0; d < pb->dim; d++) xs[d] = x[d] + pb->drift[d] * s + pb->sigma * sqrt(s) * z[d];
     st->ne += 1;
     if (pb->prune && st->ne > (uint32_t)pb->max_order) {
       st->flags |= OR_FLAG_OVERFLOW;
@@ -262,7 +263,7 @@ static double or_visit_b(const or_problem* pb, or_tree* st, const double* x, dou
     return val;
   }
   double xl[2];
-  for (int d = 0; d < pb->dim; d++) xl[d] = x[d] + pb->sigma * sqrt(tau) * z[d];
+  for (int d = 0; d < pb->dim; d++) xl[d] = x[d] + pb->drift[d] * tau + pb->sigma * sqrt(tau) * z[d];
   return or_g(pb, xl) / pb->q;
 }
 

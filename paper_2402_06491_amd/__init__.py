@@ -33,7 +33,8 @@ class Problem(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("dim", ctypes.c_uint32), ("diffusion", ctypes.c_double),
                 ("coef", ctypes.c_double * 8), ("u0_kind", ctypes.c_uint32), ("u0_nterms", ctypes.c_uint32),
                 ("u0_params", ctypes.c_double * 40), ("coef_mod", ctypes.c_uint32), ("coef_mod_pow", ctypes.c_uint32),
-                ("coef_mod_beta", ctypes.c_double * 2), ("coef_mod_t0", ctypes.c_double)]
+                ("coef_mod_beta", ctypes.c_double * 2), ("coef_mod_t0", ctypes.c_double),
+                ("drift", ctypes.c_double * 2)]
 
 
 class MC(ctypes.Structure):
@@ -185,6 +186,9 @@ def make_problem(d: dict) -> Problem:
         p.coef_mod_beta[1] = float(beta[1])
         p.coef_mod_pow = int(cm.get("pow", 0))
         p.coef_mod_t0 = float(cm.get("t0", 0.0))
+    b = list(d.get("drift", (0.0, 0.0))) + [0.0, 0.0]
+    p.drift[0] = float(b[0])
+    p.drift[1] = float(b[1])
     return p
 
 

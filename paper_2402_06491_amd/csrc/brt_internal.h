@@ -35,8 +35,9 @@ struct PdeT {
   uint32_t q_lo;     // Strategy B: Q - 1 with Q = floor(q 2^32); a node is a leaf iff w0 <= q_lo
   uint32_t cmod;     // 0: constant coefficients; 1: c_j exp(-bx x^2 - by y^2) (tau + t0)^(-cm_pow)
   uint32_t cm_pow;   // 0 or 1
-  uint32_t pad2;
+  uint32_t drift_on; // 1: constant drift b, an edge of duration s moves by b s + sigma W_s
   Real cm_bx, cm_by, cm_t0;
+  Real drift[2];
   Real omega[8];     // Strategy A: K c_j / lambda; Strategy B: K c_j / (1 - q)
   Real u0[kMaxU0Params];
 };
@@ -98,7 +99,7 @@ struct WalkArgs {
   uint32_t prune;
   uint32_t node_cap;
   uint32_t strategy;         // 0: Strategy A, 1: Strategy B
-  uint32_t cmod;             // 1: some problem of the launch has variable coefficients
+  uint32_t cmod;             // 1: some problem of the launch has variable coefficients or a drift
   uint32_t stack_depth;      // LDS levels per lane
   uint32_t spill_depth;      // global levels per lane
   uint32_t n_threads;        // grid size in threads (spill stride)
@@ -144,6 +145,10 @@ struct Norm {
   double omega[8] = {0};
 };
 Norm normalize(const brt_problem& p, const brt_mc& mc);
+// A problem the walker's general-coefficients variant takes: variable coefficients or a drift.
+inline bool general_coefficients(const brt_problem& p) {
+  return p.coef_mod != BRT_COEF_MOD_NONE || p.drift[0] != 0.0 || p.drift[1] != 0.0;
+}
 size_t pde_bytes(int precision);
 void pde_to_device(const brt_problem& p, const Norm& n, int precision, void* dst);
 double est_nodes(const Norm& n, const brt_mc& mc, double t);

@@ -91,8 +91,8 @@ struct Math<double> {
 template <typename Real>
 struct HotC {
   Real sigma, inv_lambda, mu, inv_q, s_scale;
-  uint32_t K, jpack, q_lo, cmod, cm_pow;
-  Real cm_bx, cm_by, cm_t0;
+  uint32_t K, jpack, q_lo, cmod, cm_pow, drift_on;
+  Real cm_bx, cm_by, cm_t0, drift0, drift1;
   Real g[6];  // first initial-data parameters (the logistic family's A, s, x0, p, n0, n1)
 };
 
@@ -112,6 +112,9 @@ __device__ __forceinline__ HotC<Real> hot_of(const PdeT<Real>& pd) {
   h.cm_bx = pd.cm_bx;
   h.cm_by = pd.cm_by;
   h.cm_t0 = pd.cm_t0;
+  h.drift_on = pd.drift_on;
+  h.drift0 = pd.drift[0];
+  h.drift1 = pd.drift[1];
   for (int i = 0; i < 6; ++i) h.g[i] = pd.u0[i];
   return h;
 }
@@ -260,8 +263,8 @@ struct Stack {
 // ------------------------------------------------------------------------------------------------
 // The walker.  MULTI: the plan has several problems (per-lane problem index); otherwise the
 // problem constants are loop invariants.  MODE bit 0 (STRAT): Strategy A (0, Sec. 2.1) or B (1, Sec. 2.2);
-// bit 1 (CMOD): some problem of the launch has variable coefficients, so the variants for constant
-// coefficients carry no trace of them.
+// bit 1 (CMOD): some problem of the launch has variable coefficients or a drift, so the variants for
+// constant coefficients and L = a Lap carry no trace of them.
 // ------------------------------------------------------------------------------------------------
 template <typename Real, int DIM, int U0, bool MULTI, int MODE>
 __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
@@ -428,10 +431,18 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
     const Real u2 = (Real)w.d * (Real)0x1p-32;
     Real sn, cs;
     Math<Real>::sincos_rev(u2, &sn, &cs);
-    const Real sdr = hc.sigma * Math<Real>::sq((Real)-2 * Math<Real>::ln(u1) * (vertex ? S : tau));
+    const Real dt = vertex ? S : tau;
+    const Real sdr = hc.sigma * Math<Real>::sq((Real)-2 * Math<Real>::ln(u1) * dt);
     Real xn[2];
     xn[0] = x[0] + sdr * cs;
     xn[1] = x[1] + sdr * sn;
+    if constexpr (CMOD) {
+      // constant drift: the edge also moves by b dt (exact for L = a Lap + b . grad)
+      if (hc.drift_on) {
+        xn[0] += hc.drift0 * dt;
+        xn[1] += hc.drift1 * dt;
+      }
+    }
 
     // one exponential per node: the vertex weight e^{(alpha-1) mu tau'} or, for logistic initial
     // data, e^{s (n.x - x0)} at the leaf

@@ -67,6 +67,9 @@ PdeT<Real> to_device(const brt_problem& p, const Norm& n) {
   d.cm_bx = (Real)p.coef_mod_beta[0];
   d.cm_by = (Real)(p.dim == 2 ? p.coef_mod_beta[1] : 0.0);
   d.cm_t0 = (Real)p.coef_mod_t0;
+  d.drift_on = (p.drift[0] != 0.0 || p.drift[1] != 0.0) ? 1u : 0u;
+  d.drift[0] = (Real)p.drift[0];
+  d.drift[1] = (Real)(p.dim == 2 ? p.drift[1] : 0.0);
   for (int i = 0; i < kMaxU0Params; ++i) d.u0[i] = (Real)p.u0_params[i];
   if (p.u0_kind == BRT_U0_GAUSS_SUM)
     for (uint32_t k = 0; k < p.u0_nterms; ++k) {
@@ -276,6 +279,8 @@ int brt_problem_check(const brt_problem* p, const brt_mc* mc) {
     default:
       return fail(BRT_E_ARG, "unknown coef_mod %u", p->coef_mod);
   }
+  if (!is_fin(p->drift[0]) || !is_fin(p->drift[1])) return fail(BRT_E_ARG, "drift must be finite");
+  if (p->dim == 1 && p->drift[1] != 0.0) return fail(BRT_E_ARG, "drift[1] must be 0 in 1-D");
   if (mc->precision != 32 && mc->precision != 64) return fail(BRT_E_ARG, "precision must be 32 or 64");
   if (!(mc->lambda > 0.0) || !is_fin(mc->lambda)) return fail(BRT_E_ARG, "lambda must be > 0");
   if (mc->max_order > 126) return fail(BRT_E_ARG, "max_order must be <= 126");
@@ -352,7 +357,7 @@ extern "C" int brt_plan_create(brt_ctx* ctx, uint32_t n_problems, const brt_prob
   p->dim = (int)problems[0].dim;
   p->u0_kind = (int)problems[0].u0_kind;
   p->n_problems = n_problems;
-  for (uint32_t i = 0; i < n_problems; ++i) p->cmod |= problems[i].coef_mod != BRT_COEF_MOD_NONE ? 1u : 0u;
+  for (uint32_t i = 0; i < n_problems; ++i) p->cmod |= general_coefficients(problems[i]) ? 1u : 0u;
   p->n_points = pts->n;
   p->n_bins = mc->max_order + 2;
   p->mc = *mc;

@@ -160,7 +160,7 @@ int run_group(brt_server* s, const std::vector<Request*>& group) {
   for (uint32_t k = 0; k < group.size(); ++k) {
     Request* r = group[k];
     pde_to_device(r->prob, r->norm, (int)mc.precision, s->h_pdes + (size_t)k * pb);
-    cmod |= r->prob.coef_mod != BRT_COEF_MOD_NONE ? 1u : 0u;
+    cmod |= general_coefficients(r->prob) ? 1u : 0u;
     for (uint32_t i = 0; i < r->n; ++i)
       if (!r->done[i]) items.push_back(Item{r, i, k, est_nodes(r->norm, mc, r->t[i])});
   }

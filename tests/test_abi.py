@@ -102,3 +102,20 @@ def test_coef_mod_validation_host_only():
     p = brt.make_problem(inputs.problem(1, 1.0, [0.0, 0.0, -1.0], inputs.const(1.0)))
     p.coef_mod = 7
     assert L.brt_problem_check(ctypes.byref(p), ctypes.byref(mc)) == -1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libbrt.so not built")
+def test_drift_validation_host_only():
+    import paper_2402_06491_amd as brt
+    from paper_2402_06491_amd import inputs
+
+    L = brt.lib()
+    mc = brt.make_mc(inputs.mc_params())
+    ok1 = brt.make_problem(inputs.problem(1, 1.0, [0.0, 1.0, -1.0], inputs.const(1.0), drift=(0.5,)))
+    ok2 = brt.make_problem(inputs.problem(2, 1.0, [0.0, 1.0, -1.0], inputs.const(1.0), drift=(0.5, -2.0)))
+    assert L.brt_problem_check(ctypes.byref(ok1), ctypes.byref(mc)) == 0
+    assert L.brt_problem_check(ctypes.byref(ok2), ctypes.byref(mc)) == 0
+    bad_1d = brt.make_problem(inputs.problem(1, 1.0, [0.0, 1.0, -1.0], inputs.const(1.0), drift=(0.5, 1.0)))
+    assert L.brt_problem_check(ctypes.byref(bad_1d), ctypes.byref(mc)) == -1
+    bad_inf = brt.make_problem(inputs.problem(2, 1.0, [0.0, 1.0, -1.0], inputs.const(1.0), drift=(float("inf"), 0.0)))
+    assert L.brt_problem_check(ctypes.byref(bad_inf), ctypes.byref(mc)) == -1

@@ -259,6 +259,34 @@ def test_variable_coefficients_2d_strategy_b_and_mixed(ctx):
     _full_parity(ctx, "varcoef_mixed_problems", wl)
 
 
+@pytest.mark.parametrize("prec", [32, 64])
+def test_drift_fisher_moving_frame(ctx, prec):
+    """Fisher with a constant drift b = 0.8 (L = Lap + b d/dx): the paths gain b times each edge's
+    duration; Strategy A, pruned order 10."""
+    prob = inputs.problem(1, 1.0, [0.0, 1.0, -1.0], inputs.logistic(1.0, 1.0 / math.sqrt(6.0), 0.0, 2), drift=(0.8,))
+    x = np.linspace(-6.0, 6.0, 20).reshape(-1, 1)
+    wl = {"problems": [prob], "mc": inputs.mc_params(seed=31, max_order=10, pade=(5, 5), precision=prec), "x": x,
+          "t": np.full(20, 1.0), "n_trees": np.full(20, 1500)}
+    _full_parity(ctx, f"drift_fisher_fp{prec}", wl)
+
+
+def test_drift_2d_strategy_b_with_variable_coefficients_and_mixed(ctx):
+    """2-D cubic with drift (0.9, -0.4) under Strategy B, with and without variable coefficients, and
+    a drift-free problem in the same launch."""
+    x = inputs.interface_points(16)[::3]
+    n = len(x)
+    drifted = inputs.problem(2, 0.8, [0.1, -0.4, 0.6, -0.5], inputs.cubic_2d_u0(3), drift=(0.9, -0.4))
+    both = inputs.problem(2, 0.8, [0.1, -0.4, 0.6, -0.5], inputs.cubic_2d_u0(3), drift=(0.9, -0.4),
+                          coef_mod={"beta": (0.3, 0.7), "t0": 0.2, "pow": 1})
+    plain = inputs.problem(2, 0.8, [0.1, -0.4, 0.6, -0.5], inputs.cubic_2d_u0(3))
+    wl = {"problems": [drifted], "mc": inputs.mc_params(seed=32, precision=64, strategy=1, q=0.55), "x": x,
+          "t": np.full(n, 0.9), "n_trees": np.full(n, 600)}
+    _full_parity(ctx, "drift_2d_strategy_b", wl)
+    wl = {"problems": [plain, drifted, both], "mc": inputs.mc_params(seed=33, precision=32), "x": x,
+          "t": np.full(n, 0.7), "n_trees": np.full(n, 500), "problem_id": (np.arange(n) % 3).astype(np.uint32)}
+    _full_parity(ctx, "drift_mixed_problems", wl)
+
+
 def test_launch_settings_do_not_change_results(ctx):
     """Every tree is computed by one lane from its own counters and segments are fixed, so launch
     settings (block size, LDS stack levels, chunk size) change nothing in the outputs."""

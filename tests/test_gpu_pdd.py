@@ -152,6 +152,14 @@ def test_tail_long_lines_32_unknown_segments(ctx):
     _tail_parity(ctx, "tail_long_lines", _cubic(2), grid, vals)
 
 
+def test_tail_rejects_a_drift(ctx):
+    import paper_2402_06491_amd as brt
+
+    prob = inputs.problem(2, 1.0, [0.0, 1.0, 0.0, -1.0], inputs.cubic_2d_u0(0), drift=(0.5, 0.0))
+    with pytest.raises(brt.BrtError, match="drift"):
+        brt.Pdd(ctx, prob, _grid())
+
+
 def test_tail_full_size_first_steps(ctx):
     """The decomposition of the 2-D cubic workload at its full size (4 x 4 subdomains of 512^2 cells,
     264 nodes per line on 10 lines, 1000 steps of boundary data), solved through its first 100 steps."""
