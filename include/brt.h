@@ -82,8 +82,10 @@ typedef struct brt_problem {
   /* Variable coefficients (Sec. 2's c_j(x, t); Example 5): with coef_mod = BRT_COEF_MOD_GAUSS_TIME every
    * non-linear coefficient becomes c_j(x, t) = c_j exp(-beta_x x^2 - beta_y y^2) (t + t0)^(-coef_mod_pow),
    * evaluated where and when a tree splits (the split position and the PDE time left after the split).
-   * The linear coefficient c_1 stays constant.  beta >= 0; coef_mod_pow is 0 or 1, and t0 > 0 when it is
-   * 1.  BRT_COEF_MOD_NONE (0) keeps every c_j constant. */
+   * The linear coefficient c_1 stays constant; BRT_COEF_MOD_GAUSS_TIME_ALL modulates c_1 too, and then c_1(x, t) u
+   * is sampled as a branching with one child (it can no longer be absorbed into the prefactor e^{mu t}).
+   * beta >= 0; coef_mod_pow is 0 or 1, and t0 > 0 when it is 1.  BRT_COEF_MOD_NONE (0) keeps every c_j
+   * constant. */
   uint32_t coef_mod;
   uint32_t coef_mod_pow;
   double coef_mod_beta[2];
@@ -97,6 +99,7 @@ typedef struct brt_problem {
 
 #define BRT_COEF_MOD_NONE 0u
 #define BRT_COEF_MOD_GAUSS_TIME 1u
+#define BRT_COEF_MOD_GAUSS_TIME_ALL 2u
 
 /* Monte Carlo parameters shared by all points of one call. */
 typedef struct brt_mc {

@@ -136,22 +136,26 @@ def normalize(problem: dict, mc: dict) -> Normalized:
     coef = [float(c) for c in problem["coef"]] + [0.0] * (8 - len(problem["coef"]))
     lam = float(mc.get("lambda", 1.0))
     strategy = strategy_of(mc)
-    J = [j for j in range(8) if j != 1 and coef[j] != 0.0]
+    # with c_1 itself modulated (c_1(x, t) u) the linear term cannot be absorbed into the prefactor: it
+    # joins the terms chosen at a split as an arity-1 branching (one child, weight K c_1 m / lam)
+    lin = linear_modulated(problem)
+    J = [j for j in range(8) if (j != 1 or lin) and coef[j] != 0.0]
+    c1 = 0.0 if lin else coef[1]  # the part of c_1 absorbed into the prefactor e^{mu t}
     K = len(J)
     q = 1.0
     if K == 0:
-        lam_eff, mu, omega = 0.0, coef[1], []
+        lam_eff, mu, omega = 0.0, c1, []
     elif strategy == 1:
         # Strategy B: u = v e^{c_1 t}; a vertex carries t K c_j / (1 - q) e^{(j-1) c_1 tau'}
         # the coin is w0 < floor(q 2^32) for a uniform 32-bit w0: its leaf probability is exactly
         # floor(q 2^32) / 2^32, and that is the q of the weights g/q and c/(1-q)
         q = math.floor(float(mc.get("q", 0.5)) * 4294967296.0) / 4294967296.0
         lam_eff = 0.0
-        mu = coef[1]
+        mu = c1
         omega = [K * coef[j] / (1.0 - q) for j in J]
     else:
         lam_eff = lam
-        mu = coef[1] + lam
+        mu = c1 + lam
         omega = [K * coef[j] / lam for j in J]
     kind = problem["u0_kind"]
     kind = U0_KINDS[kind] if isinstance(kind, str) else int(kind)
@@ -169,6 +173,12 @@ def drift_of(problem: dict):
     """The constant drift b (x and y components; y is 0 in 1-D)."""
     b = [float(v) for v in problem.get("drift", (0.0, 0.0))] + [0.0, 0.0]
     return (b[0], b[1] if int(problem["dim"]) == 2 else 0.0)
+
+
+def linear_modulated(problem: dict) -> bool:
+    """True when the coefficient modulation also applies to c_1 (coef_mod "linear")."""
+    cm = problem.get("coef_mod")
+    return bool(cm) and bool(cm.get("linear", False))
 
 
 def cmod_of(problem: dict):

@@ -310,19 +310,23 @@ def adi_solve(grid: Grid, problem, bd, U0=None, n_steps=None):
 
     abx = band(rx, grid.cx - 1)
     aby = band(ry, grid.cy - 1)
-    from oracle import cmod_of
+    from oracle import cmod_of, linear_modulated
 
     cm = cmod_of(problem)
     if cm:
         bx, by, t0, pw = cm
         exy = np.exp(-by * ys * ys)[:, None] * np.exp(-bx * xs * xs)[None, :]
         pcoef = list(coef)
-        pcoef[1] = 0.0
+        lin_c = coef[1]  # the unmodulated linear coefficient
+        if linear_modulated(problem):
+            lin_c = 0.0  # the modulation multiplies c_1 u as well
+        else:
+            pcoef[1] = 0.0
     for n in range(n_steps):
         ut = 1.5 * U - 0.5 * Uold
         if cm:
             T = 1.0 / ((n + 0.5) * dt + t0) if pw == 1 else 1.0
-            F = coef[1] * ut + (exy * T) * f_poly(pcoef, ut)
+            F = lin_c * ut + (exy * T) * f_poly(pcoef, ut)
         else:
             F = f_poly(coef, ut)
         Unew = np.zeros_like(U)

@@ -180,7 +180,7 @@ def make_problem(d: dict) -> Problem:
         p.u0_params[i] = float(v)
     cm = d.get("coef_mod")
     if cm:
-        p.coef_mod = 1
+        p.coef_mod = 2 if cm.get("linear", False) else 1
         beta = list(cm.get("beta", (0.0, 0.0))) + [0.0]
         p.coef_mod_beta[0] = float(beta[0])
         p.coef_mod_beta[1] = float(beta[1])

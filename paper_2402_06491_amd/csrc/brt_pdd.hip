@@ -252,7 +252,7 @@ struct AdiArgs {
   const double* inv_y;
   uint32_t* sync;       // [2] abort; [4 + 2g], [5 + 2g] arrivals and generation of barrier group g
   uint64_t spin_limit;  // wall-clock ticks a barrier may wait
-  double pcoef[8];      // f(u) = c_1 u + m(x, y, t) sum_{j != 1} c_j u^j: the non-linear part (c_1 zeroed) ...
+  double pcoef[8];      // f(u) = c1 u + m(x, y, t) sum_j pcoef_j u^j: the modulated part (pcoef_1 = 0 unless c_1 is modulated) ...
   const double* ex;     // ... scaled by ex[i] ey[j] (t_mid + t0)^-pow (all 1 with constant coefficients)
   const double* ey;
   uint32_t cm_pow;
@@ -829,10 +829,10 @@ int brt_pdd_create(brt_ctx* ctx, const brt_problem* prob, const brt_pdd_grid* gr
   for (double c : prob->coef)
     if (!std::isfinite(c)) return set_error(BRT_E_ARG, "pdd: non-finite coefficient");
   if (prob->u0_kind > BRT_U0_COS2_BUMP) return set_error(BRT_E_ARG, "pdd: unknown u0_kind");
-  if (prob->coef_mod > BRT_COEF_MOD_GAUSS_TIME) return set_error(BRT_E_ARG, "pdd: unknown coef_mod");
+  if (prob->coef_mod > BRT_COEF_MOD_GAUSS_TIME_ALL) return set_error(BRT_E_ARG, "pdd: unknown coef_mod");
   if (prob->drift[0] != 0.0 || prob->drift[1] != 0.0)
     return set_error(BRT_E_ARG, "pdd: the subdomain solver takes drift-free problems (L = a Lap)");
-  if (prob->coef_mod == BRT_COEF_MOD_GAUSS_TIME &&
+  if (prob->coef_mod != BRT_COEF_MOD_NONE &&
       (!(prob->coef_mod_beta[0] >= 0.0) || !(prob->coef_mod_beta[1] >= 0.0) || prob->coef_mod_pow > 1 ||
        (prob->coef_mod_pow == 1 && !(prob->coef_mod_t0 > 0.0))))
     return set_error(BRT_E_ARG, "pdd: invalid variable-coefficient parameters");
@@ -941,7 +941,7 @@ int brt_pdd_create(brt_ctx* ctx, const brt_problem* prob, const brt_pdd_grid* gr
     pivot_reciprocals(p->rx, g.cx - 1, p->seg, fac.data());
     pivot_reciprocals(p->ry, g.cy - 1, p->seg, fac.data() + (size_t)kSegs * p->seg);
     std::vector<double> exy(p->NX + 1 + p->NY + 1, 1.0);
-    if (prob->coef_mod == BRT_COEF_MOD_GAUSS_TIME) {
+    if (prob->coef_mod != BRT_COEF_MOD_NONE) {
       for (uint32_t i = 0; i <= p->NX; ++i) {
         const double x = g.x_lo + i * p->hx;
         exy[i] = std::exp(-prob->coef_mod_beta[0] * x * x);
@@ -1101,12 +1101,14 @@ int brt_pdd_solve(brt_pdd* p, uint32_t steps, double* field, void* stream) {
   int rate_khz = 0;
   PDD_TRY(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, p->device));
   a.spin_limit = (uint64_t)(kBarrierSeconds * 1e3 * (rate_khz > 0 ? rate_khz : 100000));
+  // f = c_1 u + m(x, y, t) P(u): P holds the modulated terms, c_1 among them when it is modulated too
+  const bool lin = p->prob.coef_mod == BRT_COEF_MOD_GAUSS_TIME_ALL;
   for (int j = 0; j < 8; ++j) a.pcoef[j] = p->prob.coef[j];
-  a.pcoef[1] = 0.0;
-  const bool cmod = p->prob.coef_mod == BRT_COEF_MOD_GAUSS_TIME;
+  a.pcoef[1] = lin ? p->prob.coef[1] : 0.0;
+  const bool cmod = p->prob.coef_mod != BRT_COEF_MOD_NONE;
   a.cm_pow = cmod ? p->prob.coef_mod_pow : 0u;
   a.cm_t0 = p->prob.coef_mod_t0;
-  a.c1 = p->prob.coef[1];
+  a.c1 = lin ? 0.0 : p->prob.coef[1];
   a.dt = p->dt;
   a.ex = p->d_exy;
   a.ey = p->d_exy + p->NX + 1;

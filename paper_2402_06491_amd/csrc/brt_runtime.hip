@@ -96,22 +96,26 @@ int set_error(int code, const char* fmt, ...) {
 Norm normalize(const brt_problem& p, const brt_mc& mc) {
   Norm n;
   n.sigma = std::sqrt(2.0 * p.diffusion);
+  // With c_1 itself modulated, c_1(x, t) u cannot be absorbed into the prefactor: it joins the terms
+  // chosen at a split as a branching with one child.
+  const bool lin = p.coef_mod == BRT_COEF_MOD_GAUSS_TIME_ALL;
+  const double c1 = lin ? 0.0 : p.coef[1];  // the part of c_1 in the prefactor e^{mu t}
   for (uint32_t j = 0; j < 8; ++j)
-    if (j != 1 && p.coef[j] != 0.0) n.J[n.K++] = j;
+    if ((j != 1 || lin) && p.coef[j] != 0.0) n.J[n.K++] = j;
   if (n.K == 0) {
     n.lambda = 0.0;
     n.inv_lambda = 0.0;
-    n.mu = p.coef[1];
+    n.mu = c1;
   } else if (mc.strategy == BRT_STRATEGY_B) {
     // Strategy B: u = v e^{c_1 t}; a vertex carries tau K c_j / (1 - q) e^{(j-1) c_1 tau'}.  q is the
     // coin's realised leaf probability floor(q 2^32) / 2^32, so the weights match the coin exactly.
     n.q = std::floor(mc.q * 4294967296.0) * 0x1p-32;
-    n.mu = p.coef[1];
+    n.mu = c1;
     for (uint32_t i = 0; i < n.K; ++i) n.omega[i] = (double)n.K * p.coef[n.J[i]] / (1.0 - n.q);
   } else {
     n.lambda = mc.lambda;
     n.inv_lambda = 1.0 / mc.lambda;
-    n.mu = p.coef[1] + mc.lambda;
+    n.mu = c1 + mc.lambda;
     for (uint32_t i = 0; i < n.K; ++i) n.omega[i] = (double)n.K * p.coef[n.J[i]] / mc.lambda;
   }
   n.Q = (uint64_t)std::floor(n.q * 4294967296.0);  // exact: q 2^32 is a scaling by a power of two
@@ -269,6 +273,7 @@ int brt_problem_check(const brt_problem* p, const brt_mc* mc) {
     case BRT_COEF_MOD_NONE:
       break;
     case BRT_COEF_MOD_GAUSS_TIME:
+    case BRT_COEF_MOD_GAUSS_TIME_ALL:
       if (!(p->coef_mod_beta[0] >= 0.0) || !(p->coef_mod_beta[1] >= 0.0) || !is_fin(p->coef_mod_beta[0]) ||
           !is_fin(p->coef_mod_beta[1]))
         return fail(BRT_E_ARG, "coef_mod_beta must be finite and >= 0");

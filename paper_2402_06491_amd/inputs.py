@@ -44,14 +44,15 @@ def gauss_sum(terms):
 
 
 def problem(dim, diffusion, coef, u0, coef_mod=None, drift=None):
-    """coef_mod (optional): {"beta": (bx, by), "t0": t0, "pow": 0|1} makes every non-linear coefficient
-    c_j exp(-bx x^2 - by y^2) (t + t0)^(-pow).  drift (optional): the constant b of L = a Lap + b.grad."""
+    """coef_mod (optional): {"beta": (bx, by), "t0": t0, "pow": 0|1[, "linear": True]} makes every non-linear
+    coefficient (and with "linear" c_1 too) c_j exp(-bx x^2 - by y^2) (t + t0)^(-pow).  drift (optional): the constant b of L = a Lap + b.grad."""
     coef = [float(c) for c in coef] + [0.0] * (8 - len(coef))
     d = {"dim": int(dim), "diffusion": float(diffusion), "coef": coef}
     d.update(u0)
     if coef_mod:
         d["coef_mod"] = {"beta": [float(b) for b in coef_mod.get("beta", (0.0, 0.0))],
-                         "t0": float(coef_mod.get("t0", 0.0)), "pow": int(coef_mod.get("pow", 0))}
+                         "t0": float(coef_mod.get("t0", 0.0)), "pow": int(coef_mod.get("pow", 0)),
+                         "linear": bool(coef_mod.get("linear", False))}
     if drift is not None:
         d["drift"] = [float(b) for b in drift]
     return d

@@ -102,6 +102,12 @@ def test_coef_mod_validation_host_only():
     p = brt.make_problem(inputs.problem(1, 1.0, [0.0, 0.0, -1.0], inputs.const(1.0)))
     p.coef_mod = 7
     assert L.brt_problem_check(ctypes.byref(p), ctypes.byref(mc)) == -1
+    lin = brt.make_problem(inputs.problem(1, 1.0, [0.0, 0.5, -1.0], inputs.const(1.0),
+                                          coef_mod={"beta": (1.0, 0.0), "t0": 0.1, "pow": 1, "linear": True}))
+    assert lin.coef_mod == 2
+    assert L.brt_problem_check(ctypes.byref(lin), ctypes.byref(mc)) == 0
+    lin.coef_mod = 3
+    assert L.brt_problem_check(ctypes.byref(lin), ctypes.byref(mc)) == -1
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libbrt.so not built")

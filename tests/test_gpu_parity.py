@@ -287,6 +287,24 @@ def test_drift_2d_strategy_b_with_variable_coefficients_and_mixed(ctx):
     _full_parity(ctx, "drift_mixed_problems", wl)
 
 
+@pytest.mark.parametrize("prec", [32, 64])
+def test_modulated_linear_term(ctx, prec):
+    """c_1 modulated too (coef_mod "linear"): c_1(x, t) u is sampled as a branching with one child;
+    1-D Strategy A and 2-D Strategy B."""
+    p1 = inputs.problem(1, 1.0, [0.0, 0.9, -1.0], inputs.logistic(1.0, 1.0 / math.sqrt(6.0), 0.0, 2),
+                        coef_mod={"beta": (0.4, 0.0), "t0": 0.1, "pow": 1, "linear": True})
+    x = np.linspace(-5.0, 5.0, 16).reshape(-1, 1)
+    wl = {"problems": [p1], "mc": inputs.mc_params(seed=41, max_order=10, pade=(5, 5), precision=prec), "x": x,
+          "t": np.full(16, 0.8), "n_trees": np.full(16, 1200)}
+    _full_parity(ctx, f"linear_modulated_1d_fp{prec}", wl)
+    p2 = inputs.problem(2, 0.8, [0.1, -0.7, 0.6, -0.5], inputs.cubic_2d_u0(2),
+                        coef_mod={"beta": (0.3, 0.7), "t0": 0.2, "pow": 1, "linear": True})
+    x2 = inputs.interface_points(16)[::4]
+    wl = {"problems": [p2], "mc": inputs.mc_params(seed=42, precision=prec, strategy=1, q=0.55), "x": x2,
+          "t": np.full(len(x2), 0.8), "n_trees": np.full(len(x2), 600)}
+    _full_parity(ctx, f"linear_modulated_2d_b_fp{prec}", wl)
+
+
 def test_launch_settings_do_not_change_results(ctx):
     """Every tree is computed by one lane from its own counters and segments are fixed, so launch
     settings (block size, LDS stack levels, chunk size) change nothing in the outputs."""

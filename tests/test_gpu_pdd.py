@@ -152,6 +152,17 @@ def test_tail_long_lines_32_unknown_segments(ctx):
     _tail_parity(ctx, "tail_long_lines", _cubic(2), grid, vals)
 
 
+def test_tail_modulated_linear_term(ctx):
+    """c_1 modulated with the other coefficients: f = m(x, y, t) (c_1 u + c_3 u^3) in the subdomain solves."""
+    grid = _grid(n_steps=30)
+    prob = inputs.problem(2, 1.0, [0.0, 1.0, 0.0, -1.0], inputs.cubic_2d_u0(0),
+                          coef_mod={"beta": (0.05, 0.08), "t0": 0.3, "pow": 1, "linear": True})
+    og = opdd.Grid(**grid)
+    xy, t = opdd.node_points(og)
+    vals = opdd.g_grid(prob, xy[:, 0], xy[:, 1]) * np.exp(-0.2 * t)
+    _tail_parity(ctx, "tail_linear_modulated", prob, grid, vals)
+
+
 def test_tail_rejects_a_drift(ctx):
     import paper_2402_06491_amd as brt
 

@@ -275,3 +275,17 @@ def test_space_varying_coefficient_is_applied_at_the_node():
     assert d[j0, i0 + 6] > 2.0 * d[j0 + 6, i0] > 1e-3
     np.testing.assert_allclose(d, d[::-1, :], atol=1e-12)
     np.testing.assert_allclose(d, d[:, ::-1], atol=1e-12)
+
+
+def test_time_varying_linear_coefficient_second_order():
+    """c_1 modulated too: u_t = Lap u + c u/(t + t0) with constant data is the ODE u' = c u/(t + t0),
+    u = g0 (1 + t/t0)^c; the ADI integrates it at second order (the modulation multiplies c_1 u)."""
+    g0, c, t0 = 0.6, 1.4, 0.1
+    prob = inputs.problem(2, 1.0, [0.0, c], inputs.const(g0),
+                          coef_mod={"beta": (0.0, 0.0), "t0": t0, "pow": 1, "linear": True})
+
+    def fn(X, Y, t):
+        return np.full(np.broadcast(X, Y).shape, g0 * (1.0 + t / t0) ** c)
+    e = [_max_err(_grid(8, s, T=0.5), prob, fn) for s in (80, 160, 320)]
+    for a, b in zip(e, e[1:]):
+        assert 3.5 < a / b < 5.0, e
