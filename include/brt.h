@@ -95,7 +95,27 @@ typedef struct brt_problem {
    * drift[1] must be 0 in 1-D.  {0, 0} is the paper's L = a Lap.  The domain-decomposition tail
    * (brt_pdd_*) takes drift-free problems only. */
   double drift[2];
+  /* A general L (Sec. 2.1's SDE with state-dependent coefficients, integrated by the Euler scheme as in
+   * Sec. 2.4): with sde = BRT_SDE_EULER every edge is integrated by Euler-Maruyama steps for the drift
+   * b(x) = drift + drift_lin * x (componentwise) and the diffusion
+   * sigma(x) = sqrt(2a) (1 + sigma_amp exp(-|x|^2 / (2 sigma_width^2))), i.e. the operator
+   * L = sigma(x)^2/2 Lap + b(x) . grad.  An edge of duration s takes n = ceil(s / sde_dt) equal steps
+   * (so the steps end at the branching times); step k of an edge draws its normals from the Philox block
+   * (node, tree, point, k), step 0 from the node's own block.  sde_dt >= 1e-6; sigma_amp > -1; sigma_width
+   * > 0 when sigma_amp != 0; drift_lin[1] = 0 in 1-D.  BRT_SDE_EXACT (0) takes one exact Gaussian increment
+   * per edge and needs drift_lin = 0 and sigma_amp = 0.  The domain-decomposition tail takes
+   * BRT_SDE_EXACT only.  The cost grows with the number of steps per edge, which is capped at 2^20 (longer
+   * edges then take steps longer than sde_dt). */
+  uint32_t sde;
+  uint32_t sde_pad;
+  double drift_lin[2];
+  double sigma_amp;
+  double sigma_width;
+  double sde_dt;
 } brt_problem;
+
+#define BRT_SDE_EXACT 0u
+#define BRT_SDE_EULER 1u
 
 #define BRT_COEF_MOD_NONE 0u
 #define BRT_COEF_MOD_GAUSS_TIME 1u

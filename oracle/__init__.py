@@ -79,6 +79,12 @@ class _Problem(ctypes.Structure):
         ("cmod_by", ctypes.c_double),
         ("cmod_t0", ctypes.c_double),
         ("drift", ctypes.c_double * 2),
+        ("sde", ctypes.c_int32),
+        ("sde_pad", ctypes.c_int32),
+        ("dlin", ctypes.c_double * 2),
+        ("sig_amp", ctypes.c_double),
+        ("sig_k", ctypes.c_double),
+        ("inv_h", ctypes.c_double),
     ]
 
 
@@ -121,6 +127,8 @@ class Normalized:
     q: float = 1.0        # Strategy B: probability that a node is a leaf
     cmod: tuple = None    # variable coefficients (bx, by, t0, pow): c_j exp(-bx x^2 - by y^2) (t + t0)^-pow
     drift: tuple = (0.0, 0.0)  # constant drift b of L = a Lap + b.grad (the paths are x + b s + sigma W_s)
+    euler: tuple = None   # general L by Euler-Maruyama: (B_x, B_y, A, 1/(2 w^2), 1/h) for b(x) = drift + B x,
+                          # sigma(x) = sigma (1 + A e^{-|x|^2/(2 w^2)}), steps of at most h
 
 
 def normalize(problem: dict, mc: dict) -> Normalized:
@@ -166,7 +174,19 @@ def normalize(problem: dict, mc: dict) -> Normalized:
     return Normalized(dim=int(problem["dim"]), sigma=math.sqrt(2.0 * float(problem["diffusion"])),
                       lam=lam_eff, mu=mu, J=J, omega=omega, u0_kind=kind,
                       u0_params=params, u0_nterms=nterms, strategy=strategy, q=q, cmod=cmod_of(problem),
-                      drift=drift_of(problem))
+                      drift=drift_of(problem), euler=euler_of(problem))
+
+
+def euler_of(problem: dict):
+    """(B_x, B_y, A, 1/(2 w^2), 1/h) of a problem whose paths are integrated by Euler-Maruyama, else None."""
+    e = problem.get("euler")
+    if not e:
+        return None
+    bl = [float(v) for v in e.get("drift_lin", (0.0, 0.0))] + [0.0, 0.0]
+    amp = float(e.get("sigma_amp", 0.0))
+    w = float(e.get("sigma_width", 1.0))
+    return (bl[0], bl[1] if int(problem["dim"]) == 2 else 0.0, amp, 1.0 / (2.0 * w * w) if amp != 0.0 else 0.0,
+            1.0 / float(e["dt"]))
 
 
 def drift_of(problem: dict):
@@ -218,6 +238,9 @@ def _make_struct(nz: Normalized, mc: dict) -> _Problem:
     pb.node_cap = int(mc.get("node_cap", 1 << 16))
     pb.strategy = nz.strategy
     pb.drift[0], pb.drift[1] = nz.drift
+    if nz.euler:
+        pb.sde = 1
+        pb.dlin[0], pb.dlin[1], pb.sig_amp, pb.sig_k, pb.inv_h = nz.euler
     if nz.cmod:
         pb.cmod = 1
         pb.cmod_bx, pb.cmod_by, pb.cmod_t0, pb.cmod_pow = nz.cmod

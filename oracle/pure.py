@@ -53,6 +53,34 @@ def _g(kind, p, nterms, dim, x):
     raise ValueError(kind)
 
 
+def _move(nz, key, node, tree, point_id, x, dt, z):
+    """End of an edge of duration dt from x (z: the normals of the node's own block): one exact Gaussian
+    increment for constant coefficients, else ceil(dt/h) equal Euler-Maruyama steps whose k-th step
+    (k >= 1) draws its normals from the Philox block (node, tree, point, k)."""
+    dim = nz.dim
+    if not nz.euler:
+        return [x[d] + nz.drift[d] * dt + nz.sigma * math.sqrt(dt) * z[d] for d in range(dim)]
+    bx, by, amp, sk, inv_h = nz.euler
+    blin = (bx, by)
+    n = min(max(1, int(math.ceil(dt * inv_h))), 1 << 20)  # at most 2^20 steps per edge
+    h = dt / n
+    sh = math.sqrt(h)
+    y = list(x[:dim])
+    zz = list(z)
+    for k in range(n):
+        if k > 0:
+            w = philox4x32_10((node, tree, point_id, k), key)
+            u1 = (w[2] + 0.5) / 2.0 ** 32
+            u2 = w[3] / 2.0 ** 32
+            r = math.sqrt(-2.0 * math.log(u1))
+            zz = [r * math.cos(2.0 * math.pi * u2), r * math.sin(2.0 * math.pi * u2)]
+        r2 = sum(y[d] * y[d] for d in range(dim))
+        sg = nz.sigma * (1.0 + amp * math.exp(-sk * r2))
+        inc = [(nz.drift[d] + blin[d] * y[d]) * h + sg * sh * zz[d] for d in range(dim)]
+        y = [y[d] + inc[d] for d in range(dim)]
+    return y
+
+
 def _cmod(nz, x, tau):
     """Scale of the constant coefficients at a split at x with PDE time tau left (variable c_j(x, t))."""
     cm = getattr(nz, "cmod", None)
@@ -102,7 +130,7 @@ def walk_tree(nz, mc, x0, t, point_id, tree):
         if Pn > theta:
             S = -math.log(U) / nz.lam
             tau2 = max(tau - S, 0.0)
-            xs = [x[d] + nz.drift[d] * S + nz.sigma * math.sqrt(S) * z[d] for d in range(dim)]
+            xs = _move(nz, key, node - 1, tree, point_id, x, S, z)
             ne += 1
             if prune and ne > max_order:
                 return 0.0, ne, node, 1
@@ -116,7 +144,7 @@ def walk_tree(nz, mc, x0, t, point_id, tree):
                     stack.append([(xs, Pn, tau2), alpha - 1])
                 state = (xs, Pn, tau2)
         else:
-            xl = [x[d] + nz.drift[d] * tau + nz.sigma * math.sqrt(tau) * z[d] for d in range(dim)]
+            xl = _move(nz, key, node - 1, tree, point_id, x, tau, z)
             prod *= _g(nz.u0_kind, nz.u0_params, nz.u0_nterms, dim, xl)
             branch_done = True
         if branch_done:
@@ -157,7 +185,7 @@ def _walk_tree_b(nz, mc, x0, t, point_id, tree):
             span = 2.0 ** 32 - Q
             s = tau * ((w[0] - Q + 0.5) / span)
             tau2 = tau * ((2 ** 32 - 1 - w[0] + 0.5) / span)  # tau (1 - V) without cancellation
-            xs = [x[d] + nz.drift[d] * s + nz.sigma * math.sqrt(s) * z[d] for d in range(dim)]
+            xs = _move(nz, key, node - 1, tree, point_id, x, s, z)
             ne += 1
             if prune and ne > max_order:
                 return 0.0, ne, node, 1
@@ -170,7 +198,7 @@ def _walk_tree_b(nz, mc, x0, t, point_id, tree):
                 state = (xs, tau2)
                 continue
         else:
-            xl = [x[d] + nz.drift[d] * tau + nz.sigma * math.sqrt(tau) * z[d] for d in range(dim)]
+            xl = _move(nz, key, node - 1, tree, point_id, x, tau, z)
             prod *= _g(nz.u0_kind, nz.u0_params, nz.u0_nterms, dim, xl) / nz.q
         if not stack:
             return prod, ne, node, 0

@@ -80,6 +80,11 @@ typedef struct {
   int32_t cmod_pow;
   double cmod_bx, cmod_by, cmod_t0;
   double drift[2];    /* constant drift b of L = a Lap + b.grad: an edge of duration s moves by b s + sigma W_s */
+  int32_t sde;        /* 1: Euler-Maruyama edges for b(x) = drift + dlin x, sigma(x) = sigma (1 + sig_amp e^{-sig_k |x|^2}) */
+  int32_t sde_pad;
+  double dlin[2];
+  double sig_amp, sig_k;
+  double inv_h;       /* 1 / (largest Euler step) */
 } or_problem;
 
 /* ---- Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) ------------------ */
@@ -166,6 +171,42 @@ static double or_cmod(const or_problem* pb, const double* x, double tau) {
   return v;
 }
 
+/* End of one edge of duration dt that starts at x, for the node with Philox counter node (z: the normals
+ * of its own block).  Constant coefficients: one exact Gaussian increment, b dt + sigma sqrt(dt) z.  A
+ * general L: n = ceil(dt / h) equal Euler-Maruyama steps (they end at the edge's end, the branching
+ * time), y += b(y) dt/n + sigma(y) sqrt(dt/n) z_k, with z_0 = z and z_k from the block (node, tree,
+ * point, k). */
+static void or_move(const or_problem* pb, const or_tree* st, uint32_t node, const double* x, double dt,
+                    const double* z, double* out) {
+  if (!pb->sde) {
+    for (int d = 0; d < pb->dim; d++) out[d] = x[d] + pb->drift[d] * dt + pb->sigma * sqrt(dt) * z[d];
+    return;
+  }
+  const double nf = ceil(dt * pb->inv_h);
+  const uint32_t n = nf < 1.0 ? 1u : nf > 1048576.0 ? 1048576u : (uint32_t)nf;  /* at most 2^20 steps */
+  const double h = dt / (double)n, sh = sqrt(h);
+  double y[2] = {x[0], pb->dim == 2 ? x[1] : 0.0};
+  double zz[2] = {z[0], z[1]};
+  for (uint32_t k = 0; k < n; k++) {
+    if (k > 0) {
+      uint32_t ctr[4] = {node, st->tree, st->pid, k};
+      uint32_t w[4];
+      or_philox4x32_10(ctr, pb->key, w);
+      const double u1 = ((double)w[2] + 0.5) / 4294967296.0, u2 = (double)w[3] / 4294967296.0;
+      const double r = sqrt(-2.0 * log(u1));
+      zz[0] = r * cos(2.0 * M_PI * u2);
+      zz[1] = r * sin(2.0 * M_PI * u2);
+    }
+    double r2 = y[0] * y[0];
+    if (pb->dim == 2) r2 += y[1] * y[1];
+    const double sg = pb->sigma * (1.0 + pb->sig_amp * exp(-pb->sig_k * r2));
+    double inc[2];
+    for (int d = 0; d < pb->dim; d++) inc[d] = (pb->drift[d] + pb->dlin[d] * y[d]) * h + sg * sh * zz[d];
+    for (int d = 0; d < pb->dim; d++) y[d] += inc[d];
+  }
+  for (int d = 0; d < pb->dim; d++) out[d] = y[d];
+}
+
 /* Value of the subtree whose root starts at position x with lineage clock
  * product P and remaining PDE time tau. */
 static double or_visit(const or_problem* pb, or_tree* st, const double* x, double P, double tau) {
@@ -173,7 +214,8 @@ static double or_visit(const or_problem* pb, or_tree* st, const double* x, doubl
     st->flags |= OR_FLAG_CAPPED;
     return 0.0;
   }
-  uint32_t ctr[4] = {st->node, st->tree, st->pid, 0u};
+  const uint32_t node = st->node;
+  uint32_t ctr[4] = {node, st->tree, st->pid, 0u};
   uint32_t w[4];
   or_philox4x32_10(ctr, pb->key, w);
   st->node += 1;
@@ -192,7 +234,7 @@ static double or_visit(const or_problem* pb, or_tree* st, const double* x, doubl
     double tau2 = tau - S;
     if (tau2 < 0.0) tau2 = 0.0;
     double xs[2];
-    for (int d = 0; d < pb->dim; d++) xs[d] = x[d] + pb->drift[d] * S + pb->sigma * sqrt(S) * z[d];
+    or_move(pb, st, node, x, S, z, xs);
     st->ne += 1;
     if (pb->prune && st->ne > (uint32_t)pb->max_order) {
       st->flags |= OR_FLAG_OVERFLOW;
@@ -210,7 +252,7 @@ static double or_visit(const or_problem* pb, or_tree* st, const double* x, doubl
   }
   /* leaf: the path runs to the final time; evaluate g where it ends */
   double xl[2];
-  for (int d = 0; d < pb->dim; d++) xl[d] = x[d] + pb->drift[d] * tau + pb->sigma * sqrt(tau) * z[d];
+  or_move(pb, st, node, x, tau, z, xl);
   return or_g(pb, xl);
 }
 
@@ -226,7 +268,8 @@ static double or_visit_b(const or_problem* pb, or_tree* st, const double* x, dou
     st->flags |= OR_FLAG_CAPPED;
     return 0.0;
   }
-  uint32_t ctr[4] = {st->node, st->tree, st->pid, 0u};
+  const uint32_t node = st->node;
+  uint32_t ctr[4] = {node, st->tree, st->pid, 0u};
   uint32_t w[4];
   or_philox4x32_10(ctr, pb->key, w);
   st->node += 1;
@@ -246,7 +289,7 @@ static double or_visit_b(const or_problem* pb, or_tree* st, const double* x, dou
     double s = tau * (((double)((uint64_t)w[0] - pb->Q) + 0.5) / span);
     double tau2 = tau * (((double)(0xFFFFFFFFu - w[0]) + 0.5) / span);
     double xs[2];
-    for (int d = 0; d < pb->dim; d++) xs[d] = x[d] + pb->drift[d] * s + pb->sigma * sqrt(s) * z[d];
+    or_move(pb, st, node, x, s, z, xs);
     st->ne += 1;
     if (pb->prune && st->ne > (uint32_t)pb->max_order) {
       st->flags |= OR_FLAG_OVERFLOW;
@@ -263,7 +306,7 @@ static double or_visit_b(const or_problem* pb, or_tree* st, const double* x, dou
     return val;
   }
   double xl[2];
-  for (int d = 0; d < pb->dim; d++) xl[d] = x[d] + pb->drift[d] * tau + pb->sigma * sqrt(tau) * z[d];
+  or_move(pb, st, node, x, tau, z, xl);
   return or_g(pb, xl) / pb->q;
 }
 

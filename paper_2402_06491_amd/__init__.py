@@ -34,7 +34,9 @@ class Problem(ctypes.Structure):
                 ("coef", ctypes.c_double * 8), ("u0_kind", ctypes.c_uint32), ("u0_nterms", ctypes.c_uint32),
                 ("u0_params", ctypes.c_double * 40), ("coef_mod", ctypes.c_uint32), ("coef_mod_pow", ctypes.c_uint32),
                 ("coef_mod_beta", ctypes.c_double * 2), ("coef_mod_t0", ctypes.c_double),
-                ("drift", ctypes.c_double * 2)]
+                ("drift", ctypes.c_double * 2), ("sde", ctypes.c_uint32), ("sde_pad", ctypes.c_uint32),
+                ("drift_lin", ctypes.c_double * 2), ("sigma_amp", ctypes.c_double), ("sigma_width", ctypes.c_double),
+                ("sde_dt", ctypes.c_double)]
 
 
 class MC(ctypes.Structure):
@@ -189,6 +191,15 @@ def make_problem(d: dict) -> Problem:
     b = list(d.get("drift", (0.0, 0.0))) + [0.0, 0.0]
     p.drift[0] = float(b[0])
     p.drift[1] = float(b[1])
+    e = d.get("euler")
+    if e:
+        p.sde = 1
+        bl = list(e.get("drift_lin", (0.0, 0.0))) + [0.0, 0.0]
+        p.drift_lin[0] = float(bl[0])
+        p.drift_lin[1] = float(bl[1])
+        p.sigma_amp = float(e.get("sigma_amp", 0.0))
+        p.sigma_width = float(e.get("sigma_width", 1.0))
+        p.sde_dt = float(e["dt"])
     return p
 
 

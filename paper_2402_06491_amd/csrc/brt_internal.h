@@ -20,6 +20,7 @@ constexpr uint32_t kMetaCapped = 1u << 9;
 constexpr uint32_t kMetaDepth = 1u << 10;
 constexpr int kMetaNodesShift = 11;
 constexpr uint32_t kMaxNodeCap = (1u << 21) - 1;  // nodes field is 21 bits
+constexpr uint32_t kMaxEulerSteps = 1u << 20;     // Euler-Maruyama steps per edge at most
 
 // Per-problem constants after the Strategy A normalisation, in the walker's precision.
 template <typename Real>
@@ -38,6 +39,9 @@ struct PdeT {
   uint32_t drift_on; // 1: constant drift b, an edge of duration s moves by b s + sigma W_s
   Real cm_bx, cm_by, cm_t0;
   Real drift[2];
+  uint32_t sde;      // 1: Euler-Maruyama steps for b(x) = drift + dlin x, sigma(x) = sigma (1 + sig_amp e^{-sig_k |x|^2})
+  uint32_t pad3;
+  Real dlin[2], sig_amp, sig_k, inv_h;
   Real omega[8];     // Strategy A: K c_j / lambda; Strategy B: K c_j / (1 - q)
   Real u0[kMaxU0Params];
 };
@@ -147,7 +151,7 @@ struct Norm {
 Norm normalize(const brt_problem& p, const brt_mc& mc);
 // A problem the walker's general-coefficients variant takes: variable coefficients or a drift.
 inline bool general_coefficients(const brt_problem& p) {
-  return p.coef_mod != BRT_COEF_MOD_NONE || p.drift[0] != 0.0 || p.drift[1] != 0.0;
+  return p.coef_mod != BRT_COEF_MOD_NONE || p.drift[0] != 0.0 || p.drift[1] != 0.0 || p.sde != BRT_SDE_EXACT;
 }
 size_t pde_bytes(int precision);
 void pde_to_device(const brt_problem& p, const Norm& n, int precision, void* dst);

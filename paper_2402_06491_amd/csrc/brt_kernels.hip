@@ -91,8 +91,9 @@ struct Math<double> {
 template <typename Real>
 struct HotC {
   Real sigma, inv_lambda, mu, inv_q, s_scale;
-  uint32_t K, jpack, q_lo, cmod, cm_pow, drift_on;
+  uint32_t K, jpack, q_lo, cmod, cm_pow, drift_on, sde;
   Real cm_bx, cm_by, cm_t0, drift0, drift1;
+  Real dlin0, dlin1, sig_amp, sig_k, inv_h;  // a general L (Euler-Maruyama edges)
   Real g[6];  // first initial-data parameters (the logistic family's A, s, x0, p, n0, n1)
 };
 
@@ -115,6 +116,12 @@ __device__ __forceinline__ HotC<Real> hot_of(const PdeT<Real>& pd) {
   h.drift_on = pd.drift_on;
   h.drift0 = pd.drift[0];
   h.drift1 = pd.drift[1];
+  h.sde = pd.sde;
+  h.dlin0 = pd.dlin[0];
+  h.dlin1 = pd.dlin[1];
+  h.sig_amp = pd.sig_amp;
+  h.sig_k = pd.sig_k;
+  h.inv_h = pd.inv_h;
   for (int i = 0; i < 6; ++i) h.g[i] = pd.u0[i];
   return h;
 }
@@ -174,6 +181,42 @@ __device__ __forceinline__ Real eval_g(const PdeT<Real>& pd, const Real* x) {
 __device__ __forceinline__ uint64_t lanemask_lt() {
   const uint32_t lane = __lane_id();
   return (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+}
+
+// One edge of a general L = sigma(x)^2/2 Lap + b(x) . grad (Sec. 2.1's SDE, the Euler scheme of Sec. 2.4):
+// n = ceil(dt / h) (at most kMaxEulerSteps) equal Euler-Maruyama steps, which end at the edge's end (its branching time), with
+// b(x) = drift + dlin x and sigma(x) = sigma (1 + sig_amp e^{-sig_k |x|^2}).  Step 0 uses the node's own
+// normals (radius r0, angle cos/sin c0, s0), step k the Philox block (node, tree, point, k).
+template <typename Real, int DIM>
+__device__ __forceinline__ void euler_edge(const HotC<Real>& hc, const Real* x, Real dt, Real r0, Real c0, Real s0,
+                                           uint32_t node, uint32_t tree, uint32_t pid, uint32_t k0, uint32_t k1,
+                                           Real* out) {
+  const Real nf = ceil(dt * hc.inv_h);
+  const uint32_t n = nf < (Real)1 ? 1u : nf > (Real)kMaxEulerSteps ? kMaxEulerSteps : (uint32_t)nf;
+  const Real h = dt / (Real)n, sh = Math<Real>::sq(h);
+  Real y0 = x[0], y1 = DIM == 2 ? x[1] : (Real)0;
+  Real za = r0 * c0, zb = r0 * s0;
+  for (uint32_t k = 0; k < n; ++k) {
+    if (k > 0) {
+      const U4 v = philox4x32_10(node, tree, pid, k, k0, k1);
+      const Real u1 = ((Real)v.c + (Real)0.5) * (Real)0x1p-32;
+      const Real u2 = (Real)v.d * (Real)0x1p-32;
+      const Real r = Math<Real>::sq((Real)-2 * Math<Real>::ln(u1));
+      Real sn, cs;
+      Math<Real>::sincos_rev(u2, &sn, &cs);
+      za = r * cs;
+      zb = r * sn;
+    }
+    Real r2 = y0 * y0;
+    if constexpr (DIM == 2) r2 += y1 * y1;
+    const Real sg = hc.sigma * ((Real)1 + hc.sig_amp * Math<Real>::ex(-hc.sig_k * r2));
+    const Real i0 = (hc.drift0 + hc.dlin0 * y0) * h + sg * sh * za;
+    const Real i1 = (hc.drift1 + hc.dlin1 * y1) * h + sg * sh * zb;
+    y0 += i0;
+    if constexpr (DIM == 2) y1 += i1;
+  }
+  out[0] = y0;
+  out[1] = DIM == 2 ? y1 : x[1];
 }
 
 template <typename Real, int DIM>
@@ -437,8 +480,12 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
     xn[0] = x[0] + sdr * cs;
     xn[1] = x[1] + sdr * sn;
     if constexpr (CMOD) {
-      // constant drift: the edge also moves by b dt (exact for L = a Lap + b . grad)
-      if (hc.drift_on) {
+      if (hc.sde) {
+        // a general L: the edge is integrated by Euler-Maruyama steps instead
+        euler_edge<Real, DIM>(hc, x, dt, Math<Real>::sq((Real)-2 * Math<Real>::ln(u1)), cs, sn, node, tree, pid, a.key0,
+                              a.key1, xn);
+      } else if (hc.drift_on) {
+        // constant drift: the edge also moves by b dt (exact for L = a Lap + b . grad)
         xn[0] += hc.drift0 * dt;
         xn[1] += hc.drift1 * dt;
       }

@@ -830,8 +830,8 @@ int brt_pdd_create(brt_ctx* ctx, const brt_problem* prob, const brt_pdd_grid* gr
     if (!std::isfinite(c)) return set_error(BRT_E_ARG, "pdd: non-finite coefficient");
   if (prob->u0_kind > BRT_U0_COS2_BUMP) return set_error(BRT_E_ARG, "pdd: unknown u0_kind");
   if (prob->coef_mod > BRT_COEF_MOD_GAUSS_TIME_ALL) return set_error(BRT_E_ARG, "pdd: unknown coef_mod");
-  if (prob->drift[0] != 0.0 || prob->drift[1] != 0.0)
-    return set_error(BRT_E_ARG, "pdd: the subdomain solver takes drift-free problems (L = a Lap)");
+  if (prob->drift[0] != 0.0 || prob->drift[1] != 0.0 || prob->sde != BRT_SDE_EXACT)
+    return set_error(BRT_E_ARG, "pdd: the subdomain solver takes L = a Lap (no drift, constant sigma)");
   if (prob->coef_mod != BRT_COEF_MOD_NONE &&
       (!(prob->coef_mod_beta[0] >= 0.0) || !(prob->coef_mod_beta[1] >= 0.0) || prob->coef_mod_pow > 1 ||
        (prob->coef_mod_pow == 1 && !(prob->coef_mod_t0 > 0.0))))

@@ -70,6 +70,14 @@ PdeT<Real> to_device(const brt_problem& p, const Norm& n) {
   d.drift_on = (p.drift[0] != 0.0 || p.drift[1] != 0.0) ? 1u : 0u;
   d.drift[0] = (Real)p.drift[0];
   d.drift[1] = (Real)(p.dim == 2 ? p.drift[1] : 0.0);
+  d.sde = p.sde;
+  if (p.sde == BRT_SDE_EULER) {
+    d.dlin[0] = (Real)p.drift_lin[0];
+    d.dlin[1] = (Real)(p.dim == 2 ? p.drift_lin[1] : 0.0);
+    d.sig_amp = (Real)p.sigma_amp;
+    d.sig_k = p.sigma_amp != 0.0 ? (Real)(1.0 / (2.0 * p.sigma_width * p.sigma_width)) : (Real)0;
+    d.inv_h = (Real)(1.0 / p.sde_dt);
+  }
   for (int i = 0; i < kMaxU0Params; ++i) d.u0[i] = (Real)p.u0_params[i];
   if (p.u0_kind == BRT_U0_GAUSS_SUM)
     for (uint32_t k = 0; k < p.u0_nterms; ++k) {
@@ -286,6 +294,19 @@ int brt_problem_check(const brt_problem* p, const brt_mc* mc) {
   }
   if (!is_fin(p->drift[0]) || !is_fin(p->drift[1])) return fail(BRT_E_ARG, "drift must be finite");
   if (p->dim == 1 && p->drift[1] != 0.0) return fail(BRT_E_ARG, "drift[1] must be 0 in 1-D");
+  if (p->sde == BRT_SDE_EXACT) {
+    if (p->drift_lin[0] != 0.0 || p->drift_lin[1] != 0.0 || p->sigma_amp != 0.0)
+      return fail(BRT_E_ARG, "drift_lin and sigma_amp need sde = BRT_SDE_EULER");
+  } else if (p->sde == BRT_SDE_EULER) {
+    if (!(p->sde_dt >= 1e-6) || !is_fin(p->sde_dt)) return fail(BRT_E_ARG, "sde_dt must be finite and >= 1e-6");
+    if (!is_fin(p->drift_lin[0]) || !is_fin(p->drift_lin[1])) return fail(BRT_E_ARG, "drift_lin must be finite");
+    if (p->dim == 1 && p->drift_lin[1] != 0.0) return fail(BRT_E_ARG, "drift_lin[1] must be 0 in 1-D");
+    if (!(p->sigma_amp > -1.0) || !is_fin(p->sigma_amp)) return fail(BRT_E_ARG, "sigma_amp must be finite and > -1");
+    if (p->sigma_amp != 0.0 && (!(p->sigma_width > 0.0) || !is_fin(p->sigma_width)))
+      return fail(BRT_E_ARG, "sigma_width must be finite and > 0");
+  } else {
+    return fail(BRT_E_ARG, "unknown sde %u", p->sde);
+  }
   if (mc->precision != 32 && mc->precision != 64) return fail(BRT_E_ARG, "precision must be 32 or 64");
   if (!(mc->lambda > 0.0) || !is_fin(mc->lambda)) return fail(BRT_E_ARG, "lambda must be > 0");
   if (mc->max_order > 126) return fail(BRT_E_ARG, "max_order must be <= 126");

@@ -43,9 +43,12 @@ def gauss_sum(terms):
     return {"u0_kind": "gauss_sum", "u0_params": params, "u0_nterms": len(terms)}
 
 
-def problem(dim, diffusion, coef, u0, coef_mod=None, drift=None):
+def problem(dim, diffusion, coef, u0, coef_mod=None, drift=None, euler=None):
     """coef_mod (optional): {"beta": (bx, by), "t0": t0, "pow": 0|1[, "linear": True]} makes every non-linear
-    coefficient (and with "linear" c_1 too) c_j exp(-bx x^2 - by y^2) (t + t0)^(-pow).  drift (optional): the constant b of L = a Lap + b.grad."""
+    coefficient (and with "linear" c_1 too) c_j exp(-bx x^2 - by y^2) (t + t0)^(-pow).  drift (optional):
+    the constant b of L = a Lap + b.grad.  euler (optional): {"dt": h, "drift_lin": (B_x, B_y),
+    "sigma_amp": A, "sigma_width": w} integrates the paths by Euler-Maruyama steps of at most h for
+    b(x) = drift + B x and sigma(x) = sqrt(2a) (1 + A exp(-|x|^2/(2 w^2)))."""
     coef = [float(c) for c in coef] + [0.0] * (8 - len(coef))
     d = {"dim": int(dim), "diffusion": float(diffusion), "coef": coef}
     d.update(u0)
@@ -55,6 +58,10 @@ def problem(dim, diffusion, coef, u0, coef_mod=None, drift=None):
                          "linear": bool(coef_mod.get("linear", False))}
     if drift is not None:
         d["drift"] = [float(b) for b in drift]
+    if euler is not None:
+        d["euler"] = {"dt": float(euler["dt"]), "drift_lin": [float(b) for b in euler.get("drift_lin", (0.0, 0.0))],
+                      "sigma_amp": float(euler.get("sigma_amp", 0.0)),
+                      "sigma_width": float(euler.get("sigma_width", 1.0))}
     return d
 
 

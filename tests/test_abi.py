@@ -125,3 +125,30 @@ def test_drift_validation_host_only():
     assert L.brt_problem_check(ctypes.byref(bad_1d), ctypes.byref(mc)) == -1
     bad_inf = brt.make_problem(inputs.problem(2, 1.0, [0.0, 1.0, -1.0], inputs.const(1.0), drift=(float("inf"), 0.0)))
     assert L.brt_problem_check(ctypes.byref(bad_inf), ctypes.byref(mc)) == -1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libbrt.so not built")
+def test_euler_validation_host_only():
+    import paper_2402_06491_amd as brt
+    from paper_2402_06491_amd import inputs
+
+    L = brt.lib()
+    mc = brt.make_mc(inputs.mc_params())
+
+    def check(**kw):
+        d = inputs.problem(2, 1.0, [0.0, 1.0, -1.0], inputs.const(1.0), **kw)
+        return L.brt_problem_check(ctypes.byref(brt.make_problem(d)), ctypes.byref(mc))
+
+    assert check(euler={"dt": 0.01, "drift_lin": (0.5, -1.0), "sigma_amp": 0.3, "sigma_width": 1.0}) == 0
+    assert check(euler={"dt": 0.0}) == -1
+    assert check(euler={"dt": 0.01, "sigma_amp": -1.0, "sigma_width": 1.0}) == -1
+    assert check(euler={"dt": 0.01, "sigma_amp": 0.5, "sigma_width": 0.0}) == -1
+    p = brt.make_problem(inputs.problem(2, 1.0, [0.0, 1.0, -1.0], inputs.const(1.0)))
+    p.sigma_amp = 0.5  # needs the Euler scheme
+    assert L.brt_problem_check(ctypes.byref(p), ctypes.byref(mc)) == -1
+    p.sigma_amp = 0.0
+    p.sde = 5
+    assert L.brt_problem_check(ctypes.byref(p), ctypes.byref(mc)) == -1
+    one_d = brt.make_problem(inputs.problem(1, 1.0, [0.0, 1.0, -1.0], inputs.const(1.0),
+                                            euler={"dt": 0.01, "drift_lin": (0.5, 1.0)}))
+    assert L.brt_problem_check(ctypes.byref(one_d), ctypes.byref(mc)) == -1

@@ -305,6 +305,28 @@ def test_modulated_linear_term(ctx, prec):
     _full_parity(ctx, f"linear_modulated_2d_b_fp{prec}", wl)
 
 
+def test_euler_maruyama_general_operator(ctx):
+    """A general L (b(x) = b + B x, sigma(x) with a Gaussian bump) integrated by Euler-Maruyama steps of at
+    most h: FP64 paths tree by tree (on FP32 paths a step count ceil(s/h) may round differently from
+    the oracle's FP64 one at an exact step boundary).  The linear drifts contract (an expanding one
+    sends paths far out, where e^{-beta x^2} of the variable coefficients magnifies last-bit
+    differences past the FP64 tree bound).  1-D Fisher under Strategy A with 10+ steps per
+    unit time, and a 2-D Strategy B problem with variable coefficients and c_1(x, t) as well."""
+    p1 = inputs.problem(1, 1.0, [0.0, 1.0, -1.0], inputs.logistic(1.0, 1.0 / math.sqrt(6.0), 0.0, 2), drift=(0.4,),
+                        euler={"dt": 0.09, "drift_lin": (-0.6,), "sigma_amp": 0.5, "sigma_width": 2.0})
+    x = np.linspace(-5.0, 5.0, 12).reshape(-1, 1)
+    wl = {"problems": [p1], "mc": inputs.mc_params(seed=51, max_order=10, pade=(5, 5), precision=64), "x": x,
+          "t": np.full(12, 1.0), "n_trees": np.full(12, 800)}
+    _full_parity(ctx, "euler_fisher_fp64", wl)
+    p2 = inputs.problem(2, 0.8, [0.1, -0.7, 0.6, -0.5], inputs.cubic_2d_u0(2), drift=(0.3, -0.2),
+                        coef_mod={"beta": (0.3, 0.7), "t0": 0.2, "pow": 1, "linear": True},
+                        euler={"dt": 0.07, "drift_lin": (-0.5, -0.3), "sigma_amp": 0.4, "sigma_width": 1.5})
+    x2 = inputs.interface_points(16)[::5]
+    wl = {"problems": [p2], "mc": inputs.mc_params(seed=52, precision=64, strategy=1, q=0.55), "x": x2,
+          "t": np.full(len(x2), 0.8), "n_trees": np.full(len(x2), 400)}
+    _full_parity(ctx, "euler_2d_strategy_b_fp64", wl)
+
+
 def test_launch_settings_do_not_change_results(ctx):
     """Every tree is computed by one lane from its own counters and segments are fixed, so launch
     settings (block size, LDS stack levels, chunk size) change nothing in the outputs."""

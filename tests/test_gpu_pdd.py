@@ -169,6 +169,9 @@ def test_tail_rejects_a_drift(ctx):
     prob = inputs.problem(2, 1.0, [0.0, 1.0, 0.0, -1.0], inputs.cubic_2d_u0(0), drift=(0.5, 0.0))
     with pytest.raises(brt.BrtError, match="drift"):
         brt.Pdd(ctx, prob, _grid())
+    prob = inputs.problem(2, 1.0, [0.0, 1.0, 0.0, -1.0], inputs.cubic_2d_u0(0), euler={"dt": 0.01})
+    with pytest.raises(brt.BrtError, match="constant sigma"):
+        brt.Pdd(ctx, prob, _grid())
 
 
 def test_tail_full_size_first_steps(ctx):
