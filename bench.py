@@ -296,6 +296,7 @@ def pdd_bench(ctx, trees_per_node, cpu_steps):
     interior = g["px"] * g["py"] * (g["cx"] - 1) * (g["cy"] - 1)
     alg_bytes = 40.0 * interior * g["n_steps"]
     achieved = alg_bytes / (solve_ms * 1e-3) / 1e9
+    n_groups, die_local = pd.barrier()
     u = field.cpu().numpy()
     res = {"workload": wl["name"], "nodes": int(len(t)), "trees_per_node": int(trees_per_node),
            "grid": {k: g[k] for k in ("px", "py", "cx", "cy", "n_steps", "ns_x", "nt")},
@@ -304,6 +305,7 @@ def pdd_bench(ctx, trees_per_node, cpu_steps):
            "adi_roofline": {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
                             "frac": achieved / 8000.0, "algorithmic_bytes": alg_bytes,
                             "traffic": pmc_traffic(adi_source_sha(), name="adi_pdd_cubic_2d_pmc.json")},
+           "barrier_groups": n_groups, "die_local_groups": die_local,
            "field_finite": bool(np.isfinite(u).all()), "field_max": float(np.abs(u).max())}
     pd.close()
     if cpu_steps > 0:

@@ -391,9 +391,11 @@ int brt_pdd_interpolate(brt_pdd* pdd, const double* node_values, void* stream);
 int brt_pdd_boundary(const brt_pdd* pdd, uint32_t line, double* dst, void* stream);
 /* Solve every subdomain from u0 at the grid nodes through `steps` time steps (1..n_steps) with the
  * current boundary data and write the field at step `steps` to `field` (device).  One persistent
- * cooperative launch; work items of 64 lines are taken from per-phase counters, phases are separated
- * by a grid barrier.  Asynchronous; BRT_E_DEVICE if the barrier timed out (reported by the next
- * brt_pdd_* call that synchronises: brt_pdd_get_timing). */
+ * cooperative launch; each phase's work items (32 lines of a subdomain, 16 for lines of more than 512
+ * unknowns) are dealt statically to the blocks, and phases are separated by a barrier: one per die
+ * when the blocks and the subdomains split evenly over the dies (each die's blocks then own whole
+ * subdomains), else one over the grid.  Asynchronous; BRT_E_DEVICE if a barrier timed out (reported
+ * by the next brt_pdd_* call that synchronises: brt_pdd_get_timing). */
 int brt_pdd_solve(brt_pdd* pdd, uint32_t steps, double* field, void* stream);
 /* The whole tail: Monte Carlo at the nodes (a plan with `mc` and trees_per_node trees per node,
  * Pade values), interpolation, and the solve through n_steps.  node_u (device, nullable) receives the
@@ -404,6 +406,12 @@ int brt_pdd_run(brt_pdd* pdd, const brt_mc* mc, uint64_t trees_per_node, double*
  * ms[0] Monte Carlo (0 after brt_pdd_solve), ms[1] interpolation, ms[2] subdomain solves; BRT_E_DEVICE
  * if the solver's grid barrier timed out. */
 int brt_pdd_get_timing(brt_pdd* pdd, double* ms);
+/* Barrier placement of the last solve (waits for it): *groups receives the number of barrier groups
+ * (8 when the blocks and the subdomains split evenly over the dies, else 1; 0 before any solve) and
+ * *die_local how many of them had all their blocks on one die.  Such a group synchronises through
+ * its die's L2 alone (no L2 write-back at its barriers); the others use device-scope fences.  The
+ * result does not depend on the placement.  Errors: BRT_E_ARG (NULL argument), BRT_E_DEVICE. */
+int brt_pdd_get_barrier(brt_pdd* pdd, uint32_t* groups, uint32_t* die_local);
 void brt_pdd_destroy(brt_pdd* pdd);
 
 #ifdef __cplusplus

@@ -142,6 +142,8 @@ _SIGS = [
     ("brt_pdd_run", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(MC), ctypes.c_uint64, ctypes.c_void_p,
                                    ctypes.c_void_p, ctypes.c_void_p]),
     ("brt_pdd_get_timing", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
+    ("brt_pdd_get_barrier", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32),
+                                            ctypes.POINTER(ctypes.c_uint32)]),
     ("brt_pdd_destroy", None, [ctypes.c_void_p]),
 ]
 
@@ -555,6 +557,12 @@ class Pdd:
         ms = (ctypes.c_double * 3)()
         _check(lib().brt_pdd_get_timing(self._h, ms))
         return tuple(ms)
+
+    def barrier(self):
+        """(barrier groups, groups whose blocks all ran on one die) of the last solve; waits for it."""
+        g, d = ctypes.c_uint32(), ctypes.c_uint32()
+        _check(lib().brt_pdd_get_barrier(self._h, ctypes.byref(g), ctypes.byref(d)))
+        return int(g.value), int(d.value)
 
     def close(self):
         if self._h:

@@ -39,7 +39,7 @@ constexpr double kBarrierSeconds = 5.0;
 // tiles map onto whole cache lines.
 constexpr uint32_t kFieldLead = 15;  // doubles before column 0
 constexpr uint32_t kXcds = 8;        // workgroups are dealt to the accelerator's dies round-robin
-constexpr uint32_t kSyncWords = 4 + 2 * kXcds;  // abort word, then arrivals and generation per group
+constexpr uint32_t kSyncWords = 4 + 2 * kXcds;  // abort word, then arrivals and die mask per group
 
 #define PDD_TRY(expr)                                                                               \
   do {                                                                                              \
@@ -250,7 +250,7 @@ struct AdiArgs {
   const LineDev* lines;
   const double* inv_x;  // pivots' reciprocals of the x and the y lines, kSegs * S each, zero-padded
   const double* inv_y;
-  uint32_t* sync;       // [2] abort; [4 + 2g], [5 + 2g] arrivals and generation of barrier group g
+  uint32_t* sync;       // [2] abort; [4 + 2g] arrivals at, [5 + 2g] dies of the blocks of barrier group g
   uint64_t spin_limit;  // wall-clock ticks a barrier may wait
   double pcoef[8];      // f(u) = c1 u + m(x, y, t) sum_j pcoef_j u^j: the modulated part (pcoef_1 = 0 unless c_1 is modulated) ...
   const double* ex;     // ... scaled by ex[i] ey[j] (t_mid + t0)^-pow (all 1 with constant coefficients)
@@ -288,24 +288,36 @@ __device__ inline double time_factor(const AdiArgs& a, uint32_t n) {
   return a.cm_pow ? 1.0 / ((n + 0.5) * a.dt + a.cm_t0) : 1.0;
 }
 
-// Barrier of a group of blocks (sense by generation count; cnt[0] counts arrivals, cnt[1] is the
-// generation).  Every block waits at most spin_limit wall-clock ticks; on a time-out, or when any block
-// has timed out, it raises the abort word and returns false so that every block leaves the kernel.
+// Die (XCD) this wave runs on.
+__device__ inline uint32_t xcc_id() {
+  uint32_t v;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
+  return v & 0xfu;
+}
+
+// Barrier of a group of blocks: cnt counts arrivals from the start of the launch, so the k-th barrier
+// is passed when it reaches k * members (no reset between barriers).  Every block waits at most
+// spin_limit wall-clock ticks; on a time-out, or when any block has timed out, it raises the abort
+// word and returns false so that every block leaves the kernel.
+//
+// Fences.  With die_local set, every block of the group runs on one die, and all that the group's
+// blocks read after a barrier was written by the group itself: the die's L2 is then the coherence
+// point, so each wave waits until its stores are in L2 and the arriving side needs no L2 write-back,
+// and the leaving side invalidates only the CU's L1.  Otherwise device-scope fences (L2 write-back
+// and invalidation) order the phases.
 __device__ bool group_barrier(uint32_t* cnt, uint32_t* abort_word, uint32_t members, uint32_t& gen, uint64_t spin_limit,
-                              uint32_t* flag) {
+                              bool die_local, uint32_t* flag) {
+  if (die_local) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t ok = 1;
-    __threadfence();
-    const uint32_t target = gen + 1;
-    if (atomicAdd(&cnt[0], 1u) == members - 1) {
-      __hip_atomic_store(&cnt[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(&cnt[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
+    if (!die_local) __threadfence();
+    const uint32_t target = (gen + 1) * members;
+    if (atomicAdd(cnt, 1u) != target - 1) {
       const uint64_t t0 = wall_clock64();
-      // relaxed polling: an acquiring load would invalidate this XCD's L2 on every poll while other
-      // blocks still work; the fence below acquires once the generation has moved
-      while (__hip_atomic_load(&cnt[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != target) {
+      // relaxed polling: an acquiring load would invalidate the caches on every poll while other
+      // blocks still work; the fence below acquires once the count has reached the target
+      while ((int32_t)(__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) < 0) {
         if (__hip_atomic_load(abort_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
             wall_clock64() - t0 > spin_limit) {
           atomicExch(abort_word, 1u);
@@ -315,8 +327,11 @@ __device__ bool group_barrier(uint32_t* cnt, uint32_t* abort_word, uint32_t memb
         __builtin_amdgcn_s_sleep(2);
       }
     }
-    __threadfence();
-    gen = target;
+    if (die_local)
+      asm volatile("buffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
+    else
+      __threadfence();
+    gen += 1;
     *flag = ok;
   }
   __syncthreads();
@@ -736,14 +751,18 @@ __global__ __launch_bounds__(AdiShape<S>::threads) void adi_kernel(AdiArgs a) {
   // Items of a phase cost the same (equal subdomains), so they are dealt statically: no counter
   // traffic between the barriers.
   const ItemRange xr = block_items(x_items), yr = block_items(y_items);
+  // Which dies the group's blocks run on: one bit per die, complete after the group's first barrier.
+  if (threadIdx.x == 0) atomicOr(bar + 1, 1u << xcc_id());
+  if (!group_barrier(bar, a.sync + 2, members, gen, a.spin_limit, false, &barrier_ok)) return;
+  const bool die_local = __popc(__hip_atomic_load(bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == 1;
   for (uint32_t n = 0; n < a.steps; ++n) {
     const double* cur = (n & 1) ? a.f1 : a.f0;
     double* prev = (n & 1) ? a.f0 : a.f1;  // holds u^{n-1}; receives u^{n+1}
     for (uint32_t it = xr.begin; it < xr.end; it += xr.stride) x_sweep<S>(a, it, n, cur, prev, smem);
-    if (!group_barrier(bar, a.sync + 2, members, gen, a.spin_limit, &barrier_ok)) return;
+    if (!group_barrier(bar, a.sync + 2, members, gen, a.spin_limit, die_local, &barrier_ok)) return;
     for (uint32_t it = yr.begin; it < yr.end; it += yr.stride) y_sweep<S>(a, it, n, prev, smem);
     for (uint32_t it = blockIdx.x; it < l_items; it += gridDim.x) write_lines(a, it, n, prev);
-    if (!group_barrier(bar, a.sync + 2, members, gen, a.spin_limit, &barrier_ok)) return;
+    if (!group_barrier(bar, a.sync + 2, members, gen, a.spin_limit, die_local, &barrier_ok)) return;
   }
 }
 
@@ -777,6 +796,7 @@ struct brt_pdd {
   uint64_t plan_trees = 0;
   hipEvent_t ev[6] = {};
   bool recorded[3] = {false, false, false};
+  uint32_t last_groups = 0;  // barrier groups of the last solve
   int grid = 0;
   int seg = 16;    // unknowns per segment of the solver's line solves
   size_t lds = 0;  // dynamic LDS of the solver launch (bytes)
@@ -1125,6 +1145,7 @@ int brt_pdd_solve(brt_pdd* p, uint32_t steps, double* field, void* stream) {
   // Subdomains are decoupled: when every die's blocks own whole subdomains in both phases, each die's
   // blocks synchronise among themselves only.
   a.groups = (p->grid % kXcds == 0 && (g.px * g.py) % kXcds == 0) ? kXcds : 1u;
+  p->last_groups = a.groups;
   const uint32_t lines = adi_lines(p->seg), threads = adi_threads(p->seg);
   a.x_blk = (g.cy - 1 + lines - 1) / lines;
   a.y_blk = (g.cx - 1 + lines - 1) / lines;
@@ -1188,6 +1209,18 @@ int brt_pdd_run(brt_pdd* p, const brt_mc* mc, uint64_t trees_per_node, double* n
   rc = brt_pdd_interpolate(p, u, stream);
   if (rc != BRT_OK) return rc;
   return brt_pdd_solve(p, p->g.n_steps, field, stream);
+}
+
+int brt_pdd_get_barrier(brt_pdd* p, uint32_t* groups, uint32_t* die_local) {
+  if (!p || !groups || !die_local) return set_error(BRT_E_ARG, "brt_pdd_get_barrier: NULL argument");
+  *groups = *die_local = 0;
+  if (!p->recorded[2]) return BRT_OK;
+  PDD_TRY(hipEventSynchronize(p->ev[5]));
+  uint32_t w[kSyncWords];
+  PDD_TRY(hipMemcpy(w, p->d_sync, sizeof(w), hipMemcpyDeviceToHost));
+  *groups = p->last_groups;
+  for (uint32_t g = 0; g < p->last_groups; ++g) *die_local += __builtin_popcount(w[5 + 2 * g]) == 1 ? 1u : 0u;
+  return BRT_OK;
 }
 
 int brt_pdd_get_timing(brt_pdd* p, double* ms) {
