@@ -992,11 +992,22 @@ int brt_pdd_create(brt_ctx* ctx, const brt_problem* prob, const brt_pdd_grid* gr
     const uint32_t x_items = nsub * ((g.cy - 1 + lines - 1) / lines);
     const uint32_t y_items = nsub * ((g.cx - 1 + lines - 1) / lines);
     const uint64_t cap = (uint64_t)per_cu * p->n_cu;
-    // Half the compute units, a multiple of the die count: the phases are bound by the memory system,
-    // and on the 4 x 4 x 512^2 workload a step took 76 us at 128 blocks of 1024 threads and 88 at 256
-    // (more concurrent blocks only lengthen every block's memory latency).
-    const uint64_t half = std::max<uint64_t>(kXcds, (uint64_t)p->n_cu / 2 / kXcds * kXcds);
-    p->grid = (int)std::min<uint64_t>({(uint64_t)std::max(x_items, y_items), half, cap});
+    const uint64_t items = std::max(x_items, y_items);
+    if (nsub % kXcds == 0 && cap >= kXcds) {
+      // Die-local barriers (the subdomains split over the dies): the fewest rounds of items over all
+      // resident blocks, dealt evenly, a multiple of the die count.  On the 4 x 4 x 512^2 workload a
+      // step takes 54 us at 256 blocks of 1024 threads (one item per block and phase), 61 at 128 and
+      // 65-67 at 160 or 192 (uneven rounds).
+      const uint64_t cap8 = cap / kXcds * kXcds;
+      const uint64_t rounds = (items + cap8 - 1) / cap8;
+      p->grid = (int)std::min<uint64_t>(cap8, ((items + rounds - 1) / rounds + kXcds - 1) / kXcds * kXcds);
+    } else {
+      // One barrier over the grid, with device-scope fences: half the compute units, a multiple of the
+      // die count (a step of that workload took 76 us at 128 blocks and 88 at 256 with these fences:
+      // more blocks lengthen every block's memory latency and add L2 write-backs at the barriers).
+      const uint64_t half = std::max<uint64_t>(kXcds, (uint64_t)p->n_cu / 2 / kXcds * kXcds);
+      p->grid = (int)std::min<uint64_t>({items, half, cap});
+    }
   }
   if (rc != BRT_OK) {
     pdd_free(p);
