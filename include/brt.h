@@ -392,9 +392,9 @@ int brt_pdd_boundary(const brt_pdd* pdd, uint32_t line, double* dst, void* strea
 /* Solve every subdomain from u0 at the grid nodes through `steps` time steps (1..n_steps) with the
  * current boundary data and write the field at step `steps` to `field` (device).  One persistent
  * cooperative launch; each phase's work items (32 lines of a subdomain, 16 for lines of more than 512
- * unknowns) are dealt statically to the blocks, and phases are separated by a barrier: one per die
- * when the blocks and the subdomains split evenly over the dies (each die's blocks then own whole
- * subdomains), else one over the grid.  Asynchronous; BRT_E_DEVICE if a barrier timed out (reported
+ * unknowns) are dealt statically to the blocks, and phases are separated by a barrier among the
+ * blocks that own the same subdomains: one per subdomain or one per die when blocks and subdomains
+ * split evenly (see brt_pdd_get_barrier), else one over the grid.  Asynchronous; BRT_E_DEVICE if a barrier timed out (reported
  * by the next brt_pdd_* call that synchronises: brt_pdd_get_timing). */
 int brt_pdd_solve(brt_pdd* pdd, uint32_t steps, double* field, void* stream);
 /* The whole tail: Monte Carlo at the nodes (a plan with `mc` and trees_per_node trees per node,
@@ -407,7 +407,8 @@ int brt_pdd_run(brt_pdd* pdd, const brt_mc* mc, uint64_t trees_per_node, double*
  * if the solver's grid barrier timed out. */
 int brt_pdd_get_timing(brt_pdd* pdd, double* ms);
 /* Barrier placement of the last solve (waits for it): *groups receives the number of barrier groups
- * (8 when the blocks and the subdomains split evenly over the dies, else 1; 0 before any solve) and
+ * (one per subdomain when the blocks split evenly over them and the subdomains over the dies, else 8
+ * when blocks and subdomains split evenly over the dies, else 1; 0 before any solve) and
  * *die_local how many of them had all their blocks on one die.  Such a group synchronises through
  * its die's L2 alone (no L2 write-back at its barriers); the others use device-scope fences.  The
  * result does not depend on the placement.  Errors: BRT_E_ARG (NULL argument), BRT_E_DEVICE. */

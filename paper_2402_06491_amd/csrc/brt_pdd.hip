@@ -39,7 +39,8 @@ constexpr double kBarrierSeconds = 5.0;
 // tiles map onto whole cache lines.
 constexpr uint32_t kFieldLead = 15;  // doubles before column 0
 constexpr uint32_t kXcds = 8;        // workgroups are dealt to the accelerator's dies round-robin
-constexpr uint32_t kSyncWords = 4 + 2 * kXcds;  // abort word, then arrivals and die mask per group
+constexpr uint32_t kMaxGroups = 512;             // barrier groups of a launch
+constexpr uint32_t kSyncWords = 4 + 2 * kMaxGroups;  // abort word, then arrivals and die mask per group
 
 #define PDD_TRY(expr)                                                                               \
   do {                                                                                              \
@@ -714,18 +715,32 @@ __device__ void write_lines(const AdiArgs& a, uint32_t item, uint32_t n, double*
   }
 }
 
+// Blocks are dealt to the dies round-robin (block b on die b mod 8).  With a grid that is a multiple
+// of the die count, the blocks of die x, ranked r = b / 8, form `parts` consecutive parts of equal size
+// (parts a multiple of 8; 8 parts: one per die).  Part k = x (parts / 8) + r / size holds the blocks
+// that synchronise together when parts are barrier groups.
+struct BlockPart {
+  uint32_t part, rank, size;
+};
+__device__ inline BlockPart block_part(uint32_t parts) {
+  const uint32_t b = blockIdx.x, size = gridDim.x / parts, r = b / kXcds;
+  return {(b % kXcds) * (parts / kXcds) + r / size, r % size, size};
+}
+
 // Items of a phase taken by this block.  With a grid that is a multiple of the die count, the items
-// are split into one contiguous range per die and dealt round-robin over the die's blocks: the blocks
-// of a die then work on neighbouring strips at the same time and share the halo lines in its L2.
+// are split into one contiguous range per part (the barrier groups when there are more than 8, else
+// the dies) and dealt round-robin over the part's blocks: a group's blocks then take exactly the items
+// of its subdomains, and the blocks of a die work on neighbouring strips at the same time and share
+// the halo lines in its L2.
 struct ItemRange {
   uint32_t begin, end, stride;
 };
-__device__ inline ItemRange block_items(uint32_t n_items) {
-  const uint32_t b = blockIdx.x, g = gridDim.x;
-  if (g % kXcds != 0) return {b, n_items, g};
-  const uint32_t x = b % kXcds;
-  return {(uint32_t)((uint64_t)n_items * x / kXcds) + b / kXcds, (uint32_t)((uint64_t)n_items * (x + 1) / kXcds),
-          g / kXcds};
+__device__ inline ItemRange block_items(uint32_t n_items, uint32_t groups) {
+  if (gridDim.x % kXcds != 0) return {blockIdx.x, n_items, gridDim.x};
+  const uint32_t parts = groups > kXcds ? groups : kXcds;
+  const BlockPart p = block_part(parts);
+  return {(uint32_t)((uint64_t)n_items * p.part / parts) + p.rank, (uint32_t)((uint64_t)n_items * (p.part + 1) / parts),
+          p.size};
 }
 
 template <int S>
@@ -734,7 +749,7 @@ __global__ __launch_bounds__(AdiShape<S>::threads) void adi_kernel(AdiArgs a) {
   __shared__ uint32_t barrier_ok;
   uint32_t gen = 0;
   const uint32_t nsub = a.px * a.py;
-  uint32_t* const bar = a.sync + 4 + 2 * (blockIdx.x % a.groups);
+  uint32_t* const bar = a.sync + 4 + 2 * (a.groups > 1 ? block_part(a.groups).part : 0u);
   const uint32_t members = gridDim.x / a.groups;
   const uint32_t x_items = nsub * a.x_blk;
   const uint32_t y_items = nsub * a.y_blk;
@@ -750,7 +765,7 @@ __global__ __launch_bounds__(AdiShape<S>::threads) void adi_kernel(AdiArgs a) {
   }
   // Items of a phase cost the same (equal subdomains), so they are dealt statically: no counter
   // traffic between the barriers.
-  const ItemRange xr = block_items(x_items), yr = block_items(y_items);
+  const ItemRange xr = block_items(x_items, a.groups), yr = block_items(y_items, a.groups);
   // Which dies the group's blocks run on: one bit per die, complete after the group's first barrier.
   if (threadIdx.x == 0) atomicOr(bar + 1, 1u << xcc_id());
   if (!group_barrier(bar, a.sync + 2, members, gen, a.spin_limit, false, &barrier_ok)) return;
@@ -1153,9 +1168,11 @@ int brt_pdd_solve(brt_pdd* p, uint32_t steps, double* field, void* stream) {
   a.cy = g.cy;
   a.steps = steps;
   a.nblocks = (uint32_t)p->grid;
-  // Subdomains are decoupled: when every die's blocks own whole subdomains in both phases, each die's
-  // blocks synchronise among themselves only.
-  a.groups = (p->grid % kXcds == 0 && (g.px * g.py) % kXcds == 0) ? kXcds : 1u;
+  // Subdomains are decoupled, so blocks that own whole subdomains in both phases synchronise among
+  // themselves only: one group per subdomain when the grid splits evenly over them (a group then waits
+  // only for the blocks of its own subdomain), else one per die, else one over the grid.
+  const uint32_t nsub = g.px * g.py, grid = (uint32_t)p->grid;
+  a.groups = nsub % kXcds != 0 || grid % kXcds != 0 ? 1u : grid % nsub == 0 && nsub <= kMaxGroups ? nsub : kXcds;
   p->last_groups = a.groups;
   const uint32_t lines = adi_lines(p->seg), threads = adi_threads(p->seg);
   a.x_blk = (g.cy - 1 + lines - 1) / lines;

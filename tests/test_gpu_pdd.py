@@ -78,8 +78,8 @@ def _tail_parity(ctx, name, problem, grid, node_values, steps=None, groups=None)
         n_groups, die_local = pd.barrier()
         print(f"[case] {name}: {n_groups} barrier groups, {die_local} on one die", flush=True)
         if groups is not None:
-            # blocks are dealt to the dies round-robin, so each group of blocks b = g (mod 8) shares one
-            # die, and its barriers take the die-local fences
+            # blocks are dealt to the dies round-robin and every group is formed from the blocks of one
+            # die, so its barriers take the die-local fences
             assert (n_groups, die_local) == (groups, groups)
         ofield = opdd.adi_solve(og, problem, obd, n_steps=steps)
         err = float(np.abs(field - ofield).max())
@@ -134,17 +134,17 @@ def test_tail_odd_subdomain_width(ctx):
     _tail_parity(ctx, "tail_odd_width", _cubic(1), grid, vals)
 
 
-@pytest.mark.parametrize("px,py", [(4, 2), (4, 4)])
+@pytest.mark.parametrize("px,py", [(4, 2), (4, 4), (6, 4)])
 def test_tail_die_barrier_groups(ctx, px, py):
-    """8 and 16 small subdomains: the solver launches one block per subdomain and, with the subdomains
-    split evenly over the dies, synchronises each die's blocks among themselves (one and two blocks
-    per group) through the die's L2; the subdomains then never read each other's field values."""
+    """8, 16 and 24 small subdomains: the solver launches one block per subdomain and, with the subdomains
+    split evenly over the dies, synchronises each subdomain's blocks among themselves (one group per
+    subdomain) through their die's L2; the subdomains then never read each other's field values."""
     grid = _grid(x_lo=-6.0, x_hi=6.0, px=px, py=py, cx=16, cy=12, n_steps=30, ns_x=13, ns_y=9, nt=3, T=0.3)
     og = opdd.Grid(**grid)
     rng = np.random.default_rng(px * 10 + py)
     xy, t = opdd.node_points(og)
     vals = 0.5 * np.exp(-(xy[:, 0] ** 2 + xy[:, 1] ** 2) / 12.0) * (1 + t) + 0.02 * rng.normal(size=len(t))
-    _tail_parity(ctx, f"tail_groups_{px}x{py}", _cubic(3), grid, vals, groups=8)
+    _tail_parity(ctx, f"tail_groups_{px}x{py}", _cubic(3), grid, vals, groups=px * py)
 
 
 def test_tail_long_lines_32_unknown_segments(ctx):
