@@ -152,3 +152,16 @@ def test_euler_validation_host_only():
     one_d = brt.make_problem(inputs.problem(1, 1.0, [0.0, 1.0, -1.0], inputs.const(1.0),
                                             euler={"dt": 0.01, "drift_lin": (0.5, 1.0)}))
     assert L.brt_problem_check(ctypes.byref(one_d), ctypes.byref(mc)) == -1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libbrt.so not built")
+def test_pdd_queries_reject_null_arguments_host_only():
+    """The tail's query entry points check their arguments on the host before any device call."""
+    import paper_2402_06491_amd as brt
+
+    L = brt.lib()
+    g, d = ctypes.c_uint32(7), ctypes.c_uint32(7)
+    assert L.brt_pdd_get_barrier(None, ctypes.byref(g), ctypes.byref(d)) == -1
+    assert b"brt_pdd_get_barrier" in L.brt_last_error()
+    ms = (ctypes.c_double * 3)()
+    assert L.brt_pdd_get_timing(None, ms) == -1
