@@ -303,9 +303,11 @@ __device__ inline uint32_t xcc_id() {
 //
 // Fences.  With die_local set, every block of the group runs on one die, and all that the group's
 // blocks read after a barrier was written by the group itself: the die's L2 is then the coherence
-// point, so each wave waits until its stores are in L2 and the arriving side needs no L2 write-back,
-// and the leaving side invalidates only the CU's L1.  Otherwise device-scope fences (L2 write-back
-// and invalidation) order the phases.
+// point, so each wave waits until its stores are in L2 and the arriving side needs no L2 write-back.
+// The leaving side must still drop the CU's vector L1, which may hold lines this CU read before the
+// barrier and other CUs have rewritten since: the device-scope invalidate does that (and leaves the
+// L2's lines of device memory in place); the workgroup-scope form does not clear it.  Otherwise
+// device-scope fences (L2 write-back and invalidation) order the phases.
 __device__ bool group_barrier(uint32_t* cnt, uint32_t* abort_word, uint32_t members, uint32_t& gen, uint64_t spin_limit,
                               bool die_local, uint32_t* flag) {
   if (die_local) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -329,7 +331,7 @@ __device__ bool group_barrier(uint32_t* cnt, uint32_t* abort_word, uint32_t memb
       }
     }
     if (die_local)
-      asm volatile("buffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
+      asm volatile("buffer_inv sc1\n\ts_waitcnt vmcnt(0)" ::: "memory");
     else
       __threadfence();
     gen += 1;

@@ -147,6 +147,29 @@ def test_tail_die_barrier_groups(ctx, px, py):
     _tail_parity(ctx, f"tail_groups_{px}x{py}", _cubic(3), grid, vals, groups=px * py)
 
 
+def test_tail_die_groups_of_several_subdomains(ctx):
+    """8 x 5 subdomains of 16 x 224 cells: 280 x items over 144 blocks, which do not split evenly over
+    the 40 subdomains, so each die's 18 blocks form one barrier group for its 5 subdomains (two rounds
+    of x items, most blocks idle in the y phase)."""
+    grid = _grid(x_lo=-6.0, x_hi=6.0, y_lo=-6.0, y_hi=6.0, px=8, py=5, cx=16, cy=224, n_steps=12, ns_x=17, ns_y=57,
+                 nt=3, T=0.2)
+    og = opdd.Grid(**grid)
+    rng = np.random.default_rng(85)
+    xy, t = opdd.node_points(og)
+    vals = 0.5 * np.exp(-(xy[:, 0] ** 2 + xy[:, 1] ** 2) / 15.0) * (1 + 0.5 * t) + 0.02 * rng.normal(size=len(t))
+    _tail_parity(ctx, "tail_die_groups_8x5", _cubic(4), grid, vals, groups=8)
+
+
+def test_tail_long_lines_in_subdomain_groups(ctx):
+    """4 x 2 subdomains of 600 x 20 cells: the 32-unknown segment shape (16 lines per item) under one
+    barrier group per subdomain (152 blocks, 19 per subdomain)."""
+    grid = _grid(x_lo=-6.0, x_hi=6.0, px=4, py=2, cx=600, cy=20, n_steps=10, ns_x=65, ns_y=7, nt=3, T=0.2)
+    og = opdd.Grid(**grid)
+    xy, t = opdd.node_points(og)
+    vals = 0.4 * np.exp(-(xy[:, 0] ** 2 + 2.0 * xy[:, 1] ** 2) / 8.0) * (1.0 + t)
+    _tail_parity(ctx, "tail_long_lines_groups", _cubic(5), grid, vals, groups=8)
+
+
 def test_tail_long_lines_32_unknown_segments(ctx):
     """2 x 1 subdomains of 600 x 30 cells: lines of 599 unknowns take the solver's 32-unknown segments
     (the ragged last segment holds 23), and the short y lines leave most segments empty."""
