@@ -6,7 +6,8 @@ Workload (default): the 1-D Fisher equation u_t = u_xx + u - u^2 with the travel
 series order 12 with pruning, Pade [6/6], FP32 paths with FP64 clock, products and moments.
 
 One step = one run of the whole path (tree walk, per-bin moment reduction, FP64 finalize with Pade)
-over all 192 points, replayed as a HIP graph with the inputs already resident in HBM.
+over all 192 points, captured once into a HIP graph on a created stream and replayed, with the inputs
+already resident in HBM.
 
 Prints one JSON line on stdout (progress goes to stderr):
   value          trees per second over the timed steps (whole job)
@@ -289,9 +290,12 @@ def pdd_bench(ctx, trees_per_node, cpu_steps):
     node_u = torch.empty(len(t), dtype=torch.float64, device="cuda")
     field = torch.empty((pd.NY + 1, pd.NX + 1), dtype=torch.float64, device="cuda")
     times = []
-    for rep in range(3):  # the first run builds the nodes' plan and captures its graph
-        pd.run(wl["mc"], trees_per_node, node_u=node_u, field=field)
-        times.append(pd.timing())
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):  # a created stream: the nodes' plan is captured once and replayed
+        for rep in range(3):  # the first run builds the nodes' plan and captures its graph
+            pd.run(wl["mc"], trees_per_node, node_u=node_u, field=field)
+            times.append(pd.timing())
+    torch.cuda.synchronize()
     mc_ms, int_ms, solve_ms = (min(x[k] for x in times[1:]) for k in range(3))
     interior = g["px"] * g["py"] * (g["cx"] - 1) * (g["cy"] - 1)
     alg_bytes = 40.0 * interior * g["n_steps"]
@@ -409,9 +413,13 @@ def main():
     plan = brt.Plan(ctx, wl["problems"], wl["mc"], wl["x"], wl["t"], wl["n_trees"],
                     problem_id=wl.get("problem_id"), point_id=wl.get("point_id"))
     out = plan.outputs(records=True)
-    stream = torch.cuda.current_stream()
-    for i in range(args.warmup):
-        plan.execute(out)
+    # A created stream: brt_plan_execute captures the step (walk, reduce, finalize) into a HIP graph on
+    # its first run and replays it afterwards (torch's default stream is NULL, where it would enqueue
+    # kernel by kernel).
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        for i in range(args.warmup):
+            plan.execute(out, stream=stream)
     torch.cuda.synchronize()
     log(f"warmup done ({args.warmup} steps)")
 
@@ -420,21 +428,25 @@ def main():
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.steps):
-        starts[i].record(stream)
-        plan.execute(out)
-        ends[i].record(stream)
+    with torch.cuda.stream(stream):
+        for i in range(args.steps):
+            starts[i].record(stream)
+            plan.execute(out, stream=stream)
+            ends[i].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    graph = plan.graph_stats()
     lat = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
     total_trees = int(np.sum(wl["n_trees"]))
     value = total_trees * args.steps / wall
-    log(f"timed {args.steps} steps: {wall * 1e3 / args.steps:.3f} ms/step, {value:.4g} trees/s")
+    log(f"timed {args.steps} steps: {wall * 1e3 / args.steps:.3f} ms/step, {value:.4g} trees/s; graph {graph}")
 
-    # ---- walker kernel duration with HIP events on the launch stream ----
+    # ---- walker kernel duration with HIP events on the launch stream (timing mode enqueues the
+    # kernels one by one, with events between them) ----
     plan.set_timing(True)
-    for i in range(args.steps):
-        plan.execute(out)
+    with torch.cuda.stream(stream):
+        for i in range(args.steps):
+            plan.execute(out, stream=stream)
     (walk_ms, red_ms, fin_ms), runs = plan.get_timing()
     plan.set_timing(False)
     walk_s = walk_ms / runs / 1e3
@@ -463,6 +475,8 @@ def main():
                    "launch": tuned},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "what": "one step = all point queries of the workload"},
+        "graph": dict(graph, what="HIP graphs instantiated / graph launches / kernel-by-kernel runs of the "
+                                  "timed plan over warmup and timed steps"),
         "roofline": roofline,
         "pade": {"finite": int(np.isfinite(u).sum()), "pole_flagged": int(((flags & 1) != 0).sum())},
     }

@@ -105,7 +105,9 @@ typedef struct brt_problem {
    * > 0 when sigma_amp != 0; drift_lin[1] = 0 in 1-D.  BRT_SDE_EXACT (0) takes one exact Gaussian increment
    * per edge and needs drift_lin = 0 and sigma_amp = 0.  The domain-decomposition tail takes
    * BRT_SDE_EXACT only.  The cost grows with the number of steps per edge, which is capped at 2^20 (longer
-   * edges then take steps longer than sde_dt). */
+   * edges then take steps longer than sde_dt).  BRT_SDE_EULER needs FP64 paths (brt_mc.precision = 64):
+   * the step count of an edge is a ceiling of its duration, which an FP32 path would round differently
+   * at a step boundary; brt_problem_check returns BRT_E_ARG otherwise. */
   uint32_t sde;
   uint32_t sde_pad;
   double drift_lin[2];
@@ -223,9 +225,19 @@ int brt_plan_create(brt_ctx* ctx, uint32_t n_problems, const brt_problem* proble
                     const brt_points* points, brt_plan** out);
 
 /* Run a plan on `stream`: tree walk (persistent, work-stealing), per-bin moment reduction and the
- * FP64 finalize (coefficients, covariance, Pade, SE).  Asynchronous; the first run with a given
- * brt_out is captured into a HIP graph and later runs with the same brt_out replay it. */
+ * FP64 finalize (coefficients, covariance, Pade, SE).  Asynchronous.  On a created stream (not NULL)
+ * the first run with a given brt_out and stream is captured into a HIP graph (its kernels only: the
+ * counters are cleared by a kernel, not a memset) and later runs with the same brt_out and stream
+ * replay it; on the NULL stream, with graphs switched off (brt_plan_set_graph) or in timing mode the
+ * kernels are enqueued one by one.  Both ways give bit-identical results. */
 int brt_plan_execute(brt_plan* plan, const brt_out* out, void* stream);
+
+/* Graph use of a plan: enable = 0 makes brt_plan_execute enqueue kernel by kernel on every stream
+ * (default 1).  brt_plan_graph_stats reports (each pointer nullable) how many graphs the plan has
+ * instantiated, how many graph launches and how many kernel-by-kernel runs it has made (host
+ * counters; no synchronisation).  Errors: BRT_E_ARG (NULL plan). */
+int brt_plan_set_graph(brt_plan* plan, int enable);
+int brt_plan_graph_stats(const brt_plan* plan, uint64_t* captures, uint64_t* replays, uint64_t* direct);
 
 /* Totals of a plan (host): number of points, trees, bins B, work chunks. */
 int brt_plan_info(const brt_plan* plan, uint32_t* n_points, uint64_t* n_trees, uint32_t* n_bins,

@@ -118,6 +118,9 @@ _SIGS = [
     ("brt_plan_set_timing", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     ("brt_plan_get_timing", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_uint64)]),
+    ("brt_plan_set_graph", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    ("brt_plan_graph_stats", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64),
+                                            ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]),
     ("brt_plan_destroy", None, [ctypes.c_void_p]),
     ("brt_solve", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.POINTER(Problem), ctypes.POINTER(MC),
                                  ctypes.POINTER(Points), ctypes.POINTER(Out), ctypes.c_void_p]),
@@ -363,6 +366,15 @@ class Plan:
         """Enqueue the whole path on `stream` (torch's current stream by default)."""
         o = make_out(tensors)
         _check(lib().brt_plan_execute(self._h, ctypes.byref(o), _stream_handle(stream)))
+
+    def set_graph(self, enable: bool):
+        _check(lib().brt_plan_set_graph(self._h, int(bool(enable))))
+
+    def graph_stats(self) -> dict:
+        """Graphs instantiated, graph launches and kernel-by-kernel runs of this plan so far."""
+        c, r, d = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().brt_plan_graph_stats(self._h, ctypes.byref(c), ctypes.byref(r), ctypes.byref(d)))
+        return {"captures": c.value, "replays": r.value, "direct": d.value}
 
     def depth_exceeded(self) -> int:
         v = ctypes.c_uint64()

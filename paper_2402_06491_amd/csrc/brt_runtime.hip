@@ -194,6 +194,9 @@ struct brt_plan {
   brt_out graph_out{};
   hipStream_t graph_stream = nullptr;
   bool use_graph = true;
+  uint64_t graph_captures = 0;  // graphs instantiated
+  uint64_t graph_replays = 0;   // hipGraphLaunch calls (the first launch of a new graph included)
+  uint64_t direct_runs = 0;     // runs enqueued kernel by kernel
   // per-kernel timing mode: events before the walk and after walk, reduce and finalize
   bool timing = false;
   std::vector<std::array<hipEvent_t, 4>> ev_pool;
@@ -308,6 +311,10 @@ int brt_problem_check(const brt_problem* p, const brt_mc* mc) {
     return fail(BRT_E_ARG, "unknown sde %u", p->sde);
   }
   if (mc->precision != 32 && mc->precision != 64) return fail(BRT_E_ARG, "precision must be 32 or 64");
+  // An Euler edge takes ceil(s / h) steps; an FP32 path's edge duration s differs from its FP64 value by a
+  // rounding, which can change the step count (and the tree) at a step boundary: only FP64 paths step.
+  if (p->sde == BRT_SDE_EULER && mc->precision != 64)
+    return fail(BRT_E_ARG, "Euler-Maruyama paths (sde = BRT_SDE_EULER) need precision 64");
   if (!(mc->lambda > 0.0) || !is_fin(mc->lambda)) return fail(BRT_E_ARG, "lambda must be > 0");
   if (mc->max_order > 126) return fail(BRT_E_ARG, "max_order must be <= 126");
   if (mc->node_cap < 1 || mc->node_cap > kMaxNodeCap) return fail(BRT_E_ARG, "node_cap must be in [1, 2^21-1]");
@@ -625,9 +632,14 @@ int brt_plan_execute(brt_plan* p, const brt_out* o, void* stream) {
   if (o->struct_size != sizeof(brt_out)) return fail(BRT_E_ARG, "brt_out.struct_size mismatch");
   HIP_TRY(hipSetDevice(p->ctx->device));
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  if (!s || !p->use_graph || p->timing) return enqueue(p, o, s);
+  if (!s || !p->use_graph || p->timing) {
+    const int rc = enqueue(p, o, s);
+    if (!rc) p->direct_runs += 1;
+    return rc;
+  }
   if (p->graph && p->graph_stream == s && std::memcmp(&p->graph_out, o, sizeof(brt_out)) == 0) {
     HIP_TRY(hipGraphLaunch(p->graph, s));
+    p->graph_replays += 1;
     return BRT_OK;
   }
   if (p->graph) {
@@ -655,7 +667,23 @@ int brt_plan_execute(brt_plan* p, const brt_out* o, void* stream) {
   }
   p->graph_out = *o;
   p->graph_stream = s;
+  p->graph_captures += 1;
   HIP_TRY(hipGraphLaunch(p->graph, s));
+  p->graph_replays += 1;
+  return BRT_OK;
+}
+
+int brt_plan_set_graph(brt_plan* p, int enable) {
+  if (!p) return fail(BRT_E_ARG, "brt_plan_set_graph: NULL plan");
+  p->use_graph = enable != 0;
+  return BRT_OK;
+}
+
+int brt_plan_graph_stats(const brt_plan* p, uint64_t* captures, uint64_t* replays, uint64_t* direct) {
+  if (!p) return fail(BRT_E_ARG, "brt_plan_graph_stats: NULL plan");
+  if (captures) *captures = p->graph_captures;
+  if (replays) *replays = p->graph_replays;
+  if (direct) *direct = p->direct_runs;
   return BRT_OK;
 }
 

@@ -133,13 +133,17 @@ def test_euler_validation_host_only():
     from paper_2402_06491_amd import inputs
 
     L = brt.lib()
-    mc = brt.make_mc(inputs.mc_params())
+    mc = brt.make_mc(inputs.mc_params(precision=64))
+    mc32 = brt.make_mc(inputs.mc_params(precision=32))
 
-    def check(**kw):
+    def check(m=mc, **kw):
         d = inputs.problem(2, 1.0, [0.0, 1.0, -1.0], inputs.const(1.0), **kw)
-        return L.brt_problem_check(ctypes.byref(brt.make_problem(d)), ctypes.byref(mc))
+        return L.brt_problem_check(ctypes.byref(brt.make_problem(d)), ctypes.byref(m))
 
     assert check(euler={"dt": 0.01, "drift_lin": (0.5, -1.0), "sigma_amp": 0.3, "sigma_width": 1.0}) == 0
+    # FP32 paths do not step (the step count ceil(s/h) of an FP32 edge can differ from the FP64 one)
+    assert check(mc32, euler={"dt": 0.01, "drift_lin": (0.5, -1.0), "sigma_amp": 0.3, "sigma_width": 1.0}) == -1
+    assert "precision 64" in L.brt_last_error().decode()
     assert check(euler={"dt": 0.0}) == -1
     assert check(euler={"dt": 0.01, "sigma_amp": -1.0, "sigma_width": 1.0}) == -1
     assert check(euler={"dt": 0.01, "sigma_amp": 0.5, "sigma_width": 0.0}) == -1

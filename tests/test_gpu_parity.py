@@ -179,31 +179,52 @@ def test_edge_small_chunks_and_stack_depth(ctx):
     ctx.set_launch()
 
 
-def test_determinism_and_graph_replay(ctx):
-    """Two executes of one plan (graph replay) and a fresh plan give identical bits."""
+def test_graph_replay_matches_direct_enqueue_and_oracle(ctx):
+    """A plan run on a created stream is captured once into a HIP graph and replayed; its outputs are
+    bit-identical to the same plan enqueued kernel by kernel and to a fresh plan, and they match the
+    oracle tree by tree."""
     import torch
 
     from paper_2402_06491_amd import Plan
 
     wl = inputs.fisher(n_trees=5000, n_x=16)
-    _announce("determinism", wl)
+    _announce("graph_replay", wl)
+    stream = torch.cuda.Stream()
     plan = Plan(ctx, wl["problems"], wl["mc"], wl["x"], wl["t"], wl["n_trees"])
     out = plan.outputs()
     results = []
-    for _ in range(3):
-        plan.execute(out)
-        torch.cuda.synchronize()
-        results.append({k: v.cpu().numpy().copy() for k, v in out.items()})
-        for v in out.values():
-            v.zero_()
+    with torch.cuda.stream(stream):
+        for _ in range(3):
+            plan.execute(out, stream=stream)
+            stream.synchronize()
+            results.append({k: v.cpu().numpy().copy() for k, v in out.items()})
+            for v in out.values():
+                v.zero_()
+            stream.synchronize()
+    st = plan.graph_stats()
+    assert st == {"captures": 1, "replays": 3, "direct": 0}, st
+    # the same plan, kernel by kernel on the same stream
+    plan.set_graph(False)
+    with torch.cuda.stream(stream):
+        plan.execute(out, stream=stream)
+        stream.synchronize()
+    results.append({k: v.cpu().numpy().copy() for k, v in out.items()})
+    assert plan.graph_stats()["direct"] == 1
     plan2 = Plan(ctx, wl["problems"], wl["mc"], wl["x"], wl["t"], wl["n_trees"])
     out2 = plan2.outputs()
-    plan2.execute(out2)
+    plan2.execute(out2)  # torch's default stream (NULL): enqueued directly
     torch.cuda.synchronize()
+    assert plan2.graph_stats() == {"captures": 0, "replays": 0, "direct": 1}
     results.append({k: v.cpu().numpy() for k, v in out2.items()})
     for r in results[1:]:
         for k in r:
             np.testing.assert_array_equal(r[k], results[0][k], err_msg=k)
+    # and the replayed results are the oracle's trees
+    pi, ti, ri = P.tree_items(wl)
+    orc = P.oracle_trees(wl, pi, ti)
+    P.compare_trees(results[2], ri, orc, P.FP32_TOL, pi)
+    plan.close()
+    plan2.close()
 
 
 @pytest.mark.parametrize("prec", [32, 64])
