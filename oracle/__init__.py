@@ -17,8 +17,10 @@ Pieces:
     the number of splits Ne (the partial contributions whose sum is the series);
   * :func:`coefficients`: a_n = e^{mu t} S1_n / N and their covariance
     (the sample mean of the multiplicative functional, Sec. 2.4);
-  * :func:`pade`: the [L/M] Pade approximant of the series evaluated at z = 1
-    (Sec. 2.1 end, Sec. 2.4), plain dense solve of the M x M linear system;
+  * :func:`pade_value`: the [L/M] Pade approximant of the series evaluated at z = 1
+    (Sec. 2.1 end, Sec. 2.4), with the degrees chosen by an SVD rank test of the
+    denominator's linear conditions (:func:`pade_order`, reading R13), plus the
+    neighbouring orders and the poles (:func:`pade_summary`);
   * :func:`solve`: everything above for a set of points.
 
 Parity pins for all of this live in ``tests/test_oracle_*.py``.
@@ -339,60 +341,161 @@ def coefficients(mom: dict, mu: float, t: float):
 # ---------------------------------------------------------------------------
 # Pade approximant (Sec. 2.1 end; robustness discussion of Sec. 2.4)
 # ---------------------------------------------------------------------------
-def pade_coeffs(a, L: int, M: int):
-    """Numerator p_0..p_L and denominator q_0..q_M (q_0 = 1) of the [L/M] approximant.
+# Relative rank tolerance of the order selection (reading R13): a singular value of the linear
+# conditions on the denominator counts as zero when it is at most PADE_TOL times the 2-norm of the
+# coefficients a_0..a_{L+M}.
+PADE_TOL = 1e-12
+# A pole of the approximant within POLE_DIST of the segment [0, 1] (the path along which the series is
+# continued to z = 1) is flagged: the value there is then unreliable.
+POLE_DIST = 0.5
+# A value whose sensitivity sum_k |du/da_k| |a_k| exceeds SENSITIVE_KAPPA is flagged: a relative change of
+# 1e-5 in every coefficient (the accuracy of coefficients summed from FP32 paths) can move it by 1e-3.
+SENSITIVE_KAPPA = 100.0
 
-    Defined by P(z) - Q(z) F(z) = O(z^{L+M+1}): for k = L+1..L+M,
-    sum_{j=0}^{M} q_j a_{k-j} = 0 (a_i = 0 for i < 0); then
-    p_i = sum_{j=0}^{min(i,M)} q_j a_{i-j}.  The M x M system is solved by LU with
-    partial pivoting; it counts as singular (numpy.linalg.LinAlgError) when an
-    entry is not finite or the smallest pivot is below 1e-13 times the largest.
-    """
-    from scipy.linalg import lu_factor, lu_solve
 
+def _coef(a, i):
+    return float(a[i]) if 0 <= i < len(a) else 0.0
+
+
+def denominator_conditions(a, L: int, M: int):
+    """The M x (M+1) matrix C with C[i, j] = a_{L+1+i-j} (i = 0..M-1, j = 0..M; a_k = 0 for k < 0).
+
+    The [L/M] approximant P/Q of F(z) = sum a_n z^n satisfies Q F - P = O(z^{L+M+1}); the coefficients of
+    z^{L+1}..z^{L+M} of Q F involve q alone, so C q = 0 for q = (q_0..q_M)."""
+    return np.array([[_coef(a, L + 1 + i - j) for j in range(M + 1)] for i in range(M)], dtype=np.float64)
+
+
+def pade_order(a, L: int, M: int, tol: float = PADE_TOL):
+    """The degrees actually used for a requested [L/M] (reading R13).
+
+    After Gonnet, Guettel and Trefethen, "Robust Pade approximation via SVD" (SIAM Review 55, 2013):
+    with s = ||a_0..a_{L+M}||_2, count rho = the singular values of C (denominator_conditions) above
+    tol * s.  If rho < M the conditions have a null space of dimension M + 1 - rho > 1 (the data come from
+    a rational of lower degree, or carry no information at that order): lower both degrees by M - rho
+    (L stays >= 0) and look again.  Once C has full rank its null vector is unique up to scale; if the
+    square block C[:, 1:] is itself rank deficient (smallest singular value at most tol * s) that vector
+    has q_0 = 0 and no approximant with Q(0) = 1 exists: take [L+1/M-1], the next entry on the same
+    antidiagonal of the Pade table.  All-zero data give [0/0].  Returns (L, M, margin), where margin is
+    the smallest ratio, over every rank decision taken, of the deciding singular value to the threshold
+    tol * s or its reciprocal (how far the decisions are from flipping; inf when none was taken)."""
     a = np.asarray(a, dtype=np.float64)
-    coef = lambda i: a[i] if i >= 0 else 0.0  # noqa: E731
+    s = float(np.linalg.norm(a[: L + M + 1]))
+    if s == 0.0 or not np.isfinite(s):
+        return 0, 0, math.inf
+    thr = tol * s
+    margin = math.inf
+
+    def note(sv):
+        nonlocal margin
+        if sv > 0.0:
+            margin = min(margin, sv / thr if sv > thr else thr / sv)
+
+    while M > 0:
+        sv = np.linalg.svd(denominator_conditions(a, L, M), compute_uv=False)
+        rho = int(np.sum(sv > thr))
+        if rho < M:
+            note(sv[rho])  # the largest singular value counted as zero
+            if rho > 0:
+                note(sv[rho - 1])
+            L, M = max(L - (M - rho), 0), rho
+            continue
+        note(sv[M - 1])
+        svT = np.linalg.svd(denominator_conditions(a, L, M)[:, 1:], compute_uv=False)
+        note(svT[-1])
+        if svT[-1] <= thr:
+            L, M = L + 1, M - 1
+            continue
+        break
+    return L, M, margin
+
+
+def pade_coeffs(a, L: int, M: int):
+    """Numerator p_0..p_L and denominator q_0..q_M (q_0 = 1) of the [L/M] approximant of sum a_n z^n.
+
+    Defined by Q(z) F(z) - P(z) = O(z^{L+M+1}): C q = 0 with q_0 = 1 (denominator_conditions), i.e. the
+    M x M system C[:, 1:] (q_1..q_M) = -C[:, 0], solved by numpy's LU; then p_i = sum_{j<=min(i,M)} q_j a_{i-j}.
+    No degree selection here: pade_order chooses (L, M)."""
+    a = np.asarray(a, dtype=np.float64)
     q = np.ones(M + 1)
     if M > 0:
-        T = np.array([[coef(L + i - j) for j in range(1, M + 1)] for i in range(1, M + 1)])
-        rhs = -np.array([coef(L + i) for i in range(1, M + 1)])
-        if not (np.all(np.isfinite(T)) and np.all(np.isfinite(rhs))):
-            raise np.linalg.LinAlgError("non-finite Pade system")
-        piv = np.abs(np.diag(lu_factor(T, check_finite=False)[0])) if np.any(T) else np.zeros(M)
-        if piv.max() == 0.0 or piv.min() <= 1e-13 * piv.max():
-            raise np.linalg.LinAlgError("singular Pade system")
-        q[1:] = lu_solve(lu_factor(T, check_finite=False), rhs, check_finite=False)
-    p = np.array([sum(q[j] * coef(i - j) for j in range(0, min(i, M) + 1)) for i in range(L + 1)])
+        C = denominator_conditions(a, L, M)
+        q[1:] = np.linalg.solve(C[:, 1:], -C[:, 0])
+    p = np.array([sum(q[j] * _coef(a, i - j) for j in range(0, min(i, M) + 1)) for i in range(L + 1)])
     return p, q
 
 
-def pade_value(a, L: int, M: int, z: float = 1.0):
-    """[L/M](z); if the system is singular, lower M by one and raise L by one (same order)."""
-    while True:
-        try:
-            p, q = pade_coeffs(a, L, M)
-            break
-        except np.linalg.LinAlgError:
-            if M == 0:
-                raise
-            L, M = L + 1, M - 1
+def pade_value(a, L: int, M: int, z: float = 1.0, tol: float = PADE_TOL):
+    """The approximant at z for a requested [L/M]: degrees from pade_order, then P(z)/Q(z).
+
+    Returns (value, (L', M') used, q)."""
+    Lu, Mu, _ = pade_order(a, L, M, tol)
+    p, q = pade_coeffs(a, Lu, Mu)
     num = sum(p[i] * z ** i for i in range(len(p)))
     den = sum(q[j] * z ** j for j in range(len(q)))
-    return num / den, (L, M), q
+    return num / den, (Lu, Mu), q
 
 
-def pade_se(a, cov, L: int, M: int):
-    """Delta-method standard error of [L/M](1) with central-difference gradient."""
+def pade_neighbours(a, L: int, M: int, tol: float = PADE_TOL):
+    """The [L-1/M] and [L/M-1] values at z = 1 (each with its own degree selection; NaN where the order
+    does not exist).  Sec. 2.4 judges an approximant by comparing it across numbers of coefficients: a
+    value that moves a lot when one coefficient is dropped is not yet converged."""
+    lo = pade_value(a, L - 1, M, tol=tol)[0] if L >= 1 else float("nan")
+    mo = pade_value(a, L, M - 1, tol=tol)[0] if M >= 1 else float("nan")
+    return lo, mo
+
+
+def pole_distance(q):
+    """Distance from the segment [0, 1] to the nearest zero of Q(z) = sum q_j z^j (a pole of the
+    approximant; inf if Q is constant), the zeros from numpy.roots (eigenvalues of the companion matrix)."""
+    q = np.trim_zeros(np.asarray(q, dtype=np.float64), "b")
+    if len(q) <= 1:
+        return math.inf
+    r = np.roots(q[::-1])
+    return float(min(abs(z - min(max(z.real, 0.0), 1.0)) for z in r)) if len(r) else math.inf
+
+
+def pade_gradient(a, L: int, M: int, tol: float = PADE_TOL):
+    """Gradient of [L'/M'](1) with respect to a_0..a_{L'+M'} at the degrees (L', M') that pade_order
+    chooses for a, by central differences (step 1e-6 |a_k|, or 1e-12 for a zero coefficient); zero for
+    the coefficients the approximant does not use."""
     a = np.asarray(a, dtype=np.float64)
-    n = L + M + 1
+    Lu, Mu, _ = pade_order(a, L, M, tol)
+
+    def val(b):
+        p, q = pade_coeffs(b, Lu, Mu)
+        return sum(p) / sum(q)
+
     grad = np.zeros(len(a))
-    for k in range(n):
-        h = 1e-6 * max(abs(a[k]), 1e-300) if a[k] != 0 else 1e-12
+    for k in range(min(len(a), Lu + Mu + 1)):
+        h = 1e-6 * abs(a[k]) if a[k] != 0 else 1e-12
         ap = a.copy(); ap[k] += h
         am = a.copy(); am[k] -= h
-        grad[k] = (pade_value(ap, L, M)[0] - pade_value(am, L, M)[0]) / (2 * h)
-    var = float(grad @ cov @ grad)
+        grad[k] = (val(ap) - val(am)) / (2 * h)
+    return grad
+
+
+def pade_se(a, cov, L: int, M: int, tol: float = PADE_TOL):
+    """Delta-method standard error of the approximant at z = 1: sqrt(g' Cov g) with g = pade_gradient."""
+    g = pade_gradient(a, L, M, tol)
+    var = float(g @ cov @ g)
     return math.sqrt(max(var, 0.0))
+
+
+def pade_summary(a, cov, L: int, M: int, tol: float = PADE_TOL):
+    """Everything the finalize reports about the approximant of one point: value, degrees used and the
+    margin of their selection, SE, the two neighbour values, the sensitivity kappa = sum_k |du/da_k| |a_k|,
+    the pole distance from [0, 1] and the flags (pole, sensitive, lowered)."""
+    a = np.asarray(a, dtype=np.float64)
+    val, used, q = pade_value(a, L, M, tol=tol)
+    margin = pade_order(a, L, M, tol)[2]
+    lo, mo = pade_neighbours(a, L, M, tol)
+    g = pade_gradient(a, L, M, tol)
+    kappa = float(np.abs(g) @ np.abs(a))
+    dist = pole_distance(q)
+    se = math.sqrt(max(float(g @ cov @ g), 0.0)) if cov is not None else float("nan")
+    return {"pade": val, "pade_order": used, "pade_q": q, "order_margin": margin, "pade_se": se,
+            "pade_lo": lo, "pade_mo": mo, "kappa": kappa, "pole_distance": dist,
+            "pole": dist <= POLE_DIST, "sensitive": kappa > SENSITIVE_KAPPA, "lowered": used != (L, M)}
 
 
 def solve(problem: dict, mc: dict, x, t, n_trees, point_ids=None, nthreads: int = 0):
@@ -419,11 +522,10 @@ def solve(problem: dict, mc: dict, x, t, n_trees, point_ids=None, nthreads: int 
         mom = moments(rec, mc)
         a, cov = coefficients(mom, nz.mu, float(t[i]))
         series = a[: no + 1]
-        try:
-            val, used, q = pade_value(series, L, M)
-            se = pade_se(series, cov[: no + 1, : no + 1], L, M)
-        except np.linalg.LinAlgError:
-            val, used, q, se = float("nan"), (L, 0), np.ones(1), float("nan")
-        out.append({"moments": mom, "a": a, "cov": cov, "pade": val, "pade_order": used, "pade_q": q,
-                    "pade_se": se, "partial_sum": math.fsum(a.tolist()), "records": rec})
+        if np.all(np.isfinite(series)):
+            pd = pade_summary(series, cov[: no + 1, : no + 1], L, M)
+        else:
+            pd = {"pade": float("nan"), "pade_order": None, "pade_q": np.ones(1), "pade_se": float("nan")}
+        out.append({"moments": mom, "a": a, "cov": cov, **pd, "partial_sum": math.fsum(a.tolist()),
+                    "records": rec})
     return out
