@@ -16,6 +16,8 @@ Prints one JSON line on stdout (progress goes to stderr):
                  (HIP events on the launch stream), against the FP32 vector peak expressed in ops
   cpu_baseline   the CPU oracle timed on a bounded sample of the same trees, on the host's cores
   parity         the sampled trees compared with the oracle (shape bit-exact, value within tolerance)
+  pade_parity    when the sample is the whole workload: the Pade values against the oracle's, point by
+                 point, and both against the exact travelling wave
 """
 from __future__ import annotations
 
@@ -73,6 +75,8 @@ def describe(wl):
 
 
 def cpu_threads():
+    """Worker threads for the CPU oracle: the host cores this process may use, at most 16 (the CPU share
+    of one GPU on the benchmark machines)."""
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:
@@ -80,8 +84,20 @@ def cpu_threads():
     return max(1, min(n, 16))
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(wl, gpu_meta, gpu_f, target_s):
-    """Time the oracle on the first S trees of every point; compare those trees with the GPU records."""
+    """Time the oracle on the first S trees of every point (a calibration run as warm-up, then the median
+    of 3 timed runs); compare the trees of the first timed run with the GPU records.  Returns the
+    baseline, the tree parity and the oracle's records (for the Pade parity)."""
     import oracle
 
     oracle.build(force=False)
@@ -99,11 +115,20 @@ def cpu_baseline(wl, gpu_meta, gpu_f, target_s):
             recs.append(r)
         return time.perf_counter() - t0, recs
 
-    dt, _ = run(2000)  # calibration
+    dt, _ = run(2000)  # calibration and warm-up
     rate = npts * 2000 / max(dt, 1e-6)
     S = int(min(n_trees.min(), max(1000, rate * target_s / npts)))
-    log(f"cpu baseline: {threads} threads, calibrated {rate:.3g} trees/s, sample {S} trees x {npts} points")
-    dt, recs = run(S)
+    log(f"cpu baseline: {threads} threads of {os.cpu_count()} ({cpu_model()}), calibrated {rate:.3g} trees/s, "
+        f"sample {S} trees x {npts} points, median of 3")
+    times = []
+    recs = None
+    for rep in range(3):
+        dt, r = run(S)
+        times.append(dt)
+        if rep == 0:
+            recs = r
+        del r
+    dt = float(np.median(times))
     # parity of the sampled trees: shapes bit-exact; values within tol |F| + 1e-6 max_point |F|
     tol = 2e-4 if wl["mc"]["precision"] == 32 else 1e-12
     max_rel, mism, checked, worst_ratio, worst = 0.0, 0, 0, 0.0, []
@@ -126,11 +151,60 @@ def cpu_baseline(wl, gpu_meta, gpu_f, target_s):
         if big.any():
             max_rel = max(max_rel, float((diff[big] / absF[big]).max()))
         checked += S
-    return ({"value": npts * S / dt, "unit": "trees/s", "cores": threads, "kind": "oracle",
-             "sample": f"first {S} trees of each of the {npts} points ({npts * S} trees, {dt:.1f} s)"},
+    return ({"value": npts * S / dt, "unit": "trees/s", "cores": threads, "nproc": os.cpu_count(),
+             "cpu_model": cpu_model(), "runs_s": times, "kind": "oracle",
+             "sample": f"first {S} trees of each of the {npts} points ({npts * S} trees, median {dt:.1f} s of 3 "
+                       f"runs after a warm-up)"},
             {"trees_checked": checked, "shape_mismatches": mism, "max_rel_tree_diff_big": max_rel,
              "tree_tol": tol, "worst_err_over_bound": worst_ratio,
-             "worst_tree": dict(zip(["point", "tree", "ne", "nodes", "F_gpu", "F_oracle"], worst))})
+             "worst_tree": dict(zip(["point", "tree", "ne", "nodes", "F_gpu", "F_oracle"], worst))},
+            recs if S == int(n_trees.min()) == int(n_trees.max()) else None)
+
+
+def pade_parity(wl, recs, gpu):
+    """The headline's Pade values against the oracle's, from the oracle's walk of every tree of every
+    point: the oracle's moments (exact sums), coefficients and Pade summary per point, then the same
+    point-by-point rule as the parity tests (a point is exempt from the 1e-3 bound only when both sides
+    flag it POLE or SENSITIVE), and the error of both against the exact travelling wave per t."""
+    import oracle
+    from paper_2402_06491_amd import inputs
+
+    mc = wl["mc"]
+    L, M, no = int(mc["pade_L"]), int(mc["pade_M"]), int(mc["max_order"])
+    nz = oracle.normalize(wl["problems"][0], mc)
+    rows = []
+    for p, rec in enumerate(recs):
+        mom = oracle.moments(rec, mc)
+        a, cov = oracle.coefficients(mom, nz.mu, float(wl["t"][p]))
+        summ = oracle.pade_summary(a[: no + 1], cov[: no + 1, : no + 1], L, M)
+        fl = int(gpu["flags"][p])
+        dev_flag = bool(fl & 33)
+        orc_flag = summ["pole"] or summ["sensitive"]
+        rows.append({"p": p, "t": float(wl["t"][p]), "du": abs(float(gpu["u"][p]) - summ["pade"]),
+                     "both": dev_flag and orc_flag, "either": dev_flag or orc_flag,
+                     "same_order": (int(gpu["pade_diag"][p][0]), int(gpu["pade_diag"][p][1])) == summ["pade_order"],
+                     "u_gpu": float(gpu["u"][p]), "u_orc": summ["pade"],
+                     "exact": float(inputs.fisher_exact(float(wl["x"][p][0]), float(wl["t"][p])))
+                     if wl["name"] == "fisher_1d" else float("nan")})
+    unf = [r for r in rows if not r["both"]]
+    out = {"points": len(rows), "flagged_both": int(sum(r["both"] for r in rows)),
+           "flagged_either": int(sum(r["either"] for r in rows)),
+           "unflagged_max_abs_du": float(max((r["du"] for r in unf), default=0.0)),
+           "unflagged_within_1e-3": int(sum(r["du"] <= 1e-3 for r in unf)), "unflagged": len(unf),
+           "degree_mismatches": int(sum(not r["same_order"] for r in rows)),
+           "rule": "|u_gpu - u_oracle| <= 1e-3 at every point unless the device and the oracle both flag it "
+                   "(pole within 0.5 of [0, 1], or kappa = sum |du/da_k||a_k| > 100)"}
+    if wl["name"] == "fisher_1d":
+        per_t = {}
+        for t in sorted(set(r["t"] for r in rows)):
+            sel = [r for r in rows if r["t"] == t]
+            ok = [r for r in sel if not r["either"]]
+            per_t[str(t)] = {"points": len(sel), "unflagged": len(ok),
+                             "gpu_max_abs_err_vs_exact_unflagged": float(max((abs(r["u_gpu"] - r["exact"]) for r in ok), default=float("nan"))),
+                             "gpu_median_abs_err_vs_exact_unflagged": float(np.median([abs(r["u_gpu"] - r["exact"]) for r in ok])) if ok else None,
+                             "oracle_median_abs_err_vs_exact_unflagged": float(np.median([abs(r["u_orc"] - r["exact"]) for r in ok])) if ok else None}
+        out["vs_exact_wave"] = per_t
+    return out
 
 
 def pmc_traffic(kernel_src_sha, launches_trees=None, name="walk_fisher_pmc.json"):
@@ -372,7 +446,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="fisher")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="upper bound of one timed oracle run (the whole workload when it fits)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=2.0,
                     help="length of the served request stream replayed after the throughput steps (0: skip)")
@@ -478,18 +553,27 @@ def main():
         "graph": dict(graph, what="HIP graphs instantiated / graph launches / kernel-by-kernel runs of the "
                                   "timed plan over warmup and timed steps"),
         "roofline": roofline,
-        "pade": {"finite": int(np.isfinite(u).sum()), "pole_flagged": int(((flags & 1) != 0).sum())},
+        "pade": {"finite": int(np.isfinite(u).sum()), "pole_flagged": int(((flags & 1) != 0).sum()),
+                 "sensitive_flagged": int(((flags & 32) != 0).sum()),
+                 "lowered": int(((flags & 2) != 0).sum())},
     }
     if not args.no_cpu_baseline:
         meta = out["tree_meta"].cpu().numpy()
         f = out["tree_f"].cpu().numpy()
-        cb, parity = cpu_baseline(wl, meta, f, args.cpu_seconds)
+        cb, parity, recs = cpu_baseline(wl, meta, f, args.cpu_seconds)
+        del meta, f
         result["cpu_baseline"] = cb
         result["parity"] = parity
         log(f"cpu baseline {cb['value']:.4g} trees/s on {cb['cores']} threads; parity {parity}")
+        if recs is not None:
+            gpu = {k: out[k].cpu().numpy() for k in ("u", "flags", "pade_diag")}
+            t_pp = time.perf_counter()
+            result["pade_parity"] = pade_parity(wl, recs, gpu)
+            log(f"pade parity ({time.perf_counter() - t_pp:.1f} s): {result['pade_parity']}")
+        del recs
     se_a = out["se"].cpu().numpy()
     plan.close()
-    del out
+    del out, starts, ends
     if not args.no_strategy_b:
         result["strategy_b"] = strategy_compare(ctx, wl, wall * 1e3 / args.steps, se_a)
     if args.serve_seconds > 0:
@@ -505,7 +589,11 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    # Explicit teardown while the HIP runtime (and a profiler attached to it) is still up: the library's
+    # objects, then torch's cached device memory; nothing GPU-side is left for exit-time destructors.
     ctx.close()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     print(json.dumps(result), flush=True)
 
 

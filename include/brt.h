@@ -158,12 +158,36 @@ typedef struct brt_points {
                                  point's sample with fresh trees); NULL = 0 */
 } brt_points;
 
+/* The Pade step (end of Sec. 2.1; Sec. 2.4 on spurious poles and on judging an approximant across
+ * numbers of coefficients).  For a requested [L/M] the degrees actually used come from the singular values
+ * of the M x (M+1) linear conditions C[i][j] = a_{L+1+i-j} (i < M, j <= M; a_k = 0 for k < 0) that the
+ * denominator q satisfies, C q = 0 (robust Pade of Gonnet, Guettel and Trefethen, SIAM Review 2013):
+ * with s = ||a_0..a_{L+M}||_2, a singular value counts as zero when it is at most 1e-12 s; rank rho < M
+ * lowers both degrees by M - rho and the test repeats; a full-rank C whose square block C[:, 1:] is rank
+ * deficient (no denominator with q_0 = 1) moves to [L+1/M-1]; all-zero coefficients give [0/0].  q_0 = 1
+ * and the square system (LU with partial pivoting) then give q, and u = P(1)/Q(1). */
+
 /* Per-point flags (brt_out.flags). */
-#define BRT_FLAG_POLE 1u       /* the Pade denominator changes sign on [0,1] or vanishes at 1 */
-#define BRT_FLAG_LOWERED 2u    /* singular Pade system: the denominator degree was lowered */
+#define BRT_FLAG_POLE 1u       /* the approximant has a pole within 0.5 of the segment [0, 1] (counted by the
+                                  argument principle along that contour): its value at 1 is unreliable */
+#define BRT_FLAG_LOWERED 2u    /* the degrees used are below the requested [L/M] (rank test above) */
 #define BRT_FLAG_OVERFLOW 4u   /* some trees were pruned */
 #define BRT_FLAG_CAPPED 8u     /* some trees hit the node cap */
 #define BRT_FLAG_DEPTH 16u     /* some trees exceeded the stack depth (their values are missing) */
+#define BRT_FLAG_SENSITIVE 32u /* kappa = sum_k |du/da_k| |a_k| > 100: a relative error of 1e-5 in every
+                                  coefficient (the accuracy of sums of FP32 paths) can move u by 1e-3 */
+
+/* Columns of brt_out.pade_diag (doubles, BRT_PADE_DIAG per point). */
+#define BRT_PADE_DIAG 6
+#define BRT_DIAG_L 0           /* numerator degree used */
+#define BRT_DIAG_M 1           /* denominator degree used */
+#define BRT_DIAG_U_LM1 2       /* value of [L-1/M] (its own degree selection; NaN when L = 0) */
+#define BRT_DIAG_U_MM1 3       /* value of [L/M-1] (NaN when M = 0) */
+#define BRT_DIAG_KAPPA 4       /* sensitivity sum_k |du/da_k| |a_k| (exact gradient of the approximant) */
+#define BRT_DIAG_MARGIN 5      /* how far the degree selection was from flipping: the smallest ratio of a
+                                  deciding singular value to the threshold 1e-12 s, or its reciprocal
+                                  (inf when no decision was needed); a lower bound of it when the full rank
+                                  was settled by sigma_min(C[:, 1:]) >= 1/||C[:, 1:]^-1||_F */
 
 /* Outputs.  All device pointers, caller-owned, each may be NULL.  B = max_order + 2. */
 typedef struct brt_out {
@@ -183,6 +207,7 @@ typedef struct brt_out {
                          precision paths (vertex weights reach e^{32} and overflow FP32). */
   uint32_t* tree_meta;/* total trees: bits 0-7 min(Ne,255), bit 8 overflow, bit 9 capped,
                          bit 10 depth exceeded, bits 11-31 nodes visited */
+  double* pade_diag;  /* n*BRT_PADE_DIAG: degrees used, neighbour values, sensitivity, selection margin */
 } brt_out;
 
 typedef struct brt_ctx brt_ctx;

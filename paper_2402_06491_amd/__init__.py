@@ -19,7 +19,8 @@ BRT_OK = 0
 ERRORS = {-1: "BRT_E_ARG", -2: "BRT_E_DEVICE", -3: "BRT_E_NOMEM", -4: "BRT_E_BUSY", -5: "BRT_E_RANGE",
           -6: "BRT_E_STATE"}
 U0_KINDS = {"const": 0, "logistic": 1, "gauss_sum": 2, "cos2_bump": 3}
-FLAG_POLE, FLAG_LOWERED, FLAG_OVERFLOW, FLAG_CAPPED, FLAG_DEPTH = 1, 2, 4, 8, 16
+FLAG_POLE, FLAG_LOWERED, FLAG_OVERFLOW, FLAG_CAPPED, FLAG_DEPTH, FLAG_SENSITIVE = 1, 2, 4, 8, 16, 32
+PADE_DIAG = 6  # columns of the pade_diag output: L used, M used, [L-1/M], [L/M-1], kappa, selection margin
 META_OVERFLOW, META_CAPPED, META_DEPTH, META_NODES_SHIFT = 1 << 8, 1 << 9, 1 << 10, 11
 
 
@@ -55,7 +56,8 @@ class Points(ctypes.Structure):
 class Out(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32)] + [
         (name, ctypes.c_void_p) for name in
-        ("u", "se", "psum", "coef", "coef_var", "hist", "s1", "s2", "nodes", "flags", "tree_f", "tree_meta")]
+        ("u", "se", "psum", "coef", "coef_var", "hist", "s1", "s2", "nodes", "flags", "tree_f", "tree_meta",
+         "pade_diag")]
 
 
 class Launch(ctypes.Structure):
@@ -311,6 +313,7 @@ def alloc_outputs(n_points, n_bins, total_trees, precision, records=True, device
         "s2": torch.empty((n_points, n_bins), dtype=torch.float64, device=device),
         "nodes": torch.empty(n_points, dtype=torch.int64, device=device),
         "flags": torch.empty(n_points, dtype=torch.int32, device=device),
+        "pade_diag": torch.empty((n_points, PADE_DIAG), dtype=torch.float64, device=device),
     }
     if records:
         o["tree_f"] = torch.empty(max(total_trees, 1), dtype=torch.float64, device=device)

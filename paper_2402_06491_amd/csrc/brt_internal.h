@@ -137,6 +137,7 @@ struct FinalizeArgs {
   double* s2;
   unsigned long long* nodes;
   uint32_t* flags;
+  double* pade_diag;  // [n][BRT_PADE_DIAG] (nullable)
 };
 
 // Strategy A normalisation of one problem (brt_runtime.hip).

@@ -5,9 +5,13 @@
 //                   fixed-order wave reduction, so the result does not depend on scheduling.
 //  finalize_kernel  one wave per point, FP64: Neumaier-compensated sums over the point's segments,
 //                   coefficients a_n = e^{mu t} S1_n / N (the sample mean of the functional, Sec. 2.4)
-//                   and their variances, the [L/M] Pade approximant at z = 1 (Sec. 2.1 end) by LU with
-//                   partial pivoting, and its delta-method standard error from the exact gradient of
-//                   the approximant with respect to the coefficients.
+//                   and their variances, the [L/M] Pade approximant at z = 1 (Sec. 2.1 end) with its
+//                   degrees chosen by the singular values of the denominator's linear conditions (one-sided
+//                   Jacobi) and its denominator by LU with partial pivoting, its delta-method standard error
+//                   and sensitivity from the exact gradient of the approximant with respect to the
+//                   coefficients, the neighbouring orders [L-1/M] and [L/M-1] (Sec. 2.4 judges an
+//                   approximant across numbers of coefficients), and a count of its poles near [0, 1]
+//                   by the argument principle.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -123,12 +127,61 @@ __global__ __launch_bounds__(64) void reduce_kernel(ReduceArgs a) {
 
 constexpr int kMaxBins = 128;  // B = max_order + 2 <= 128
 constexpr int kMaxPadeM = 16;
+// Degree selection of the approximant: a singular value of the denominator's linear conditions counts as
+// zero when it is at most kPadeTol times the 2-norm of the coefficients a_0..a_{L+M}.
+constexpr double kPadeTol = 1e-12;
+// A zero of the denominator within kPoleDist of the segment [0, 1] is reported (BRT_FLAG_POLE), and a value
+// whose sensitivity sum_k |du/da_k| |a_k| exceeds kSensitive (BRT_FLAG_SENSITIVE).
+constexpr double kPoleDist = 0.5;
+constexpr double kSensitive = 100.0;
+constexpr int kWindingSamples = 32;  // samples of the pole-test contour per lane (2048 per point)
 
-// LU factorisation with partial pivoting, in place (row-major M x M, multipliers below the
-// diagonal), perm[i] = original row now at position i.  Singular when an entry is not finite or the
-// smallest pivot magnitude is at most 1e-13 times the largest.
-__device__ bool lu_factor(double* T, int M, int* perm) {
-  double pmax = 0.0, pmin = 1e308;
+__host__ __device__ __forceinline__ double coef_at(const double* a, int k) { return k >= 0 ? a[k] : 0.0; }
+
+// Singular values of the n_vec x len matrix whose rows are stored in V (row i at V[i * len]), by one-sided
+// Jacobi rotations of those rows (Hestenes): rotate pairs of rows until every pair is orthogonal; the row
+// norms are then the singular values (n_vec <= len).  V is overwritten; sv[0..n_vec) comes out descending.
+__host__ __device__ void jacobi_singular_values(double* V, int n_vec, int len, double* sv) {
+  for (int sweep = 0; sweep < 64; ++sweep) {
+    bool rotated = false;
+    for (int i = 0; i < n_vec - 1; ++i)
+      for (int j = i + 1; j < n_vec; ++j) {
+        double al = 0.0, be = 0.0, ga = 0.0;
+        for (int k = 0; k < len; ++k) {
+          const double x = V[i * len + k], y = V[j * len + k];
+          al += x * x;
+          be += y * y;
+          ga += x * y;
+        }
+        if (ga == 0.0 || fabs(ga) <= 1e-15 * sqrt(al * be)) continue;
+        rotated = true;
+        const double zeta = (be - al) / (2.0 * ga);
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+        for (int k = 0; k < len; ++k) {
+          const double x = V[i * len + k], y = V[j * len + k];
+          V[i * len + k] = c * x - s * y;
+          V[j * len + k] = s * x + c * y;
+        }
+      }
+    if (!rotated) break;
+  }
+  for (int i = 0; i < n_vec; ++i) {
+    double n2 = 0.0;
+    for (int k = 0; k < len; ++k) n2 += V[i * len + k] * V[i * len + k];
+    sv[i] = sqrt(n2);
+  }
+  for (int i = 1; i < n_vec; ++i)  // insertion sort, descending
+    for (int j = i; j > 0 && sv[j] > sv[j - 1]; --j) {
+      const double tmp = sv[j];
+      sv[j] = sv[j - 1];
+      sv[j - 1] = tmp;
+    }
+}
+
+// LU factorisation with partial pivoting, in place (row-major M x M, multipliers below the diagonal),
+// perm[i] = original row now at position i.  False on a zero or non-finite pivot.
+__host__ __device__ bool lu_factor(double* T, int M, int* perm) {
   for (int i = 0; i < M; ++i) perm[i] = i;
   for (int c = 0; c < M; ++c) {
     int piv = c;
@@ -140,7 +193,7 @@ __device__ bool lu_factor(double* T, int M, int* perm) {
         piv = r;
       }
     }
-    if (!(best == best) || best > 1.7e308) return false;
+    if (!(best == best) || best > 1.7e308 || best == 0.0) return false;
     if (piv != c) {
       for (int j = 0; j < M; ++j) {
         const double tmp = T[c * M + j];
@@ -151,77 +204,150 @@ __device__ bool lu_factor(double* T, int M, int* perm) {
       perm[c] = perm[piv];
       perm[piv] = tp;
     }
-    if (best == 0.0) return false;
-    pmax = best > pmax ? best : pmax;
-    pmin = best < pmin ? best : pmin;
     for (int r = c + 1; r < M; ++r) {
       const double l = T[r * M + c] / T[c * M + c];
       T[r * M + c] = l;
       for (int j = c + 1; j < M; ++j) T[r * M + j] -= l * T[c * M + j];
     }
   }
-  return pmin > 1e-13 * pmax;
+  return true;
+}
+
+struct Order {
+  int L, M;
+  double margin;  // smallest distance (as a ratio) of a deciding singular value from the threshold
+};
+
+// Degrees used for a requested [L/M]: the rows of C (C[i][j] = a_{L+1+i-j}, i < M, j <= M) are the linear
+// conditions C q = 0 on the denominator.  With s = ||a_0..a_{L+M}||_2 and rho the singular values of C above
+// kPadeTol s: rho < M lowers both degrees by M - rho; a full-rank C whose square block C[:, 1:] has its
+// smallest singular value at most kPadeTol s (no denominator with q_0 = 1) moves to [L+1/M-1].  V holds
+// (M+1)^2 doubles of scratch.
+__host__ __device__ Order select_order(const double* a, int L, int M, double* V) {
+  Order o{L, M, HUGE_VAL};
+  double s2 = 0.0;
+  for (int k = 0; k <= L + M; ++k) s2 += a[k] * a[k];
+  const double s = sqrt(s2);
+  if (!(s > 0.0) || !(s <= 1.7e308)) return Order{0, 0, HUGE_VAL};
+  const double thr = kPadeTol * s;
+  double sv[kMaxPadeM];
+  auto note = [&](double v) {
+    if (v > 0.0) {
+      const double r = v > thr ? v / thr : thr / v;
+      o.margin = r < o.margin ? r : o.margin;
+    }
+  };
+  while (o.M > 0) {
+    const int m = o.M, l = o.L;
+    // Shortcut for the common case, equivalent to the singular-value rule below: the square block T = C[:, 1:]
+    // has sigma_min(T) >= 1 / ||T^-1||_F, and every singular value of C is at least the matching one of T
+    // (C C^T = c c^T + T T^T).  A bound well above the threshold settles it: full rank, denominator with
+    // q_0 = 1, no change of degrees; the margin reported is then this lower bound.
+    {
+      int piv[kMaxPadeM];
+      for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) V[i * m + j] = coef_at(a, l + i - j);
+      if (lu_factor(V, m, piv)) {
+        double fro2 = 0.0;
+        for (int c = 0; c < m; ++c) {  // column c of T^-1: L y = P e_c, U x = y
+          double x[kMaxPadeM];
+          for (int i = 0; i < m; ++i) {
+            double v = piv[i] == c ? 1.0 : 0.0;
+            for (int j = 0; j < i; ++j) v -= V[i * m + j] * x[j];
+            x[i] = v;
+          }
+          for (int i = m - 1; i >= 0; --i) {
+            double v = x[i];
+            for (int j = i + 1; j < m; ++j) v -= V[i * m + j] * x[j];
+            x[i] = v / V[i * m + i];
+            fro2 += x[i] * x[i];
+          }
+        }
+        const double lb = 1.0 / sqrt(fro2);
+        if (lb > 64.0 * thr && lb <= 1.7e308) {
+          note(lb);
+          break;
+        }
+      }
+    }
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j <= m; ++j) V[i * (m + 1) + j] = coef_at(a, l + 1 + i - j);
+    jacobi_singular_values(V, m, m + 1, sv);
+    int rho = 0;
+    while (rho < m && sv[rho] > thr) ++rho;
+    if (rho < m) {
+      note(sv[rho]);
+      if (rho > 0) note(sv[rho - 1]);
+      o.L = l - (m - rho) > 0 ? l - (m - rho) : 0;
+      o.M = rho;
+      continue;
+    }
+    note(sv[m - 1]);
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) V[i * m + j] = coef_at(a, l + i - j);  // C[i][j + 1]
+    jacobi_singular_values(V, m, m, sv);
+    note(sv[m - 1]);
+    if (sv[m - 1] <= thr) {
+      o.L = l + 1;
+      o.M = m - 1;
+      continue;
+    }
+    break;
+  }
+  return o;
 }
 
 struct PadeResult {
   double value;
   int L, M;       // degrees used
-  bool lowered;
+  double margin;  // of their selection
 };
 
-// [L/M] at z = 1 of sum_n a_n z^n.  The denominator q (q_0 = 1) satisfies
+// [L/M] at z = 1 of sum_n a_n z^n with the degrees from select_order.  The denominator q (q_0 = 1) solves
 // sum_{j=0}^{M} q_j a_{k-j} = 0 for k = L+1..L+M (a_i = 0 for i < 0); with partial sums
-// A_m = a_0 + ... + a_m the value is sum_j q_j A_{L-j} / sum_j q_j.  A singular system moves to
-// [L+1/M-1] (same total order), down to M = 0 (the partial sum).  On return T holds the LU factors
-// (M x M), perm the pivoting and q the denominator.
-__device__ PadeResult pade(const double* a, int L, int M, double* q, double* T, int* perm) {
-  PadeResult r{0.0, L, M, false};
+// A_m = a_0 + ... + a_m the value is sum_j q_j A_{L-j} / sum_j q_j.  On return T holds the LU factors
+// (M x M), perm the pivoting and q the denominator (for pade_gradient).
+__host__ __device__ PadeResult pade(const double* a, int L, int M, double* q, double* T, int* perm, double* V) {
+  const Order o = select_order(a, L, M, V);
+  PadeResult r{0.0, o.L, o.M, o.margin};
   while (true) {
     q[0] = 1.0;
-    if (M == 0) break;
-    for (int i = 0; i < M; ++i)
-      for (int j = 0; j < M; ++j) {
-        const int k = L + i - j;  // T_{ij} = a_{L+i-j}, i, j = 1..M
-        T[i * M + j] = k >= 0 ? a[k] : 0.0;
-      }
-    bool ok = lu_factor(T, M, perm);
-    for (int i = 0; ok && i < M; ++i)
-      if (!(fabs(a[L + 1 + i]) <= 1.7e308)) ok = false;
-    if (ok) {
+    const int m = r.M, l = r.L;
+    if (m == 0) break;
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) T[i * m + j] = coef_at(a, l + i - j);  // T_{ij} = a_{L+i-j}, i, j = 1..M
+    if (lu_factor(T, m, perm)) {
       double y[kMaxPadeM];
-      for (int i = 0; i < M; ++i) {  // forward: L y = P (-b)
-        double s = -a[L + 1 + perm[i]];
-        for (int j = 0; j < i; ++j) s -= T[i * M + j] * y[j];
+      for (int i = 0; i < m; ++i) {  // forward: L y = P (-b)
+        double s = -a[l + 1 + perm[i]];
+        for (int j = 0; j < i; ++j) s -= T[i * m + j] * y[j];
         y[i] = s;
       }
-      for (int i = M - 1; i >= 0; --i) {  // backward: U q = y
+      for (int i = m - 1; i >= 0; --i) {  // backward: U q = y
         double s = y[i];
-        for (int j = i + 1; j < M; ++j) s -= T[i * M + j] * q[j + 1];
-        q[i + 1] = s / T[i * M + i];
+        for (int j = i + 1; j < m; ++j) s -= T[i * m + j] * q[j + 1];
+        q[i + 1] = s / T[i * m + i];
       }
       break;
     }
-    L += 1;
-    M -= 1;
-    r.lowered = true;
+    r.L = l + 1;  // an exactly singular square system (the rank test keeps these out): next antidiagonal entry
+    r.M = m - 1;
   }
   double num = 0.0, den = 0.0;
-  for (int j = 0; j <= M; ++j) {
+  for (int j = 0; j <= r.M; ++j) {
     double A = 0.0;
-    for (int i = 0; i <= L - j; ++i) A += a[i];
+    for (int i = 0; i <= r.L - j; ++i) A += a[i];
     num += q[j] * A;
     den += q[j];
   }
   r.value = num / den;
-  r.L = L;
-  r.M = M;
   return r;
 }
 
 // Gradient g_k = d value / d a_k (k = 0..L+M) of the approximant returned by pade().  With
 // D = sum_j q_j and c_j = (A_{L-j} - value)/D, solve T^T y = c; then
 //   g_k = [k <= L] sum_{j=0}^{min(M, L-k)} q_j / D  -  sum_{i=1}^{M} y_i q_{L+i-k}  (0 <= L+i-k <= M).
-__device__ void pade_gradient(const double* a, const PadeResult& r, const double* q, const double* T,
+__host__ __device__ void pade_gradient(const double* a, const PadeResult& r, const double* q, const double* T,
                               const int* perm, double* g) {
   const int L = r.L, M = r.M;
   double D = 0.0;
@@ -259,14 +385,74 @@ __device__ void pade_gradient(const double* a, const PadeResult& r, const double
   }
 }
 
+// Point k (0 <= k < n) of the boundary of {z : dist(z, [0, 1]) <= kPoleDist}, counter-clockwise at equal
+// arc length: the lower side, the right half circle around 1, the upper side, the left half circle around 0.
+// The half circles use single-precision sin/cos: the samples only have to lie on the contour to ~1e-7.
+__host__ __device__ void stadium_point(int k, int n, double* re, double* im) {
+  const double r = kPoleDist, pi = 3.141592653589793;
+  const double per = 2.0 + 2.0 * pi * r;
+  double s = per * (double)k / (double)n;
+  if (s < 1.0) {
+    *re = s;
+    *im = -r;
+    return;
+  }
+  s -= 1.0;
+  if (s < pi * r) {
+    const float ph = (float)(-0.5 * pi + s / r);
+    *re = 1.0 + r * (double)cosf(ph);
+    *im = r * (double)sinf(ph);
+    return;
+  }
+  s -= pi * r;
+  if (s < 1.0) {
+    *re = 1.0 - s;
+    *im = r;
+    return;
+  }
+  s -= 1.0;
+  const float ph = (float)(0.5 * pi + s / r);
+  *re = r * (double)cosf(ph);
+  *im = r * (double)sinf(ph);
+}
+
+// Q(z) = sum_{j<=M} q_j z^j at a complex z (Horner).
+__host__ __device__ void q_eval(const double* q, int M, double zr, double zi, double* vr, double* vi) {
+  double ar = q[M], ai = 0.0;
+  for (int j = M - 1; j >= 0; --j) {
+    const double nr = ar * zr - ai * zi + q[j];
+    ai = ar * zi + ai * zr;
+    ar = nr;
+  }
+  *vr = ar;
+  *vi = ai;
+}
+
+// Phase of w1 / w0 (w0, w1 != 0) in (-pi, pi], in single precision after scaling the product w1 conj(w0):
+// the winding count only needs each step to an accuracy far below pi.
+__host__ __device__ __forceinline__ float phase_step(double r0, double i0, double r1, double i1) {
+  const double re = r1 * r0 + i1 * i0, im = i1 * r0 - r1 * i0;
+  const double m = fmax(fabs(re), fabs(im));
+  if (!(m > 0.0)) return 0.0f;
+  return atan2f((float)(im / m), (float)(re / m));
+}
+
+// Per-lane scratch of the three Pade evaluations of a point (the value, [L-1/M] and [L/M-1]).
+struct PadeScratch {
+  double q[kMaxPadeM + 1];
+  double T[kMaxPadeM * kMaxPadeM];
+  double V[(kMaxPadeM + 1) * (kMaxPadeM + 1)];
+  int perm[kMaxPadeM];
+};
+
 __global__ __launch_bounds__(64) void finalize_kernel(FinalizeArgs a) {
   __shared__ double coef[kMaxBins];
   __shared__ double m1[kMaxBins];
   __shared__ double m2[kMaxBins];
   __shared__ double grad[kMaxBins];
-  __shared__ double T[kMaxPadeM * kMaxPadeM];
-  __shared__ double q[kMaxPadeM + 1];
-  __shared__ int perm[kMaxPadeM];
+  __shared__ PadeScratch ps[3];
+  __shared__ double res[3];             // values of lanes 0..2
+  __shared__ int m_used;
   __shared__ unsigned long long extra[3];
 
   const uint32_t p = blockIdx.x;
@@ -315,42 +501,79 @@ __global__ __launch_bounds__(64) void finalize_kernel(FinalizeArgs a) {
   for (uint32_t s = lane; s < pr.seg_count; s += kWave) nodes += a.seg_nodes[pr.seg_begin + s];
   nodes = wave_sum_u64(nodes);
 
+  // Lanes 0, 1, 2 evaluate [L/M], [L-1/M] and [L/M-1] side by side, each with its own degree selection.
+  const int L = (int)a.pade_L, M = (int)a.pade_M;
+  PadeResult r{};
+  if (lane < 3) {
+    const int Lk = lane == 1 ? L - 1 : L, Mk = lane == 2 ? M - 1 : M;
+    PadeScratch& w = ps[lane];
+    if (Lk >= 0 && Mk >= 0) {
+      r = pade(coef, Lk, Mk, w.q, w.T, w.perm, w.V);
+      res[lane] = r.value;
+    } else {
+      res[lane] = NAN;
+    }
+    if (lane == 0) m_used = r.M;
+  }
+  __syncthreads();
+  // Pole test: the number of zeros of Q inside the contour around [0, 1] is the winding number of Q along
+  // it (argument principle), summed from the phase steps between consecutive samples.
+  const int mq = m_used;
+  const double* qm = ps[0].q;
+  float wind = 0.0f;
+  bool on_contour = false;
+  if (mq > 0) {
+    const int n = kWave * kWindingSamples;
+    double zr, zi, pr0, pi0;
+    stadium_point((int)lane * kWindingSamples, n, &zr, &zi);
+    q_eval(qm, mq, zr, zi, &pr0, &pi0);
+    for (int k = 1; k <= kWindingSamples; ++k) {
+      double pr1, pi1;
+      stadium_point(((int)lane * kWindingSamples + k) % n, n, &zr, &zi);
+      q_eval(qm, mq, zr, zi, &pr1, &pi1);
+      on_contour |= (pr1 == 0.0 && pi1 == 0.0);
+      wind += phase_step(pr0, pi0, pr1, pi1);
+      pr0 = pr1;
+      pi0 = pi1;
+    }
+  }
+  for (int off = 32; off >= 1; off >>= 1) wind += __shfl_xor(wind, off);
+  on_contour = __ballot(on_contour) != 0;
   if (lane == 0) {
     uint32_t fl = 0;
     if (extra[0] > 0) fl |= BRT_FLAG_OVERFLOW;
     if (extra[1] > 0) fl |= BRT_FLAG_CAPPED;
     if (extra[2] > 0) fl |= BRT_FLAG_DEPTH;
+    if (on_contour || wind > 3.14159265f) fl |= BRT_FLAG_POLE;  // winding number >= 1
+    if (r.L != L || r.M != M) fl |= BRT_FLAG_LOWERED;
     double psum = 0.0;
     for (uint32_t b = 0; b < B; ++b) psum += coef[b];
-    const PadeResult r = pade(coef, (int)a.pade_L, (int)a.pade_M, q, T, perm);
-    if (r.lowered) fl |= BRT_FLAG_LOWERED;
-    // pole test: Q(0) = 1; flag a value <= 1e-8 anywhere on [0, 1]
-    for (int k = 1; k <= 64; ++k) {
-      const double z = k / 64.0;
-      double qz = 0.0, zp = 1.0;
-      for (int j = 0; j <= r.M; ++j) {
-        qz += q[j] * zp;
-        zp *= z;
-      }
-      if (!(qz > 1e-8)) {
-        fl |= BRT_FLAG_POLE;
-        break;
-      }
-    }
     // delta method: Var(u) = sum_kl g_k g_l Cov(a_k, a_l) with
-    // Cov(a_k, a_l) = scale^2 (delta_kl m2_k - m1_k m1_l) / (N - 1)
-    pade_gradient(coef, r, q, T, perm, grad);
-    double gg = 0.0, gm = 0.0;
+    // Cov(a_k, a_l) = scale^2 (delta_kl m2_k - m1_k m1_l) / (N - 1); sensitivity kappa = sum_k |g_k| |a_k|
+    PadeScratch& w = ps[0];
+    pade_gradient(coef, r, w.q, w.T, w.perm, grad);
+    double gg = 0.0, gm = 0.0, kappa = 0.0;
     for (int k = 0; k <= r.L + r.M; ++k) {
       gg += grad[k] * grad[k] * m2[k];
       gm += grad[k] * m1[k];
+      kappa += fabs(grad[k]) * fabs(coef[k]);
     }
     const double var = N > 1 ? scale * scale * (gg - gm * gm) / (N - 1.0) : 0.0;
+    if (kappa > kSensitive) fl |= BRT_FLAG_SENSITIVE;
     if (a.u) a.u[row] = r.value;
     if (a.se) a.se[row] = sqrt(var > 0.0 ? var : 0.0);
     if (a.psum) a.psum[row] = psum;
     if (a.flags) a.flags[row] = fl;
     if (a.nodes) a.nodes[row] = nodes;
+    if (a.pade_diag) {
+      double* d = a.pade_diag + (size_t)row * BRT_PADE_DIAG;
+      d[0] = (double)r.L;
+      d[1] = (double)r.M;
+      d[2] = res[1];
+      d[3] = res[2];
+      d[4] = kappa;
+      d[5] = r.margin;
+    }
   }
 }
 

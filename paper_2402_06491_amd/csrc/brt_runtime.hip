@@ -620,6 +620,7 @@ static int enqueue(brt_plan* p, const brt_out* o, hipStream_t s) {
   f.s2 = o->s2;
   f.nodes = reinterpret_cast<unsigned long long*>(o->nodes);
   f.flags = o->flags;
+  f.pade_diag = o->pade_diag;
   HIP_TRY(launch_finalize(f, s));
   if (ev) HIP_TRY(hipEventRecord((*ev)[3], s));
   return BRT_OK;

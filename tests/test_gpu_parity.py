@@ -48,9 +48,10 @@ def _full_parity(ctx, name, wl, launch=None, pade_tol=1e-3):
         a = r["a"]
         np.testing.assert_allclose(gpu["coef"][p], a, rtol=0, atol=(tol + 1e-12) * np.abs(a).max() + 1e-300)
         assert abs(gpu["psum"][p] - r["psum"]) <= (tol + 1e-12) * np.abs(a).sum() + 1e-300
-    du, strict, n = P.compare_pade(wl, gpu, opade, pade_tol)
-    print(f"[case] {name}: max rel tree diff {worst:.3e}, max |du| {du:.3e}, {strict}/{n} points within "
-          f"{pade_tol}, bins {B}", flush=True)
+    du, strict, n, flagged, near = P.compare_pade(wl, gpu, opade, pade_tol)
+    print(f"[case] {name}: max rel tree diff {worst:.3e}, max |du| {du:.3e} over {strict} unflagged points "
+          f"(all within {pade_tol}), {flagged}/{n} flagged on both sides, {near} degree choices near the "
+          f"threshold, bins {B}", flush=True)
     return gpu, orc
 
 
