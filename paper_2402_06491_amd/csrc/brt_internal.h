@@ -80,12 +80,20 @@ struct Segment {
   uint32_t out;  // index of the partial this segment writes
 };
 
-// Per (segment, bin) partial moments.
+// Per (segment, bin) partial moments: the count, the compensated sum of F as an unevaluated pair
+// s1_hi + s1_lo, and the sum of F*F (each F*F rounded to FP64).  The finalize joins a point's segments
+// exactly (kAccWords digit words) and rounds once, so the result does not depend on the order of the
+// segments.  Entries B, B+1, B+2 of a segment count trees pruned (overflow), capped and over the stack
+// depth in `count`.
 struct Partial {
   uint64_t count;
-  double s1;
+  double s1_hi;
+  double s1_lo;
   double s2;
 };
+// Digit words of an exact sum: word k holds a signed sum of 32-bit digits weighing 2^(32k - 1074), which
+// covers every finite double (k <= 65) with headroom for carries.
+constexpr int kAccWords = 68;
 
 struct WalkArgs {
   const PointRec* points;

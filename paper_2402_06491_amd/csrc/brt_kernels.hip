@@ -68,6 +68,7 @@ struct Math<float> {
     *s = __builtin_amdgcn_sinf(u);
     *c = __builtin_amdgcn_cosf(u);
   }
+  static __device__ __forceinline__ float cos_rev(float u) { return __builtin_amdgcn_cosf(u); }
   static __device__ __forceinline__ float cos_half_pi(float v) {  // cos(pi v / 2) = cos(2 pi (v/4))
     return __builtin_amdgcn_cosf(0.25f * v);
   }
@@ -80,6 +81,7 @@ struct Math<double> {
   static __device__ __forceinline__ double sq(double x) { return sqrt(x); }
   static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
   static __device__ __forceinline__ void sincos_rev(double u, double* s, double* c) { sincospi(2.0 * u, s, c); }
+  static __device__ __forceinline__ double cos_rev(double u) { return cospi(2.0 * u); }
   static __device__ __forceinline__ double cos_half_pi(double v) { return cospi(0.5 * v); }
 };
 
@@ -472,13 +474,17 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
     // dt = S on the way to a split, tau to a leaf
     const Real u1 = ((Real)w.c + (Real)0.5) * (Real)0x1p-32;
     const Real u2 = (Real)w.d * (Real)0x1p-32;
-    Real sn, cs;
-    Math<Real>::sincos_rev(u2, &sn, &cs);
+    // 1-D paths use the cosine half of the Box-Muller pair only (an Euler edge's first step in 2-D uses both)
+    Real sn = 0, cs;
+    if constexpr (DIM == 2)
+      Math<Real>::sincos_rev(u2, &sn, &cs);
+    else
+      cs = Math<Real>::cos_rev(u2);
     const Real dt = vertex ? S : tau;
     const Real sdr = hc.sigma * Math<Real>::sq((Real)-2 * Math<Real>::ln(u1) * dt);
     Real xn[2];
     xn[0] = x[0] + sdr * cs;
-    xn[1] = x[1] + sdr * sn;
+    xn[1] = DIM == 2 ? x[1] + sdr * sn : x[1];
     if constexpr (CMOD) {
       if (hc.sde) {
         // a general L: the edge is integrated by Euler-Maruyama steps instead
@@ -487,7 +493,7 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
       } else if (hc.drift_on) {
         // constant drift: the edge also moves by b dt (exact for L = a Lap + b . grad)
         xn[0] += hc.drift0 * dt;
-        xn[1] += hc.drift1 * dt;
+        if constexpr (DIM == 2) xn[1] += hc.drift1 * dt;
       }
     }
 
@@ -538,7 +544,7 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
     }
     const bool cont = vok && alpha > 0;  // the vertex's first child departs from the split point
     x[0] = cont ? xn[0] : x[0];
-    x[1] = cont ? xn[1] : x[1];
+    if constexpr (DIM == 2) x[1] = cont ? xn[1] : x[1];
     P = cont ? Pn : P;
     tau = cont ? tau2 : tau;
     const bool branch_end = !done && !cont;  // a leaf, or a vertex without children

@@ -1,9 +1,10 @@
 // Moment reduction and FP64 finalize of the random-tree Monte Carlo (gfx950).
 //
-//  reduce_kernel    one wave per segment of one point's trees: per-bin count, sum F, sum F^2 with
-//                   per-lane LDS accumulators (each lane sums its own records in index order) and a
-//                   fixed-order wave reduction, so the result does not depend on scheduling.
-//  finalize_kernel  one wave per point, FP64: Neumaier-compensated sums over the point's segments,
+//  reduce_kernel    one wave per segment of one point's trees: per-bin count, compensated
+//                   (double-double) sum of F and plain sum of F*F, each lane adding its records in index
+//                   order, the lanes joined by a fixed butterfly.
+//  finalize_kernel  one wave per point, FP64: the point's segment sums joined exactly (integer digit
+//                   words) and rounded once, so the result does not depend on the order of the segments,
 //                   coefficients a_n = e^{mu t} S1_n / N (the sample mean of the functional, Sec. 2.4)
 //                   and their variances, the [L/M] Pade approximant at z = 1 (Sec. 2.1 end) with its
 //                   degrees chosen by the singular values of the denominator's linear conditions (one-sided
@@ -14,13 +15,17 @@
 //                   by the argument principle.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
 
 #include "brt_internal.h"
 
 namespace brt {
 
-constexpr int kRedGroup = 16;  // moment bins accumulated per pass over a segment
-constexpr int kRedBatch = 32;  // records loaded per lane before they are accumulated
+constexpr int kRedGroup = 16;   // bins accumulated per pass over a segment (per-lane sums in LDS)
+static_assert(kSegTrees <= 65535, "per-lane counts are 16-bit");
+constexpr int kRedBatch = 32;   // records loaded per lane before they are accumulated
 constexpr uint32_t kAbsent = 0xffffffffu;  // marks a batch slot past the end of the segment (no real
                                            // record has every flag bit set)
 
@@ -36,12 +41,126 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
   return v;
 }
 
-// Partials layout per segment: bins 0..B-1 (B-1 is the tail, Ne > max_order without pruning) with
-// moments, then counts of overflow, capped and depth-exceeded trees.
-__global__ __launch_bounds__(64) void reduce_kernel(ReduceArgs a) {
-  __shared__ double ls1[kRedGroup][kWave];
-  __shared__ double ls2[kRedGroup][kWave];
-  __shared__ uint32_t lcnt[kRedGroup][kWave];
+// A finite double v as sign, significand and position: |v| = m 2^(p - 1074) with m < 2^53 and p >= 0
+// (p = biased exponent - 1 for normal numbers, 0 for subnormal ones).
+__host__ __device__ __forceinline__ void split_double(double v, uint32_t* p, uint64_t* m, bool* neg) {
+  uint64_t bits;
+  memcpy(&bits, &v, sizeof(bits));
+  const uint32_t e = (uint32_t)(bits >> 52) & 0x7ffu;
+  const uint64_t frac = bits & ((1ull << 52) - 1);
+  *neg = (bits >> 63) != 0;
+  *m = e ? (frac | (1ull << 52)) : frac;
+  *p = e ? e - 1 : 0;
+}
+
+// The three signed digits that add v (finite, nonzero) to a digit-word accumulator at words k, k+1, k+2.
+__host__ __device__ __forceinline__ void digits_of(double v, uint32_t* k, unsigned long long* d) {
+  uint32_t p;
+  uint64_t m;
+  bool neg;
+  split_double(v, &p, &m, &neg);
+  *k = p >> 5;
+  const uint32_t sh = p & 31u;
+  const uint64_t lo = m << sh;
+  const uint64_t hi = sh ? (m >> (64 - sh)) : 0ull;
+  const uint64_t d0 = lo & 0xffffffffull, d1 = lo >> 32, d2 = hi;
+  d[0] = neg ? (unsigned long long)(0ull - d0) : d0;  // two's complement: adding it subtracts the digit
+  d[1] = neg ? (unsigned long long)(0ull - d1) : d1;
+  d[2] = neg ? (unsigned long long)(0ull - d2) : d2;
+}
+
+// The digit words of one sum (kAccWords signed words, word k weighing 2^(32k - 1074), word k at
+// w[k * stride]) rounded once to the nearest double, ties to even; special = the non-finite values seen
+// (bit 0 +inf, bit 1 -inf, bit 2 NaN).
+__host__ __device__ double acc_round(const unsigned long long* w, int stride, unsigned long long special) {
+  if (special & 4ull) return NAN;
+  if ((special & 3ull) == 3ull) return NAN;
+  if (special & 1ull) return INFINITY;
+  if (special & 2ull) return -INFINITY;
+  // carry-propagate into 32-bit digits; the final carry is the sign (0 or -1)
+  uint32_t dg[kAccWords];
+  long long carry = 0;
+  for (int k = 0; k < kAccWords; ++k) {
+    const long long t = (long long)w[(size_t)k * stride] + carry;
+    dg[k] = (uint32_t)((unsigned long long)t & 0xffffffffull);
+    carry = t >> 32;
+  }
+  const bool neg = carry < 0;
+  if (neg) {  // magnitude of the two's complement number
+    unsigned long long c = 1;
+    for (int k = 0; k < kAccWords; ++k) {
+      const unsigned long long t = (unsigned long long)(uint32_t)~dg[k] + c;
+      dg[k] = (uint32_t)t;
+      c = t >> 32;
+    }
+  }
+  int K = kAccWords - 1;
+  while (K >= 0 && dg[K] == 0) --K;
+  if (K < 0) return 0.0;
+  // the 64 bits from the leading one down (left-aligned), and whether anything nonzero lies below them
+  int nb = 32;
+  while (!((dg[K] >> (nb - 1)) & 1u)) --nb;  // bit length of the leading digit
+  const long long msb = 32ll * K + nb - 1;  // position of the leading one (bit 0 weighs 2^-1074)
+  // digits K, K-1, K-2 as a 96-bit window [d2 d1 d0], shifted so that the leading one is bit 63 of top
+  const unsigned long long d2 = dg[K], d1 = K >= 1 ? dg[K - 1] : 0u, d0 = K >= 2 ? dg[K - 2] : 0u;
+  const unsigned long long hi64 = (d2 << 32) | d1;  // bits 32K + 31 .. 32K - 32
+  const int sh = 32 - nb;                           // left shift that puts the leading one at bit 63
+  const unsigned long long top = sh ? (hi64 << sh) | (d0 >> (32 - sh)) : hi64;
+  bool sticky = sh ? ((d0 & ((1ull << (32 - sh)) - 1)) != 0) : (d0 != 0);
+  for (int k = 0; k < K - 2 && !sticky; ++k) sticky = dg[k] != 0;
+  double r;
+  if (msb <= 52) {
+    // at most 53 significant bits with lowest weight 2^-1074: exactly representable
+    r = ldexp((double)(top >> (63 - msb)), -1074);
+  } else {
+    unsigned long long mant = top >> 11;          // 53 bits
+    const unsigned long long rem = top & 0x7ffull;
+    if (rem > 0x400ull || (rem == 0x400ull && (sticky || (mant & 1ull)))) mant += 1;
+    long long e2 = msb - 52 - 1074;
+    if (mant >> 53) {
+      mant >>= 1;
+      e2 += 1;
+    }
+    r = e2 > 1023 - 52 ? INFINITY : ldexp((double)mant, (int)e2);
+  }
+  return neg ? -r : r;
+}
+
+// Error-free sum (Knuth's TwoSum): s + e = a + b exactly, s = fl(a + b).
+__host__ __device__ __forceinline__ void two_sum(double a, double b, double* s, double* e) {
+  const double t = a + b;
+  const double bb = t - a;
+  *e = (a - (t - bb)) + (b - bb);
+  *s = t;
+}
+
+// Compensated (double-double) running sum hi + lo: hi takes the rounded sum, lo the exact rounding errors.
+__device__ __forceinline__ void dd_add(double* hi, double* lo, double x) {
+  double s, e;
+  two_sum(*hi, x, &s, &e);
+  *hi = s;
+  *lo += e;
+}
+
+// Sum of a double-double over the wave by a fixed butterfly.
+__device__ __forceinline__ void wave_sum_dd(double* hi, double* lo) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const double h2 = __shfl_xor(*hi, off), l2 = __shfl_xor(*lo, off);
+    double s, e;
+    two_sum(*hi, h2, &s, &e);
+    const double l = (*lo + l2) + e;
+    two_sum(s, l, hi, lo);
+  }
+}
+
+// One wave per segment of one point's trees: per bin, the count, the sum of F as a compensated
+// (double-double) sum and the sum of F*F (each square rounded to FP64), every lane adding its records in
+// index order into its own LDS column, the lanes joined by a fixed butterfly.  Non-finite values
+// propagate into the sums (the finalize classifies them).
+__global__ __launch_bounds__(kWave) void reduce_kernel(ReduceArgs a) {
+  __shared__ double s1h[kRedGroup][kWave], s1l[kRedGroup][kWave], s2[kRedGroup][kWave];
+  __shared__ uint16_t lcnt[kRedGroup][kWave];  // a segment holds at most kSegTrees <= 65535 trees
 
   const uint32_t seg = blockIdx.x;
   const uint32_t lane = threadIdx.x;
@@ -56,13 +175,14 @@ __global__ __launch_bounds__(64) void reduce_kernel(ReduceArgs a) {
   uint32_t n_ovf = 0, n_cap = 0, n_dep = 0;
   for (uint32_t g0 = 0; g0 < B; g0 += kRedGroup) {
     for (int k = 0; k < kRedGroup; ++k) {
-      ls1[k][lane] = 0.0;
-      ls2[k][lane] = 0.0;
-      lcnt[k][lane] = 0u;
+      s1h[k][lane] = 0.0;
+      s1l[k][lane] = 0.0;
+      s2[k][lane] = 0.0;
+      lcnt[k][lane] = 0;
     }
     bool above = false;
-    // records are loaded kRedBatch at a time so that many loads are in flight per lane; each lane
-    // still adds its records in increasing index order
+    // records are loaded kRedBatch at a time so that many loads are in flight per lane; each lane still
+    // adds its records in increasing index order
     for (uint32_t i0 = sg.begin + lane; i0 < sg.end; i0 += kWave * kRedBatch) {
       uint32_t mb[kRedBatch];
       double fb[kRedBatch];
@@ -74,44 +194,36 @@ __global__ __launch_bounds__(64) void reduce_kernel(ReduceArgs a) {
       }
 #pragma unroll
       for (int j = 0; j < kRedBatch; ++j) {
-      const uint32_t m = mb[j];
-      const double f = fb[j];
-      if (m == kAbsent) continue;
-      if (g0 == 0) {
-        nodes += (unsigned long long)(m >> kMetaNodesShift);
-        n_ovf += (m >> 8) & 1u;
-        n_cap += (m >> 9) & 1u;
-        n_dep += (m >> 10) & 1u;
-      }
-      if (m & (kMetaOverflow | kMetaCapped | kMetaDepth)) continue;
-      const uint32_t ne = m & kMetaNeMask;
-      const uint32_t bin = ne < B - 1 ? ne : B - 1;
-      if (bin >= g0 && bin < g0 + kRedGroup) {
+        const uint32_t m = mb[j];
+        if (m == kAbsent) continue;
+        if (g0 == 0) {
+          nodes += (unsigned long long)(m >> kMetaNodesShift);
+          n_ovf += (m >> 8) & 1u;
+          n_cap += (m >> 9) & 1u;
+          n_dep += (m >> 10) & 1u;
+        }
+        if (m & (kMetaOverflow | kMetaCapped | kMetaDepth)) continue;
+        const uint32_t ne = m & kMetaNeMask;
+        const uint32_t bin = ne < B - 1 ? ne : B - 1;
+        above |= bin >= g0 + kRedGroup;
+        if (bin < g0 || bin >= g0 + kRedGroup) continue;
         const uint32_t k = bin - g0;
-        ls1[k][lane] += f;
-        ls2[k][lane] += f * f;
-        lcnt[k][lane] += 1u;
-      }
-      above |= bin >= g0 + kRedGroup;
+        const double f = fb[j];
+        lcnt[k][lane] += 1;
+        dd_add(&s1h[k][lane], &s1l[k][lane], f);
+        s2[k][lane] += __dmul_rn(f, f);  // the square rounded on its own, not fused into the sum
       }
     }
     for (int k = 0; k < kRedGroup; ++k) {
       const uint32_t b = g0 + k;
-      const double v1 = wave_sum_f64(ls1[k][lane]);
-      const double v2 = wave_sum_f64(ls2[k][lane]);
+      double h = s1h[k][lane], l = s1l[k][lane];
+      wave_sum_dd(&h, &l);
+      const double v2 = wave_sum_f64(s2[k][lane]);
       const unsigned long long c = wave_sum_u64((unsigned long long)lcnt[k][lane]);
-      if (lane == 0 && b < B) {
-        out[b].count = c;
-        out[b].s1 = v1;
-        out[b].s2 = v2;
-      }
+      if (lane == 0 && b < B) out[b] = Partial{c, h, l, v2};
     }
     if (__ballot(above) == 0) {
-      for (uint32_t b = g0 + kRedGroup + lane; b < B; b += kWave) {
-        out[b].count = 0;
-        out[b].s1 = 0.0;
-        out[b].s2 = 0.0;
-      }
+      for (uint32_t b = g0 + kRedGroup + lane; b < B; b += kWave) out[b] = Partial{0, 0.0, 0.0, 0.0};
       break;
     }
   }
@@ -119,9 +231,9 @@ __global__ __launch_bounds__(64) void reduce_kernel(ReduceArgs a) {
   const unsigned long long o = wave_sum_u64(n_ovf), c = wave_sum_u64(n_cap), d = wave_sum_u64(n_dep);
   if (lane == 0) {
     a.seg_nodes[sg.out] = nodes;
-    out[B] = Partial{o, 0.0, 0.0};
-    out[B + 1] = Partial{c, 0.0, 0.0};
-    out[B + 2] = Partial{d, 0.0, 0.0};
+    out[B] = Partial{o, 0.0, 0.0, 0.0};
+    out[B + 1] = Partial{c, 0.0, 0.0, 0.0};
+    out[B + 2] = Partial{d, 0.0, 0.0, 0.0};
   }
 }
 
@@ -140,29 +252,36 @@ __host__ __device__ __forceinline__ double coef_at(const double* a, int k) { ret
 
 // Singular values of the n_vec x len matrix whose rows are stored in V (row i at V[i * len]), by one-sided
 // Jacobi rotations of those rows (Hestenes): rotate pairs of rows until every pair is orthogonal; the row
-// norms are then the singular values (n_vec <= len).  V is overwritten; sv[0..n_vec) comes out descending.
+// norms are then the singular values (n_vec <= len).  Squared row norms are kept and updated by the
+// rotation identities (a' = a - t g, b' = b + t g), recomputed at the start of every sweep.  V is
+// overwritten; sv[0..n_vec) comes out descending.
 __host__ __device__ void jacobi_singular_values(double* V, int n_vec, int len, double* sv) {
+  double nrm[kMaxPadeM + 1];
   for (int sweep = 0; sweep < 64; ++sweep) {
+    for (int i = 0; i < n_vec; ++i) {
+      double n2 = 0.0;
+      for (int k = 0; k < len; ++k) n2 += V[i * len + k] * V[i * len + k];
+      nrm[i] = n2;
+    }
     bool rotated = false;
     for (int i = 0; i < n_vec - 1; ++i)
       for (int j = i + 1; j < n_vec; ++j) {
-        double al = 0.0, be = 0.0, ga = 0.0;
-        for (int k = 0; k < len; ++k) {
-          const double x = V[i * len + k], y = V[j * len + k];
-          al += x * x;
-          be += y * y;
-          ga += x * y;
-        }
-        if (ga == 0.0 || fabs(ga) <= 1e-15 * sqrt(al * be)) continue;
+        double ga = 0.0;
+        for (int k = 0; k < len; ++k) ga += V[i * len + k] * V[j * len + k];
+        const double al = nrm[i], be = nrm[j];
+        if (ga == 0.0 || ga * ga <= 1e-30 * (al * be)) continue;
         rotated = true;
-        const double zeta = (be - al) / (2.0 * ga);
-        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        // tan of the rotation angle, the smaller root of t^2 + 2 zeta t - 1 = 0 with zeta = (be - al)/(2 ga)
+        const double d = be - al;
+        const double t = (d >= 0.0 ? 2.0 * ga : -2.0 * ga) / (fabs(d) + sqrt(d * d + 4.0 * ga * ga));
         const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
         for (int k = 0; k < len; ++k) {
           const double x = V[i * len + k], y = V[j * len + k];
           V[i * len + k] = c * x - s * y;
           V[j * len + k] = s * x + c * y;
         }
+        nrm[i] = al - t * ga;
+        nrm[j] = be + t * ga;
       }
     if (!rotated) break;
   }
@@ -204,8 +323,9 @@ __host__ __device__ bool lu_factor(double* T, int M, int* perm) {
       perm[c] = perm[piv];
       perm[piv] = tp;
     }
+    const double inv = 1.0 / T[c * M + c];
     for (int r = c + 1; r < M; ++r) {
-      const double l = T[r * M + c] / T[c * M + c];
+      const double l = T[r * M + c] * inv;
       T[r * M + c] = l;
       for (int j = c + 1; j < M; ++j) T[r * M + j] -= l * T[c * M + j];
     }
@@ -221,7 +341,9 @@ struct Order {
 // Degrees used for a requested [L/M]: the rows of C (C[i][j] = a_{L+1+i-j}, i < M, j <= M) are the linear
 // conditions C q = 0 on the denominator.  With s = ||a_0..a_{L+M}||_2 and rho the singular values of C above
 // kPadeTol s: rho < M lowers both degrees by M - rho; a full-rank C whose square block C[:, 1:] has its
-// smallest singular value at most kPadeTol s (no denominator with q_0 = 1) moves to [L+1/M-1].  V holds
+// smallest singular value at most kPadeTol s (no denominator with q_0 = 1) moves to [L+1/M-1].  The square
+// block is looked at first (by a bound from its LU factors, then by its singular values): when its smallest
+// singular value is above the threshold, so are all of C's, and C itself is not decomposed.  V holds
 // (M+1)^2 doubles of scratch.
 __host__ __device__ Order select_order(const double* a, int L, int M, double* V) {
   Order o{L, M, HUGE_VAL};
@@ -270,6 +392,13 @@ __host__ __device__ Order select_order(const double* a, int L, int M, double* V)
         }
       }
     }
+    // the square block first: sigma_min(C[:, 1:]) above the threshold gives full rank of C as well
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) V[i * m + j] = coef_at(a, l + i - j);  // C[i][j + 1]
+    double svT[kMaxPadeM];
+    jacobi_singular_values(V, m, m, svT);
+    note(svT[m - 1]);
+    if (svT[m - 1] > thr) break;
     for (int i = 0; i < m; ++i)
       for (int j = 0; j <= m; ++j) V[i * (m + 1) + j] = coef_at(a, l + 1 + i - j);
     jacobi_singular_values(V, m, m + 1, sv);
@@ -283,16 +412,9 @@ __host__ __device__ Order select_order(const double* a, int L, int M, double* V)
       continue;
     }
     note(sv[m - 1]);
-    for (int i = 0; i < m; ++i)
-      for (int j = 0; j < m; ++j) V[i * m + j] = coef_at(a, l + i - j);  // C[i][j + 1]
-    jacobi_singular_values(V, m, m, sv);
-    note(sv[m - 1]);
-    if (sv[m - 1] <= thr) {
-      o.L = l + 1;
-      o.M = m - 1;
-      continue;
-    }
-    break;
+    // C has full rank but its square block does not: no denominator with q_0 = 1
+    o.L = l + 1;
+    o.M = m - 1;
   }
   return o;
 }
@@ -454,6 +576,7 @@ __global__ __launch_bounds__(64) void finalize_kernel(FinalizeArgs a) {
   __shared__ double res[3];             // values of lanes 0..2
   __shared__ int m_used;
   __shared__ unsigned long long extra[3];
+  __shared__ unsigned long long wacc[kAccWords * kWave];  // digit words, one column per lane
 
   const uint32_t p = blockIdx.x;
   const uint32_t lane = threadIdx.x;
@@ -464,39 +587,77 @@ __global__ __launch_bounds__(64) void finalize_kernel(FinalizeArgs a) {
   const double N = (double)pr.n_total;
   const double scale = exp(pr.mu * pr.t);
 
+  // Counts and flag counts: integer sums over the point's segments.
   for (uint32_t b = lane; b < NB; b += kWave) {
-    // Neumaier-compensated sums over the point's segments, in segment order
-    double s1 = 0.0, c1 = 0.0, s2 = 0.0, c2 = 0.0;
     unsigned long long cnt = 0;
-    for (uint32_t s = 0; s < pr.seg_count; ++s) {
-      const Partial& pt = a.partials[(size_t)(pr.seg_begin + s) * NB + b];
-      cnt += pt.count;
-      const double t1 = s1 + pt.s1;
-      c1 += fabs(s1) >= fabs(pt.s1) ? (s1 - t1) + pt.s1 : (pt.s1 - t1) + s1;
-      s1 = t1;
-      const double t2 = s2 + pt.s2;
-      c2 += fabs(s2) >= fabs(pt.s2) ? (s2 - t2) + pt.s2 : (pt.s2 - t2) + s2;
-      s2 = t2;
-    }
-    s1 += c1;
-    s2 += c2;
+    for (uint32_t s = 0; s < pr.seg_count; ++s) cnt += a.partials[(size_t)(pr.seg_begin + s) * NB + b].count;
     if (a.hist) a.hist[(size_t)row * NB + b] = cnt;
-    if (b < B) {
-      if (a.s1) a.s1[(size_t)row * B + b] = s1;
-      if (a.s2) a.s2[(size_t)row * B + b] = s2;
-      const double mm1 = N > 0 ? s1 / N : 0.0;
-      const double mm2 = N > 0 ? s2 / N : 0.0;
-      m1[b] = mm1;
-      m2[b] = mm2;
-      coef[b] = scale * mm1;
-      const double var = N > 1 ? scale * scale * (mm2 - mm1 * mm1) / (N - 1.0) : 0.0;
-      if (a.coef) a.coef[(size_t)row * B + b] = scale * mm1;
-      if (a.coef_var) a.coef_var[(size_t)row * B + b] = var;
-    } else {
-      extra[b - B] = cnt;
+    if (b >= B) extra[b - B] = cnt;
+  }
+  // The sums: lane j takes the pair (bin j/2, sum j%2) and adds every segment's value exactly into its own
+  // column of digit words, then rounds the total once.  Non-finite segment sums are classified instead.
+  for (uint32_t j0 = 0; j0 < 2 * B; j0 += kWave) {
+    const uint32_t j = j0 + lane;
+    unsigned long long* w = wacc + lane;
+    for (int k = 0; k < kAccWords; ++k) w[k * kWave] = 0ull;
+    unsigned long long special = 0;
+    if (j < 2 * B) {
+      const uint32_t b = j >> 1;
+      // a window of three words in registers at the last value's word index; a value on another word
+      // first moves the window into the lane's LDS column (the segments of a point share a word almost
+      // always, and each word takes at most 2^31 digits, far above a point's number of segments)
+      uint32_t wk = 0xffffffffu;
+      unsigned long long r0 = 0, r1 = 0, r2 = 0;
+      for (uint32_t s = 0; s < pr.seg_count; ++s) {
+        const Partial& pt = a.partials[(size_t)(pr.seg_begin + s) * NB + b];
+        const double parts[2] = {(j & 1) ? pt.s2 : pt.s1_hi, (j & 1) ? 0.0 : pt.s1_lo};
+        for (int q = 0; q < 2; ++q) {
+          const double x = parts[q];
+          if (x == 0.0) continue;
+          if (!(fabs(x) <= 1.7976931348623157e308)) {
+            special |= x != x ? 4ull : (x > 0 ? 1ull : 2ull);
+            continue;
+          }
+          uint32_t k;
+          unsigned long long d[3];
+          digits_of(x, &k, d);
+          if (k != wk) {
+            if (wk != 0xffffffffu) {
+              w[(size_t)wk * kWave] += r0;
+              w[(size_t)(wk + 1) * kWave] += r1;
+              w[(size_t)(wk + 2) * kWave] += r2;
+            }
+            wk = k;
+            r0 = r1 = r2 = 0;
+          }
+          r0 += d[0];
+          r1 += d[1];
+          r2 += d[2];
+        }
+      }
+      if (wk != 0xffffffffu) {
+        w[(size_t)wk * kWave] += r0;
+        w[(size_t)(wk + 1) * kWave] += r1;
+        w[(size_t)(wk + 2) * kWave] += r2;
+      }
+      const double v = acc_round(w, kWave, special);
+      const double mm = N > 0 ? v / N : 0.0;
+      if (j & 1) {
+        m2[b] = mm;
+        if (a.s2) a.s2[(size_t)row * B + b] = v;
+      } else {
+        m1[b] = mm;
+        coef[b] = scale * mm;
+        if (a.s1) a.s1[(size_t)row * B + b] = v;
+        if (a.coef) a.coef[(size_t)row * B + b] = scale * mm;
+      }
     }
   }
   __syncthreads();
+  for (uint32_t b = lane; b < B; b += kWave) {
+    const double var = N > 1 ? scale * scale * (m2[b] - m1[b] * m1[b]) / (N - 1.0) : 0.0;
+    if (a.coef_var) a.coef_var[(size_t)row * B + b] = var;
+  }
   unsigned long long nodes = 0;
   for (uint32_t s = lane; s < pr.seg_count; s += kWave) nodes += a.seg_nodes[pr.seg_begin + s];
   nodes = wave_sum_u64(nodes);

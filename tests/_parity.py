@@ -141,6 +141,37 @@ def compare_moments(wl, gpu, omom, tol):
         assert np.all(d2 <= (2 * tol + 1e-13) * m["s2"] + 1e-300), (p, d2, m["s2"])
 
 
+def _ulps(a, b):
+    """Distance in units in the last place between two finite doubles of the same sign (0 if equal)."""
+    if a == b:
+        return 0
+    ia = np.array([a], np.float64).view(np.int64)[0]
+    ib = np.array([b], np.float64).view(np.int64)[0]
+    return abs(int(ia) - int(ib)) if (a > 0) == (b > 0) else 1 << 62
+
+
+def check_exact_sums(wl, gpu, rec_idx, point_idx):
+    """The device's per-bin sums against the exactly rounded sums of its own tree values (math.fsum).
+    S1 within 1 ulp: the device sums each segment in double-double (error at most about 2^-100 sum|F|) and
+    joins the segments exactly, so it differs from the exactly rounded sum only where that sum lies within
+    its error of a rounding midpoint (FP32-path values have short significands, and sums of a few of them
+    can sit exactly on a midpoint).  S2 (sum of F*F, positive terms, plain FP64 per lane in a fixed order,
+    segments joined exactly) within 1e-13 relative."""
+    B = oracle.n_bins(wl["mc"])
+    ne, flags, depth, _ = decode_meta(gpu["tree_meta"][rec_idx])
+    F = gpu["tree_f"][rec_idx].astype(np.float64)
+    ok = (flags == 0) & (depth == 0)
+    b = np.minimum(ne, B - 1)
+    for p in range(len(wl["t"])):
+        sel = ok & (point_idx == p)
+        for k in range(B):
+            v = F[sel & (b == k)]
+            s1 = math.fsum(v.tolist())
+            s2 = math.fsum((v * v).tolist())
+            assert _ulps(gpu["s1"][p][k], s1) <= 1, (p, k, gpu["s1"][p][k], s1)
+            assert abs(gpu["s2"][p][k] - s2) <= 1e-13 * s2, (p, k, gpu["s2"][p][k], s2)
+
+
 def oracle_pade(wl, omom):
     """Oracle coefficients and Pade summary (value, degrees, SE, neighbours, kappa, pole) per point from
     exact moments."""

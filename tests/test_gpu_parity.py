@@ -42,6 +42,7 @@ def _full_parity(ctx, name, wl, launch=None, pade_tol=1e-3):
     worst = P.compare_trees(gpu, ri, orc, tol, pi)
     omom = P.oracle_moments(wl, orc, pi)
     P.compare_moments(wl, gpu, omom, tol)
+    P.check_exact_sums(wl, gpu, ri, pi)
     opade = P.oracle_pade(wl, omom)
     B = oracle.n_bins(wl["mc"])
     for p, r in enumerate(opade):
