@@ -286,6 +286,25 @@ void brt_plan_destroy(brt_plan* plan);
 int brt_solve(brt_ctx* ctx, uint32_t n_problems, const brt_problem* problems, const brt_mc* mc,
               const brt_points* points, const brt_out* out, void* stream);
 
+/* brt_solve for callers that cannot allocate (code under graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same arguments and bit-identical results, with no device or
+ * host allocation.  Every buffer brt_solve would allocate (problem table, point records, work chunks,
+ * reduction partials, counters and, when out->tree_f / out->tree_meta are NULL, the tree records)
+ * lives in one device array of the library, fixed in size, which each GPU the library runs on holds
+ * until the process ends; the host tables live in fixed arrays.  Limits: at most
+ * BRT_NOALLOC_MAX_POINTS points and BRT_NOALLOC_MAX_TREES trees in one call, pruning on and
+ * 1 <= max_order <= BRT_NOALLOC_MAX_ORDER (the walker's stack is held in LDS only); beyond them it
+ * returns BRT_E_ARG with a message and runs nothing.  All calls on one GPU share that array and
+ * keep nothing from the previous call: calls that overlapped would race on it, so the library runs
+ * them one at a time under a process-wide lock, and each call waits for its stream before it
+ * returns.  The caller passes and owns the outputs as for brt_solve.  Returns BRT_E_RANGE if a tree
+ * exceeded the stack depth. */
+#define BRT_NOALLOC_MAX_POINTS 4096u
+#define BRT_NOALLOC_MAX_TREES (1u << 22)
+#define BRT_NOALLOC_MAX_ORDER 16u
+int brt_solve_noalloc(brt_ctx* ctx, uint32_t n_problems, const brt_problem* problems, const brt_mc* mc,
+                      const brt_points* points, const brt_out* out, void* stream);
+
 /* Autotuner: time the tree walker for candidate launch settings (waves per block 1/2/4, LDS stack
  * levels 4..16, chunk sizes 256/1024/4096 trees) on the given points (subsampled to about 2^28 trees
  * when larger; fastest of three runs), set the fastest on the context (used by plans and servers

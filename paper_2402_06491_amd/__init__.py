@@ -126,6 +126,9 @@ _SIGS = [
     ("brt_plan_destroy", None, [ctypes.c_void_p]),
     ("brt_solve", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.POINTER(Problem), ctypes.POINTER(MC),
                                  ctypes.POINTER(Points), ctypes.POINTER(Out), ctypes.c_void_p]),
+    ("brt_solve_noalloc", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.POINTER(Problem),
+                                         ctypes.POINTER(MC), ctypes.POINTER(Points), ctypes.POINTER(Out),
+                                         ctypes.c_void_p]),
     ("brt_autotune", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.POINTER(Problem), ctypes.POINTER(MC),
                                     ctypes.POINTER(Points), ctypes.c_char_p, ctypes.POINTER(Launch)]),
     ("brt_server_create", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ServerOpts), ctypes.POINTER(ctypes.c_void_p)]),
@@ -407,8 +410,8 @@ class Plan:
 
 
 def solve(ctx: Context, problems, mc: dict, x, t, n_trees, problem_id=None, point_id=None, records=True,
-          stream=None):
-    """One-shot brt_solve; returns the output tensors (on the GPU)."""
+          stream=None, noalloc=False):
+    """One-shot brt_solve (brt_solve_noalloc with noalloc=True); returns the output tensors (on the GPU)."""
     if isinstance(problems, dict):
         problems = [problems]
     arr = (Problem * len(problems))(*[make_problem(p) for p in problems])
@@ -418,8 +421,8 @@ def solve(ctx: Context, problems, mc: dict, x, t, n_trees, problem_id=None, poin
     nb = int(mc.get("max_order", 12)) + 2
     tensors = alloc_outputs(n, nb, total, int(mc.get("precision", 32)), records)
     o = make_out(tensors)
-    _check(lib().brt_solve(ctx._h, len(problems), arr, ctypes.byref(m), ctypes.byref(pts), ctypes.byref(o),
-                           _stream_handle(stream)))
+    fn = lib().brt_solve_noalloc if noalloc else lib().brt_solve
+    _check(fn(ctx._h, len(problems), arr, ctypes.byref(m), ctypes.byref(pts), ctypes.byref(o), _stream_handle(stream)))
     return tensors
 
 

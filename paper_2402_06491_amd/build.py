@@ -8,7 +8,8 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libbrt.so")
-SOURCES = ["brt_kernels.hip", "brt_moments.hip", "brt_runtime.hip", "brt_serve.hip", "brt_tune.hip", "brt_pdd.hip"]
+SOURCES = ["brt_kernels.hip", "brt_moments.hip", "brt_runtime.hip", "brt_serve.hip", "brt_tune.hip", "brt_pdd.hip",
+           "brt_noalloc.hip"]
 # Packed FP32 VALU forms are disabled for every HIP translation unit (the compiler would otherwise
 # form v_pk_* from ordinary float code).
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall",

@@ -148,6 +148,21 @@ struct FinalizeArgs {
   double* pade_diag;  // [n][BRT_PADE_DIAG] (nullable)
 };
 
+}  // namespace brt
+
+// A context: one HIP device and its launch settings (brt_runtime.hip).
+struct brt_ctx {
+  int device = 0;
+  int n_cu = 0;
+  brt_launch launch{};
+};
+
+namespace brt {
+
+// Look up the address of the allocation-free entry point's scratch array on `device` (current) once per
+// device (brt_noalloc.hip); BRT_E_DEVICE if the lookup fails.
+int noalloc_init_device(int device);
+
 // Strategy A normalisation of one problem (brt_runtime.hip).
 struct Norm {
   double sigma = 0, lambda = 0, inv_lambda = 0, mu = 0;

@@ -160,12 +160,6 @@ double est_nodes(const Norm& n, const brt_mc& mc, double t) {
 
 }  // namespace brt
 
-struct brt_ctx {
-  int device = 0;
-  int n_cu = 0;
-  brt_launch launch{};
-};
-
 struct brt_plan {
   brt_ctx* ctx = nullptr;
   int precision = 32, dim = 1, u0_kind = 0;
@@ -227,6 +221,12 @@ int brt_create(brt_ctx** out, int device) {
   c->launch.blocks_per_cu = 0;
   c->launch.chunk_trees = 1024;
   c->launch.stack_depth = 0;
+  // the allocation-free entry point's scratch array: its address on this device, looked up once
+  const int rc = noalloc_init_device(device);
+  if (rc) {
+    delete c;
+    return rc;
+  }
   *out = c;
   g_err.clear();
   return BRT_OK;
