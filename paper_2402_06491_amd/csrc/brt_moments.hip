@@ -69,52 +69,62 @@ __host__ __device__ __forceinline__ void digits_of(double v, uint32_t* k, unsign
   d[2] = neg ? (unsigned long long)(0ull - d2) : d2;
 }
 
-// The digit words of one sum (kAccWords signed words, word k weighing 2^(32k - 1074), word k at
-// w[k * stride]) rounded once to the nearest double, ties to even; special = the non-finite values seen
-// (bit 0 +inf, bit 1 -inf, bit 2 NaN).
-__host__ __device__ double acc_round(const unsigned long long* w, int stride, unsigned long long special) {
+// The digit words of one sum (kAccWords signed words w[0..kAccWords), word k weighing 2^(32k - 1074)) rounded
+// once to the nearest double, ties to even; special = the non-finite values seen (bit 0 +inf, bit 1 -inf,
+// bit 2 NaN).  Only the span of nonzero words and the two words above it take part (a word holds a sum of
+// fewer than 2^31 digits, so its carry dies out within two words); the span is overwritten by the 32-bit
+// digits of the magnitude.
+__host__ __device__ double acc_round(unsigned long long* w, unsigned long long special) {
   if (special & 4ull) return NAN;
   if ((special & 3ull) == 3ull) return NAN;
   if (special & 1ull) return INFINITY;
   if (special & 2ull) return -INFINITY;
+  int lo = -1, hi = -1;
+  for (int k = 0; k < kAccWords; ++k)
+    if (w[k] != 0ull) {
+      hi = k;
+      if (lo < 0) lo = k;
+    }
+  if (lo < 0) return 0.0;
+  const int top = hi + 2 < kAccWords ? hi + 2 : kAccWords - 1;
   // carry-propagate into 32-bit digits; the final carry is the sign (0 or -1)
-  uint32_t dg[kAccWords];
   long long carry = 0;
-  for (int k = 0; k < kAccWords; ++k) {
-    const long long t = (long long)w[(size_t)k * stride] + carry;
-    dg[k] = (uint32_t)((unsigned long long)t & 0xffffffffull);
+  for (int k = lo; k <= top; ++k) {
+    const long long t = (long long)w[k] + carry;
+    w[k] = (unsigned long long)t & 0xffffffffull;
     carry = t >> 32;
   }
   const bool neg = carry < 0;
-  if (neg) {  // magnitude of the two's complement number
+  if (neg) {  // magnitude of the two's complement number (the zero digits below lo pass a carry of 1 up)
     unsigned long long c = 1;
-    for (int k = 0; k < kAccWords; ++k) {
-      const unsigned long long t = (unsigned long long)(uint32_t)~dg[k] + c;
-      dg[k] = (uint32_t)t;
+    for (int k = lo; k <= top; ++k) {
+      const unsigned long long t = (unsigned long long)(uint32_t)~(uint32_t)w[k] + c;
+      w[k] = t & 0xffffffffull;
       c = t >> 32;
     }
   }
-  int K = kAccWords - 1;
-  while (K >= 0 && dg[K] == 0) --K;
-  if (K < 0) return 0.0;
+  int K = top;
+  while (K >= lo && w[K] == 0ull) --K;
+  if (K < lo) return 0.0;
   // the 64 bits from the leading one down (left-aligned), and whether anything nonzero lies below them
+  const uint32_t dK = (uint32_t)w[K];
   int nb = 32;
-  while (!((dg[K] >> (nb - 1)) & 1u)) --nb;  // bit length of the leading digit
+  while (!((dK >> (nb - 1)) & 1u)) --nb;  // bit length of the leading digit
   const long long msb = 32ll * K + nb - 1;  // position of the leading one (bit 0 weighs 2^-1074)
   // digits K, K-1, K-2 as a 96-bit window [d2 d1 d0], shifted so that the leading one is bit 63 of top
-  const unsigned long long d2 = dg[K], d1 = K >= 1 ? dg[K - 1] : 0u, d0 = K >= 2 ? dg[K - 2] : 0u;
+  const unsigned long long d2 = dK, d1 = K >= 1 ? (uint32_t)w[K - 1] : 0u, d0 = K >= 2 ? (uint32_t)w[K - 2] : 0u;
   const unsigned long long hi64 = (d2 << 32) | d1;  // bits 32K + 31 .. 32K - 32
   const int sh = 32 - nb;                           // left shift that puts the leading one at bit 63
-  const unsigned long long top = sh ? (hi64 << sh) | (d0 >> (32 - sh)) : hi64;
+  const unsigned long long topb = sh ? (hi64 << sh) | (d0 >> (32 - sh)) : hi64;
   bool sticky = sh ? ((d0 & ((1ull << (32 - sh)) - 1)) != 0) : (d0 != 0);
-  for (int k = 0; k < K - 2 && !sticky; ++k) sticky = dg[k] != 0;
+  for (int k = lo; k < K - 2 && !sticky; ++k) sticky = w[k] != 0ull;
   double r;
   if (msb <= 52) {
     // at most 53 significant bits with lowest weight 2^-1074: exactly representable
-    r = ldexp((double)(top >> (63 - msb)), -1074);
+    r = ldexp((double)(topb >> (63 - msb)), -1074);
   } else {
-    unsigned long long mant = top >> 11;          // 53 bits
-    const unsigned long long rem = top & 0x7ffull;
+    unsigned long long mant = topb >> 11;          // 53 bits
+    const unsigned long long rem = topb & 0x7ffull;
     if (rem > 0x400ull || (rem == 0x400ull && (sticky || (mant & 1ull)))) mant += 1;
     long long e2 = msb - 52 - 1074;
     if (mant >> 53) {
@@ -238,7 +248,6 @@ __global__ __launch_bounds__(kWave) void reduce_kernel(ReduceArgs a) {
 }
 
 constexpr int kMaxBins = 128;  // B = max_order + 2 <= 128
-constexpr int kMaxPadeM = 16;
 // Degree selection of the approximant: a singular value of the denominator's linear conditions counts as
 // zero when it is at most kPadeTol times the 2-norm of the coefficients a_0..a_{L+M}.
 constexpr double kPadeTol = 1e-12;
@@ -247,177 +256,15 @@ constexpr double kPadeTol = 1e-12;
 constexpr double kPoleDist = 0.5;
 constexpr double kSensitive = 100.0;
 constexpr int kWindingSamples = 32;  // samples of the pole-test contour per lane (2048 per point)
+constexpr int kJoinGroup = 16;       // bins joined per pass of the finalize
+constexpr int kAccStride = kAccWords + 1;  // LDS column of one exact sum (padded against bank conflicts)
 
 __host__ __device__ __forceinline__ double coef_at(const double* a, int k) { return k >= 0 ? a[k] : 0.0; }
-
-// Singular values of the n_vec x len matrix whose rows are stored in V (row i at V[i * len]), by one-sided
-// Jacobi rotations of those rows (Hestenes): rotate pairs of rows until every pair is orthogonal; the row
-// norms are then the singular values (n_vec <= len).  Squared row norms are kept and updated by the
-// rotation identities (a' = a - t g, b' = b + t g), recomputed at the start of every sweep.  V is
-// overwritten; sv[0..n_vec) comes out descending.
-__host__ __device__ void jacobi_singular_values(double* V, int n_vec, int len, double* sv) {
-  double nrm[kMaxPadeM + 1];
-  for (int sweep = 0; sweep < 64; ++sweep) {
-    for (int i = 0; i < n_vec; ++i) {
-      double n2 = 0.0;
-      for (int k = 0; k < len; ++k) n2 += V[i * len + k] * V[i * len + k];
-      nrm[i] = n2;
-    }
-    bool rotated = false;
-    for (int i = 0; i < n_vec - 1; ++i)
-      for (int j = i + 1; j < n_vec; ++j) {
-        double ga = 0.0;
-        for (int k = 0; k < len; ++k) ga += V[i * len + k] * V[j * len + k];
-        const double al = nrm[i], be = nrm[j];
-        if (ga == 0.0 || ga * ga <= 1e-30 * (al * be)) continue;
-        rotated = true;
-        // tan of the rotation angle, the smaller root of t^2 + 2 zeta t - 1 = 0 with zeta = (be - al)/(2 ga)
-        const double d = be - al;
-        const double t = (d >= 0.0 ? 2.0 * ga : -2.0 * ga) / (fabs(d) + sqrt(d * d + 4.0 * ga * ga));
-        const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-        for (int k = 0; k < len; ++k) {
-          const double x = V[i * len + k], y = V[j * len + k];
-          V[i * len + k] = c * x - s * y;
-          V[j * len + k] = s * x + c * y;
-        }
-        nrm[i] = al - t * ga;
-        nrm[j] = be + t * ga;
-      }
-    if (!rotated) break;
-  }
-  for (int i = 0; i < n_vec; ++i) {
-    double n2 = 0.0;
-    for (int k = 0; k < len; ++k) n2 += V[i * len + k] * V[i * len + k];
-    sv[i] = sqrt(n2);
-  }
-  for (int i = 1; i < n_vec; ++i)  // insertion sort, descending
-    for (int j = i; j > 0 && sv[j] > sv[j - 1]; --j) {
-      const double tmp = sv[j];
-      sv[j] = sv[j - 1];
-      sv[j - 1] = tmp;
-    }
-}
-
-// LU factorisation with partial pivoting, in place (row-major M x M, multipliers below the diagonal),
-// perm[i] = original row now at position i.  False on a zero or non-finite pivot.
-__host__ __device__ bool lu_factor(double* T, int M, int* perm) {
-  for (int i = 0; i < M; ++i) perm[i] = i;
-  for (int c = 0; c < M; ++c) {
-    int piv = c;
-    double best = fabs(T[c * M + c]);
-    for (int r = c + 1; r < M; ++r) {
-      const double v = fabs(T[r * M + c]);
-      if (v > best || !(v == v)) {
-        best = v;
-        piv = r;
-      }
-    }
-    if (!(best == best) || best > 1.7e308 || best == 0.0) return false;
-    if (piv != c) {
-      for (int j = 0; j < M; ++j) {
-        const double tmp = T[c * M + j];
-        T[c * M + j] = T[piv * M + j];
-        T[piv * M + j] = tmp;
-      }
-      const int tp = perm[c];
-      perm[c] = perm[piv];
-      perm[piv] = tp;
-    }
-    const double inv = 1.0 / T[c * M + c];
-    for (int r = c + 1; r < M; ++r) {
-      const double l = T[r * M + c] * inv;
-      T[r * M + c] = l;
-      for (int j = c + 1; j < M; ++j) T[r * M + j] -= l * T[c * M + j];
-    }
-  }
-  return true;
-}
 
 struct Order {
   int L, M;
   double margin;  // smallest distance (as a ratio) of a deciding singular value from the threshold
 };
-
-// Degrees used for a requested [L/M]: the rows of C (C[i][j] = a_{L+1+i-j}, i < M, j <= M) are the linear
-// conditions C q = 0 on the denominator.  With s = ||a_0..a_{L+M}||_2 and rho the singular values of C above
-// kPadeTol s: rho < M lowers both degrees by M - rho; a full-rank C whose square block C[:, 1:] has its
-// smallest singular value at most kPadeTol s (no denominator with q_0 = 1) moves to [L+1/M-1].  The square
-// block is looked at first (by a bound from its LU factors, then by its singular values): when its smallest
-// singular value is above the threshold, so are all of C's, and C itself is not decomposed.  V holds
-// (M+1)^2 doubles of scratch.
-__host__ __device__ Order select_order(const double* a, int L, int M, double* V) {
-  Order o{L, M, HUGE_VAL};
-  double s2 = 0.0;
-  for (int k = 0; k <= L + M; ++k) s2 += a[k] * a[k];
-  const double s = sqrt(s2);
-  if (!(s > 0.0) || !(s <= 1.7e308)) return Order{0, 0, HUGE_VAL};
-  const double thr = kPadeTol * s;
-  double sv[kMaxPadeM];
-  auto note = [&](double v) {
-    if (v > 0.0) {
-      const double r = v > thr ? v / thr : thr / v;
-      o.margin = r < o.margin ? r : o.margin;
-    }
-  };
-  while (o.M > 0) {
-    const int m = o.M, l = o.L;
-    // Shortcut for the common case, equivalent to the singular-value rule below: the square block T = C[:, 1:]
-    // has sigma_min(T) >= 1 / ||T^-1||_F, and every singular value of C is at least the matching one of T
-    // (C C^T = c c^T + T T^T).  A bound well above the threshold settles it: full rank, denominator with
-    // q_0 = 1, no change of degrees; the margin reported is then this lower bound.
-    {
-      int piv[kMaxPadeM];
-      for (int i = 0; i < m; ++i)
-        for (int j = 0; j < m; ++j) V[i * m + j] = coef_at(a, l + i - j);
-      if (lu_factor(V, m, piv)) {
-        double fro2 = 0.0;
-        for (int c = 0; c < m; ++c) {  // column c of T^-1: L y = P e_c, U x = y
-          double x[kMaxPadeM];
-          for (int i = 0; i < m; ++i) {
-            double v = piv[i] == c ? 1.0 : 0.0;
-            for (int j = 0; j < i; ++j) v -= V[i * m + j] * x[j];
-            x[i] = v;
-          }
-          for (int i = m - 1; i >= 0; --i) {
-            double v = x[i];
-            for (int j = i + 1; j < m; ++j) v -= V[i * m + j] * x[j];
-            x[i] = v / V[i * m + i];
-            fro2 += x[i] * x[i];
-          }
-        }
-        const double lb = 1.0 / sqrt(fro2);
-        if (lb > 64.0 * thr && lb <= 1.7e308) {
-          note(lb);
-          break;
-        }
-      }
-    }
-    // the square block first: sigma_min(C[:, 1:]) above the threshold gives full rank of C as well
-    for (int i = 0; i < m; ++i)
-      for (int j = 0; j < m; ++j) V[i * m + j] = coef_at(a, l + i - j);  // C[i][j + 1]
-    double svT[kMaxPadeM];
-    jacobi_singular_values(V, m, m, svT);
-    note(svT[m - 1]);
-    if (svT[m - 1] > thr) break;
-    for (int i = 0; i < m; ++i)
-      for (int j = 0; j <= m; ++j) V[i * (m + 1) + j] = coef_at(a, l + 1 + i - j);
-    jacobi_singular_values(V, m, m + 1, sv);
-    int rho = 0;
-    while (rho < m && sv[rho] > thr) ++rho;
-    if (rho < m) {
-      note(sv[rho]);
-      if (rho > 0) note(sv[rho - 1]);
-      o.L = l - (m - rho) > 0 ? l - (m - rho) : 0;
-      o.M = rho;
-      continue;
-    }
-    note(sv[m - 1]);
-    // C has full rank but its square block does not: no denominator with q_0 = 1
-    o.L = l + 1;
-    o.M = m - 1;
-  }
-  return o;
-}
 
 struct PadeResult {
   double value;
@@ -425,95 +272,360 @@ struct PadeResult {
   double margin;  // of their selection
 };
 
-// [L/M] at z = 1 of sum_n a_n z^n with the degrees from select_order.  The denominator q (q_0 = 1) solves
-// sum_{j=0}^{M} q_j a_{k-j} = 0 for k = L+1..L+M (a_i = 0 for i < 0); with partial sums
-// A_m = a_0 + ... + a_m the value is sum_j q_j A_{L-j} / sum_j q_j.  On return T holds the LU factors
-// (M x M), perm the pivoting and q the denominator (for pade_gradient).
-__host__ __device__ PadeResult pade(const double* a, int L, int M, double* q, double* T, int* perm, double* V) {
-  const Order o = select_order(a, L, M, V);
-  PadeResult r{0.0, o.L, o.M, o.margin};
-  while (true) {
-    q[0] = 1.0;
-    const int m = r.M, l = r.L;
-    if (m == 0) break;
-    for (int i = 0; i < m; ++i)
-      for (int j = 0; j < m; ++j) T[i * m + j] = coef_at(a, l + i - j);  // T_{ij} = a_{L+i-j}, i, j = 1..M
-    if (lu_factor(T, m, perm)) {
-      double y[kMaxPadeM];
-      for (int i = 0; i < m; ++i) {  // forward: L y = P (-b)
-        double s = -a[l + 1 + perm[i]];
-        for (int j = 0; j < i; ++j) s -= T[i * m + j] * y[j];
-        y[i] = s;
+// The small dense linear algebra of the Pade step for denominators of degree M <= MM.  Every array has a
+// compile-time size and every loop runs to MM with the runtime size as a guard, so that after unrolling
+// all indices are constants and the arrays live in registers (the coefficients a_n are read from LDS).
+template <int MM>
+struct SmallPade {
+  // Singular values of the nv x len matrix with rows V[0..nv) (nv <= len <= MM + 1), by one-sided Jacobi
+  // rotations of those rows (Hestenes): rotate pairs of rows, in cyclic order, until every pair is
+  // orthogonal; the row norms are then the singular values.  Squared row norms are kept and updated by
+  // the rotation identities (a' = a - t g, b' = b + t g), recomputed at the start of every sweep.  V is
+  // overwritten; sv[0..nv) comes out descending.
+  __host__ __device__ static void singular_values(double (&V)[MM][MM + 1], int nv, int len, double (&sv)[MM]) {
+    double nrm[MM];
+    for (int sweep = 0; sweep < 64; ++sweep) {
+#pragma unroll
+      for (int i = 0; i < MM; ++i) {
+        double n2 = 0.0;
+#pragma unroll
+        for (int k = 0; k <= MM; ++k)
+          if (k < len) n2 += V[i][k] * V[i][k];
+        nrm[i] = n2;
       }
-      for (int i = m - 1; i >= 0; --i) {  // backward: U q = y
-        double s = y[i];
-        for (int j = i + 1; j < m; ++j) s -= T[i * m + j] * q[j + 1];
-        q[i + 1] = s / T[i * m + i];
+      bool rotated = false;
+#pragma unroll
+      for (int i = 0; i < MM - 1; ++i) {
+#pragma unroll
+        for (int j = i + 1; j < MM; ++j) {
+          if (j >= nv) continue;
+          double ga = 0.0;
+#pragma unroll
+          for (int k = 0; k <= MM; ++k)
+            if (k < len) ga += V[i][k] * V[j][k];
+          const double al = nrm[i], be = nrm[j];
+          if (ga == 0.0 || ga * ga <= 1e-30 * (al * be)) continue;
+          rotated = true;
+          // tan of the rotation angle, the smaller root of t^2 + 2 zeta t - 1 = 0 with zeta = (be - al)/(2 ga)
+          const double d = be - al;
+          const double t = (d >= 0.0 ? 2.0 * ga : -2.0 * ga) / (fabs(d) + sqrt(d * d + 4.0 * ga * ga));
+          const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+#pragma unroll
+          for (int k = 0; k <= MM; ++k) {
+            if (k >= len) continue;
+            const double x = V[i][k], y = V[j][k];
+            V[i][k] = c * x - s * y;
+            V[j][k] = s * x + c * y;
+          }
+          nrm[i] = al - t * ga;
+          nrm[j] = be + t * ga;
+        }
       }
-      break;
+      if (!rotated) break;
     }
-    r.L = l + 1;  // an exactly singular square system (the rank test keeps these out): next antidiagonal entry
-    r.M = m - 1;
+#pragma unroll
+    for (int i = 0; i < MM; ++i) {
+      double n2 = 0.0;
+#pragma unroll
+      for (int k = 0; k <= MM; ++k)
+        if (k < len) n2 += V[i][k] * V[i][k];
+      sv[i] = i < nv ? sqrt(n2) : 0.0;
+    }
+    // descending order (the unused entries are zeros and stay behind the used ones)
+#pragma unroll
+    for (int pass = 0; pass < MM - 1; ++pass)
+#pragma unroll
+      for (int i = 0; i < MM - 1 - pass; ++i)
+        if (sv[i + 1] > sv[i]) {
+          const double tmp = sv[i];
+          sv[i] = sv[i + 1];
+          sv[i + 1] = tmp;
+        }
   }
-  double num = 0.0, den = 0.0;
-  for (int j = 0; j <= r.M; ++j) {
-    double A = 0.0;
-    for (int i = 0; i <= r.L - j; ++i) A += a[i];
-    num += q[j] * A;
-    den += q[j];
-  }
-  r.value = num / den;
-  return r;
-}
 
-// Gradient g_k = d value / d a_k (k = 0..L+M) of the approximant returned by pade().  With
-// D = sum_j q_j and c_j = (A_{L-j} - value)/D, solve T^T y = c; then
-//   g_k = [k <= L] sum_{j=0}^{min(M, L-k)} q_j / D  -  sum_{i=1}^{M} y_i q_{L+i-k}  (0 <= L+i-k <= M).
-__host__ __device__ void pade_gradient(const double* a, const PadeResult& r, const double* q, const double* T,
-                              const int* perm, double* g) {
-  const int L = r.L, M = r.M;
-  double D = 0.0;
-  for (int j = 0; j <= M; ++j) D += q[j];
-  double y[kMaxPadeM];
-  if (M > 0) {
-    double v[kMaxPadeM];
-    for (int i = 0; i < M; ++i) {  // U^T v = c
+  // LU factorisation with partial pivoting of the m x m block T, in place (multipliers below the
+  // diagonal); perm[i] = original row now at position i.  False on a zero or non-finite pivot.
+  __host__ __device__ static bool lu(double (&T)[MM][MM], int m, int (&perm)[MM]) {
+#pragma unroll
+    for (int i = 0; i < MM; ++i) perm[i] = i;
+#pragma unroll
+    for (int c = 0; c < MM; ++c) {
+      if (c >= m) break;
+      int piv = c;
+      double best = fabs(T[c][c]);
+#pragma unroll
+      for (int r = c + 1; r < MM; ++r) {
+        if (r >= m) continue;
+        const double v = fabs(T[r][c]);
+        if (v > best || !(v == v)) {
+          best = v;
+          piv = r;
+        }
+      }
+      if (!(best == best) || best > 1.7e308 || best == 0.0) return false;
+#pragma unroll
+      for (int r = c + 1; r < MM; ++r) {
+        if (r != piv) continue;
+#pragma unroll
+        for (int j = 0; j < MM; ++j) {
+          const double tmp = T[c][j];
+          T[c][j] = T[r][j];
+          T[r][j] = tmp;
+        }
+        const int tp = perm[c];
+        perm[c] = perm[r];
+        perm[r] = tp;
+      }
+      const double inv = 1.0 / T[c][c];
+#pragma unroll
+      for (int r = c + 1; r < MM; ++r) {
+        if (r >= m) continue;
+        const double l = T[r][c] * inv;
+        T[r][c] = l;
+#pragma unroll
+        for (int j = c + 1; j < MM; ++j)
+          if (j < m) T[r][j] -= l * T[c][j];
+      }
+    }
+    return true;
+  }
+
+  // T_{ij} = a_{l+i-j}, i, j < m: the square block of the denominator's conditions.
+  __host__ __device__ static void toeplitz(const double* a, int l, int m, double (&T)[MM][MM]) {
+#pragma unroll
+    for (int i = 0; i < MM; ++i)
+#pragma unroll
+      for (int j = 0; j < MM; ++j) T[i][j] = (i < m && j < m) ? coef_at(a, l + i - j) : 0.0;
+  }
+
+  // Degrees used for a requested [L/M]: the rows of C (C[i][j] = a_{L+1+i-j}, i < M, j <= M) are the linear
+  // conditions C q = 0 on the denominator.  With s = ||a_0..a_{L+M}||_2 and rho the singular values of C
+  // above kPadeTol s: rho < M lowers both degrees by M - rho; a full-rank C whose square block C[:, 1:] has
+  // its smallest singular value at most kPadeTol s (no denominator with q_0 = 1) moves to [L+1/M-1].  The
+  // square block is looked at first (by a bound from its LU factors, then by its singular values): when its
+  // smallest singular value is above the threshold, so are all of C's, and C itself is not decomposed.
+  __host__ __device__ static Order select_order(const double* a, int L, int M) {
+    Order o{L, M, HUGE_VAL};
+    double s2 = 0.0;
+    for (int k = 0; k <= L + M; ++k) s2 += a[k] * a[k];
+    const double s = sqrt(s2);
+    if (!(s > 0.0) || !(s <= 1.7e308)) return Order{0, 0, HUGE_VAL};
+    const double thr = kPadeTol * s;
+    auto note = [&](double v) {
+      if (v > 0.0) {
+        const double r = v > thr ? v / thr : thr / v;
+        o.margin = r < o.margin ? r : o.margin;
+      }
+    };
+    while (o.M > 0) {
+      const int m = o.M, l = o.L;
+      // Shortcut for the common case, equivalent to the singular-value rule below: the square block
+      // T = C[:, 1:] has sigma_min(T) >= 1 / ||T^-1||_F, and every singular value of C is at least the
+      // matching one of T (C C^T = c c^T + T T^T).  A bound well above the threshold settles it: full rank,
+      // denominator with q_0 = 1, no change of degrees; the margin reported is then this lower bound.
+      {
+        double T[MM][MM];
+        int piv[MM];
+        toeplitz(a, l, m, T);
+        if (lu(T, m, piv)) {
+          double fro2 = 0.0;
+#pragma unroll
+          for (int c = 0; c < MM; ++c) {  // column c of T^-1: L y = P e_c, U x = y
+            if (c >= m) continue;
+            double x[MM];
+#pragma unroll
+            for (int i = 0; i < MM; ++i) {
+              double v = piv[i] == c ? 1.0 : 0.0;
+#pragma unroll
+              for (int j = 0; j < i; ++j) v -= T[i][j] * x[j];
+              x[i] = v;
+            }
+#pragma unroll
+            for (int i = MM - 1; i >= 0; --i) {
+              if (i >= m) continue;
+              double v = x[i];
+#pragma unroll
+              for (int j = i + 1; j < MM; ++j)
+                if (j < m) v -= T[i][j] * x[j];
+              x[i] = v / T[i][i];
+              fro2 += x[i] * x[i];
+            }
+          }
+          const double lb = 1.0 / sqrt(fro2);
+          if (lb > 64.0 * thr && lb <= 1.7e308) {
+            note(lb);
+            break;
+          }
+        }
+      }
+      double V[MM][MM + 1];
+      double sv[MM];
+      // the square block first: sigma_min(C[:, 1:]) above the threshold gives full rank of C as well
+#pragma unroll
+      for (int i = 0; i < MM; ++i)
+#pragma unroll
+        for (int j = 0; j <= MM; ++j) V[i][j] = (i < m && j < m) ? coef_at(a, l + i - j) : 0.0;  // C[i][j + 1]
+      singular_values(V, m, m, sv);
+      double last = 0.0;
+#pragma unroll
+      for (int i = 0; i < MM; ++i)
+        if (i == m - 1) last = sv[i];
+      note(last);
+      if (last > thr) break;
+#pragma unroll
+      for (int i = 0; i < MM; ++i)
+#pragma unroll
+        for (int j = 0; j <= MM; ++j) V[i][j] = (i < m && j <= m) ? coef_at(a, l + 1 + i - j) : 0.0;
+      singular_values(V, m, m + 1, sv);
+      int rho = 0;
+#pragma unroll
+      for (int i = 0; i < MM; ++i)
+        if (i < m && rho == i && sv[i] > thr) rho = i + 1;
+      if (rho < m) {
+        double at = 0.0, below = 0.0;
+#pragma unroll
+        for (int i = 0; i < MM; ++i) {
+          if (i == rho) at = sv[i];
+          if (i == rho - 1) below = sv[i];
+        }
+        note(at);
+        if (rho > 0) note(below);
+        o.L = l - (m - rho) > 0 ? l - (m - rho) : 0;
+        o.M = rho;
+        continue;
+      }
+      double lastc = 0.0;
+#pragma unroll
+      for (int i = 0; i < MM; ++i)
+        if (i == m - 1) lastc = sv[i];
+      note(lastc);
+      // C has full rank but its square block does not: no denominator with q_0 = 1
+      o.L = l + 1;
+      o.M = m - 1;
+    }
+    return o;
+  }
+
+  // [L/M] at z = 1 of sum_n a_n z^n with the degrees from select_order.  The denominator q (q_0 = 1) solves
+  // sum_{j=0}^{M} q_j a_{k-j} = 0 for k = L+1..L+M (a_i = 0 for i < 0); with partial sums
+  // A_m = a_0 + ... + a_m the value is sum_j q_j A_{L-j} / sum_j q_j.  On return T holds the LU factors,
+  // perm the pivoting and q the denominator (for gradient), q_j = 0 for j > M.
+  __host__ __device__ static PadeResult pade(const double* a, int L, int M, double (&q)[MM + 1],
+                                             double (&T)[MM][MM], int (&perm)[MM]) {
+    const Order o = select_order(a, L, M);
+    PadeResult r{0.0, o.L, o.M, o.margin};
+#pragma unroll
+    for (int j = 0; j <= MM; ++j) q[j] = j == 0 ? 1.0 : 0.0;
+    while (r.M > 0) {
+      const int m = r.M, l = r.L;
+      toeplitz(a, l, m, T);
+      if (lu(T, m, perm)) {
+        double y[MM];
+#pragma unroll
+        for (int i = 0; i < MM; ++i) {  // forward: L y = P (-b)
+          if (i >= m) continue;
+          double v = -a[l + 1 + perm[i]];
+#pragma unroll
+          for (int j = 0; j < i; ++j) v -= T[i][j] * y[j];
+          y[i] = v;
+        }
+#pragma unroll
+        for (int i = MM - 1; i >= 0; --i) {  // backward: U q = y
+          if (i >= m) continue;
+          double v = y[i];
+#pragma unroll
+          for (int j = i + 1; j < MM; ++j)
+            if (j < m) v -= T[i][j] * q[j + 1];
+          q[i + 1] = v / T[i][i];
+        }
+        break;
+      }
+      r.L = l + 1;  // an exactly singular square system (the rank test keeps these out): next antidiagonal entry
+      r.M = m - 1;
+    }
+    double num = 0.0, den = 0.0;
+#pragma unroll
+    for (int j = 0; j <= MM; ++j) {
+      if (j > r.M) continue;
       double A = 0.0;
-      for (int m = 0; m <= L - (i + 1); ++m) A += a[m];
-      double s = (A - r.value) / D;
-      for (int j = 0; j < i; ++j) s -= T[j * M + i] * v[j];
-      v[i] = s / T[i * M + i];
+      for (int i = 0; i <= r.L - j; ++i) A += a[i];
+      num += q[j] * A;
+      den += q[j];
     }
-    double w[kMaxPadeM];
-    for (int i = M - 1; i >= 0; --i) {  // L^T w = v
-      double s = v[i];
-      for (int j = i + 1; j < M; ++j) s -= T[j * M + i] * w[j];
-      w[i] = s;
-    }
-    for (int i = 0; i < M; ++i) y[perm[i]] = w[i];  // P y = w
+    r.value = num / den;
+    return r;
   }
-  for (int k = 0; k <= L + M; ++k) {
-    double gk = 0.0;
-    if (k <= L) {
-      const int jm = (L - k) < M ? (L - k) : M;
-      for (int j = 0; j <= jm; ++j) gk += q[j];
-      gk /= D;
+
+  // Gradient g_k = d value / d a_k (k = 0..L+M) of the approximant returned by pade(); qs is q in LDS (for
+  // the index L + i - k).  With D = sum_j q_j and c_j = (A_{L-j} - value)/D, solve T^T y = c; then
+  //   g_k = [k <= L] sum_{j=0}^{min(M, L-k)} q_j / D  -  sum_{i=1}^{M} y_i q_{L+i-k}  (0 <= L+i-k <= M).
+  __host__ __device__ static void gradient(const double* a, const PadeResult& r, const double (&q)[MM + 1],
+                                           const double* qs, const double (&T)[MM][MM], const int (&perm)[MM],
+                                           double* g) {
+    const int L = r.L, M = r.M;
+    double D = 0.0;
+#pragma unroll
+    for (int j = 0; j <= MM; ++j)
+      if (j <= M) D += q[j];
+    double y[MM];
+#pragma unroll
+    for (int i = 0; i < MM; ++i) y[i] = 0.0;
+    if (M > 0) {
+      double v[MM];
+#pragma unroll
+      for (int i = 0; i < MM; ++i) {  // U^T v = c
+        if (i >= M) continue;
+        double A = 0.0;
+        for (int m = 0; m <= L - (i + 1); ++m) A += a[m];
+        double s = (A - r.value) / D;
+#pragma unroll
+        for (int j = 0; j < i; ++j) s -= T[j][i] * v[j];
+        v[i] = s / T[i][i];
+      }
+      double w[MM];
+#pragma unroll
+      for (int i = MM - 1; i >= 0; --i) {  // L^T w = v
+        if (i >= M) continue;
+        double s = v[i];
+#pragma unroll
+        for (int j = i + 1; j < MM; ++j)
+          if (j < M) s -= T[j][i] * w[j];
+        w[i] = s;
+      }
+#pragma unroll
+      for (int i = 0; i < MM; ++i) {  // P y = w
+        if (i >= M) continue;
+#pragma unroll
+        for (int k = 0; k < MM; ++k)
+          if (perm[i] == k) y[k] = w[i];
+      }
     }
-    for (int i = 1; i <= M; ++i) {
-      const int j = L + i - k;
-      if (j >= 0 && j <= M) gk -= y[i - 1] * q[j];
+    for (int k = 0; k <= L + M; ++k) {
+      double gk = 0.0;
+      if (k <= L) {
+        const int jm = (L - k) < M ? (L - k) : M;
+#pragma unroll
+        for (int j = 0; j <= MM; ++j)
+          if (j <= jm) gk += q[j];
+        gk /= D;
+      }
+#pragma unroll
+      for (int i = 1; i <= MM; ++i) {
+        if (i > M) continue;
+        const int j = L + i - k;
+        if (j >= 0 && j <= M) gk -= y[i - 1] * qs[j];
+      }
+      g[k] = gk;
     }
-    g[k] = gk;
   }
-}
+};
 
 // Point k (0 <= k < n) of the boundary of {z : dist(z, [0, 1]) <= kPoleDist}, counter-clockwise at equal
 // arc length: the lower side, the right half circle around 1, the upper side, the left half circle around 0.
 // The half circles use single-precision sin/cos: the samples only have to lie on the contour to ~1e-7.
-__host__ __device__ void stadium_point(int k, int n, double* re, double* im) {
+__host__ __device__ __forceinline__ void stadium_point(int k, double step, double* re, double* im) {
   const double r = kPoleDist, pi = 3.141592653589793;
-  const double per = 2.0 + 2.0 * pi * r;
-  double s = per * (double)k / (double)n;
+  double s = step * (double)k;
   if (s < 1.0) {
     *re = s;
     *im = -r;
@@ -521,7 +633,7 @@ __host__ __device__ void stadium_point(int k, int n, double* re, double* im) {
   }
   s -= 1.0;
   if (s < pi * r) {
-    const float ph = (float)(-0.5 * pi + s / r);
+    const float ph = (float)(-0.5 * pi + s * (1.0 / r));
     *re = 1.0 + r * (double)cosf(ph);
     *im = r * (double)sinf(ph);
     return;
@@ -533,50 +645,51 @@ __host__ __device__ void stadium_point(int k, int n, double* re, double* im) {
     return;
   }
   s -= 1.0;
-  const float ph = (float)(0.5 * pi + s / r);
+  const float ph = (float)(0.5 * pi + s * (1.0 / r));
   *re = r * (double)cosf(ph);
   *im = r * (double)sinf(ph);
 }
 
-// Q(z) = sum_{j<=M} q_j z^j at a complex z (Horner).
-__host__ __device__ void q_eval(const double* q, int M, double zr, double zi, double* vr, double* vi) {
-  double ar = q[M], ai = 0.0;
-  for (int j = M - 1; j >= 0; --j) {
-    const double nr = ar * zr - ai * zi + q[j];
-    ai = ar * zi + ai * zr;
-    ar = nr;
-  }
-  *vr = ar;
-  *vi = ai;
-}
-
-// Phase of w1 / w0 (w0, w1 != 0) in (-pi, pi], in single precision after scaling the product w1 conj(w0):
-// the winding count only needs each step to an accuracy far below pi.
+// Phase of w1 / w0 (w0, w1 != 0) in (-pi, pi], in single precision after scaling the product w1 conj(w0) by
+// a power of two: the winding count only needs each step to an accuracy far below pi.
 __host__ __device__ __forceinline__ float phase_step(double r0, double i0, double r1, double i1) {
   const double re = r1 * r0 + i1 * i0, im = i1 * r0 - r1 * i0;
   const double m = fmax(fabs(re), fabs(im));
-  if (!(m > 0.0)) return 0.0f;
-  return atan2f((float)(im / m), (float)(re / m));
+  if (!(m > 0.0) || !(m <= 1.7e308)) return 0.0f;
+  int e;
+  frexp(m, &e);
+  const double sc = ldexp(1.0, -e);
+  return atan2f((float)(im * sc), (float)(re * sc));
 }
 
-// Per-lane scratch of the three Pade evaluations of a point (the value, [L-1/M] and [L/M-1]).
-struct PadeScratch {
-  double q[kMaxPadeM + 1];
-  double T[kMaxPadeM * kMaxPadeM];
-  double V[(kMaxPadeM + 1) * (kMaxPadeM + 1)];
-  int perm[kMaxPadeM];
-};
+// Adds a finite or non-finite double exactly into an LDS column of digit words (atomically, so that any
+// number of lanes may add into one column); non-finite values are recorded in *special instead.
+__device__ __forceinline__ void lds_add_exact(unsigned long long* col, unsigned int* special, double x) {
+  if (x == 0.0) return;
+  if (!(fabs(x) <= 1.7976931348623157e308)) {
+    atomicOr(special, x != x ? 4u : (x > 0 ? 1u : 2u));
+    return;
+  }
+  uint32_t k;
+  unsigned long long d[3];
+  digits_of(x, &k, d);
+  if (d[0]) atomicAdd(col + k, d[0]);
+  if (d[1]) atomicAdd(col + k + 1, d[1]);
+  if (d[2]) atomicAdd(col + k + 2, d[2]);
+}
 
+template <int MM>
 __global__ __launch_bounds__(64) void finalize_kernel(FinalizeArgs a) {
   __shared__ double coef[kMaxBins];
   __shared__ double m1[kMaxBins];
   __shared__ double m2[kMaxBins];
   __shared__ double grad[kMaxBins];
-  __shared__ PadeScratch ps[3];
+  __shared__ double qs[MM + 1];         // lane 0's denominator, for the pole test and the gradient
   __shared__ double res[3];             // values of lanes 0..2
   __shared__ int m_used;
-  __shared__ unsigned long long extra[3];
-  __shared__ unsigned long long wacc[kAccWords * kWave];  // digit words, one column per lane
+  __shared__ unsigned long long cnt[kJoinGroup + 3];
+  __shared__ unsigned int special[2 * kJoinGroup];
+  __shared__ unsigned long long wacc[2 * kJoinGroup * kAccStride];  // digit words of the sums being joined
 
   const uint32_t p = blockIdx.x;
   const uint32_t lane = threadIdx.x;
@@ -586,63 +699,54 @@ __global__ __launch_bounds__(64) void finalize_kernel(FinalizeArgs a) {
   const uint32_t NB = B + 3;
   const double N = (double)pr.n_total;
   const double scale = exp(pr.mu * pr.t);
+  const Partial* parts = a.partials + (size_t)pr.seg_begin * NB;
 
-  // Counts and flag counts: integer sums over the point's segments.
-  for (uint32_t b = lane; b < NB; b += kWave) {
-    unsigned long long cnt = 0;
-    for (uint32_t s = 0; s < pr.seg_count; ++s) cnt += a.partials[(size_t)(pr.seg_begin + s) * NB + b].count;
-    if (a.hist) a.hist[(size_t)row * NB + b] = cnt;
-    if (b >= B) extra[b - B] = cnt;
-  }
-  // The sums: lane j takes the pair (bin j/2, sum j%2) and adds every segment's value exactly into its own
-  // column of digit words, then rounds the total once.  Non-finite segment sums are classified instead.
-  for (uint32_t j0 = 0; j0 < 2 * B; j0 += kWave) {
-    const uint32_t j = j0 + lane;
-    unsigned long long* w = wacc + lane;
-    for (int k = 0; k < kAccWords; ++k) w[k * kWave] = 0ull;
-    unsigned long long special = 0;
-    if (j < 2 * B) {
-      const uint32_t b = j >> 1;
-      // a window of three words in registers at the last value's word index; a value on another word
-      // first moves the window into the lane's LDS column (the segments of a point share a word almost
-      // always, and each word takes at most 2^31 digits, far above a point's number of segments)
-      uint32_t wk = 0xffffffffu;
-      unsigned long long r0 = 0, r1 = 0, r2 = 0;
-      for (uint32_t s = 0; s < pr.seg_count; ++s) {
-        const Partial& pt = a.partials[(size_t)(pr.seg_begin + s) * NB + b];
-        const double parts[2] = {(j & 1) ? pt.s2 : pt.s1_hi, (j & 1) ? 0.0 : pt.s1_lo};
-        for (int q = 0; q < 2; ++q) {
-          const double x = parts[q];
-          if (x == 0.0) continue;
-          if (!(fabs(x) <= 1.7976931348623157e308)) {
-            special |= x != x ? 4ull : (x > 0 ? 1ull : 2ull);
-            continue;
-          }
-          uint32_t k;
-          unsigned long long d[3];
-          digits_of(x, &k, d);
-          if (k != wk) {
-            if (wk != 0xffffffffu) {
-              w[(size_t)wk * kWave] += r0;
-              w[(size_t)(wk + 1) * kWave] += r1;
-              w[(size_t)(wk + 2) * kWave] += r2;
-            }
-            wk = k;
-            r0 = r1 = r2 = 0;
-          }
-          r0 += d[0];
-          r1 += d[1];
-          r2 += d[2];
+  // The point's segments joined exactly, kJoinGroup bins at a time: lanes take segments, add each
+  // segment's count and sums into shared columns of digit words (integer atomics: the result does not
+  // depend on the order), and lane j then rounds the column of (bin j/2, sum j%2) once.
+  unsigned long long extra[3] = {0, 0, 0};
+  for (uint32_t g0 = 0; g0 < B; g0 += kJoinGroup) {
+    const uint32_t nb = B - g0 < (uint32_t)kJoinGroup ? B - g0 : (uint32_t)kJoinGroup;
+    for (uint32_t i = lane; i < 2 * kJoinGroup * kAccStride; i += kWave) wacc[i] = 0ull;
+    if (lane < kJoinGroup + 3) cnt[lane] = 0ull;
+    if (lane < 2 * kJoinGroup) special[lane] = 0u;
+    __syncthreads();
+    for (uint32_t sg = lane; sg < pr.seg_count; sg += kWave) {
+      const Partial* prow = parts + (size_t)sg * NB + g0;
+      Partial v[kJoinGroup];
+#pragma unroll
+      for (int b = 0; b < kJoinGroup; ++b)
+        v[b] = (uint32_t)b < nb ? prow[b] : Partial{0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int b = 0; b < kJoinGroup; ++b) {
+        if ((uint32_t)b >= nb) continue;
+        if (v[b].count) atomicAdd(&cnt[b], (unsigned long long)v[b].count);
+        unsigned long long* c1 = wacc + (2 * b) * kAccStride;
+        lds_add_exact(c1, &special[2 * b], v[b].s1_hi);
+        lds_add_exact(c1, &special[2 * b], v[b].s1_lo);
+        lds_add_exact(c1 + kAccStride, &special[2 * b + 1], v[b].s2);
+      }
+      if (g0 == 0) {
+        const Partial* ext = parts + (size_t)sg * NB + B;
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+          const unsigned long long c = ext[e].count;
+          if (c) atomicAdd(&cnt[kJoinGroup + e], c);
         }
       }
-      if (wk != 0xffffffffu) {
-        w[(size_t)wk * kWave] += r0;
-        w[(size_t)(wk + 1) * kWave] += r1;
-        w[(size_t)(wk + 2) * kWave] += r2;
-      }
-      const double v = acc_round(w, kWave, special);
+    }
+    __syncthreads();
+    if (lane < nb && a.hist) a.hist[(size_t)row * NB + g0 + lane] = cnt[lane];
+    if (g0 == 0) {
+#pragma unroll
+      for (int e = 0; e < 3; ++e) extra[e] = cnt[kJoinGroup + e];
+      if (lane < 3 && a.hist) a.hist[(size_t)row * NB + B + lane] = cnt[kJoinGroup + lane];
+    }
+    if (lane < 2 * nb) {
+      const uint32_t b = g0 + (lane >> 1);
+      const double v = acc_round(wacc + lane * kAccStride, special[lane]);
       const double mm = N > 0 ? v / N : 0.0;
-      if (j & 1) {
+      if (lane & 1) {
         m2[b] = mm;
         if (a.s2) a.s2[(size_t)row * B + b] = v;
       } else {
@@ -652,8 +756,8 @@ __global__ __launch_bounds__(64) void finalize_kernel(FinalizeArgs a) {
         if (a.coef) a.coef[(size_t)row * B + b] = scale * mm;
       }
     }
+    __syncthreads();
   }
-  __syncthreads();
   for (uint32_t b = lane; b < B; b += kWave) {
     const double var = N > 1 ? scale * scale * (m2[b] - m1[b] * m1[b]) / (N - 1.0) : 0.0;
     if (a.coef_var) a.coef_var[(size_t)row * B + b] = var;
@@ -665,33 +769,53 @@ __global__ __launch_bounds__(64) void finalize_kernel(FinalizeArgs a) {
   // Lanes 0, 1, 2 evaluate [L/M], [L-1/M] and [L/M-1] side by side, each with its own degree selection.
   const int L = (int)a.pade_L, M = (int)a.pade_M;
   PadeResult r{};
+  double q[MM + 1];
+  double T[MM][MM];
+  int perm[MM];
   if (lane < 3) {
     const int Lk = lane == 1 ? L - 1 : L, Mk = lane == 2 ? M - 1 : M;
-    PadeScratch& w = ps[lane];
     if (Lk >= 0 && Mk >= 0) {
-      r = pade(coef, Lk, Mk, w.q, w.T, w.perm, w.V);
+      r = SmallPade<MM>::pade(coef, Lk, Mk, q, T, perm);
       res[lane] = r.value;
     } else {
       res[lane] = NAN;
     }
-    if (lane == 0) m_used = r.M;
+    if (lane == 0) {
+      m_used = r.M;
+#pragma unroll
+      for (int j = 0; j <= MM; ++j) qs[j] = q[j];
+    }
   }
   __syncthreads();
   // Pole test: the number of zeros of Q inside the contour around [0, 1] is the winding number of Q along
   // it (argument principle), summed from the phase steps between consecutive samples.
   const int mq = m_used;
-  const double* qm = ps[0].q;
   float wind = 0.0f;
   bool on_contour = false;
   if (mq > 0) {
+    double qr[MM + 1];
+#pragma unroll
+    for (int j = 0; j <= MM; ++j) qr[j] = qs[j];
+    auto q_at = [&](double zr, double zi, double* vr, double* vi) {  // Horner; q_j = 0 above the degree
+      double ar = qr[MM], ai = 0.0;
+#pragma unroll
+      for (int j = MM - 1; j >= 0; --j) {
+        const double nr = ar * zr - ai * zi + qr[j];
+        ai = ar * zi + ai * zr;
+        ar = nr;
+      }
+      *vr = ar;
+      *vi = ai;
+    };
     const int n = kWave * kWindingSamples;
+    const double step = (2.0 + 2.0 * 3.141592653589793 * kPoleDist) / (double)n;
     double zr, zi, pr0, pi0;
-    stadium_point((int)lane * kWindingSamples, n, &zr, &zi);
-    q_eval(qm, mq, zr, zi, &pr0, &pi0);
+    stadium_point((int)lane * kWindingSamples, step, &zr, &zi);
+    q_at(zr, zi, &pr0, &pi0);
     for (int k = 1; k <= kWindingSamples; ++k) {
       double pr1, pi1;
-      stadium_point(((int)lane * kWindingSamples + k) % n, n, &zr, &zi);
-      q_eval(qm, mq, zr, zi, &pr1, &pi1);
+      stadium_point(((int)lane * kWindingSamples + k) % n, step, &zr, &zi);
+      q_at(zr, zi, &pr1, &pi1);
       on_contour |= (pr1 == 0.0 && pi1 == 0.0);
       wind += phase_step(pr0, pi0, pr1, pi1);
       pr0 = pr1;
@@ -711,8 +835,7 @@ __global__ __launch_bounds__(64) void finalize_kernel(FinalizeArgs a) {
     for (uint32_t b = 0; b < B; ++b) psum += coef[b];
     // delta method: Var(u) = sum_kl g_k g_l Cov(a_k, a_l) with
     // Cov(a_k, a_l) = scale^2 (delta_kl m2_k - m1_k m1_l) / (N - 1); sensitivity kappa = sum_k |g_k| |a_k|
-    PadeScratch& w = ps[0];
-    pade_gradient(coef, r, w.q, w.T, w.perm, grad);
+    SmallPade<MM>::gradient(coef, r, q, qs, T, perm, grad);
     double gg = 0.0, gm = 0.0, kappa = 0.0;
     for (int k = 0; k <= r.L + r.M; ++k) {
       gg += grad[k] * grad[k] * m2[k];
@@ -746,7 +869,12 @@ hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
 
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s) {
   if (a.n_points == 0) return hipSuccess;
-  hipLaunchKernelGGL(finalize_kernel, dim3(a.n_points), dim3(kWave), 0, s, a);
+  if (a.pade_M <= 6)
+    hipLaunchKernelGGL(finalize_kernel<6>, dim3(a.n_points), dim3(kWave), 0, s, a);
+  else if (a.pade_M <= 8)
+    hipLaunchKernelGGL(finalize_kernel<8>, dim3(a.n_points), dim3(kWave), 0, s, a);
+  else
+    hipLaunchKernelGGL(finalize_kernel<16>, dim3(a.n_points), dim3(kWave), 0, s, a);
   return hipGetLastError();
 }
 
