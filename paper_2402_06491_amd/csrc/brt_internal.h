@@ -181,7 +181,8 @@ size_t pde_bytes(int precision);
 void pde_to_device(const brt_problem& p, const Norm& n, int precision, void* dst);
 double est_nodes(const Norm& n, const brt_mc& mc, double t);
 int set_error(int code, const char* fmt, ...);  // records the thread's error message, returns code
-constexpr uint32_t kSegTrees = 1u << 13;          // trees per reduction segment
+constexpr uint32_t kSegTrees = 1u << 13;          // trees per reduction segment of a serving round
+constexpr uint32_t kPlanSegTrees = 1u << 15;      // trees per reduction segment of a plan
 constexpr uint32_t kMaxDepthUnpruned = 64;        // stack levels per lane when trees are not pruned
 constexpr uint32_t kDefaultLdsLevels = 8;         // stack levels per lane kept in LDS by default
 

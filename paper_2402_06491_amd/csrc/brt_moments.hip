@@ -1,6 +1,6 @@
 // Moment reduction and FP64 finalize of the random-tree Monte Carlo (gfx950).
 //
-//  reduce_kernel    one wave per segment of one point's trees: per-bin count, compensated
+//  reduce_kernel    one wave per segment of one point's trees (up to 2^15 of them): per-bin count, compensated
 //                   (double-double) sum of F and plain sum of F*F, each lane adding its records in index
 //                   order, the lanes joined by a fixed butterfly.
 //  finalize_kernel  one wave per point, FP64: the point's segment sums joined exactly (integer digit
@@ -24,7 +24,7 @@
 namespace brt {
 
 constexpr int kRedGroup = 16;   // bins accumulated per pass over a segment (per-lane sums in LDS)
-static_assert(kSegTrees <= 65535, "per-lane counts are 16-bit");
+static_assert(kSegTrees <= 65535 && kPlanSegTrees <= 65535, "per-lane counts are 16-bit");
 constexpr int kRedBatch = 32;   // records loaded per lane before they are accumulated
 constexpr uint32_t kAbsent = 0xffffffffu;  // marks a batch slot past the end of the segment (no real
                                            // record has every flag bit set)
@@ -170,7 +170,7 @@ __device__ __forceinline__ void wave_sum_dd(double* hi, double* lo) {
 // propagate into the sums (the finalize classifies them).
 __global__ __launch_bounds__(kWave) void reduce_kernel(ReduceArgs a) {
   __shared__ double s1h[kRedGroup][kWave], s1l[kRedGroup][kWave], s2[kRedGroup][kWave];
-  __shared__ uint16_t lcnt[kRedGroup][kWave];  // a segment holds at most kSegTrees <= 65535 trees
+  __shared__ uint16_t lcnt[kRedGroup][kWave];  // a segment holds at most 65535 trees
 
   const uint32_t seg = blockIdx.x;
   const uint32_t lane = threadIdx.x;

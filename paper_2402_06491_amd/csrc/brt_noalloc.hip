@@ -24,7 +24,7 @@ constexpr uint64_t kNaMaxTrees = BRT_NOALLOC_MAX_TREES;
 constexpr uint32_t kNaMaxOrder = BRT_NOALLOC_MAX_ORDER;
 constexpr uint32_t kNaMaxBins = kNaMaxOrder + 2;
 constexpr uint32_t kNaMaxChunks = (uint32_t)(kNaMaxTrees / 64) + kNaMaxPoints;  // chunks hold >= 64 trees
-constexpr uint32_t kNaMaxSegs = (uint32_t)(kNaMaxTrees / kSegTrees) + kNaMaxPoints;
+constexpr uint32_t kNaMaxSegs = (uint32_t)(kNaMaxTrees / kPlanSegTrees) + kNaMaxPoints;
 constexpr int kNaMaxDevices = 64;
 
 constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -165,9 +165,9 @@ extern "C" int brt_solve_noalloc(brt_ctx* ctx, uint32_t n_problems, const brt_pr
   for (uint32_t i = 0; i < pts->n; ++i) {
     PointRec& r = h_points[i];
     r.seg_begin = ns;
-    for (uint32_t b0 = 0; b0 < r.n_trees; b0 += kSegTrees) {
+    for (uint32_t b0 = 0; b0 < r.n_trees; b0 += kPlanSegTrees) {
       if (ns == kNaMaxSegs) return na_fail(BRT_E_ARG, "too many reduction segments");
-      h_segs[ns] = Segment{i, b0, std::min(r.n_trees, b0 + kSegTrees), ns};
+      h_segs[ns] = Segment{i, b0, std::min(r.n_trees, b0 + kPlanSegTrees), ns};
       ++ns;
     }
     r.seg_count = ns - r.seg_begin;
