@@ -162,6 +162,8 @@ namespace brt {
 // Look up the address of the allocation-free entry point's scratch array on `device` (current) once per
 // device (brt_noalloc.hip); BRT_E_DEVICE if the lookup fails.
 int noalloc_init_device(int device);
+// Copy the pole test's contour samples to `device` (current) once (brt_moments.hip); BRT_E_DEVICE on failure.
+int contour_init_device(int device);
 
 // Strategy A normalisation of one problem (brt_runtime.hip).
 struct Norm {
@@ -182,7 +184,7 @@ void pde_to_device(const brt_problem& p, const Norm& n, int precision, void* dst
 double est_nodes(const Norm& n, const brt_mc& mc, double t);
 int set_error(int code, const char* fmt, ...);  // records the thread's error message, returns code
 constexpr uint32_t kSegTrees = 1u << 13;          // trees per reduction segment of a serving round
-constexpr uint32_t kPlanSegTrees = 1u << 15;      // trees per reduction segment of a plan
+constexpr uint32_t kPlanSegTrees = 1u << 16;      // trees per reduction segment of a plan
 constexpr uint32_t kMaxDepthUnpruned = 64;        // stack levels per lane when trees are not pruned
 constexpr uint32_t kDefaultLdsLevels = 8;         // stack levels per lane kept in LDS by default
 

@@ -1,6 +1,6 @@
 // Moment reduction and FP64 finalize of the random-tree Monte Carlo (gfx950).
 //
-//  reduce_kernel    one wave per segment of one point's trees (up to 2^15 of them): per-bin count, compensated
+//  reduce_kernel    one wave per segment of one point's trees (up to 2^16 of them): per-bin count, compensated
 //                   (double-double) sum of F and plain sum of F*F, each lane adding its records in index
 //                   order, the lanes joined by a fixed butterfly.
 //  finalize_kernel  one wave per point, FP64: the point's segment sums joined exactly (integer digit
@@ -18,13 +18,15 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 
 #include "brt_internal.h"
 
 namespace brt {
 
 constexpr int kRedGroup = 16;   // bins accumulated per pass over a segment (per-lane sums in LDS)
-static_assert(kSegTrees <= 65535 && kPlanSegTrees <= 65535, "per-lane counts are 16-bit");
+static_assert((kSegTrees + kWave - 1) / kWave <= 65535 && (kPlanSegTrees + kWave - 1) / kWave <= 65535,
+              "per-lane counts are 16-bit");
 constexpr int kRedBatch = 32;   // records loaded per lane before they are accumulated
 constexpr uint32_t kAbsent = 0xffffffffu;  // marks a batch slot past the end of the segment (no real
                                            // record has every flag bit set)
@@ -170,7 +172,7 @@ __device__ __forceinline__ void wave_sum_dd(double* hi, double* lo) {
 // propagate into the sums (the finalize classifies them).
 __global__ __launch_bounds__(kWave) void reduce_kernel(ReduceArgs a) {
   __shared__ double s1h[kRedGroup][kWave], s1l[kRedGroup][kWave], s2[kRedGroup][kWave];
-  __shared__ uint16_t lcnt[kRedGroup][kWave];  // a segment holds at most 65535 trees
+  __shared__ uint16_t lcnt[kRedGroup][kWave];  // a lane takes at most 65535 of a segment's trees
 
   const uint32_t seg = blockIdx.x;
   const uint32_t lane = threadIdx.x;
@@ -620,12 +622,15 @@ struct SmallPade {
   }
 };
 
-// Point k (0 <= k < n) of the boundary of {z : dist(z, [0, 1]) <= kPoleDist}, counter-clockwise at equal
-// arc length: the lower side, the right half circle around 1, the upper side, the left half circle around 0.
-// The half circles use single-precision sin/cos: the samples only have to lie on the contour to ~1e-7.
-__host__ __device__ __forceinline__ void stadium_point(int k, double step, double* re, double* im) {
+// Samples of the pole test's contour, the boundary of {z : dist(z, [0, 1]) <= kPoleDist}, counter-clockwise
+// at equal arc length: the lower side, the right half circle around 1, the upper side, the left half
+// circle around 0.  The same for every point: computed once on the host and copied to each device.
+constexpr int kContourSamples = kWave * kWindingSamples;
+__device__ double2 g_contour[kContourSamples];
+
+static void stadium_point(int k, double* re, double* im) {
   const double r = kPoleDist, pi = 3.141592653589793;
-  double s = step * (double)k;
+  double s = (2.0 + 2.0 * pi * r) * (double)k / (double)kContourSamples;
   if (s < 1.0) {
     *re = s;
     *im = -r;
@@ -633,9 +638,8 @@ __host__ __device__ __forceinline__ void stadium_point(int k, double step, doubl
   }
   s -= 1.0;
   if (s < pi * r) {
-    const float ph = (float)(-0.5 * pi + s * (1.0 / r));
-    *re = 1.0 + r * (double)cosf(ph);
-    *im = r * (double)sinf(ph);
+    *re = 1.0 + r * std::cos(-0.5 * pi + s / r);
+    *im = r * std::sin(-0.5 * pi + s / r);
     return;
   }
   s -= pi * r;
@@ -645,9 +649,20 @@ __host__ __device__ __forceinline__ void stadium_point(int k, double step, doubl
     return;
   }
   s -= 1.0;
-  const float ph = (float)(0.5 * pi + s * (1.0 / r));
-  *re = r * (double)cosf(ph);
-  *im = r * (double)sinf(ph);
+  *re = r * std::cos(0.5 * pi + s / r);
+  *im = r * std::sin(0.5 * pi + s / r);
+}
+
+int contour_init_device(int device) {
+  static bool done[64] = {};
+  if (device < 0 || device >= 64) return set_error(BRT_E_DEVICE, "device %d: no contour slot", device);
+  if (done[device]) return BRT_OK;
+  double2 h[kContourSamples];
+  for (int k = 0; k < kContourSamples; ++k) stadium_point(k, &h[k].x, &h[k].y);
+  const hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(g_contour), h, sizeof(h));
+  if (e != hipSuccess) return set_error(BRT_E_DEVICE, "contour table on device %d: %s", device, hipGetErrorString(e));
+  done[device] = true;
+  return BRT_OK;
 }
 
 // Phase of w1 / w0 (w0, w1 != 0) in (-pi, pi], in single precision after scaling the product w1 conj(w0) by
@@ -807,15 +822,13 @@ __global__ __launch_bounds__(64) void finalize_kernel(FinalizeArgs a) {
       *vr = ar;
       *vi = ai;
     };
-    const int n = kWave * kWindingSamples;
-    const double step = (2.0 + 2.0 * 3.141592653589793 * kPoleDist) / (double)n;
-    double zr, zi, pr0, pi0;
-    stadium_point((int)lane * kWindingSamples, step, &zr, &zi);
-    q_at(zr, zi, &pr0, &pi0);
+    double pr0, pi0;
+    const double2 z0 = g_contour[lane * kWindingSamples];
+    q_at(z0.x, z0.y, &pr0, &pi0);
     for (int k = 1; k <= kWindingSamples; ++k) {
       double pr1, pi1;
-      stadium_point(((int)lane * kWindingSamples + k) % n, step, &zr, &zi);
-      q_at(zr, zi, &pr1, &pi1);
+      const double2 z = g_contour[(lane * kWindingSamples + k) % kContourSamples];
+      q_at(z.x, z.y, &pr1, &pi1);
       on_contour |= (pr1 == 0.0 && pi1 == 0.0);
       wind += phase_step(pr0, pi0, pr1, pi1);
       pr0 = pr1;

@@ -222,7 +222,8 @@ int brt_create(brt_ctx** out, int device) {
   c->launch.chunk_trees = 1024;
   c->launch.stack_depth = 0;
   // the allocation-free entry point's scratch array: its address on this device, looked up once
-  const int rc = noalloc_init_device(device);
+  int rc = noalloc_init_device(device);
+  if (!rc) rc = contour_init_device(device);  // the finalize's pole-test contour
   if (rc) {
     delete c;
     return rc;
