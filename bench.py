@@ -161,6 +161,107 @@ def cpu_baseline(wl, gpu_meta, gpu_f, target_s):
             recs if S == int(n_trees.min()) == int(n_trees.max()) else None)
 
 
+def describe_extra(wl):
+    if wl["name"] == "kpp_1d":
+        return ("kpp_1d: u_t=0.5u_xx+u^2-u, u0=1/(1+e^x), 16 x in [-4,4], t=1, 1e5 trees/point, unpruned "
+                "(bins 0..63 + tail), node cap 2^16, FP64")
+    if wl["name"] == "poly_batch":
+        return (f"poly_batch: 4096 points of 8 PDEs (f of degree 2..5, coefficients U[-1,1]), t log-uniform "
+                f"in [0.25,4], 1e4..1e6 trees/point (log-uniform), order 12 pruned, Pade [6/6], "
+                f"FP{wl['mc']['precision']} paths")
+    return wl["name"]
+
+
+def cpu_sample_rate(wl, target_s):
+    """The oracle on a proportional sample of a workload (the first ceil(f n_i) trees of every point, so
+    the sample has the workload's mix of points): a calibration run as warm-up, then the median of 3."""
+    import oracle
+
+    oracle.build(force=False)
+    threads = cpu_threads()
+    n_trees = np.asarray(wl["n_trees"], dtype=np.int64)
+    pid = np.asarray(wl.get("problem_id", np.zeros(len(n_trees), np.uint32)))
+
+    def run(f):
+        k = np.maximum(1, np.ceil(f * n_trees)).astype(np.int64)
+        t0 = time.perf_counter()
+        for p in range(len(n_trees)):
+            oracle.walk_point(wl["problems"][int(pid[p])], wl["mc"], wl["x"][p], float(wl["t"][p]), p, int(k[p]),
+                              nthreads=threads)
+        return time.perf_counter() - t0, int(k.sum())
+
+    f = min(1.0, 2e5 / max(1, n_trees.sum()))
+    dt, n = run(f)
+    f = min(1.0, f * target_s / max(dt, 1e-3))
+    times = []
+    for _ in range(3):
+        dt, n = run(f)
+        times.append(dt)
+    dt = float(np.median(times))
+    return {"value": n / dt, "unit": "trees/s", "cores": threads, "nproc": os.cpu_count(), "cpu_model": cpu_model(),
+            "runs_s": times, "kind": "oracle",
+            "sample": f"first {f:.4g} of every point's trees ({n} trees, the workload's mix), median {dt:.2f} s of 3 "
+                      f"runs after a warm-up"}
+
+
+def config_bench(ctx, wl, steps, warmup, cpu_s):
+    """Throughput of one more workload: the same step (walk, reduce, finalize) replayed as a graph on a
+    created stream, the walker's duration from HIP events in timing mode, and the oracle on a sample."""
+    import tempfile
+
+    import torch
+
+    import paper_2402_06491_amd as brt
+
+    tuned = ctx.autotune(wl["problems"], wl["mc"], wl["x"], wl["t"], wl["n_trees"], problem_id=wl.get("problem_id"),
+                         cache_path=os.path.join(tempfile.gettempdir(), "brt_autotune.jsonl"))
+    plan = brt.Plan(ctx, wl["problems"], wl["mc"], wl["x"], wl["t"], wl["n_trees"], problem_id=wl.get("problem_id"))
+    out = plan.outputs(records=False)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        for _ in range(warmup):
+            plan.execute(out, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        for _ in range(steps):
+            plan.execute(out, stream=stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    graph = plan.graph_stats()
+    plan.set_timing(True)
+    with torch.cuda.stream(stream):
+        for _ in range(steps):
+            plan.execute(out, stream=stream)
+    (walk_ms, red_ms, fin_ms), runs = plan.get_timing()
+    plan.set_timing(False)
+    nodes = int(out["nodes"].sum().item())
+    flags = out["flags"].cpu().numpy()
+    plan.close()
+    del out
+    total = int(np.sum(wl["n_trees"]))
+    dim = int(wl["problems"][0]["dim"])
+    walk_s = walk_ms / runs / 1e3
+    achieved = nodes * OPS_PER_NODE[dim] / walk_s / 1e12
+    res = {"workload": describe_extra(wl), "points": len(wl["t"]), "total_trees": total,
+           "value": total * steps / wall, "unit": "trees/s", "ms_per_step": wall * 1e3 / steps, "steps": steps,
+           "dtype": "f32" if wl["mc"]["precision"] == 32 else "f64", "launch": tuned, "graph": graph,
+           "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TOPS, "unit": "Top/s",
+                        "frac": achieved / PEAK_TOPS, "traffic": None, "kernel": "walk_kernel",
+                        "kernel_ms": walk_s * 1e3, "nodes_per_launch": nodes, "ops_per_node": OPS_PER_NODE[dim],
+                        "reduce_ms": red_ms / runs, "finalize_ms": fin_ms / runs},
+           "pade": {"pole_flagged": int(((flags & 1) != 0).sum()), "sensitive_flagged": int(((flags & 32) != 0).sum()),
+                    "lowered": int(((flags & 2) != 0).sum())}}
+    log(f"{wl['name']} FP{wl['mc']['precision']}: {wall * 1e3 / steps:.3f} ms/step, {res['value']:.4g} trees/s, "
+        f"walker {walk_s * 1e3:.3f} ms ({100 * achieved / PEAK_TOPS:.1f}% of peak), reduce {red_ms / runs:.3f} ms, "
+        f"finalize {fin_ms / runs:.3f} ms")
+    if cpu_s > 0:
+        res["cpu_baseline"] = cpu_sample_rate(wl, cpu_s)
+        log(f"{wl['name']} FP{wl['mc']['precision']} cpu baseline {res['cpu_baseline']['value']:.4g} trees/s "
+            f"({res['cpu_baseline']['sample']})")
+    return res
+
+
 def pade_parity(wl, recs, gpu):
     """The headline's Pade values against the oracle's, from the oracle's walk of every tree of every
     point: the oracle's moments (exact sums), coefficients and Pade summary per point, then the same
@@ -297,35 +398,102 @@ def pmc_summary(fetch_dir, write_dir, command):
         print(json.dumps(adi))
 
 
-def serve_stream(ctx, reqs, mc, max_active, opts):
-    """Replay a request stream in real time through a brt_server; returns its statistics."""
+def serve_stream(ctx, reqs, mc, opts, realtime=True):
+    """Replay a request stream through a brt_server (in real time, or all requests at once); returns its
+    statistics and every completed request's result."""
     import paper_2402_06491_amd as brt
 
-    srv = brt.Server(ctx, 2, "gauss_sum", mc, max_active_requests=max_active, **opts)
-    pending, rejected = {}, 0
-    t0 = time.perf_counter()
-    for r in reqs:
-        while time.perf_counter() - t0 < r["arrival"]:
-            for tk in [tk for tk, n in pending.items() if srv.poll(tk, n) is not None]:
+    srv = brt.Server(ctx, 2, "gauss_sum", mc, **opts)
+    pending, results, rejected = {}, {}, 0
+
+    def collect():
+        for tk, (rid, n) in list(pending.items()):
+            r = srv.poll(tk, n)
+            if r is not None:
+                results[rid] = r
                 del pending[tk]
+
+    t0 = time.perf_counter()
+    last_log = t0
+    for r in reqs:
+        while realtime and time.perf_counter() - t0 < r["arrival"]:
+            collect()
             time.sleep(0.0005)
         try:
-            pending[srv.submit(r["problem"], r["x"], r["t"], stream_id=r["id"])] = len(r["t"])
+            pending[srv.submit(r["problem"], r["x"], r["t"], stream_id=r["id"])] = (r["id"], len(r["t"]))
         except brt.BrtError as e:
             if e.code != -4:
                 raise
             rejected += 1
+        if time.perf_counter() - last_log > 10.0:
+            last_log = time.perf_counter()
+            log(f"serving: {r['id'] + 1} requests submitted, {len(results)} completed")
     srv.drain(timeout_s=900.0)
-    for tk, n in pending.items():
-        srv.poll(tk, n)
+    collect()
     st = srv.stats()
     srv.close()
     st["rejected_at_submit"] = rejected
-    return st
+    return st, results
 
 
-def serve_bench(ctx, duration, rate, opts):
-    """The served mixed-size query stream: continuous batching against one request at a time."""
+def plain_per_request(ctx, reqs, results, mc):
+    """The plain path: one brt_solve launch per request, in arrival order, each point with the trees the
+    server gave it (the same Philox trees, so the same estimates and errors).  Latency from the measured
+    service times with first-come-first-served queueing at the recorded arrival times."""
+    import torch
+
+    import paper_2402_06491_amd as brt
+
+    finish, lat, trees = 0.0, [], 0
+    t_first = reqs[0]["arrival"]
+    for r in reqs:
+        res = results[r["id"]]
+        n = len(r["t"])
+        nt = res["trees"].astype(np.int64)
+        ids = (r["id"] * 1024 + np.arange(n)).astype(np.uint32)
+        t0 = time.perf_counter()
+        brt.solve(ctx, r["problem"], mc, r["x"], r["t"], nt, point_id=ids, records=False)
+        torch.cuda.synchronize()
+        svc = time.perf_counter() - t0
+        start = max(finish, r["arrival"])
+        finish = start + svc
+        lat.append(finish - r["arrival"])
+        trees += int(nt.sum())
+    lat = np.array(lat)
+    span = finish - t_first
+    return {"requests": len(reqs), "trees": trees, "span_s": span, "trees_per_s": trees / span,
+            "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+            "mean_latency_s": float(lat.mean())}
+
+
+def family_plan_rate(ctx):
+    """The plan rate on the served family: the 2-D cubic problem's 1536 interface points x 1e5 trees in
+    one plan (FP32 paths), replayed as a graph."""
+    import torch
+
+    import paper_2402_06491_amd as brt
+    from paper_2402_06491_amd import inputs
+
+    wl = inputs.cubic_2d(n_trees=100_000)
+    plan = brt.Plan(ctx, wl["problems"], wl["mc"], wl["x"], wl["t"], wl["n_trees"], problem_id=wl["problem_id"])
+    out = plan.outputs(records=False)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        plan.execute(out, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            plan.execute(out, stream=stream)
+        torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / 5
+    plan.close()
+    return int(np.sum(wl["n_trees"])) / dt
+
+
+def serve_bench(ctx, duration, rate, opts, plain_requests, saturated_requests):
+    """The served mixed-size query stream (Poisson arrivals, 1..1024 points per request, target SE, tree
+    cap): continuous batching in real time; the plain one-launch-per-request path on the stream's first
+    requests; the server saturated with requests (all submitted at once) against the plan rate."""
     from paper_2402_06491_amd import inputs
 
     reqs = inputs.served_stream(rate=rate, duration=duration)
@@ -333,16 +501,40 @@ def serve_bench(ctx, duration, rate, opts):
     log(f"serving: {len(reqs)} requests over {duration} s ({sum(len(r['t']) for r in reqs)} points)")
     out = {"requests": len(reqs), "arrival_rate_per_s": rate, "duration_s": duration,
            "points": int(sum(len(r["t"]) for r in reqs)), **{k: v for k, v in opts.items()}}
-    for name, max_active in (("batched", 0), ("one_request_at_a_time", 1)):
-        st = serve_stream(ctx, reqs, mc, max_active, opts)
-        out[name] = {"trees_per_s": st["trees_per_s"], "p50_latency_s": st["p50_latency_s"],
-                     "p99_latency_s": st["p99_latency_s"], "mean_latency_s": st["mean_latency_s"],
-                     "completed": st["completed"], "trees": st["trees"], "ticks": st["ticks"],
-                     "span_s": st["span_s"], "busy_s": st["busy_s"]}
-        log(f"serving {name}: {st['trees_per_s']:.4g} trees/s, p50 {st['p50_latency_s']:.3f} s, "
-            f"p99 {st['p99_latency_s']:.3f} s, {st['completed']} completed in {st['span_s']:.2f} s")
-    b, o = out["batched"], out["one_request_at_a_time"]
-    out["speedup_trees_per_s"] = b["trees_per_s"] / o["trees_per_s"] if o["trees_per_s"] else None
+    st, res = serve_stream(ctx, reqs, mc, opts)
+    se = np.concatenate([res[r["id"]]["se"] for r in reqs if r["id"] in res])
+    tr = np.concatenate([res[r["id"]]["trees"] for r in reqs if r["id"] in res]).astype(np.int64)
+    out["batched"] = {"trees_per_s": st["trees_per_s"], "p50_latency_s": st["p50_latency_s"],
+                      "p99_latency_s": st["p99_latency_s"], "mean_latency_s": st["mean_latency_s"],
+                      "completed": st["completed"], "trees": st["trees"], "ticks": st["ticks"],
+                      "span_s": st["span_s"], "device_busy_s": st["busy_s"],
+                      "points_at_target_se": int(np.sum(se <= opts["target_se"])),
+                      "points_at_tree_cap": int(np.sum((se > opts["target_se"]) & (tr >= opts["max_trees"]))),
+                      "share_at_target_se": float(np.mean(se <= opts["target_se"])),
+                      "mean_trees_per_point": float(tr.mean())}
+    b = out["batched"]
+    log(f"serving batched: {b['trees_per_s']:.4g} trees/s, p50 {b['p50_latency_s']:.3f} s, p99 "
+        f"{b['p99_latency_s']:.3f} s, {b['completed']} completed in {b['span_s']:.2f} s; "
+        f"{100 * b['share_at_target_se']:.1f}% of points reached SE <= {opts['target_se']}")
+    head = [r for r in reqs if r["id"] in res][:plain_requests]
+    if head:
+        out["plain_one_launch_per_request"] = plain_per_request(ctx, head, res, mc)
+        lat = np.array([res[r["id"]]["latency_s"] for r in head])
+        out["batched_same_requests"] = {"requests": len(head), "p50_latency_s": float(np.percentile(lat, 50)),
+                                        "p99_latency_s": float(np.percentile(lat, 99))}
+        pl = out["plain_one_launch_per_request"]
+        log(f"serving plain (first {len(head)} requests): {pl['trees_per_s']:.4g} trees/s, p50 "
+            f"{pl['p50_latency_s']:.3f} s, p99 {pl['p99_latency_s']:.3f} s; batched on the same requests: p50 "
+            f"{out['batched_same_requests']['p50_latency_s']:.3f} s, p99 {out['batched_same_requests']['p99_latency_s']:.3f} s")
+    sat = reqs[:saturated_requests]
+    if sat:
+        st2, _ = serve_stream(ctx, sat, mc, opts, realtime=False)
+        rate_plan = family_plan_rate(ctx)
+        out["saturated"] = {"requests": len(sat), "trees_per_s": st2["trees_per_s"], "span_s": st2["span_s"],
+                            "device_busy_s": st2["busy_s"], "plan_trees_per_s": rate_plan,
+                            "fraction_of_plan_rate": st2["trees_per_s"] / rate_plan}
+        log(f"serving saturated ({len(sat)} requests at once): {st2['trees_per_s']:.4g} trees/s = "
+            f"{100 * st2['trees_per_s'] / rate_plan:.1f}% of the plan rate {rate_plan:.4g} trees/s")
     return out
 
 
@@ -449,14 +641,24 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="upper bound of one timed oracle run (the whole workload when it fits)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve-seconds", type=float, default=2.0,
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of the served request stream replayed after the throughput steps (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
-    ap.add_argument("--serve-max-trees", type=int, default=1 << 18)
+    ap.add_argument("--serve-max-trees", type=int, default=1 << 20)
+    ap.add_argument("--serve-max-points", type=int, default=16384, help="the server's device slots")
+    ap.add_argument("--serve-round-trees", type=int, default=32768, help="trees per point per tick")
+    ap.add_argument("--serve-plain-requests", type=int, default=1000,
+                    help="requests of the stream replayed through one brt_solve launch each")
+    ap.add_argument("--serve-saturated-requests", type=int, default=1000,
+                    help="requests of the stream submitted at once to measure the server's full rate")
     ap.add_argument("--pdd-trees", type=int, default=100_000,
                     help="trees per node of the domain-decomposition tail run after the steps (0: skip)")
     ap.add_argument("--pdd-cpu-steps", type=int, default=5)
     ap.add_argument("--no-strategy-b", action="store_true")
+    ap.add_argument("--configs", default="kpp,poly_batch",
+                    help="more workloads timed after the headline (comma list of kpp, poly_batch; empty: none)")
+    ap.add_argument("--config-steps", type=int, default=5)
+    ap.add_argument("--config-cpu-seconds", type=float, default=2.0)
     ap.add_argument("--pmc-calibration", action="store_true",
                     help="end with a plain 512 MiB device copy (scale of the rocprofv3 byte counters)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -576,11 +778,28 @@ def main():
     del out, starts, ends
     if not args.no_strategy_b:
         result["strategy_b"] = strategy_compare(ctx, wl, wall * 1e3 / args.steps, se_a)
+    if args.configs:
+        from paper_2402_06491_amd import inputs
+
+        extra = {}
+        headline_launch = ctx.get_launch()
+        for name in [c for c in args.configs.split(",") if c]:
+            if name == "kpp":
+                extra["kpp_fp64"] = config_bench(ctx, inputs.kpp(), args.config_steps, 1, args.config_cpu_seconds)
+            elif name == "poly_batch":
+                for prec in (32, 64):
+                    extra[f"poly_batch_fp{prec}"] = config_bench(ctx, inputs.poly_batch(precision=prec),
+                                                                 args.config_steps, 1, args.config_cpu_seconds)
+            else:
+                raise SystemExit(f"unknown config {name}")
+        ctx.set_launch(**headline_launch)  # the serving and tail legs below run with the headline's settings
+        result["configs"] = extra
     if args.serve_seconds > 0:
         result["serving"] = serve_bench(ctx, args.serve_seconds, args.serve_rate,
-                                        {"max_points": 8192, "round_trees": 16384,
+                                        {"max_points": args.serve_max_points, "round_trees": args.serve_round_trees,
                                          "max_trees": args.serve_max_trees, "target_se": 1e-3,
-                                         "queue_cap": 100_000})
+                                         "queue_cap": 100_000}, args.serve_plain_requests,
+                                        args.serve_saturated_requests)
     if args.pdd_trees > 0:
         result["pdd"] = pdd_bench(ctx, args.pdd_trees, args.pdd_cpu_steps)
     if args.pmc_calibration:

@@ -319,10 +319,13 @@ int brt_autotune(brt_ctx* ctx, uint32_t n_problems, const brt_problem* problems,
  * probabilistic part of Sec. 3: independent points, each summed from independent trees).
  *
  * An engine thread runs ticks; each tick adds one round of `round_trees` trees to every unfinished
- * point of every admitted request, packing all requests (64 per launch) into shared launches.  The
- * reduction partials of every round stay on the device in the point's slot; the finalize recomputes
- * coefficients, Pade value and SE from them after every round.  A point finishes when its SE
- * <= target_se or its trees reach max_trees; a request completes when all its points finish.
+ * point of the admitted requests it covers, packing them (64 requests per launch) into shared launches.
+ * Admitted requests are split between two lanes with their own streams: while one lane's tick runs on
+ * the device, the engine reads the other lane's results (copied back by its tick), admits requests and
+ * enqueues that lane's next tick.  The reduction partials of every round stay on the device in the
+ * point's slot; the finalize recomputes coefficients, Pade value and SE from them after every round.
+ * A point finishes when its SE <= target_se or its trees reach max_trees; a request completes when
+ * all its points finish.
  * Requests are admitted at tick boundaries while enough free slots (max_points, the memory bound)
  * remain; at most queue_cap requests wait, beyond that submit returns BRT_E_BUSY.  A point's trees
  * are addressed by (mc.seed, stream_id*1024 + point index, tree counter), so its results are
@@ -366,7 +369,7 @@ typedef struct brt_server_stats {
   uint32_t struct_size;
   uint64_t submitted, completed, rejected, ticks, trees, nodes;
   double p50_latency_s, p99_latency_s, mean_latency_s;
-  double busy_s;                /* wall time spent in ticks */
+  double busy_s;                /* device time of the ticks (HIP events around each tick, summed over lanes) */
   double span_s;                /* first submit to last completion */
   double trees_per_s;           /* trees / span_s */
 } brt_server_stats;

@@ -184,7 +184,15 @@ void pde_to_device(const brt_problem& p, const Norm& n, int precision, void* dst
 double est_nodes(const Norm& n, const brt_mc& mc, double t);
 int set_error(int code, const char* fmt, ...);  // records the thread's error message, returns code
 constexpr uint32_t kSegTrees = 1u << 13;          // trees per reduction segment of a serving round
-constexpr uint32_t kPlanSegTrees = 1u << 16;      // trees per reduction segment of a plan
+constexpr uint32_t kPlanSegMin = 1u << 10, kPlanSegMax = 1u << 16;  // trees per reduction segment of a plan
+// A plan's segment size: the power of two in [kPlanSegMin, kPlanSegMax] nearest above total / 4096, so
+// that a large workload has few partials per point to join and a small one still spreads its
+// reduction over many waves.
+inline uint32_t plan_seg_trees(uint64_t total) {
+  uint32_t s = kPlanSegMin;
+  while (s < kPlanSegMax && (uint64_t)s * 4096u < total) s <<= 1;
+  return s;
+}
 constexpr uint32_t kMaxDepthUnpruned = 64;        // stack levels per lane when trees are not pruned
 constexpr uint32_t kDefaultLdsLevels = 8;         // stack levels per lane kept in LDS by default
 

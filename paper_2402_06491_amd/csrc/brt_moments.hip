@@ -25,7 +25,7 @@
 namespace brt {
 
 constexpr int kRedGroup = 16;   // bins accumulated per pass over a segment (per-lane sums in LDS)
-static_assert((kSegTrees + kWave - 1) / kWave <= 65535 && (kPlanSegTrees + kWave - 1) / kWave <= 65535,
+static_assert((kSegTrees + kWave - 1) / kWave <= 65535 && (kPlanSegMax + kWave - 1) / kWave <= 65535,
               "per-lane counts are 16-bit");
 constexpr int kRedBatch = 32;   // records loaded per lane before they are accumulated
 constexpr uint32_t kAbsent = 0xffffffffu;  // marks a batch slot past the end of the segment (no real

@@ -24,7 +24,7 @@ constexpr uint64_t kNaMaxTrees = BRT_NOALLOC_MAX_TREES;
 constexpr uint32_t kNaMaxOrder = BRT_NOALLOC_MAX_ORDER;
 constexpr uint32_t kNaMaxBins = kNaMaxOrder + 2;
 constexpr uint32_t kNaMaxChunks = (uint32_t)(kNaMaxTrees / 64) + kNaMaxPoints;  // chunks hold >= 64 trees
-constexpr uint32_t kNaMaxSegs = (uint32_t)(kNaMaxTrees / kPlanSegTrees) + kNaMaxPoints;
+constexpr uint32_t kNaMaxSegs = (uint32_t)(kNaMaxTrees / kPlanSegMin) + kNaMaxPoints;
 constexpr int kNaMaxDevices = 64;
 
 constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -39,7 +39,7 @@ constexpr size_t kOffSegNodes = align256(kOffPartials + (size_t)kNaMaxSegs * (kN
 constexpr size_t kOffTreeF = align256(kOffSegNodes + (size_t)kNaMaxSegs * sizeof(unsigned long long));
 constexpr size_t kOffTreeMeta = align256(kOffTreeF + (size_t)kNaMaxTrees * sizeof(double));
 constexpr size_t kScratchBytes = align256(kOffTreeMeta + (size_t)kNaMaxTrees * sizeof(uint32_t));
-static_assert(kScratchBytes <= (size_t(56) << 20), "the scratch array is meant to stay near 52.5 MiB");
+static_assert(kScratchBytes <= (size_t(60) << 20), "the scratch array is meant to stay near 55 MiB");
 
 // The device scratch array.  In host code its name is only a handle for hipGetSymbolAddress: the device
 // address of each GPU's copy is looked up once (noalloc_init_device) and used everywhere instead.
@@ -162,12 +162,13 @@ extern "C" int brt_solve_noalloc(brt_ctx* ctx, uint32_t n_problems, const brt_pr
     }
   }
   // reduction segments, in point order
+  const uint32_t seg_trees = plan_seg_trees(total);
   for (uint32_t i = 0; i < pts->n; ++i) {
     PointRec& r = h_points[i];
     r.seg_begin = ns;
-    for (uint32_t b0 = 0; b0 < r.n_trees; b0 += kPlanSegTrees) {
+    for (uint32_t b0 = 0; b0 < r.n_trees; b0 += seg_trees) {
       if (ns == kNaMaxSegs) return na_fail(BRT_E_ARG, "too many reduction segments");
-      h_segs[ns] = Segment{i, b0, std::min(r.n_trees, b0 + kPlanSegTrees), ns};
+      h_segs[ns] = Segment{i, b0, std::min(r.n_trees, b0 + seg_trees), ns};
       ++ns;
     }
     r.seg_count = ns - r.seg_begin;

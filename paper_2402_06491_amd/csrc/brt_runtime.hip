@@ -458,11 +458,12 @@ extern "C" int brt_plan_create(brt_ctx* ctx, uint32_t n_problems, const brt_prob
     for (uint32_t b0 = 0; b0 < n; b0 += ct) p->chunks.push_back(Chunk{i, b0, std::min(n, b0 + ct), 0u});
   }
   // reduction segments, in point order
+  const uint32_t seg_trees = plan_seg_trees(p->total_trees);
   for (uint32_t i = 0; i < pts->n; ++i) {
     PointRec& r = p->points[i];
     r.seg_begin = (uint32_t)p->segs.size();
-    for (uint32_t b0 = 0; b0 < r.n_trees; b0 += kPlanSegTrees)
-      p->segs.push_back(Segment{i, b0, std::min(r.n_trees, b0 + kPlanSegTrees), (uint32_t)p->segs.size()});
+    for (uint32_t b0 = 0; b0 < r.n_trees; b0 += seg_trees)
+      p->segs.push_back(Segment{i, b0, std::min(r.n_trees, b0 + seg_trees), (uint32_t)p->segs.size()});
     r.seg_count = (uint32_t)p->segs.size() - r.seg_begin;
   }
 

@@ -1,17 +1,23 @@
 // Continuous-batching server for point queries (brt_server_* in include/brt.h).
 //
-// An engine thread runs ticks.  A tick gives every unfinished point of every admitted request one
-// more round of `round_trees` trees: the rounds of all requests are packed into as few launches as
-// the problem table allows (64 problems, i.e. requests, per launch), so requests of different sizes
-// and horizons share the GPU.  Each point owns a device slot holding the reduction partials of all
-// its rounds; the finalize recomputes the point's coefficients, Pade value and SE from the slot after
-// every round.  A point finishes when its SE reaches the target or its trees reach the cap; a request
-// completes when all its points have finished, and its slots are freed.  New requests are admitted
-// at tick boundaries while free slots remain (memory admission); the submission queue is bounded.
+// An engine thread runs ticks.  A tick gives every unfinished point of the requests it covers one more
+// round of `round_trees` trees: the rounds of all those requests are packed into as few launches as the
+// problem table allows (64 problems, i.e. requests, per launch), so requests of different sizes and
+// horizons share the GPU.  Each point owns a device slot holding the reduction partials of all its
+// rounds; the finalize recomputes the point's coefficients, Pade value and SE from the slot after every
+// round.  A point finishes when its SE reaches the target or its trees reach the cap; a request completes
+// when all its points have finished, and its slots are freed.  New requests are admitted at tick
+// boundaries while free slots remain (memory admission); the submission queue is bounded.
 //
-// A point's trees are addressed by (seed, point id, tree counter), its partials are combined in
-// round order, and the number of rounds depends only on its own SE: its results are bit-identical
-// whether it is served alone or among other requests.
+// Admitted requests are split between two lanes, each with its own stream, staging and device buffers
+// (the slots and their partials are shared).  The engine alternates: it waits for one lane's tick, reads
+// its results (copied back by the tick itself), admits requests and enqueues that lane's next tick,
+// while the other lane's tick runs on the GPU.  So the host's packing and bookkeeping overlap the
+// device's work, and the two lanes' kernels may overlap on the device.
+//
+// A point's trees are addressed by (seed, point id, tree counter), its partials are combined in round
+// order, and the number of rounds depends only on its own SE: its results are bit-identical whether it
+// is served alone or among other requests, in either lane.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -37,6 +43,8 @@ namespace {
 
 constexpr uint32_t kMaxRequestPoints = 1024;
 constexpr uint32_t kChunkTrees = 1024;
+constexpr int kLanes = 2;
+constexpr uint32_t kCounterStride = 16;  // 64 bytes between the chunk counters of a lane's launch groups
 
 struct Request {
   uint64_t ticket = 0;
@@ -44,6 +52,7 @@ struct Request {
   Norm norm;
   uint32_t stream_id = 0;
   uint32_t n = 0;
+  int lane = 0;
   std::vector<double> x, t;
   Clock::time_point arrival, finished_at;
   std::vector<uint32_t> slot, rounds;
@@ -54,45 +63,54 @@ struct Request {
   std::vector<uint32_t> flags;
 };
 
+// One lane: a stream, its launch staging (pinned) and device buffers, and the read-back of its ticks.
+struct Lane {
+  hipStream_t stream = nullptr;
+  hipEvent_t ev_start = nullptr, ev_done = nullptr;
+  void* d_pdes = nullptr;                 // [max_groups][kMaxProblems] problem tables
+  PointRec* d_points = nullptr;           // [max_points]
+  Chunk* d_chunks = nullptr;              // [max_points * chunks_per_round]
+  Segment* d_segs = nullptr;              // [max_points * segs_per_round]
+  uint32_t* d_counter = nullptr;          // [max_groups * kCounterStride]
+  unsigned long long* d_depth = nullptr;  // [max_groups]
+  double* d_tree_f = nullptr;             // [max_points * round_trees]
+  uint32_t* d_tree_meta = nullptr;
+  void* d_spill = nullptr;
+  PointRec* h_points = nullptr;
+  Chunk* h_chunks = nullptr;
+  Segment* h_segs = nullptr;
+  unsigned char* h_pdes = nullptr;
+  double *h_u = nullptr, *h_se = nullptr, *h_coef = nullptr;  // read-back, indexed by slot
+  unsigned long long* h_nodes = nullptr;
+  uint32_t* h_flags = nullptr;
+  std::vector<Request*> reqs;      // admitted, unfinished requests of this lane
+  std::vector<Request*> inflight;  // the requests of the tick in flight
+  bool busy = false;
+  uint32_t slot_lo = 0, slot_hi = 0;  // slots read back by the tick in flight
+};
+
 }  // namespace
 
 struct brt_server {
   int device = 0;
   int n_cu = 0;
   brt_server_opts opts{};
-  hipStream_t stream = nullptr;
-  uint32_t B = 0, NB = 0, segs_per_round = 0, max_segs = 0, chunks_per_round = 0;
+  uint32_t B = 0, NB = 0, segs_per_round = 0, max_segs = 0, chunks_per_round = 0, max_groups = 0;
   int grid = 0, wpb = 4, lds_depth = 0, spill_depth = 0;
-  // device buffers
-  void* d_pdes = nullptr;
-  PointRec* d_points = nullptr;
-  Chunk* d_chunks = nullptr;
-  Segment* d_segs = nullptr;
-  uint32_t* d_counter = nullptr;
-  unsigned long long* d_depth = nullptr;
-  double* d_tree_f = nullptr;
-  uint32_t* d_tree_meta = nullptr;
-  void* d_spill = nullptr;
+  Lane lanes[kLanes];
+  // per-slot device state shared by the lanes (each slot belongs to one point of one lane at a time)
   Partial* d_partials = nullptr;
   unsigned long long* d_seg_nodes = nullptr;
   double *d_u = nullptr, *d_se = nullptr, *d_coef = nullptr;
   unsigned long long* d_nodes = nullptr;
   uint32_t* d_flags = nullptr;
-  // pinned staging
-  PointRec* h_points = nullptr;
-  Chunk* h_chunks = nullptr;
-  Segment* h_segs = nullptr;
-  unsigned char* h_pdes = nullptr;
-  double *h_u = nullptr, *h_se = nullptr;
-  unsigned long long* h_nodes = nullptr;
-  uint32_t* h_flags = nullptr;
   // state
   std::mutex mu;
   std::condition_variable cv, done_cv;
   std::deque<Request*> queue;
-  std::vector<Request*> active;
   std::unordered_map<uint64_t, Request*> requests;
   std::vector<uint32_t> free_slots;
+  uint32_t n_active = 0;  // admitted, incomplete requests
   uint64_t next_ticket = 1;
   bool stop = false;     // finish the admitted requests, then exit
   bool abandon = false;  // exit at the next tick boundary
@@ -117,13 +135,19 @@ namespace {
 
 void server_free(brt_server* s) {
   if (!s) return;
-  if (s->stream) (void)hipStreamDestroy(s->stream);
-  void* dev[] = {s->d_pdes, s->d_points, s->d_chunks, s->d_segs, s->d_counter, s->d_depth, s->d_tree_f,
-                 s->d_tree_meta, s->d_spill, s->d_partials, s->d_seg_nodes, s->d_u, s->d_se, s->d_coef,
-                 s->d_nodes, s->d_flags};
+  for (Lane& L : s->lanes) {
+    if (L.stream) (void)hipStreamSynchronize(L.stream);
+    void* dev[] = {L.d_pdes, L.d_points, L.d_chunks, L.d_segs, L.d_counter, L.d_depth, L.d_tree_f, L.d_tree_meta,
+                   L.d_spill};
+    for (void* p : dev) (void)hipFree(p);
+    void* host[] = {L.h_points, L.h_chunks, L.h_segs, L.h_pdes, L.h_u, L.h_se, L.h_coef, L.h_nodes, L.h_flags};
+    for (void* p : host) (void)hipHostFree(p);
+    if (L.ev_start) (void)hipEventDestroy(L.ev_start);
+    if (L.ev_done) (void)hipEventDestroy(L.ev_done);
+    if (L.stream) (void)hipStreamDestroy(L.stream);
+  }
+  void* dev[] = {s->d_partials, s->d_seg_nodes, s->d_u, s->d_se, s->d_coef, s->d_nodes, s->d_flags};
   for (void* p : dev) (void)hipFree(p);
-  void* host[] = {s->h_points, s->h_chunks, s->h_segs, s->h_pdes, s->h_u, s->h_se, s->h_nodes, s->h_flags};
-  for (void* p : host) (void)hipHostFree(p);
   for (auto& kv : s->requests) delete kv.second;
   for (Request* r : s->queue)
     if (!s->requests.count(r->ticket)) delete r;
@@ -144,143 +168,222 @@ int host_alloc(T** p, size_t n) {
   return BRT_OK;
 }
 
-// One launch group: up to kMaxProblems requests' unfinished points, one round each.
-int run_group(brt_server* s, const std::vector<Request*>& group) {
+// Enqueue one tick of a lane on its stream: one round for every unfinished point of the lane's requests,
+// in launch groups of up to kMaxProblems requests, then the copies of every slot's results back to the
+// lane's pinned buffers and the completion event.  Nothing here waits for the device.
+int issue_tick(brt_server* s, Lane& L) {
   const brt_mc& mc = s->opts.mc;
   const uint32_t R = s->opts.round_trees;
   const size_t pb = pde_bytes((int)mc.precision);
-  // points, most expensive first (longest-processing-time order of the chunks)
   struct Item {
     Request* r;
     uint32_t i, k;
     double cost;
   };
   std::vector<Item> items;
-  uint32_t cmod = 0;
-  for (uint32_t k = 0; k < group.size(); ++k) {
-    Request* r = group[k];
-    pde_to_device(r->prob, r->norm, (int)mc.precision, s->h_pdes + (size_t)k * pb);
-    cmod |= general_coefficients(r->prob) ? 1u : 0u;
-    for (uint32_t i = 0; i < r->n; ++i)
-      if (!r->done[i]) items.push_back(Item{r, i, k, est_nodes(r->norm, mc, r->t[i])});
-  }
-  std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.cost > b.cost; });
-  const uint32_t np = (uint32_t)items.size();
-  uint32_t nc = 0, ns = 0;
-  for (uint32_t p = 0; p < np; ++p) {
-    const Item& it = items[p];
-    Request* r = it.r;
-    const uint32_t slot = r->slot[it.i];
-    const uint32_t round = r->rounds[it.i];
-    PointRec& pr = s->h_points[p];
-    std::memset(&pr, 0, sizeof(pr));
-    pr.x[0] = r->x[(size_t)it.i * s->opts.dim];
-    pr.x[1] = s->opts.dim == 2 ? r->x[(size_t)it.i * 2 + 1] : 0.0;
-    pr.t = r->t[it.i];
-    pr.theta = r->norm.K > 0 ? std::exp(-r->norm.lambda * pr.t) : 1.0;
-    pr.mu = r->norm.mu;
-    pr.tree_base = (uint64_t)p * R;
-    pr.n_trees = R;
-    pr.point_id = r->stream_id * kMaxRequestPoints + it.i;
-    pr.pde = it.k;
-    pr.tree_first = round * R;
-    pr.n_total = (uint64_t)(round + 1) * R;
-    pr.seg_begin = slot * s->max_segs;
-    pr.seg_count = (round + 1) * s->segs_per_round;
-    pr.out_row = slot;
+  uint32_t np = 0, nc = 0, ns = 0, slot_lo = ~0u, slot_hi = 0;
+  L.inflight = L.reqs;
+  SRV_TRY(hipEventRecord(L.ev_start, L.stream));
+  for (size_t g0 = 0, grp = 0; g0 < L.reqs.size(); g0 += kMaxProblems, ++grp) {
+    const size_t g1 = std::min(L.reqs.size(), g0 + (size_t)kMaxProblems);
+    // the group's points, most expensive first (longest-processing-time order of the chunks)
+    items.clear();
+    uint32_t cmod = 0;
+    unsigned char* pdes = L.h_pdes + grp * kMaxProblems * pb;
+    for (size_t k = g0; k < g1; ++k) {
+      Request* r = L.reqs[k];
+      pde_to_device(r->prob, r->norm, (int)mc.precision, pdes + (k - g0) * pb);
+      cmod |= general_coefficients(r->prob) ? 1u : 0u;
+      for (uint32_t i = 0; i < r->n; ++i)
+        if (!r->done[i]) items.push_back(Item{r, i, (uint32_t)(k - g0), est_nodes(r->norm, mc, r->t[i])});
+    }
+    std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.cost > b.cost; });
+    const uint32_t p0 = np, c0 = nc, s0 = ns;
+    for (const Item& it : items) {
+      Request* r = it.r;
+      const uint32_t slot = r->slot[it.i];
+      const uint32_t round = r->rounds[it.i];
+      slot_lo = std::min(slot_lo, slot);
+      slot_hi = std::max(slot_hi, slot + 1);
+      PointRec& pr = L.h_points[np];
+      std::memset(&pr, 0, sizeof(pr));
+      pr.x[0] = r->x[(size_t)it.i * s->opts.dim];
+      pr.x[1] = s->opts.dim == 2 ? r->x[(size_t)it.i * 2 + 1] : 0.0;
+      pr.t = r->t[it.i];
+      pr.theta = r->norm.K > 0 ? std::exp(-r->norm.lambda * pr.t) : 1.0;
+      pr.mu = r->norm.mu;
+      pr.tree_base = (uint64_t)np * R;
+      pr.n_trees = R;
+      pr.point_id = r->stream_id * kMaxRequestPoints + it.i;
+      pr.pde = it.k;
+      pr.tree_first = round * R;
+      pr.n_total = (uint64_t)(round + 1) * R;
+      pr.seg_begin = slot * s->max_segs;
+      pr.seg_count = (round + 1) * s->segs_per_round;
+      pr.out_row = slot;
+      for (uint32_t g = 0; g < s->segs_per_round; ++g)
+        L.h_segs[ns++] = Segment{np, g * kSegTrees, (g + 1) * kSegTrees, slot * s->max_segs + round * s->segs_per_round + g};
+      ++np;
+    }
+    // chunks interleaved in cost order: all points' first chunks, then their second chunks, ...
     for (uint32_t c = 0; c < s->chunks_per_round; ++c)
-      s->h_chunks[nc++] = Chunk{p, c * kChunkTrees, (c + 1) * kChunkTrees, 0u};
-    for (uint32_t g = 0; g < s->segs_per_round; ++g)
-      s->h_segs[ns++] = Segment{p, g * kSegTrees, (g + 1) * kSegTrees, slot * s->max_segs + round * s->segs_per_round + g};
+      for (uint32_t p = p0; p < np; ++p) L.h_chunks[nc++] = Chunk{p, c * kChunkTrees, (c + 1) * kChunkTrees, 0u};
+    if (np == p0) continue;
+    void* d_pdes = static_cast<unsigned char*>(L.d_pdes) + grp * kMaxProblems * pb;
+    SRV_TRY(hipMemcpyAsync(d_pdes, pdes, (g1 - g0) * pb, hipMemcpyHostToDevice, L.stream));
+    SRV_TRY(hipMemcpyAsync(L.d_points + p0, L.h_points + p0, (np - p0) * sizeof(PointRec), hipMemcpyHostToDevice,
+                           L.stream));
+    SRV_TRY(hipMemcpyAsync(L.d_chunks + c0, L.h_chunks + c0, (nc - c0) * sizeof(Chunk), hipMemcpyHostToDevice, L.stream));
+    SRV_TRY(hipMemcpyAsync(L.d_segs + s0, L.h_segs + s0, (ns - s0) * sizeof(Segment), hipMemcpyHostToDevice, L.stream));
+    uint32_t* counter = L.d_counter + grp * kCounterStride;
+    unsigned long long* depth = L.d_depth + grp;
+    SRV_TRY(launch_reset(counter, depth, L.stream));
+    WalkArgs w{};
+    w.points = L.d_points;
+    w.chunks = L.d_chunks + c0;
+    w.n_chunks = nc - c0;
+    w.n_problems = (uint32_t)(g1 - g0);
+    w.pdes = d_pdes;
+    w.chunk_counter = counter;
+    w.depth_counter = depth;
+    w.tree_f = L.d_tree_f;
+    w.tree_meta = L.d_tree_meta;
+    w.spill = L.d_spill;
+    w.key0 = (uint32_t)(mc.seed & 0xffffffffull);
+    w.key1 = (uint32_t)(mc.seed >> 32);
+    w.max_order = mc.max_order;
+    w.prune = mc.prune;
+    w.node_cap = mc.node_cap;
+    w.strategy = mc.strategy;
+    w.cmod = cmod;
+    w.stack_depth = (uint32_t)s->lds_depth;
+    w.spill_depth = (uint32_t)s->spill_depth;
+    w.n_threads = (uint32_t)(s->grid * s->wpb * kWave);
+    const int grid = std::max(1, std::min<int>(s->grid, (int)(nc - c0)));
+    SRV_TRY(launch_walk((int)mc.precision, (int)s->opts.dim, (int)s->opts.u0_kind, w, grid, s->wpb, L.stream));
+    ReduceArgs ra{};
+    ra.points = L.d_points;
+    ra.segs = L.d_segs + s0;
+    ra.n_segs = ns - s0;
+    ra.tree_f = L.d_tree_f;
+    ra.tree_meta = L.d_tree_meta;
+    ra.partials = s->d_partials;
+    ra.seg_nodes = s->d_seg_nodes;
+    ra.n_bins = s->B;
+    SRV_TRY(launch_reduce(ra, L.stream));
+    FinalizeArgs f{};
+    f.points = L.d_points + p0;
+    f.n_points = np - p0;
+    f.partials = s->d_partials;
+    f.seg_nodes = s->d_seg_nodes;
+    f.n_bins = s->B;
+    f.pade_L = mc.pade_L;
+    f.pade_M = mc.pade_M;
+    f.u = s->d_u;
+    f.se = s->d_se;
+    f.coef = s->d_coef;
+    f.nodes = s->d_nodes;
+    f.flags = s->d_flags;
+    SRV_TRY(launch_finalize(f, L.stream));
   }
-  // chunks interleaved in cost order: all points' first chunks, then their second chunks, ...
-  std::vector<Chunk> order(nc);
-  for (uint32_t c = 0, o = 0; c < s->chunks_per_round; ++c)
-    for (uint32_t p = 0; p < np; ++p) order[o++] = s->h_chunks[(size_t)p * s->chunks_per_round + c];
-  std::memcpy(s->h_chunks, order.data(), nc * sizeof(Chunk));
-
-  SRV_TRY(hipMemcpyAsync(s->d_pdes, s->h_pdes, group.size() * pb, hipMemcpyHostToDevice, s->stream));
-  SRV_TRY(hipMemcpyAsync(s->d_points, s->h_points, np * sizeof(PointRec), hipMemcpyHostToDevice, s->stream));
-  SRV_TRY(hipMemcpyAsync(s->d_chunks, s->h_chunks, nc * sizeof(Chunk), hipMemcpyHostToDevice, s->stream));
-  SRV_TRY(hipMemcpyAsync(s->d_segs, s->h_segs, ns * sizeof(Segment), hipMemcpyHostToDevice, s->stream));
-  SRV_TRY(launch_reset(s->d_counter, s->d_depth, s->stream));
-  WalkArgs w{};
-  w.points = s->d_points;
-  w.chunks = s->d_chunks;
-  w.n_chunks = nc;
-  w.n_problems = (uint32_t)group.size();
-  w.pdes = s->d_pdes;
-  w.chunk_counter = s->d_counter;
-  w.depth_counter = s->d_depth;
-  w.tree_f = s->d_tree_f;
-  w.tree_meta = s->d_tree_meta;
-  w.spill = s->d_spill;
-  w.key0 = (uint32_t)(mc.seed & 0xffffffffull);
-  w.key1 = (uint32_t)(mc.seed >> 32);
-  w.max_order = mc.max_order;
-  w.prune = mc.prune;
-  w.node_cap = mc.node_cap;
-  w.strategy = mc.strategy;
-  w.cmod = cmod;
-  w.stack_depth = (uint32_t)s->lds_depth;
-  w.spill_depth = (uint32_t)s->spill_depth;
-  w.n_threads = (uint32_t)(s->grid * s->wpb * kWave);
-  const int grid = std::max(1, std::min<int>(s->grid, (int)nc));
-  SRV_TRY(launch_walk((int)mc.precision, (int)s->opts.dim, (int)s->opts.u0_kind, w, grid, s->wpb, s->stream));
-  ReduceArgs ra{};
-  ra.points = s->d_points;
-  ra.segs = s->d_segs;
-  ra.n_segs = ns;
-  ra.tree_f = s->d_tree_f;
-  ra.tree_meta = s->d_tree_meta;
-  ra.partials = s->d_partials;
-  ra.seg_nodes = s->d_seg_nodes;
-  ra.n_bins = s->B;
-  SRV_TRY(launch_reduce(ra, s->stream));
-  FinalizeArgs f{};
-  f.points = s->d_points;
-  f.n_points = np;
-  f.partials = s->d_partials;
-  f.seg_nodes = s->d_seg_nodes;
-  f.n_bins = s->B;
-  f.pade_L = mc.pade_L;
-  f.pade_M = mc.pade_M;
-  f.u = s->d_u;
-  f.se = s->d_se;
-  f.coef = s->d_coef;
-  f.nodes = s->d_nodes;
-  f.flags = s->d_flags;
-  SRV_TRY(launch_finalize(f, s->stream));
-  // the staging buffers are reused by the next group: wait for this group's copies and kernels
-  SRV_TRY(hipStreamSynchronize(s->stream));
+  // the lane's results back to its pinned buffers (the span of slots its points occupy)
+  if (np > 0) {
+    const size_t n = slot_hi - slot_lo;
+    SRV_TRY(hipMemcpyAsync(L.h_u + slot_lo, s->d_u + slot_lo, n * sizeof(double), hipMemcpyDeviceToHost, L.stream));
+    SRV_TRY(hipMemcpyAsync(L.h_se + slot_lo, s->d_se + slot_lo, n * sizeof(double), hipMemcpyDeviceToHost, L.stream));
+    SRV_TRY(hipMemcpyAsync(L.h_flags + slot_lo, s->d_flags + slot_lo, n * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                           L.stream));
+    SRV_TRY(hipMemcpyAsync(L.h_nodes + slot_lo, s->d_nodes + slot_lo, n * sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, L.stream));
+    SRV_TRY(hipMemcpyAsync(L.h_coef + (size_t)slot_lo * s->B, s->d_coef + (size_t)slot_lo * s->B,
+                           n * s->B * sizeof(double), hipMemcpyDeviceToHost, L.stream));
+  }
+  SRV_TRY(hipEventRecord(L.ev_done, L.stream));
+  L.slot_lo = np ? slot_lo : 0;
+  L.slot_hi = np ? slot_hi : 0;
+  L.busy = true;
   return BRT_OK;
 }
 
-int run_tick(brt_server* s, const std::vector<Request*>& act) {
-  const auto t0 = Clock::now();
-  std::vector<Request*> group;
-  for (Request* r : act) {
-    group.push_back(r);
-    if (group.size() == (size_t)kMaxProblems) {
-      int rc = run_group(s, group);
-      if (rc) return rc;
-      group.clear();
+// Wait for a lane's tick and fold its results into its requests (called without the lock; takes it).
+int finish_tick(brt_server* s, Lane& L) {
+  SRV_TRY(hipEventSynchronize(L.ev_done));
+  float ms = 0.f;
+  SRV_TRY(hipEventElapsedTime(&ms, L.ev_start, L.ev_done));
+  L.busy = false;
+  const uint32_t R = s->opts.round_trees;
+  const auto now = Clock::now();
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->busy_s += ms * 1e-3;
+  s->ticks += 1;
+  std::vector<Request*> still;
+  for (Request* r : L.inflight) {
+    for (uint32_t i = 0; i < r->n; ++i) {
+      if (r->done[i]) continue;
+      const uint32_t slot = r->slot[i];
+      r->rounds[i] += 1;
+      s->trees += R;
+      const uint64_t n_trees = (uint64_t)r->rounds[i] * R;
+      const double se = L.h_se[slot];
+      const bool reached = s->opts.target_se > 0.0 && se <= s->opts.target_se;
+      if (reached || n_trees >= s->opts.max_trees) {
+        r->done[i] = 1;
+        r->n_done += 1;
+        r->u[i] = L.h_u[slot];
+        r->se[i] = se;
+        r->flags[i] = L.h_flags[slot];
+        s->nodes += L.h_nodes[slot];
+        std::memcpy(r->coef.data() + (size_t)i * s->B, L.h_coef + (size_t)slot * s->B, s->B * sizeof(double));
+      }
+    }
+    if (r->n_done == r->n) {
+      r->complete = true;
+      r->finished_at = now;
+      for (uint32_t i = 0; i < r->n; ++i) s->free_slots.push_back(r->slot[i]);
+      s->latencies.push_back(std::chrono::duration<double>(now - r->arrival).count());
+      s->completed += 1;
+      s->n_active -= 1;
+      s->last_complete = now;
+    } else {
+      still.push_back(r);
     }
   }
-  if (!group.empty()) {
-    int rc = run_group(s, group);
-    if (rc) return rc;
-  }
-  const uint32_t slots = s->opts.max_points;
-  SRV_TRY(hipMemcpyAsync(s->h_u, s->d_u, slots * sizeof(double), hipMemcpyDeviceToHost, s->stream));
-  SRV_TRY(hipMemcpyAsync(s->h_se, s->d_se, slots * sizeof(double), hipMemcpyDeviceToHost, s->stream));
-  SRV_TRY(hipMemcpyAsync(s->h_flags, s->d_flags, slots * sizeof(uint32_t), hipMemcpyDeviceToHost, s->stream));
-  SRV_TRY(hipMemcpyAsync(s->h_nodes, s->d_nodes, slots * sizeof(unsigned long long), hipMemcpyDeviceToHost,
-                         s->stream));
-  SRV_TRY(hipStreamSynchronize(s->stream));
-  s->busy_s += std::chrono::duration<double>(Clock::now() - t0).count();
-  s->ticks += 1;
+  // requests admitted into this lane while its tick ran are already in L.reqs after the in-flight ones
+  std::vector<Request*> added(L.reqs.begin() + (ptrdiff_t)L.inflight.size(), L.reqs.end());
+  L.reqs.swap(still);
+  L.reqs.insert(L.reqs.end(), added.begin(), added.end());
+  L.inflight.clear();
+  s->done_cv.notify_all();
   return BRT_OK;
+}
+
+// Admission (under the lock): queued requests in arrival order while their points fit the free slots and
+// the cap on requests in flight allows; each goes to the lane with fewer unfinished points.
+void admit(brt_server* s) {
+  while (!s->queue.empty()) {
+    Request* r = s->queue.front();
+    if (r->n > s->free_slots.size()) break;
+    if (s->opts.max_active_requests && s->n_active >= s->opts.max_active_requests) break;
+    s->queue.pop_front();
+    for (uint32_t i = 0; i < r->n; ++i) {
+      r->slot[i] = s->free_slots.back();
+      s->free_slots.pop_back();
+    }
+    size_t load[kLanes] = {0, 0};
+    for (int l = 0; l < kLanes; ++l)
+      for (Request* q : s->lanes[l].reqs) load[l] += q->n - q->n_done;
+    r->lane = load[1] < load[0] ? 1 : 0;
+    s->lanes[r->lane].reqs.push_back(r);
+    s->n_active += 1;
+  }
+}
+
+void engine_fail(brt_server* s, int rc) {
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->engine_rc = rc;
+  s->engine_msg = brt_last_error();
+  s->stop = true;
+  s->done_cv.notify_all();
 }
 
 void engine_main(brt_server* s) {
@@ -291,76 +394,31 @@ void engine_main(brt_server* s) {
     s->done_cv.notify_all();
     return;
   }
-  const uint32_t R = s->opts.round_trees;
+  int turn = 0;
   while (true) {
-    std::vector<Request*> act;
+    Lane& L = s->lanes[turn];
+    if (L.busy) {
+      const int rc = finish_tick(s, L);
+      if (rc) return engine_fail(s, rc);
+    }
+    bool issue = false;
     {
       std::unique_lock<std::mutex> lk(s->mu);
       if (s->abandon) return;
-      // admission: by free slots (device memory) and the optional cap on requests in flight
-      while (!s->queue.empty()) {
-        Request* r = s->queue.front();
-        if (r->n > s->free_slots.size()) break;
-        if (s->opts.max_active_requests && s->active.size() >= s->opts.max_active_requests) break;
-        s->queue.pop_front();
-        for (uint32_t i = 0; i < r->n; ++i) {
-          r->slot[i] = s->free_slots.back();
-          s->free_slots.pop_back();
-        }
-        s->active.push_back(r);
-      }
-      if (s->active.empty()) {
-        if (s->stop) return;
+      admit(s);
+      issue = !L.reqs.empty();
+      if (!issue && !s->lanes[turn ^ 1].busy && s->lanes[turn ^ 1].reqs.empty()) {
+        // nothing in flight and nothing admitted
+        if (s->stop && s->queue.empty()) return;
         s->cv.wait_for(lk, std::chrono::milliseconds(2));
         continue;
       }
-      act = s->active;
     }
-    const int rc = run_tick(s, act);
-    std::lock_guard<std::mutex> lk(s->mu);
-    if (rc) {
-      s->engine_rc = rc;
-      s->engine_msg = brt_last_error();
-      s->stop = true;
-      s->done_cv.notify_all();
-      return;
+    if (issue) {
+      const int rc = issue_tick(s, L);
+      if (rc) return engine_fail(s, rc);
     }
-    const auto now = Clock::now();
-    std::vector<Request*> still;
-    for (Request* r : act) {
-      for (uint32_t i = 0; i < r->n; ++i) {
-        if (r->done[i]) continue;
-        const uint32_t slot = r->slot[i];
-        r->rounds[i] += 1;
-        s->trees += R;
-        const uint64_t n_trees = (uint64_t)r->rounds[i] * R;
-        const double se = s->h_se[slot];
-        const bool reached = s->opts.target_se > 0.0 && se <= s->opts.target_se;
-        if (reached || n_trees >= s->opts.max_trees) {
-          r->done[i] = 1;
-          r->n_done += 1;
-          r->u[i] = s->h_u[slot];
-          r->se[i] = se;
-          r->flags[i] = s->h_flags[slot];
-          s->nodes += s->h_nodes[slot];
-          // coefficients of the finished point
-          (void)hipMemcpy(r->coef.data() + (size_t)i * s->B, s->d_coef + (size_t)slot * s->B, s->B * sizeof(double),
-                          hipMemcpyDeviceToHost);
-        }
-      }
-      if (r->n_done == r->n) {
-        r->complete = true;
-        r->finished_at = now;
-        for (uint32_t i = 0; i < r->n; ++i) s->free_slots.push_back(r->slot[i]);
-        s->latencies.push_back(std::chrono::duration<double>(now - r->arrival).count());
-        s->completed += 1;
-        s->last_complete = now;
-      } else {
-        still.push_back(r);
-      }
-    }
-    s->active.swap(still);
-    s->done_cv.notify_all();
+    turn ^= 1;
   }
 }
 
@@ -423,15 +481,34 @@ int brt_server_create(brt_ctx* ctx, const brt_server_opts* o, brt_server** out) 
   const size_t P = o->max_points;
   const size_t R = o->round_trees;
   int rc = BRT_OK;
-  rc = rc ? rc : (hipStreamCreate(&s->stream) == hipSuccess ? BRT_OK : set_error(BRT_E_DEVICE, "server: stream"));
-  rc = rc ? rc : dev_alloc(reinterpret_cast<unsigned char**>(&s->d_pdes), kMaxProblems * pde_bytes((int)mc.precision));
-  rc = rc ? rc : dev_alloc(&s->d_points, P);
-  rc = rc ? rc : dev_alloc(&s->d_chunks, P * s->chunks_per_round);
-  rc = rc ? rc : dev_alloc(&s->d_segs, P * s->segs_per_round);
-  rc = rc ? rc : dev_alloc(&s->d_counter, 16);
-  rc = rc ? rc : dev_alloc(&s->d_depth, 8);
-  rc = rc ? rc : dev_alloc(&s->d_tree_f, P * R);
-  rc = rc ? rc : dev_alloc(&s->d_tree_meta, P * R);
+  s->max_groups = (uint32_t)((P + kMaxProblems - 1) / kMaxProblems);  // requests of one point each, 64 per launch
+  const size_t pb = pde_bytes((int)mc.precision);
+  const size_t spill = s->spill_depth > 0 ? (size_t)s->grid * s->wpb * kWave * s->spill_depth *
+                                                stack_entry_size((int)mc.precision, (int)o->dim)
+                                          : 0;
+  for (Lane& L : s->lanes) {
+    rc = rc ? rc : (hipStreamCreate(&L.stream) == hipSuccess ? BRT_OK : set_error(BRT_E_DEVICE, "server: stream"));
+    rc = rc ? rc : (hipEventCreate(&L.ev_start) == hipSuccess ? BRT_OK : set_error(BRT_E_DEVICE, "server: event"));
+    rc = rc ? rc : (hipEventCreate(&L.ev_done) == hipSuccess ? BRT_OK : set_error(BRT_E_DEVICE, "server: event"));
+    rc = rc ? rc : dev_alloc(reinterpret_cast<unsigned char**>(&L.d_pdes), s->max_groups * kMaxProblems * pb);
+    rc = rc ? rc : dev_alloc(&L.d_points, P);
+    rc = rc ? rc : dev_alloc(&L.d_chunks, P * s->chunks_per_round);
+    rc = rc ? rc : dev_alloc(&L.d_segs, P * s->segs_per_round);
+    rc = rc ? rc : dev_alloc(&L.d_counter, (size_t)s->max_groups * kCounterStride);
+    rc = rc ? rc : dev_alloc(&L.d_depth, s->max_groups);
+    rc = rc ? rc : dev_alloc(&L.d_tree_f, P * R);
+    rc = rc ? rc : dev_alloc(&L.d_tree_meta, P * R);
+    if (!rc && spill) rc = dev_alloc(reinterpret_cast<unsigned char**>(&L.d_spill), spill);
+    rc = rc ? rc : host_alloc(&L.h_points, P);
+    rc = rc ? rc : host_alloc(&L.h_chunks, P * s->chunks_per_round);
+    rc = rc ? rc : host_alloc(&L.h_segs, P * s->segs_per_round);
+    rc = rc ? rc : host_alloc(&L.h_pdes, s->max_groups * kMaxProblems * pb);
+    rc = rc ? rc : host_alloc(&L.h_u, P);
+    rc = rc ? rc : host_alloc(&L.h_se, P);
+    rc = rc ? rc : host_alloc(&L.h_coef, P * s->B);
+    rc = rc ? rc : host_alloc(&L.h_nodes, P);
+    rc = rc ? rc : host_alloc(&L.h_flags, P);
+  }
   rc = rc ? rc : dev_alloc(&s->d_partials, P * s->max_segs * s->NB);
   rc = rc ? rc : dev_alloc(&s->d_seg_nodes, P * s->max_segs);
   rc = rc ? rc : dev_alloc(&s->d_u, P);
@@ -439,17 +516,6 @@ int brt_server_create(brt_ctx* ctx, const brt_server_opts* o, brt_server** out) 
   rc = rc ? rc : dev_alloc(&s->d_coef, P * s->B);
   rc = rc ? rc : dev_alloc(&s->d_nodes, P);
   rc = rc ? rc : dev_alloc(&s->d_flags, P);
-  if (!rc && s->spill_depth > 0)
-    rc = dev_alloc(reinterpret_cast<unsigned char**>(&s->d_spill), (size_t)s->grid * s->wpb * kWave *
-                                                                       s->spill_depth * stack_entry_size((int)mc.precision, (int)o->dim));
-  rc = rc ? rc : host_alloc(&s->h_points, P);
-  rc = rc ? rc : host_alloc(&s->h_chunks, P * s->chunks_per_round);
-  rc = rc ? rc : host_alloc(&s->h_segs, P * s->segs_per_round);
-  rc = rc ? rc : host_alloc(&s->h_pdes, kMaxProblems * pde_bytes((int)mc.precision));
-  rc = rc ? rc : host_alloc(&s->h_u, P);
-  rc = rc ? rc : host_alloc(&s->h_se, P);
-  rc = rc ? rc : host_alloc(&s->h_nodes, P);
-  rc = rc ? rc : host_alloc(&s->h_flags, P);
   if (rc) {
     server_free(s);
     return rc;
@@ -545,10 +611,9 @@ int brt_server_drain(brt_server* s, double timeout_s) {
   if (!s) return set_error(BRT_E_ARG, "brt_server_drain: NULL server");
   std::unique_lock<std::mutex> lk(s->mu);
   const auto deadline = Clock::now() + std::chrono::duration<double>(timeout_s);
-  while (!s->queue.empty() || !s->active.empty()) {
+  while (!s->queue.empty() || s->n_active > 0) {
     if (s->engine_rc) return set_error(s->engine_rc, "server stopped: %s", s->engine_msg.c_str());
-    if (s->done_cv.wait_until(lk, deadline) == std::cv_status::timeout &&
-        (!s->queue.empty() || !s->active.empty()))
+    if (s->done_cv.wait_until(lk, deadline) == std::cv_status::timeout && (!s->queue.empty() || s->n_active > 0))
       return set_error(BRT_E_BUSY, "brt_server_drain: timed out");
   }
   return s->engine_rc;

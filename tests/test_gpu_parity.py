@@ -119,6 +119,68 @@ def test_fisher_full_sampled(ctx):
     print(f"[case] fisher_full_sampled: max rel tree diff {worst:.3e}", flush=True)
 
 
+def _subset(wl, pts):
+    """The workload restricted to the given points, keeping their Philox point ids."""
+    pid = wl.get("point_id")
+    pid = np.arange(len(wl["t"]), dtype=np.uint32) if pid is None else np.asarray(pid, np.uint32)
+    return dict(wl, x=np.asarray(wl["x"])[pts], t=np.asarray(wl["t"])[pts], n_trees=np.asarray(wl["n_trees"])[pts],
+                problem_id=np.asarray(wl["problem_id"])[pts], point_id=pid[pts])
+
+
+@pytest.mark.parametrize("prec", [32, 64])
+def test_poly_batch_full_size_sampled(ctx, prec):
+    """The uneven batch at its full size (4096 points of 8 PDEs, 1e4..1e6 trees per point, about 8.8e8
+    trees) in one launch, as the bench runs it: 16 sampled trees at each of 512 sampled points against
+    the oracle tree by tree; and every tree of the 8 points with the fewest trees against the oracle's
+    walk of them, through the moments (exact sums), coefficients and the Pade value (1e-3 unless both
+    sides flag the point)."""
+    import torch
+
+    from paper_2402_06491_amd import Plan
+
+    wl = inputs.poly_batch(precision=prec)
+    _announce(f"poly_batch_full_size_sampled_fp{prec}", wl)
+    tol = P.FP64_TOL if prec == 64 else P.FP32_TOL
+    plan = Plan(ctx, wl["problems"], wl["mc"], wl["x"], wl["t"], wl["n_trees"], problem_id=wl["problem_id"])
+    out = plan.outputs(records=True)
+    plan.execute(out)
+    torch.cuda.synchronize()
+    n_trees = np.asarray(wl["n_trees"], np.int64)
+    base = np.concatenate([[0], np.cumsum(n_trees)])
+    assert np.array_equal(out["hist"].sum(dim=1).cpu().numpy(), n_trees)
+
+    rng = np.random.default_rng(77 + prec)
+    pts = rng.choice(len(n_trees), size=512, replace=False)
+    pi = np.repeat(pts, 16)
+    ti = np.concatenate([rng.integers(0, n_trees[p], 16) for p in pts])
+    rec = torch.as_tensor(base[pi] + ti, device="cuda")
+    g = {"tree_f": out["tree_f"][rec].cpu().numpy(), "tree_meta": out["tree_meta"][rec].cpu().numpy()}
+    orc = P.oracle_trees(wl, pi, ti)
+    worst = P.compare_trees(g, np.arange(len(pi)), orc, tol, pi)
+
+    full = np.sort(np.argsort(n_trees, kind="stable")[:8])
+    sub = _subset(wl, full)
+    rows = torch.as_tensor(full, device="cuda")
+    g2 = {k: out[k][rows].cpu().numpy() for k in ("u", "se", "psum", "coef", "coef_var", "hist", "s1", "s2",
+                                                  "nodes", "flags", "pade_diag")}
+    recs = torch.cat([torch.arange(int(base[p]), int(base[p + 1]), device="cuda") for p in full])
+    g2["tree_f"] = out["tree_f"][recs].cpu().numpy()
+    g2["tree_meta"] = out["tree_meta"][recs].cpu().numpy()
+    plan.close()
+    del out
+    spi, sti, sri = P.tree_items(sub)
+    sorc = P.oracle_trees(sub, spi, sti)
+    P.compare_trees(g2, sri, sorc, tol, spi)
+    omom = P.oracle_moments(sub, sorc, spi)
+    P.compare_moments(sub, g2, omom, tol)
+    P.check_exact_sums(sub, g2, sri, spi)
+    opade = P.oracle_pade(sub, omom)
+    du, strict, n, flagged, near = P.compare_pade(sub, g2, opade, 1e-3)
+    print(f"[case] poly_batch_full_size_sampled_fp{prec}: {len(pi)} sampled trees, max rel diff {worst:.3e}; "
+          f"{int(n_trees[full].sum())} trees of {len(full)} points in full: max |du| {du:.3e} over {strict} "
+          f"unflagged points, {flagged} flagged on both sides, {near} degree choices near the threshold", flush=True)
+
+
 # ---------------------------------------------------------------- edge cases --------------------
 def test_edge_empty_and_ragged_points(ctx):
     wl = inputs.fisher(n_trees=1, n_x=6, times=(0.5,))
