@@ -319,7 +319,7 @@ int brt_autotune(brt_ctx* ctx, uint32_t n_problems, const brt_problem* problems,
  * probabilistic part of Sec. 3: independent points, each summed from independent trees).
  *
  * An engine thread runs ticks; each tick adds one round of `round_trees` trees to every unfinished
- * point of the admitted requests it covers, packing them (64 requests per launch) into shared launches.
+ * point of the admitted requests it covers, packing them (8 requests per launch) into shared launches.
  * Admitted requests are split between two lanes with their own streams: while one lane's tick runs on
  * the device, the engine reads the other lane's results (copied back by its tick), admits requests and
  * enqueues that lane's next tick.  The reduction partials of every round stay on the device in the

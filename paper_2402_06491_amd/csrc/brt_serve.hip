@@ -1,13 +1,14 @@
 // Continuous-batching server for point queries (brt_server_* in include/brt.h).
 //
 // An engine thread runs ticks.  A tick gives every unfinished point of the requests it covers one more
-// round of `round_trees` trees: the rounds of all those requests are packed into as few launches as the
-// problem table allows (64 problems, i.e. requests, per launch), so requests of different sizes and
-// horizons share the GPU.  Each point owns a device slot holding the reduction partials of all its
+// round of `round_trees` trees: the rounds of those requests are packed into launch groups of up to
+// kGroupPoints points and kMaxProblems requests (problems), so requests of different sizes and horizons
+// share launches.  Each point owns a device slot holding the reduction partials of all its
 // rounds; the finalize recomputes the point's coefficients, Pade value and SE from the slot after every
 // round.  A point finishes when its SE reaches the target or its trees reach the cap; a request completes
 // when all its points have finished, and its slots are freed.  New requests are admitted at tick
-// boundaries while free slots remain (memory admission); the submission queue is bounded.
+// boundaries while free slots remain (memory admission); a point's slot is freed as soon as the point
+// finishes and its results are read; the submission queue is bounded.
 //
 // Admitted requests are split between two lanes, each with its own stream, staging and device buffers
 // (the slots and their partials are shared).  The engine alternates: it waits for one lane's tick, reads
@@ -44,6 +45,11 @@ namespace {
 constexpr uint32_t kMaxRequestPoints = 1024;
 constexpr uint32_t kChunkTrees = 1024;
 constexpr int kLanes = 2;
+// Launch groups: consecutive requests of a lane until the group holds kGroupPoints unfinished points or
+// kMaxProblems requests.  The walker keeps the group's problem table in LDS beside its stack levels (at 64
+// problems, 16 KB in FP32, it costs a third of the walker's resident waves), so large requests go in small
+// groups and only small requests share a launch with many others.
+constexpr uint32_t kGroupPoints = 4096;
 constexpr uint32_t kCounterStride = 16;  // 64 bytes between the chunk counters of a lane's launch groups
 
 struct Request {
@@ -67,7 +73,7 @@ struct Request {
 struct Lane {
   hipStream_t stream = nullptr;
   hipEvent_t ev_start = nullptr, ev_done = nullptr;
-  void* d_pdes = nullptr;                 // [max_groups][kMaxProblems] problem tables
+  void* d_pdes = nullptr;                 // problem tables of the tick's launch groups, back to back
   PointRec* d_points = nullptr;           // [max_points]
   Chunk* d_chunks = nullptr;              // [max_points * chunks_per_round]
   Segment* d_segs = nullptr;              // [max_points * segs_per_round]
@@ -97,6 +103,7 @@ struct brt_server {
   brt_server_opts opts{};
   uint32_t B = 0, NB = 0, segs_per_round = 0, max_segs = 0, chunks_per_round = 0, max_groups = 0;
   int grid = 0, wpb = 4, lds_depth = 0, spill_depth = 0;
+  int grid_k[kMaxProblems + 1] = {};  // resident walker blocks for a launch group of k problems
   Lane lanes[kLanes];
   // per-slot device state shared by the lanes (each slot belongs to one point of one lane at a time)
   Partial* d_partials = nullptr;
@@ -169,7 +176,7 @@ int host_alloc(T** p, size_t n) {
 }
 
 // Enqueue one tick of a lane on its stream: one round for every unfinished point of the lane's requests,
-// in launch groups of up to kMaxProblems requests, then the copies of every slot's results back to the
+// in launch groups (kGroupPoints, kMaxProblems), then the copies of every slot's results back to the
 // lane's pinned buffers and the completion event.  Nothing here waits for the device.
 int issue_tick(brt_server* s, Lane& L) {
   const brt_mc& mc = s->opts.mc;
@@ -184,12 +191,16 @@ int issue_tick(brt_server* s, Lane& L) {
   uint32_t np = 0, nc = 0, ns = 0, slot_lo = ~0u, slot_hi = 0;
   L.inflight = L.reqs;
   SRV_TRY(hipEventRecord(L.ev_start, L.stream));
-  for (size_t g0 = 0, grp = 0; g0 < L.reqs.size(); g0 += kMaxProblems, ++grp) {
-    const size_t g1 = std::min(L.reqs.size(), g0 + (size_t)kMaxProblems);
+  for (size_t g0 = 0, grp = 0, prob_off = 0; g0 < L.reqs.size(); ++grp) {
+    size_t g1 = g0;
+    for (uint32_t pts = 0; g1 < L.reqs.size() && g1 - g0 < (size_t)kMaxProblems && pts < kGroupPoints; ++g1)
+      pts += L.reqs[g1]->n - L.reqs[g1]->n_done;
+    const size_t gprob = prob_off, kprob = g1 - g0;
+    prob_off += kprob;
     // the group's points, most expensive first (longest-processing-time order of the chunks)
     items.clear();
     uint32_t cmod = 0;
-    unsigned char* pdes = L.h_pdes + grp * kMaxProblems * pb;
+    unsigned char* pdes = L.h_pdes + gprob * pb;
     for (size_t k = g0; k < g1; ++k) {
       Request* r = L.reqs[k];
       pde_to_device(r->prob, r->norm, (int)mc.precision, pdes + (k - g0) * pb);
@@ -228,9 +239,10 @@ int issue_tick(brt_server* s, Lane& L) {
     // chunks interleaved in cost order: all points' first chunks, then their second chunks, ...
     for (uint32_t c = 0; c < s->chunks_per_round; ++c)
       for (uint32_t p = p0; p < np; ++p) L.h_chunks[nc++] = Chunk{p, c * kChunkTrees, (c + 1) * kChunkTrees, 0u};
+    g0 = g1;  // the next group starts after this one
     if (np == p0) continue;
-    void* d_pdes = static_cast<unsigned char*>(L.d_pdes) + grp * kMaxProblems * pb;
-    SRV_TRY(hipMemcpyAsync(d_pdes, pdes, (g1 - g0) * pb, hipMemcpyHostToDevice, L.stream));
+    void* d_pdes = static_cast<unsigned char*>(L.d_pdes) + gprob * pb;
+    SRV_TRY(hipMemcpyAsync(d_pdes, pdes, kprob * pb, hipMemcpyHostToDevice, L.stream));
     SRV_TRY(hipMemcpyAsync(L.d_points + p0, L.h_points + p0, (np - p0) * sizeof(PointRec), hipMemcpyHostToDevice,
                            L.stream));
     SRV_TRY(hipMemcpyAsync(L.d_chunks + c0, L.h_chunks + c0, (nc - c0) * sizeof(Chunk), hipMemcpyHostToDevice, L.stream));
@@ -242,7 +254,7 @@ int issue_tick(brt_server* s, Lane& L) {
     w.points = L.d_points;
     w.chunks = L.d_chunks + c0;
     w.n_chunks = nc - c0;
-    w.n_problems = (uint32_t)(g1 - g0);
+    w.n_problems = (uint32_t)kprob;
     w.pdes = d_pdes;
     w.chunk_counter = counter;
     w.depth_counter = depth;
@@ -258,8 +270,8 @@ int issue_tick(brt_server* s, Lane& L) {
     w.cmod = cmod;
     w.stack_depth = (uint32_t)s->lds_depth;
     w.spill_depth = (uint32_t)s->spill_depth;
-    w.n_threads = (uint32_t)(s->grid * s->wpb * kWave);
-    const int grid = std::max(1, std::min<int>(s->grid, (int)(nc - c0)));
+    w.n_threads = (uint32_t)(s->grid * s->wpb * kWave);  // the spill area's stride (sized for the largest grid)
+    const int grid = std::max(1, std::min<int>(s->grid_k[kprob], (int)(nc - c0)));
     SRV_TRY(launch_walk((int)mc.precision, (int)s->opts.dim, (int)s->opts.u0_kind, w, grid, s->wpb, L.stream));
     ReduceArgs ra{};
     ra.points = L.d_points;
@@ -334,12 +346,12 @@ int finish_tick(brt_server* s, Lane& L) {
         r->flags[i] = L.h_flags[slot];
         s->nodes += L.h_nodes[slot];
         std::memcpy(r->coef.data() + (size_t)i * s->B, L.h_coef + (size_t)slot * s->B, s->B * sizeof(double));
+        s->free_slots.push_back(slot);  // the point's results are on the host: its slot takes the next point
       }
     }
     if (r->n_done == r->n) {
       r->complete = true;
       r->finished_at = now;
-      for (uint32_t i = 0; i < r->n; ++i) s->free_slots.push_back(r->slot[i]);
       s->latencies.push_back(std::chrono::duration<double>(now - r->arrival).count());
       s->completed += 1;
       s->n_active -= 1;
@@ -466,22 +478,27 @@ int brt_server_create(brt_ctx* ctx, const brt_server_opts* o, brt_server** out) 
   const uint32_t needed = mc.prune ? std::max(1u, mc.max_order) : kMaxDepthUnpruned;
   s->lds_depth = (int)std::min(needed, lc.stack_depth ? lc.stack_depth : kDefaultLdsLevels);
   s->spill_depth = (int)(needed - (uint32_t)s->lds_depth);
-  int maxb = walk_max_blocks_per_cu((int)mc.precision, (int)o->dim, (int)o->u0_kind, kMaxProblems, s->lds_depth, s->wpb,
-                                 (int)mc.strategy);
-  while (maxb <= 0 && s->wpb > 1) {
-    s->wpb -= 1;
-    maxb = walk_max_blocks_per_cu((int)mc.precision, (int)o->dim, (int)o->u0_kind, kMaxProblems, s->lds_depth, s->wpb,
-                                 (int)mc.strategy);
+  // resident blocks per CU for every launch-group size (its problem table shares the block's LDS); a
+  // block size that does not fit one problem's table is reduced
+  for (int k = 1; k <= kMaxProblems; ++k) {
+    int maxb = walk_max_blocks_per_cu((int)mc.precision, (int)o->dim, (int)o->u0_kind, k, s->lds_depth, s->wpb,
+                                      (int)mc.strategy);
+    while (k == 1 && maxb <= 0 && s->wpb > 1) {
+      s->wpb -= 1;
+      maxb = walk_max_blocks_per_cu((int)mc.precision, (int)o->dim, (int)o->u0_kind, k, s->lds_depth, s->wpb,
+                                    (int)mc.strategy);
+    }
+    if (maxb <= 0) {
+      server_free(s);
+      return set_error(BRT_E_ARG, "server: walker launch for %d problems does not fit the device", k);
+    }
+    s->grid_k[k] = maxb * s->n_cu;
   }
-  if (maxb <= 0) {
-    server_free(s);
-    return set_error(BRT_E_ARG, "server: walker launch does not fit the device");
-  }
-  s->grid = maxb * s->n_cu;
+  s->grid = *std::max_element(s->grid_k + 1, s->grid_k + kMaxProblems + 1);  // sizes the stack spill area
   const size_t P = o->max_points;
   const size_t R = o->round_trees;
   int rc = BRT_OK;
-  s->max_groups = (uint32_t)((P + kMaxProblems - 1) / kMaxProblems);  // requests of one point each, 64 per launch
+  s->max_groups = (uint32_t)P;  // at most one group per request
   const size_t pb = pde_bytes((int)mc.precision);
   const size_t spill = s->spill_depth > 0 ? (size_t)s->grid * s->wpb * kWave * s->spill_depth *
                                                 stack_entry_size((int)mc.precision, (int)o->dim)
@@ -490,7 +507,7 @@ int brt_server_create(brt_ctx* ctx, const brt_server_opts* o, brt_server** out) 
     rc = rc ? rc : (hipStreamCreate(&L.stream) == hipSuccess ? BRT_OK : set_error(BRT_E_DEVICE, "server: stream"));
     rc = rc ? rc : (hipEventCreate(&L.ev_start) == hipSuccess ? BRT_OK : set_error(BRT_E_DEVICE, "server: event"));
     rc = rc ? rc : (hipEventCreate(&L.ev_done) == hipSuccess ? BRT_OK : set_error(BRT_E_DEVICE, "server: event"));
-    rc = rc ? rc : dev_alloc(reinterpret_cast<unsigned char**>(&L.d_pdes), s->max_groups * kMaxProblems * pb);
+    rc = rc ? rc : dev_alloc(reinterpret_cast<unsigned char**>(&L.d_pdes), P * pb);  // one problem per request
     rc = rc ? rc : dev_alloc(&L.d_points, P);
     rc = rc ? rc : dev_alloc(&L.d_chunks, P * s->chunks_per_round);
     rc = rc ? rc : dev_alloc(&L.d_segs, P * s->segs_per_round);
@@ -502,7 +519,7 @@ int brt_server_create(brt_ctx* ctx, const brt_server_opts* o, brt_server** out) 
     rc = rc ? rc : host_alloc(&L.h_points, P);
     rc = rc ? rc : host_alloc(&L.h_chunks, P * s->chunks_per_round);
     rc = rc ? rc : host_alloc(&L.h_segs, P * s->segs_per_round);
-    rc = rc ? rc : host_alloc(&L.h_pdes, s->max_groups * kMaxProblems * pb);
+    rc = rc ? rc : host_alloc(&L.h_pdes, P * pb);
     rc = rc ? rc : host_alloc(&L.h_u, P);
     rc = rc ? rc : host_alloc(&L.h_se, P);
     rc = rc ? rc : host_alloc(&L.h_coef, P * s->B);

@@ -216,6 +216,19 @@ def test_tail_full_size_first_steps(ctx):
     _tail_parity(ctx, "tail_full_size_100_steps", wl["problem"], grid, vals, steps=100, groups=16)
 
 
+def test_tail_full_step_count(ctx):
+    """The workload's full step count (1000 steps to t = 1, boundary data at 8 node times on lines of 33
+    nodes, outer edges from Monte Carlo nodes) on 2 x 2 subdomains of 128^2 cells over [-8, 8]^2: the
+    field after every one of the 1000 steps' accumulation against the oracle's solve."""
+    prob = _cubic(0)
+    grid = _grid(x_lo=-8.0, x_hi=8.0, y_lo=-8.0, y_hi=8.0, px=2, py=2, cx=128, cy=128, T=1.0, n_steps=1000,
+                 ns_x=33, ns_y=33, nt=8)
+    og = opdd.Grid(**grid)
+    xy, t = opdd.node_points(og)
+    vals = opdd.g_grid(prob, xy[:, 0], xy[:, 1]) * np.exp(-0.3 * t)
+    _tail_parity(ctx, "tail_full_step_count_2x2x128", prob, grid, vals)
+
+
 def test_pdd_end_to_end_against_oracle_monte_carlo(ctx):
     """Monte Carlo at the nodes (FP64 paths) then the tail, against the oracle's own Monte Carlo values
     fed to the oracle's tail.  The node values agree to the Pade parity bound; the fields then agree to
