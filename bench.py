@@ -333,7 +333,7 @@ def walker_source_sha():
 
 
 def adi_source_sha():
-    return source_sha(("brt_pdd.hip", "brt_internal.h"))
+    return source_sha(("brt_pdd.hip",))  # the ADI kernel and its launch live in this file alone
 
 
 COPY_BYTES = 512 << 20  # the plain device copy of --pmc-calibration

@@ -97,6 +97,7 @@ struct HotC {
   Real cm_bx, cm_by, cm_t0, drift0, drift1;
   Real dlin0, dlin1, sig_amp, sig_k, inv_h;  // a general L (Euler-Maruyama edges)
   Real g[6];  // first initial-data parameters (the logistic family's A, s, x0, p, n0, n1)
+  Real omega0;  // the first term's vertex weight (the only one when K == 1)
 };
 
 template <typename Real>
@@ -125,6 +126,7 @@ __device__ __forceinline__ HotC<Real> hot_of(const PdeT<Real>& pd) {
   h.sig_k = pd.sig_k;
   h.inv_h = pd.inv_h;
   for (int i = 0; i < 6; ++i) h.g[i] = pd.u0[i];
+  h.omega0 = pd.omega[0];
   return h;
 }
 
@@ -438,7 +440,12 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
       if (!more) break;
       continue;
     }
-    if (!active) continue;
+    // Lanes without a tree step along on their stale state (no memory effects: push, pop and record
+    // are guarded), which keeps the node step free of a divergent exit; the variants with general
+    // coefficients skip them, as their Euler edges take a data-dependent number of steps.
+    if constexpr (CMOD) {
+      if (!active) continue;
+    }
 
     const PdeT<Real>& pd = pdes[MULTI ? pde_lane : 0u];  // per-arity weights and the other data families
     const HotC<Real> hc = MULTI ? hot_of(pd) : h0;
@@ -516,12 +523,18 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
     // Strategy B's vertex weight carries the time left tau (eta(t) = t) and its leaves divide by q
     const Real wscale = (STRAT == 1 ? tau : (Real)1) * cscale;
     const Real lscale = STRAT == 1 ? hc.inv_q : (Real)1;
+    // the chosen term's weight: with one problem of one non-linear term a loop invariant, else the table's
+    Real om;
+    if (!MULTI && hc.K == 1)
+      om = hc.omega0;
+    else
+      om = pd.omega[idx];
     Real factor;
     if constexpr (U0 == 1) {
-      factor = vertex ? wscale * pd.omega[idx] * E : lscale * logistic_finish<Real>(hc.g, E);
+      factor = vertex ? wscale * om * E : lscale * logistic_finish<Real>(hc.g, E);
     } else {
       if (vertex)
-        factor = wscale * pd.omega[idx] * E;
+        factor = wscale * om * E;
       else
         factor = lscale * eval_g<Real, DIM, U0>(pd, xn);
     }
@@ -533,7 +546,7 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
     node += capped ? 0u : 1u;
     F *= (double)factor;
     bool done = capped || ovf;
-    if (vok && alpha >= 2) {
+    if (active && vok && alpha >= 2) {
       if (sp == max_depth) {
         flags |= kMetaDepth;
         done = true;
@@ -547,7 +560,7 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
     if constexpr (DIM == 2) x[1] = cont ? xn[1] : x[1];
     P = cont ? Pn : P;
     tau = cont ? tau2 : tau;
-    const bool branch_end = !done && !cont;  // a leaf, or a vertex without children
+    const bool branch_end = active && !done && !cont;  // a leaf, or a vertex without children
     if (branch_end) {
       if (sp == 0) {
         done = true;
@@ -562,7 +575,7 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
         }
       }
     }
-    if (done) {
+    if (active && done) {
       a.tree_f[rec] = flags ? 0.0 : F;
       a.tree_meta[rec] = (ne < 255u ? ne : 255u) | flags | (node << kMetaNodesShift);
       if (flags & kMetaDepth) atomicAdd(a.depth_counter, 1ull);
