@@ -48,6 +48,30 @@ __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c
   return U4{c0, c1, c2, c3};
 }
 
+// The same block for a counter (c0, c1, c2, 0) whose first round's product of c2 is given with its xor:
+// h1 = hi(M1 c2) ^ c1 ^ k0 and l1 = lo(M1 c2).  The walker's counters (node, tree, point id, 0) keep
+// (tree, point id) through a whole tree, so that half of the first round is done once per tree.
+__device__ __forceinline__ U4 philox4x32_10_tree(uint32_t c0, uint32_t h1, uint32_t l1, uint32_t k0, uint32_t k1) {
+  const uint64_t q = (uint64_t)0xD2511F53u * (uint64_t)c0;
+  uint32_t a0 = h1, a1 = l1, a2 = (uint32_t)(q >> 32) ^ k1, a3 = (uint32_t)q;
+  k0 += 0x9E3779B9u;
+  k1 += 0xBB67AE85u;
+#pragma unroll
+  for (int r = 1; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)a0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)a2;
+    const uint32_t n0 = xor3((uint32_t)(p1 >> 32), a1, k0);
+    const uint32_t n2 = xor3((uint32_t)(p0 >> 32), a3, k1);
+    a1 = (uint32_t)p1;
+    a3 = (uint32_t)p0;
+    a0 = n0;
+    a2 = n2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return U4{a0, a1, a2, a3};
+}
+
 // ------------------------------------------------------------------------------------------------
 // Precision-dependent elementary functions.
 // FP32: hardware log2/exp2/sqrt/sin/cos/rcp (v_log_f32, v_exp_f32, v_sqrt_f32, v_sin_f32, v_cos_f32,
@@ -367,7 +391,7 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
   // the current one is requested as soon as the current one starts.
   uint32_t c_next = 0, c_end = 0;
   bool more = true;
-  uint32_t c_pid = 0, c_pde = 0, c_tfirst = 0;
+  uint32_t c_pid = 0, c_pde = 0, c_tfirst = 0, c_ph = 0, c_pl = 0;
   uint64_t c_base = 0;
   double c_theta = 1.0;
   Real c_t = 0, c_x0 = 0, c_x1 = 0;
@@ -377,6 +401,7 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
   // per-lane tree state
   bool active = false;
   uint32_t tree = 0, node = 0, ne = 0, flags = 0, sp = 0, pid = 0, pde_lane = 0;
+  uint32_t ph = 0, pl = 0;  // the tree's share of the first Philox round (philox4x32_10_tree)
   uint64_t rec = 0;
   double P = 1.0, theta = 1.0;
   double F = 1.0;  // running product of the tree's factors (FP64 for range: weights reach e^{32} per vertex)
@@ -401,6 +426,9 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
           const uint32_t point = __builtin_amdgcn_readfirstlane(ch.point);
           const PointRec& pr = a.points[point];
           c_pid = pr.point_id;
+          const uint64_t pq = (uint64_t)0xCD9E8D57u * (uint64_t)c_pid;  // the first Philox round's point part
+          c_ph = (uint32_t)(pq >> 32) ^ a.key0;
+          c_pl = (uint32_t)pq;
           c_pde = pr.pde;
           c_tfirst = pr.tree_first;
           c_base = pr.tree_base;
@@ -418,6 +446,8 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
         if (!active && rank < take) {
           tree = c_tfirst + c_next + rank;
           pid = c_pid;
+          ph = c_ph ^ tree;
+          pl = c_pl;
           pde_lane = c_pde;
           rec = c_base + c_next + rank;
           theta = c_theta;
@@ -454,7 +484,7 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
     // Vertex and leaf quantities are computed for every lane and chosen with selects; only the stack
     // push, the stack pop and the record write are divergent.
     const bool capped = node >= node_cap;
-    const U4 w = philox4x32_10(node, tree, pid, 0u, a.key0, a.key1);
+    const U4 w = philox4x32_10_tree(node, ph, pl, a.key0, a.key1);
     double Pn = P;
     bool vertex;
     Real S;     // time from the node's start to its split
@@ -523,18 +553,20 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
     // Strategy B's vertex weight carries the time left tau (eta(t) = t) and its leaves divide by q
     const Real wscale = (STRAT == 1 ? tau : (Real)1) * cscale;
     const Real lscale = STRAT == 1 ? hc.inv_q : (Real)1;
-    // the chosen term's weight: with one problem of one non-linear term a loop invariant, else the table's
-    Real om;
-    if (!MULTI && hc.K == 1)
-      om = hc.omega0;
-    else
-      om = pd.omega[idx];
+    // the chosen term's weight from the table; with logistic initial data, one problem and one non-linear
+    // term it is a loop invariant (the other families keep the table read: there the branch around it
+    // costs the walker registers)
     Real factor;
     if constexpr (U0 == 1) {
+      Real om;
+      if (!MULTI && hc.K == 1)
+        om = hc.omega0;
+      else
+        om = pd.omega[idx];
       factor = vertex ? wscale * om * E : lscale * logistic_finish<Real>(hc.g, E);
     } else {
       if (vertex)
-        factor = wscale * om * E;
+        factor = wscale * pd.omega[idx] * E;
       else
         factor = lscale * eval_g<Real, DIM, U0>(pd, xn);
     }
