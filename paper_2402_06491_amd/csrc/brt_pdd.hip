@@ -304,10 +304,10 @@ __device__ inline uint32_t xcc_id() {
 // Fences.  With die_local set, every block of the group runs on one die, and all that the group's
 // blocks read after a barrier was written by the group itself: the die's L2 is then the coherence
 // point, so each wave waits until its stores are in L2 and the arriving side needs no L2 write-back.
-// The leaving side must still drop the CU's vector L1, which may hold lines this CU read before the
-// barrier and other CUs have rewritten since: the device-scope invalidate does that (and leaves the
-// L2's lines of device memory in place); the workgroup-scope form does not clear it.  Otherwise
-// device-scope fences (L2 write-back and invalidation) order the phases.
+// The CU's vector L1 may hold lines this CU read before the barrier and other CUs have rewritten
+// since; the sweeps read every such field value with L1-bypassing loads (ldg2_c), so the leaving side
+// needs no invalidate either.  Otherwise device-scope fences (L2 write-back and invalidation) order
+// the phases.
 __device__ bool group_barrier(uint32_t* cnt, uint32_t* abort_word, uint32_t members, uint32_t& gen, uint64_t spin_limit,
                               bool die_local, uint32_t* flag) {
   if (die_local) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -330,10 +330,7 @@ __device__ bool group_barrier(uint32_t* cnt, uint32_t* abort_word, uint32_t memb
         __builtin_amdgcn_s_sleep(2);
       }
     }
-    if (die_local)
-      asm volatile("buffer_inv sc1\n\ts_waitcnt vmcnt(0)" ::: "memory");
-    else
-      __threadfence();
+    if (!die_local) __threadfence();
     gen += 1;
     *flag = ok;
   }
@@ -414,6 +411,21 @@ __device__ inline dpair ldg2(const double* base, uint32_t byte_off) {
 }
 __device__ inline void stg2(double* base, uint32_t byte_off, dpair v) {
   *reinterpret_cast<dpair*>(reinterpret_cast<char*>(base) + byte_off) = v;
+}
+// A pair of field values that other blocks of the group wrote since the last barrier, loaded past the
+// CU's vector L1 (agent-scope coherent loads), so that leaving a die-local barrier needs no L1
+// invalidate: the L1 may keep lines of the read-only data (boundary data, coefficient factors).
+__device__ inline dpair ldg2_c(const double* base, uint32_t byte_off) {
+  const unsigned long long* q =
+      reinterpret_cast<const unsigned long long*>(reinterpret_cast<const char*>(base) + byte_off);
+  const unsigned long long lo = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const unsigned long long hi = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return dpair{__longlong_as_double((long long)lo), __longlong_as_double((long long)hi)};
+}
+__device__ inline double ldg_c(const double* base, uint32_t byte_off) {
+  const unsigned long long* q =
+      reinterpret_cast<const unsigned long long*>(reinterpret_cast<const char*>(base) + byte_off);
+  return __longlong_as_double((long long)__hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
 }
 
 // Keeps the scheduler from hoisting the loads of a later batch above this point.
@@ -558,14 +570,14 @@ __device__ void x_sweep(const AdiArgs& a, uint32_t item, uint32_t n, const doubl
   } else {
     const uint32_t vo = 8 * pa;
     const dpair exv = ldg2(a.ex + c0 + 1, vo);
-    dpair up = ldg2(cur_row(min(r0, nrows + 1)), vo), mid = ldg2(cur_row(min(r0 + 1, nrows + 1)), vo);
+    dpair up = ldg2_c(cur_row(min(r0, nrows + 1)), vo), mid = ldg2_c(cur_row(min(r0 + 1, nrows + 1)), vo);
 #pragma unroll
     for (uint32_t k0 = 0; k0 < R; k0 += kXBatch) {
       dpair cv[kXBatch], pv[kXBatch];
 #pragma unroll
       for (int k = 0; k < kXBatch; ++k) {
-        cv[k] = ldg2(cur_row(min(r0 + k0 + k + 2, nrows + 1)), vo);
-        pv[k] = ldg2(prev_b + (size_t)min(r0 + k0 + k, nrows - 1) * W, vo);
+        cv[k] = ldg2_c(cur_row(min(r0 + k0 + k + 2, nrows + 1)), vo);
+        pv[k] = ldg2_c(prev_b + (size_t)min(r0 + k0 + k, nrows - 1) * W, vo);
       }
 #pragma unroll
       for (int k = 0; k < kXBatch; ++k) {
@@ -601,8 +613,8 @@ __device__ void x_sweep(const AdiArgs& a, uint32_t item, uint32_t n, const doubl
     dpair fv[R];
 #pragma unroll
     for (uint32_t k = 0; k < R; ++k)
-      fv[k] = r0 + k < nrows ? (pb < m ? ldg2(yr_b + (size_t)(r0 + k) * W, 8 * pa)
-                                       : dpair{ldg(yr_b + (size_t)(r0 + k) * W, 8 * pa), 0.0})
+      fv[k] = r0 + k < nrows ? (pb < m ? ldg2_c(yr_b + (size_t)(r0 + k) * W, 8 * pa)
+                                       : dpair{ldg_c(yr_b + (size_t)(r0 + k) * W, 8 * pa), 0.0})
                              : dpair{0.0, 0.0};
 #pragma unroll
     for (uint32_t k = 0; k < R; ++k) {
@@ -656,7 +668,7 @@ __device__ void y_sweep(const AdiArgs& a, uint32_t item, uint32_t n, double* __r
 #pragma unroll
     for (int k = 0; k < kYBatch; ++k) {
       const uint32_t p = min(q + G * (kb + k), m - 1);
-      rv[k] = ldg2(yr_b, 8 * ((1 + p) * W + x));
+      rv[k] = ldg2_c(yr_b, 8 * ((1 + p) * W + x));
     }
 #pragma unroll
     for (int k = 0; k < kYBatch; ++k) {
