@@ -258,7 +258,9 @@ constexpr double kPadeTol = 1e-12;
 constexpr double kPoleDist = 0.5;
 constexpr double kSensitive = 100.0;
 constexpr int kWindingSamples = 32;  // samples of the pole-test contour per lane (2048 per point)
-constexpr int kJoinGroup = 16;       // bins joined per pass of the finalize
+constexpr int kJoinGroup = 16;       // bins joined per pass of the finalize (its LDS columns bound the blocks per CU)
+constexpr int kJoinBatch = 16;       // a segment's bins loaded per batch
+static_assert(2 * kJoinGroup <= kWave, "one lane rounds each column of a pass");
 constexpr int kAccStride = kAccWords + 1;  // LDS column of one exact sum (padded against bank conflicts)
 
 __host__ __device__ __forceinline__ double coef_at(const double* a, int k) { return k >= 0 ? a[k] : 0.0; }
@@ -722,24 +724,27 @@ __global__ __launch_bounds__(64) void finalize_kernel(FinalizeArgs a) {
   unsigned long long extra[3] = {0, 0, 0};
   for (uint32_t g0 = 0; g0 < B; g0 += kJoinGroup) {
     const uint32_t nb = B - g0 < (uint32_t)kJoinGroup ? B - g0 : (uint32_t)kJoinGroup;
-    for (uint32_t i = lane; i < 2 * kJoinGroup * kAccStride; i += kWave) wacc[i] = 0ull;
+    for (uint32_t i = lane; i < 2 * nb * kAccStride; i += kWave) wacc[i] = 0ull;
     if (lane < kJoinGroup + 3) cnt[lane] = 0ull;
     if (lane < 2 * kJoinGroup) special[lane] = 0u;
     __syncthreads();
     for (uint32_t sg = lane; sg < pr.seg_count; sg += kWave) {
       const Partial* prow = parts + (size_t)sg * NB + g0;
-      Partial v[kJoinGroup];
+      for (uint32_t b0 = 0; b0 < nb; b0 += kJoinBatch) {
+        Partial v[kJoinBatch];
 #pragma unroll
-      for (int b = 0; b < kJoinGroup; ++b)
-        v[b] = (uint32_t)b < nb ? prow[b] : Partial{0, 0.0, 0.0, 0.0};
+        for (int k = 0; k < kJoinBatch; ++k)
+          v[k] = b0 + k < nb ? prow[b0 + k] : Partial{0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int b = 0; b < kJoinGroup; ++b) {
-        if ((uint32_t)b >= nb) continue;
-        if (v[b].count) atomicAdd(&cnt[b], (unsigned long long)v[b].count);
-        unsigned long long* c1 = wacc + (2 * b) * kAccStride;
-        lds_add_exact(c1, &special[2 * b], v[b].s1_hi);
-        lds_add_exact(c1, &special[2 * b], v[b].s1_lo);
-        lds_add_exact(c1 + kAccStride, &special[2 * b + 1], v[b].s2);
+        for (int k = 0; k < kJoinBatch; ++k) {
+          const uint32_t b = b0 + k;
+          if (b >= nb) continue;
+          if (v[k].count) atomicAdd(&cnt[b], (unsigned long long)v[k].count);
+          unsigned long long* c1 = wacc + (2 * b) * kAccStride;
+          lds_add_exact(c1, &special[2 * b], v[k].s1_hi);
+          lds_add_exact(c1, &special[2 * b], v[k].s1_lo);
+          lds_add_exact(c1 + kAccStride, &special[2 * b + 1], v[k].s2);
+        }
       }
       if (g0 == 0) {
         const Partial* ext = parts + (size_t)sg * NB + B;
