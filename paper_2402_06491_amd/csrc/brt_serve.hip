@@ -6,7 +6,7 @@
 // share launches.  Each point owns a device slot holding the reduction partials of all its
 // rounds; the finalize recomputes the point's coefficients, Pade value and SE from the slot after every
 // round.  A point finishes when its SE reaches the target or its trees reach the cap; a request completes
-// when all its points have finished, and its slots are freed.  New requests are admitted at tick
+// when all its points have finished.  New requests are admitted at tick
 // boundaries while free slots remain (memory admission); a point's slot is freed as soon as the point
 // finishes and its results are read; the submission queue is bounded.
 //
