@@ -272,6 +272,16 @@ __host__ __device__ constexpr size_t pde_table_bytes(int n) {
 // ------------------------------------------------------------------------------------------------
 #define BRT_LDS __attribute__((address_space(3)))
 
+// Wave-uniform copies (scalar registers) of values loaded from a wave-uniform address.
+__device__ __forceinline__ uint32_t rfl_u32(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t rfl_u64(uint64_t v) {
+  return ((uint64_t)rfl_u32((uint32_t)(v >> 32)) << 32) | rfl_u32((uint32_t)v);
+}
+__device__ __forceinline__ double rfl_f64(double v) { return __builtin_bit_cast(double, rfl_u64(__builtin_bit_cast(uint64_t, v))); }
+// An empty statement that reads a register: the compiler completes the load that wrote it first.
+__device__ __forceinline__ void consume(double v) { asm volatile("" ::"v"(v)); }
+__device__ __forceinline__ void consume(float v) { asm volatile("" ::"v"(v)); }
+
 template <typename Real, int DIM, int STRAT>
 struct Stack {
   // LDS pointers carry their address space so that the compiler keeps ds_* instructions for them
@@ -326,6 +336,13 @@ struct Stack {
       if constexpr (DIM == 2) x[1] = gX[spill_depth + o];
       rem = (uint32_t)gR[o] - 1u;
       gR[o] = (uint8_t)rem;
+      // Consume the loaded values in this (rare) branch: the wait for them is then placed here, and
+      // the common path, where the merged values are used, waits on no memory counter (which on this
+      // architecture also counts the record stores).
+      if constexpr (STRAT == 0) consume(*p);
+      else consume(*t);
+      consume(x[0]);
+      if constexpr (DIM == 2) consume(x[1]);
     }
     return rem;
   }
@@ -424,18 +441,21 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
           c_next = __builtin_amdgcn_readfirstlane(ch.begin);
           c_end = __builtin_amdgcn_readfirstlane(ch.end);
           const uint32_t point = __builtin_amdgcn_readfirstlane(ch.point);
+          // The point's constants are made wave-uniform here, so that the loads complete at the chunk
+          // switch: a load still pending in a vector register would make later code wait on the
+          // counter that also counts the record stores (vmcnt), in every node step.
           const PointRec& pr = a.points[point];
-          c_pid = pr.point_id;
+          c_pid = rfl_u32(pr.point_id);
           const uint64_t pq = (uint64_t)0xCD9E8D57u * (uint64_t)c_pid;  // the first Philox round's point part
           c_ph = (uint32_t)(pq >> 32) ^ a.key0;
           c_pl = (uint32_t)pq;
-          c_pde = pr.pde;
-          c_tfirst = pr.tree_first;
-          c_base = pr.tree_base;
-          c_theta = pr.theta;
-          c_t = (Real)pr.t;
-          c_x0 = (Real)pr.x[0];
-          c_x1 = (Real)pr.x[1];
+          c_pde = rfl_u32(pr.pde);
+          c_tfirst = rfl_u32(pr.tree_first);
+          c_base = rfl_u64(pr.tree_base);
+          c_theta = rfl_f64(pr.theta);
+          c_t = (Real)rfl_f64(pr.t);
+          c_x0 = (Real)rfl_f64(pr.x[0]);
+          c_x1 = (Real)rfl_f64(pr.x[1]);
         }
       }
       if (more) {
