@@ -206,11 +206,6 @@ __device__ __forceinline__ Real eval_g(const PdeT<Real>& pd, const Real* x) {
   }
 }
 
-__device__ __forceinline__ uint64_t lanemask_lt() {
-  const uint32_t lane = __lane_id();
-  return (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-}
-
 // One edge of a general L = sigma(x)^2/2 Lap + b(x) . grad (Sec. 2.1's SDE, the Euler scheme of Sec. 2.4):
 // n = ceil(dt / h) (at most kMaxEulerSteps) equal Euler-Maruyama steps, which end at the edge's end (its branching time), with
 // b(x) = drift + dlin x and sigma(x) = sigma (1 + sig_amp e^{-sig_k |x|^2}).  Step 0 uses the node's own
@@ -396,7 +391,6 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
   }
   const uint32_t max_depth = a.stack_depth + a.spill_depth;
 
-  const uint64_t lt = lanemask_lt();
   // one problem: its constants loaded once (uniform, scalar registers)
   const HotC<Real> h0 = hot_of(*reinterpret_cast<const PdeT<Real>*>(a.pdes));
   const uint32_t node_cap = a.node_cap;
@@ -416,7 +410,11 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
   if (lane == 0) next_raw = atomicAdd(a.chunk_counter, 1u);
 
   // per-lane tree state
-  bool active = false;
+  uint64_t amask = 0;  // lanes that hold a tree
+  // The variants with general coefficients leave the node step early on lanes without a tree (a
+  // divergent continue), after which the lanes' copies of a carried mask would differ: they rebuild
+  // the mask from this per-lane flag at the top of every step instead, where all lanes have met.
+  bool live = false;
   uint32_t tree = 0, node = 0, ne = 0, flags = 0, sp = 0, pid = 0, pde_lane = 0;
   uint32_t ph = 0, pl = 0;  // the tree's share of the first Philox round (philox4x32_10_tree)
   uint64_t rec = 0;
@@ -428,8 +426,11 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
 
   while (true) {
     // ---- refill: idle lanes take trees from the wave's chunk; at most one chunk switch per
-    // iteration (lanes left without a tree at a chunk boundary wait one node step) ----
-    const uint64_t need = __ballot(!active);
+    // iteration (lanes left without a tree at a chunk boundary wait one node step).  Which lanes hold
+    // a tree is the wave-uniform mask `amask` (scalar registers); a lane reads its bit through
+    // inverse_ballot. ----
+    if constexpr (CMOD) amask = __ballot(live);
+    const uint64_t need = ~amask;
     if (need != 0 && more) {
       if (c_next == c_end) {
         const uint32_t ci = __builtin_amdgcn_readfirstlane(next_raw);
@@ -462,8 +463,10 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
         const uint32_t avail = c_end - c_next;
         const uint32_t cnt = (uint32_t)__popcll(need);
         const uint32_t take = cnt < avail ? cnt : avail;
-        const uint32_t rank = (uint32_t)__popcll(need & lt);
-        if (!active && rank < take) {
+        // the lane's rank among the idle lanes; the `take` lowest idle lanes get the next trees
+        const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(need >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
+        const uint64_t got = need & __ballot(rank < take);
+        if (__builtin_amdgcn_inverse_ballot_w64(got)) {
           tree = c_tfirst + c_next + rank;
           pid = c_pid;
           ph = c_ph ^ tree;
@@ -481,15 +484,16 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
           ne = 0;
           flags = 0;
           sp = 0;
-          active = true;
+          live = true;
         }
+        amask |= got;
         c_next += take;
       }
     }
-    if (__ballot(active) == 0) {
-      if (!more) break;
-      continue;
-    }
+    // No lane holds a tree only when the chunks are used up (or the wave met an empty chunk: it then
+    // takes one guarded step on stale state and refills again).
+    if (amask == 0 && !more) break;
+    const bool active = __builtin_amdgcn_inverse_ballot_w64(amask);
     // Lanes without a tree step along on their stale state (no memory effects: push, pop and record
     // are guarded), which keeps the node step free of a divergent exit; the variants with general
     // coefficients skip them, as their Euler edges take a data-dependent number of steps.
@@ -627,11 +631,16 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
         }
       }
     }
-    if (active && done) {
+    const bool fin = active && done;
+    if (fin) {
       a.tree_f[rec] = flags ? 0.0 : F;
       a.tree_meta[rec] = (ne < 255u ? ne : 255u) | flags | (node << kMetaNodesShift);
       if (flags & kMetaDepth) atomicAdd(a.depth_counter, 1ull);
-      active = false;
+    }
+    if constexpr (CMOD) {
+      if (fin) live = false;
+    } else {
+      amask &= ~__ballot(fin);
     }
   }
 }
