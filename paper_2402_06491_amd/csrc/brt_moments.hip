@@ -27,7 +27,7 @@ namespace brt {
 constexpr int kRedGroup = 16;   // bins accumulated per pass over a segment (per-lane sums in LDS)
 static_assert((kSegTrees + kWave - 1) / kWave <= 65535 && (kPlanSegMax + kWave - 1) / kWave <= 65535,
               "per-lane counts are 16-bit");
-constexpr int kRedBatch = 32;   // records loaded per lane before they are accumulated
+constexpr int kRedBatch = 16;   // records loaded per lane per batch (two batches in flight)
 constexpr uint32_t kAbsent = 0xffffffffu;  // marks a batch slot past the end of the segment (no real
                                            // record has every flag bit set)
 
@@ -193,17 +193,25 @@ __global__ __launch_bounds__(kWave) void reduce_kernel(ReduceArgs a) {
       lcnt[k][lane] = 0;
     }
     bool above = false;
-    // records are loaded kRedBatch at a time so that many loads are in flight per lane; each lane still
-    // adds its records in increasing index order
-    for (uint32_t i0 = sg.begin + lane; i0 < sg.end; i0 += kWave * kRedBatch) {
-      uint32_t mb[kRedBatch];
-      double fb[kRedBatch];
+    // records are loaded kRedBatch at a time, and the next batch is requested before the current one
+    // is added (two batches in registers), so the loads' latency overlaps the accumulation; each lane
+    // still adds its records in increasing index order
+    uint32_t mb[kRedBatch], mn[kRedBatch];
+    double fb[kRedBatch], fn[kRedBatch];
+    auto load_batch = [&](uint32_t i0, uint32_t* m, double* f) {
 #pragma unroll
       for (int j = 0; j < kRedBatch; ++j) {
         const uint32_t i = i0 + j * kWave;
-        mb[j] = i < sg.end ? M[i] : kAbsent;
-        fb[j] = i < sg.end ? F[i] : 0.0;
+        m[j] = i < sg.end ? M[i] : kAbsent;
+        f[j] = i < sg.end ? F[i] : 0.0;
       }
+    };
+    load_batch(sg.begin + lane, mb, fb);
+    // complete the first batch here: the loop then waits for its prefetch only where it copies it
+#pragma unroll
+    for (int j = 0; j < kRedBatch; ++j) asm volatile("" ::"v"(mb[j]), "v"(fb[j]));
+    for (uint32_t i0 = sg.begin + lane; i0 < sg.end; i0 += kWave * kRedBatch) {
+      load_batch(i0 + kWave * kRedBatch, mn, fn);
 #pragma unroll
       for (int j = 0; j < kRedBatch; ++j) {
         const uint32_t m = mb[j];
@@ -224,6 +232,11 @@ __global__ __launch_bounds__(kWave) void reduce_kernel(ReduceArgs a) {
         lcnt[k][lane] += 1;
         dd_add(&s1h[k][lane], &s1l[k][lane], f);
         s2[k][lane] += __dmul_rn(f, f);  // the square rounded on its own, not fused into the sum
+      }
+#pragma unroll
+      for (int j = 0; j < kRedBatch; ++j) {
+        mb[j] = mn[j];
+        fb[j] = fn[j];
       }
     }
     for (int k = 0; k < kRedGroup; ++k) {
