@@ -268,6 +268,71 @@ def test_pdd_end_to_end_against_oracle_monte_carlo(ctx):
     assert dfield <= 4.0 * dnode + FIELD_TOL * max(1.0, float(np.abs(ofield).max()))
 
 
+def test_pdd_monte_carlo_leg_full_size(ctx):
+    """The tail workload's Monte Carlo leg at its full size, as the bench runs it (2640 line nodes x 1e5
+    trees, FP32 paths; paper Sec. 3, the values that the interpolation turns into boundary data):
+    the node values brt_pdd_run produces equal, bit for bit, those of a plan over the same nodes; 4000
+    of that plan's trees, sampled over all nodes, agree with the oracle tree by tree; and every tree of
+    two sampled nodes goes through the oracle's moments and Pade value (1e-3 unless both sides flag)."""
+    import torch
+
+    import paper_2402_06491_amd as brt
+    from paper_2402_06491_amd import Plan
+
+    wl = inputs.pdd_cubic_2d()
+    prob, grid, mc, nt = wl["problem"], wl["grid"], wl["mc"], wl["n_trees"]
+    _announce("pdd_monte_carlo_leg_full_size", grid)
+    pd = brt.Pdd(ctx, prob, grid)
+    try:
+        xy, t = pd.nodes()
+        n = len(t)
+        node_u = torch.empty(n, dtype=torch.float64, device="cuda")
+        pd.run(mc, nt, node_u=node_u)
+        torch.cuda.synchronize()
+        u_pdd = node_u.cpu().numpy()
+    finally:
+        pd.close()
+    pw = {"problems": [prob], "mc": mc, "x": np.asarray(xy), "t": np.asarray(t),
+          "n_trees": np.full(n, nt, np.int64), "problem_id": np.zeros(n, np.uint32)}
+    plan = Plan(ctx, [prob], mc, pw["x"], pw["t"], pw["n_trees"], problem_id=pw["problem_id"])
+    out = plan.outputs(records=True)
+    plan.execute(out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out["u"].cpu().numpy(), u_pdd, equal_nan=True)
+    assert np.all(out["hist"].sum(dim=1).cpu().numpy() == nt)
+
+    rng = np.random.default_rng(2640)
+    pi = rng.integers(0, n, size=4000)
+    ti = rng.integers(0, nt, size=4000)
+    rec = torch.as_tensor(pi * nt + ti, device="cuda")
+    g = {"tree_f": out["tree_f"][rec].cpu().numpy(), "tree_meta": out["tree_meta"][rec].cpu().numpy()}
+    orc = P.oracle_trees(pw, pi, ti)
+    worst = P.compare_trees(g, np.arange(len(pi)), orc, P.FP32_TOL, pi)
+
+    full = np.sort(rng.choice(n, size=2, replace=False))
+    sub = dict(pw, x=pw["x"][full], t=pw["t"][full], n_trees=pw["n_trees"][full],
+               problem_id=pw["problem_id"][full], point_id=full.astype(np.uint32))
+    rows = torch.as_tensor(full, device="cuda")
+    g2 = {k: out[k][rows].cpu().numpy() for k in ("u", "se", "psum", "coef", "coef_var", "hist", "s1", "s2",
+                                                  "nodes", "flags", "pade_diag")}
+    recs = torch.cat([torch.arange(int(p) * nt, (int(p) + 1) * nt, device="cuda") for p in full])
+    g2["tree_f"] = out["tree_f"][recs].cpu().numpy()
+    g2["tree_meta"] = out["tree_meta"][recs].cpu().numpy()
+    plan.close()
+    del out
+    spi, sti, sri = P.tree_items(sub)
+    sorc = P.oracle_trees(sub, spi, sti)
+    P.compare_trees(g2, sri, sorc, P.FP32_TOL, spi)
+    omom = P.oracle_moments(sub, sorc, spi)
+    P.compare_moments(sub, g2, omom, P.FP32_TOL)
+    P.check_exact_sums(sub, g2, sri, spi)
+    opade = P.oracle_pade(sub, omom)
+    du, strict, _, flagged, near = P.compare_pade(sub, g2, opade, 1e-3)
+    print(f"[case] pdd_monte_carlo_leg_full_size: {n} nodes x {nt} trees; {len(pi)} sampled trees, max rel diff "
+          f"{worst:.3e}; nodes {full.tolist()} in full: max |du| {du:.3e} over {strict} unflagged, {flagged} "
+          f"flagged on both sides, {near} degree choices near the threshold", flush=True)
+
+
 @pytest.mark.parametrize("pw", [0, 1])
 def test_tail_variable_coefficients(ctx, pw):
     """Reaction with c_j(x, t) = c_j e^{-bx x^2 - by y^2} (t + t0)^-pow at the node and the mid-step time."""
