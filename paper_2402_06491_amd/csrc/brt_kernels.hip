@@ -259,14 +259,6 @@ __host__ __device__ constexpr size_t pde_table_bytes(int n) {
   return ((size_t)n * sizeof(PdeT<Real>) + 15) & ~(size_t)15;
 }
 
-// ------------------------------------------------------------------------------------------------
-// Per-lane DFS stack.  An entry is pushed for each vertex that still has children to start: the
-// state its children depart from (clock product P, position, time left) and the number of children
-// not yet started.  The top `lds_depth` levels live in LDS (structure of arrays, one slot per lane so
-// lanes never conflict); deeper levels go to the thread's own slice of a global spill area.
-// ------------------------------------------------------------------------------------------------
-#define BRT_LDS __attribute__((address_space(3)))
-
 // Wave-uniform copies (scalar registers) of values loaded from a wave-uniform address.
 __device__ __forceinline__ uint32_t rfl_u32(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ __forceinline__ uint64_t rfl_u64(uint64_t v) {
@@ -276,6 +268,14 @@ __device__ __forceinline__ double rfl_f64(double v) { return __builtin_bit_cast(
 // An empty statement that reads a register: the compiler completes the load that wrote it first.
 __device__ __forceinline__ void consume(double v) { asm volatile("" ::"v"(v)); }
 __device__ __forceinline__ void consume(float v) { asm volatile("" ::"v"(v)); }
+
+// ------------------------------------------------------------------------------------------------
+// Per-lane DFS stack.  An entry is pushed for each vertex that still has children to start: the
+// state its children depart from (clock product P, position, time left) and the number of children
+// not yet started.  The top `lds_depth` levels live in LDS (structure of arrays, one slot per lane so
+// lanes never conflict); deeper levels go to the thread's own slice of a global spill area.
+// ------------------------------------------------------------------------------------------------
+#define BRT_LDS __attribute__((address_space(3)))
 
 template <typename Real, int DIM, int STRAT>
 struct Stack {
@@ -409,12 +409,13 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
   uint32_t next_raw = 0;
   if (lane == 0) next_raw = atomicAdd(a.chunk_counter, 1u);
 
-  // per-lane tree state
-  uint64_t amask = 0;  // lanes that hold a tree
+  // which lanes hold a tree (wave-uniform, in scalar registers)
+  uint64_t amask = 0;
   // The variants with general coefficients leave the node step early on lanes without a tree (a
   // divergent continue), after which the lanes' copies of a carried mask would differ: they rebuild
   // the mask from this per-lane flag at the top of every step instead, where all lanes have met.
   bool live = false;
+  // per-lane tree state
   uint32_t tree = 0, node = 0, ne = 0, flags = 0, sp = 0, pid = 0, pde_lane = 0;
   uint32_t ph = 0, pl = 0;  // the tree's share of the first Philox round (philox4x32_10_tree)
   uint64_t rec = 0;
