@@ -178,8 +178,11 @@ __global__ __launch_bounds__(kWave) void reduce_kernel(ReduceArgs a) {
   const uint32_t lane = threadIdx.x;
   const Segment sg = a.segs[seg];
   const PointRec& pr = a.points[sg.point];
-  const double* F = a.tree_f + pr.tree_base;
-  const uint32_t* M = a.tree_meta + pr.tree_base;
+  // the segment's records, indexed from its first tree (a segment holds at most 2^16 trees, so these
+  // 32-bit indices cannot wrap even where the point's own tree indices approach 2^32)
+  const double* F = a.tree_f + pr.tree_base + sg.begin;
+  const uint32_t* M = a.tree_meta + pr.tree_base + sg.begin;
+  const uint32_t n_seg = sg.end - sg.begin;
   const uint32_t B = a.n_bins;
   Partial* out = a.partials + (size_t)sg.out * (B + 3);
 
@@ -202,15 +205,15 @@ __global__ __launch_bounds__(kWave) void reduce_kernel(ReduceArgs a) {
 #pragma unroll
       for (int j = 0; j < kRedBatch; ++j) {
         const uint32_t i = i0 + j * kWave;
-        m[j] = i < sg.end ? M[i] : kAbsent;
-        f[j] = i < sg.end ? F[i] : 0.0;
+        m[j] = i < n_seg ? M[i] : kAbsent;
+        f[j] = i < n_seg ? F[i] : 0.0;
       }
     };
-    load_batch(sg.begin + lane, mb, fb);
+    load_batch(lane, mb, fb);
     // complete the first batch here: the loop then waits for its prefetch only where it copies it
 #pragma unroll
     for (int j = 0; j < kRedBatch; ++j) asm volatile("" ::"v"(mb[j]), "v"(fb[j]));
-    for (uint32_t i0 = sg.begin + lane; i0 < sg.end; i0 += kWave * kRedBatch) {
+    for (uint32_t i0 = lane; i0 < n_seg; i0 += kWave * kRedBatch) {
       load_batch(i0 + kWave * kRedBatch, mn, fn);
 #pragma unroll
       for (int j = 0; j < kRedBatch; ++j) {

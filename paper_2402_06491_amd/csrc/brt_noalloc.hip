@@ -155,10 +155,11 @@ extern "C" int brt_solve_noalloc(brt_ctx* ctx, uint32_t n_problems, const brt_pr
   const uint32_t ct = ctx->launch.chunk_trees;
   uint32_t nc = 0, ns = 0;
   for (uint32_t k = 0; k < pts->n; ++k) {
-    const uint32_t i = h_order[k], n = h_points[i].n_trees;
-    for (uint32_t b0 = 0; b0 < n; b0 += ct) {
+    const uint32_t i = h_order[k];
+    const uint64_t n = h_points[i].n_trees;
+    for (uint64_t b0 = 0; b0 < n; b0 += ct) {
       if (nc == kNaMaxChunks) return na_fail(BRT_E_ARG, "too many work chunks");
-      h_chunks[nc++] = Chunk{i, b0, std::min(n, b0 + ct), 0u};
+      h_chunks[nc++] = Chunk{i, (uint32_t)b0, (uint32_t)std::min<uint64_t>(n, b0 + ct), 0u};
     }
   }
   // reduction segments, in point order
@@ -166,9 +167,9 @@ extern "C" int brt_solve_noalloc(brt_ctx* ctx, uint32_t n_problems, const brt_pr
   for (uint32_t i = 0; i < pts->n; ++i) {
     PointRec& r = h_points[i];
     r.seg_begin = ns;
-    for (uint32_t b0 = 0; b0 < r.n_trees; b0 += seg_trees) {
+    for (uint64_t b0 = 0; b0 < r.n_trees; b0 += seg_trees) {
       if (ns == kNaMaxSegs) return na_fail(BRT_E_ARG, "too many reduction segments");
-      h_segs[ns] = Segment{i, b0, std::min(r.n_trees, b0 + seg_trees), ns};
+      h_segs[ns] = Segment{i, (uint32_t)b0, (uint32_t)std::min<uint64_t>(r.n_trees, b0 + seg_trees), ns};
       ++ns;
     }
     r.seg_count = ns - r.seg_begin;

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+#include <new>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -453,18 +454,26 @@ extern "C" int brt_plan_create(brt_ctx* ctx, uint32_t n_problems, const brt_prob
   std::vector<uint32_t> order(pts->n);
   std::iota(order.begin(), order.end(), 0u);
   std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return cost[a] > cost[b]; });
-  for (uint32_t i : order) {
-    const uint32_t n = p->points[i].n_trees;
-    for (uint32_t b0 = 0; b0 < n; b0 += ct) p->chunks.push_back(Chunk{i, b0, std::min(n, b0 + ct), 0u});
-  }
-  // reduction segments, in point order
+  // (64-bit range counters: a point's tree count reaches 2^32 - 1, where a 32-bit counter would wrap)
   const uint32_t seg_trees = plan_seg_trees(p->total_trees);
-  for (uint32_t i = 0; i < pts->n; ++i) {
-    PointRec& r = p->points[i];
-    r.seg_begin = (uint32_t)p->segs.size();
-    for (uint32_t b0 = 0; b0 < r.n_trees; b0 += seg_trees)
-      p->segs.push_back(Segment{i, b0, std::min(r.n_trees, b0 + seg_trees), (uint32_t)p->segs.size()});
-    r.seg_count = (uint32_t)p->segs.size() - r.seg_begin;
+  try {
+    for (uint32_t i : order) {
+      const uint64_t n = p->points[i].n_trees;
+      for (uint64_t b0 = 0; b0 < n; b0 += ct)
+        p->chunks.push_back(Chunk{i, (uint32_t)b0, (uint32_t)std::min<uint64_t>(n, b0 + ct), 0u});
+    }
+    // reduction segments, in point order
+    for (uint32_t i = 0; i < pts->n; ++i) {
+      PointRec& r = p->points[i];
+      r.seg_begin = (uint32_t)p->segs.size();
+      for (uint64_t b0 = 0; b0 < r.n_trees; b0 += seg_trees)
+        p->segs.push_back(Segment{i, (uint32_t)b0, (uint32_t)std::min<uint64_t>(r.n_trees, b0 + seg_trees),
+                                  (uint32_t)p->segs.size()});
+      r.seg_count = (uint32_t)p->segs.size() - r.seg_begin;
+    }
+  } catch (const std::bad_alloc&) {
+    plan_free(p);
+    return fail(BRT_E_NOMEM, "plan: host allocation of the chunk and segment tables");
   }
 
   // Stack depth: with pruning a lineage holds at most max_order vertices with children still to

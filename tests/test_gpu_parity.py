@@ -227,6 +227,47 @@ def test_edge_max_order_and_mixed_problems(ctx):
     _full_parity(ctx, "edge_16_problems", wl, pade_tol=1e-3)
 
 
+def test_edge_max_trees_per_point(ctx):
+    """One point with the largest tree count a plan takes (2^32 - 1 trees: 51.5 GB of tree records) and
+    no non-linear term (every tree is one leaf), FP32 paths: every tree is counted exactly once, by a
+    reduction whose last segments end next to 2^32; the value matches the heat-kernel mean within its
+    Monte Carlo error; trees at both ends of the Philox tree counter agree with the oracle."""
+    import torch
+
+    from paper_2402_06491_amd import Plan
+
+    nt = (1 << 32) - 1
+    g = inputs.gauss_sum([(1.0, 0.0, 0.0, 1.0)])
+    wl = {"problems": [inputs.problem(1, 1.0, [0, 0, 0], g)], "mc": inputs.mc_params(seed=11, precision=32),
+          "x": np.array([[0.3]]), "t": np.array([1.0]), "n_trees": np.array([nt], np.int64)}
+    _announce("edge_max_trees_per_point", wl)
+    plan = Plan(ctx, wl["problems"], wl["mc"], wl["x"], wl["t"], wl["n_trees"])
+    out = plan.outputs(records=True)
+    try:
+        plan.execute(out)
+        torch.cuda.synchronize()
+        B = oracle.n_bins(wl["mc"])
+        hist = out["hist"].cpu().numpy()[0]
+        assert int(hist[0]) == nt and int(hist[:B].sum()) == nt and int(hist[B:].sum()) == 0, hist
+        assert int(out["nodes"].cpu().numpy()[0]) == nt
+        ti = np.array([0, 1, 2, 777, 65535, 65536, nt - 65537, nt - 3, nt - 2, nt - 1], np.int64)
+        pi = np.zeros(len(ti), np.int64)
+        rec = torch.as_tensor(ti, device="cuda")
+        gt = {"tree_f": out["tree_f"][rec].cpu().numpy(), "tree_meta": out["tree_meta"][rec].cpu().numpy()}
+        orc = P.oracle_trees(wl, pi, ti)
+        P.compare_trees(gt, np.arange(len(ti)), orc, P.FP32_TOL, pi)
+        # u_t = u_xx from a Gaussian of width 1: the width grows to sqrt(1 + 2t)
+        exact = math.exp(-0.3 ** 2 / (2 * 3.0)) / math.sqrt(3.0)
+        u = float(out["u"].cpu().numpy()[0])
+        se = float(out["se"].cpu().numpy()[0])
+        print(f"[case] edge_max_trees_per_point: u {u:.9f} exact {exact:.9f} se {se:.2e}", flush=True)
+        assert abs(u - exact) <= 6 * se + 1e-6, (u, exact, se)
+    finally:
+        plan.close()
+        del out
+        torch.cuda.empty_cache()
+
+
 def test_edge_cos2_bump_2d(ctx):
     prob = inputs.problem(2, 1.0, [0, 0, -1.25, -1.0], {"u0_kind": "cos2_bump", "u0_params": [-2.0, 10.0, 40.0],
                                                          "u0_nterms": 0})
