@@ -189,6 +189,34 @@ def test_edge_empty_and_ragged_points(ctx):
     assert gpu["hist"][0].sum() == 0 and gpu["u"][0] == 0.0
 
 
+def test_edge_zero_points(ctx):
+    """A plan, brt_solve and brt_solve_noalloc with no points at all run (their kernels find no work)
+    and return empty outputs."""
+    import torch
+
+    import paper_2402_06491_amd as brt
+    from paper_2402_06491_amd import Plan
+
+    wl = inputs.fisher(n_trees=10, n_x=1, times=(0.5,))
+    x, t, nt = np.zeros((0, 1)), np.zeros(0), np.zeros(0, np.int64)
+    _announce("edge_zero_points", dict(wl, x=x, t=t, n_trees=nt))
+    plan = Plan(ctx, wl["problems"], wl["mc"], x, t, nt)
+    try:
+        out = plan.outputs(records=True)
+        plan.execute(out)
+        s = torch.cuda.Stream()  # a created stream: the step is captured into a graph, then replayed
+        plan.execute(out, stream=s)
+        plan.execute(out, stream=s)
+        torch.cuda.synchronize()
+        assert out["u"].numel() == 0 and out["hist"].shape[0] == 0
+    finally:
+        plan.close()
+    for na in (False, True):
+        o = brt.solve(ctx, wl["problems"], wl["mc"], x, t, nt, noalloc=na)
+        torch.cuda.synchronize()
+        assert o["u"].numel() == 0 and o["se"].numel() == 0
+
+
 def test_edge_time_zero_and_no_nonlinearity(ctx):
     wl = inputs.fisher(n_trees=500, n_x=8, times=(0.0,))
     _full_parity(ctx, "edge_t0", wl)
