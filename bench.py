@@ -308,17 +308,21 @@ def pade_parity(wl, recs, gpu):
     return out
 
 
-def pmc_traffic(kernel_src_sha, launches_trees=None, name="walk_fisher_pmc.json"):
-    """HBM bytes per launch of a kernel from its committed rocprofv3 counter summary, if that was taken
-    on the current kernel source (else None)."""
+def pmc_record(kernel_src_sha, name="walk_fisher_pmc.json"):
+    """A kernel's committed rocprofv3 counter summary, if it was taken on the current kernel source
+    (else None)."""
     path = os.path.join(ROOT, "profiles", name)
     try:
         d = json.load(open(path))
     except (OSError, ValueError):
         return None
-    if d.get("kernel_source_sha256") != kernel_src_sha:
-        return None
-    return d.get("hbm_bytes_per_launch")
+    return d if d.get("kernel_source_sha256") == kernel_src_sha else None
+
+
+def pmc_traffic(kernel_src_sha, launches_trees=None, name="walk_fisher_pmc.json"):
+    """HBM bytes per launch of a kernel from its committed counter summary (None if stale)."""
+    d = pmc_record(kernel_src_sha, name)
+    return d.get("hbm_bytes_per_launch") if d else None
 
 
 def source_sha(files):
@@ -340,7 +344,7 @@ COPY_BYTES = 512 << 20  # the plain device copy of --pmc-calibration
 FISHER_WALKER = "walk_kernel<float, 1, 1, false, 0>"  # the headline's walker (1-D, logistic data, Strategy A)
 
 
-def pmc_summary(fetch_dir, write_dir, command):
+def pmc_summary(fetch_dir, write_dir, command, launch=None):
     """Write profiles/walk_fisher_pmc.json (and profiles/adi_pdd_cubic_2d_pmc.json when the runs include
     the domain-decomposition tail) from two rocprofv3 --pmc runs of this script (FETCH_SIZE, then
     WRITE_SIZE, with --pmc-calibration): the last dispatch of each kernel (the timed plan's last direct
@@ -378,6 +382,8 @@ def pmc_summary(fetch_dir, write_dir, command):
            "fetch_scale": fs, "write_scale": ws,
            "hbm_bytes_per_launch": fw * 1024.0 * fs + ww * 1024.0 * ws,
            "algorithmic_bytes_per_launch": 12 * trees, "command": command}
+    if launch:
+        out["launch"] = json.loads(launch)  # the walker launch the counter runs used (their autotuner's choice)
     path = os.path.join(ROOT, "profiles", "walk_fisher_pmc.json")
     json.dump(out, open(path, "w"), indent=1)
     print(json.dumps(out))
@@ -664,9 +670,10 @@ def main():
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the counter summaries under profiles/ from two rocprofv3 --pmc runs and exit")
     ap.add_argument("--pmc-command", default="", help="the command of the counter runs, recorded in the summary")
+    ap.add_argument("--pmc-launch", default="", help="the walker launch of the counter runs (JSON), recorded in the summary")
     args = ap.parse_args()
     if args.pmc_summary:
-        pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.pmc_command)
+        pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.pmc_command, args.pmc_launch or None)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
@@ -734,6 +741,7 @@ def main():
     sha = walker_source_sha()
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_TOPS, "unit": "Top/s",
                 "frac": achieved / PEAK_TOPS, "traffic": pmc_traffic(sha, total_trees),
+                "traffic_launch": (pmc_record(sha) or {}).get("launch"),
                 "kernel": "walk_kernel", "kernel_ms": walk_s * 1e3, "nodes_per_launch": nodes,
                 "ops_per_node": OPS_PER_NODE[dim], "reduce_ms": red_ms / runs, "finalize_ms": fin_ms / runs}
     log(f"walk kernel {walk_s * 1e3:.3f} ms, {nodes} nodes, {achieved:.2f} Top/s "
