@@ -344,7 +344,7 @@ COPY_BYTES = 512 << 20  # the plain device copy of --pmc-calibration
 FISHER_WALKER = "walk_kernel<float, 1, 1, false, 0>"  # the headline's walker (1-D, logistic data, Strategy A)
 
 
-def pmc_summary(fetch_dir, write_dir, command, launch=None):
+def pmc_summary(fetch_dir, write_dir, command, launch=None, which="both"):
     """Write profiles/walk_fisher_pmc.json (and profiles/adi_pdd_cubic_2d_pmc.json when the runs include
     the domain-decomposition tail) from two rocprofv3 --pmc runs of this script (FETCH_SIZE, then
     WRITE_SIZE, with --pmc-calibration): the last dispatch of each kernel (the timed plan's last direct
@@ -374,19 +374,22 @@ def pmc_summary(fetch_dir, write_dir, command, launch=None):
     ww, wc = read(write_dir, "WRITE_SIZE", FISHER_WALKER)
     fs = COPY_BYTES / (fc * 1024.0)
     ws = COPY_BYTES / (wc * 1024.0)
-    wl = workload("fisher")
-    trees = int(np.sum(wl["n_trees"]))
-    out = {"kernel": "walk_kernel", "workload": wl["name"], "kernel_source_sha256": walker_source_sha(),
-           "fetch_kib_per_dispatch": fw, "write_kib_per_dispatch": ww,
-           "copy_fetch_kib": fc, "copy_write_kib": wc, "copy_bytes": COPY_BYTES,
-           "fetch_scale": fs, "write_scale": ws,
-           "hbm_bytes_per_launch": fw * 1024.0 * fs + ww * 1024.0 * ws,
-           "algorithmic_bytes_per_launch": 12 * trees, "command": command}
-    if launch:
-        out["launch"] = json.loads(launch)  # the walker launch the counter runs used (their autotuner's choice)
-    path = os.path.join(ROOT, "profiles", "walk_fisher_pmc.json")
-    json.dump(out, open(path, "w"), indent=1)
-    print(json.dumps(out))
+    if which in ("both", "walker"):
+        wl = workload("fisher")
+        trees = int(np.sum(wl["n_trees"]))
+        out = {"kernel": "walk_kernel", "workload": wl["name"], "kernel_source_sha256": walker_source_sha(),
+               "fetch_kib_per_dispatch": fw, "write_kib_per_dispatch": ww,
+               "copy_fetch_kib": fc, "copy_write_kib": wc, "copy_bytes": COPY_BYTES,
+               "fetch_scale": fs, "write_scale": ws,
+               "hbm_bytes_per_launch": fw * 1024.0 * fs + ww * 1024.0 * ws,
+               "algorithmic_bytes_per_launch": 12 * trees, "command": command}
+        if launch:
+            out["launch"] = json.loads(launch)  # the walker launch the counter runs used (their autotuner's choice)
+        path = os.path.join(ROOT, "profiles", "walk_fisher_pmc.json")
+        json.dump(out, open(path, "w"), indent=1)
+        print(json.dumps(out))
+    if which not in ("both", "adi"):
+        return
     fa, _ = read(fetch_dir, "FETCH_SIZE", "adi_kernel")
     wa, _ = read(write_dir, "WRITE_SIZE", "adi_kernel")
     if fa is not None and wa is not None:
@@ -671,9 +674,12 @@ def main():
                     help="write the counter summaries under profiles/ from two rocprofv3 --pmc runs and exit")
     ap.add_argument("--pmc-command", default="", help="the command of the counter runs, recorded in the summary")
     ap.add_argument("--pmc-launch", default="", help="the walker launch of the counter runs (JSON), recorded in the summary")
+    ap.add_argument("--pmc-which", default="both", choices=("both", "walker", "adi"),
+                    help="which kernels' summaries --pmc-summary writes")
     args = ap.parse_args()
     if args.pmc_summary:
-        pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.pmc_command, args.pmc_launch or None)
+        pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.pmc_command, args.pmc_launch or None,
+                    args.pmc_which)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",

@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "brt.h"
+#include "brt_api.h"
 #include "brt_internal.h"
 
 using brt::set_error;
@@ -868,418 +869,436 @@ const void* adi_kernel_ptr(int S) {
 extern "C" {
 
 int brt_pdd_create(brt_ctx* ctx, const brt_problem* prob, const brt_pdd_grid* grid, brt_pdd** out) {
-  if (!ctx || !prob || !grid || !out) return set_error(BRT_E_ARG, "brt_pdd_create: NULL argument");
-  *out = nullptr;
-  if (prob->struct_size != sizeof(brt_problem)) return set_error(BRT_E_ARG, "brt_problem.struct_size mismatch");
-  if (grid->struct_size != sizeof(brt_pdd_grid)) return set_error(BRT_E_ARG, "brt_pdd_grid.struct_size mismatch");
-  const brt_pdd_grid& g = *grid;
-  if (prob->dim != 2) return set_error(BRT_E_ARG, "pdd: the problem must be 2-D");
-  if (!(prob->diffusion > 0.0) || !std::isfinite(prob->diffusion)) return set_error(BRT_E_ARG, "pdd: diffusion must be > 0");
-  for (double c : prob->coef)
-    if (!std::isfinite(c)) return set_error(BRT_E_ARG, "pdd: non-finite coefficient");
-  if (prob->u0_kind > BRT_U0_COS2_BUMP) return set_error(BRT_E_ARG, "pdd: unknown u0_kind");
-  if (prob->coef_mod > BRT_COEF_MOD_GAUSS_TIME_ALL) return set_error(BRT_E_ARG, "pdd: unknown coef_mod");
-  if (prob->drift[0] != 0.0 || prob->drift[1] != 0.0 || prob->sde != BRT_SDE_EXACT)
-    return set_error(BRT_E_ARG, "pdd: the subdomain solver takes L = a Lap (no drift, constant sigma)");
-  if (prob->coef_mod != BRT_COEF_MOD_NONE &&
-      (!(prob->coef_mod_beta[0] >= 0.0) || !(prob->coef_mod_beta[1] >= 0.0) || prob->coef_mod_pow > 1 ||
-       (prob->coef_mod_pow == 1 && !(prob->coef_mod_t0 > 0.0))))
-    return set_error(BRT_E_ARG, "pdd: invalid variable-coefficient parameters");
-  if (prob->u0_kind == BRT_U0_GAUSS_SUM && (prob->u0_nterms < 1 || prob->u0_nterms > 8))
-    return set_error(BRT_E_ARG, "pdd: gauss_sum needs 1..8 terms");
-  if (!(g.x_hi > g.x_lo) || !(g.y_hi > g.y_lo) || !std::isfinite(g.x_lo + g.x_hi + g.y_lo + g.y_hi))
-    return set_error(BRT_E_ARG, "pdd: empty or non-finite domain");
-  if (g.px < 1 || g.py < 1 || g.px > kMaxSub || g.py > kMaxSub) return set_error(BRT_E_ARG, "pdd: px, py must be 1..64");
-  if (g.cx < 2 || g.cy < 2 || g.cx > kMaxCells || g.cy > kMaxCells) return set_error(BRT_E_ARG, "pdd: cx, cy must be 2..1024");
-  if (!(g.T > 0.0) || !std::isfinite(g.T)) return set_error(BRT_E_ARG, "pdd: T must be > 0");
-  if (g.n_steps < 1 || g.n_steps > (1u << 20)) return set_error(BRT_E_ARG, "pdd: n_steps must be 1..2^20");
-  if (g.ns_x < 4 || g.ns_y < 4 || g.ns_x > kMaxNodesPerLine || g.ns_y > kMaxNodesPerLine)
-    return set_error(BRT_E_ARG, "pdd: ns_x, ns_y must be 4..257");
-  if (g.nt < 3 || g.nt > kMaxNt) return set_error(BRT_E_ARG, "pdd: nt must be 3..63");
-  if (g.outer != BRT_PDD_OUTER_LINES && g.outer != BRT_PDD_OUTER_ZERO) return set_error(BRT_E_ARG, "pdd: unknown outer");
-  if (g.outer == BRT_PDD_OUTER_ZERO && g.px == 1 && g.py == 1)
-    return set_error(BRT_E_ARG, "pdd: no lines (one subdomain with zero outer edges)");
+  return brt::api_guard("brt_pdd_create", [&]() -> int {
+    if (!ctx || !prob || !grid || !out) return set_error(BRT_E_ARG, "brt_pdd_create: NULL argument");
+    *out = nullptr;
+    if (prob->struct_size != sizeof(brt_problem)) return set_error(BRT_E_ARG, "brt_problem.struct_size mismatch");
+    if (grid->struct_size != sizeof(brt_pdd_grid)) return set_error(BRT_E_ARG, "brt_pdd_grid.struct_size mismatch");
+    const brt_pdd_grid& g = *grid;
+    if (prob->dim != 2) return set_error(BRT_E_ARG, "pdd: the problem must be 2-D");
+    if (!(prob->diffusion > 0.0) || !std::isfinite(prob->diffusion)) return set_error(BRT_E_ARG, "pdd: diffusion must be > 0");
+    for (double c : prob->coef)
+      if (!std::isfinite(c)) return set_error(BRT_E_ARG, "pdd: non-finite coefficient");
+    if (prob->u0_kind > BRT_U0_COS2_BUMP) return set_error(BRT_E_ARG, "pdd: unknown u0_kind");
+    if (prob->coef_mod > BRT_COEF_MOD_GAUSS_TIME_ALL) return set_error(BRT_E_ARG, "pdd: unknown coef_mod");
+    if (prob->drift[0] != 0.0 || prob->drift[1] != 0.0 || prob->sde != BRT_SDE_EXACT)
+      return set_error(BRT_E_ARG, "pdd: the subdomain solver takes L = a Lap (no drift, constant sigma)");
+    if (prob->coef_mod != BRT_COEF_MOD_NONE &&
+        (!(prob->coef_mod_beta[0] >= 0.0) || !(prob->coef_mod_beta[1] >= 0.0) || prob->coef_mod_pow > 1 ||
+         (prob->coef_mod_pow == 1 && !(prob->coef_mod_t0 > 0.0))))
+      return set_error(BRT_E_ARG, "pdd: invalid variable-coefficient parameters");
+    if (prob->u0_kind == BRT_U0_GAUSS_SUM && (prob->u0_nterms < 1 || prob->u0_nterms > 8))
+      return set_error(BRT_E_ARG, "pdd: gauss_sum needs 1..8 terms");
+    if (!(g.x_hi > g.x_lo) || !(g.y_hi > g.y_lo) || !std::isfinite(g.x_lo + g.x_hi + g.y_lo + g.y_hi))
+      return set_error(BRT_E_ARG, "pdd: empty or non-finite domain");
+    if (g.px < 1 || g.py < 1 || g.px > kMaxSub || g.py > kMaxSub) return set_error(BRT_E_ARG, "pdd: px, py must be 1..64");
+    if (g.cx < 2 || g.cy < 2 || g.cx > kMaxCells || g.cy > kMaxCells) return set_error(BRT_E_ARG, "pdd: cx, cy must be 2..1024");
+    if (!(g.T > 0.0) || !std::isfinite(g.T)) return set_error(BRT_E_ARG, "pdd: T must be > 0");
+    if (g.n_steps < 1 || g.n_steps > (1u << 20)) return set_error(BRT_E_ARG, "pdd: n_steps must be 1..2^20");
+    if (g.ns_x < 4 || g.ns_y < 4 || g.ns_x > kMaxNodesPerLine || g.ns_y > kMaxNodesPerLine)
+      return set_error(BRT_E_ARG, "pdd: ns_x, ns_y must be 4..257");
+    if (g.nt < 3 || g.nt > kMaxNt) return set_error(BRT_E_ARG, "pdd: nt must be 3..63");
+    if (g.outer != BRT_PDD_OUTER_LINES && g.outer != BRT_PDD_OUTER_ZERO) return set_error(BRT_E_ARG, "pdd: unknown outer");
+    if (g.outer == BRT_PDD_OUTER_ZERO && g.px == 1 && g.py == 1)
+      return set_error(BRT_E_ARG, "pdd: no lines (one subdomain with zero outer edges)");
 
-  brt_pdd* p = new (std::nothrow) brt_pdd;
-  if (!p) return set_error(BRT_E_NOMEM, "pdd: host allocation");
-  p->ctx = ctx;
-  p->prob = *prob;
-  p->g = g;
-  p->NX = g.px * g.cx;
-  p->NY = g.py * g.cy;
-  p->hx = (g.x_hi - g.x_lo) / p->NX;
-  p->hy = (g.y_hi - g.y_lo) / p->NY;
-  p->dt = g.T / g.n_steps;
-  p->rx = prob->diffusion * p->dt / (p->hx * p->hx);
-  p->ry = prob->diffusion * p->dt / (p->hy * p->hy);
-  p->u0.kind = prob->u0_kind;
-  p->u0.nterms = prob->u0_nterms;
-  std::memcpy(p->u0.p, prob->u0_params, sizeof(p->u0.p));
-  for (auto& v : p->vline) v = -1;
-  for (auto& v : p->hline) v = -1;
-  const bool edges = g.outer == BRT_PDD_OUTER_LINES;
-  uint64_t node_off = 0, bd_off = 0;
-  for (int orient = 0; orient < 2; ++orient) {
-    const uint32_t parts = orient == 0 ? g.px : g.py;
-    for (uint32_t k = 0; k <= parts; ++k) {
-      if (!edges && (k == 0 || k == parts)) continue;
-      LineDev L{};
-      L.orient = (uint32_t)orient;
-      L.k = k;
-      if (orient == 0) {
-        L.c = g.x_lo + k * (g.x_hi - g.x_lo) / g.px;
-        L.n_fine = p->NY + 1;
-        L.ns = g.ns_y;
-        L.s_lo = g.y_lo;
-        L.hs = (g.y_hi - g.y_lo) / (g.ns_y - 1);
-        L.hf = p->hy;
-        p->vline[k] = (int16_t)p->lines.size();
-        p->n_vlines += 1;
+    brt_pdd* p = new (std::nothrow) brt_pdd;
+    if (!p) return set_error(BRT_E_NOMEM, "pdd: host allocation");
+    p->ctx = ctx;
+    p->prob = *prob;
+    p->g = g;
+    p->NX = g.px * g.cx;
+    p->NY = g.py * g.cy;
+    p->hx = (g.x_hi - g.x_lo) / p->NX;
+    p->hy = (g.y_hi - g.y_lo) / p->NY;
+    p->dt = g.T / g.n_steps;
+    p->rx = prob->diffusion * p->dt / (p->hx * p->hx);
+    p->ry = prob->diffusion * p->dt / (p->hy * p->hy);
+    p->u0.kind = prob->u0_kind;
+    p->u0.nterms = prob->u0_nterms;
+    std::memcpy(p->u0.p, prob->u0_params, sizeof(p->u0.p));
+    for (auto& v : p->vline) v = -1;
+    for (auto& v : p->hline) v = -1;
+    const bool edges = g.outer == BRT_PDD_OUTER_LINES;
+    uint64_t node_off = 0, bd_off = 0;
+    for (int orient = 0; orient < 2; ++orient) {
+      const uint32_t parts = orient == 0 ? g.px : g.py;
+      for (uint32_t k = 0; k <= parts; ++k) {
+        if (!edges && (k == 0 || k == parts)) continue;
+        LineDev L{};
+        L.orient = (uint32_t)orient;
+        L.k = k;
+        if (orient == 0) {
+          L.c = g.x_lo + k * (g.x_hi - g.x_lo) / g.px;
+          L.n_fine = p->NY + 1;
+          L.ns = g.ns_y;
+          L.s_lo = g.y_lo;
+          L.hs = (g.y_hi - g.y_lo) / (g.ns_y - 1);
+          L.hf = p->hy;
+          p->vline[k] = (int16_t)p->lines.size();
+          p->n_vlines += 1;
+        } else {
+          L.c = g.y_lo + k * (g.y_hi - g.y_lo) / g.py;
+          L.n_fine = p->NX + 1;
+          L.ns = g.ns_x;
+          L.s_lo = g.x_lo;
+          L.hs = (g.x_hi - g.x_lo) / (g.ns_x - 1);
+          L.hf = p->hx;
+          p->hline[k] = (int16_t)p->lines.size();
+        }
+        L.node_off = node_off;
+        L.bd_off = bd_off;
+        node_off += (uint64_t)g.nt * L.ns;
+        bd_off += (uint64_t)(g.n_steps + 1) * L.n_fine;
+        p->lines.push_back(L);
+      }
+    }
+    p->n_nodes = node_off;
+    p->bd_doubles = bd_off;
+    p->max_ns = std::max(g.ns_x, g.ns_y);
+    p->max_fine = std::max(p->NX, p->NY) + 1;
+    p->W = (p->NX + 1 + 15) & ~15u;
+    const size_t field = (size_t)p->W * (p->NY + 1) + kFieldLead + 1;
+    const double bytes = 8.0 * ((double)p->bd_doubles + 3.0 * (double)field);
+    if (bytes > 128e9) {
+      pdd_free(p);
+      return set_error(BRT_E_ARG, "pdd: grid needs %.1f GB of device memory (limit 128 GB)", bytes / 1e9);
+    }
+    int rc = BRT_OK;
+    auto dev_alloc = [&](void** ptr, size_t n) {
+      if (rc != BRT_OK) return;
+      if (hipMalloc(ptr, n) != hipSuccess) rc = set_error(BRT_E_NOMEM, "pdd: device allocation of %zu bytes", n);
+    };
+    if (hipGetDevice(&p->device) != hipSuccess) rc = set_error(BRT_E_DEVICE, "pdd: no device");
+    hipDeviceProp_t prop;
+    if (rc == BRT_OK && hipGetDeviceProperties(&prop, p->device) != hipSuccess) rc = set_error(BRT_E_DEVICE, "pdd: device query");
+    if (rc == BRT_OK) p->n_cu = prop.multiProcessorCount;
+    const uint32_t rows = g.nt + 1;
+    p->spl_rows = (size_t)p->lines.size() * rows * p->max_ns;
+    p->spl_fine = (size_t)rows * p->lines.size() * p->max_fine;
+    dev_alloc((void**)&p->d_lines, sizeof(LineDev) * p->lines.size());
+    dev_alloc((void**)&p->d_bd, 8 * p->bd_doubles);
+    for (double*& f : p->d_f) dev_alloc((void**)&f, 8 * field);
+    p->seg = seg_length(g);
+    dev_alloc((void**)&p->d_fac, 8 * 2 * (size_t)kSegs * p->seg);
+    dev_alloc((void**)&p->d_spl, 8 * (3 * p->spl_rows + 3 * p->spl_fine));
+    dev_alloc((void**)&p->d_sync, 4 * (size_t)kSyncWords);
+    dev_alloc((void**)&p->d_node_u, 8 * std::max<uint64_t>(p->n_nodes, 1));
+    dev_alloc((void**)&p->d_exy, 8 * (size_t)(p->NX + 1 + p->NY + 1));
+    for (hipEvent_t& e : p->ev)
+      if (rc == BRT_OK && hipEventCreate(&e) != hipSuccess) rc = set_error(BRT_E_DEVICE, "pdd: event creation");
+    if (rc == BRT_OK) {
+      std::vector<double> fac(2 * (size_t)kSegs * p->seg);
+      pivot_reciprocals(p->rx, g.cx - 1, p->seg, fac.data());
+      pivot_reciprocals(p->ry, g.cy - 1, p->seg, fac.data() + (size_t)kSegs * p->seg);
+      std::vector<double> exy(p->NX + 1 + p->NY + 1, 1.0);
+      if (prob->coef_mod != BRT_COEF_MOD_NONE) {
+        for (uint32_t i = 0; i <= p->NX; ++i) {
+          const double x = g.x_lo + i * p->hx;
+          exy[i] = std::exp(-prob->coef_mod_beta[0] * x * x);
+        }
+        for (uint32_t j = 0; j <= p->NY; ++j) {
+          const double y = g.y_lo + j * p->hy;
+          exy[p->NX + 1 + j] = std::exp(-prob->coef_mod_beta[1] * y * y);
+        }
+      }
+      if (hipMemcpy(p->d_exy, exy.data(), 8 * exy.size(), hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(p->d_fac, fac.data(), 8 * fac.size(), hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(p->d_lines, p->lines.data(), sizeof(LineDev) * p->lines.size(), hipMemcpyHostToDevice) != hipSuccess)
+        rc = set_error(BRT_E_DEVICE, "pdd: upload");
+    }
+    if (rc == BRT_OK) {
+      int per_cu = 0;
+      p->lds = 8 * adi_lds_doubles(p->seg);
+      if (hipFuncSetAttribute(adi_kernel_ptr(p->seg), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)p->lds) != hipSuccess)
+        rc = set_error(BRT_E_DEVICE, "pdd: solver LDS of %zu bytes", p->lds);
+      if (rc == BRT_OK &&
+          (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, adi_kernel_ptr(p->seg), adi_threads(p->seg),
+                                                        p->lds) != hipSuccess ||
+           per_cu < 1))
+        rc = set_error(BRT_E_DEVICE, "pdd: solver occupancy query (LDS %zu bytes)", p->lds);
+      const uint32_t nsub = g.px * g.py;
+      const uint32_t lines = adi_lines(p->seg);
+      const uint32_t x_items = nsub * ((g.cy - 1 + lines - 1) / lines);
+      const uint32_t y_items = nsub * ((g.cx - 1 + lines - 1) / lines);
+      const uint64_t cap = (uint64_t)per_cu * p->n_cu;
+      const uint64_t items = std::max(x_items, y_items);
+      if (nsub % kXcds == 0 && cap >= kXcds) {
+        // Die-local barriers (the subdomains split over the dies): the fewest rounds of items over all
+        // resident blocks, dealt evenly, a multiple of the die count.  On the 4 x 4 x 512^2 workload a
+        // step takes 54 us at 256 blocks of 1024 threads (one item per block and phase), 61 at 128 and
+        // 65-67 at 160 or 192 (uneven rounds).
+        const uint64_t cap8 = cap / kXcds * kXcds;
+        const uint64_t rounds = (items + cap8 - 1) / cap8;
+        p->grid = (int)std::min<uint64_t>(cap8, ((items + rounds - 1) / rounds + kXcds - 1) / kXcds * kXcds);
       } else {
-        L.c = g.y_lo + k * (g.y_hi - g.y_lo) / g.py;
-        L.n_fine = p->NX + 1;
-        L.ns = g.ns_x;
-        L.s_lo = g.x_lo;
-        L.hs = (g.x_hi - g.x_lo) / (g.ns_x - 1);
-        L.hf = p->hx;
-        p->hline[k] = (int16_t)p->lines.size();
-      }
-      L.node_off = node_off;
-      L.bd_off = bd_off;
-      node_off += (uint64_t)g.nt * L.ns;
-      bd_off += (uint64_t)(g.n_steps + 1) * L.n_fine;
-      p->lines.push_back(L);
-    }
-  }
-  p->n_nodes = node_off;
-  p->bd_doubles = bd_off;
-  p->max_ns = std::max(g.ns_x, g.ns_y);
-  p->max_fine = std::max(p->NX, p->NY) + 1;
-  p->W = (p->NX + 1 + 15) & ~15u;
-  const size_t field = (size_t)p->W * (p->NY + 1) + kFieldLead + 1;
-  const double bytes = 8.0 * ((double)p->bd_doubles + 3.0 * (double)field);
-  if (bytes > 128e9) {
-    pdd_free(p);
-    return set_error(BRT_E_ARG, "pdd: grid needs %.1f GB of device memory (limit 128 GB)", bytes / 1e9);
-  }
-  int rc = BRT_OK;
-  auto dev_alloc = [&](void** ptr, size_t n) {
-    if (rc != BRT_OK) return;
-    if (hipMalloc(ptr, n) != hipSuccess) rc = set_error(BRT_E_NOMEM, "pdd: device allocation of %zu bytes", n);
-  };
-  if (hipGetDevice(&p->device) != hipSuccess) rc = set_error(BRT_E_DEVICE, "pdd: no device");
-  hipDeviceProp_t prop;
-  if (rc == BRT_OK && hipGetDeviceProperties(&prop, p->device) != hipSuccess) rc = set_error(BRT_E_DEVICE, "pdd: device query");
-  if (rc == BRT_OK) p->n_cu = prop.multiProcessorCount;
-  const uint32_t rows = g.nt + 1;
-  p->spl_rows = (size_t)p->lines.size() * rows * p->max_ns;
-  p->spl_fine = (size_t)rows * p->lines.size() * p->max_fine;
-  dev_alloc((void**)&p->d_lines, sizeof(LineDev) * p->lines.size());
-  dev_alloc((void**)&p->d_bd, 8 * p->bd_doubles);
-  for (double*& f : p->d_f) dev_alloc((void**)&f, 8 * field);
-  p->seg = seg_length(g);
-  dev_alloc((void**)&p->d_fac, 8 * 2 * (size_t)kSegs * p->seg);
-  dev_alloc((void**)&p->d_spl, 8 * (3 * p->spl_rows + 3 * p->spl_fine));
-  dev_alloc((void**)&p->d_sync, 4 * (size_t)kSyncWords);
-  dev_alloc((void**)&p->d_node_u, 8 * std::max<uint64_t>(p->n_nodes, 1));
-  dev_alloc((void**)&p->d_exy, 8 * (size_t)(p->NX + 1 + p->NY + 1));
-  for (hipEvent_t& e : p->ev)
-    if (rc == BRT_OK && hipEventCreate(&e) != hipSuccess) rc = set_error(BRT_E_DEVICE, "pdd: event creation");
-  if (rc == BRT_OK) {
-    std::vector<double> fac(2 * (size_t)kSegs * p->seg);
-    pivot_reciprocals(p->rx, g.cx - 1, p->seg, fac.data());
-    pivot_reciprocals(p->ry, g.cy - 1, p->seg, fac.data() + (size_t)kSegs * p->seg);
-    std::vector<double> exy(p->NX + 1 + p->NY + 1, 1.0);
-    if (prob->coef_mod != BRT_COEF_MOD_NONE) {
-      for (uint32_t i = 0; i <= p->NX; ++i) {
-        const double x = g.x_lo + i * p->hx;
-        exy[i] = std::exp(-prob->coef_mod_beta[0] * x * x);
-      }
-      for (uint32_t j = 0; j <= p->NY; ++j) {
-        const double y = g.y_lo + j * p->hy;
-        exy[p->NX + 1 + j] = std::exp(-prob->coef_mod_beta[1] * y * y);
+        // One barrier over the grid, with device-scope fences: half the compute units, a multiple of the
+        // die count (a step of that workload took 76 us at 128 blocks and 88 at 256 with these fences:
+        // more blocks lengthen every block's memory latency and add L2 write-backs at the barriers).
+        const uint64_t half = std::max<uint64_t>(kXcds, (uint64_t)p->n_cu / 2 / kXcds * kXcds);
+        p->grid = (int)std::min<uint64_t>({items, half, cap});
       }
     }
-    if (hipMemcpy(p->d_exy, exy.data(), 8 * exy.size(), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(p->d_fac, fac.data(), 8 * fac.size(), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(p->d_lines, p->lines.data(), sizeof(LineDev) * p->lines.size(), hipMemcpyHostToDevice) != hipSuccess)
-      rc = set_error(BRT_E_DEVICE, "pdd: upload");
-  }
-  if (rc == BRT_OK) {
-    int per_cu = 0;
-    p->lds = 8 * adi_lds_doubles(p->seg);
-    if (hipFuncSetAttribute(adi_kernel_ptr(p->seg), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)p->lds) != hipSuccess)
-      rc = set_error(BRT_E_DEVICE, "pdd: solver LDS of %zu bytes", p->lds);
-    if (rc == BRT_OK &&
-        (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, adi_kernel_ptr(p->seg), adi_threads(p->seg),
-                                                      p->lds) != hipSuccess ||
-         per_cu < 1))
-      rc = set_error(BRT_E_DEVICE, "pdd: solver occupancy query (LDS %zu bytes)", p->lds);
-    const uint32_t nsub = g.px * g.py;
-    const uint32_t lines = adi_lines(p->seg);
-    const uint32_t x_items = nsub * ((g.cy - 1 + lines - 1) / lines);
-    const uint32_t y_items = nsub * ((g.cx - 1 + lines - 1) / lines);
-    const uint64_t cap = (uint64_t)per_cu * p->n_cu;
-    const uint64_t items = std::max(x_items, y_items);
-    if (nsub % kXcds == 0 && cap >= kXcds) {
-      // Die-local barriers (the subdomains split over the dies): the fewest rounds of items over all
-      // resident blocks, dealt evenly, a multiple of the die count.  On the 4 x 4 x 512^2 workload a
-      // step takes 54 us at 256 blocks of 1024 threads (one item per block and phase), 61 at 128 and
-      // 65-67 at 160 or 192 (uneven rounds).
-      const uint64_t cap8 = cap / kXcds * kXcds;
-      const uint64_t rounds = (items + cap8 - 1) / cap8;
-      p->grid = (int)std::min<uint64_t>(cap8, ((items + rounds - 1) / rounds + kXcds - 1) / kXcds * kXcds);
-    } else {
-      // One barrier over the grid, with device-scope fences: half the compute units, a multiple of the
-      // die count (a step of that workload took 76 us at 128 blocks and 88 at 256 with these fences:
-      // more blocks lengthen every block's memory latency and add L2 write-backs at the barriers).
-      const uint64_t half = std::max<uint64_t>(kXcds, (uint64_t)p->n_cu / 2 / kXcds * kXcds);
-      p->grid = (int)std::min<uint64_t>({items, half, cap});
+    if (rc != BRT_OK) {
+      pdd_free(p);
+      return rc;
     }
-  }
-  if (rc != BRT_OK) {
-    pdd_free(p);
-    return rc;
-  }
-  *out = p;
-  return BRT_OK;
+    *out = p;
+    return BRT_OK;
+  });
 }
 
 int brt_pdd_nodes(const brt_pdd* p, double* xy, double* t, uint64_t* n) {
-  if (!p || !n) return set_error(BRT_E_ARG, "brt_pdd_nodes: NULL argument");
-  *n = p->n_nodes;
-  uint64_t i = 0;
-  for (const LineDev& L : p->lines) {
-    for (uint32_t k = 1; k <= p->g.nt; ++k) {
-      const double tk = k * p->g.T / p->g.nt;
-      for (uint32_t s = 0; s < L.ns; ++s, ++i) {
-        const double pos = L.s_lo + s * L.hs;
-        if (xy) {
-          xy[2 * i] = L.orient == 0 ? L.c : pos;
-          xy[2 * i + 1] = L.orient == 0 ? pos : L.c;
+  return brt::api_guard("brt_pdd_nodes", [&]() -> int {
+    if (!p || !n) return set_error(BRT_E_ARG, "brt_pdd_nodes: NULL argument");
+    *n = p->n_nodes;
+    uint64_t i = 0;
+    for (const LineDev& L : p->lines) {
+      for (uint32_t k = 1; k <= p->g.nt; ++k) {
+        const double tk = k * p->g.T / p->g.nt;
+        for (uint32_t s = 0; s < L.ns; ++s, ++i) {
+          const double pos = L.s_lo + s * L.hs;
+          if (xy) {
+            xy[2 * i] = L.orient == 0 ? L.c : pos;
+            xy[2 * i + 1] = L.orient == 0 ? pos : L.c;
+          }
+          if (t) t[i] = tk;
         }
-        if (t) t[i] = tk;
       }
     }
-  }
-  return BRT_OK;
+    return BRT_OK;
+  });
 }
 
 int brt_pdd_lines(const brt_pdd* p, uint32_t* n_lines, uint32_t* orient, double* coord, uint32_t* n_fine) {
-  if (!p || !n_lines) return set_error(BRT_E_ARG, "brt_pdd_lines: NULL argument");
-  *n_lines = (uint32_t)p->lines.size();
-  for (size_t l = 0; l < p->lines.size(); ++l) {
-    if (orient) orient[l] = p->lines[l].orient;
-    if (coord) coord[l] = p->lines[l].c;
-    if (n_fine) n_fine[l] = p->lines[l].n_fine;
-  }
-  return BRT_OK;
+  return brt::api_guard("brt_pdd_lines", [&]() -> int {
+    if (!p || !n_lines) return set_error(BRT_E_ARG, "brt_pdd_lines: NULL argument");
+    *n_lines = (uint32_t)p->lines.size();
+    for (size_t l = 0; l < p->lines.size(); ++l) {
+      if (orient) orient[l] = p->lines[l].orient;
+      if (coord) coord[l] = p->lines[l].c;
+      if (n_fine) n_fine[l] = p->lines[l].n_fine;
+    }
+    return BRT_OK;
+  });
 }
 
 int brt_pdd_interpolate(brt_pdd* p, const double* node_values, void* stream) {
-  if (!p || !node_values) return set_error(BRT_E_ARG, "brt_pdd_interpolate: NULL argument");
-  hipStream_t s = (hipStream_t)stream;
-  SplineArgs a{};
-  a.lines = p->d_lines;
-  a.n_lines = (uint32_t)p->lines.size();
-  a.rows = p->g.nt + 1;
-  a.max_ns = p->max_ns;
-  a.max_fine = p->max_fine;
-  a.node_values = node_values;
-  a.vals = p->d_spl;
-  a.mom = a.vals + p->spl_rows;
-  a.cp = a.mom + p->spl_rows;
-  a.rowsv = a.cp + p->spl_rows;
-  a.tmom = a.rowsv + p->spl_fine;
-  a.tcp = a.tmom + p->spl_fine;
-  a.bd = p->d_bd;
-  a.ht = p->g.T / p->g.nt;
-  a.dt = p->dt;
-  a.n_steps = p->g.n_steps;
-  a.u0 = p->u0;
-  PDD_TRY(hipEventRecord(p->ev[2], s));
-  const uint32_t nr = a.n_lines * a.rows;
-  spline_rows_kernel<<<(nr + 63) / 64, 64, 0, s>>>(a);
-  PDD_TRY(hipGetLastError());
-  spline_s_kernel<<<dim3((p->max_fine + 255) / 256, nr), 256, 0, s>>>(a);
-  PDD_TRY(hipGetLastError());
-  spline_t_kernel<<<dim3((p->max_fine + 255) / 256, a.n_lines), 256, 0, s>>>(a);
-  PDD_TRY(hipGetLastError());
-  PDD_TRY(hipEventRecord(p->ev[3], s));
-  p->recorded[1] = true;
-  return BRT_OK;
+  return brt::api_guard("brt_pdd_interpolate", [&]() -> int {
+    if (!p || !node_values) return set_error(BRT_E_ARG, "brt_pdd_interpolate: NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    SplineArgs a{};
+    a.lines = p->d_lines;
+    a.n_lines = (uint32_t)p->lines.size();
+    a.rows = p->g.nt + 1;
+    a.max_ns = p->max_ns;
+    a.max_fine = p->max_fine;
+    a.node_values = node_values;
+    a.vals = p->d_spl;
+    a.mom = a.vals + p->spl_rows;
+    a.cp = a.mom + p->spl_rows;
+    a.rowsv = a.cp + p->spl_rows;
+    a.tmom = a.rowsv + p->spl_fine;
+    a.tcp = a.tmom + p->spl_fine;
+    a.bd = p->d_bd;
+    a.ht = p->g.T / p->g.nt;
+    a.dt = p->dt;
+    a.n_steps = p->g.n_steps;
+    a.u0 = p->u0;
+    PDD_TRY(hipEventRecord(p->ev[2], s));
+    const uint32_t nr = a.n_lines * a.rows;
+    spline_rows_kernel<<<(nr + 63) / 64, 64, 0, s>>>(a);
+    PDD_TRY(hipGetLastError());
+    spline_s_kernel<<<dim3((p->max_fine + 255) / 256, nr), 256, 0, s>>>(a);
+    PDD_TRY(hipGetLastError());
+    spline_t_kernel<<<dim3((p->max_fine + 255) / 256, a.n_lines), 256, 0, s>>>(a);
+    PDD_TRY(hipGetLastError());
+    PDD_TRY(hipEventRecord(p->ev[3], s));
+    p->recorded[1] = true;
+    return BRT_OK;
+  });
 }
 
 int brt_pdd_boundary(const brt_pdd* p, uint32_t line, double* dst, void* stream) {
-  if (!p || !dst) return set_error(BRT_E_ARG, "brt_pdd_boundary: NULL argument");
-  if (line >= p->lines.size()) return set_error(BRT_E_ARG, "brt_pdd_boundary: no line %u", line);
-  const LineDev& L = p->lines[line];
-  PDD_TRY(hipMemcpyAsync(dst, p->d_bd + L.bd_off, 8 * (size_t)(p->g.n_steps + 1) * L.n_fine, hipMemcpyDeviceToDevice,
-                         (hipStream_t)stream));
-  return BRT_OK;
+  return brt::api_guard("brt_pdd_boundary", [&]() -> int {
+    if (!p || !dst) return set_error(BRT_E_ARG, "brt_pdd_boundary: NULL argument");
+    if (line >= p->lines.size()) return set_error(BRT_E_ARG, "brt_pdd_boundary: no line %u", line);
+    const LineDev& L = p->lines[line];
+    PDD_TRY(hipMemcpyAsync(dst, p->d_bd + L.bd_off, 8 * (size_t)(p->g.n_steps + 1) * L.n_fine, hipMemcpyDeviceToDevice,
+                           (hipStream_t)stream));
+    return BRT_OK;
+  });
 }
 
 int brt_pdd_solve(brt_pdd* p, uint32_t steps, double* field, void* stream) {
-  if (!p || !field) return set_error(BRT_E_ARG, "brt_pdd_solve: NULL argument");
-  if (steps < 1 || steps > p->g.n_steps) return set_error(BRT_E_ARG, "brt_pdd_solve: steps must be 1..%u", p->g.n_steps);
-  hipStream_t s = (hipStream_t)stream;
-  const brt_pdd_grid& g = p->g;
-  PDD_TRY(hipEventRecord(p->ev[4], s));
-  FieldArgs fa{};
-  fa.f0 = p->d_f[0] + kFieldLead;
-  fa.f1 = p->d_f[1] + kFieldLead;
-  fa.W = p->W;
-  fa.bd = p->d_bd;
-  fa.lines = p->d_lines;
-  fa.NX = p->NX;
-  fa.NY = p->NY;
-  fa.cx = g.cx;
-  fa.cy = g.cy;
-  fa.zero_outer = g.outer == BRT_PDD_OUTER_ZERO;
-  fa.x_lo = g.x_lo;
-  fa.y_lo = g.y_lo;
-  fa.hx = p->hx;
-  fa.hy = p->hy;
-  std::memcpy(fa.vline, p->vline, sizeof(fa.vline));
-  std::memcpy(fa.hline, p->hline, sizeof(fa.hline));
-  fa.u0 = p->u0;
-  const uint64_t n_field = (uint64_t)(p->NX + 1) * (p->NY + 1);
-  init_field_kernel<<<(unsigned)((n_field + 255) / 256), 256, 0, s>>>(fa);
-  PDD_TRY(hipGetLastError());
-  PDD_TRY(hipMemsetAsync(p->d_sync, 0, 4 * (size_t)kSyncWords, s));
+  return brt::api_guard("brt_pdd_solve", [&]() -> int {
+    if (!p || !field) return set_error(BRT_E_ARG, "brt_pdd_solve: NULL argument");
+    if (steps < 1 || steps > p->g.n_steps) return set_error(BRT_E_ARG, "brt_pdd_solve: steps must be 1..%u", p->g.n_steps);
+    hipStream_t s = (hipStream_t)stream;
+    const brt_pdd_grid& g = p->g;
+    PDD_TRY(hipEventRecord(p->ev[4], s));
+    FieldArgs fa{};
+    fa.f0 = p->d_f[0] + kFieldLead;
+    fa.f1 = p->d_f[1] + kFieldLead;
+    fa.W = p->W;
+    fa.bd = p->d_bd;
+    fa.lines = p->d_lines;
+    fa.NX = p->NX;
+    fa.NY = p->NY;
+    fa.cx = g.cx;
+    fa.cy = g.cy;
+    fa.zero_outer = g.outer == BRT_PDD_OUTER_ZERO;
+    fa.x_lo = g.x_lo;
+    fa.y_lo = g.y_lo;
+    fa.hx = p->hx;
+    fa.hy = p->hy;
+    std::memcpy(fa.vline, p->vline, sizeof(fa.vline));
+    std::memcpy(fa.hline, p->hline, sizeof(fa.hline));
+    fa.u0 = p->u0;
+    const uint64_t n_field = (uint64_t)(p->NX + 1) * (p->NY + 1);
+    init_field_kernel<<<(unsigned)((n_field + 255) / 256), 256, 0, s>>>(fa);
+    PDD_TRY(hipGetLastError());
+    PDD_TRY(hipMemsetAsync(p->d_sync, 0, 4 * (size_t)kSyncWords, s));
 
-  AdiArgs a{};
-  a.f0 = p->d_f[0] + kFieldLead;
-  a.f1 = p->d_f[1] + kFieldLead;
-  a.yrhs = p->d_f[2] + kFieldLead;
-  a.bd = p->d_bd;
-  a.lines = p->d_lines;
-  a.inv_x = p->d_fac;
-  a.inv_y = p->d_fac + (size_t)kSegs * p->seg;
-  a.sync = p->d_sync;
-  int rate_khz = 0;
-  PDD_TRY(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, p->device));
-  a.spin_limit = (uint64_t)(kBarrierSeconds * 1e3 * (rate_khz > 0 ? rate_khz : 100000));
-  // f = c_1 u + m(x, y, t) P(u): P holds the modulated terms, c_1 among them when it is modulated too
-  const bool lin = p->prob.coef_mod == BRT_COEF_MOD_GAUSS_TIME_ALL;
-  for (int j = 0; j < 8; ++j) a.pcoef[j] = p->prob.coef[j];
-  a.pcoef[1] = lin ? p->prob.coef[1] : 0.0;
-  const bool cmod = p->prob.coef_mod != BRT_COEF_MOD_NONE;
-  a.cm_pow = cmod ? p->prob.coef_mod_pow : 0u;
-  a.cm_t0 = p->prob.coef_mod_t0;
-  a.c1 = lin ? 0.0 : p->prob.coef[1];
-  a.dt = p->dt;
-  a.ex = p->d_exy;
-  a.ey = p->d_exy + p->NX + 1;
-  a.rx2 = 0.5 * p->rx;
-  a.ry2 = 0.5 * p->ry;
-  a.dt2 = 0.5 * p->dt;
-  a.W = p->W;
-  a.px = g.px;
-  a.py = g.py;
-  a.cx = g.cx;
-  a.cy = g.cy;
-  a.steps = steps;
-  a.nblocks = (uint32_t)p->grid;
-  // Subdomains are decoupled, so blocks that own whole subdomains in both phases synchronise among
-  // themselves only: one group per subdomain when the grid splits evenly over them (a group then waits
-  // only for the blocks of its own subdomain), else one per die, else one over the grid.
-  const uint32_t nsub = g.px * g.py, grid = (uint32_t)p->grid;
-  a.groups = nsub % kXcds != 0 || grid % kXcds != 0 ? 1u : grid % nsub == 0 && nsub <= kMaxGroups ? nsub : kXcds;
-  p->last_groups = a.groups;
-  const uint32_t lines = adi_lines(p->seg), threads = adi_threads(p->seg);
-  a.x_blk = (g.cy - 1 + lines - 1) / lines;
-  a.y_blk = (g.cx - 1 + lines - 1) / lines;
-  a.n_vlines = p->n_vlines;
-  a.bv = (p->NY + 1 + threads - 1) / threads;
-  a.bh = (p->NX + 1 + threads - 1) / threads;
-  a.n_lines = (uint32_t)p->lines.size();
-  std::memcpy(a.vline, p->vline, sizeof(a.vline));
-  std::memcpy(a.hline, p->hline, sizeof(a.hline));
-  a.v_fine = p->NY + 1;
-  a.h_fine = p->NX + 1;
-  for (size_t l = 0; l < p->lines.size(); ++l) a.bd_off[l] = p->lines[l].bd_off;
-  void* kargs[] = {&a};
-  PDD_TRY(hipLaunchCooperativeKernel(adi_kernel_ptr(p->seg), dim3(p->grid), dim3(threads), kargs,
-                                     (unsigned)p->lds, s));
-  const double* result = ((steps & 1) ? p->d_f[1] : p->d_f[0]) + kFieldLead;
-  PDD_TRY(hipMemcpy2DAsync(field, 8 * (size_t)(p->NX + 1), result, 8 * (size_t)p->W, 8 * (size_t)(p->NX + 1), p->NY + 1,
-                           hipMemcpyDeviceToDevice, s));
-  PDD_TRY(hipEventRecord(p->ev[5], s));
-  p->recorded[2] = true;
-  return BRT_OK;
+    AdiArgs a{};
+    a.f0 = p->d_f[0] + kFieldLead;
+    a.f1 = p->d_f[1] + kFieldLead;
+    a.yrhs = p->d_f[2] + kFieldLead;
+    a.bd = p->d_bd;
+    a.lines = p->d_lines;
+    a.inv_x = p->d_fac;
+    a.inv_y = p->d_fac + (size_t)kSegs * p->seg;
+    a.sync = p->d_sync;
+    int rate_khz = 0;
+    PDD_TRY(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, p->device));
+    a.spin_limit = (uint64_t)(kBarrierSeconds * 1e3 * (rate_khz > 0 ? rate_khz : 100000));
+    // f = c_1 u + m(x, y, t) P(u): P holds the modulated terms, c_1 among them when it is modulated too
+    const bool lin = p->prob.coef_mod == BRT_COEF_MOD_GAUSS_TIME_ALL;
+    for (int j = 0; j < 8; ++j) a.pcoef[j] = p->prob.coef[j];
+    a.pcoef[1] = lin ? p->prob.coef[1] : 0.0;
+    const bool cmod = p->prob.coef_mod != BRT_COEF_MOD_NONE;
+    a.cm_pow = cmod ? p->prob.coef_mod_pow : 0u;
+    a.cm_t0 = p->prob.coef_mod_t0;
+    a.c1 = lin ? 0.0 : p->prob.coef[1];
+    a.dt = p->dt;
+    a.ex = p->d_exy;
+    a.ey = p->d_exy + p->NX + 1;
+    a.rx2 = 0.5 * p->rx;
+    a.ry2 = 0.5 * p->ry;
+    a.dt2 = 0.5 * p->dt;
+    a.W = p->W;
+    a.px = g.px;
+    a.py = g.py;
+    a.cx = g.cx;
+    a.cy = g.cy;
+    a.steps = steps;
+    a.nblocks = (uint32_t)p->grid;
+    // Subdomains are decoupled, so blocks that own whole subdomains in both phases synchronise among
+    // themselves only: one group per subdomain when the grid splits evenly over them (a group then waits
+    // only for the blocks of its own subdomain), else one per die, else one over the grid.
+    const uint32_t nsub = g.px * g.py, grid = (uint32_t)p->grid;
+    a.groups = nsub % kXcds != 0 || grid % kXcds != 0 ? 1u : grid % nsub == 0 && nsub <= kMaxGroups ? nsub : kXcds;
+    p->last_groups = a.groups;
+    const uint32_t lines = adi_lines(p->seg), threads = adi_threads(p->seg);
+    a.x_blk = (g.cy - 1 + lines - 1) / lines;
+    a.y_blk = (g.cx - 1 + lines - 1) / lines;
+    a.n_vlines = p->n_vlines;
+    a.bv = (p->NY + 1 + threads - 1) / threads;
+    a.bh = (p->NX + 1 + threads - 1) / threads;
+    a.n_lines = (uint32_t)p->lines.size();
+    std::memcpy(a.vline, p->vline, sizeof(a.vline));
+    std::memcpy(a.hline, p->hline, sizeof(a.hline));
+    a.v_fine = p->NY + 1;
+    a.h_fine = p->NX + 1;
+    for (size_t l = 0; l < p->lines.size(); ++l) a.bd_off[l] = p->lines[l].bd_off;
+    void* kargs[] = {&a};
+    PDD_TRY(hipLaunchCooperativeKernel(adi_kernel_ptr(p->seg), dim3(p->grid), dim3(threads), kargs,
+                                       (unsigned)p->lds, s));
+    const double* result = ((steps & 1) ? p->d_f[1] : p->d_f[0]) + kFieldLead;
+    PDD_TRY(hipMemcpy2DAsync(field, 8 * (size_t)(p->NX + 1), result, 8 * (size_t)p->W, 8 * (size_t)(p->NX + 1), p->NY + 1,
+                             hipMemcpyDeviceToDevice, s));
+    PDD_TRY(hipEventRecord(p->ev[5], s));
+    p->recorded[2] = true;
+    return BRT_OK;
+  });
 }
 
 int brt_pdd_run(brt_pdd* p, const brt_mc* mc, uint64_t trees_per_node, double* node_u, double* field, void* stream) {
-  if (!p || !mc || !field) return set_error(BRT_E_ARG, "brt_pdd_run: NULL argument");
-  if (mc->struct_size != sizeof(brt_mc)) return set_error(BRT_E_ARG, "brt_mc.struct_size mismatch");
-  if (trees_per_node < 1 || trees_per_node > 0xffffffffull) return set_error(BRT_E_ARG, "brt_pdd_run: trees_per_node must be 1..2^32-1");
-  hipStream_t s = (hipStream_t)stream;
-  if (p->plan && (std::memcmp(&p->plan_mc, mc, sizeof(brt_mc)) != 0 || p->plan_trees != trees_per_node)) {
-    brt_plan_destroy(p->plan);
-    p->plan = nullptr;
-  }
-  if (!p->plan) {
-    std::vector<double> xy(2 * p->n_nodes), t(p->n_nodes);
-    std::vector<uint64_t> nt(p->n_nodes, trees_per_node);
-    uint64_t n = 0;
-    brt_pdd_nodes(p, xy.data(), t.data(), &n);
-    brt_points pts{};
-    pts.struct_size = sizeof(pts);
-    pts.n = (uint32_t)n;
-    pts.x = xy.data();
-    pts.t = t.data();
-    pts.n_trees = nt.data();
-    const int rc = brt_plan_create(p->ctx, 1, &p->prob, mc, &pts, &p->plan);
-    if (rc != BRT_OK) {
+  return brt::api_guard("brt_pdd_run", [&]() -> int {
+    if (!p || !mc || !field) return set_error(BRT_E_ARG, "brt_pdd_run: NULL argument");
+    if (mc->struct_size != sizeof(brt_mc)) return set_error(BRT_E_ARG, "brt_mc.struct_size mismatch");
+    if (trees_per_node < 1 || trees_per_node > 0xffffffffull) return set_error(BRT_E_ARG, "brt_pdd_run: trees_per_node must be 1..2^32-1");
+    hipStream_t s = (hipStream_t)stream;
+    if (p->plan && (std::memcmp(&p->plan_mc, mc, sizeof(brt_mc)) != 0 || p->plan_trees != trees_per_node)) {
+      brt_plan_destroy(p->plan);
       p->plan = nullptr;
-      return rc;
     }
-    p->plan_mc = *mc;
-    p->plan_trees = trees_per_node;
-  }
-  double* u = node_u ? node_u : p->d_node_u;
-  brt_out o{};
-  o.struct_size = sizeof(o);
-  o.u = u;
-  PDD_TRY(hipEventRecord(p->ev[0], s));
-  int rc = brt_plan_execute(p->plan, &o, stream);
-  if (rc != BRT_OK) return rc;
-  PDD_TRY(hipEventRecord(p->ev[1], s));
-  p->recorded[0] = true;
-  rc = brt_pdd_interpolate(p, u, stream);
-  if (rc != BRT_OK) return rc;
-  return brt_pdd_solve(p, p->g.n_steps, field, stream);
+    if (!p->plan) {
+      std::vector<double> xy(2 * p->n_nodes), t(p->n_nodes);
+      std::vector<uint64_t> nt(p->n_nodes, trees_per_node);
+      uint64_t n = 0;
+      brt_pdd_nodes(p, xy.data(), t.data(), &n);
+      brt_points pts{};
+      pts.struct_size = sizeof(pts);
+      pts.n = (uint32_t)n;
+      pts.x = xy.data();
+      pts.t = t.data();
+      pts.n_trees = nt.data();
+      const int rc = brt_plan_create(p->ctx, 1, &p->prob, mc, &pts, &p->plan);
+      if (rc != BRT_OK) {
+        p->plan = nullptr;
+        return rc;
+      }
+      p->plan_mc = *mc;
+      p->plan_trees = trees_per_node;
+    }
+    double* u = node_u ? node_u : p->d_node_u;
+    brt_out o{};
+    o.struct_size = sizeof(o);
+    o.u = u;
+    PDD_TRY(hipEventRecord(p->ev[0], s));
+    int rc = brt_plan_execute(p->plan, &o, stream);
+    if (rc != BRT_OK) return rc;
+    PDD_TRY(hipEventRecord(p->ev[1], s));
+    p->recorded[0] = true;
+    rc = brt_pdd_interpolate(p, u, stream);
+    if (rc != BRT_OK) return rc;
+    return brt_pdd_solve(p, p->g.n_steps, field, stream);
+  });
 }
 
 int brt_pdd_get_barrier(brt_pdd* p, uint32_t* groups, uint32_t* die_local) {
-  if (!p || !groups || !die_local) return set_error(BRT_E_ARG, "brt_pdd_get_barrier: NULL argument");
-  *groups = *die_local = 0;
-  if (!p->recorded[2]) return BRT_OK;
-  PDD_TRY(hipEventSynchronize(p->ev[5]));
-  uint32_t w[kSyncWords];
-  PDD_TRY(hipMemcpy(w, p->d_sync, sizeof(w), hipMemcpyDeviceToHost));
-  *groups = p->last_groups;
-  for (uint32_t g = 0; g < p->last_groups; ++g) *die_local += __builtin_popcount(w[5 + 2 * g]) == 1 ? 1u : 0u;
-  return BRT_OK;
+  return brt::api_guard("brt_pdd_get_barrier", [&]() -> int {
+    if (!p || !groups || !die_local) return set_error(BRT_E_ARG, "brt_pdd_get_barrier: NULL argument");
+    *groups = *die_local = 0;
+    if (!p->recorded[2]) return BRT_OK;
+    PDD_TRY(hipEventSynchronize(p->ev[5]));
+    uint32_t w[kSyncWords];
+    PDD_TRY(hipMemcpy(w, p->d_sync, sizeof(w), hipMemcpyDeviceToHost));
+    *groups = p->last_groups;
+    for (uint32_t g = 0; g < p->last_groups; ++g) *die_local += __builtin_popcount(w[5 + 2 * g]) == 1 ? 1u : 0u;
+    return BRT_OK;
+  });
 }
 
 int brt_pdd_get_timing(brt_pdd* p, double* ms) {
-  if (!p || !ms) return set_error(BRT_E_ARG, "brt_pdd_get_timing: NULL argument");
-  for (int k = 0; k < 3; ++k) {
-    ms[k] = 0.0;
-    if (!p->recorded[k]) continue;
-    PDD_TRY(hipEventSynchronize(p->ev[2 * k + 1]));
-    float v = 0.f;
-    PDD_TRY(hipEventElapsedTime(&v, p->ev[2 * k], p->ev[2 * k + 1]));
-    ms[k] = v;
-  }
-  p->recorded[0] = false;
-  uint32_t abort_word = 0;
-  PDD_TRY(hipMemcpy(&abort_word, p->d_sync + 2, 4, hipMemcpyDeviceToHost));
-  if (abort_word) return set_error(BRT_E_DEVICE, "pdd: the solver's grid barrier timed out");
-  return BRT_OK;
+  return brt::api_guard("brt_pdd_get_timing", [&]() -> int {
+    if (!p || !ms) return set_error(BRT_E_ARG, "brt_pdd_get_timing: NULL argument");
+    for (int k = 0; k < 3; ++k) {
+      ms[k] = 0.0;
+      if (!p->recorded[k]) continue;
+      PDD_TRY(hipEventSynchronize(p->ev[2 * k + 1]));
+      float v = 0.f;
+      PDD_TRY(hipEventElapsedTime(&v, p->ev[2 * k], p->ev[2 * k + 1]));
+      ms[k] = v;
+    }
+    p->recorded[0] = false;
+    uint32_t abort_word = 0;
+    PDD_TRY(hipMemcpy(&abort_word, p->d_sync + 2, 4, hipMemcpyDeviceToHost));
+    if (abort_word) return set_error(BRT_E_DEVICE, "pdd: the solver's grid barrier timed out");
+    return BRT_OK;
+  });
 }
 
 void brt_pdd_destroy(brt_pdd* p) { pdd_free(p); }

@@ -25,6 +25,7 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <mutex>
@@ -35,6 +36,7 @@
 #include <vector>
 
 #include "brt.h"
+#include "brt_api.h"
 #include "brt_internal.h"
 
 using namespace brt;
@@ -122,7 +124,7 @@ struct brt_server {
   bool stop = false;     // finish the admitted requests, then exit
   bool abandon = false;  // exit at the next tick boundary
   int engine_rc = BRT_OK;
-  std::string engine_msg;
+  char engine_msg[512] = {};  // the engine's error (a fixed buffer: recording it never allocates)
   std::thread engine;
   // statistics
   std::vector<double> latencies;
@@ -393,16 +395,16 @@ void admit(brt_server* s) {
 void engine_fail(brt_server* s, int rc) {
   std::lock_guard<std::mutex> lk(s->mu);
   s->engine_rc = rc;
-  s->engine_msg = brt_last_error();
+  std::snprintf(s->engine_msg, sizeof(s->engine_msg), "%s", brt_last_error());
   s->stop = true;
   s->done_cv.notify_all();
 }
 
-void engine_main(brt_server* s) {
+void engine_loop(brt_server* s) {
   if (hipSetDevice(s->device) != hipSuccess) {
     std::lock_guard<std::mutex> lk(s->mu);
     s->engine_rc = BRT_E_DEVICE;
-    s->engine_msg = "server engine: hipSetDevice failed";
+    std::snprintf(s->engine_msg, sizeof(s->engine_msg), "%s", "server engine: hipSetDevice failed");
     s->done_cv.notify_all();
     return;
   }
@@ -434,233 +436,255 @@ void engine_main(brt_server* s) {
   }
 }
 
+// The engine thread: a C++ exception (a failed host allocation in the bookkeeping) stops the server
+// with an error that submit and poll then report, instead of terminating the process.
+void engine_main(brt_server* s) {
+  try {
+    engine_loop(s);
+  } catch (const std::bad_alloc&) {
+    engine_fail(s, set_error(BRT_E_NOMEM, "server engine: host allocation failed"));
+  } catch (...) {
+    engine_fail(s, set_error(BRT_E_ARG, "server engine: internal error"));
+  }
+}
+
 }  // namespace
 
 extern "C" {
 
 int brt_server_create(brt_ctx* ctx, const brt_server_opts* o, brt_server** out) {
-  if (!ctx || !o || !out) return set_error(BRT_E_ARG, "brt_server_create: NULL argument");
-  *out = nullptr;
-  if (o->struct_size != sizeof(brt_server_opts)) return set_error(BRT_E_ARG, "brt_server_opts.struct_size mismatch");
-  if (o->dim != 1 && o->dim != 2) return set_error(BRT_E_ARG, "server: dim must be 1 or 2");
-  if (o->u0_kind > BRT_U0_COS2_BUMP) return set_error(BRT_E_ARG, "server: unknown u0_kind");
-  const brt_mc& mc = o->mc;
-  if (mc.struct_size != sizeof(brt_mc) || (mc.precision != 32 && mc.precision != 64) || !(mc.lambda > 0.0) ||
-      mc.max_order > 126 || mc.node_cap < 1 || mc.node_cap > kMaxNodeCap || mc.pade_L + mc.pade_M > mc.max_order ||
-      mc.pade_M > 16 || mc.strategy > BRT_STRATEGY_B)
-    return set_error(BRT_E_ARG, "server: invalid Monte Carlo parameters");
-  if (o->max_points < 1 || o->max_points > (1u << 20)) return set_error(BRT_E_ARG, "server: max_points must be 1..2^20");
-  if (o->round_trees < kSegTrees || o->round_trees % kSegTrees || o->round_trees > (1u << 22))
-    return set_error(BRT_E_ARG, "server: round_trees must be a multiple of %u, at most 2^22", kSegTrees);
-  if (o->max_trees < o->round_trees || o->max_trees % o->round_trees || o->max_trees > (1u << 26))
-    return set_error(BRT_E_ARG, "server: max_trees must be a multiple of round_trees, at most 2^26");
-  if (!(o->target_se >= 0.0)) return set_error(BRT_E_ARG, "server: target_se must be >= 0");
-  if (o->queue_cap < 1) return set_error(BRT_E_ARG, "server: queue_cap must be >= 1");
+  return brt::api_guard("brt_server_create", [&]() -> int {
+    if (!ctx || !o || !out) return set_error(BRT_E_ARG, "brt_server_create: NULL argument");
+    *out = nullptr;
+    if (o->struct_size != sizeof(brt_server_opts)) return set_error(BRT_E_ARG, "brt_server_opts.struct_size mismatch");
+    if (o->dim != 1 && o->dim != 2) return set_error(BRT_E_ARG, "server: dim must be 1 or 2");
+    if (o->u0_kind > BRT_U0_COS2_BUMP) return set_error(BRT_E_ARG, "server: unknown u0_kind");
+    const brt_mc& mc = o->mc;
+    if (mc.struct_size != sizeof(brt_mc) || (mc.precision != 32 && mc.precision != 64) || !(mc.lambda > 0.0) ||
+        mc.max_order > 126 || mc.node_cap < 1 || mc.node_cap > kMaxNodeCap || mc.pade_L + mc.pade_M > mc.max_order ||
+        mc.pade_M > 16 || mc.strategy > BRT_STRATEGY_B)
+      return set_error(BRT_E_ARG, "server: invalid Monte Carlo parameters");
+    if (o->max_points < 1 || o->max_points > (1u << 20)) return set_error(BRT_E_ARG, "server: max_points must be 1..2^20");
+    if (o->round_trees < kSegTrees || o->round_trees % kSegTrees || o->round_trees > (1u << 22))
+      return set_error(BRT_E_ARG, "server: round_trees must be a multiple of %u, at most 2^22", kSegTrees);
+    if (o->max_trees < o->round_trees || o->max_trees % o->round_trees || o->max_trees > (1u << 26))
+      return set_error(BRT_E_ARG, "server: max_trees must be a multiple of round_trees, at most 2^26");
+    if (!(o->target_se >= 0.0)) return set_error(BRT_E_ARG, "server: target_se must be >= 0");
+    if (o->queue_cap < 1) return set_error(BRT_E_ARG, "server: queue_cap must be >= 1");
 
-  brt_server* s = new (std::nothrow) brt_server;
-  if (!s) return set_error(BRT_E_NOMEM, "server: host allocation");
-  s->opts = *o;
-  brt_launch lc{};
-  lc.struct_size = sizeof(lc);
-  brt_get_launch(ctx, &lc);
-  s->wpb = (int)lc.waves_per_block;
-  hipDeviceProp_t prop;
-  if (hipGetDevice(&s->device) != hipSuccess || hipGetDeviceProperties(&prop, s->device) != hipSuccess) {
-    server_free(s);
-    return set_error(BRT_E_DEVICE, "server: device query failed");
-  }
-  s->n_cu = prop.multiProcessorCount;
-  s->B = mc.max_order + 2;
-  s->NB = s->B + 3;
-  s->segs_per_round = o->round_trees / kSegTrees;
-  s->max_segs = o->max_trees / kSegTrees;
-  s->chunks_per_round = o->round_trees / kChunkTrees;
-  const uint32_t needed = mc.prune ? std::max(1u, mc.max_order) : kMaxDepthUnpruned;
-  s->lds_depth = (int)std::min(needed, lc.stack_depth ? lc.stack_depth : kDefaultLdsLevels);
-  s->spill_depth = (int)(needed - (uint32_t)s->lds_depth);
-  // resident blocks per CU for every launch-group size (its problem table shares the block's LDS); a
-  // block size that does not fit one problem's table is reduced
-  for (int k = 1; k <= kMaxProblems; ++k) {
-    int maxb = walk_max_blocks_per_cu((int)mc.precision, (int)o->dim, (int)o->u0_kind, k, s->lds_depth, s->wpb,
-                                      (int)mc.strategy);
-    while (k == 1 && maxb <= 0 && s->wpb > 1) {
-      s->wpb -= 1;
-      maxb = walk_max_blocks_per_cu((int)mc.precision, (int)o->dim, (int)o->u0_kind, k, s->lds_depth, s->wpb,
-                                    (int)mc.strategy);
-    }
-    if (maxb <= 0) {
+    brt_server* s = new (std::nothrow) brt_server;
+    if (!s) return set_error(BRT_E_NOMEM, "server: host allocation");
+    s->opts = *o;
+    brt_launch lc{};
+    lc.struct_size = sizeof(lc);
+    brt_get_launch(ctx, &lc);
+    s->wpb = (int)lc.waves_per_block;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&s->device) != hipSuccess || hipGetDeviceProperties(&prop, s->device) != hipSuccess) {
       server_free(s);
-      return set_error(BRT_E_ARG, "server: walker launch for %d problems does not fit the device", k);
+      return set_error(BRT_E_DEVICE, "server: device query failed");
     }
-    s->grid_k[k] = maxb * s->n_cu;
-  }
-  s->grid = *std::max_element(s->grid_k + 1, s->grid_k + kMaxProblems + 1);  // sizes the stack spill area
-  const size_t P = o->max_points;
-  const size_t R = o->round_trees;
-  int rc = BRT_OK;
-  s->max_groups = (uint32_t)P;  // at most one group per request
-  const size_t pb = pde_bytes((int)mc.precision);
-  const size_t spill = s->spill_depth > 0 ? (size_t)s->grid * s->wpb * kWave * s->spill_depth *
-                                                stack_entry_size((int)mc.precision, (int)o->dim)
-                                          : 0;
-  for (Lane& L : s->lanes) {
-    rc = rc ? rc : (hipStreamCreate(&L.stream) == hipSuccess ? BRT_OK : set_error(BRT_E_DEVICE, "server: stream"));
-    rc = rc ? rc : (hipEventCreate(&L.ev_start) == hipSuccess ? BRT_OK : set_error(BRT_E_DEVICE, "server: event"));
-    rc = rc ? rc : (hipEventCreate(&L.ev_done) == hipSuccess ? BRT_OK : set_error(BRT_E_DEVICE, "server: event"));
-    rc = rc ? rc : dev_alloc(reinterpret_cast<unsigned char**>(&L.d_pdes), P * pb);  // one problem per request
-    rc = rc ? rc : dev_alloc(&L.d_points, P);
-    rc = rc ? rc : dev_alloc(&L.d_chunks, P * s->chunks_per_round);
-    rc = rc ? rc : dev_alloc(&L.d_segs, P * s->segs_per_round);
-    rc = rc ? rc : dev_alloc(&L.d_counter, (size_t)s->max_groups * kCounterStride);
-    rc = rc ? rc : dev_alloc(&L.d_depth, s->max_groups);
-    rc = rc ? rc : dev_alloc(&L.d_tree_f, P * R);
-    rc = rc ? rc : dev_alloc(&L.d_tree_meta, P * R);
-    if (!rc && spill) rc = dev_alloc(reinterpret_cast<unsigned char**>(&L.d_spill), spill);
-    rc = rc ? rc : host_alloc(&L.h_points, P);
-    rc = rc ? rc : host_alloc(&L.h_chunks, P * s->chunks_per_round);
-    rc = rc ? rc : host_alloc(&L.h_segs, P * s->segs_per_round);
-    rc = rc ? rc : host_alloc(&L.h_pdes, P * pb);
-    rc = rc ? rc : host_alloc(&L.h_u, P);
-    rc = rc ? rc : host_alloc(&L.h_se, P);
-    rc = rc ? rc : host_alloc(&L.h_coef, P * s->B);
-    rc = rc ? rc : host_alloc(&L.h_nodes, P);
-    rc = rc ? rc : host_alloc(&L.h_flags, P);
-  }
-  rc = rc ? rc : dev_alloc(&s->d_partials, P * s->max_segs * s->NB);
-  rc = rc ? rc : dev_alloc(&s->d_seg_nodes, P * s->max_segs);
-  rc = rc ? rc : dev_alloc(&s->d_u, P);
-  rc = rc ? rc : dev_alloc(&s->d_se, P);
-  rc = rc ? rc : dev_alloc(&s->d_coef, P * s->B);
-  rc = rc ? rc : dev_alloc(&s->d_nodes, P);
-  rc = rc ? rc : dev_alloc(&s->d_flags, P);
-  if (rc) {
-    server_free(s);
-    return rc;
-  }
-  s->free_slots.resize(P);
-  for (size_t i = 0; i < P; ++i) s->free_slots[i] = (uint32_t)(P - 1 - i);
-  s->engine = std::thread(engine_main, s);
-  *out = s;
-  return BRT_OK;
+    s->n_cu = prop.multiProcessorCount;
+    s->B = mc.max_order + 2;
+    s->NB = s->B + 3;
+    s->segs_per_round = o->round_trees / kSegTrees;
+    s->max_segs = o->max_trees / kSegTrees;
+    s->chunks_per_round = o->round_trees / kChunkTrees;
+    const uint32_t needed = mc.prune ? std::max(1u, mc.max_order) : kMaxDepthUnpruned;
+    s->lds_depth = (int)std::min(needed, lc.stack_depth ? lc.stack_depth : kDefaultLdsLevels);
+    s->spill_depth = (int)(needed - (uint32_t)s->lds_depth);
+    // resident blocks per CU for every launch-group size (its problem table shares the block's LDS); a
+    // block size that does not fit one problem's table is reduced
+    for (int k = 1; k <= kMaxProblems; ++k) {
+      int maxb = walk_max_blocks_per_cu((int)mc.precision, (int)o->dim, (int)o->u0_kind, k, s->lds_depth, s->wpb,
+                                        (int)mc.strategy);
+      while (k == 1 && maxb <= 0 && s->wpb > 1) {
+        s->wpb -= 1;
+        maxb = walk_max_blocks_per_cu((int)mc.precision, (int)o->dim, (int)o->u0_kind, k, s->lds_depth, s->wpb,
+                                      (int)mc.strategy);
+      }
+      if (maxb <= 0) {
+        server_free(s);
+        return set_error(BRT_E_ARG, "server: walker launch for %d problems does not fit the device", k);
+      }
+      s->grid_k[k] = maxb * s->n_cu;
+    }
+    s->grid = *std::max_element(s->grid_k + 1, s->grid_k + kMaxProblems + 1);  // sizes the stack spill area
+    const size_t P = o->max_points;
+    const size_t R = o->round_trees;
+    int rc = BRT_OK;
+    s->max_groups = (uint32_t)P;  // at most one group per request
+    const size_t pb = pde_bytes((int)mc.precision);
+    const size_t spill = s->spill_depth > 0 ? (size_t)s->grid * s->wpb * kWave * s->spill_depth *
+                                                  stack_entry_size((int)mc.precision, (int)o->dim)
+                                            : 0;
+    for (Lane& L : s->lanes) {
+      rc = rc ? rc : (hipStreamCreate(&L.stream) == hipSuccess ? BRT_OK : set_error(BRT_E_DEVICE, "server: stream"));
+      rc = rc ? rc : (hipEventCreate(&L.ev_start) == hipSuccess ? BRT_OK : set_error(BRT_E_DEVICE, "server: event"));
+      rc = rc ? rc : (hipEventCreate(&L.ev_done) == hipSuccess ? BRT_OK : set_error(BRT_E_DEVICE, "server: event"));
+      rc = rc ? rc : dev_alloc(reinterpret_cast<unsigned char**>(&L.d_pdes), P * pb);  // one problem per request
+      rc = rc ? rc : dev_alloc(&L.d_points, P);
+      rc = rc ? rc : dev_alloc(&L.d_chunks, P * s->chunks_per_round);
+      rc = rc ? rc : dev_alloc(&L.d_segs, P * s->segs_per_round);
+      rc = rc ? rc : dev_alloc(&L.d_counter, (size_t)s->max_groups * kCounterStride);
+      rc = rc ? rc : dev_alloc(&L.d_depth, s->max_groups);
+      rc = rc ? rc : dev_alloc(&L.d_tree_f, P * R);
+      rc = rc ? rc : dev_alloc(&L.d_tree_meta, P * R);
+      if (!rc && spill) rc = dev_alloc(reinterpret_cast<unsigned char**>(&L.d_spill), spill);
+      rc = rc ? rc : host_alloc(&L.h_points, P);
+      rc = rc ? rc : host_alloc(&L.h_chunks, P * s->chunks_per_round);
+      rc = rc ? rc : host_alloc(&L.h_segs, P * s->segs_per_round);
+      rc = rc ? rc : host_alloc(&L.h_pdes, P * pb);
+      rc = rc ? rc : host_alloc(&L.h_u, P);
+      rc = rc ? rc : host_alloc(&L.h_se, P);
+      rc = rc ? rc : host_alloc(&L.h_coef, P * s->B);
+      rc = rc ? rc : host_alloc(&L.h_nodes, P);
+      rc = rc ? rc : host_alloc(&L.h_flags, P);
+    }
+    rc = rc ? rc : dev_alloc(&s->d_partials, P * s->max_segs * s->NB);
+    rc = rc ? rc : dev_alloc(&s->d_seg_nodes, P * s->max_segs);
+    rc = rc ? rc : dev_alloc(&s->d_u, P);
+    rc = rc ? rc : dev_alloc(&s->d_se, P);
+    rc = rc ? rc : dev_alloc(&s->d_coef, P * s->B);
+    rc = rc ? rc : dev_alloc(&s->d_nodes, P);
+    rc = rc ? rc : dev_alloc(&s->d_flags, P);
+    if (rc) {
+      server_free(s);
+      return rc;
+    }
+    s->free_slots.resize(P);
+    for (size_t i = 0; i < P; ++i) s->free_slots[i] = (uint32_t)(P - 1 - i);
+    s->engine = std::thread(engine_main, s);
+    *out = s;
+    return BRT_OK;
+  });
 }
 
 int brt_server_submit(brt_server* s, const brt_request* q, uint64_t* ticket) {
-  if (!s || !q || !ticket) return set_error(BRT_E_ARG, "brt_server_submit: NULL argument");
-  if (q->struct_size != sizeof(brt_request)) return set_error(BRT_E_ARG, "brt_request.struct_size mismatch");
-  if (!q->problem || !q->x || !q->t) return set_error(BRT_E_ARG, "brt_server_submit: NULL array");
-  if (q->n < 1 || q->n > kMaxRequestPoints || q->n > s->opts.max_points)
-    return set_error(BRT_E_ARG, "brt_server_submit: 1..%u points per request", std::min(kMaxRequestPoints, s->opts.max_points));
-  if (q->stream_id >= (1u << 22)) return set_error(BRT_E_ARG, "brt_server_submit: stream_id must be < 2^22");
-  int rc = brt_problem_check(q->problem, &s->opts.mc);
-  if (rc) return rc;
-  if (q->problem->dim != s->opts.dim || q->problem->u0_kind != s->opts.u0_kind)
-    return set_error(BRT_E_ARG, "brt_server_submit: problem dim/u0_kind differ from the server's");
-  for (uint32_t i = 0; i < q->n; ++i)
-    if (!(q->t[i] >= 0.0) || !std::isfinite(q->t[i])) return set_error(BRT_E_ARG, "brt_server_submit: bad t");
-  Request* r = new (std::nothrow) Request;
-  if (!r) return set_error(BRT_E_NOMEM, "brt_server_submit: host allocation");
-  r->prob = *q->problem;
-  r->norm = normalize(r->prob, s->opts.mc);
-  r->stream_id = q->stream_id;
-  r->n = q->n;
-  r->x.assign(q->x, q->x + (size_t)q->n * s->opts.dim);
-  r->t.assign(q->t, q->t + q->n);
-  r->slot.assign(q->n, 0u);
-  r->rounds.assign(q->n, 0u);
-  r->done.assign(q->n, 0u);
-  r->u.assign(q->n, 0.0);
-  r->se.assign(q->n, 0.0);
-  r->flags.assign(q->n, 0u);
-  r->coef.assign((size_t)q->n * s->B, 0.0);
-  std::lock_guard<std::mutex> lk(s->mu);
-  if (s->engine_rc) {
-    delete r;
-    return set_error(s->engine_rc, "server stopped: %s", s->engine_msg.c_str());
-  }
-  if (s->queue.size() >= s->opts.queue_cap) {
-    delete r;
-    s->rejected += 1;
-    return set_error(BRT_E_BUSY, "server: admission queue full (%u requests)", s->opts.queue_cap);
-  }
-  r->ticket = s->next_ticket++;
-  r->arrival = Clock::now();
-  if (!s->any_submit) {
-    s->any_submit = true;
-    s->first_submit = r->arrival;
-  }
-  s->submitted += 1;
-  s->queue.push_back(r);
-  s->requests[r->ticket] = r;
-  *ticket = r->ticket;
-  s->cv.notify_all();
-  return BRT_OK;
+  return brt::api_guard("brt_server_submit", [&]() -> int {
+    if (!s || !q || !ticket) return set_error(BRT_E_ARG, "brt_server_submit: NULL argument");
+    if (q->struct_size != sizeof(brt_request)) return set_error(BRT_E_ARG, "brt_request.struct_size mismatch");
+    if (!q->problem || !q->x || !q->t) return set_error(BRT_E_ARG, "brt_server_submit: NULL array");
+    if (q->n < 1 || q->n > kMaxRequestPoints || q->n > s->opts.max_points)
+      return set_error(BRT_E_ARG, "brt_server_submit: 1..%u points per request", std::min(kMaxRequestPoints, s->opts.max_points));
+    if (q->stream_id >= (1u << 22)) return set_error(BRT_E_ARG, "brt_server_submit: stream_id must be < 2^22");
+    int rc = brt_problem_check(q->problem, &s->opts.mc);
+    if (rc) return rc;
+    if (q->problem->dim != s->opts.dim || q->problem->u0_kind != s->opts.u0_kind)
+      return set_error(BRT_E_ARG, "brt_server_submit: problem dim/u0_kind differ from the server's");
+    for (uint32_t i = 0; i < q->n; ++i)
+      if (!(q->t[i] >= 0.0) || !std::isfinite(q->t[i])) return set_error(BRT_E_ARG, "brt_server_submit: bad t");
+    Request* r = new (std::nothrow) Request;
+    if (!r) return set_error(BRT_E_NOMEM, "brt_server_submit: host allocation");
+    r->prob = *q->problem;
+    r->norm = normalize(r->prob, s->opts.mc);
+    r->stream_id = q->stream_id;
+    r->n = q->n;
+    r->x.assign(q->x, q->x + (size_t)q->n * s->opts.dim);
+    r->t.assign(q->t, q->t + q->n);
+    r->slot.assign(q->n, 0u);
+    r->rounds.assign(q->n, 0u);
+    r->done.assign(q->n, 0u);
+    r->u.assign(q->n, 0.0);
+    r->se.assign(q->n, 0.0);
+    r->flags.assign(q->n, 0u);
+    r->coef.assign((size_t)q->n * s->B, 0.0);
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->engine_rc) {
+      delete r;
+      return set_error(s->engine_rc, "server stopped: %s", s->engine_msg);
+    }
+    if (s->queue.size() >= s->opts.queue_cap) {
+      delete r;
+      s->rejected += 1;
+      return set_error(BRT_E_BUSY, "server: admission queue full (%u requests)", s->opts.queue_cap);
+    }
+    r->ticket = s->next_ticket++;
+    r->arrival = Clock::now();
+    if (!s->any_submit) {
+      s->any_submit = true;
+      s->first_submit = r->arrival;
+    }
+    s->submitted += 1;
+    s->queue.push_back(r);
+    s->requests[r->ticket] = r;
+    *ticket = r->ticket;
+    s->cv.notify_all();
+    return BRT_OK;
+  });
 }
 
 int brt_server_poll(brt_server* s, uint64_t ticket, brt_result* out, int* done) {
-  if (!s || !done) return set_error(BRT_E_ARG, "brt_server_poll: NULL argument");
-  if (out && out->struct_size != sizeof(brt_result)) return set_error(BRT_E_ARG, "brt_result.struct_size mismatch");
-  std::lock_guard<std::mutex> lk(s->mu);
-  auto it = s->requests.find(ticket);
-  if (it == s->requests.end()) return set_error(BRT_E_STATE, "brt_server_poll: unknown ticket %llu", (unsigned long long)ticket);
-  Request* r = it->second;
-  *done = r->complete ? 1 : 0;
-  if (!r->complete) {
-    if (s->engine_rc) return set_error(s->engine_rc, "server stopped: %s", s->engine_msg.c_str());
-    return BRT_OK;
-  }
-  if (out) {
-    const uint32_t R = s->opts.round_trees;
-    for (uint32_t i = 0; i < r->n; ++i) {
-      if (out->u) out->u[i] = r->u[i];
-      if (out->se) out->se[i] = r->se[i];
-      if (out->flags) out->flags[i] = r->flags[i];
-      if (out->trees) out->trees[i] = (uint64_t)r->rounds[i] * R;
+  return brt::api_guard("brt_server_poll", [&]() -> int {
+    if (!s || !done) return set_error(BRT_E_ARG, "brt_server_poll: NULL argument");
+    if (out && out->struct_size != sizeof(brt_result)) return set_error(BRT_E_ARG, "brt_result.struct_size mismatch");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->requests.find(ticket);
+    if (it == s->requests.end()) return set_error(BRT_E_STATE, "brt_server_poll: unknown ticket %llu", (unsigned long long)ticket);
+    Request* r = it->second;
+    *done = r->complete ? 1 : 0;
+    if (!r->complete) {
+      if (s->engine_rc) return set_error(s->engine_rc, "server stopped: %s", s->engine_msg);
+      return BRT_OK;
     }
-    if (out->coef) std::memcpy(out->coef, r->coef.data(), r->coef.size() * sizeof(double));
-    out->latency_s = std::chrono::duration<double>(r->finished_at - r->arrival).count();
-  }
-  s->requests.erase(it);
-  delete r;
-  return BRT_OK;
+    if (out) {
+      const uint32_t R = s->opts.round_trees;
+      for (uint32_t i = 0; i < r->n; ++i) {
+        if (out->u) out->u[i] = r->u[i];
+        if (out->se) out->se[i] = r->se[i];
+        if (out->flags) out->flags[i] = r->flags[i];
+        if (out->trees) out->trees[i] = (uint64_t)r->rounds[i] * R;
+      }
+      if (out->coef) std::memcpy(out->coef, r->coef.data(), r->coef.size() * sizeof(double));
+      out->latency_s = std::chrono::duration<double>(r->finished_at - r->arrival).count();
+    }
+    s->requests.erase(it);
+    delete r;
+    return BRT_OK;
+  });
 }
 
 int brt_server_drain(brt_server* s, double timeout_s) {
-  if (!s) return set_error(BRT_E_ARG, "brt_server_drain: NULL server");
-  std::unique_lock<std::mutex> lk(s->mu);
-  const auto deadline = Clock::now() + std::chrono::duration<double>(timeout_s);
-  while (!s->queue.empty() || s->n_active > 0) {
-    if (s->engine_rc) return set_error(s->engine_rc, "server stopped: %s", s->engine_msg.c_str());
-    if (s->done_cv.wait_until(lk, deadline) == std::cv_status::timeout && (!s->queue.empty() || s->n_active > 0))
-      return set_error(BRT_E_BUSY, "brt_server_drain: timed out");
-  }
-  return s->engine_rc;
+  return brt::api_guard("brt_server_drain", [&]() -> int {
+    if (!s) return set_error(BRT_E_ARG, "brt_server_drain: NULL server");
+    std::unique_lock<std::mutex> lk(s->mu);
+    const auto deadline = Clock::now() + std::chrono::duration<double>(timeout_s);
+    while (!s->queue.empty() || s->n_active > 0) {
+      if (s->engine_rc) return set_error(s->engine_rc, "server stopped: %s", s->engine_msg);
+      if (s->done_cv.wait_until(lk, deadline) == std::cv_status::timeout && (!s->queue.empty() || s->n_active > 0))
+        return set_error(BRT_E_BUSY, "brt_server_drain: timed out");
+    }
+    return s->engine_rc;
+  });
 }
 
 int brt_server_stats_get(brt_server* s, brt_server_stats* o) {
-  if (!s || !o || o->struct_size != sizeof(brt_server_stats)) return set_error(BRT_E_ARG, "brt_server_stats_get: bad arguments");
-  std::lock_guard<std::mutex> lk(s->mu);
-  std::vector<double> l = s->latencies;
-  std::sort(l.begin(), l.end());
-  auto pct = [&](double q) {
-    if (l.empty()) return 0.0;
-    const double pos = q * (double)(l.size() - 1);
-    const size_t i = (size_t)pos;
-    const double f = pos - (double)i;
-    return i + 1 < l.size() ? l[i] * (1 - f) + l[i + 1] * f : l[i];
-  };
-  o->submitted = s->submitted;
-  o->completed = s->completed;
-  o->rejected = s->rejected;
-  o->ticks = s->ticks;
-  o->trees = s->trees;
-  o->nodes = s->nodes;
-  o->p50_latency_s = pct(0.50);
-  o->p99_latency_s = pct(0.99);
-  o->mean_latency_s = l.empty() ? 0.0 : std::accumulate(l.begin(), l.end(), 0.0) / (double)l.size();
-  o->busy_s = s->busy_s;
-  o->span_s = (s->any_submit && s->completed) ? std::chrono::duration<double>(s->last_complete - s->first_submit).count() : 0.0;
-  o->trees_per_s = o->span_s > 0 ? (double)s->trees / o->span_s : 0.0;
-  return BRT_OK;
+  return brt::api_guard("brt_server_stats_get", [&]() -> int {
+    if (!s || !o || o->struct_size != sizeof(brt_server_stats)) return set_error(BRT_E_ARG, "brt_server_stats_get: bad arguments");
+    std::lock_guard<std::mutex> lk(s->mu);
+    std::vector<double> l = s->latencies;
+    std::sort(l.begin(), l.end());
+    auto pct = [&](double q) {
+      if (l.empty()) return 0.0;
+      const double pos = q * (double)(l.size() - 1);
+      const size_t i = (size_t)pos;
+      const double f = pos - (double)i;
+      return i + 1 < l.size() ? l[i] * (1 - f) + l[i + 1] * f : l[i];
+    };
+    o->submitted = s->submitted;
+    o->completed = s->completed;
+    o->rejected = s->rejected;
+    o->ticks = s->ticks;
+    o->trees = s->trees;
+    o->nodes = s->nodes;
+    o->p50_latency_s = pct(0.50);
+    o->p99_latency_s = pct(0.99);
+    o->mean_latency_s = l.empty() ? 0.0 : std::accumulate(l.begin(), l.end(), 0.0) / (double)l.size();
+    o->busy_s = s->busy_s;
+    o->span_s = (s->any_submit && s->completed) ? std::chrono::duration<double>(s->last_complete - s->first_submit).count() : 0.0;
+    o->trees_per_s = o->span_s > 0 ? (double)s->trees / o->span_s : 0.0;
+    return BRT_OK;
+  });
 }
 
 void brt_server_destroy(brt_server* s) {
