@@ -25,6 +25,8 @@
  *    never frees them.  Streams are hipStream_t passed as void* (NULL = the
  *    null stream).
  *  - The library never calls exit(); device faults surface as BRT_E_DEVICE.
+ *    No C++ exception crosses the interface: a failed host allocation inside
+ *    a call returns BRT_E_NOMEM.
  *
  * Randomness (the documented stream; any implementation of the method that
  * follows it walks the same trees): one Philox4x32-10 block (Salmon et al.,
