@@ -45,7 +45,7 @@ METRIC = "random trees/sec at fixed error vs oracle; p50/p99 point-query latency
 OPS_PER_NODE = {1: 114, 2: 116}
 # FP32 vector peak of MI355X expressed in operations: 157.3 TFLOP/s counts an FMA as 2 flops, i.e.
 # 78.6 T lane-operations/s (256 CUs x 4 SIMDs x 32 lanes per cycle x 2.4 GHz).  Plain, non-packed VALU
-# code reaches it: a microbenchmark of independent FMA chains measured 62.6 T FMA/s on the box.
+# code reaches it: a microbenchmark of independent FMA chains measured 62.6 T FMA/s on an MI355X.
 PEAK_TOPS = 78.6
 
 
@@ -682,7 +682,7 @@ def main():
                     args.pmc_which)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+        print("bench.py measures one GPU only: the library has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
         sys.exit(2)
 
