@@ -103,7 +103,7 @@ struct brt_server {
   int device = 0;
   int n_cu = 0;
   brt_server_opts opts{};
-  uint32_t B = 0, NB = 0, segs_per_round = 0, max_segs = 0, chunks_per_round = 0, max_groups = 0;
+  uint32_t B = 0, NB = 0, seg_trees = 0, segs_per_round = 0, max_segs = 0, chunks_per_round = 0, max_groups = 0;
   int grid = 0, wpb = 4, lds_depth = 0, spill_depth = 0;
   int grid_k[kMaxProblems + 1] = {};  // resident walker blocks for a launch group of k problems
   Lane lanes[kLanes];
@@ -235,7 +235,7 @@ int issue_tick(brt_server* s, Lane& L) {
       pr.seg_count = (round + 1) * s->segs_per_round;
       pr.out_row = slot;
       for (uint32_t g = 0; g < s->segs_per_round; ++g)
-        L.h_segs[ns++] = Segment{np, g * kSegTrees, (g + 1) * kSegTrees, slot * s->max_segs + round * s->segs_per_round + g};
+        L.h_segs[ns++] = Segment{np, g * s->seg_trees, (g + 1) * s->seg_trees, slot * s->max_segs + round * s->segs_per_round + g};
       ++np;
     }
     // chunks interleaved in cost order: all points' first chunks, then their second chunks, ...
@@ -487,8 +487,13 @@ int brt_server_create(brt_ctx* ctx, const brt_server_opts* o, brt_server** out) 
     s->n_cu = prop.multiProcessorCount;
     s->B = mc.max_order + 2;
     s->NB = s->B + 3;
-    s->segs_per_round = o->round_trees / kSegTrees;
-    s->max_segs = o->max_trees / kSegTrees;
+    // reduction segments: the largest power of two up to the plan's largest segment that divides a
+    // round (one segment per point and round at the default 32768 trees): fewer, longer segments make
+    // both the reduction (fewer per-bin butterflies) and every tick's exact join in the finalize cheaper
+    s->seg_trees = kSegTrees;
+    while (s->seg_trees < kPlanSegMax && o->round_trees % (2 * s->seg_trees) == 0) s->seg_trees *= 2;
+    s->segs_per_round = o->round_trees / s->seg_trees;
+    s->max_segs = o->max_trees / s->seg_trees;
     s->chunks_per_round = o->round_trees / kChunkTrees;
     const uint32_t needed = mc.prune ? std::max(1u, mc.max_order) : kMaxDepthUnpruned;
     s->lds_depth = (int)std::min(needed, lc.stack_depth ? lc.stack_depth : kDefaultLdsLevels);

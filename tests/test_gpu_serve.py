@@ -56,21 +56,25 @@ def _wait(srv, tickets, timeout=120.0):
     return out
 
 
-def test_served_request_matches_oracle(ctx):
+@pytest.mark.parametrize("round_trees", [8192, 32768])
+def test_served_request_matches_oracle(ctx, round_trees):
+    """Two rounds of a served request against the oracle's walk of the same trees.  Rounds of 8192
+    trees are reduced in one 8192-tree segment each, rounds of 32768 in one 32768-tree segment."""
     import paper_2402_06491_amd as brt
 
-    print("\n[case] serve_vs_oracle: 1 request x 6 points, 2 rounds of 8192 trees", flush=True)
+    n = 2 * round_trees
+    print(f"\n[case] serve_vs_oracle: 1 request x 6 points, 2 rounds of {round_trees} trees", flush=True)
     mc = _mc()
-    srv = brt.Server(ctx, 2, "gauss_sum", mc, max_points=64, round_trees=8192, max_trees=16384, target_se=0.0)
+    srv = brt.Server(ctx, 2, "gauss_sum", mc, max_points=64, round_trees=round_trees, max_trees=n, target_se=0.0)
     rng = np.random.default_rng(3)
     prob, x, t = _request(5, 6, rng)
     tk = srv.submit(prob, x, t, stream_id=7)
     res = _wait(srv, {tk: 6})[tk]
     srv.close()
-    assert np.all(res["trees"] == 16384)
+    assert np.all(res["trees"] == n)
     B = mc["max_order"] + 2
     for i in range(6):
-        rec = oracle.walk(prob, mc, np.repeat(x[i:i + 1], 16384, axis=0), t[i], 7 * 1024 + i, np.arange(16384))
+        rec = oracle.walk(prob, mc, np.repeat(x[i:i + 1], n, axis=0), t[i], 7 * 1024 + i, np.arange(n))
         mom = oracle.moments(rec, mc)
         nz = oracle.normalize(prob, mc)
         a, _ = oracle.coefficients(mom, nz.mu, float(t[i]))
