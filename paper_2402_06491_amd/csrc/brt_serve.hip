@@ -104,8 +104,10 @@ struct brt_server {
   int n_cu = 0;
   brt_server_opts opts{};
   uint32_t B = 0, NB = 0, seg_trees = 0, segs_per_round = 0, max_segs = 0, chunks_per_round = 0, max_groups = 0;
-  int grid = 0, wpb = 4, lds_depth = 0, spill_depth = 0;
+  int wpb = 4, lds_depth = 0, spill_depth = 0;
   int grid_k[kMaxProblems + 1] = {};  // resident walker blocks for a launch group of k problems
+  int wpb_k[kMaxProblems + 1] = {};   // and their waves per block
+  size_t spill_threads = 0;           // the spill area's stride: the most threads of any group's launch
   Lane lanes[kLanes];
   // per-slot device state shared by the lanes (each slot belongs to one point of one lane at a time)
   Partial* d_partials = nullptr;
@@ -272,9 +274,10 @@ int issue_tick(brt_server* s, Lane& L) {
     w.cmod = cmod;
     w.stack_depth = (uint32_t)s->lds_depth;
     w.spill_depth = (uint32_t)s->spill_depth;
-    w.n_threads = (uint32_t)(s->grid * s->wpb * kWave);  // the spill area's stride (sized for the largest grid)
+    w.n_threads = (uint32_t)s->spill_threads;
     const int grid = std::max(1, std::min<int>(s->grid_k[kprob], (int)(nc - c0)));
-    SRV_TRY(launch_walk((int)mc.precision, (int)s->opts.dim, (int)s->opts.u0_kind, w, grid, s->wpb, L.stream));
+    SRV_TRY(launch_walk((int)mc.precision, (int)s->opts.dim, (int)s->opts.u0_kind, w, grid, s->wpb_k[kprob],
+                        L.stream));
     ReduceArgs ra{};
     ra.points = L.d_points;
     ra.segs = L.d_segs + s0;
@@ -498,29 +501,38 @@ int brt_server_create(brt_ctx* ctx, const brt_server_opts* o, brt_server** out) 
     const uint32_t needed = mc.prune ? std::max(1u, mc.max_order) : kMaxDepthUnpruned;
     s->lds_depth = (int)std::min(needed, lc.stack_depth ? lc.stack_depth : kDefaultLdsLevels);
     s->spill_depth = (int)(needed - (uint32_t)s->lds_depth);
-    // resident blocks per CU for every launch-group size (its problem table shares the block's LDS); a
-    // block size that does not fit one problem's table is reduced
+    // resident blocks per CU and waves per block for every launch-group size.  One problem takes the
+    // context's block size (reduced if one problem's table does not fit); a group of several takes the
+    // block size with the most resident waves, the larger one on a tie: every block holds its own copy of
+    // the group's problem table in LDS, so larger blocks share a copy among more waves
+    auto fit = [&](int k, int w) {
+      return walk_max_blocks_per_cu((int)mc.precision, (int)o->dim, (int)o->u0_kind, k, s->lds_depth, w,
+                                    (int)mc.strategy);
+    };
     for (int k = 1; k <= kMaxProblems; ++k) {
-      int maxb = walk_max_blocks_per_cu((int)mc.precision, (int)o->dim, (int)o->u0_kind, k, s->lds_depth, s->wpb,
-                                        (int)mc.strategy);
-      while (k == 1 && maxb <= 0 && s->wpb > 1) {
-        s->wpb -= 1;
-        maxb = walk_max_blocks_per_cu((int)mc.precision, (int)o->dim, (int)o->u0_kind, k, s->lds_depth, s->wpb,
-                                      (int)mc.strategy);
+      int maxb = 0, w = 0;
+      if (k == 1) {
+        for (w = s->wpb; w >= 1 && (maxb = fit(k, w)) <= 0;) --w;
+      } else {
+        for (int c = kMaxWalkThreads / kWave; c >= 1; --c) {
+          const int b = fit(k, c);
+          if (b * c > maxb * w) maxb = b, w = c;
+        }
       }
-      if (maxb <= 0) {
+      if (maxb <= 0 || w <= 0) {
         server_free(s);
         return set_error(BRT_E_ARG, "server: walker launch for %d problems does not fit the device", k);
       }
       s->grid_k[k] = maxb * s->n_cu;
+      s->wpb_k[k] = w;
+      s->spill_threads = std::max(s->spill_threads, (size_t)s->grid_k[k] * w * kWave);
     }
-    s->grid = *std::max_element(s->grid_k + 1, s->grid_k + kMaxProblems + 1);  // sizes the stack spill area
     const size_t P = o->max_points;
     const size_t R = o->round_trees;
     int rc = BRT_OK;
     s->max_groups = (uint32_t)P;  // at most one group per request
     const size_t pb = pde_bytes((int)mc.precision);
-    const size_t spill = s->spill_depth > 0 ? (size_t)s->grid * s->wpb * kWave * s->spill_depth *
+    const size_t spill = s->spill_depth > 0 ? s->spill_threads * s->spill_depth *
                                                   stack_entry_size((int)mc.precision, (int)o->dim)
                                             : 0;
     for (Lane& L : s->lanes) {
