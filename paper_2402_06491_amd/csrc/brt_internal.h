@@ -10,6 +10,10 @@ namespace brt {
 
 constexpr int kWave = 64;
 constexpr int kMaxProblems = 64;
+// How a walker launch holds its problems: one problem (constants in scalar registers), a table of
+// several (each lane reads its problem's record), or a family of several that differ only in their
+// initial data (shared constants in scalar registers, each lane reads its problem's initial data).
+constexpr int kOneProblem = 0, kProblemTable = 1, kFamily = 2;
 constexpr int kMaxU0Params = 32;
 constexpr int kMaxWalkThreads = 256;  // walker block size limit (4 waves): lets FP64 walkers keep state in VGPRs
 
@@ -115,6 +119,7 @@ struct WalkArgs {
   uint32_t stack_depth;      // LDS levels per lane
   uint32_t spill_depth;      // global levels per lane
   uint32_t n_threads;        // grid size in threads (spill stride)
+  uint32_t u0_stride;        // > 0: the n_problems > 1 problems form a family; initial-data parameters kept per problem
 };
 
 struct ReduceArgs {
@@ -202,9 +207,11 @@ hipError_t launch_walk(int precision, int dim, int u0_kind, const WalkArgs& a, i
                        hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s);
-size_t walk_lds_bytes(int precision, int dim, int stack_depth, int waves_per_block, int n_problems, int strategy);
+// u0_stride > 0: a family launch (WalkArgs::u0_stride)
+size_t walk_lds_bytes(int precision, int dim, int stack_depth, int waves_per_block, int n_problems, int strategy,
+                      int u0_stride = 0);
 size_t stack_entry_size(int precision, int dim);  // bytes of one spill level (full layout)
 int walk_max_blocks_per_cu(int precision, int dim, int u0_kind, int n_problems, int stack_depth, int waves_per_block,
-                           int strategy);
+                           int strategy, int u0_stride = 0);
 
 }  // namespace brt

@@ -172,15 +172,14 @@ __device__ __forceinline__ Real logistic_finish(const Real* g, Real e) {
 }
 
 template <typename Real, int DIM, int U0>
-__device__ __forceinline__ Real eval_g(const PdeT<Real>& pd, const Real* x) {
-  const Real* p = pd.u0;
+__device__ __forceinline__ Real eval_g(const Real* p, uint32_t nterms, const Real* x) {
   if constexpr (U0 == 0) {
     return p[0];
   } else if constexpr (U0 == 1) {
-    return logistic_finish<Real>(pd.u0, Math<Real>::ex(logistic_arg<Real, DIM>(pd.u0, x)));
+    return logistic_finish<Real>(p, Math<Real>::ex(logistic_arg<Real, DIM>(p, x)));
   } else if constexpr (U0 == 2) {
     Real acc = 0;
-    for (uint32_t k = 0; k < pd.u0_nterms; ++k) {
+    for (uint32_t k = 0; k < nterms; ++k) {
       const Real* q = p + 4 * k;
       const Real dx = x[0] - q[1];
       Real r2 = dx * dx;
@@ -254,9 +253,15 @@ __host__ __device__ constexpr size_t stack_lds_entry_bytes() {
   return (STRAT == 0 ? sizeof(double) : sizeof(Real)) + DIM * sizeof(Real) + 1;
 }
 
+// LDS bytes of a launch's problem table: n full records, or (u0_stride > 0, a family of problems that
+// differ only in their initial data) the first problem's record, then every problem's number of
+// initial-data terms and its first u0_stride initial-data parameters.
+__host__ __device__ constexpr size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
 template <typename Real>
-__host__ __device__ constexpr size_t pde_table_bytes(int n) {
-  return ((size_t)n * sizeof(PdeT<Real>) + 15) & ~(size_t)15;
+__host__ __device__ constexpr size_t pde_table_bytes(int n, int u0_stride = 0) {
+  return u0_stride == 0 ? align16((size_t)n * sizeof(PdeT<Real>))
+                        : align16(sizeof(PdeT<Real>)) + align16((size_t)n * sizeof(uint32_t)) +
+                              align16((size_t)n * (size_t)u0_stride * sizeof(Real));
 }
 
 // Wave-uniform copies (scalar registers) of values loaded from a wave-uniform address.
@@ -344,24 +349,35 @@ struct Stack {
 };
 
 // ------------------------------------------------------------------------------------------------
-// The walker.  MULTI: the plan has several problems (per-lane problem index); otherwise the
-// problem constants are loop invariants.  MODE bit 0 (STRAT): Strategy A (0, Sec. 2.1) or B (1, Sec. 2.2);
+// The walker.  TAB: kOneProblem, the problem constants are loop invariants; kProblemTable, several
+// problems, each lane reads its tree's problem from the LDS table; kFamily, several problems that differ
+// only in their initial data (the constants of the node step are loop invariants, a leaf reads its
+// problem's initial-data parameters from the LDS table).  MODE bit 0 (STRAT): Strategy A (0, Sec. 2.1) or B (1, Sec. 2.2);
 // bit 1 (CMOD): some problem of the launch has variable coefficients or a drift, so the variants for
 // constant coefficients and L = a Lap carry no trace of them.
 // ------------------------------------------------------------------------------------------------
-template <typename Real, int DIM, int U0, bool MULTI, int MODE>
+template <typename Real, int DIM, int U0, int TAB, int MODE>
 __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
+  constexpr bool MULTI = TAB == kProblemTable;
   constexpr int STRAT = MODE & 1;
   constexpr bool CMOD = (MODE & 2) != 0;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
 
   // problem table -> LDS
   PdeT<Real>* pdes = reinterpret_cast<PdeT<Real>*>(smem);
+  const uint32_t u0s = TAB == kFamily ? a.u0_stride : 0u;
+  uint32_t* fam_nt = reinterpret_cast<uint32_t*>(smem + align16(sizeof(PdeT<Real>)));
+  Real* fam_u0 = reinterpret_cast<Real*>(smem + align16(sizeof(PdeT<Real>)) + align16(a.n_problems * sizeof(uint32_t)));
   {
     const uint32_t* src = reinterpret_cast<const uint32_t*>(a.pdes);
     uint32_t* dst = reinterpret_cast<uint32_t*>(smem);
-    const uint32_t words = (uint32_t)(a.n_problems * sizeof(PdeT<Real>) / 4);
+    const uint32_t words = (uint32_t)((TAB == kFamily ? 1u : a.n_problems) * sizeof(PdeT<Real>) / 4);
     for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) dst[i] = src[i];
+    if constexpr (TAB == kFamily) {
+      const PdeT<Real>* gp = reinterpret_cast<const PdeT<Real>*>(a.pdes);
+      for (uint32_t i = threadIdx.x; i < a.n_problems; i += blockDim.x) fam_nt[i] = gp[i].u0_nterms;
+      for (uint32_t i = threadIdx.x; i < a.n_problems * u0s; i += blockDim.x) fam_u0[i] = gp[i / u0s].u0[i % u0s];
+    }
   }
   __syncthreads();
 
@@ -370,7 +386,7 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
   Stack<Real, DIM, STRAT> st;
   {
     const uint32_t depth = a.stack_depth;
-    unsigned char* wbase = smem + pde_table_bytes<Real>(a.n_problems) +
+    unsigned char* wbase = smem + pde_table_bytes<Real>((int)a.n_problems, (int)u0s) +
                            (size_t)wave * depth * kWave * stack_lds_entry_bytes<Real, DIM, STRAT>();
     // Strategy A: [P double][X DIM reals][R bytes]; Strategy B: [X DIM reals][T reals][R bytes]
     st.P = (BRT_LDS double*)(wbase);
@@ -573,7 +589,15 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
         if (hc.cm_pow) cscale = (Real)1 / (tau2 + hc.cm_t0);
       }
     }
-    if constexpr (U0 == 1) earg = vertex ? earg : logistic_arg<Real, DIM>(hc.g, xn);
+    // the initial data's parameters: the lane's problem's (a family's table) or the problem's
+    const Real* g;
+    if constexpr (TAB == kFamily)
+      g = fam_u0 + pde_lane * u0s;
+    else if constexpr (U0 == 1)
+      g = hc.g;
+    else
+      g = pd.u0;
+    if constexpr (U0 == 1) earg = vertex ? earg : logistic_arg<Real, DIM>(g, xn);
     const Real E = Math<Real>::ex(earg);
     // Strategy B's vertex weight carries the time left tau (eta(t) = t) and its leaves divide by q
     const Real wscale = (STRAT == 1 ? tau : (Real)1) * cscale;
@@ -588,12 +612,12 @@ __global__ __launch_bounds__(kMaxWalkThreads) void walk_kernel(WalkArgs a) {
         om = hc.omega0;
       else
         om = pd.omega[idx];
-      factor = vertex ? wscale * om * E : lscale * logistic_finish<Real>(hc.g, E);
+      factor = vertex ? wscale * om * E : lscale * logistic_finish<Real>(g, E);
     } else {
       if (vertex)
         factor = wscale * pd.omega[idx] * E;
       else
-        factor = lscale * eval_g<Real, DIM, U0>(pd, xn);
+        factor = lscale * eval_g<Real, DIM, U0>(g, TAB == kFamily ? fam_nt[pde_lane] : pd.u0_nterms, xn);
     }
 
     ne += vertex ? 1u : 0u;
@@ -667,57 +691,69 @@ static size_t lds_entry(int dim, int strategy) {
   return strategy ? stack_lds_entry_bytes<Real, 2, 1>() : stack_lds_entry_bytes<Real, 2, 0>();
 }
 
-size_t walk_lds_bytes(int precision, int dim, int stack_depth, int waves_per_block, int n_problems, int strategy) {
+size_t walk_lds_bytes(int precision, int dim, int stack_depth, int waves_per_block, int n_problems, int strategy,
+                      int u0_stride) {
   const size_t sd = (size_t)stack_depth * kWave * waves_per_block;
-  if (precision == 32) return pde_table_bytes<float>(n_problems) + sd * lds_entry<float>(dim, strategy);
-  return pde_table_bytes<double>(n_problems) + sd * lds_entry<double>(dim, strategy);
+  const int us = n_problems > 1 ? u0_stride : 0;
+  if (precision == 32) return pde_table_bytes<float>(n_problems, us) + sd * lds_entry<float>(dim, strategy);
+  return pde_table_bytes<double>(n_problems, us) + sd * lds_entry<double>(dim, strategy);
 }
 
-template <typename Real, int DIM, int U0, bool MULTI, int MODE>
+template <typename Real, int DIM, int U0, int TAB, int MODE>
 static const void* walk_ptr() {
-  return reinterpret_cast<const void*>(&walk_kernel<Real, DIM, U0, MULTI, MODE>);
+  return reinterpret_cast<const void*>(&walk_kernel<Real, DIM, U0, TAB, MODE>);
 }
 
-template <typename Real, int DIM, bool MULTI, int MODE>
+template <typename Real, int DIM, int TAB, int MODE>
 static const void* walk_ptr_u0(int u0) {
   switch (u0) {
-    case 0: return walk_ptr<Real, DIM, 0, MULTI, MODE>();
-    case 1: return walk_ptr<Real, DIM, 1, MULTI, MODE>();
-    case 2: return walk_ptr<Real, DIM, 2, MULTI, MODE>();
-    default: return walk_ptr<Real, DIM, 3, MULTI, MODE>();
+    case 0: return walk_ptr<Real, DIM, 0, TAB, MODE>();
+    case 1: return walk_ptr<Real, DIM, 1, TAB, MODE>();
+    case 2: return walk_ptr<Real, DIM, 2, TAB, MODE>();
+    default: return walk_ptr<Real, DIM, 3, TAB, MODE>();
   }
 }
 
 template <typename Real, int DIM, int MODE>
-static const void* walk_ptr_multi(int u0, bool multi) {
-  return multi ? walk_ptr_u0<Real, DIM, true, MODE>(u0) : walk_ptr_u0<Real, DIM, false, MODE>(u0);
-}
-
-template <typename Real, int DIM>
-static const void* walk_ptr_m(int u0, bool multi, int mode) {
-  switch (mode) {
-    case 0: return walk_ptr_multi<Real, DIM, 0>(u0, multi);
-    case 1: return walk_ptr_multi<Real, DIM, 1>(u0, multi);
-    case 2: return walk_ptr_multi<Real, DIM, 2>(u0, multi);
-    default: return walk_ptr_multi<Real, DIM, 3>(u0, multi);
+static const void* walk_ptr_tab(int u0, int tab) {
+  switch (tab) {
+    case kOneProblem: return walk_ptr_u0<Real, DIM, kOneProblem, MODE>(u0);
+    case kProblemTable: return walk_ptr_u0<Real, DIM, kProblemTable, MODE>(u0);
+    default: return walk_ptr_u0<Real, DIM, kFamily, MODE>(u0);
   }
 }
 
-static const void* walk_fn(int precision, int dim, int u0, bool multi, int mode) {
+template <typename Real, int DIM>
+static const void* walk_ptr_m(int u0, int tab, int mode) {
+  switch (mode) {
+    case 0: return walk_ptr_tab<Real, DIM, 0>(u0, tab);
+    case 1: return walk_ptr_tab<Real, DIM, 1>(u0, tab);
+    case 2: return walk_ptr_tab<Real, DIM, 2>(u0, tab);
+    default: return walk_ptr_tab<Real, DIM, 3>(u0, tab);
+  }
+}
+
+// The table mode of a launch of n problems (u0_stride > 0: they form a family).
+static int walk_tab(int n_problems, int u0_stride) {
+  return n_problems <= 1 ? kOneProblem : (u0_stride > 0 ? kFamily : kProblemTable);
+}
+
+static const void* walk_fn(int precision, int dim, int u0, int tab, int mode) {
   if (precision == 32)
-    return dim == 1 ? walk_ptr_m<float, 1>(u0, multi, mode) : walk_ptr_m<float, 2>(u0, multi, mode);
-  return dim == 1 ? walk_ptr_m<double, 1>(u0, multi, mode) : walk_ptr_m<double, 2>(u0, multi, mode);
+    return dim == 1 ? walk_ptr_m<float, 1>(u0, tab, mode) : walk_ptr_m<float, 2>(u0, tab, mode);
+  return dim == 1 ? walk_ptr_m<double, 1>(u0, tab, mode) : walk_ptr_m<double, 2>(u0, tab, mode);
 }
 
 int walk_max_blocks_per_cu(int precision, int dim, int u0_kind, int n_problems, int stack_depth, int waves_per_block,
-                           int strategy) {
+                           int strategy, int u0_stride) {
   int nb = 0;
-  const size_t lds = walk_lds_bytes(precision, dim, stack_depth, waves_per_block, n_problems, strategy);
+  const size_t lds = walk_lds_bytes(precision, dim, stack_depth, waves_per_block, n_problems, strategy, u0_stride);
+  const int tab = walk_tab(n_problems, u0_stride);
   // the smaller occupancy of the strategy's variants with and without variable coefficients, so a grid
   // sized by it stays resident
   int best = 1 << 30;
   for (int mode = strategy; mode < 4; mode += 2) {
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_fn(precision, dim, u0_kind, n_problems > 1, mode),
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_fn(precision, dim, u0_kind, tab, mode),
                                                      waves_per_block * kWave, lds) != hipSuccess)
       return 0;
     best = nb < best ? nb : best;
@@ -733,8 +769,9 @@ hipError_t launch_reset(uint32_t* chunk_counter, unsigned long long* depth_count
 hipError_t launch_walk(int precision, int dim, int u0_kind, const WalkArgs& a, int grid, int waves_per_block,
                        hipStream_t s) {
   const size_t lds = walk_lds_bytes(precision, dim, (int)a.stack_depth, waves_per_block, (int)a.n_problems,
-                                    (int)a.strategy);
-  const void* fn = walk_fn(precision, dim, u0_kind, a.n_problems > 1, (int)(a.strategy | (a.cmod ? 2u : 0u)));
+                                    (int)a.strategy, (int)a.u0_stride);
+  const void* fn = walk_fn(precision, dim, u0_kind, walk_tab((int)a.n_problems, (int)a.u0_stride),
+                           (int)(a.strategy | (a.cmod ? 2u : 0u)));
   void* args[] = {const_cast<WalkArgs*>(&a)};
   return hipLaunchKernel(fn, dim3(grid), dim3(waves_per_block * kWave), args, lds, s);
 }

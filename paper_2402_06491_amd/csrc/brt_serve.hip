@@ -107,6 +107,10 @@ struct brt_server {
   int wpb = 4, lds_depth = 0, spill_depth = 0;
   int grid_k[kMaxProblems + 1] = {};  // resident walker blocks for a launch group of k problems
   int wpb_k[kMaxProblems + 1] = {};   // and their waves per block
+  // the same for a launch group whose problems form a family, by its initial-data stride (found on
+  // first use; -1: no block size fits, the group takes the full table)
+  int fam_grid[kMaxProblems + 1][kMaxU0Params + 1] = {};
+  int fam_wpb[kMaxProblems + 1][kMaxU0Params + 1] = {};
   size_t spill_threads = 0;           // the spill area's stride: the most threads of any group's launch
   Lane lanes[kLanes];
   // per-slot device state shared by the lanes (each slot belongs to one point of one lane at a time)
@@ -165,6 +169,41 @@ void server_free(brt_server* s) {
   delete s;
 }
 
+// Whether two problem records (device layout) differ at most in their initial data.
+template <typename Real>
+bool same_but_u0(const unsigned char* a, const unsigned char* b) {
+  PdeT<Real> x, y;
+  std::memcpy(&x, a, sizeof(x));
+  std::memcpy(&y, b, sizeof(y));
+  std::memset(x.u0, 0, sizeof(x.u0));
+  std::memset(y.u0, 0, sizeof(y.u0));
+  x.u0_nterms = y.u0_nterms = 0;
+  return std::memcmp(&x, &y, sizeof(x)) == 0;
+}
+
+// Initial-data parameters a problem's leaves read.
+uint32_t u0_params_used(const brt_problem& p) {
+  switch (p.u0_kind) {
+    case BRT_U0_CONST: return 1;
+    case BRT_U0_LOGISTIC: return 6;
+    case BRT_U0_GAUSS_SUM: return 4 * p.u0_nterms;
+    default: return 3;
+  }
+}
+
+// The initial-data stride of a launch group of k > 1 problems (records back to back at `pdes`) if they
+// form a family, else 0.
+uint32_t family_stride(int precision, const unsigned char* pdes, size_t pb, Request* const* reqs, size_t k) {
+  if (k < 2) return 0;
+  uint32_t stride = 1;
+  for (size_t i = 0; i < k; ++i) {
+    if (i > 0 && !(precision == 32 ? same_but_u0<float>(pdes, pdes + i * pb) : same_but_u0<double>(pdes, pdes + i * pb)))
+      return 0;
+    stride = std::max(stride, u0_params_used(reqs[i]->prob));
+  }
+  return std::min<uint32_t>(stride, (uint32_t)kMaxU0Params);
+}
+
 template <typename T>
 int dev_alloc(T** p, size_t n) {
   if (hipMalloc(reinterpret_cast<void**>(p), std::max<size_t>(1, n) * sizeof(T)) != hipSuccess)
@@ -199,7 +238,7 @@ int issue_tick(brt_server* s, Lane& L) {
     size_t g1 = g0;
     for (uint32_t pts = 0; g1 < L.reqs.size() && g1 - g0 < (size_t)kMaxProblems && pts < kGroupPoints; ++g1)
       pts += L.reqs[g1]->n - L.reqs[g1]->n_done;
-    const size_t gprob = prob_off, kprob = g1 - g0;
+    const size_t gprob = prob_off, kprob = g1 - g0, gfirst = g0;
     prob_off += kprob;
     // the group's points, most expensive first (longest-processing-time order of the chunks)
     items.clear();
@@ -275,9 +314,35 @@ int issue_tick(brt_server* s, Lane& L) {
     w.stack_depth = (uint32_t)s->lds_depth;
     w.spill_depth = (uint32_t)s->spill_depth;
     w.n_threads = (uint32_t)s->spill_threads;
-    const int grid = std::max(1, std::min<int>(s->grid_k[kprob], (int)(nc - c0)));
-    SRV_TRY(launch_walk((int)mc.precision, (int)s->opts.dim, (int)s->opts.u0_kind, w, grid, s->wpb_k[kprob],
-                        L.stream));
+    // a family (requests that differ only in their initial data) keeps only the initial data per problem
+    // in the block's table: more resident blocks, and the node step's constants stay in scalar registers
+    int kgrid = s->grid_k[kprob], kwpb = s->wpb_k[kprob];
+    w.u0_stride = family_stride((int)mc.precision, pdes, pb, L.reqs.data() + gfirst, kprob);
+    if (w.u0_stride) {
+      int& fg = s->fam_grid[kprob][w.u0_stride];
+      int& fw = s->fam_wpb[kprob][w.u0_stride];
+      if (fg == 0) {
+        int maxb = 0, wb = 0;
+        for (int c = kMaxWalkThreads / kWave; c >= 1; --c) {
+          const int b = walk_max_blocks_per_cu((int)mc.precision, (int)s->opts.dim, (int)s->opts.u0_kind, (int)kprob,
+                                               s->lds_depth, c, (int)mc.strategy, (int)w.u0_stride);
+          if (b * c > maxb * wb) maxb = b, wb = c;
+        }
+        // the spill area holds spill_threads threads' levels
+        if (maxb > 0 && s->spill_depth > 0)
+          maxb = std::min<int>(maxb, (int)(s->spill_threads / ((size_t)wb * kWave * s->n_cu)));
+        fg = maxb > 0 ? maxb * s->n_cu : -1;
+        fw = wb;
+      }
+      if (fg > 0) {
+        kgrid = fg;
+        kwpb = fw;
+      } else {
+        w.u0_stride = 0;
+      }
+    }
+    const int grid = std::max(1, std::min<int>(kgrid, (int)(nc - c0)));
+    SRV_TRY(launch_walk((int)mc.precision, (int)s->opts.dim, (int)s->opts.u0_kind, w, grid, kwpb, L.stream));
     ReduceArgs ra{};
     ra.points = L.d_points;
     ra.segs = L.d_segs + s0;

@@ -2,7 +2,8 @@
 
 * a served request's coefficients equal the oracle's over the same trees (the trees of point i of a
   request with stream id s are trees 0..n-1 with Philox point id s*1024 + i);
-* a request's results are bit-identical served alone and inside a mix of other requests;
+* a request's results are bit-identical served alone and inside a mix of other requests (requests that
+  differ only in their initial data, and requests with other coefficients);
 * admission by device slots and the bounded queue.
 """
 import time
@@ -82,15 +83,31 @@ def test_served_request_matches_oracle(ctx, round_trees):
         np.testing.assert_allclose(res["coef"][i][:B], a, rtol=0, atol=(P.FP32_TOL + 1e-6) * scale + 1e-300)
 
 
-def test_alone_equals_mixed(ctx):
+def _other(k, n, rng, mix):
+    """Another request of the mix.  "family": the probe's coefficients with Gaussian sums of 2, 4 or 6
+    terms (a launch group keeps only their initial data per problem); "table": other coefficients too
+    (the group keeps every problem's full record)."""
+    r = np.random.default_rng(500 + k)
+    nterms = (2, 4, 6)[k % 3]
+    u0 = inputs.gauss_sum([(r.uniform(0.2, 1.0), r.uniform(-6, 6), r.uniform(-6, 6), r.uniform(0.5, 2.0))
+                           for _ in range(nterms)])
+    coef = [0.0, 1.0, 0.0, -1.0] if mix == "family" else [0.0, 1.0, -0.25 * (k % 3), -1.0 + 0.1 * (k % 2)]
+    prob = inputs.problem(2, 1.0, coef, u0)
+    x = rng.uniform(-8, 8, size=(n, 2))
+    t = np.exp(rng.uniform(np.log(0.25), np.log(1.0), size=n))
+    return prob, x, t
+
+
+@pytest.mark.parametrize("mix", ["family", "table"])
+def test_alone_equals_mixed(ctx, mix):
     import paper_2402_06491_amd as brt
 
-    print("\n[case] serve_alone_vs_mixed: 1 request alone, then among 12 others", flush=True)
+    print(f"\n[case] serve_alone_vs_mixed ({mix}): 1 request alone, then among 12 others", flush=True)
     mc = _mc()
     kw = dict(max_points=2048, round_trees=8192, max_trees=32768, target_se=2e-2)
     rng = np.random.default_rng(11)
     probe = _request(1, 40, rng)
-    others = [_request(100 + k, int(rng.integers(1, 200)), rng) for k in range(12)]
+    others = [_other(k, int(rng.integers(1, 200)), rng, mix) for k in range(12)]
 
     srv = brt.Server(ctx, 2, "gauss_sum", mc, **kw)
     tk = srv.submit(*probe, stream_id=9)
