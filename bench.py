@@ -341,7 +341,7 @@ def adi_source_sha():
 
 
 COPY_BYTES = 512 << 20  # the plain device copy of --pmc-calibration
-FISHER_WALKER = "walk_kernel<float, 1, 1, false, 0>"  # the headline's walker (1-D, logistic data, Strategy A)
+FISHER_WALKER = "walk_kernel<float, 1, 1, 0, 0>"  # the headline's walker (1-D, logistic data, one problem, Strategy A)
 
 
 def pmc_summary(fetch_dir, write_dir, command, launch=None, which="both"):
