@@ -319,10 +319,16 @@ def pmc_record(kernel_src_sha, name="walk_fisher_pmc.json"):
     return d if d.get("kernel_source_sha256") == kernel_src_sha else None
 
 
-def pmc_traffic(kernel_src_sha, launches_trees=None, name="walk_fisher_pmc.json"):
-    """HBM bytes per launch of a kernel from its committed counter summary (None if stale)."""
+def pmc_traffic(kernel_src_sha, launch=None, name="walk_fisher_pmc.json"):
+    """HBM bytes per launch of a kernel from its committed counter summary (None if stale), and the
+    launch they were taken at: the summary's record for `launch` when it holds one, else its latest."""
     d = pmc_record(kernel_src_sha, name)
-    return d.get("hbm_bytes_per_launch") if d else None
+    if not d:
+        return None, None
+    for r in d.get("by_launch", []):
+        if launch is not None and r.get("launch") == launch:
+            return r["hbm_bytes_per_launch"], r["launch"]
+    return d.get("hbm_bytes_per_launch"), d.get("launch")
 
 
 def source_sha(files):
@@ -384,8 +390,14 @@ def pmc_summary(fetch_dir, write_dir, command, launch=None, which="both"):
                "hbm_bytes_per_launch": fw * 1024.0 * fs + ww * 1024.0 * ws,
                "algorithmic_bytes_per_launch": 12 * trees, "command": command}
         if launch:
-            out["launch"] = json.loads(launch)  # the walker launch the counter runs used (their autotuner's choice)
+            out["launch"] = json.loads(launch)  # the walker launch the counter runs used
+        # one record per launch shape taken on the current source (the spill traffic depends on it)
         path = os.path.join(ROOT, "profiles", "walk_fisher_pmc.json")
+        prev = pmc_record(out["kernel_source_sha256"]) or {}
+        keys = ("fetch_kib_per_dispatch", "write_kib_per_dispatch", "fetch_scale", "write_scale",
+                "hbm_bytes_per_launch", "launch")
+        out["by_launch"] = [r for r in prev.get("by_launch", []) if r.get("launch") != out.get("launch")]
+        out["by_launch"].append({k: out.get(k) for k in keys})
         json.dump(out, open(path, "w"), indent=1)
         print(json.dumps(out))
     if which not in ("both", "adi"):
@@ -583,7 +595,7 @@ def pdd_bench(ctx, trees_per_node, cpu_steps):
            "adi_us_per_step": solve_ms * 1e3 / g["n_steps"],
            "adi_roofline": {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
                             "frac": achieved / 8000.0, "algorithmic_bytes": alg_bytes,
-                            "traffic": pmc_traffic(adi_source_sha(), name="adi_pdd_cubic_2d_pmc.json")},
+                            "traffic": pmc_traffic(adi_source_sha(), name="adi_pdd_cubic_2d_pmc.json")[0]},
            "barrier_groups": n_groups, "die_local_groups": die_local,
            "field_finite": bool(np.isfinite(u).all()), "field_max": float(np.abs(u).max())}
     pd.close()
@@ -674,6 +686,9 @@ def main():
                     help="write the counter summaries under profiles/ from two rocprofv3 --pmc runs and exit")
     ap.add_argument("--pmc-command", default="", help="the command of the counter runs, recorded in the summary")
     ap.add_argument("--pmc-launch", default="", help="the walker launch of the counter runs (JSON), recorded in the summary")
+    ap.add_argument("--launch", default="",
+                    help="the headline walker's launch (JSON, e.g. for counter runs at a given launch) instead of "
+                         "the autotuner's")
     ap.add_argument("--pmc-which", default="both", choices=("both", "walker", "adi"),
                     help="which kernels' summaries --pmc-summary writes")
     args = ap.parse_args()
@@ -697,9 +712,15 @@ def main():
     import tempfile
 
     t_tune = time.perf_counter()
-    tuned = ctx.autotune(wl["problems"], wl["mc"], wl["x"], wl["t"], wl["n_trees"], problem_id=wl.get("problem_id"),
-                         cache_path=os.path.join(tempfile.gettempdir(), "brt_autotune.jsonl"))
-    log(f"autotuned launch {tuned} in {time.perf_counter() - t_tune:.1f} s")
+    if args.launch:
+        ctx.set_launch(**json.loads(args.launch))
+        tuned = ctx.get_launch()
+        log(f"launch {tuned} (given)")
+    else:
+        tuned = ctx.autotune(wl["problems"], wl["mc"], wl["x"], wl["t"], wl["n_trees"],
+                             problem_id=wl.get("problem_id"),
+                             cache_path=os.path.join(tempfile.gettempdir(), "brt_autotune.jsonl"))
+        log(f"autotuned launch {tuned} in {time.perf_counter() - t_tune:.1f} s")
     plan = brt.Plan(ctx, wl["problems"], wl["mc"], wl["x"], wl["t"], wl["n_trees"],
                     problem_id=wl.get("problem_id"), point_id=wl.get("point_id"))
     out = plan.outputs(records=True)
@@ -745,9 +766,9 @@ def main():
     ops = nodes * OPS_PER_NODE[dim]
     achieved = ops / walk_s / 1e12
     sha = walker_source_sha()
+    traffic, traffic_launch = pmc_traffic(sha, tuned)
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_TOPS, "unit": "Top/s",
-                "frac": achieved / PEAK_TOPS, "traffic": pmc_traffic(sha, total_trees),
-                "traffic_launch": (pmc_record(sha) or {}).get("launch"),
+                "frac": achieved / PEAK_TOPS, "traffic": traffic, "traffic_launch": traffic_launch,
                 "kernel": "walk_kernel", "kernel_ms": walk_s * 1e3, "nodes_per_launch": nodes,
                 "ops_per_node": OPS_PER_NODE[dim], "reduce_ms": red_ms / runs, "finalize_ms": fin_ms / runs}
     log(f"walk kernel {walk_s * 1e3:.3f} ms, {nodes} nodes, {achieved:.2f} Top/s "
