@@ -489,7 +489,8 @@ def plain_per_request(ctx, reqs, results, mc):
 
 def family_plan_rate(ctx):
     """The plan rate on the served family: the 2-D cubic problem's 1536 interface points x 1e5 trees in
-    one plan (FP32 paths), replayed as a graph."""
+    one plan (FP32 paths, t = 1), replayed as a graph; trees and tree nodes per second (the served
+    points' times differ, so their trees differ in size: nodes compare the two)."""
     import torch
 
     import paper_2402_06491_amd as brt
@@ -507,8 +508,9 @@ def family_plan_rate(ctx):
             plan.execute(out, stream=stream)
         torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / 5
+    nodes = int(out["nodes"].sum().item())
     plan.close()
-    return int(np.sum(wl["n_trees"])) / dt
+    return int(np.sum(wl["n_trees"])) / dt, nodes / dt
 
 
 def serve_bench(ctx, duration, rate, opts, plain_requests, saturated_requests):
@@ -550,12 +552,16 @@ def serve_bench(ctx, duration, rate, opts, plain_requests, saturated_requests):
     sat = reqs[:saturated_requests]
     if sat:
         st2, _ = serve_stream(ctx, sat, mc, opts, realtime=False)
-        rate_plan = family_plan_rate(ctx)
+        rate_plan, node_rate_plan = family_plan_rate(ctx)
+        node_rate = st2["nodes"] / st2["span_s"]
         out["saturated"] = {"requests": len(sat), "trees_per_s": st2["trees_per_s"], "span_s": st2["span_s"],
                             "device_busy_s": st2["busy_s"], "plan_trees_per_s": rate_plan,
-                            "fraction_of_plan_rate": st2["trees_per_s"] / rate_plan}
+                            "fraction_of_plan_rate": st2["trees_per_s"] / rate_plan,
+                            "nodes_per_s": node_rate, "plan_nodes_per_s": node_rate_plan,
+                            "fraction_of_plan_node_rate": node_rate / node_rate_plan}
         log(f"serving saturated ({len(sat)} requests at once): {st2['trees_per_s']:.4g} trees/s = "
-            f"{100 * st2['trees_per_s'] / rate_plan:.1f}% of the plan rate {rate_plan:.4g} trees/s")
+            f"{100 * st2['trees_per_s'] / rate_plan:.1f}% of the plan rate {rate_plan:.4g} trees/s; "
+            f"{node_rate:.4g} nodes/s = {100 * node_rate / node_rate_plan:.1f}% of the plan's {node_rate_plan:.4g}")
     return out
 
 

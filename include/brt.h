@@ -322,8 +322,10 @@ int brt_autotune(brt_ctx* ctx, uint32_t n_problems, const brt_problem* problems,
  *
  * An engine thread runs ticks; each tick adds one round of `round_trees` trees to every unfinished
  * point of the admitted requests it covers, packing consecutive requests into shared launches (a
- * launch group closes once it holds 4096 unfinished points or 64 requests).  A point's slot is freed
- * as soon as the point finishes, not when its whole request does.
+ * launch group closes once it holds 4096 unfinished points or 64 requests).  Requests whose problems
+ * differ only in their initial data (u0 parameters and term count) share a group's walker constants;
+ * a group with other differences keeps every problem's full record (slower, same results).  A point's
+ * slot is freed as soon as the point finishes, not when its whole request does.
  * Admitted requests are split between two lanes with their own streams: while one lane's tick runs on
  * the device, the engine reads the other lane's results (copied back by its tick), admits requests and
  * enqueues that lane's next tick.  The reduction partials of every round stay on the device in the

@@ -107,8 +107,9 @@ struct brt_server {
   int wpb = 4, lds_depth = 0, spill_depth = 0;
   int grid_k[kMaxProblems + 1] = {};  // resident walker blocks for a launch group of k problems
   int wpb_k[kMaxProblems + 1] = {};   // and their waves per block
-  // the same for a launch group whose problems form a family, by its initial-data stride (found on
-  // first use; -1: no block size fits, the group takes the full table)
+  // the same for a launch group whose problems form a family, by its initial-data stride (found at
+  // creation for the strides the served initial-data kind has; -1: no block size fits, the group takes
+  // the full table)
   int fam_grid[kMaxProblems + 1][kMaxU0Params + 1] = {};
   int fam_wpb[kMaxProblems + 1][kMaxU0Params + 1] = {};
   size_t spill_threads = 0;           // the spill area's stride: the most threads of any group's launch
@@ -202,6 +203,25 @@ uint32_t family_stride(int precision, const unsigned char* pdes, size_t pb, Requ
     stride = std::max(stride, u0_params_used(reqs[i]->prob));
   }
   return std::min<uint32_t>(stride, (uint32_t)kMaxU0Params);
+}
+
+// The resident grid and block size of a family launch of k problems at initial-data stride `stride`
+// (the block size with the most resident waves, the larger on a tie), found once.
+void family_launch(brt_server* s, int k, int stride) {
+  int& fg = s->fam_grid[k][stride];
+  if (fg != 0) return;
+  const brt_mc& mc = s->opts.mc;
+  int maxb = 0, wb = 0;
+  for (int c = kMaxWalkThreads / kWave; c >= 1; --c) {
+    const int b = walk_max_blocks_per_cu((int)mc.precision, (int)s->opts.dim, (int)s->opts.u0_kind, k, s->lds_depth, c,
+                                         (int)mc.strategy, stride);
+    if (b * c > maxb * wb) maxb = b, wb = c;
+  }
+  // the spill area holds spill_threads threads' levels
+  if (maxb > 0 && s->spill_depth > 0)
+    maxb = std::min<int>(maxb, (int)(s->spill_threads / ((size_t)wb * kWave * s->n_cu)));
+  fg = maxb > 0 ? maxb * s->n_cu : -1;
+  s->fam_wpb[k][stride] = wb;
 }
 
 template <typename T>
@@ -319,24 +339,10 @@ int issue_tick(brt_server* s, Lane& L) {
     int kgrid = s->grid_k[kprob], kwpb = s->wpb_k[kprob];
     w.u0_stride = family_stride((int)mc.precision, pdes, pb, L.reqs.data() + gfirst, kprob);
     if (w.u0_stride) {
-      int& fg = s->fam_grid[kprob][w.u0_stride];
-      int& fw = s->fam_wpb[kprob][w.u0_stride];
-      if (fg == 0) {
-        int maxb = 0, wb = 0;
-        for (int c = kMaxWalkThreads / kWave; c >= 1; --c) {
-          const int b = walk_max_blocks_per_cu((int)mc.precision, (int)s->opts.dim, (int)s->opts.u0_kind, (int)kprob,
-                                               s->lds_depth, c, (int)mc.strategy, (int)w.u0_stride);
-          if (b * c > maxb * wb) maxb = b, wb = c;
-        }
-        // the spill area holds spill_threads threads' levels
-        if (maxb > 0 && s->spill_depth > 0)
-          maxb = std::min<int>(maxb, (int)(s->spill_threads / ((size_t)wb * kWave * s->n_cu)));
-        fg = maxb > 0 ? maxb * s->n_cu : -1;
-        fw = wb;
-      }
-      if (fg > 0) {
-        kgrid = fg;
-        kwpb = fw;
+      family_launch(s, (int)kprob, (int)w.u0_stride);
+      if (s->fam_grid[kprob][w.u0_stride] > 0) {
+        kgrid = s->fam_grid[kprob][w.u0_stride];
+        kwpb = s->fam_wpb[kprob][w.u0_stride];
       } else {
         w.u0_stride = 0;
       }
@@ -591,6 +597,16 @@ int brt_server_create(brt_ctx* ctx, const brt_server_opts* o, brt_server** out) 
       s->grid_k[k] = maxb * s->n_cu;
       s->wpb_k[k] = w;
       s->spill_threads = std::max(s->spill_threads, (size_t)s->grid_k[k] * w * kWave);
+    }
+    // family launches at every stride the served initial-data kind can give (Gaussian sums: 4 per term)
+    for (int k = 2; k <= kMaxProblems; ++k) {
+      if (o->u0_kind == BRT_U0_GAUSS_SUM) {
+        for (int st = 4; st <= kMaxU0Params; st += 4) family_launch(s, k, st);
+      } else {
+        brt_problem one{};
+        one.u0_kind = o->u0_kind;
+        family_launch(s, k, (int)u0_params_used(one));
+      }
     }
     const size_t P = o->max_points;
     const size_t R = o->round_trees;
