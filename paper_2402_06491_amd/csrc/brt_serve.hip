@@ -52,6 +52,9 @@ constexpr int kLanes = 2;
 // problems, 16 KB in FP32, it costs a third of the walker's resident waves), so large requests go in small
 // groups and only small requests share a launch with many others.
 constexpr uint32_t kGroupPoints = 4096;
+// Walker blocks per CU left free by a launch group's persistent walker (when it would hold three or
+// more): the other lane's reduction and finalize then run beside it instead of waiting for its end.
+constexpr int kSpareBlocks = 1;
 constexpr uint32_t kCounterStride = 16;  // 64 bytes between the chunk counters of a lane's launch groups
 
 struct Request {
@@ -220,6 +223,7 @@ void family_launch(brt_server* s, int k, int stride) {
   // the spill area holds spill_threads threads' levels
   if (maxb > 0 && s->spill_depth > 0)
     maxb = std::min<int>(maxb, (int)(s->spill_threads / ((size_t)wb * kWave * s->n_cu)));
+  if (maxb >= 2 + kSpareBlocks) maxb -= kSpareBlocks;
   fg = maxb > 0 ? maxb * s->n_cu : -1;
   s->fam_wpb[k][stride] = wb;
 }
@@ -594,7 +598,7 @@ int brt_server_create(brt_ctx* ctx, const brt_server_opts* o, brt_server** out) 
         server_free(s);
         return set_error(BRT_E_ARG, "server: walker launch for %d problems does not fit the device", k);
       }
-      s->grid_k[k] = maxb * s->n_cu;
+      s->grid_k[k] = (maxb >= 2 + kSpareBlocks ? maxb - kSpareBlocks : maxb) * s->n_cu;
       s->wpb_k[k] = w;
       s->spill_threads = std::max(s->spill_threads, (size_t)s->grid_k[k] * w * kWave);
     }
