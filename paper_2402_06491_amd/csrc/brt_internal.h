@@ -207,6 +207,11 @@ hipError_t launch_walk(int precision, int dim, int u0_kind, const WalkArgs& a, i
                        hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s);
+// Initial-data parameters a problem's leaves read (BRT_U0_* kind; nterms for Gaussian sums).
+uint32_t u0_param_count(uint32_t u0_kind, uint32_t nterms);
+// The initial-data stride of a launch of n problem records (device layout, back to back) if they form a
+// family (equal but for their initial-data parameters and term counts), else 0.
+uint32_t family_u0_stride(int precision, uint32_t u0_kind, const void* recs, size_t n);
 // u0_stride > 0: a family launch (WalkArgs::u0_stride)
 size_t walk_lds_bytes(int precision, int dim, int stack_depth, int waves_per_block, int n_problems, int strategy,
                       int u0_stride = 0);

@@ -133,6 +133,37 @@ Norm normalize(const brt_problem& p, const brt_mc& mc) {
 
 size_t pde_bytes(int precision) { return precision == 32 ? sizeof(PdeT<float>) : sizeof(PdeT<double>); }
 
+uint32_t u0_param_count(uint32_t u0_kind, uint32_t nterms) {
+  switch (u0_kind) {
+    case BRT_U0_CONST: return 1;
+    case BRT_U0_LOGISTIC: return 6;
+    case BRT_U0_GAUSS_SUM: return 4 * nterms;
+    default: return 3;
+  }
+}
+
+template <typename Real>
+static uint32_t family_stride_t(uint32_t u0_kind, const void* recs, size_t n) {
+  if (n < 2) return 0;
+  const PdeT<Real>* r = static_cast<const PdeT<Real>*>(recs);
+  PdeT<Real> first = r[0];
+  std::memset(first.u0, 0, sizeof(first.u0));
+  first.u0_nterms = 0;
+  uint32_t stride = 1;
+  for (size_t i = 0; i < n; ++i) {
+    PdeT<Real> x = r[i];
+    stride = std::max(stride, u0_param_count(u0_kind, x.u0_nterms));
+    std::memset(x.u0, 0, sizeof(x.u0));
+    x.u0_nterms = 0;
+    if (std::memcmp(&x, &first, sizeof(x)) != 0) return 0;
+  }
+  return std::min<uint32_t>(stride, (uint32_t)kMaxU0Params);
+}
+
+uint32_t family_u0_stride(int precision, uint32_t u0_kind, const void* recs, size_t n) {
+  return precision == 32 ? family_stride_t<float>(u0_kind, recs, n) : family_stride_t<double>(u0_kind, recs, n);
+}
+
 void pde_to_device(const brt_problem& p, const Norm& n, int precision, void* dst) {
   if (precision == 32) {
     const PdeT<float> d = to_device<float>(p, n);
@@ -166,6 +197,7 @@ struct brt_plan {
   int precision = 32, dim = 1, u0_kind = 0;
   uint32_t n_problems = 0, n_points = 0, n_bins = 0;
   uint32_t cmod = 0;  // some problem has variable coefficients
+  uint32_t u0_stride = 0;  // > 0: the problems differ only in their initial data (a family launch)
   uint64_t total_trees = 0;
   brt_mc mc{};
   std::vector<PointRec> points;
@@ -498,10 +530,12 @@ extern "C" int brt_plan_create(brt_ctx* ctx, uint32_t n_problems, const brt_prob
     if (p->precision == 32) {
       std::vector<PdeT<float>> tab(n_problems);
       for (uint32_t i = 0; i < n_problems; ++i) tab[i] = to_device<float>(problems[i], norms[i]);
+      p->u0_stride = family_u0_stride(32, (uint32_t)p->u0_kind, tab.data(), tab.size());
       rc = upload(reinterpret_cast<PdeT<float>**>(&p->d_pdes), tab);
     } else {
       std::vector<PdeT<double>> tab(n_problems);
       for (uint32_t i = 0; i < n_problems; ++i) tab[i] = to_device<double>(problems[i], norms[i]);
+      p->u0_stride = family_u0_stride(64, (uint32_t)p->u0_kind, tab.data(), tab.size());
       rc = upload(reinterpret_cast<PdeT<double>**>(&p->d_pdes), tab);
     }
     if (!rc) rc = upload(&p->d_points, p->points);
@@ -526,11 +560,11 @@ extern "C" int brt_plan_create(brt_ctx* ctx, uint32_t n_problems, const brt_prob
     // persistent grid: as many blocks as are resident at once
     int bpc = (int)ctx->launch.blocks_per_cu;
     int maxb = walk_max_blocks_per_cu(p->precision, p->dim, p->u0_kind, (int)p->n_problems, p->stack_depth, p->waves_per_block,
-                                   (int)p->mc.strategy);
+                                   (int)p->mc.strategy, (int)p->u0_stride);
     while (maxb <= 0 && p->waves_per_block > 1) {  // shrink the block until its LDS fits
       p->waves_per_block -= 1;
       maxb = walk_max_blocks_per_cu(p->precision, p->dim, p->u0_kind, (int)p->n_problems, p->stack_depth, p->waves_per_block,
-                                   (int)p->mc.strategy);
+                                   (int)p->mc.strategy, (int)p->u0_stride);
     }
     if (maxb <= 0) {
       plan_free(p);
@@ -611,6 +645,7 @@ static int enqueue(brt_plan* p, const brt_out* o, hipStream_t s) {
     w.spill_depth = (uint32_t)p->spill_depth;
     w.spill = p->d_spill;
     w.n_threads = (uint32_t)(p->grid * p->waves_per_block * kWave);
+    w.u0_stride = p->u0_stride;
     HIP_TRY(launch_walk(p->precision, p->dim, p->u0_kind, w, p->grid, p->waves_per_block, s));
   }
   if (ev) HIP_TRY(hipEventRecord((*ev)[1], s));

@@ -173,41 +173,6 @@ void server_free(brt_server* s) {
   delete s;
 }
 
-// Whether two problem records (device layout) differ at most in their initial data.
-template <typename Real>
-bool same_but_u0(const unsigned char* a, const unsigned char* b) {
-  PdeT<Real> x, y;
-  std::memcpy(&x, a, sizeof(x));
-  std::memcpy(&y, b, sizeof(y));
-  std::memset(x.u0, 0, sizeof(x.u0));
-  std::memset(y.u0, 0, sizeof(y.u0));
-  x.u0_nterms = y.u0_nterms = 0;
-  return std::memcmp(&x, &y, sizeof(x)) == 0;
-}
-
-// Initial-data parameters a problem's leaves read.
-uint32_t u0_params_used(const brt_problem& p) {
-  switch (p.u0_kind) {
-    case BRT_U0_CONST: return 1;
-    case BRT_U0_LOGISTIC: return 6;
-    case BRT_U0_GAUSS_SUM: return 4 * p.u0_nterms;
-    default: return 3;
-  }
-}
-
-// The initial-data stride of a launch group of k > 1 problems (records back to back at `pdes`) if they
-// form a family, else 0.
-uint32_t family_stride(int precision, const unsigned char* pdes, size_t pb, Request* const* reqs, size_t k) {
-  if (k < 2) return 0;
-  uint32_t stride = 1;
-  for (size_t i = 0; i < k; ++i) {
-    if (i > 0 && !(precision == 32 ? same_but_u0<float>(pdes, pdes + i * pb) : same_but_u0<double>(pdes, pdes + i * pb)))
-      return 0;
-    stride = std::max(stride, u0_params_used(reqs[i]->prob));
-  }
-  return std::min<uint32_t>(stride, (uint32_t)kMaxU0Params);
-}
-
 // The resident grid and block size of a family launch of k problems at initial-data stride `stride`
 // (the block size with the most resident waves, the larger on a tie), found once.
 void family_launch(brt_server* s, int k, int stride) {
@@ -262,7 +227,7 @@ int issue_tick(brt_server* s, Lane& L) {
     size_t g1 = g0;
     for (uint32_t pts = 0; g1 < L.reqs.size() && g1 - g0 < (size_t)kMaxProblems && pts < kGroupPoints; ++g1)
       pts += L.reqs[g1]->n - L.reqs[g1]->n_done;
-    const size_t gprob = prob_off, kprob = g1 - g0, gfirst = g0;
+    const size_t gprob = prob_off, kprob = g1 - g0;
     prob_off += kprob;
     // the group's points, most expensive first (longest-processing-time order of the chunks)
     items.clear();
@@ -341,7 +306,7 @@ int issue_tick(brt_server* s, Lane& L) {
     // a family (requests that differ only in their initial data) keeps only the initial data per problem
     // in the block's table: more resident blocks, and the node step's constants stay in scalar registers
     int kgrid = s->grid_k[kprob], kwpb = s->wpb_k[kprob];
-    w.u0_stride = family_stride((int)mc.precision, pdes, pb, L.reqs.data() + gfirst, kprob);
+    w.u0_stride = family_u0_stride((int)mc.precision, s->opts.u0_kind, pdes, kprob);
     if (w.u0_stride) {
       family_launch(s, (int)kprob, (int)w.u0_stride);
       if (s->fam_grid[kprob][w.u0_stride] > 0) {
@@ -607,9 +572,7 @@ int brt_server_create(brt_ctx* ctx, const brt_server_opts* o, brt_server** out) 
       if (o->u0_kind == BRT_U0_GAUSS_SUM) {
         for (int st = 4; st <= kMaxU0Params; st += 4) family_launch(s, k, st);
       } else {
-        brt_problem one{};
-        one.u0_kind = o->u0_kind;
-        family_launch(s, k, (int)u0_params_used(one));
+        family_launch(s, k, (int)u0_param_count(o->u0_kind, 0));
       }
     }
     const size_t P = o->max_points;

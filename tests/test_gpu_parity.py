@@ -529,3 +529,30 @@ def test_alone_equals_in_batch(ctx):
         alone = P.gpu_run(ctx, one, records=False)
         for k in ("u", "se", "coef", "hist", "s1", "s2", "nodes"):
             np.testing.assert_array_equal(alone[k][0], batch[k][p], err_msg=f"{k} point {p}")
+
+
+@pytest.mark.parametrize("prec", [32, 64])
+def test_family_batch(ctx, prec):
+    """Problems that differ only in their initial data (Gaussian sums of 1, 3 and 8 terms, the same
+    coefficients) form a family: one launch keeps only their initial data per problem.  Against the
+    oracle, and every sampled point bit-identical to the same point solved with its problem alone."""
+    probs = []
+    for k, nterms in enumerate((1, 3, 8)):
+        r = np.random.default_rng(300 + k)
+        probs.append(inputs.problem(2, 1.0, [0.0, 1.0, 0.0, -1.0], inputs.gauss_sum(
+            [(r.uniform(0.2, 1.0), r.uniform(-3, 3), r.uniform(-3, 3), r.uniform(0.5, 2.0)) for _ in range(nterms)])))
+    rng = np.random.default_rng(12)
+    n = 48
+    wl = {"problems": probs, "mc": inputs.mc_params(seed=5, precision=prec),
+          "x": rng.uniform(-4, 4, size=(n, 2)), "t": rng.uniform(0.2, 1.0, size=n),
+          "n_trees": rng.integers(1, 700, size=n), "problem_id": (np.arange(n) % 3).astype(np.uint32),
+          "point_id": np.arange(n, dtype=np.uint32)}
+    gpu, _ = _full_parity(ctx, f"family_batch_fp{prec}", wl)
+    for p in (0, 1, 2, 47):
+        k = int(wl["problem_id"][p])
+        one = {"problems": [probs[k]], "mc": wl["mc"], "x": wl["x"][p:p + 1], "t": wl["t"][p:p + 1],
+               "n_trees": wl["n_trees"][p:p + 1], "problem_id": np.zeros(1, np.uint32),
+               "point_id": wl["point_id"][p:p + 1]}
+        alone = P.gpu_run(ctx, one, records=False)
+        for key in ("u", "se", "coef", "hist", "s1", "s2", "nodes"):
+            np.testing.assert_array_equal(alone[key][0], gpu[key][p], err_msg=f"{key} point {p}")
