@@ -247,7 +247,8 @@ int brt_get_launch(brt_ctx* ctx, brt_launch* launch);
  * mu = c_1 + lambda, vertex weight K c_j / lambda e^{(j-1) mu tau}), upload the point records, cut
  * every point's trees into work chunks ordered by estimated cost, and reserve device scratch
  * (tree records unless the caller supplies brt_out.tree_f/tree_meta).  Host arrays are copied.
- * At most 64 problems per plan; all of one dim and u0_kind. */
+ * At most 64 problems per plan; all of one dim and u0_kind.  Problems that differ only in their
+ * initial data (u0 parameters and term count) run as a family, their shared constants held once. */
 int brt_plan_create(brt_ctx* ctx, uint32_t n_problems, const brt_problem* problems, const brt_mc* mc,
                     const brt_points* points, brt_plan** out);
 
