@@ -398,9 +398,6 @@ __device__ inline uint32_t lds_pos(uint32_t p) {
 }
 
 // Global accesses at a 32-bit byte offset from a base that is uniform over the block.
-__device__ inline double ldg(const double* base, uint32_t byte_off) {
-  return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + byte_off);
-}
 __device__ inline void stg(double* base, uint32_t byte_off, double v) {
   *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + byte_off) = v;
 }
