@@ -3,7 +3,8 @@
 // An engine thread runs ticks.  A tick gives every unfinished point of the requests it covers one more
 // round of `round_trees` trees: the rounds of those requests are packed into launch groups of up to
 // kGroupPoints points and kMaxProblems requests (problems), so requests of different sizes and horizons
-// share launches.  Each point owns a device slot holding the reduction partials of all its
+// share launches; a group whose problems differ only in their initial data runs the walker's family
+// mode (shared constants in scalar registers).  Each point owns a device slot holding the reduction partials of all its
 // rounds; the finalize recomputes the point's coefficients, Pade value and SE from the slot after every
 // round.  A point finishes when its SE reaches the target or its trees reach the cap; a request completes
 // when all its points have finished.  New requests are admitted at tick
@@ -49,7 +50,8 @@ constexpr uint32_t kChunkTrees = 1024;
 constexpr int kLanes = 2;
 // Launch groups: consecutive requests of a lane until the group holds kGroupPoints unfinished points or
 // kMaxProblems requests.  The walker keeps the group's problem table in LDS beside its stack levels (at 64
-// problems, 16 KB in FP32, it costs a third of the walker's resident waves), so large requests go in small
+// full FP32 records, 16 KB, it costs a third of the walker's resident waves; a family of problems that
+// differ only in their initial data keeps just those, 8.4 KB at most), so large requests go in small
 // groups and only small requests share a launch with many others.
 constexpr uint32_t kGroupPoints = 4096;
 // Walker blocks per CU left free by a launch group's persistent walker (when it would hold three or
