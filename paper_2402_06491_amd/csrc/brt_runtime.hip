@@ -145,13 +145,17 @@ uint32_t u0_param_count(uint32_t u0_kind, uint32_t nterms) {
 template <typename Real>
 static uint32_t family_stride_t(uint32_t u0_kind, const void* recs, size_t n) {
   if (n < 2) return 0;
-  const PdeT<Real>* r = static_cast<const PdeT<Real>*>(recs);
-  PdeT<Real> first = r[0];
+  // records compared byte by byte (their padding is zero: to_device clears every record), so they are
+  // copied with memcpy, which keeps the padding bytes
+  const unsigned char* r = static_cast<const unsigned char*>(recs);
+  PdeT<Real> first;
+  std::memcpy(&first, r, sizeof(first));
   std::memset(first.u0, 0, sizeof(first.u0));
   first.u0_nterms = 0;
   uint32_t stride = 1;
   for (size_t i = 0; i < n; ++i) {
-    PdeT<Real> x = r[i];
+    PdeT<Real> x;
+    std::memcpy(&x, r + i * sizeof(PdeT<Real>), sizeof(x));
     stride = std::max(stride, u0_param_count(u0_kind, x.u0_nterms));
     std::memset(x.u0, 0, sizeof(x.u0));
     x.u0_nterms = 0;
@@ -591,16 +595,15 @@ extern "C" {
 int brt_plan_info(const brt_plan* p, uint32_t* n_points, uint64_t* n_trees, uint32_t* n_bins, uint32_t* n_chunks);
 }
 
+// (called from entry points, which turn exceptions into status codes)
 static int ensure_records(brt_plan* p) {
-  return brt::api_guard("brt_plan_info", [&]() -> int {
-    if (p->d_tree_f) return BRT_OK;
-    const size_t n = std::max<uint64_t>(1, p->total_trees);
-    const size_t fb = n * sizeof(double);
-    if (hipMalloc(reinterpret_cast<void**>(&p->d_tree_f), fb) != hipSuccess) return fail(BRT_E_NOMEM, "tree records: hipMalloc(%zu)", fb);
-    if (hipMalloc(reinterpret_cast<void**>(&p->d_tree_meta), n * 4) != hipSuccess)
-      return fail(BRT_E_NOMEM, "tree records: hipMalloc(%zu)", n * 4);
-    return BRT_OK;
-  });
+  if (p->d_tree_f) return BRT_OK;
+  const size_t n = std::max<uint64_t>(1, p->total_trees);
+  const size_t fb = n * sizeof(double);
+  if (hipMalloc(reinterpret_cast<void**>(&p->d_tree_f), fb) != hipSuccess) return fail(BRT_E_NOMEM, "tree records: hipMalloc(%zu)", fb);
+  if (hipMalloc(reinterpret_cast<void**>(&p->d_tree_meta), n * 4) != hipSuccess)
+    return fail(BRT_E_NOMEM, "tree records: hipMalloc(%zu)", n * 4);
+  return BRT_OK;
 }
 
 static int enqueue(brt_plan* p, const brt_out* o, hipStream_t s) {
@@ -753,12 +756,14 @@ int brt_plan_graph_stats(const brt_plan* p, uint64_t* captures, uint64_t* replay
 }
 
 int brt_plan_info(const brt_plan* p, uint32_t* n_points, uint64_t* n_trees, uint32_t* n_bins, uint32_t* n_chunks) {
-  if (!p) return fail(BRT_E_ARG, "brt_plan_info: NULL plan");
-  if (n_points) *n_points = p->n_points;
-  if (n_trees) *n_trees = p->total_trees;
-  if (n_bins) *n_bins = p->n_bins;
-  if (n_chunks) *n_chunks = (uint32_t)p->chunks.size();
-  return BRT_OK;
+  return brt::api_guard("brt_plan_info", [&]() -> int {
+    if (!p) return fail(BRT_E_ARG, "brt_plan_info: NULL plan");
+    if (n_points) *n_points = p->n_points;
+    if (n_trees) *n_trees = p->total_trees;
+    if (n_bins) *n_bins = p->n_bins;
+    if (n_chunks) *n_chunks = (uint32_t)p->chunks.size();
+    return BRT_OK;
+  });
 }
 
 int brt_plan_depth_exceeded(brt_plan* p, uint64_t* count) {

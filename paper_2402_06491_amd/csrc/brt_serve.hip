@@ -4,9 +4,9 @@
 // round of `round_trees` trees: the rounds of those requests are packed into launch groups of up to
 // kGroupPoints points and kMaxProblems requests (problems), so requests of different sizes and horizons
 // share launches; a group whose problems differ only in their initial data runs the walker's family
-// mode (shared constants in scalar registers).  Each point owns a device slot holding the reduction partials of all its
-// rounds; the finalize recomputes the point's coefficients, Pade value and SE from the slot after every
-// round.  A point finishes when its SE reaches the target or its trees reach the cap; a request completes
+// mode (shared constants in scalar registers).  Each point owns a device slot holding the reduction
+// partials of all its rounds; the finalize recomputes the point's coefficients, Pade value and SE from
+// the slot after every round.  A point finishes when its SE reaches the target or its trees reach the cap; a request completes
 // when all its points have finished.  New requests are admitted at tick
 // boundaries while free slots remain (memory admission); a point's slot is freed as soon as the point
 // finishes and its results are read; the submission queue is bounded.
